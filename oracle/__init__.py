@@ -1,0 +1,17 @@
+"""CPU oracle for the deterministic MIS-2 and MIS-2 aggregation.
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product library.
+"""
+from .oracle import (  # noqa: F401
+    build_oracle,
+    xorshift64star,
+    hash_priority,
+    id_bits,
+    pack,
+    mis2,
+    mis2_ex,
+    aggregate,
+    quotient,
+    coarsen,
+)

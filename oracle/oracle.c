@@ -1,0 +1,438 @@
+/*
+ * oracle.c -- plain, slow, obviously correct CPU reference for the deterministic
+ * distance-2 maximal independent set (MIS-2) and the MIS-2 aggregation of
+ * Kelley & Rajamanickam, "Parallel, Portable Algorithms for Distance-2 Maximal
+ * Independent Set and Graph Coarsening" (arXiv 2204.02934).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the checker that the HIP library is
+ * compared against.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark load it; the product path never does.  It shares no
+ * code, header, table or constant with the GPU library.
+ *
+ * Every loop below runs sequentially, in increasing vertex order, exactly in
+ * the order the paper states the steps; nothing is blocked, fused or
+ * reordered.  Readings taken where the paper is silent are marked "Reading".
+ *
+ * Pins (in tests/): the worked example of Fig. 1 (exact intermediate values),
+ * a brute-force Luby-on-G^2 implementation (Section IV, Lemma 2) on small
+ * graphs, breadth-first validity checks of the definitions (Section I),
+ * closed-form special cases, exhaustive packing checks (Section V-C, Eq. 1),
+ * brute-force aggregation invariants (Section III-B, Alg. 3) and Table III
+ * counts (soft: the paper does not fix the hash bits, see oracle_hash).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_IN  0u           /* Section V-C: IN is the value 0          */
+#define ORACLE_OUT 0xFFFFFFFFu  /* Section V-C: OUT is UINT_MAX (32 bits)  */
+
+/* ------------------------------------------------------------------------- */
+/* Section V-A: f is 64-bit xorshift* (an xorshift step followed by a         */
+/* multiplicative linear congruential step).  The paper gives no constants;  */
+/* Reading: Vigna's published xorshift64* (ACM TOMS 2016): shifts 12, 25, 27 */
+/* and multiplier 2685821657736338717, arithmetic modulo 2^64.               */
+/* ------------------------------------------------------------------------- */
+uint64_t oracle_xorshift64star(uint64_t x)
+{
+    x ^= x >> 12;
+    x ^= x << 25;
+    x ^= x >> 27;
+    return x * UINT64_C(2685821657736338717);
+}
+
+/* Section V-A: h(iter, v) = f(f(iter) XOR f(v)).
+ * Reading (seed): the paper has no seed; the first argument of h becomes
+ * (seed << 32) XOR iter, so seed 0 is the paper's formula unchanged. */
+uint64_t oracle_hash(uint64_t seed, uint64_t iter, uint64_t v)
+{
+    uint64_t i = (seed << 32) ^ iter;
+    return oracle_xorshift64star(oracle_xorshift64star(i) ^ oracle_xorshift64star(v));
+}
+
+/* Section V-C, Eq. (1): b = ceil(log2(|V| + 2)), i.e. the smallest integer b
+ * with 2^b >= |V| + 2, computed with integers only. */
+int oracle_id_bits(int64_t n)
+{
+    int b = 0;
+    while (b < 63 && (INT64_C(1) << b) < n + 2)
+        b++;
+    return b;
+}
+
+/* Section V-C: an undecided tuple is (priority << b) | (id + 1) in 32 bits.
+ * Reading: the priority keeps the low 32 - b bits of the hash (the shift in
+ * a 32-bit type drops the rest); with b = 32 there are no priority bits. */
+uint32_t oracle_pack(uint64_t prio, int64_t v, int b)
+{
+    int pb = 32 - b;
+    uint64_t p = (pb <= 0) ? 0 : (prio & ((UINT64_C(1) << pb) - 1));
+    return (uint32_t)((p << b) | (uint64_t)(v + 1));
+}
+
+/*
+ * Algorithm 1 (Section III-A), optionally on the subgraph induced by the
+ * vertices with active[v] != 0 (the second MIS-2 of Alg. 3).
+ *
+ *   n, row_ptr[n+1], col[nnz]  symmetric CSR without self-loops
+ *   active                     NULL = every vertex; else induced subgraph
+ *   seed                       hash seed (see oracle_hash)
+ *   prio, prio_rounds          NULL = hash priorities; else injected
+ *                              priorities prio[r*n + v] for rounds r <
+ *                              prio_rounds (used for the Fig. 1 example)
+ *   status[n]                  out: 1 if v is IN, else 0
+ *   n_iters                    out: loop executions (Table I's count)
+ *   trace[cap][4]              out, may be NULL: per round, at its start,
+ *                              |wl1|, |wl2|, sum of CSR row lengths over wl1
+ *                              and over wl2
+ *   T_hist, M_hist, D_hist     out, may be NULL: [cap][n] snapshots of T
+ *                              after Refresh Row, M after Refresh Column and
+ *                              T after Decide Set
+ * Returns 0, -1 on bad arguments, -6 if injected priorities ran out.
+ */
+int oracle_mis2_ex(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                   const uint8_t *active, uint64_t seed,
+                   const uint64_t *prio, int32_t prio_rounds,
+                   uint8_t *status, int32_t *n_iters,
+                   int64_t *trace, int32_t trace_cap,
+                   uint32_t *T_hist, uint32_t *M_hist, uint32_t *D_hist,
+                   int32_t hist_cap)
+{
+    if (n < 0 || (n > 0 && (!row_ptr || !status || !n_iters)))
+        return -1;
+    if (n == 0) {
+        if (n_iters) *n_iters = 0;
+        return 0;
+    }
+    int b = oracle_id_bits(n);
+    if (b > 32)
+        return -1;
+
+    uint32_t *T = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+    uint32_t *M = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+    int64_t *wl1 = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *wl2 = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    if (!T || !M || !wl1 || !wl2) {
+        free(T); free(M); free(wl1); free(wl2);
+        return -1;
+    }
+
+    /* worklist1 <- 0..|V|, worklist2 <- 0..|V| (restricted to the subgraph).
+     * Inactive vertices are never touched and count as absent. */
+    int64_t n1 = 0, n2 = 0;
+    for (int64_t v = 0; v < n; v++) {
+        T[v] = ORACLE_OUT;
+        M[v] = ORACLE_OUT;
+        if (!active || active[v]) {
+            wl1[n1++] = v;
+            wl2[n2++] = v;
+        }
+    }
+
+    int32_t iter = 0;
+    int rc = 0;
+    while (n1 > 0) {
+        if (trace && iter < trace_cap) {
+            int64_t d1 = 0, d2 = 0;
+            for (int64_t i = 0; i < n1; i++) d1 += row_ptr[wl1[i] + 1] - row_ptr[wl1[i]];
+            for (int64_t i = 0; i < n2; i++) d2 += row_ptr[wl2[i] + 1] - row_ptr[wl2[i]];
+            trace[4 * iter + 0] = n1;
+            trace[4 * iter + 1] = n2;
+            trace[4 * iter + 2] = d1;
+            trace[4 * iter + 3] = d2;
+        }
+
+        /* Refresh Row: T_v <- h(iter, v) | v+1 for v in worklist1. */
+        for (int64_t i = 0; i < n1; i++) {
+            int64_t v = wl1[i];
+            uint64_t p;
+            if (prio) {
+                if (iter >= prio_rounds) { rc = -6; goto done; }
+                p = prio[(int64_t)iter * n + v];
+            } else {
+                p = oracle_hash(seed, (uint64_t)iter, (uint64_t)v);
+            }
+            T[v] = oracle_pack(p, v, b);
+        }
+        if (T_hist && iter < hist_cap)
+            memcpy(T_hist + (int64_t)iter * n, T, sizeof(uint32_t) * (size_t)n);
+
+        /* Refresh Column: M_v <- min of T over the closed neighbourhood
+         * adj(v) + {v}; an IN minimum becomes OUT.
+         * Reading: the neighbourhood includes v itself -- Fig. 1 shows
+         * M = (1,1) at vertex 1, whose only neighbour carries (3,2). */
+        for (int64_t i = 0; i < n2; i++) {
+            int64_t v = wl2[i];
+            uint32_t m = T[v];
+            for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+                int64_t w = col[e];
+                if (active && !active[w]) continue;
+                if (T[w] < m) m = T[w];
+            }
+            if (m == ORACLE_IN) m = ORACLE_OUT;
+            M[v] = m;
+        }
+        if (M_hist && iter < hist_cap)
+            memcpy(M_hist + (int64_t)iter * n, M, sizeof(uint32_t) * (size_t)n);
+
+        /* Decide Set for v in worklist1, both tests against t0 = T_v as it
+         * was after Refresh Row.  Reading: the two ifs are exclusive ("if
+         * some M_w is OUT then OUT, else if every M_w equals T_v then IN");
+         * for an undecided t0 they cannot both hold.  Decide Set writes only
+         * T_v and reads only M, so the order of this loop is immaterial. */
+        for (int64_t i = 0; i < n1; i++) {
+            int64_t v = wl1[i];
+            uint32_t t0 = T[v];
+            int any_out = (M[v] == ORACLE_OUT);
+            int all_eq = (M[v] == t0);
+            for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+                int64_t w = col[e];
+                if (active && !active[w]) continue;
+                if (M[w] == ORACLE_OUT) any_out = 1;
+                if (M[w] != t0) all_eq = 0;
+            }
+            if (any_out)
+                T[v] = ORACLE_OUT;
+            else if (all_eq)
+                T[v] = ORACLE_IN;
+        }
+        if (D_hist && iter < hist_cap)
+            memcpy(D_hist + (int64_t)iter * n, T, sizeof(uint32_t) * (size_t)n);
+
+        /* Compact the worklists, keeping their order (a stable filter). */
+        int64_t k = 0;
+        for (int64_t i = 0; i < n1; i++) {
+            int64_t v = wl1[i];
+            if (T[v] != ORACLE_IN && T[v] != ORACLE_OUT) wl1[k++] = v;
+        }
+        n1 = k;
+        k = 0;
+        for (int64_t i = 0; i < n2; i++) {
+            int64_t v = wl2[i];
+            if (M[v] != ORACLE_OUT) wl2[k++] = v;
+        }
+        n2 = k;
+        iter++;
+    }
+
+    /* return {v : T_v = IN} */
+    for (int64_t v = 0; v < n; v++)
+        status[v] = (uint8_t)((!active || active[v]) && T[v] == ORACLE_IN);
+    *n_iters = iter;
+
+done:
+    free(T); free(M); free(wl1); free(wl2);
+    return rc;
+}
+
+/* Algorithm 1 on the whole graph with hash priorities. */
+int oracle_mis2(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                uint64_t seed, uint8_t *status, int32_t *n_iters)
+{
+    return oracle_mis2_ex(n, row_ptr, col, NULL, seed, NULL, 0, status, n_iters,
+                          NULL, 0, NULL, NULL, NULL, 0);
+}
+
+/*
+ * Algorithm 3 (Section III-B): MIS-2 based aggregation.
+ *
+ *   agg[n]      out: aggregate of every vertex, numbered 0..n_agg-1
+ *   n_agg       out
+ *   info[8]     out, may be NULL: roots of phase 1, accepted roots of
+ *               phase 2, vertices joined in phase 3, rounds of the two
+ *               MIS-2 runs, size of the phase-2 MIS-2, vertices left
+ *               unaggregated after phase 1, 0
+ *   roots[n]    out, may be NULL: 1 = phase-1 root, 2 = accepted phase-2
+ *               root, 0 otherwise
+ *   trace1/2    out, may be NULL: per-round traces of the two MIS-2 runs
+ *               ([cap][4], as in oracle_mis2_ex)
+ * Returns 0; -1 on bad arguments; -5 if an invariant the paper guarantees
+ * fails (overlapping phase-1 aggregates, or a phase-3 vertex with no
+ * aggregated neighbour).
+ */
+int oracle_aggregate_ex(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                        uint64_t seed, int32_t *agg, int64_t *n_agg,
+                        int64_t *info, uint8_t *roots,
+                        int64_t *trace1, int64_t *trace2, int32_t trace_cap)
+{
+    if (n < 0 || !n_agg || (n > 0 && (!row_ptr || !agg)))
+        return -1;
+    if (info) memset(info, 0, 8 * sizeof(int64_t));
+    if (n == 0) { *n_agg = 0; return 0; }
+
+    uint8_t *st1 = (uint8_t *)calloc((size_t)n, 1);
+    uint8_t *st2 = (uint8_t *)calloc((size_t)n, 1);
+    uint8_t *act = (uint8_t *)calloc((size_t)n, 1);
+    int32_t *label = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *label1 = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *tent = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t *aggsize = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    int64_t *coupling = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    int rc = 0;
+    if (!st1 || !st2 || !act || !label || !label1 || !tent || !aggsize || !coupling) {
+        rc = -1;
+        goto done;
+    }
+    for (int64_t v = 0; v < n; v++) label[v] = -1;
+    if (roots) memset(roots, 0, (size_t)n);
+
+    /* Phase 1: M1 <- MIS2(G); each root and its neighbours form an
+     * aggregate.  Reading: roots are numbered in increasing vertex id. */
+    int32_t it1 = 0;
+    rc = oracle_mis2_ex(n, row_ptr, col, NULL, seed, NULL, 0, st1, &it1,
+                        trace1, trace_cap, NULL, NULL, NULL, 0);
+    if (rc) goto done;
+    int64_t na = 0;
+    for (int64_t v = 0; v < n; v++) {
+        if (!st1[v]) continue;
+        if (label[v] != -1) { rc = -5; goto done; }
+        label[v] = (int32_t)na;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+            int64_t w = col[e];
+            if (label[w] != -1) { rc = -5; goto done; }  /* roots are >= 3 apart */
+            label[w] = (int32_t)na;
+        }
+        if (roots) roots[v] = 1;
+        na++;
+    }
+    int64_t n1 = na;
+
+    /* Phase 2: M2 <- MIS2(G minus the aggregated vertices).
+     * Reading: the induced subgraph keeps the original vertex ids, the same
+     * b and restarts iter at 0. */
+    int64_t unagg = 0;
+    for (int64_t v = 0; v < n; v++) {
+        act[v] = (uint8_t)(label[v] == -1);
+        unagg += act[v];
+        label1[v] = label[v];
+    }
+    int32_t it2 = 0;
+    rc = oracle_mis2_ex(n, row_ptr, col, act, seed, NULL, 0, st2, &it2,
+                        trace2, trace_cap, NULL, NULL, NULL, 0);
+    if (rc) goto done;
+    int64_t m2 = 0;
+    for (int64_t v = 0; v < n; v++) {
+        if (!st2[v]) continue;
+        m2++;
+        /* "v has >= 2 unaggregated neighbours": neighbours u != v that are
+         * unlabelled after phase 1. */
+        int64_t cnt = 0;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++)
+            if (label1[col[e]] == -1) cnt++;
+        if (cnt < 2) continue;
+        label[v] = (int32_t)na;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+            int64_t u = col[e];
+            if (label1[u] != -1) continue;
+            if (label[u] != -1) { rc = -5; goto done; }
+            label[u] = (int32_t)na;
+        }
+        if (roots) roots[v] = 2;
+        na++;
+    }
+    int64_t n2 = na - n1;
+
+    /* Phase 3: tent <- labels (frozen); aggsize(a) and coupling(a, v) are
+     * taken over tent.  Each unaggregated v joins the aggregate with the
+     * largest coupling, a tie going to the smaller aggsize.
+     * Reading: a remaining tie goes to the smaller aggregate id. */
+    for (int64_t v = 0; v < n; v++) {
+        tent[v] = label[v];
+        if (tent[v] >= 0) aggsize[tent[v]]++;
+    }
+    int64_t joined = 0;
+    for (int64_t v = 0; v < n; v++) {
+        if (tent[v] != -1) continue;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+            int32_t a = tent[col[e]];
+            if (a >= 0) coupling[a]++;
+        }
+        int64_t best = -1;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+            int32_t a = tent[col[e]];
+            if (a < 0) continue;
+            if (best < 0 || coupling[a] > coupling[best] ||
+                (coupling[a] == coupling[best] &&
+                 (aggsize[a] < aggsize[best] ||
+                  (aggsize[a] == aggsize[best] && a < best))))
+                best = a;
+        }
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+            int32_t a = tent[col[e]];
+            if (a >= 0) coupling[a] = 0;
+        }
+        if (best < 0) { rc = -5; goto done; }
+        label[v] = (int32_t)best;
+        joined++;
+    }
+
+    memcpy(agg, label, sizeof(int32_t) * (size_t)n);
+    *n_agg = na;
+    if (info) {
+        info[0] = n1; info[1] = n2; info[2] = joined;
+        info[3] = it1; info[4] = it2; info[5] = m2; info[6] = unagg;
+    }
+
+done:
+    free(st1); free(st2); free(act); free(label); free(label1); free(tent);
+    free(aggsize); free(coupling);
+    return rc;
+}
+
+int oracle_aggregate(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                     uint64_t seed, int32_t *agg, int64_t *n_agg)
+{
+    return oracle_aggregate_ex(n, row_ptr, col, seed, agg, n_agg, NULL, NULL,
+                               NULL, NULL, 0);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Coarse graph for the next level of a multilevel coarsening.  The paper     */
+/* coarsens recursively (Sections I and II) but does not say how the coarse  */
+/* graph is formed.  Reading: the quotient graph -- vertices are the          */
+/* aggregates, and a and c are adjacent iff some edge (u, v) has agg u = a,   */
+/* agg v = c and a != c; no self-loops, no duplicates, columns ascending.     */
+/* ------------------------------------------------------------------------- */
+typedef struct { int32_t a, c; } oracle_pair;
+
+static int oracle_pair_cmp(const void *x, const void *y)
+{
+    const oracle_pair *p = (const oracle_pair *)x, *q = (const oracle_pair *)y;
+    if (p->a != q->a) return p->a < q->a ? -1 : 1;
+    if (p->c != q->c) return p->c < q->c ? -1 : 1;
+    return 0;
+}
+
+/* crow_ptr[n_agg+1] and ccol[cap] are caller-owned.  Returns the coarse nnz,
+ * -1 on bad arguments, -3 if cap is too small. */
+int64_t oracle_quotient(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                        const int32_t *agg, int64_t n_agg,
+                        int64_t *crow_ptr, int32_t *ccol, int64_t cap)
+{
+    if (n < 0 || n_agg < 0 || !crow_ptr || (n > 0 && (!row_ptr || !agg)))
+        return -1;
+    int64_t nnz = n > 0 ? row_ptr[n] : 0;
+    oracle_pair *p = (oracle_pair *)malloc(sizeof(oracle_pair) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!p) return -1;
+    int64_t k = 0;
+    for (int64_t u = 0; u < n; u++)
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; e++) {
+            int32_t a = agg[u], c = agg[col[e]];
+            if (a < 0 || a >= n_agg || c < 0 || c >= n_agg) { free(p); return -1; }
+            if (a != c) { p[k].a = a; p[k].c = c; k++; }
+        }
+    qsort(p, (size_t)k, sizeof(oracle_pair), oracle_pair_cmp);
+    int64_t m = 0;
+    for (int64_t i = 0; i < k; i++)
+        if (i == 0 || oracle_pair_cmp(&p[i], &p[i - 1]) != 0)
+            p[m++] = p[i];
+    if (m > cap || (m > 0 && !ccol)) { free(p); return -3; }
+    for (int64_t a = 0; a <= n_agg; a++) crow_ptr[a] = 0;
+    for (int64_t i = 0; i < m; i++) {
+        crow_ptr[p[i].a + 1]++;
+        ccol[i] = p[i].c;
+    }
+    for (int64_t a = 0; a < n_agg; a++) crow_ptr[a + 1] += crow_ptr[a];
+    free(p);
+    return m;
+}

@@ -1,0 +1,206 @@
+"""ctypes wrapper around oracle.c, the plain CPU reference implementation.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg use it to check and time the HIP library; the library itself
+never imports it.  The arithmetic lives in oracle.c; this file only marshals
+numpy arrays and runs the multilevel loop (a plain Python loop over
+aggregate + quotient, Sections I-II of the paper: coarsen recursively until
+the graph is below a size threshold).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+def build_oracle(force=True):
+    """Compile oracle.c with gcc into oracle/liboracle.so."""
+    global _lib
+    if not force and os.path.exists(_LIB):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC",
+                           "-shared", _SRC, "-o", tmp])
+    os.replace(tmp, _LIB)
+    _lib = None
+    return _LIB
+
+
+def _get():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build_oracle()
+        lib = ctypes.CDLL(_LIB)
+        lib.oracle_xorshift64star.restype = ctypes.c_uint64
+        lib.oracle_xorshift64star.argtypes = [ctypes.c_uint64]
+        lib.oracle_hash.restype = ctypes.c_uint64
+        lib.oracle_hash.argtypes = [ctypes.c_uint64] * 3
+        lib.oracle_id_bits.restype = ctypes.c_int
+        lib.oracle_id_bits.argtypes = [ctypes.c_int64]
+        lib.oracle_pack.restype = ctypes.c_uint32
+        lib.oracle_pack.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int]
+        lib.oracle_mis2_ex.restype = ctypes.c_int
+        lib.oracle_mis2_ex.argtypes = [
+            ctypes.c_int64, _i64p, _i32p, _u8p, ctypes.c_uint64, _u64p, ctypes.c_int32,
+            _u8p, _i32p, _i64p, ctypes.c_int32, _u32p, _u32p, _u32p, ctypes.c_int32]
+        lib.oracle_aggregate_ex.restype = ctypes.c_int
+        lib.oracle_aggregate_ex.argtypes = [
+            ctypes.c_int64, _i64p, _i32p, ctypes.c_uint64, _i32p, _i64p, _i64p, _u8p,
+            _i64p, _i64p, ctypes.c_int32]
+        lib.oracle_quotient.restype = ctypes.c_int64
+        lib.oracle_quotient.argtypes = [
+            ctypes.c_int64, _i64p, _i32p, _i32p, ctypes.c_int64, _i64p, _i32p, ctypes.c_int64]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a, t):
+    if a is None:
+        return ctypes.cast(None, t)
+    return a.ctypes.data_as(t)
+
+
+def _csr(row_ptr, col):
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    if col.size == 0:
+        col = np.zeros(1, np.int32)  # a valid pointer for an edgeless graph
+    return row_ptr, col
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def xorshift64star(x):
+    return int(_get().oracle_xorshift64star(x & 0xFFFFFFFFFFFFFFFF))
+
+
+def hash_priority(seed, it, v):
+    return int(_get().oracle_hash(seed, it, v))
+
+
+def id_bits(n):
+    return int(_get().oracle_id_bits(n))
+
+
+def pack(prio, v, b):
+    return int(_get().oracle_pack(prio & 0xFFFFFFFFFFFFFFFF, v, b))
+
+
+TRACE_CAP = 4096
+
+
+def mis2_ex(row_ptr, col, seed=0, active=None, prio=None, history=0):
+    """Alg. 1 with everything exposed.  Returns a dict with status (u8[n]),
+    n_iters, trace (int64[rounds, 4]) and, when history > 0, T/M/D snapshots
+    of shape [min(rounds, history), n]."""
+    row_ptr, col = _csr(row_ptr, col)
+    n = row_ptr.size - 1
+    status = np.zeros(max(n, 1), np.uint8)
+    it = ctypes.c_int32(0)
+    trace = np.zeros((TRACE_CAP, 4), np.int64)
+    act = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
+    pr = None
+    rounds = 0
+    if prio is not None:
+        pr = np.ascontiguousarray(prio, dtype=np.uint64)
+        rounds = pr.shape[0]
+        pr = pr.reshape(-1)
+    hist = None
+    if history:
+        hist = [np.zeros((history, max(n, 1)), np.uint32) for _ in range(3)]
+    rc = _get().oracle_mis2_ex(
+        n, _ptr(row_ptr, _i64p), _ptr(col, _i32p), _ptr(act, _u8p), seed,
+        _ptr(pr, _u64p), rounds, _ptr(status, _u8p), ctypes.byref(it),
+        _ptr(trace, _i64p), TRACE_CAP,
+        *(_ptr(h, _u32p) for h in (hist or [None] * 3)), history)
+    if rc:
+        raise OracleError("oracle_mis2_ex returned %d" % rc)
+    r = it.value
+    out = {"status": status[:n], "n_iters": r, "trace": trace[:min(r, TRACE_CAP)].copy()}
+    if history:
+        k = min(r, history)
+        out["T"], out["M"], out["D"] = (h[:k, :n] for h in hist)
+    return out
+
+
+def mis2(row_ptr, col, seed=0):
+    """Alg. 1: returns (status u8[n], n_iters)."""
+    o = mis2_ex(row_ptr, col, seed)
+    return o["status"], o["n_iters"]
+
+
+def aggregate(row_ptr, col, seed=0, detail=False):
+    """Alg. 3: returns (agg int32[n], n_agg) or, with detail, a dict that also
+    holds per-phase counts, root marks and the two MIS-2 traces."""
+    row_ptr, col = _csr(row_ptr, col)
+    n = row_ptr.size - 1
+    agg = np.zeros(max(n, 1), np.int32)
+    nagg = ctypes.c_int64(0)
+    info = np.zeros(8, np.int64)
+    roots = np.zeros(max(n, 1), np.uint8)
+    t1 = np.zeros((TRACE_CAP, 4), np.int64)
+    t2 = np.zeros((TRACE_CAP, 4), np.int64)
+    rc = _get().oracle_aggregate_ex(
+        n, _ptr(row_ptr, _i64p), _ptr(col, _i32p), seed, _ptr(agg, _i32p),
+        ctypes.byref(nagg), _ptr(info, _i64p), _ptr(roots, _u8p),
+        _ptr(t1, _i64p), _ptr(t2, _i64p), TRACE_CAP)
+    if rc:
+        raise OracleError("oracle_aggregate_ex returned %d" % rc)
+    if not detail:
+        return agg[:n], int(nagg.value)
+    return {"agg": agg[:n], "n_agg": int(nagg.value), "n1": int(info[0]),
+            "n2": int(info[1]), "joined": int(info[2]), "iters1": int(info[3]),
+            "iters2": int(info[4]), "m2": int(info[5]), "unagg1": int(info[6]),
+            "roots": roots[:n], "trace1": t1[:min(int(info[3]), TRACE_CAP)].copy(),
+            "trace2": t2[:min(int(info[4]), TRACE_CAP)].copy()}
+
+
+def quotient(row_ptr, col, agg, n_agg):
+    """Coarse (quotient) graph of an aggregation: returns (row_ptr, col)."""
+    row_ptr, col = _csr(row_ptr, col)
+    n = row_ptr.size - 1
+    agg = np.ascontiguousarray(agg, dtype=np.int32)
+    if agg.size == 0:
+        agg = np.zeros(1, np.int32)
+    cap = int(row_ptr[-1]) if n > 0 else 0
+    crow = np.zeros(n_agg + 1, np.int64)
+    ccol = np.zeros(max(cap, 1), np.int32)
+    m = _get().oracle_quotient(n, _ptr(row_ptr, _i64p), _ptr(col, _i32p),
+                               _ptr(agg, _i32p), n_agg, _ptr(crow, _i64p),
+                               _ptr(ccol, _i32p), cap)
+    if m < 0:
+        raise OracleError("oracle_quotient returned %d" % m)
+    return crow, ccol[:m].copy()
+
+
+def coarsen(row_ptr, col, seed=0, stop_below=1000, max_levels=64):
+    """Multilevel coarsening: aggregate, then take the quotient graph, while
+    the graph has at least stop_below vertices; stop early when a level does
+    not shrink.  Reading: every level uses the same seed.  Returns a list of
+    per-level dicts {n, nnz, agg, n_agg}; the coarse graph of level l is the
+    input of level l + 1."""
+    row_ptr, col = np.asarray(row_ptr, np.int64), np.asarray(col, np.int32)
+    levels = []
+    while row_ptr.size - 1 >= stop_below and len(levels) < max_levels:
+        n = row_ptr.size - 1
+        agg, n_agg = aggregate(row_ptr, col, seed)
+        levels.append({"n": n, "nnz": int(row_ptr[-1]), "agg": agg, "n_agg": n_agg})
+        if n_agg == n:
+            break
+        row_ptr, col = quotient(row_ptr, col, agg, n_agg)
+    return levels
