@@ -1,0 +1,76 @@
+"""ctypes loader for libmis2.so (the C ABI in include/mis2.h).
+
+There is no fallback: if the HIP library is missing, loading raises.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmis2.so")
+
+MIS2_OK = 0
+MIS2_EINVAL = -1
+MIS2_EGRAPH = -2
+MIS2_ENOSPACE = -3
+MIS2_EHIP = -4
+MIS2_EINTERNAL = -5
+
+MIS2_OP_MIS2 = 0
+MIS2_OP_AGGREGATE = 1
+MIS2_OP_COARSEN = 2
+
+MIS2_OPT_VALIDATE = 0
+MIS2_OPT_LANES_PER_ROW = 1
+MIS2_OPT_GRID_BLOCKS = 2
+
+# Every symbol include/mis2.h declares.
+EXPORTS = (
+    "mis2_create", "mis2_destroy", "mis2_last_error", "mis2_set_option",
+    "mis2_workspace_bytes", "mis2_set_workspace", "mis2_run", "mis2_last_trace",
+    "mis2_aggregate",
+)
+
+
+class Mis2Graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+
+
+class Mis2Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("mis2 error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libmis2.so and declare its signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libmis2.so is not built (run __graft_entry__.build() or "
+                           "python -m paper_2204_02934_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
+    gp = ctypes.POINTER(Mis2Graph)
+    sig = {
+        "mis2_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int]),
+        "mis2_destroy": (None, [vp]),
+        "mis2_last_error": (ctypes.c_char_p, [vp]),
+        "mis2_set_option": (ctypes.c_int, [vp, ctypes.c_int, i64]),
+        "mis2_workspace_bytes": (ctypes.c_int, [i64, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+        "mis2_set_workspace": (ctypes.c_int, [vp, vp, ctypes.c_size_t]),
+        "mis2_run": (ctypes.c_int, [vp, gp, u64, vp, ctypes.POINTER(i64), ctypes.POINTER(i32), vp]),
+        "mis2_last_trace": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(i64), i32,
+                                           ctypes.POINTER(i32)]),
+        "mis2_aggregate": (ctypes.c_int, [vp, gp, u64, vp, ctypes.POINTER(i64), vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib

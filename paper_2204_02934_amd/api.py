@@ -1,0 +1,142 @@
+"""Python binding of the MIS-2 library: argument marshalling only.
+
+PyTorch provides device memory (inputs, outputs, workspace) and the HIP
+stream; every step of the computation runs in libmis2.so's kernels.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import Mis2Error, Mis2Graph
+
+
+def _check(lib, ctx, rc):
+    if rc != _lib.MIS2_OK:
+        msg = lib.mis2_last_error(ctx)
+        raise Mis2Error(rc, msg.decode() if msg else "")
+
+
+def _stream_ptr(stream, device):
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def as_device_csr(row_ptr, col, device="cuda"):
+    """(row_ptr int64, col int32) as contiguous tensors on `device`."""
+    rp = torch.as_tensor(np.asarray(row_ptr) if not torch.is_tensor(row_ptr) else row_ptr)
+    cc = torch.as_tensor(np.asarray(col) if not torch.is_tensor(col) else col)
+    rp = rp.to(device=device, dtype=torch.int64).contiguous()
+    cc = cc.to(device=device, dtype=torch.int32).contiguous()
+    if cc.numel() == 0:
+        cc = torch.zeros(1, dtype=torch.int32, device=device)  # a valid pointer
+    return rp, cc
+
+
+class Context:
+    """One mis2_ctx bound to a GPU, with a torch-allocated workspace that grows
+    on demand (allocation happens outside the library calls)."""
+
+    def __init__(self, device=None, validate=False, lanes=0, blocks=0):
+        self.lib = _lib.load()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.ptr = ctypes.c_void_p()
+        _check(self.lib, None, self.lib.mis2_create(ctypes.byref(self.ptr), self.device.index or 0))
+        self._ws = None
+        self.set_option(_lib.MIS2_OPT_VALIDATE, int(validate))
+        self.set_option(_lib.MIS2_OPT_LANES_PER_ROW, lanes)
+        self.set_option(_lib.MIS2_OPT_GRID_BLOCKS, blocks)
+
+    def __del__(self):
+        lib = getattr(self, "lib", None)
+        if lib is not None and getattr(self, "ptr", None):
+            lib.mis2_destroy(self.ptr)
+            self.ptr = None
+
+    def set_option(self, option, value):
+        _check(self.lib, self.ptr, self.lib.mis2_set_option(self.ptr, option, int(value)))
+
+    def workspace_bytes(self, n, op):
+        b = ctypes.c_size_t(0)
+        _check(self.lib, self.ptr, self.lib.mis2_workspace_bytes(int(n), op, ctypes.byref(b)))
+        return b.value
+
+    def ensure_workspace(self, n, op):
+        need = self.workspace_bytes(n, op)
+        if self._ws is None or self._ws.numel() < need:
+            # torch's caching allocator returns 512-byte aligned blocks
+            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+            _check(self.lib, self.ptr, self.lib.mis2_set_workspace(
+                self.ptr, ctypes.c_void_p(self._ws.data_ptr()), self._ws.numel()))
+        return self._ws
+
+    def graph(self, row_ptr, col, nnz=None):
+        rp, cc = as_device_csr(row_ptr, col, self.device)
+        n = rp.numel() - 1
+        if nnz is None:
+            nnz = int(rp[-1].item())
+        return Mis2Graph(n, nnz, rp.data_ptr(), cc.data_ptr()), (rp, cc)
+
+    def mis2(self, row_ptr, col, seed=0, stream=None, nnz=None):
+        """Algorithm 1.  Returns (status uint8[n] on the GPU, n_roots, n_iters)."""
+        g, keep = self.graph(row_ptr, col, nnz)
+        self.ensure_workspace(g.n, _lib.MIS2_OP_MIS2)
+        status = torch.empty(max(g.n, 1), dtype=torch.uint8, device=self.device)
+        nr, ni = ctypes.c_int64(0), ctypes.c_int32(0)
+        rc = self.lib.mis2_run(self.ptr, ctypes.byref(g), ctypes.c_uint64(seed),
+                               ctypes.c_void_p(status.data_ptr()), ctypes.byref(nr),
+                               ctypes.byref(ni), _stream_ptr(stream, self.device))
+        _check(self.lib, self.ptr, rc)
+        del keep
+        return status[:g.n], nr.value, ni.value
+
+    def aggregate(self, row_ptr, col, seed=0, stream=None, nnz=None, want_roots=False):
+        """Algorithm 3.  Returns (agg int32[n] on the GPU, n_agg) or, with
+        want_roots, (agg, n_agg, roots uint8[n])."""
+        g, keep = self.graph(row_ptr, col, nnz)
+        self.ensure_workspace(g.n, _lib.MIS2_OP_AGGREGATE)
+        agg = torch.empty(max(g.n, 1), dtype=torch.int32, device=self.device)
+        roots = torch.empty(max(g.n, 1), dtype=torch.uint8, device=self.device) if want_roots else None
+        na = ctypes.c_int64(0)
+        rc = self.lib.mis2_aggregate(self.ptr, ctypes.byref(g), ctypes.c_uint64(seed),
+                                     ctypes.c_void_p(agg.data_ptr()), ctypes.byref(na),
+                                     ctypes.c_void_p(roots.data_ptr() if roots is not None else 0),
+                                     _stream_ptr(stream, self.device))
+        _check(self.lib, self.ptr, rc)
+        del keep
+        if want_roots:
+            return agg[:g.n], na.value, roots[:g.n]
+        return agg[:g.n], na.value
+
+    def last_trace(self, phase=0, cap=4096):
+        """Per-round (|worklist1|, |worklist2|) of the last call, int64[rounds, 2]."""
+        buf = (ctypes.c_int64 * (2 * cap))()
+        r = ctypes.c_int32(0)
+        _check(self.lib, self.ptr, self.lib.mis2_last_trace(self.ptr, phase, buf, cap, ctypes.byref(r)))
+        k = min(r.value, cap)
+        return np.ctypeslib.as_array(buf)[:2 * k].reshape(k, 2).copy()
+
+
+_default = {}
+
+
+def default_context(device=None):
+    if device is None:
+        device = torch.cuda.current_device()
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def mis2(row_ptr, col, seed=0, stream=None):
+    """Deterministic MIS-2 (Algorithm 1): (status, n_roots, n_iters)."""
+    return default_context().mis2(row_ptr, col, seed, stream)
+
+
+def aggregate(row_ptr, col, seed=0, stream=None):
+    """MIS-2 aggregation (Algorithm 3): (agg_id, n_agg)."""
+    return default_context().aggregate(row_ptr, col, seed, stream)

@@ -1,0 +1,154 @@
+// compact.hip -- order-preserving stream compaction for gfx950.
+//
+// out = [v in 0..n-1 : pred(v)] in increasing v.  Used wherever a numbering
+// must be deterministic: aggregate ids are ranks of roots in increasing
+// vertex id, so the positions here are exact prefix sums (no atomics).
+// Three launches: per-tile counts, one-workgroup scan of the tile counts,
+// per-tile scatter with a workgroup scan built from wave64 ballots.
+#include "internal.h"
+
+namespace mis2 {
+
+namespace {
+
+constexpr int kItems = 8;                  // elements per thread per tile
+constexpr int kTile = kBlock * kItems;     // 2048 elements per tile
+constexpr int kWaves = kBlock / 64;
+
+struct PredU32Eq {
+    const uint32_t *a;
+    uint32_t value;
+    __device__ bool operator()(int64_t i) const { return a[i] == value; }
+};
+struct PredI32Eq {
+    const int32_t *a;
+    int32_t value;
+    __device__ bool operator()(int64_t i) const { return a[i] == value; }
+};
+struct PredU8Nz {
+    const uint8_t *a;
+    __device__ bool operator()(int64_t i) const { return a[i] != 0; }
+};
+
+__device__ __forceinline__ uint64_t lanes_below(int lane) {
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+template <class P>
+__global__ __launch_bounds__(kBlock) void k_tile_count(P pred, int64_t n,
+                                                       uint32_t *__restrict__ blocksum) {
+    __shared__ uint32_t part[kWaves];
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; j++) {
+        const int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
+        if (i < n && pred(i)) c++;
+    }
+    for (int off = 32; off > 0; off >>= 1) c += (uint32_t)__shfl_xor((int)c, off, 64);
+    if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kWaves; w++) t += part[w];
+        blocksum[blockIdx.x] = t;
+    }
+}
+
+// Exclusive scan of blocksum[0..nb) in place; the total goes to
+// blocksum[nb] and *d_count.  One workgroup, chunks of kBlock with a carry.
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(uint32_t *__restrict__ blocksum, int64_t nb,
+                                                       uint32_t *__restrict__ d_count) {
+    __shared__ uint32_t wsum[kWaves];
+    __shared__ uint32_t carry_s;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    const int lane = (int)(threadIdx.x & 63u), wave = (int)(threadIdx.x >> 6);
+    for (int64_t c0 = 0; c0 < nb; c0 += kBlock) {
+        const int64_t i = c0 + threadIdx.x;
+        const uint32_t x = i < nb ? blocksum[i] : 0u;
+        // inclusive scan inside the wavefront
+        uint32_t incl = x;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t before = carry_s;
+        for (int w = 0; w < wave; w++) before += wsum[w];
+        if (i < nb) blocksum[i] = before + incl - x;
+        __syncthreads();
+        if (threadIdx.x == kBlock - 1) carry_s = before + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        blocksum[nb] = carry_s;
+        *d_count = carry_s;
+    }
+}
+
+template <class P>
+__global__ __launch_bounds__(kBlock) void k_tile_scatter(P pred, int64_t n,
+                                                         const uint32_t *__restrict__ blocksum,
+                                                         int32_t *__restrict__ out) {
+    __shared__ uint32_t wcount[kItems][kWaves];
+    const int lane = (int)(threadIdx.x & 63u), wave = (int)(threadIdx.x >> 6);
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    uint64_t masks[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; j++) {
+        const int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
+        const bool p = i < n && pred(i);
+        masks[j] = __ballot(p);
+        if (lane == 0) wcount[j][wave] = (uint32_t)__popcll(masks[j]);
+    }
+    __syncthreads();
+    uint32_t run = blocksum[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < kItems; j++) {
+        uint32_t before = run;
+        for (int w = 0; w < wave; w++) before += wcount[j][w];
+        const int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
+        if ((masks[j] >> lane) & 1ull)
+            out[before + (uint32_t)__popcll(masks[j] & lanes_below(lane))] = (int32_t)i;
+        for (int w = 0; w < kWaves; w++) run += wcount[j][w];
+    }
+}
+
+template <class P>
+hipError_t compact(P pred, int64_t n, int32_t *out, uint32_t *d_count, uint32_t *blocksum,
+                   hipStream_t s) {
+    const int64_t nb = compact_blocks(n);
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_tile_count<P>, dim3((unsigned)nb), dim3(kBlock), 0, s, pred, n,
+                           blocksum);
+    }
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kBlock), 0, s, blocksum, nb, d_count);
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_tile_scatter<P>, dim3((unsigned)nb), dim3(kBlock), 0, s, pred, n,
+                           blocksum, out);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t compact_blocks(int64_t n) { return n <= 0 ? 0 : (n + kTile - 1) / kTile; }
+
+hipError_t compact_u32_eq(const uint32_t *a, uint32_t value, int64_t n, int32_t *out,
+                          uint32_t *d_count, uint32_t *blocksum, hipStream_t s) {
+    return compact(PredU32Eq{a, value}, n, out, d_count, blocksum, s);
+}
+
+hipError_t compact_i32_eq(const int32_t *a, int32_t value, int64_t n, int32_t *out,
+                          uint32_t *d_count, uint32_t *blocksum, hipStream_t s) {
+    return compact(PredI32Eq{a, value}, n, out, d_count, blocksum, s);
+}
+
+hipError_t compact_u8_nz(const uint8_t *a, int64_t n, int32_t *out, uint32_t *d_count,
+                         uint32_t *blocksum, hipStream_t s) {
+    return compact(PredU8Nz{a}, n, out, d_count, blocksum, s);
+}
+
+}  // namespace mis2

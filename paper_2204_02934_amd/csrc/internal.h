@@ -1,0 +1,159 @@
+// internal.h -- shared declarations of the gfx950 MIS-2 library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "mis2.h"
+
+namespace mis2 {
+
+// Packed status values (Section V-C): IN = 0 < undecided tuples < OUT = UINT_MAX.
+constexpr uint32_t kIn = 0u;
+constexpr uint32_t kOut = 0xFFFFFFFFu;
+// M value of a vertex outside the induced subgraph of a masked run.  A real
+// M is never 0 because Refresh Column turns an IN minimum into OUT, so the
+// value can mark "absent" without a separate mask array.
+constexpr uint32_t kAbsent = 0u;
+
+constexpr int kBlock = 256;       // threads per workgroup (4 wave64s)
+constexpr int kTraceCap = 1024;   // rounds whose worklist sizes are recorded
+constexpr int kRing = 4;          // per-round counter slots, slot = round % kRing
+constexpr int kScalars = 64;      // misc device scalars
+
+// Section V-A: f = xorshift64* (Vigna's parameters 12, 25, 27 and multiplier
+// 2685821657736338717, arithmetic mod 2^64); h(i, v) = f(f(i) ^ f(v)).
+__host__ __device__ __forceinline__ uint64_t xs64star(uint64_t x) {
+    x ^= x >> 12;
+    x ^= x << 25;
+    x ^= x >> 27;
+    return x * 0x2545F4914F6CDD1Dull;
+}
+
+// What a kernel needs to build the packed tuple of one round.
+struct TupleParams {
+    uint64_t f_iter;  // f((seed << 32) ^ iter): the per-round half of h
+    uint64_t pmask;   // 2^(32-b) - 1, or 0 when b = 32
+    uint32_t b;       // id bits, the smallest b with 2^b >= n + 2
+};
+
+// Section V-C: (priority << b) | (v + 1); the priority keeps the low 32 - b
+// bits of h.
+__device__ __forceinline__ uint32_t make_tuple(const TupleParams &p, uint32_t v) {
+    const uint64_t h = xs64star(p.f_iter ^ xs64star((uint64_t)v));
+    return (uint32_t)(((h & p.pmask) << p.b) | (uint64_t)(v + 1u));
+}
+
+int id_bits(int64_t n);
+TupleParams tuple_params(int64_t n, uint64_t seed, uint64_t iter);
+
+// Scalar slots in Workspace::scalars.
+enum Scalar {
+    kS_Roots = 0,     // |MIS-2| of mis2_run
+    kS_Count1 = 1,    // phase-1 root count (aggregation)
+    kS_Active = 2,    // vertices left after phase 1
+    kS_Count2 = 3,    // accepted phase-2 roots
+    kS_Left = 4,      // vertices left after phase 2
+    kS_Err = 5,       // error bits
+    kS_Zero = 7,      // stays 0
+};
+
+// The caller's workspace, carved into arrays (all 256-byte aligned).
+struct Workspace {
+    uint32_t *T = nullptr;        // [n] packed row status tuples
+    uint32_t *M = nullptr;        // [n] radius-1 minima
+    int32_t *wl1[2] = {};         // [n] undecided vertices, double buffered
+    int32_t *wl2[2] = {};         // [n] vertices without an IN neighbour, double buffered
+    uint32_t *ring = nullptr;     // [2][kRing] worklist sizes (list 0 = wl1, 1 = wl2)
+    uint32_t *trace = nullptr;    // [kTraceCap][2] sizes at the start of each round
+    uint32_t *scalars = nullptr;  // [kScalars]
+    // aggregation only
+    int32_t *label = nullptr;     // [n] aggregate labels, -1 = none
+    int32_t *list = nullptr;      // [n] ordered vertex lists
+    uint8_t *flag = nullptr;      // [n]
+    int32_t *aggsize = nullptr;   // [n]
+    uint32_t *blocksum = nullptr; // [compact_blocks(n) + 1]
+    int32_t *active = nullptr;    // [n] vertices of an induced subgraph
+};
+
+size_t workspace_bytes(int64_t n, int op);
+bool carve(void *base, size_t bytes, int64_t n, int op, Workspace *ws);
+
+// Launch-plan knobs; never change results.
+struct Plan {
+    int lanes = 0;   // lanes per CSR row (power of two <= 64); 0 = automatic
+    int blocks = 0;  // workgroups per sweep; 0 = automatic
+};
+
+// One sweep's worklist plumbing.  cnt_in == nullptr means the identity list
+// 0..identity_n-1.  cnt_zero (may be null) is cleared by the sweep for a
+// later round; trace_slot (may be null) receives the input size.
+struct SweepIO {
+    const int32_t *wl_in;
+    const uint32_t *cnt_in;
+    int64_t identity_n;
+    int32_t *wl_out;
+    uint32_t *cnt_out;
+    uint32_t *cnt_zero;
+    uint32_t *trace_slot;
+};
+
+// mis2_kernels.hip
+hipError_t launch_init_tuples(const TupleParams &tp, int64_t n, uint32_t *T, uint32_t *ring,
+                              hipStream_t s);
+hipError_t launch_init_masked(const TupleParams &tp, int64_t n, const int32_t *label, uint32_t *T,
+                              uint32_t *M, uint32_t *ring, hipStream_t s);
+hipError_t launch_refresh_column(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
+                                 const uint32_t *T, uint32_t *M, const SweepIO &io, hipStream_t s);
+hipError_t launch_decide(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
+                         uint32_t *T, const uint32_t *M, const TupleParams &next,
+                         const SweepIO &io, hipStream_t s);
+hipError_t launch_status(int64_t n, const uint32_t *T, uint8_t *status, uint32_t *count,
+                         hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t count, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t *p, uint8_t value, int64_t count, hipStream_t s);
+hipError_t launch_validate(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                           uint32_t *err, hipStream_t s);
+
+// compact.hip: out = [v : pred(v)] in increasing v, size -> *d_count.
+// blocksum needs compact_blocks(n) + 1 entries.
+int64_t compact_blocks(int64_t n);
+hipError_t compact_u32_eq(const uint32_t *a, uint32_t value, int64_t n, int32_t *out,
+                          uint32_t *d_count, uint32_t *blocksum, hipStream_t s);
+hipError_t compact_i32_eq(const int32_t *a, int32_t value, int64_t n, int32_t *out,
+                          uint32_t *d_count, uint32_t *blocksum, hipStream_t s);
+hipError_t compact_u8_nz(const uint8_t *a, int64_t n, int32_t *out, uint32_t *d_count,
+                         uint32_t *blocksum, hipStream_t s);
+
+// aggregate.hip
+hipError_t launch_label_roots(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                              const int32_t *roots, const uint32_t *d_count,
+                              const uint32_t *d_base, bool only_unlabelled, int32_t *label,
+                              uint8_t *root_mark, uint8_t mark, hipStream_t s);
+hipError_t launch_accept_phase2(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                                const uint32_t *T, const int32_t *label, uint8_t *flag,
+                                hipStream_t s);
+hipError_t launch_aggsize(int64_t n, const int32_t *label, int32_t *aggsize, hipStream_t s);
+hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStream_t s);
+hipError_t launch_phase3(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                         const int32_t *label, const int32_t *aggsize, const int32_t *rows,
+                         const uint32_t *d_rows, int32_t *agg_out, uint32_t *err, hipStream_t s);
+
+}  // namespace mis2
+
+// Context (abi.hip).
+struct mis2_ctx {
+    int device = 0;
+    int num_cus = 256;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    uint32_t *pinned = nullptr;  // host-pinned scalars for read-back
+    std::string err;
+    int validate = 0;
+    mis2::Plan plan;
+    std::vector<int64_t> trace[2];  // per-round |wl1|, |wl2| of the last run(s)
+};

@@ -140,13 +140,13 @@ def chung_lu(n, mean_deg=16.0, gamma=2.1, cap=20000, seed=1, permute_ids=True):
     cdf /= cdf[-1]
     rng = np.random.default_rng(seed)
     m = int(round(n * mean_deg / 2.0))
-    u = np.empty(m, np.int64)
-    v = np.empty(m, np.int64)
-    chunk = 1 << 22
-    for s in range(0, m, chunk):
-        e = min(m, s + chunk)
-        u[s:e] = np.searchsorted(cdf, rng.random(e - s), side="right")
-        v[s:e] = np.searchsorted(cdf, rng.random(e - s), side="right")
+    # Inverse-CDF draws of the two endpoint columns.  Each column's uniforms
+    # are sorted before the search (a cache-friendly search) and the second
+    # column is then shuffled; a sorted i.i.d. column paired with an
+    # independent shuffled i.i.d. column has the law of i.i.d. pairs.
+    u = np.searchsorted(cdf, np.sort(rng.random(m)), side="right").astype(np.int64)
+    v = np.searchsorted(cdf, np.sort(rng.random(m)), side="right").astype(np.int64)
+    v = v[rng.permutation(m)]
     np.minimum(u, n - 1, out=u)
     np.minimum(v, n - 1, out=v)
     if permute_ids:

@@ -1,0 +1,201 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle, bit for
+bit, on seeded graphs: MIS-2 status, round counts and per-round worklist
+sizes (Algorithm 1), aggregation labels, aggregate counts and root marks
+(Algorithm 3).  Every result is integer, so the bar is exact equality."""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2204_02934_amd import graphs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2204_02934_amd import api as a
+    return a
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    return api.Context(0)
+
+
+def _small_graphs():
+    out = [("edgeless1", graphs.edgeless(1)), ("edgeless100", graphs.edgeless(100)),
+           ("path2", graphs.path(2)), ("path3", graphs.path(3)), ("path101", graphs.path(101)),
+           ("cycle64", graphs.cycle(64)), ("complete40", graphs.complete(40)),
+           ("star70", graphs.star(70, 0)), ("star70b", graphs.star(70, 69)),
+           ("grid2d_64", graphs.grid2d_5pt(64, 64)), ("grid2d_ragged", graphs.grid2d_5pt(37, 29)),
+           ("grid7_17", graphs.grid3d_7pt(17, 13, 11)), ("grid27_30", graphs.grid3d_27pt(30, 30, 30)),
+           ("grid27_ragged", graphs.grid3d_27pt(23, 19, 7)),
+           ("chunglu_50k", graphs.chung_lu(50000, 16.0, 2.1, 3000, seed=5)),
+           ("dropped7_20", graphs.dropped_7pt(20, 0.1, seed=3)),
+           ("union", graphs.disjoint_union([graphs.grid2d_5pt(10, 10), graphs.complete(9),
+                                            graphs.edgeless(5), graphs.path(17)]))]
+    rng = np.random.default_rng(9)
+    for k in range(6):
+        n = int(rng.integers(2, 3000))
+        out.append(("er%d" % k, graphs.erdos_renyi(n, float(min(0.5, 8.0 / n)), seed=k)))
+    return out
+
+
+SMALL = _small_graphs()
+
+
+def _check_mis2(ctx, rp, c, seed=0, name=""):
+    status, nr, it = ctx.mis2(rp, c, seed)
+    o = oracle.mis2_ex(rp, c, seed)
+    got = status.cpu().numpy()
+    assert np.array_equal(got, o["status"]), name
+    assert it == o["n_iters"], (name, it, o["n_iters"])
+    assert nr == int(o["status"].sum())
+    tr = ctx.last_trace(0)
+    assert np.array_equal(tr, o["trace"][:, :2]), name
+
+
+@pytest.mark.parametrize("name", [s[0] for s in SMALL])
+def test_mis2_parity_small(ctx, name):
+    rp, c = dict(SMALL)[name]
+    _say("mis2 parity", name, rp.size - 1, int(rp[-1]))
+    _check_mis2(ctx, rp, c, 0, name)
+
+
+def test_mis2_empty_graph(ctx):
+    status, nr, it = ctx.mis2(np.zeros(1, np.int64), np.zeros(0, np.int32))
+    assert status.numel() == 0 and nr == 0 and it == 0
+
+
+@pytest.mark.parametrize("seed", [1, 7, 2**31 + 5])
+def test_mis2_parity_seeds(ctx, seed):
+    rp, c = graphs.grid3d_27pt(21, 20, 19)
+    _check_mis2(ctx, rp, c, seed, "seed%d" % seed)
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
+def test_mis2_every_lane_plan(api, lanes):
+    for blocks in (1, 13, 0):
+        c = api.Context(0, lanes=lanes, blocks=blocks)
+        for name in ("grid27_ragged", "chunglu_50k", "star70"):
+            rp, cc = dict(SMALL)[name]
+            _check_mis2(c, rp, cc, 0, "%s L%d B%d" % (name, lanes, blocks))
+
+
+def test_mis2_repeatable(ctx):
+    rp, c = dict(SMALL)["chunglu_50k"]
+    first = ctx.mis2(rp, c, 0)[0].cpu().numpy()
+    for _ in range(5):
+        assert np.array_equal(ctx.mis2(rp, c, 0)[0].cpu().numpy(), first)
+
+
+def _check_agg(ctx, rp, c, seed=0, name=""):
+    agg, na, roots = ctx.aggregate(rp, c, seed, want_roots=True)
+    d = oracle.aggregate(rp, c, seed, detail=True)
+    assert na == d["n_agg"], (name, na, d["n_agg"])
+    assert np.array_equal(roots.cpu().numpy(), d["roots"]), name
+    assert np.array_equal(agg.cpu().numpy(), d["agg"]), name
+    assert np.array_equal(ctx.last_trace(0), d["trace1"][:, :2]), name
+    assert np.array_equal(ctx.last_trace(1), d["trace2"][:, :2]), name
+
+
+@pytest.mark.parametrize("name", [s[0] for s in SMALL])
+def test_aggregate_parity_small(ctx, name):
+    rp, c = dict(SMALL)[name]
+    _say("aggregate parity", name, rp.size - 1, int(rp[-1]))
+    _check_agg(ctx, rp, c, 0, name)
+
+
+@pytest.mark.parametrize("lanes", [1, 8, 64])
+def test_aggregate_lane_plans(api, lanes):
+    c = api.Context(0, lanes=lanes, blocks=7)
+    for name in ("grid27_ragged", "chunglu_50k", "path101"):
+        rp, cc = dict(SMALL)[name]
+        _check_agg(c, rp, cc, 3, name)
+
+
+def test_aggregate_empty(ctx):
+    agg, na = ctx.aggregate(np.zeros(1, np.int64), np.zeros(0, np.int32))
+    assert agg.numel() == 0 and na == 0
+
+
+# ---------------------------------------------------------------- full sizes
+@functools.lru_cache(maxsize=None)
+def _c1():
+    return graphs.grid2d_5pt(64, 64)
+
+
+@functools.lru_cache(maxsize=None)
+def _c2():
+    return graphs.grid3d_27pt(100, 100, 100)
+
+
+@functools.lru_cache(maxsize=None)
+def _c3():
+    return graphs.chung_lu(4_000_000, 16.0, 2.1, 20000, seed=1)
+
+
+def test_c1_grid2d_64(ctx):
+    rp, c = _c1()
+    _check_mis2(ctx, rp, c, 0, "C1")
+    _check_agg(ctx, rp, c, 0, "C1")
+
+
+def test_c2_grid27_100(ctx):
+    rp, c = _c2()
+    _say("C2 27-point 100^3", rp.size - 1, int(rp[-1]))
+    _check_mis2(ctx, rp, c, 0, "C2")
+    _check_agg(ctx, rp, c, 0, "C2")
+
+
+def test_c3_chung_lu_4m(ctx):
+    rp, c = _c3()
+    _say("C3 Chung-Lu", rp.size - 1, int(rp[-1]))
+    _check_mis2(ctx, rp, c, 0, "C3")
+    _check_agg(ctx, rp, c, 0, "C3")
+
+
+# ---------------------------------------------------------------- error paths
+def test_invalid_csr_rejected_when_validating(api):
+    from paper_2204_02934_amd._lib import Mis2Error
+    c = api.Context(0, validate=True)
+    rp = np.array([0, 1, 2], np.int64)
+    for bad_col in ([1, 5], [0, 0], [-1, 0]):  # out of range, self-loop, negative
+        with pytest.raises(Mis2Error) as e:
+            c.mis2(rp, np.array(bad_col, np.int32))
+        assert e.value.code == -2
+    with pytest.raises(Mis2Error) as e:
+        c.mis2(np.array([0, 2, 1], np.int64), np.array([1, 0], np.int32))
+    assert e.value.code == -2
+    # a valid graph still passes with validation on
+    rp, cc = graphs.grid2d_5pt(9, 9)
+    _check_mis2(c, rp, cc, 0, "validated")
+
+
+def test_workspace_too_small(api):
+    import ctypes
+    import torch
+    from paper_2204_02934_amd import _lib
+    from paper_2204_02934_amd._lib import Mis2Error
+    c = api.Context(0)
+    rp, cc = graphs.grid2d_5pt(20, 20)
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    assert c.lib.mis2_set_workspace(c.ptr, ctypes.c_void_p(ws.data_ptr()), 1024) == 0
+    g, keep = c.graph(rp, cc)
+    st = torch.empty(400, dtype=torch.uint8, device="cuda")
+    rc = c.lib.mis2_run(c.ptr, ctypes.byref(g), 0, ctypes.c_void_p(st.data_ptr()), None, None,
+                        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == _lib.MIS2_ENOSPACE
+    assert b"workspace" in c.lib.mis2_last_error(c.ptr)
+    with pytest.raises(Mis2Error):
+        c.set_option(_lib.MIS2_OPT_LANES_PER_ROW, 3)
