@@ -1,0 +1,218 @@
+"""Benchmark: deterministic MIS-2 + MIS-2 aggregation on one MI355X.
+
+One step = one mis2_run and one mis2_aggregate call on the same device-resident
+graph (default workload: 3D 27-point Laplacian graph on a 100^3 grid, 1M
+vertices, 25.46M stored entries, int64 row offsets, int32 columns, seed 0).
+Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+
+value = graph nnz / step time (nnz/s).  roofline: the sweep kernel with the
+largest share of GPU time, its algorithmic bytes per launch (exact, from an
+untimed accounting run: 4 B per visited column index, 20 B (Refresh Column)
+or 24 B (Decide Set) per worklist row, 4 B per row kept) over its mean launch
+duration from HIP events recorded on the library's stream in a second timed
+loop.  cpu_baseline: the CPU oracle on the host, one thread.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_2204_02934_amd import graphs
+    if name == "c1":
+        return "2D 5-point Laplacian graph 64x64 (n=4096), MIS-2 + MIS-2 aggregation", \
+            graphs.grid2d_5pt(64, 64)
+    if name == "c2":
+        return "3D 27-point Laplacian graph 100^3 (n=1,000,000), MIS-2 + MIS-2 aggregation", \
+            graphs.grid3d_27pt(100, 100, 100)
+    if name == "c3":
+        return "Chung-Lu power-law graph (n=4,000,000, mean degree 16, exponent 2.1, cap 20000), " \
+               "MIS-2 + MIS-2 aggregation", graphs.chung_lu(4_000_000, 16.0, 2.1, 20000, seed=1)
+    raise SystemExit("unknown workload " + name)
+
+
+def sweep_bytes(rec, identity):
+    """Algorithmic bytes of one sweep launch: column indices of the visited
+    rows, per-row terms (row extents 8, worklist entry 4 unless the list is
+    the identity, own value 4, written value 4, plus the compulsory first
+    touch of the gathered value 4 (Refresh Column) or read of M_v and T_v
+    (Decide Set)), and the compacted worklist written."""
+    per_row = 20 if rec["kind"] == 0 else 24
+    if identity:
+        per_row -= 4
+    return 4 * rec["edges"] + per_row * rec["rows"] + 4 * rec["rows_out"]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        raise SystemExit("bench.py measures one GPU: this build has no multi-GPU path "
+                         "(--gpus %d requested)" % args.gpus)
+
+    import numpy as np
+    import torch
+
+    from paper_2204_02934_amd import api
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    name, (rp_h, col_h) = workload(args.workload)
+    n, nnz = rp_h.size - 1, int(rp_h[-1])
+    log("workload:", name, "n=%d nnz=%d" % (n, nnz))
+    dev = torch.device("cuda", 0)
+    rp, col = api.as_device_csr(rp_h, col_h, dev)
+
+    ctx = api.Context(0)
+    ctx.ensure_workspace(n, 1)
+    torch.cuda.synchronize()
+
+    def step(c):
+        c.mis2(rp, col, args.seed, nnz=nnz)
+        c.aggregate(rp, col, args.seed, nnz=nnz)
+
+    for _ in range(args.warmup):
+        step(ctx)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    # value: plain timed loop
+    t_mis = []
+    t_agg = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        ctx.mis2(rp, col, args.seed, nnz=nnz)
+        b = time.perf_counter()
+        ctx.aggregate(rp, col, args.seed, nnz=nnz)
+        c = time.perf_counter()
+        t_mis.append(b - a)
+        t_agg.append(c - b)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    log("timed: %.3f ms/step (mis2 %.3f ms, aggregate %.3f ms)"
+        % (ms_per_step, 1e3 * np.median(t_mis), 1e3 * np.median(t_agg)))
+
+    # algorithmic bytes per launch (untimed accounting run; results are
+    # deterministic, so every timed step visits the same rows)
+    acc = api.Context(0, account=True)
+    acc.ensure_workspace(n, 1)
+    acc.mis2(rp, col, args.seed, nnz=nnz)
+    recs_mis = acc.last_sweeps()
+    acc.aggregate(rp, col, args.seed, nnz=nnz)
+    recs_agg = acc.last_sweeps()
+    accounted = recs_mis + recs_agg
+
+    # launch durations: a second timed loop with HIP events around each sweep
+    prof = api.Context(0, profile=True)
+    prof.ensure_workspace(n, 1)
+    step(prof)
+    torch.cuda.synchronize()
+    dur = [0.0] * len(accounted)
+    tp0 = time.perf_counter()
+    for _ in range(args.steps):
+        prof.mis2(rp, col, args.seed, nnz=nnz)
+        r1 = prof.last_sweeps()
+        prof.aggregate(rp, col, args.seed, nnz=nnz)
+        r2 = prof.last_sweeps()
+        recs = r1 + r2
+        assert len(recs) == len(accounted)
+        for i, r in enumerate(recs):
+            assert (r["kind"], r["phase"], r["round"], r["rows"]) == \
+                (accounted[i]["kind"], accounted[i]["phase"], accounted[i]["round"],
+                 accounted[i]["rows"])
+            dur[i] += r["ms"]
+    torch.cuda.synchronize()
+    ms_profiled = 1e3 * (time.perf_counter() - tp0) / args.steps
+    dur = [d / args.steps for d in dur]
+    kinds = {0: "refresh_column", 1: "decide"}
+    per_kind = {}
+    for i, r in enumerate(accounted):
+        ident = (r["phase"] == 0 and r["round"] == 0)
+        k = kinds[r["kind"]]
+        e = per_kind.setdefault(k, {"bytes": 0, "ms": 0.0, "launches": 0})
+        e["bytes"] += sweep_bytes(r, ident)
+        e["ms"] += dur[i]
+        e["launches"] += 1
+    dom = max(per_kind, key=lambda k: per_kind[k]["ms"])
+    d = per_kind[dom]
+    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9  # GB/s = mean bytes per launch / mean duration
+    sweep_ms = sum(v["ms"] for v in per_kind.values())
+    sweep_bytes_total = sum(v["bytes"] for v in per_kind.values())
+    log("per kind:", json.dumps(per_kind))
+
+    rounds_mis = 1 + max(r["round"] for r in recs_mis) if recs_mis else 0
+
+    # CPU baseline: the oracle, single-threaded, on a bounded sample
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        reps = 0
+        tc0 = time.perf_counter()
+        while True:
+            oracle.mis2(rp_h, col_h, args.seed)
+            oracle.aggregate(rp_h, col_h, args.seed)
+            reps += 1
+            if time.perf_counter() - tc0 > 8.0 or reps >= 20:
+                break
+        tcpu = (time.perf_counter() - tc0) / reps
+        cpu = {"value": nnz / tcpu, "unit": "nnz/s", "cores": 1, "kind": "oracle",
+               "sample": "%d full steps (MIS-2 + aggregation) of the same graph, %.2f s each"
+                         % (reps, tcpu)}
+        log("cpu oracle: %.3f s/step" % tcpu)
+
+    out = {
+        "metric": "MIS-2+aggregation graph nnz/s and HBM GB/s fraction",
+        "value": nnz / (ms_per_step * 1e-3),
+        "unit": "nnz/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": name, "n": n, "nnz": nnz, "seed": args.seed,
+                   "step": "mis2_run + mis2_aggregate, graph resident in HBM",
+                   "index_types": "int64 row offsets, int32 columns"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": dom, "launches_per_step": d["launches"],
+                     "bytes_per_launch": d["bytes"] / d["launches"],
+                     "mean_launch_ms": d["ms"] / d["launches"]},
+        "cpu_baseline": cpu,
+        "mis2_ms": 1e3 * float(np.median(t_mis)),
+        "aggregate_ms": 1e3 * float(np.median(t_agg)),
+        "mis2_rounds": rounds_mis,
+        "sweep_gpu_ms_per_step": sweep_ms,
+        "sweep_bytes_per_step": sweep_bytes_total,
+        "ms_per_step_profiled": ms_profiled,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

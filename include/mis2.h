@@ -55,6 +55,8 @@ extern "C" {
 #define MIS2_OPT_VALIDATE      0  /* 1: check the CSR on the GPU before each call (default 0) */
 #define MIS2_OPT_LANES_PER_ROW 1  /* 0 = automatic; else 1, 2, 4, 8, 16, 32 or 64 lanes per CSR row */
 #define MIS2_OPT_GRID_BLOCKS   2  /* 0 = automatic; else the number of 256-thread workgroups per sweep */
+#define MIS2_OPT_PROFILE       3  /* 1: time every sweep launch with HIP events on the call's stream */
+#define MIS2_OPT_ACCOUNT       4  /* 1: sweeps also sum the CSR row lengths they visit (extra atomics) */
 
 typedef struct mis2_ctx mis2_ctx;
 
@@ -115,6 +117,23 @@ int mis2_run(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, uint8_t *status,
  * number of rounds recorded.  Reads host-side state only. */
 int mis2_last_trace(const mis2_ctx *ctx, int phase, int64_t *sizes, int32_t cap,
                     int32_t *rounds);
+
+/* One sweep launch of the last mis2_run / mis2_aggregate call. */
+typedef struct mis2_sweep_record {
+    int32_t kind;      /* 0 = Refresh Column (worklist2), 1 = Decide Set (worklist1) */
+    int32_t phase;     /* 0 = MIS-2 of G; 1 = MIS-2 of the phase-2 induced subgraph */
+    int32_t round;     /* round of Algorithm 1, from 0 */
+    int32_t lanes;     /* lanes per CSR row used by the launch */
+    int64_t rows;      /* worklist entries processed */
+    int64_t rows_out;  /* entries kept for the next round */
+    int64_t edges;     /* sum of the processed CSR row lengths with MIS2_OPT_ACCOUNT, else -1 */
+    float ms;          /* launch duration with MIS2_OPT_PROFILE, else -1 */
+    int32_t reserved;
+} mis2_sweep_record;
+
+/* Copy up to `cap` records of the last call's sweep launches to host array
+ * `out`, in launch order; *count (host) receives the total number. */
+int mis2_last_sweeps(const mis2_ctx *ctx, mis2_sweep_record *out, int32_t cap, int32_t *count);
 
 /*
  * mis2_aggregate -- Algorithm 3 (Section III-B): MIS-2 based aggregation.

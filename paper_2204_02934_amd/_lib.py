@@ -22,18 +22,26 @@ MIS2_OP_COARSEN = 2
 MIS2_OPT_VALIDATE = 0
 MIS2_OPT_LANES_PER_ROW = 1
 MIS2_OPT_GRID_BLOCKS = 2
+MIS2_OPT_PROFILE = 3
+MIS2_OPT_ACCOUNT = 4
 
 # Every symbol include/mis2.h declares.
 EXPORTS = (
     "mis2_create", "mis2_destroy", "mis2_last_error", "mis2_set_option",
     "mis2_workspace_bytes", "mis2_set_workspace", "mis2_run", "mis2_last_trace",
-    "mis2_aggregate",
+    "mis2_aggregate", "mis2_last_sweeps",
 )
 
 
 class Mis2Graph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+
+
+class Mis2SweepRecord(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("phase", ctypes.c_int32), ("round", ctypes.c_int32),
+                ("lanes", ctypes.c_int32), ("rows", ctypes.c_int64), ("rows_out", ctypes.c_int64),
+                ("edges", ctypes.c_int64), ("ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
 
 
 class Mis2Error(RuntimeError):
@@ -67,6 +75,8 @@ def load():
         "mis2_last_trace": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(i64), i32,
                                            ctypes.POINTER(i32)]),
         "mis2_aggregate": (ctypes.c_int, [vp, gp, u64, vp, ctypes.POINTER(i64), vp, vp]),
+        "mis2_last_sweeps": (ctypes.c_int, [vp, ctypes.POINTER(Mis2SweepRecord), i32,
+                                            ctypes.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -39,7 +39,8 @@ class Context:
     """One mis2_ctx bound to a GPU, with a torch-allocated workspace that grows
     on demand (allocation happens outside the library calls)."""
 
-    def __init__(self, device=None, validate=False, lanes=0, blocks=0):
+    def __init__(self, device=None, validate=False, lanes=0, blocks=0, profile=False,
+                 account=False):
         self.lib = _lib.load()
         if device is None:
             device = torch.cuda.current_device()
@@ -50,6 +51,8 @@ class Context:
         self.set_option(_lib.MIS2_OPT_VALIDATE, int(validate))
         self.set_option(_lib.MIS2_OPT_LANES_PER_ROW, lanes)
         self.set_option(_lib.MIS2_OPT_GRID_BLOCKS, blocks)
+        self.set_option(_lib.MIS2_OPT_PROFILE, int(profile))
+        self.set_option(_lib.MIS2_OPT_ACCOUNT, int(account))
 
     def __del__(self):
         lib = getattr(self, "lib", None)
@@ -119,6 +122,21 @@ class Context:
         _check(self.lib, self.ptr, self.lib.mis2_last_trace(self.ptr, phase, buf, cap, ctypes.byref(r)))
         k = min(r.value, cap)
         return np.ctypeslib.as_array(buf)[:2 * k].reshape(k, 2).copy()
+
+
+    def last_sweeps(self, cap=8192):
+        """Sweep launches of the last call: list of dicts (kind 0 = Refresh
+        Column, 1 = Decide Set; edges / ms are -1 unless accounting /
+        profiling is on)."""
+        buf = (_lib.Mis2SweepRecord * cap)()
+        k = ctypes.c_int32(0)
+        _check(self.lib, self.ptr, self.lib.mis2_last_sweeps(self.ptr, buf, cap, ctypes.byref(k)))
+        out = []
+        for i in range(min(k.value, cap)):
+            r = buf[i]
+            out.append({"kind": r.kind, "phase": r.phase, "round": r.round, "lanes": r.lanes,
+                        "rows": r.rows, "rows_out": r.rows_out, "edges": r.edges, "ms": r.ms})
+        return out
 
 
 _default = {}

@@ -59,12 +59,13 @@ int lanes_for(const mis2_ctx *ctx, const mis2_graph *g) {
     return 64;
 }
 
-int blocks_for(const mis2_ctx *ctx, int64_t rows, int lanes) {
+// Workgroups of the segmented sweeps: a multiple of 8 (one run of logical
+// blocks per XCD), about 256 vertices per workgroup, at most kMaxBlocks.
+int blocks_for(const mis2_ctx *ctx, int64_t n) {
     if (ctx->plan.blocks) return ctx->plan.blocks;
-    const int64_t per = kBlock / lanes;
-    int64_t b = (rows + per - 1) / per;
-    const int64_t cap = (int64_t)ctx->num_cus * 16;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
+    int64_t b = (n + 255) / 256;
+    b = (b + 7) / 8 * 8;
+    return (int)std::max<int64_t>(8, std::min<int64_t>(b, kMaxBlocks));
 }
 
 int maybe_validate(mis2_ctx *ctx, const mis2_graph *g, const Workspace &ws, hipStream_t s) {
@@ -89,61 +90,185 @@ int get_workspace(mis2_ctx *ctx, const mis2_graph *g, int op, Workspace *ws) {
     return MIS2_OK;
 }
 
-// The round loop of Algorithm 1.  Round 0 starts either from the identity
-// worklists (whole graph) or from a list of the active vertices whose size
-// is *d_active (induced subgraph; T and M already initialised).  Rounds are
-// issued one at a time; after each, both worklist sizes are read back.
+hipEvent_t take_event(mis2_ctx *ctx) {
+    if (ctx->events_used == ctx->events.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        ctx->events.push_back(e);
+    }
+    return ctx->events[ctx->events_used++];
+}
+
+struct Launch {
+    int kind, phase, round, lanes;
+    hipEvent_t e0, e1;
+};
+
+// Segment geometry of a run: S wavefronts, seg vertices each.
+struct Geometry {
+    int blocks;
+    int64_t S, seg;
+};
+
+Geometry geometry(const mis2_ctx *ctx, int64_t n) {
+    Geometry gm;
+    gm.blocks = blocks_for(ctx, n);
+    gm.S = (int64_t)gm.blocks * (kBlock / 64);
+    gm.seg = std::max<int64_t>(1, (n + gm.S - 1) / gm.S);
+    return gm;
+}
+
+// The round loop of Algorithm 1.  Round 0 starts from the identity
+// worklists (whole graph, masked == false) or from the per-wave lists of the
+// active vertices already in wl1[0] / cnt1[0] (induced subgraph; T and M
+// already initialised).
+//
+// Rounds are issued without waiting: every sweep reads its worklist sizes
+// from device memory, so a round issued after the last one finds empty
+// worklists and does nothing.  Rounds go out in chunks of kChunk; after each
+// chunk the host copies the "worklist1 non-empty" flag of the next round to
+// pinned memory and waits only for the previous chunk's flag, so the GPU
+// always has the next chunk queued.  The per-round sizes the sweeps record
+// give the round count afterwards.
+constexpr int kChunk = 2;
+
 int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspace &ws,
-               const int32_t *active_list, const uint32_t *d_active, int phase, hipStream_t s,
-               int32_t *iters_out) {
+               const Geometry &gm, bool masked, int phase, hipStream_t s, int32_t *iters_out,
+               std::vector<Launch> *launches) {
     const int lanes = lanes_for(ctx, g);
+    unsigned long long *degs = ws.degs + (size_t)phase * kTraceCap * 2;
+    if (ctx->account) HIP_TRY(ctx, launch_fill_u64(degs, 0ull, 2 * kTraceCap, s));
+    // rows 0 and 1 of the round table (row 0 already holds the masked start
+    // sizes); each round's first sweep clears the row two rounds ahead
+    HIP_TRY(ctx, launch_fill_u32(ws.rt + (masked ? kRoundStride : 0), 0u,
+                                 (masked ? 1 : 2) * kRoundStride, s));
+    hipEvent_t chunk_done[2] = {nullptr, nullptr};
+    for (int i = 0; i < 2; i++)
+        if (!(chunk_done[i] = take_event(ctx)))
+            return fail(ctx, MIS2_EHIP, "hipEventCreate failed");
+    int round = 0, chunk = 0;
+    for (;;) {
+        for (int k = 0; k < kChunk; k++, round++) {
+            if (round + 2 >= kTraceCap)
+                return fail(ctx, MIS2_EINTERNAL, "more than %d rounds", kTraceCap - 1);
+            const int cur = round & 1, nxt = cur ^ 1;
+            const bool first = (round == 0);
+            uint32_t *row_next = ws.rt + (size_t)(round + 1) * kRoundStride;
+            SegIO col_io{first ? (masked ? ws.wl1[0] : nullptr) : ws.wl2[cur],
+                         first ? (masked ? ws.cnt1[0] : nullptr) : ws.cnt2[cur],
+                         ws.wl2[nxt],
+                         ws.cnt2[nxt],
+                         row_next + kTraceSplit,
+                         nullptr,
+                         row_next + kRoundStride,
+                         ctx->account ? degs + 2 * round + 1 : nullptr,
+                         g->n,
+                         gm.seg,
+                         gm.S};
+            SegIO dec_io{first ? (masked ? ws.wl1[0] : nullptr) : ws.wl1[cur],
+                         first ? (masked ? ws.cnt1[0] : nullptr) : ws.cnt1[cur],
+                         ws.wl1[nxt],
+                         ws.cnt1[nxt],
+                         row_next,
+                         row_next + kRtAlive,
+                         nullptr,
+                         ctx->account ? degs + 2 * round + 0 : nullptr,
+                         g->n,
+                         gm.seg,
+                         gm.S};
+            const TupleParams next = tuple_params(g->n, seed, (uint64_t)round + 1);
+            Launch lc{0, phase, round, lanes, nullptr, nullptr};
+            Launch ld{1, phase, round, lanes, nullptr, nullptr};
+            if (ctx->profile) {
+                lc.e0 = take_event(ctx), lc.e1 = take_event(ctx);
+                ld.e0 = take_event(ctx), ld.e1 = take_event(ctx);
+                if (!lc.e0 || !lc.e1 || !ld.e0 || !ld.e1)
+                    return fail(ctx, MIS2_EHIP, "hipEventCreate failed");
+                HIP_TRY(ctx, hipEventRecord(lc.e0, s));
+            }
+            HIP_TRY(ctx, launch_refresh_column(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
+                                               col_io, s));
+            if (ctx->profile) {
+                HIP_TRY(ctx, hipEventRecord(lc.e1, s));
+                HIP_TRY(ctx, hipEventRecord(ld.e0, s));
+            }
+            HIP_TRY(ctx, launch_decide(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M, next,
+                                       dec_io, s));
+            if (ctx->profile) HIP_TRY(ctx, hipEventRecord(ld.e1, s));
+            launches->push_back(lc);
+            launches->push_back(ld);
+        }
+        uint32_t *slot = ctx->pinned + 32 + (chunk & 1);
+        HIP_TRY(ctx, hipMemcpyAsync(slot, ws.rt + (size_t)round * kRoundStride + kRtAlive, 4,
+                                    hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipEventRecord(chunk_done[chunk & 1], s));
+        if (chunk > 0) {
+            HIP_TRY(ctx, hipEventSynchronize(chunk_done[(chunk - 1) & 1]));
+            if (ctx->pinned[32 + ((chunk - 1) & 1)] == 0) break;
+        }
+        chunk++;
+    }
+    // Per-round sizes as recorded by the sweeps; the first round with an
+    // empty worklist1 ends the run.
+    std::vector<uint32_t> rt((size_t)round * kRoundStride);
+    HIP_TRY(ctx, hipMemcpyAsync(rt.data(), ws.rt, rt.size() * sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
     std::vector<int64_t> &tr = ctx->trace[phase];
     tr.clear();
-    int64_t c1 = g->n, c2 = g->n;  // upper bounds for round 0
-    if (d_active) {
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, d_active, 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(ctx, hipStreamSynchronize(s));
-        c1 = c2 = ctx->pinned[0];
-    }
-    int round = 0;
-    while (c1 > 0) {
+    int r = 0;
+    for (; r < round; r++) {
+        int64_t c1 = 0, c2 = 0;
+        for (int k = 0; k < kTraceSplit; k++) {
+            c1 += rt[(size_t)r * kRoundStride + k];
+            c2 += rt[(size_t)r * kRoundStride + kTraceSplit + k];
+        }
+        if (r == 0) {
+            if (!masked) c1 = g->n;
+            c2 = c1;
+        }
+        if (c1 == 0) break;
         tr.push_back(c1);
         tr.push_back(c2);
-        const int cur = round & 1, nxt = cur ^ 1;
-        const bool first = (round == 0);
-        const uint32_t *in1 = first ? d_active : ws.ring + 0 * kRing + round % kRing;
-        const uint32_t *in2 = first ? d_active : ws.ring + 1 * kRing + round % kRing;
-        SweepIO col_io{first ? active_list : ws.wl2[cur],
-                       in2,
-                       g->n,
-                       ws.wl2[nxt],
-                       ws.ring + 1 * kRing + (round + 1) % kRing,
-                       ws.ring + 1 * kRing + (round + 2) % kRing,
-                       round < kTraceCap ? ws.trace + 2 * round + 1 : nullptr};
-        SweepIO dec_io{first ? active_list : ws.wl1[cur],
-                       in1,
-                       g->n,
-                       ws.wl1[nxt],
-                       ws.ring + 0 * kRing + (round + 1) % kRing,
-                       ws.ring + 0 * kRing + (round + 2) % kRing,
-                       round < kTraceCap ? ws.trace + 2 * round + 0 : nullptr};
-        HIP_TRY(ctx, launch_refresh_column(lanes, blocks_for(ctx, c2, lanes), g->row_ptr, g->col,
-                                           ws.T, ws.M, col_io, s));
-        const TupleParams next = tuple_params(g->n, seed, (uint64_t)round + 1);
-        HIP_TRY(ctx, launch_decide(lanes, blocks_for(ctx, c1, lanes), g->row_ptr, g->col, ws.T,
-                                   ws.M, next, dec_io, s));
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, ws.ring + 0 * kRing + (round + 1) % kRing, 4,
-                                    hipMemcpyDeviceToHost, s));
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned + 1, ws.ring + 1 * kRing + (round + 1) % kRing, 4,
+    }
+    *iters_out = r;
+    return MIS2_OK;
+}
+
+// Fill ctx->sweeps from the launches of the finished call.
+int collect_sweeps(mis2_ctx *ctx, const std::vector<Launch> &launches, const Workspace &ws,
+                   hipStream_t s) {
+    ctx->sweeps.clear();
+    std::vector<unsigned long long> degs;
+    if (ctx->account) {
+        degs.resize((size_t)2 * kTraceCap * 2);
+        HIP_TRY(ctx, hipMemcpyAsync(degs.data(), ws.degs, degs.size() * sizeof(unsigned long long),
                                     hipMemcpyDeviceToHost, s));
         HIP_TRY(ctx, hipStreamSynchronize(s));
-        c1 = ctx->pinned[0];
-        c2 = ctx->pinned[1];
-        round++;
-        if (c1 > 0 && round >= (1 << 30))
-            return fail(ctx, MIS2_EINTERNAL, "round counter overflow");
     }
-    *iters_out = round;
+    for (const Launch &l : launches) {
+        const std::vector<int64_t> &tr = ctx->trace[l.phase];
+        const int rounds = (int)(tr.size() / 2);
+        if (l.round >= rounds) continue;  // issued after the run had finished
+        mis2_sweep_record rec;
+        memset(&rec, 0, sizeof rec);
+        rec.kind = l.kind;
+        rec.phase = l.phase;
+        rec.round = l.round;
+        rec.lanes = l.lanes;
+        const int list = l.kind == 0 ? 1 : 0;
+        rec.rows = tr[2 * l.round + list];
+        rec.rows_out = l.round + 1 < rounds ? tr[2 * (l.round + 1) + list] : 0;
+        rec.edges = ctx->account ? (int64_t)degs[((size_t)l.phase * kTraceCap + l.round) * 2 + list]
+                                 : -1;
+        rec.ms = -1.0f;
+        if (ctx->profile && l.e0 && l.e1) {
+            float ms = 0.f;
+            HIP_TRY(ctx, hipEventElapsedTime(&ms, l.e0, l.e1));
+            rec.ms = ms;
+        }
+        ctx->sweeps.push_back(rec);
+    }
     return MIS2_OK;
 }
 
@@ -155,16 +280,16 @@ size_t workspace_bytes(int64_t n, int op) {
     if (n < 0) return 0;
     const size_t un = (size_t)n;
     size_t b = 0;
-    b += align_up(4 * un) * 2;                 // T, M
-    b += align_up(4 * un) * 4;                 // wl1[2], wl2[2]
-    b += align_up(4 * 2 * kRing);              // ring
-    b += align_up(4 * 2 * kTraceCap);          // trace
-    b += align_up(4 * kScalars);               // scalars
+    b += align_up(4 * un) * 2;                          // T, M
+    b += align_up(4 * un) * 4;                          // wl1[2], wl2[2]
+    b += align_up(4 * (size_t)kMaxWaves) * 4;           // cnt1[2], cnt2[2]
+    b += align_up(4 * (size_t)(kTraceCap + 2) * kRoundStride);  // round table
+    b += align_up(4 * kScalars);                        // scalars
+    b += align_up(8 * 2 * 2 * (size_t)kTraceCap);       // degs
+    b += align_up(4 * (size_t)(compact_blocks(n) + 1)); // blocksum
     if (op != MIS2_OP_MIS2) {
-        b += align_up(4 * un) * 3;             // label, list, aggsize
-        b += align_up(un);                     // flag
-        b += align_up(4 * (size_t)(compact_blocks(n) + 1));  // blocksum
-        b += align_up(4 * un);                 // active
+        b += align_up(4 * un) * 3;                      // label, list, aggsize
+        b += align_up(un);                              // flag
     }
     return b;
 }
@@ -184,16 +309,19 @@ bool carve(void *base, size_t bytes, int64_t n, int op, Workspace *ws) {
     ws->wl1[1] = (int32_t *)take(4 * un);
     ws->wl2[0] = (int32_t *)take(4 * un);
     ws->wl2[1] = (int32_t *)take(4 * un);
-    ws->ring = (uint32_t *)take(4 * 2 * kRing);
-    ws->trace = (uint32_t *)take(4 * 2 * kTraceCap);
+    ws->cnt1[0] = (uint32_t *)take(4 * (size_t)kMaxWaves);
+    ws->cnt1[1] = (uint32_t *)take(4 * (size_t)kMaxWaves);
+    ws->cnt2[0] = (uint32_t *)take(4 * (size_t)kMaxWaves);
+    ws->cnt2[1] = (uint32_t *)take(4 * (size_t)kMaxWaves);
+    ws->rt = (uint32_t *)take(4 * (size_t)(kTraceCap + 2) * kRoundStride);
     ws->scalars = (uint32_t *)take(4 * kScalars);
+    ws->degs = (unsigned long long *)take(8 * 2 * 2 * (size_t)kTraceCap);
+    ws->blocksum = (uint32_t *)take(4 * (size_t)(compact_blocks(n) + 1));
     if (op != MIS2_OP_MIS2) {
         ws->label = (int32_t *)take(4 * un);
         ws->list = (int32_t *)take(4 * un);
         ws->aggsize = (int32_t *)take(4 * un);
         ws->flag = (uint8_t *)take(un);
-        ws->blocksum = (uint32_t *)take(4 * (size_t)(compact_blocks(n) + 1));
-        ws->active = (int32_t *)take(4 * un);
     }
     return true;
 }
@@ -217,8 +345,8 @@ int mis2_create(mis2_ctx **out, int device) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         ctx->num_cus = prop.multiProcessorCount;
-    if (hipHostMalloc((void **)&ctx->pinned, 64 * sizeof(uint32_t), hipHostMallocDefault) !=
-        hipSuccess) {
+    if (hipHostMalloc((void **)&ctx->pinned, (64 + 2 * kTraceCap) * sizeof(uint32_t),
+                      hipHostMallocDefault) != hipSuccess) {
         delete ctx;
         return MIS2_EHIP;
     }
@@ -229,6 +357,7 @@ int mis2_create(mis2_ctx **out, int device) {
 void mis2_destroy(mis2_ctx *ctx) {
     if (!ctx) return;
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -249,9 +378,15 @@ int mis2_set_option(mis2_ctx *ctx, int option, int64_t value) {
             ctx->plan.lanes = (int)value;
             return MIS2_OK;
         case MIS2_OPT_GRID_BLOCKS:
-            if (value < 0 || value > (1 << 20))
-                return fail(ctx, MIS2_EINVAL, "grid blocks out of range");
+            if (value < 0 || value > kMaxBlocks)
+                return fail(ctx, MIS2_EINVAL, "grid blocks must be in [0, %d]", kMaxBlocks);
             ctx->plan.blocks = (int)value;
+            return MIS2_OK;
+        case MIS2_OPT_PROFILE:
+            ctx->profile = value != 0;
+            return MIS2_OK;
+        case MIS2_OPT_ACCOUNT:
+            ctx->account = value != 0;
             return MIS2_OK;
         default:
             return fail(ctx, MIS2_EINVAL, "unknown option %d", option);
@@ -282,6 +417,7 @@ int mis2_run(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, uint8_t *status,
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     ctx->trace[0].clear();
     ctx->trace[1].clear();
+    ctx->sweeps.clear();
     if (g->n == 0) {
         if (n_roots) *n_roots = 0;
         if (n_iters) *n_iters = 0;
@@ -291,18 +427,20 @@ int mis2_run(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, uint8_t *status,
     if ((rc = get_workspace(ctx, g, MIS2_OP_MIS2, &ws))) return rc;
     if ((rc = maybe_validate(ctx, g, ws, s))) return rc;
 
-    HIP_TRY(ctx, launch_init_tuples(tuple_params(g->n, seed, 0), g->n, ws.T, ws.ring, s));
+    ctx->events_used = 0;
+    std::vector<Launch> launches;
+    const Geometry gm = geometry(ctx, g->n);
+    HIP_TRY(ctx, launch_init_tuples(tuple_params(g->n, seed, 0), g->n, ws.T, s));
     int32_t iters = 0;
-    if ((rc = run_rounds(ctx, g, seed, ws, nullptr, nullptr, 0, s, &iters))) return rc;
-    HIP_TRY(ctx, launch_fill_u32(ws.scalars + kS_Roots, 0u, 1, s));
-    HIP_TRY(ctx, launch_status(g->n, ws.T, status, ws.scalars + kS_Roots, s));
+    if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, &iters, &launches))) return rc;
+    HIP_TRY(ctx, launch_status(g->n, ws.T, status, ws.blocksum, ws.scalars + kS_Roots, s));
     if (n_roots) {
         HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, ws.scalars + kS_Roots, 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(ctx, hipStreamSynchronize(s));
         *n_roots = ctx->pinned[0];
     }
     if (n_iters) *n_iters = iters;
-    return MIS2_OK;
+    return collect_sweeps(ctx, launches, ws, s);
 }
 
 int mis2_last_trace(const mis2_ctx *ctx, int phase, int64_t *sizes, int32_t cap, int32_t *rounds) {
@@ -317,6 +455,14 @@ int mis2_last_trace(const mis2_ctx *ctx, int phase, int64_t *sizes, int32_t cap,
     return MIS2_OK;
 }
 
+int mis2_last_sweeps(const mis2_ctx *ctx, mis2_sweep_record *out, int32_t cap, int32_t *count) {
+    if (!ctx || cap < 0 || (cap > 0 && !out)) return MIS2_EINVAL;
+    const int32_t k = (int32_t)ctx->sweeps.size();
+    for (int32_t i = 0; i < std::min(k, cap); i++) out[i] = ctx->sweeps[i];
+    if (count) *count = k;
+    return MIS2_OK;
+}
+
 int mis2_aggregate(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *agg_id,
                    int64_t *n_agg, uint8_t *roots, void *stream) {
     int rc = check_graph_args(ctx, g);
@@ -326,6 +472,7 @@ int mis2_aggregate(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     ctx->trace[0].clear();
     ctx->trace[1].clear();
+    ctx->sweeps.clear();
     if (g->n == 0) {
         if (n_agg) *n_agg = 0;
         return MIS2_OK;
@@ -335,39 +482,46 @@ int mis2_aggregate(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
     if ((rc = maybe_validate(ctx, g, ws, s))) return rc;
     const int64_t n = g->n;
     uint32_t *sc = ws.scalars;
+    ctx->events_used = 0;
+    std::vector<Launch> launches;
+    const Geometry gm = geometry(ctx, n);
 
     // Phase 1: MIS-2 of G; roots numbered by increasing id, each labelled with
     // its neighbours.
-    HIP_TRY(ctx, launch_init_tuples(tuple_params(n, seed, 0), n, ws.T, ws.ring, s));
+    HIP_TRY(ctx, launch_init_tuples(tuple_params(n, seed, 0), n, ws.T, s));
     int32_t it1 = 0, it2 = 0;
-    if ((rc = run_rounds(ctx, g, seed, ws, nullptr, nullptr, 0, s, &it1))) return rc;
+    if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, &it1, &launches))) return rc;
     HIP_TRY(ctx, launch_fill_u32(sc, 0u, kScalars, s));
     HIP_TRY(ctx, launch_fill_i32(ws.label, -1, n, s));
     if (roots) HIP_TRY(ctx, launch_fill_u8(roots, 0, n, s));
     HIP_TRY(ctx, compact_u32_eq(ws.T, kIn, n, ws.list, sc + kS_Count1, ws.blocksum, s));
     HIP_TRY(ctx, launch_label_roots(n, g->row_ptr, g->col, ws.list, sc + kS_Count1, nullptr, false,
-                                    ws.label, roots, 1, s));
+                                    ws.label, ws.aggsize, roots, 1, s));
 
     // Phase 2: MIS-2 of the subgraph induced by the unlabelled vertices (same
     // ids and b, round counter from 0); roots with >= 2 unlabelled neighbours
     // become aggregates n1 + k.
-    HIP_TRY(ctx, launch_init_masked(tuple_params(n, seed, 0), n, ws.label, ws.T, ws.M, ws.ring, s));
-    HIP_TRY(ctx, compact_i32_eq(ws.label, -1, n, ws.active,
-                                sc + kS_Active, ws.blocksum, s));
-    if ((rc = run_rounds(ctx, g, seed, ws, ws.active, sc + kS_Active, 1, s, &it2))) return rc;
+    HIP_TRY(ctx, launch_fill_u32(ws.rt, 0u, kRoundStride, s));
+    SegIO act_io{nullptr, nullptr, ws.wl1[0], ws.cnt1[0], ws.rt, nullptr, nullptr, nullptr,
+                 n, gm.seg, gm.S};
+    HIP_TRY(ctx, launch_init_masked(gm.blocks, tuple_params(n, seed, 0), n, ws.label, ws.T, ws.M,
+                                    act_io, s));
+    if ((rc = run_rounds(ctx, g, seed, ws, gm, true, 1, s, &it2, &launches))) return rc;
     HIP_TRY(ctx, launch_accept_phase2(n, g->row_ptr, g->col, ws.T, ws.label, ws.flag, s));
     HIP_TRY(ctx, compact_u8_nz(ws.flag, n, ws.list, sc + kS_Count2, ws.blocksum, s));
     HIP_TRY(ctx, launch_label_roots(n, g->row_ptr, g->col, ws.list, sc + kS_Count2,
-                                    sc + kS_Count1, true, ws.label, roots, 2, s));
+                                    sc + kS_Count1, true, ws.label, ws.aggsize, roots, 2, s));
 
-    // Phase 3: aggsize over the frozen labels, then each unlabelled vertex
-    // joins its best-coupled aggregate.
-    HIP_TRY(ctx, launch_fill_i32(ws.aggsize, 0, n, s));
-    HIP_TRY(ctx, launch_aggsize(n, ws.label, ws.aggsize, s));
+    // Phase 3: each unlabelled vertex joins its best-coupled aggregate, all
+    // counted on the labels frozen after phase 2.
     HIP_TRY(ctx, launch_copy_i32(ws.label, agg_id, n, s));
-    HIP_TRY(ctx, compact_i32_eq(ws.label, -1, n, ws.list, sc + kS_Left, ws.blocksum, s));
-    HIP_TRY(ctx, launch_phase3(n, g->row_ptr, g->col, ws.label, ws.aggsize, ws.list, sc + kS_Left,
-                               agg_id, sc + kS_Err, s));
+    SegIO left_io{nullptr, nullptr, ws.wl2[0], ws.cnt2[0], nullptr, nullptr, nullptr, nullptr,
+                  n, gm.seg, gm.S};
+    HIP_TRY(ctx, launch_list_unlabelled(gm.blocks, n, ws.label, left_io, s));
+    SegIO p3_io{ws.wl2[0], ws.cnt2[0], nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                n, gm.seg, gm.S};
+    HIP_TRY(ctx, launch_phase3(lanes_for(ctx, g), gm.blocks, g->row_ptr, g->col, ws.label,
+                               ws.aggsize, p3_io, agg_id, sc + kS_Err, s));
 
     HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, sc, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -376,7 +530,7 @@ int mis2_aggregate(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
     if (n_agg) *n_agg = (int64_t)ctx->pinned[kS_Count1] + (int64_t)ctx->pinned[kS_Count2];
     (void)it1;
     (void)it2;
-    return MIS2_OK;
+    return collect_sweeps(ctx, launches, ws, s);
 }
 
 }  // extern "C"

@@ -2,9 +2,11 @@
 //
 // Phase 1 / phase 2 labelling push a root's aggregate id to its neighbours:
 // the roots of an MIS-2 are at least three edges apart, so the written sets
-// are disjoint and the order of the writes cannot matter.  Phase 3 reads only
-// the labels frozen after phase 2 (the "tentative" labels) and writes a
-// separate output array, so every row is decided independently.
+// are disjoint and the order of the writes cannot matter.  The same pass
+// knows each aggregate's size (the root plus the neighbours it labelled), so
+// aggsize needs no histogram.  Phase 3 reads only the labels frozen after
+// phase 2 (the "tentative" labels) and writes a separate output array, so
+// every row is decided independently.
 #include "internal.h"
 
 namespace mis2 {
@@ -13,8 +15,20 @@ namespace {
 
 constexpr int kLabelLanes = 16;  // lanes per root in the labelling push
 
+__device__ __forceinline__ uint64_t lanes_below(int lane) {
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+__device__ __forceinline__ int64_t wave_id() {
+    const int64_t B = gridDim.x;
+    const int64_t b = blockIdx.x;
+    const int64_t lb = (B % 8 == 0) ? (b % 8) * (B / 8) + b / 8 : b;
+    return lb * (kBlock / 64) + (threadIdx.x >> 6);
+}
+
 // roots[0..*d_count) get ids base + k; their neighbours (all of them, or only
-// those still at -1 when only_unlabelled) get the same id.
+// those still at -1 when only_unlabelled) get the same id, and aggsize[id]
+// becomes 1 + the number of neighbours labelled.
 __global__ __launch_bounds__(kBlock) void k_label_roots(const int64_t *__restrict__ row_ptr,
                                                         const int32_t *__restrict__ col,
                                                         const int32_t *__restrict__ roots,
@@ -22,57 +36,72 @@ __global__ __launch_bounds__(kBlock) void k_label_roots(const int64_t *__restric
                                                         const uint32_t *__restrict__ d_base,
                                                         int only_unlabelled,
                                                         int32_t *__restrict__ label,
+                                                        int32_t *__restrict__ aggsize,
                                                         uint8_t *__restrict__ root_mark,
                                                         uint8_t mark) {
     constexpr int L = kLabelLanes, G = kBlock / L;
     const int64_t count = *d_count;
     const int32_t base = d_base ? (int32_t)*d_base : 0;
     const int sub = (int)(threadIdx.x & (L - 1));
-    for (int64_t k = (int64_t)blockIdx.x * G + threadIdx.x / L; k < count;
-         k += (int64_t)gridDim.x * G) {
-        const int32_t r = roots[k];
-        const int32_t id = base + (int32_t)k;
-        const int64_t s = row_ptr[r], e = row_ptr[r + 1];
-        for (int64_t j = s + sub; j < e; j += L) {
-            const int32_t w = col[j];
-            if (!only_unlabelled || label[w] == -1) label[w] = id;
+    // the loop bound is the same for the whole wavefront, so the group
+    // shuffles below always run with all lanes active
+    const int64_t step = (int64_t)gridDim.x * G;
+    const int64_t k0 = (int64_t)blockIdx.x * G + (threadIdx.x & ~63u) / L;
+    for (int64_t kw = k0; kw < count; kw += step) {
+        const int64_t k = kw + (threadIdx.x & 63u) / L;
+        int took = 0;
+        int32_t r = 0, id = 0;
+        if (k < count) {
+            r = roots[k];
+            id = base + (int32_t)k;
+            const int64_t s = row_ptr[r], e = row_ptr[r + 1];
+            for (int64_t j = s + sub; j < e; j += L) {
+                const int32_t w = col[j];
+                if (!only_unlabelled || label[w] == -1) {
+                    label[w] = id;
+                    took++;
+                }
+            }
         }
-        if (sub == 0) {
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1) took += __shfl_xor(took, off, L);
+        if (k < count && sub == 0) {
             label[r] = id;
+            aggsize[id] = 1 + took;
             if (root_mark) root_mark[r] = mark;
         }
     }
 }
 
 // flag[v] = 1 iff v is a root of the phase-2 MIS-2 (T_v = IN in the masked
-// run) with at least two neighbours that are unlabelled after phase 1.
+// run) with at least two neighbours that are unlabelled after phase 1.  Each
+// wavefront scans 64 vertices at a time and counts the candidates' rows
+// cooperatively, one row at a time.
 __global__ __launch_bounds__(kBlock) void k_accept_phase2(int64_t n,
                                                           const int64_t *__restrict__ row_ptr,
                                                           const int32_t *__restrict__ col,
                                                           const uint32_t *__restrict__ T,
                                                           const int32_t *__restrict__ label,
                                                           uint8_t *__restrict__ flag) {
-    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * kBlock) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * 64; base < n;
+         base += waves * 64) {
+        const int64_t v = base + lane;
+        const bool cand = v < n && label[v] == -1 && T[v] == kIn;
+        uint64_t mask = __ballot(cand);
         uint8_t f = 0;
-        if (label[v] == -1 && T[v] == kIn) {
-            // The whole row is counted: this toolchain miscompiles a loop whose
-            // exit test depends on the count when the count is used after it.
+        while (mask) {
+            const int t = __ffsll((unsigned long long)mask) - 1;
+            mask &= mask - 1;
+            const int64_t u = base + t;
+            const int64_t s = row_ptr[u], e = row_ptr[u + 1];
             int cnt = 0;
-            const int64_t e = row_ptr[v + 1];
-            for (int64_t j = row_ptr[v]; j < e; j++) cnt += label[col[j]] == -1;
-            f = cnt >= 2;
+            for (int64_t j = s + lane; j < e; j += 64) cnt += label[col[j]] == -1;
+            for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+            if (lane == t) f = cnt >= 2;
         }
-        flag[v] = f;
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_aggsize(int64_t n, const int32_t *__restrict__ label,
-                                                    int32_t *__restrict__ aggsize) {
-    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * kBlock) {
-        const int32_t a = label[v];
-        if (a >= 0) atomicAdd(&aggsize[a], 1);
+        if (v < n) flag[v] = f;
     }
 }
 
@@ -83,6 +112,25 @@ __global__ __launch_bounds__(kBlock) void k_copy_i32(const int32_t *__restrict__
         dst[i] = src[i];
 }
 
+// Each wavefront lists, in order, the vertices of its own range still
+// unlabelled after phase 2, as its segment of io.wl_out.
+__global__ __launch_bounds__(kBlock) void k_list_unlabelled(int64_t n,
+                                                            const int32_t *__restrict__ label,
+                                                            SegIO io) {
+    const int64_t w = wave_id();
+    const int lane = (int)(threadIdx.x & 63u);
+    const int64_t lo = w * io.seg, hi = min(n, lo + io.seg);
+    uint32_t kept = 0;
+    for (int64_t v0 = lo; v0 < hi; v0 += 64) {
+        const int64_t v = v0 + lane;
+        const bool keep = v < hi && label[v] == -1;
+        const uint64_t mask = __ballot(keep);
+        if (keep) io.wl_out[lo + kept + (uint32_t)__popcll(mask & lanes_below(lane))] = (int32_t)v;
+        kept += (uint32_t)__popcll(mask);
+    }
+    if (lane == 0 && w < io.S) io.cnt_out[w] = kept;
+}
+
 // Candidate order of phase 3: larger coupling first, then smaller aggsize,
 // then smaller aggregate id.  Returns true if (c1, s1, a1) beats (c2, s2, a2).
 __device__ __forceinline__ bool better(int c1, int s1, int a1, int c2, int s2, int a2) {
@@ -91,35 +139,52 @@ __device__ __forceinline__ bool better(int c1, int s1, int a1, int c2, int s2, i
     return a1 < a2;
 }
 
-// One wavefront per unaggregated row.  Lane j of chunk c1 holds the tent
-// label of neighbour c1*64 + j; its coupling is the number of equal labels
-// over all chunks, counted with broadcasts.  A lane-wise best is reduced
-// across the wavefront with the candidate order above.
+constexpr int32_t kPad = -2;  // label of a padding lane; never equals an aggregate id
+
+// One group of L lanes per unaggregated row of the wavefront's segment.
+// Lane j of chunk c1 holds the tent label of neighbour c1*L + j; its
+// coupling is the number of equal labels over all chunks of the row, counted
+// with in-group broadcasts.  The group's best candidate is then reduced with
+// the candidate order above.
+template <int L>
 __global__ __launch_bounds__(kBlock) void k_phase3(const int64_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col,
                                                    const int32_t *__restrict__ label,
                                                    const int32_t *__restrict__ aggsize,
-                                                   const int32_t *__restrict__ rows,
-                                                   const uint32_t *__restrict__ d_rows,
-                                                   int32_t *__restrict__ agg_out,
+                                                   SegIO io, int32_t *__restrict__ agg_out,
                                                    uint32_t *__restrict__ err) {
+    const int64_t w = wave_id();
+    if (w >= io.S) return;
+    const int64_t count = io.cnt_in[w];
+    const int64_t sbase = w * io.seg;
+    constexpr int G = 64 / L;
     const int lane = (int)(threadIdx.x & 63u);
-    const int64_t nrows = *d_rows;
-    const int64_t wstep = (int64_t)gridDim.x * (kBlock / 64);
-    for (int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); k < nrows;
-         k += wstep) {
-        const int32_t v = rows[k];
-        const int64_t s = row_ptr[v], e = row_ptr[v + 1];
-        int bc = 0, bs = 0x7FFFFFFF, ba = 0x7FFFFFFF;  // best (coupling, size, id)
-        for (int64_t c1 = s; c1 < e; c1 += 64) {
-            const int64_t j = c1 + lane;
-            const int32_t a = j < e ? label[col[j]] : -1;
+    const int sub = lane & (L - 1);
+    for (int64_t i0 = 0; i0 < count; i0 += G) {
+        const int64_t i = i0 + lane / L;
+        const bool valid = i < count;
+        int32_t v = 0;
+        int64_t s = 0, e = 0;
+        if (valid) {
+            v = io.wl_in[sbase + i];
+            s = row_ptr[v];
+            e = row_ptr[v + 1];
+        }
+        // every lane of the wavefront runs the same number of chunk steps
+        int64_t chunks = (e - s + L - 1) / L;
+        int64_t wmax = chunks;
+        for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off, 64));
+        int bc = 0, bs = 0x7FFFFFFF, ba = 0x7FFFFFFF;
+        for (int64_t c1 = 0; c1 < wmax; c1++) {
+            const int64_t j = s + c1 * L + sub;
+            const int32_t a = (c1 < chunks && j < e) ? label[col[j]] : kPad;
             int cnt = 0;
-            for (int64_t c2 = s; c2 < e; c2 += 64) {
-                const int64_t j2 = c2 + lane;
-                const int32_t a2 = j2 < e ? label[col[j2]] : -1;
-                const int lim = (int)min<int64_t>(64, e - c2);
-                for (int t = 0; t < lim; t++) cnt += (__shfl(a2, t, 64) == a);
+            for (int64_t c2 = 0; c2 < wmax; c2++) {
+                const int64_t j2 = s + c2 * L + sub;
+                const int32_t a2 =
+                    c2 == c1 ? a : ((c2 < chunks && j2 < e) ? label[col[j2]] : kPad);
+#pragma unroll
+                for (int t = 0; t < L; t++) cnt += (__shfl(a2, t, L) == a);
             }
             if (a >= 0) {
                 const int sz = aggsize[a];
@@ -130,17 +195,18 @@ __global__ __launch_bounds__(kBlock) void k_phase3(const int64_t *__restrict__ r
                 }
             }
         }
-        for (int off = 32; off > 0; off >>= 1) {
-            const int oc = __shfl_xor(bc, off, 64);
-            const int os = __shfl_xor(bs, off, 64);
-            const int oa = __shfl_xor(ba, off, 64);
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1) {
+            const int oc = __shfl_xor(bc, off, L);
+            const int os = __shfl_xor(bs, off, L);
+            const int oa = __shfl_xor(ba, off, L);
             if (better(oc, os, oa, bc, bs, ba)) {
                 bc = oc;
                 bs = os;
                 ba = oa;
             }
         }
-        if (lane == 0) {
+        if (valid && sub == 0) {
             if (bc > 0)
                 agg_out[v] = ba;
             else
@@ -161,24 +227,18 @@ int grid_for(int64_t work, int per_block, int cap) {
 hipError_t launch_label_roots(int64_t n, const int64_t *row_ptr, const int32_t *col,
                               const int32_t *roots, const uint32_t *d_count,
                               const uint32_t *d_base, bool only_unlabelled, int32_t *label,
-                              uint8_t *root_mark, uint8_t mark, hipStream_t s) {
-    hipLaunchKernelGGL(k_label_roots, dim3(grid_for(n / 4 + 1, kBlock / kLabelLanes, 4096)),
+                              int32_t *aggsize, uint8_t *root_mark, uint8_t mark, hipStream_t s) {
+    hipLaunchKernelGGL(k_label_roots, dim3(grid_for(n / 8 + 1, kBlock / kLabelLanes, 4096)),
                        dim3(kBlock), 0, s, row_ptr, col, roots, d_count, d_base,
-                       (int)only_unlabelled, label, root_mark, mark);
+                       (int)only_unlabelled, label, aggsize, root_mark, mark);
     return hipGetLastError();
 }
 
 hipError_t launch_accept_phase2(int64_t n, const int64_t *row_ptr, const int32_t *col,
                                 const uint32_t *T, const int32_t *label, uint8_t *flag,
                                 hipStream_t s) {
-    hipLaunchKernelGGL(k_accept_phase2, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, n,
+    hipLaunchKernelGGL(k_accept_phase2, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, n,
                        row_ptr, col, T, label, flag);
-    return hipGetLastError();
-}
-
-hipError_t launch_aggsize(int64_t n, const int32_t *label, int32_t *aggsize, hipStream_t s) {
-    hipLaunchKernelGGL(k_aggsize, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, n, label,
-                       aggsize);
     return hipGetLastError();
 }
 
@@ -189,11 +249,29 @@ hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_phase3(int64_t n, const int64_t *row_ptr, const int32_t *col,
-                         const int32_t *label, const int32_t *aggsize, const int32_t *rows,
-                         const uint32_t *d_rows, int32_t *agg_out, uint32_t *err, hipStream_t s) {
-    hipLaunchKernelGGL(k_phase3, dim3(grid_for(n / 8 + 1, kBlock / 64, 4096)), dim3(kBlock), 0, s,
-                       row_ptr, col, label, aggsize, rows, d_rows, agg_out, err);
+hipError_t launch_list_unlabelled(int blocks, int64_t n, const int32_t *label, const SegIO &io,
+                                  hipStream_t s) {
+    hipLaunchKernelGGL(k_list_unlabelled, dim3(blocks), dim3(kBlock), 0, s, n, label, io);
+    return hipGetLastError();
+}
+
+#define MIS2_P3_DISPATCH(L, ...)                                                       \
+    switch (L) {                                                                       \
+        case 1: hipLaunchKernelGGL(k_phase3<1>, __VA_ARGS__); break;                   \
+        case 2: hipLaunchKernelGGL(k_phase3<2>, __VA_ARGS__); break;                   \
+        case 4: hipLaunchKernelGGL(k_phase3<4>, __VA_ARGS__); break;                   \
+        case 8: hipLaunchKernelGGL(k_phase3<8>, __VA_ARGS__); break;                   \
+        case 16: hipLaunchKernelGGL(k_phase3<16>, __VA_ARGS__); break;                 \
+        case 32: hipLaunchKernelGGL(k_phase3<32>, __VA_ARGS__); break;                 \
+        case 64: hipLaunchKernelGGL(k_phase3<64>, __VA_ARGS__); break;                 \
+        default: return hipErrorInvalidValue;                                          \
+    }
+
+hipError_t launch_phase3(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
+                         const int32_t *label, const int32_t *aggsize, const SegIO &io,
+                         int32_t *agg_out, uint32_t *err, hipStream_t s) {
+    MIS2_P3_DISPATCH(lanes, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col, label, aggsize, io,
+                     agg_out, err);
     return hipGetLastError();
 }
 

@@ -20,11 +20,6 @@ struct PredU32Eq {
     uint32_t value;
     __device__ bool operator()(int64_t i) const { return a[i] == value; }
 };
-struct PredI32Eq {
-    const int32_t *a;
-    int32_t value;
-    __device__ bool operator()(int64_t i) const { return a[i] == value; }
-};
 struct PredU8Nz {
     const uint8_t *a;
     __device__ bool operator()(int64_t i) const { return a[i] != 0; }
@@ -141,9 +136,9 @@ hipError_t compact_u32_eq(const uint32_t *a, uint32_t value, int64_t n, int32_t 
     return compact(PredU32Eq{a, value}, n, out, d_count, blocksum, s);
 }
 
-hipError_t compact_i32_eq(const int32_t *a, int32_t value, int64_t n, int32_t *out,
-                          uint32_t *d_count, uint32_t *blocksum, hipStream_t s) {
-    return compact(PredI32Eq{a, value}, n, out, d_count, blocksum, s);
+hipError_t launch_scan_tiles(uint32_t *blocksum, int64_t nb, uint32_t *d_total, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kBlock), 0, s, blocksum, nb, d_total);
+    return hipGetLastError();
 }
 
 hipError_t compact_u8_nz(const uint8_t *a, int64_t n, int32_t *out, uint32_t *d_count,

@@ -20,9 +20,15 @@ constexpr uint32_t kOut = 0xFFFFFFFFu;
 constexpr uint32_t kAbsent = 0u;
 
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64s)
-constexpr int kTraceCap = 1024;   // rounds whose worklist sizes are recorded
+constexpr int kTraceCap = 4096;   // most rounds of one MIS-2 run
 constexpr int kRing = 4;          // per-round counter slots, slot = round % kRing
 constexpr int kScalars = 64;      // misc device scalars
+constexpr int kTraceSplit = 8;    // per-round size counters, one per XCD
+// Round table: row r holds the size of worklist1 (entries 0..7, summed) and
+// worklist2 (8..15) at the start of round r, and at entry 16 a flag that is
+// non-zero iff worklist1 is non-empty there.
+constexpr int kRoundStride = 32;
+constexpr int kRtAlive = 16;
 
 // Section V-A: f = xorshift64* (Vigna's parameters 12, 25, 27 and multiplier
 // 2685821657736338717, arithmetic mod 2^64); h(i, v) = f(f(i) ^ f(v)).
@@ -52,31 +58,32 @@ TupleParams tuple_params(int64_t n, uint64_t seed, uint64_t iter);
 
 // Scalar slots in Workspace::scalars.
 enum Scalar {
-    kS_Roots = 0,     // |MIS-2| of mis2_run
-    kS_Count1 = 1,    // phase-1 root count (aggregation)
-    kS_Active = 2,    // vertices left after phase 1
-    kS_Count2 = 3,    // accepted phase-2 roots
-    kS_Left = 4,      // vertices left after phase 2
-    kS_Err = 5,       // error bits
-    kS_Zero = 7,      // stays 0
+    kS_Roots = 0,   // |MIS-2| of mis2_run
+    kS_Count1 = 1,  // phase-1 root count (aggregation)
+    kS_Count2 = 3,  // accepted phase-2 roots
+    kS_Err = 5,     // error bits
 };
+
+constexpr int kMaxBlocks = 2048;              // most workgroups of a sweep grid
+constexpr int kMaxWaves = kMaxBlocks * (kBlock / 64);
 
 // The caller's workspace, carved into arrays (all 256-byte aligned).
 struct Workspace {
     uint32_t *T = nullptr;        // [n] packed row status tuples
     uint32_t *M = nullptr;        // [n] radius-1 minima
-    int32_t *wl1[2] = {};         // [n] undecided vertices, double buffered
+    int32_t *wl1[2] = {};         // [n] undecided vertices (per-wave segments), double buffered
     int32_t *wl2[2] = {};         // [n] vertices without an IN neighbour, double buffered
-    uint32_t *ring = nullptr;     // [2][kRing] worklist sizes (list 0 = wl1, 1 = wl2)
-    uint32_t *trace = nullptr;    // [kTraceCap][2] sizes at the start of each round
+    uint32_t *cnt1[2] = {};       // [kMaxWaves] per-wave sizes of wl1[i]
+    uint32_t *cnt2[2] = {};       // [kMaxWaves] per-wave sizes of wl2[i]
+    uint32_t *rt = nullptr;       // [kTraceCap + 2][kRoundStride] round table
     uint32_t *scalars = nullptr;  // [kScalars]
+    unsigned long long *degs = nullptr;  // [2][kTraceCap][2] row-length sums per sweep
+    uint32_t *blocksum = nullptr; // [compact_blocks(n) + 1]
     // aggregation only
     int32_t *label = nullptr;     // [n] aggregate labels, -1 = none
     int32_t *list = nullptr;      // [n] ordered vertex lists
     uint8_t *flag = nullptr;      // [n]
     int32_t *aggsize = nullptr;   // [n]
-    uint32_t *blocksum = nullptr; // [compact_blocks(n) + 1]
-    int32_t *active = nullptr;    // [n] vertices of an induced subgraph
 };
 
 size_t workspace_bytes(int64_t n, int op);
@@ -85,37 +92,47 @@ bool carve(void *base, size_t bytes, int64_t n, int op, Workspace *ws);
 // Launch-plan knobs; never change results.
 struct Plan {
     int lanes = 0;   // lanes per CSR row (power of two <= 64); 0 = automatic
-    int blocks = 0;  // workgroups per sweep; 0 = automatic
+    int blocks = 0;  // workgroups per sweep (<= kMaxBlocks); 0 = automatic
 };
 
-// One sweep's worklist plumbing.  cnt_in == nullptr means the identity list
-// 0..identity_n-1.  cnt_zero (may be null) is cleared by the sweep for a
-// later round; trace_slot (may be null) receives the input size.
-struct SweepIO {
+// One sweep's worklists.  Wavefront w owns slots [w*seg, w*seg + cnt[w]) of
+// each list.  cnt_in == nullptr means the identity lists (w's whole vertex
+// range).  trace_out (may be null) points at kTraceSplit counters whose sum
+// becomes the output size; alive_out (may be null) is set to 1 by
+// wavefronts that keep a row; round_zero (may be null) is a round-table row
+// cleared for a later round; deg_sum (may be null) accumulates the visited
+// CSR row lengths.
+struct SegIO {
     const int32_t *wl_in;
     const uint32_t *cnt_in;
-    int64_t identity_n;
     int32_t *wl_out;
     uint32_t *cnt_out;
-    uint32_t *cnt_zero;
-    uint32_t *trace_slot;
+    uint32_t *trace_out;
+    uint32_t *alive_out;
+    uint32_t *round_zero;  // may be null: kRoundStride entries the sweep clears
+    unsigned long long *deg_sum;
+    int64_t n;
+    int64_t seg;
+    int64_t S;
 };
 
 // mis2_kernels.hip
-hipError_t launch_init_tuples(const TupleParams &tp, int64_t n, uint32_t *T, uint32_t *ring,
-                              hipStream_t s);
-hipError_t launch_init_masked(const TupleParams &tp, int64_t n, const int32_t *label, uint32_t *T,
-                              uint32_t *M, uint32_t *ring, hipStream_t s);
+hipError_t launch_init_tuples(const TupleParams &tp, int64_t n, uint32_t *T, hipStream_t s);
+hipError_t launch_init_masked(int blocks, const TupleParams &tp, int64_t n, const int32_t *label,
+                              uint32_t *T, uint32_t *M, const SegIO &io, hipStream_t s);
 hipError_t launch_refresh_column(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
-                                 const uint32_t *T, uint32_t *M, const SweepIO &io, hipStream_t s);
+                                 const uint32_t *T, uint32_t *M, const SegIO &io, hipStream_t s);
 hipError_t launch_decide(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
-                         uint32_t *T, const uint32_t *M, const TupleParams &next,
-                         const SweepIO &io, hipStream_t s);
-hipError_t launch_status(int64_t n, const uint32_t *T, uint8_t *status, uint32_t *count,
+                         uint32_t *T, const uint32_t *M, const TupleParams &next, const SegIO &io,
                          hipStream_t s);
+int64_t status_blocks(int64_t n);
+hipError_t launch_status(int64_t n, const uint32_t *T, uint8_t *status, uint32_t *blocksum,
+                         uint32_t *d_total, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t count, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, uint8_t value, int64_t count, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long value, int64_t count,
+                           hipStream_t s);
 hipError_t launch_validate(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
                            uint32_t *err, hipStream_t s);
 
@@ -124,24 +141,25 @@ hipError_t launch_validate(int64_t n, int64_t nnz, const int64_t *row_ptr, const
 int64_t compact_blocks(int64_t n);
 hipError_t compact_u32_eq(const uint32_t *a, uint32_t value, int64_t n, int32_t *out,
                           uint32_t *d_count, uint32_t *blocksum, hipStream_t s);
-hipError_t compact_i32_eq(const int32_t *a, int32_t value, int64_t n, int32_t *out,
-                          uint32_t *d_count, uint32_t *blocksum, hipStream_t s);
 hipError_t compact_u8_nz(const uint8_t *a, int64_t n, int32_t *out, uint32_t *d_count,
                          uint32_t *blocksum, hipStream_t s);
+// Exclusive scan of blocksum[0..nb) in place; total -> blocksum[nb], *d_total.
+hipError_t launch_scan_tiles(uint32_t *blocksum, int64_t nb, uint32_t *d_total, hipStream_t s);
 
 // aggregate.hip
 hipError_t launch_label_roots(int64_t n, const int64_t *row_ptr, const int32_t *col,
                               const int32_t *roots, const uint32_t *d_count,
                               const uint32_t *d_base, bool only_unlabelled, int32_t *label,
-                              uint8_t *root_mark, uint8_t mark, hipStream_t s);
+                              int32_t *aggsize, uint8_t *root_mark, uint8_t mark, hipStream_t s);
 hipError_t launch_accept_phase2(int64_t n, const int64_t *row_ptr, const int32_t *col,
                                 const uint32_t *T, const int32_t *label, uint8_t *flag,
                                 hipStream_t s);
-hipError_t launch_aggsize(int64_t n, const int32_t *label, int32_t *aggsize, hipStream_t s);
 hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStream_t s);
-hipError_t launch_phase3(int64_t n, const int64_t *row_ptr, const int32_t *col,
-                         const int32_t *label, const int32_t *aggsize, const int32_t *rows,
-                         const uint32_t *d_rows, int32_t *agg_out, uint32_t *err, hipStream_t s);
+hipError_t launch_list_unlabelled(int blocks, int64_t n, const int32_t *label, const SegIO &io,
+                                  hipStream_t s);
+hipError_t launch_phase3(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
+                         const int32_t *label, const int32_t *aggsize, const SegIO &io,
+                         int32_t *agg_out, uint32_t *err, hipStream_t s);
 
 }  // namespace mis2
 
@@ -154,6 +172,11 @@ struct mis2_ctx {
     uint32_t *pinned = nullptr;  // host-pinned scalars for read-back
     std::string err;
     int validate = 0;
+    int profile = 0;
+    int account = 0;
     mis2::Plan plan;
     std::vector<int64_t> trace[2];  // per-round |wl1|, |wl2| of the last run(s)
+    std::vector<mis2_sweep_record> sweeps;  // launches of the last call
+    std::vector<hipEvent_t> events;         // profiling event pool
+    size_t events_used = 0;
 };
