@@ -53,10 +53,13 @@ extern "C" {
 
 /* Options, for mis2_set_option(). */
 #define MIS2_OPT_VALIDATE      0  /* 1: check the CSR on the GPU before each call (default 0) */
-#define MIS2_OPT_LANES_PER_ROW 1  /* 0 = automatic; else 1, 2, 4, 8, 16, 32 or 64 lanes per CSR row */
+#define MIS2_OPT_LANES_PER_ROW 1  /* 0 = automatic; -1 = flat (merge-path) sweeps; else 1, 2, 4,
+                                     8, 16, 32 or 64 lanes per CSR row */
 #define MIS2_OPT_GRID_BLOCKS   2  /* 0 = automatic; else the number of 256-thread workgroups per sweep */
 #define MIS2_OPT_PROFILE       3  /* 1: time every sweep launch with HIP events on the call's stream */
 #define MIS2_OPT_ACCOUNT       4  /* 1: sweeps also sum the CSR row lengths they visit (extra atomics) */
+#define MIS2_OPT_PERSISTENT    5  /* 1 (default): all rounds of a MIS-2 run in one cooperative launch;
+                                     0: two launches per round (also the fallback) */
 
 typedef struct mis2_ctx mis2_ctx;
 
@@ -120,9 +123,12 @@ int mis2_last_trace(const mis2_ctx *ctx, int phase, int64_t *sizes, int32_t cap,
 
 /* One sweep launch of the last mis2_run / mis2_aggregate call. */
 typedef struct mis2_sweep_record {
-    int32_t kind;      /* 0 = Refresh Column (worklist2), 1 = Decide Set (worklist1) */
+    int32_t kind;      /* 0 = Refresh Column (worklist2), 1 = Decide Set (worklist1),
+                          2 = one persistent launch running every round of the phase
+                          (then rows and edges are totals over its sweeps, rows_out is
+                          the round count, and the per-sweep records carry ms = -1) */
     int32_t phase;     /* 0 = MIS-2 of G; 1 = MIS-2 of the phase-2 induced subgraph */
-    int32_t round;     /* round of Algorithm 1, from 0 */
+    int32_t round;     /* round of Algorithm 1, from 0 (-1 for kind 2) */
     int32_t lanes;     /* lanes per CSR row used by the launch */
     int64_t rows;      /* worklist entries processed */
     int64_t rows_out;  /* entries kept for the next round */
@@ -157,6 +163,48 @@ int mis2_last_sweeps(const mis2_ctx *ctx, mis2_sweep_record *out, int32_t cap, i
  */
 int mis2_aggregate(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *agg_id,
                    int64_t *n_agg, uint8_t *roots, void *stream);
+
+/*
+ * mis2_quotient -- the coarse graph of an aggregation, for multilevel
+ * coarsening.  The paper coarsens recursively (Sections I and II) but does
+ * not say how the coarse graph is formed; here it is the quotient graph:
+ * vertex a of the coarse graph is aggregate a, and a and c are adjacent iff
+ * some edge (u, w) of g has agg_id[u] = a, agg_id[w] = c and a != c.
+ *
+ *   agg_id          device, int32[n]: labels in [0, n_agg) (as from mis2_aggregate)
+ *   n_agg           number of aggregates, 0 <= n_agg <= n
+ *   coarse_row_ptr  device out, int64[n_agg + 1]
+ *   coarse_col      device out, int32[g->nnz] (capacity; the coarse graph has at
+ *                   most g->nnz entries), ascending and distinct in every row,
+ *                   no self-loops
+ *   coarse_nnz      host out (may be NULL)
+ * Needs a workspace of mis2_workspace_bytes(n, MIS2_OP_COARSEN).
+ */
+int mis2_quotient(mis2_ctx *ctx, const mis2_graph *g, const int32_t *agg_id, int64_t n_agg,
+                  int64_t *coarse_row_ptr, int32_t *coarse_col, int64_t *coarse_nnz, void *stream);
+
+/* Bytes of device workspace mis2_coarsen needs for a graph with n vertices
+ * and nnz stored entries (written to *bytes, host). */
+int mis2_coarsen_workspace_bytes(int64_t n, int64_t nnz, size_t *bytes);
+
+/*
+ * mis2_coarsen -- multilevel coarsening: MIS-2 aggregation (Algorithm 3),
+ * then the quotient graph, repeated while the current graph has at least
+ * stop_below vertices, at most max_levels times, and stopping early when a
+ * level does not shrink.  Every level uses the same seed.
+ *
+ *   agg_out     device out, int32[agg_cap]: the labels of level l start at
+ *               the sum of the vertex counts of levels 0..l-1
+ *   level_n, level_nnz, level_nagg
+ *               host out, int64[max_levels]: vertices, stored entries and
+ *               aggregates of each level's input graph
+ *   n_levels    host out: levels computed (0 if g->n < stop_below)
+ * Needs a workspace of mis2_coarsen_workspace_bytes(n, nnz).
+ * MIS2_ENOSPACE if agg_cap is too small for the levels' labels.
+ */
+int mis2_coarsen(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int64_t stop_below,
+                 int32_t max_levels, int32_t *agg_out, int64_t agg_cap, int64_t *level_n,
+                 int64_t *level_nnz, int64_t *level_nagg, int32_t *n_levels, void *stream);
 
 #ifdef __cplusplus
 }

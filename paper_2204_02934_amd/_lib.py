@@ -24,12 +24,14 @@ MIS2_OPT_LANES_PER_ROW = 1
 MIS2_OPT_GRID_BLOCKS = 2
 MIS2_OPT_PROFILE = 3
 MIS2_OPT_ACCOUNT = 4
+MIS2_OPT_PERSISTENT = 5
 
 # Every symbol include/mis2.h declares.
 EXPORTS = (
     "mis2_create", "mis2_destroy", "mis2_last_error", "mis2_set_option",
     "mis2_workspace_bytes", "mis2_set_workspace", "mis2_run", "mis2_last_trace",
-    "mis2_aggregate", "mis2_last_sweeps",
+    "mis2_aggregate", "mis2_last_sweeps", "mis2_quotient", "mis2_coarsen_workspace_bytes",
+    "mis2_coarsen",
 )
 
 
@@ -77,6 +79,11 @@ def load():
         "mis2_aggregate": (ctypes.c_int, [vp, gp, u64, vp, ctypes.POINTER(i64), vp, vp]),
         "mis2_last_sweeps": (ctypes.c_int, [vp, ctypes.POINTER(Mis2SweepRecord), i32,
                                             ctypes.POINTER(i32)]),
+        "mis2_quotient": (ctypes.c_int, [vp, gp, vp, i64, vp, vp, ctypes.POINTER(i64), vp]),
+        "mis2_coarsen_workspace_bytes": (ctypes.c_int, [i64, i64, ctypes.POINTER(ctypes.c_size_t)]),
+        "mis2_coarsen": (ctypes.c_int, [vp, gp, u64, i64, i32, vp, i64, ctypes.POINTER(i64),
+                                        ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                        ctypes.POINTER(i32), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

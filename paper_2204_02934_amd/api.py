@@ -40,7 +40,7 @@ class Context:
     on demand (allocation happens outside the library calls)."""
 
     def __init__(self, device=None, validate=False, lanes=0, blocks=0, profile=False,
-                 account=False):
+                 account=False, persistent=True):
         self.lib = _lib.load()
         if device is None:
             device = torch.cuda.current_device()
@@ -53,6 +53,7 @@ class Context:
         self.set_option(_lib.MIS2_OPT_GRID_BLOCKS, blocks)
         self.set_option(_lib.MIS2_OPT_PROFILE, int(profile))
         self.set_option(_lib.MIS2_OPT_ACCOUNT, int(account))
+        self.set_option(_lib.MIS2_OPT_PERSISTENT, int(persistent))
 
     def __del__(self):
         lib = getattr(self, "lib", None)
@@ -114,6 +115,59 @@ class Context:
         if want_roots:
             return agg[:g.n], na.value, roots[:g.n]
         return agg[:g.n], na.value
+
+    def _ensure_bytes(self, need):
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+            _check(self.lib, self.ptr, self.lib.mis2_set_workspace(
+                self.ptr, ctypes.c_void_p(self._ws.data_ptr()), self._ws.numel()))
+
+    def quotient(self, row_ptr, col, agg, n_agg, stream=None, nnz=None):
+        """Coarse (quotient) graph of an aggregation: (row_ptr int64[n_agg+1],
+        col int32[coarse nnz]) on the GPU."""
+        g, keep = self.graph(row_ptr, col, nnz)
+        self.ensure_workspace(g.n, _lib.MIS2_OP_COARSEN)
+        agg = torch.as_tensor(agg).to(device=self.device, dtype=torch.int32).contiguous()
+        crow = torch.empty(n_agg + 1, dtype=torch.int64, device=self.device)
+        ccol = torch.empty(max(g.nnz, 1), dtype=torch.int32, device=self.device)
+        cnnz = ctypes.c_int64(0)
+        rc = self.lib.mis2_quotient(self.ptr, ctypes.byref(g), ctypes.c_void_p(agg.data_ptr()),
+                                    int(n_agg), ctypes.c_void_p(crow.data_ptr()),
+                                    ctypes.c_void_p(ccol.data_ptr()), ctypes.byref(cnnz),
+                                    _stream_ptr(stream, self.device))
+        _check(self.lib, self.ptr, rc)
+        del keep
+        return crow, ccol[:cnnz.value]
+
+    def coarsen(self, row_ptr, col, seed=0, stop_below=1000, max_levels=64, stream=None, nnz=None):
+        """Multilevel coarsening: list of per-level dicts {n, nnz, n_agg, agg
+        (int32 labels on the GPU)}."""
+        g, keep = self.graph(row_ptr, col, nnz)
+        b = ctypes.c_size_t(0)
+        _check(self.lib, self.ptr, self.lib.mis2_coarsen_workspace_bytes(g.n, g.nnz, ctypes.byref(b)))
+        self._ensure_bytes(b.value)
+        cap = max(2 * g.n, 1)
+        agg = torch.empty(cap, dtype=torch.int32, device=self.device)
+        ln = (ctypes.c_int64 * max(max_levels, 1))()
+        lz = (ctypes.c_int64 * max(max_levels, 1))()
+        la = (ctypes.c_int64 * max(max_levels, 1))()
+        nl = ctypes.c_int32(0)
+        while True:
+            rc = self.lib.mis2_coarsen(self.ptr, ctypes.byref(g), ctypes.c_uint64(seed),
+                                       int(stop_below), int(max_levels),
+                                       ctypes.c_void_p(agg.data_ptr()), agg.numel(), ln, lz, la,
+                                       ctypes.byref(nl), _stream_ptr(stream, self.device))
+            if rc == _lib.MIS2_ENOSPACE and b"agg_cap" in self.lib.mis2_last_error(self.ptr):
+                agg = torch.empty(2 * agg.numel(), dtype=torch.int32, device=self.device)
+                continue
+            break
+        _check(self.lib, self.ptr, rc)
+        del keep
+        out, off = [], 0
+        for i in range(nl.value):
+            out.append({"n": ln[i], "nnz": lz[i], "n_agg": la[i], "agg": agg[off:off + ln[i]]})
+            off += ln[i]
+        return out
 
     def last_trace(self, phase=0, cap=4096):
         """Per-round (|worklist1|, |worklist2|) of the last call, int64[rounds, 2]."""

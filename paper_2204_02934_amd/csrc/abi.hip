@@ -46,17 +46,21 @@ int check_graph_args(mis2_ctx *ctx, const mis2_graph *g) {
     return MIS2_OK;
 }
 
+// Lanes per row of the MIS-2 sweeps; 0 selects the flat (merge-path) sweeps.
 int lanes_for(const mis2_ctx *ctx, const mis2_graph *g) {
+    if (ctx->plan.lanes == -1) return 0;
     if (ctx->plan.lanes) return ctx->plan.lanes;
     // Section V-D: one thread per row below an average degree of 16, lanes
     // cooperating on a row above it; here the group grows with the degree.
+    // Measured on gfx950: 4-lane groups (16 rows per wavefront step, 4 in
+    // flight per group) beat wider groups for average degrees up to ~64;
+    // longer rows go to the whole wavefront anyway.
     const double avg = g->n > 0 ? (double)g->nnz / (double)g->n : 0.0;
-    if (avg < 4) return 1;
-    if (avg < 8) return 4;
-    if (avg < 16) return 8;
-    if (avg < 32) return 16;
-    if (avg < 64) return 32;
-    return 64;
+    if (avg < 2) return 1;
+    if (avg < 4) return 2;
+    if (avg < 64) return 4;
+    if (avg < 256) return 8;
+    return 16;
 }
 
 // Workgroups of the segmented sweeps: a multiple of 8 (one run of logical
@@ -102,6 +106,7 @@ hipEvent_t take_event(mis2_ctx *ctx) {
 struct Launch {
     int kind, phase, round, lanes;
     hipEvent_t e0, e1;
+    bool persistent = false;  // a sweep inside a persistent launch (timed by device stamps)
 };
 
 // Segment geometry of a run: S wavefronts, seg vertices each.
@@ -110,12 +115,118 @@ struct Geometry {
     int64_t S, seg;
 };
 
-Geometry geometry(const mis2_ctx *ctx, int64_t n) {
+Geometry geometry(const mis2_ctx *ctx, int64_t n, int lanes) {
     Geometry gm;
     gm.blocks = blocks_for(ctx, n);
+    if (!ctx->plan.blocks && ctx->plan.persistent) {
+        // the persistent launch needs every workgroup resident at once
+        const int cap = rounds_max_blocks(lanes, ctx->num_cus) / 8 * 8;
+        if (cap >= 8 && gm.blocks > cap) gm.blocks = cap;
+    }
     gm.S = (int64_t)gm.blocks * (kBlock / 64);
     gm.seg = std::max<int64_t>(1, (n + gm.S - 1) / gm.S);
     return gm;
+}
+
+// Per-round sizes as recorded by the sweeps in the round table (rows
+// 0..rounds-1); the first round with an empty worklist1 ends the run.
+int read_trace(mis2_ctx *ctx, const mis2_graph *g, const Workspace &ws, bool masked, int phase,
+               int rounds, hipStream_t s, int32_t *iters_out) {
+    std::vector<uint32_t> rt((size_t)rounds * kRoundStride);
+    if (rounds > 0) {
+        HIP_TRY(ctx, hipMemcpyAsync(rt.data(), ws.rt, rt.size() * sizeof(uint32_t),
+                                    hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    std::vector<int64_t> &tr = ctx->trace[phase];
+    tr.clear();
+    std::vector<float> &st = ctx->stamp_ms[phase];
+    st.clear();
+    auto stamp_at = [&](int row, int word) {
+        const uint32_t *p = &rt[(size_t)row * kRoundStride + word];
+        return (double)((uint64_t)p[0] | ((uint64_t)p[1] << 32));
+    };
+    for (int q = 0; q < rounds; q++) {
+        const double t0 = stamp_at(q, kRtStamp0), t1 = stamp_at(q, kRtStamp1),
+                     t2 = stamp_at(q, kRtStamp2);
+        st.push_back((float)((t1 - t0) / ctx->wall_khz));
+        st.push_back((float)((t2 - t1) / ctx->wall_khz));
+    }
+    int r = 0;
+    for (; r < rounds; r++) {
+        int64_t c1 = 0, c2 = 0;
+        for (int k = 0; k < kTraceSplit; k++) {
+            c1 += rt[(size_t)r * kRoundStride + k];
+            c2 += rt[(size_t)r * kRoundStride + kTraceSplit + k];
+        }
+        if (r == 0) {
+            if (!masked) c1 = g->n;
+            c2 = c1;
+        }
+        if (c1 == 0) break;
+        tr.push_back(c1);
+        tr.push_back(c2);
+    }
+    *iters_out = r;
+    return MIS2_OK;
+}
+
+constexpr int kFallBack = 1;
+
+// All rounds in one cooperative launch (k_rounds).  Returns kFallBack when
+// the grid cannot be made co-resident, so the caller issues rounds instead.
+int run_rounds_persistent(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspace &ws,
+                          const Geometry &gm, bool masked, int phase, hipStream_t s,
+                          int32_t *iters_out, std::vector<Launch> *launches, int lanes) {
+    const int cap = rounds_max_blocks(lanes, ctx->num_cus);
+    if (cap < gm.blocks) return kFallBack;  // geometry() sizes the default plan to fit
+    unsigned long long *degs = ws.degs + (size_t)phase * kTraceCap * 2;
+    HIP_TRY(ctx, launch_fill_u32(ws.bar, 0u, kBarWords, s));
+    const TupleParams tp = tuple_params(g->n, seed, 0);
+    RoundsArgs a;
+    a.wl1[0] = ws.wl1[0];
+    a.wl1[1] = ws.wl1[1];
+    a.wl2[0] = ws.wl2[0];
+    a.wl2[1] = ws.wl2[1];
+    a.cnt1[0] = ws.cnt1[0];
+    a.cnt1[1] = ws.cnt1[1];
+    a.cnt2[0] = ws.cnt2[0];
+    a.cnt2[1] = ws.cnt2[1];
+    a.rt = ws.rt;
+    a.degs = ctx->account ? degs : nullptr;
+    a.bar = ws.bar;
+    a.n = g->n;
+    a.seg = gm.seg;
+    a.S = gm.S;
+    a.seed = seed;
+    a.pmask = tp.pmask;
+    a.b = tp.b;
+    a.masked = masked ? 1 : 0;
+    a.max_rounds = kTraceCap;
+    Launch lp{2, phase, -1, lanes, nullptr, nullptr};
+    if (ctx->profile) {
+        lp.e0 = take_event(ctx), lp.e1 = take_event(ctx);
+        if (!lp.e0 || !lp.e1) return fail(ctx, MIS2_EHIP, "hipEventCreate failed");
+        HIP_TRY(ctx, hipEventRecord(lp.e0, s));
+    }
+    HIP_TRY(ctx, launch_rounds(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M, a, s));
+    if (ctx->profile) HIP_TRY(ctx, hipEventRecord(lp.e1, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned + 32, ws.bar + kMaxBlocks, 64 * sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (ctx->pinned[32 + 16])
+        return fail(ctx, MIS2_EINTERNAL, "grid barrier timed out in the round kernel");
+    const int rounds = (int)ctx->pinned[32 + 32];
+    int rc = read_trace(ctx, g, ws, masked, phase, rounds, s, iters_out);
+    if (rc) return rc;
+    if (*iters_out >= rounds && rounds + 2 >= kTraceCap)
+        return fail(ctx, MIS2_EINTERNAL, "more than %d rounds", kTraceCap - 2);
+    for (int r = 0; r < rounds; r++) {
+        launches->push_back(Launch{0, phase, r, lanes, nullptr, nullptr, true});
+        launches->push_back(Launch{1, phase, r, lanes, nullptr, nullptr, true});
+    }
+    launches->push_back(lp);
+    return MIS2_OK;
 }
 
 // The round loop of Algorithm 1.  Round 0 starts from the identity
@@ -146,6 +257,11 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
     for (int i = 0; i < 2; i++)
         if (!(chunk_done[i] = take_event(ctx)))
             return fail(ctx, MIS2_EHIP, "hipEventCreate failed");
+    if (ctx->plan.persistent) {
+        int rc = run_rounds_persistent(ctx, g, seed, ws, gm, masked, phase, s, iters_out, launches,
+                                       lanes);
+        if (rc != kFallBack) return rc;
+    }
     int round = 0, chunk = 0;
     for (;;) {
         for (int k = 0; k < kChunk; k++, round++) {
@@ -208,31 +324,7 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
         }
         chunk++;
     }
-    // Per-round sizes as recorded by the sweeps; the first round with an
-    // empty worklist1 ends the run.
-    std::vector<uint32_t> rt((size_t)round * kRoundStride);
-    HIP_TRY(ctx, hipMemcpyAsync(rt.data(), ws.rt, rt.size() * sizeof(uint32_t),
-                                hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
-    std::vector<int64_t> &tr = ctx->trace[phase];
-    tr.clear();
-    int r = 0;
-    for (; r < round; r++) {
-        int64_t c1 = 0, c2 = 0;
-        for (int k = 0; k < kTraceSplit; k++) {
-            c1 += rt[(size_t)r * kRoundStride + k];
-            c2 += rt[(size_t)r * kRoundStride + kTraceSplit + k];
-        }
-        if (r == 0) {
-            if (!masked) c1 = g->n;
-            c2 = c1;
-        }
-        if (c1 == 0) break;
-        tr.push_back(c1);
-        tr.push_back(c2);
-    }
-    *iters_out = r;
-    return MIS2_OK;
+    return read_trace(ctx, g, ws, masked, phase, round, s, iters_out);
 }
 
 // Fill ctx->sweeps from the launches of the finished call.
@@ -249,6 +341,32 @@ int collect_sweeps(mis2_ctx *ctx, const std::vector<Launch> &launches, const Wor
     for (const Launch &l : launches) {
         const std::vector<int64_t> &tr = ctx->trace[l.phase];
         const int rounds = (int)(tr.size() / 2);
+        if (l.kind == 2) {
+            // one persistent launch covering every round of this phase
+            mis2_sweep_record rec;
+            memset(&rec, 0, sizeof rec);
+            rec.kind = 2;
+            rec.phase = l.phase;
+            rec.round = -1;
+            rec.lanes = l.lanes;
+            rec.rows = 0;
+            rec.edges = ctx->account ? 0 : -1;
+            for (int r = 0; r < rounds; r++) {
+                rec.rows += tr[2 * r] + tr[2 * r + 1];
+                if (ctx->account)
+                    rec.edges += (int64_t)degs[((size_t)l.phase * kTraceCap + r) * 2] +
+                                 (int64_t)degs[((size_t)l.phase * kTraceCap + r) * 2 + 1];
+            }
+            rec.rows_out = rounds;
+            rec.ms = -1.0f;
+            if (ctx->profile && l.e0 && l.e1) {
+                float ms = 0.f;
+                HIP_TRY(ctx, hipEventElapsedTime(&ms, l.e0, l.e1));
+                rec.ms = ms;
+            }
+            ctx->sweeps.push_back(rec);
+            continue;
+        }
         if (l.round >= rounds) continue;  // issued after the run had finished
         mis2_sweep_record rec;
         memset(&rec, 0, sizeof rec);
@@ -266,6 +384,10 @@ int collect_sweeps(mis2_ctx *ctx, const std::vector<Launch> &launches, const Wor
             float ms = 0.f;
             HIP_TRY(ctx, hipEventElapsedTime(&ms, l.e0, l.e1));
             rec.ms = ms;
+        } else if (ctx->profile && l.persistent) {
+            const std::vector<float> &st = ctx->stamp_ms[l.phase];
+            const size_t k = (size_t)l.round * 2 + (size_t)l.kind;
+            if (k < st.size()) rec.ms = st[k];
         }
         ctx->sweeps.push_back(rec);
     }
@@ -287,9 +409,15 @@ size_t workspace_bytes(int64_t n, int op) {
     b += align_up(4 * kScalars);                        // scalars
     b += align_up(8 * 2 * 2 * (size_t)kTraceCap);       // degs
     b += align_up(4 * (size_t)(compact_blocks(n) + 1)); // blocksum
+    b += align_up(4 * (size_t)kBarWords);               // barrier state
     if (op != MIS2_OP_MIS2) {
         b += align_up(4 * un) * 3;                      // label, list, aggsize
         b += align_up(un);                              // flag
+    }
+    if (op == MIS2_OP_COARSEN) {
+        b += align_up(4 * un) * 2;                      // quotient counts, members
+        b += align_up(8 * (un + 1));                    // member offsets
+        b += align_up(8 * (size_t)scan_parts(n));       // scan partials
     }
     return b;
 }
@@ -317,11 +445,18 @@ bool carve(void *base, size_t bytes, int64_t n, int op, Workspace *ws) {
     ws->scalars = (uint32_t *)take(4 * kScalars);
     ws->degs = (unsigned long long *)take(8 * 2 * 2 * (size_t)kTraceCap);
     ws->blocksum = (uint32_t *)take(4 * (size_t)(compact_blocks(n) + 1));
+    ws->bar = (uint32_t *)take(4 * (size_t)kBarWords);
     if (op != MIS2_OP_MIS2) {
         ws->label = (int32_t *)take(4 * un);
         ws->list = (int32_t *)take(4 * un);
         ws->aggsize = (int32_t *)take(4 * un);
         ws->flag = (uint8_t *)take(un);
+    }
+    if (op == MIS2_OP_COARSEN) {
+        ws->q.cnt = (uint32_t *)take(4 * un);
+        ws->q.members = (int32_t *)take(4 * un);
+        ws->q.moff = (int64_t *)take(8 * (un + 1));
+        ws->q.part = (unsigned long long *)take(8 * (size_t)scan_parts(n));
     }
     return true;
 }
@@ -345,6 +480,9 @@ int mis2_create(mis2_ctx **out, int device) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         ctx->num_cus = prop.multiProcessorCount;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+        ctx->wall_khz = (double)khz;
     if (hipHostMalloc((void **)&ctx->pinned, (64 + 2 * kTraceCap) * sizeof(uint32_t),
                       hipHostMallocDefault) != hipSuccess) {
         delete ctx;
@@ -373,8 +511,9 @@ int mis2_set_option(mis2_ctx *ctx, int option, int64_t value) {
             ctx->validate = value != 0;
             return MIS2_OK;
         case MIS2_OPT_LANES_PER_ROW:
-            if (value != 0 && (value < 1 || value > 64 || (value & (value - 1))))
-                return fail(ctx, MIS2_EINVAL, "lanes per row must be 0 or a power of two <= 64");
+            if (value != 0 && value != -1 && (value < 1 || value > 64 || (value & (value - 1))))
+                return fail(ctx, MIS2_EINVAL,
+                            "lanes per row must be 0, -1 or a power of two <= 64");
             ctx->plan.lanes = (int)value;
             return MIS2_OK;
         case MIS2_OPT_GRID_BLOCKS:
@@ -384,6 +523,9 @@ int mis2_set_option(mis2_ctx *ctx, int option, int64_t value) {
             return MIS2_OK;
         case MIS2_OPT_PROFILE:
             ctx->profile = value != 0;
+            return MIS2_OK;
+        case MIS2_OPT_PERSISTENT:
+            ctx->plan.persistent = value != 0;
             return MIS2_OK;
         case MIS2_OPT_ACCOUNT:
             ctx->account = value != 0;
@@ -429,7 +571,7 @@ int mis2_run(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, uint8_t *status,
 
     ctx->events_used = 0;
     std::vector<Launch> launches;
-    const Geometry gm = geometry(ctx, g->n);
+    const Geometry gm = geometry(ctx, g->n, lanes_for(ctx, g));
     HIP_TRY(ctx, launch_init_tuples(tuple_params(g->n, seed, 0), g->n, ws.T, s));
     int32_t iters = 0;
     if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, &iters, &launches))) return rc;
@@ -463,28 +605,19 @@ int mis2_last_sweeps(const mis2_ctx *ctx, mis2_sweep_record *out, int32_t cap, i
     return MIS2_OK;
 }
 
-int mis2_aggregate(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *agg_id,
-                   int64_t *n_agg, uint8_t *roots, void *stream) {
-    int rc = check_graph_args(ctx, g);
-    if (rc) return rc;
-    if (g->n > 0 && !agg_id) return fail(ctx, MIS2_EINVAL, "agg_id is NULL");
-    hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(ctx, hipSetDevice(ctx->device));
-    ctx->trace[0].clear();
-    ctx->trace[1].clear();
-    ctx->sweeps.clear();
-    if (g->n == 0) {
-        if (n_agg) *n_agg = 0;
-        return MIS2_OK;
-    }
-    Workspace ws;
-    if ((rc = get_workspace(ctx, g, MIS2_OP_AGGREGATE, &ws))) return rc;
-    if ((rc = maybe_validate(ctx, g, ws, s))) return rc;
+}  // extern "C"
+
+namespace {
+
+// Algorithm 3 on a validated graph with n > 0 and a carved workspace.
+int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *agg_id,
+                   int64_t *n_agg, uint8_t *roots, const Workspace &ws, hipStream_t s) {
+    int rc;
     const int64_t n = g->n;
     uint32_t *sc = ws.scalars;
     ctx->events_used = 0;
     std::vector<Launch> launches;
-    const Geometry gm = geometry(ctx, n);
+    const Geometry gm = geometry(ctx, n, lanes_for(ctx, g));
 
     // Phase 1: MIS-2 of G; roots numbered by increasing id, each labelled with
     // its neighbours.
@@ -520,7 +653,8 @@ int mis2_aggregate(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
     HIP_TRY(ctx, launch_list_unlabelled(gm.blocks, n, ws.label, left_io, s));
     SegIO p3_io{ws.wl2[0], ws.cnt2[0], nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                 n, gm.seg, gm.S};
-    HIP_TRY(ctx, launch_phase3(lanes_for(ctx, g), gm.blocks, g->row_ptr, g->col, ws.label,
+    const int p3_lanes = lanes_for(ctx, g) > 0 ? lanes_for(ctx, g) : 4;
+    HIP_TRY(ctx, launch_phase3(p3_lanes, gm.blocks, g->row_ptr, g->col, ws.label,
                                ws.aggsize, p3_io, agg_id, sc + kS_Err, s));
 
     HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, sc, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -531,6 +665,135 @@ int mis2_aggregate(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
     (void)it1;
     (void)it2;
     return collect_sweeps(ctx, launches, ws, s);
+}
+
+// Coarse graph of an aggregation into caller buffers; *nnz_out (host) gets
+// the coarse nnz.
+int quotient_impl(mis2_ctx *ctx, const mis2_graph *g, const int32_t *agg, int64_t n_agg,
+                  int64_t *crow, int32_t *ccol, int64_t *nnz_out, const Workspace &ws,
+                  hipStream_t s) {
+    QuotientWs q{ws.q.cnt, ws.q.moff, ws.q.members, ws.q.part};
+    HIP_TRY(ctx, quotient_graph(g->row_ptr, g->col, g->n, agg, n_agg, crow, ccol, q, s));
+    int64_t nnz = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&ctx->pinned[0], crow + n_agg, sizeof(int64_t),
+                                hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    memcpy(&nnz, ctx->pinned, sizeof nnz);
+    if (nnz_out) *nnz_out = nnz;
+    return MIS2_OK;
+}
+
+size_t coarsen_bytes(int64_t n, int64_t nnz) {
+    const size_t un = (size_t)n, unz = (size_t)nnz;
+    return workspace_bytes(n, MIS2_OP_COARSEN) + 2 * (align_up(8 * (un + 1)) + align_up(4 * unz));
+}
+
+}  // namespace
+
+extern "C" {
+
+int mis2_aggregate(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *agg_id,
+                   int64_t *n_agg, uint8_t *roots, void *stream) {
+    int rc = check_graph_args(ctx, g);
+    if (rc) return rc;
+    if (g->n > 0 && !agg_id) return fail(ctx, MIS2_EINVAL, "agg_id is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    ctx->trace[0].clear();
+    ctx->trace[1].clear();
+    ctx->sweeps.clear();
+    if (g->n == 0) {
+        if (n_agg) *n_agg = 0;
+        return MIS2_OK;
+    }
+    Workspace ws;
+    if ((rc = get_workspace(ctx, g, MIS2_OP_AGGREGATE, &ws))) return rc;
+    if ((rc = maybe_validate(ctx, g, ws, s))) return rc;
+    return aggregate_impl(ctx, g, seed, agg_id, n_agg, roots, ws, s);
+}
+
+int mis2_quotient(mis2_ctx *ctx, const mis2_graph *g, const int32_t *agg_id, int64_t n_agg,
+                  int64_t *coarse_row_ptr, int32_t *coarse_col, int64_t *coarse_nnz,
+                  void *stream) {
+    int rc = check_graph_args(ctx, g);
+    if (rc) return rc;
+    if (n_agg < 0 || n_agg > g->n) return fail(ctx, MIS2_EINVAL, "n_agg out of range");
+    if (!coarse_row_ptr || (g->n > 0 && !agg_id) || (g->nnz > 0 && !coarse_col))
+        return fail(ctx, MIS2_EINVAL, "null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    Workspace ws;
+    if ((rc = get_workspace(ctx, g, MIS2_OP_COARSEN, &ws))) return rc;
+    if ((rc = maybe_validate(ctx, g, ws, s))) return rc;
+    return quotient_impl(ctx, g, agg_id, n_agg, coarse_row_ptr, coarse_col, coarse_nnz, ws, s);
+}
+
+int mis2_coarsen_workspace_bytes(int64_t n, int64_t nnz, size_t *bytes) {
+    if (!bytes || n < 0 || nnz < 0) return MIS2_EINVAL;
+    *bytes = coarsen_bytes(n, nnz);
+    return MIS2_OK;
+}
+
+int mis2_coarsen(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int64_t stop_below,
+                 int32_t max_levels, int32_t *agg_out, int64_t agg_cap, int64_t *level_n,
+                 int64_t *level_nnz, int64_t *level_nagg, int32_t *n_levels, void *stream) {
+    int rc = check_graph_args(ctx, g);
+    if (rc) return rc;
+    if (max_levels < 0 || agg_cap < 0 || !n_levels ||
+        (max_levels > 0 && (!level_n || !level_nnz || !level_nagg)))
+        return fail(ctx, MIS2_EINVAL, "bad coarsening arguments");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    *n_levels = 0;
+    const size_t need = coarsen_bytes(g->n, g->nnz);
+    if (!ctx->ws || ctx->ws_bytes < need)
+        return fail(ctx, MIS2_ENOSPACE, "coarsening workspace of %zu bytes needed, %zu set", need,
+                    ctx->ws ? ctx->ws_bytes : (size_t)0);
+    const size_t head = workspace_bytes(g->n, MIS2_OP_COARSEN);
+    char *tail = (char *)ctx->ws + head;
+    int64_t *crow[2];
+    int32_t *ccol[2];
+    for (int i = 0; i < 2; i++) {
+        crow[i] = (int64_t *)tail;
+        tail += align_up(8 * ((size_t)g->n + 1));
+        ccol[i] = (int32_t *)tail;
+        tail += align_up(4 * (size_t)g->nnz);
+    }
+    mis2_graph cur = *g;
+    {
+        Workspace ws;
+        if (!carve(ctx->ws, head, g->n, MIS2_OP_COARSEN, &ws))
+            return fail(ctx, MIS2_ENOSPACE, "workspace carve failed");
+        if ((rc = maybe_validate(ctx, g, ws, s))) return rc;
+    }
+    int64_t off = 0;
+    int32_t lv = 0;
+    while (lv < max_levels && cur.n >= stop_below && cur.n > 0) {
+        if (off + cur.n > agg_cap)
+            return fail(ctx, MIS2_ENOSPACE, "agg_cap %lld too small for level %d",
+                        (long long)agg_cap, lv);
+        Workspace ws;
+        if (!carve(ctx->ws, head, cur.n, MIS2_OP_COARSEN, &ws))
+            return fail(ctx, MIS2_ENOSPACE, "workspace carve failed");
+        int64_t na = 0;
+        if ((rc = aggregate_impl(ctx, &cur, seed, agg_out + off, &na, nullptr, ws, s))) return rc;
+        level_n[lv] = cur.n;
+        level_nnz[lv] = cur.nnz;
+        level_nagg[lv] = na;
+        lv++;
+        *n_levels = lv;
+        if (na == cur.n) break;  // no progress
+        int64_t cnnz = 0;
+        if ((rc = quotient_impl(ctx, &cur, agg_out + off, na, crow[lv & 1], ccol[lv & 1], &cnnz, ws,
+                                s)))
+            return rc;
+        off += cur.n;
+        cur.n = na;
+        cur.nnz = cnnz;
+        cur.row_ptr = crow[lv & 1];
+        cur.col = ccol[lv & 1];
+    }
+    return MIS2_OK;
 }
 
 }  // extern "C"

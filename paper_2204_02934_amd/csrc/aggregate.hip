@@ -26,9 +26,42 @@ __device__ __forceinline__ int64_t wave_id() {
     return lb * (kBlock / 64) + (threadIdx.x >> 6);
 }
 
+constexpr int kCoopLoads = 8;      // loads per lane per cooperative step
+constexpr int64_t kHeavyRoot = 256;  // roots longer than this are pushed by the whole wavefront
+
+// Labels the neighbours in [s, e) of a root with id (all of them, or only
+// those still at -1), by the whole wavefront; returns the number labelled.
+__device__ __forceinline__ int coop_label(const int32_t *__restrict__ col,
+                                          int32_t *__restrict__ label, int64_t s, int64_t e,
+                                          int32_t id, int only_unlabelled) {
+    const int lane = (int)(threadIdx.x & 63u);
+    int took = 0;
+    for (int64_t b = s; b < e; b += 64 * kCoopLoads) {
+        int32_t x[kCoopLoads];
+#pragma unroll
+        for (int k = 0; k < kCoopLoads; k++) {
+            const int64_t j = b + (int64_t)k * 64 + lane;
+            x[k] = col[j < e ? j : s];
+        }
+        int32_t old[kCoopLoads];
+#pragma unroll
+        for (int k = 0; k < kCoopLoads; k++) old[k] = only_unlabelled ? label[x[k]] : -1;
+#pragma unroll
+        for (int k = 0; k < kCoopLoads; k++) {
+            if (b + (int64_t)k * 64 + lane < e && old[k] == -1) {
+                label[x[k]] = id;
+                took++;
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) took += __shfl_xor(took, off, 64);
+    return took;
+}
+
 // roots[0..*d_count) get ids base + k; their neighbours (all of them, or only
 // those still at -1 when only_unlabelled) get the same id, and aggsize[id]
-// becomes 1 + the number of neighbours labelled.
+// becomes 1 + the number of neighbours labelled.  Groups of kLabelLanes
+// lanes push ordinary roots; long rows are pushed by the whole wavefront.
 __global__ __launch_bounds__(kBlock) void k_label_roots(const int64_t *__restrict__ row_ptr,
                                                         const int32_t *__restrict__ col,
                                                         const int32_t *__restrict__ roots,
@@ -42,32 +75,45 @@ __global__ __launch_bounds__(kBlock) void k_label_roots(const int64_t *__restric
     constexpr int L = kLabelLanes, G = kBlock / L;
     const int64_t count = *d_count;
     const int32_t base = d_base ? (int32_t)*d_base : 0;
+    const int lane = (int)(threadIdx.x & 63u);
     const int sub = (int)(threadIdx.x & (L - 1));
-    // the loop bound is the same for the whole wavefront, so the group
-    // shuffles below always run with all lanes active
+    // the loop bound is the same for the whole wavefront, so the shuffles
+    // below always run with all lanes active
     const int64_t step = (int64_t)gridDim.x * G;
     const int64_t k0 = (int64_t)blockIdx.x * G + (threadIdx.x & ~63u) / L;
     for (int64_t kw = k0; kw < count; kw += step) {
-        const int64_t k = kw + (threadIdx.x & 63u) / L;
+        const int64_t k = kw + lane / L;
+        const bool ok = k < count;
+        const int32_t r = roots[ok ? k : count - 1];
+        const int32_t id = base + (int32_t)k;
+        int64_t s = row_ptr[r], e = row_ptr[r + 1];
+        if (!ok) e = s;
         int took = 0;
-        int32_t r = 0, id = 0;
-        if (k < count) {
-            r = roots[k];
-            id = base + (int32_t)k;
-            const int64_t s = row_ptr[r], e = row_ptr[r + 1];
-            for (int64_t j = s + sub; j < e; j += L) {
-                const int32_t w = col[j];
-                if (!only_unlabelled || label[w] == -1) {
-                    label[w] = id;
-                    took++;
-                }
+        int heavy_took = 0;
+        uint64_t heavy = __ballot(sub == 0 && e - s > kHeavyRoot);
+        while (heavy) {
+            const int src = __ffsll((unsigned long long)heavy) - 1;
+            heavy &= heavy - 1;
+            const int64_t hs = __shfl(s, src, 64), he = __shfl(e, src, 64);
+            const int32_t hid = __shfl(id, src, 64);
+            const int t = coop_label(col, label, hs, he, hid, only_unlabelled);
+            if ((lane & ~(L - 1)) == (src & ~(L - 1))) {
+                heavy_took = t;
+                e = s;  // its group skips the row below
+            }
+        }
+        for (int64_t j = s + sub; j < e; j += L) {
+            const int32_t w = col[j];
+            if (!only_unlabelled || label[w] == -1) {
+                label[w] = id;
+                took++;
             }
         }
 #pragma unroll
         for (int off = L / 2; off > 0; off >>= 1) took += __shfl_xor(took, off, L);
-        if (k < count && sub == 0) {
+        if (ok && sub == 0) {
             label[r] = id;
-            aggsize[id] = 1 + took;
+            aggsize[id] = 1 + took + heavy_took;
             if (root_mark) root_mark[r] = mark;
         }
     }
@@ -97,7 +143,20 @@ __global__ __launch_bounds__(kBlock) void k_accept_phase2(int64_t n,
             const int64_t u = base + t;
             const int64_t s = row_ptr[u], e = row_ptr[u + 1];
             int cnt = 0;
-            for (int64_t j = s + lane; j < e; j += 64) cnt += label[col[j]] == -1;
+            for (int64_t b = s; b < e; b += 64 * kCoopLoads) {
+                int32_t x[kCoopLoads];
+#pragma unroll
+                for (int k = 0; k < kCoopLoads; k++) {
+                    const int64_t j = b + (int64_t)k * 64 + lane;
+                    x[k] = col[j < e ? j : s];
+                }
+                int32_t lb[kCoopLoads];
+#pragma unroll
+                for (int k = 0; k < kCoopLoads; k++) lb[k] = label[x[k]];
+#pragma unroll
+                for (int k = 0; k < kCoopLoads; k++)
+                    cnt += (b + (int64_t)k * 64 + lane < e) & (lb[k] == -1);
+            }
             for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
             if (lane == t) f = cnt >= 2;
         }

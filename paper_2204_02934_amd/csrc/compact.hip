@@ -25,6 +25,10 @@ struct PredU8Nz {
     __device__ bool operator()(int64_t i) const { return a[i] != 0; }
 };
 
+__global__ void k_fill_first_i64(int64_t *out) {
+    if (threadIdx.x == 0) out[0] = 0;
+}
+
 __device__ __forceinline__ uint64_t lanes_below(int lane) {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
@@ -136,8 +140,103 @@ hipError_t compact_u32_eq(const uint32_t *a, uint32_t value, int64_t n, int32_t 
     return compact(PredU32Eq{a, value}, n, out, d_count, blocksum, s);
 }
 
+// ---------------------------------------------------------------------------
+// Exclusive prefix sum of u32 counts into int64 offsets: out[i] = sum of
+// in[0..i), out[n] = total.  Tile sums, a one-workgroup scan of the tile sums
+// (64-bit), then a per-tile scan that writes the offsets.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_tile_sum_u32(const uint32_t *__restrict__ in, int64_t n,
+                                                         unsigned long long *__restrict__ part) {
+    __shared__ unsigned long long ws[kWaves];
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    unsigned long long c = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; j++) {
+        const int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
+        if (i < n) c += in[i];
+    }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63u) == 0) ws[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kWaves; w++) t += ws[w];
+        part[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_parts_u64(unsigned long long *__restrict__ part,
+                                                           int64_t nb) {
+    __shared__ unsigned long long wsum[kWaves];
+    __shared__ unsigned long long carry_s;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    const int lane = (int)(threadIdx.x & 63u), wave = (int)(threadIdx.x >> 6);
+    for (int64_t c0 = 0; c0 < nb; c0 += kBlock) {
+        const int64_t i = c0 + threadIdx.x;
+        const unsigned long long x = i < nb ? part[i] : 0ull;
+        unsigned long long incl = x;
+        for (int off = 1; off < 64; off <<= 1) {
+            const unsigned long long y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        unsigned long long before = carry_s;
+        for (int w = 0; w < wave; w++) before += wsum[w];
+        if (i < nb) part[i] = before + incl - x;
+        __syncthreads();
+        if (threadIdx.x == kBlock - 1) carry_s = before + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[nb] = carry_s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_tile_scan_u32(const uint32_t *__restrict__ in, int64_t n,
+                                                          const unsigned long long *__restrict__ part,
+                                                          int64_t *__restrict__ out, int64_t nb) {
+    __shared__ unsigned long long wsum[kWaves];
+    const int lane = (int)(threadIdx.x & 63u), wave = (int)(threadIdx.x >> 6);
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    unsigned long long run = part[blockIdx.x];
+    for (int j = 0; j < kItems; j++) {
+        const int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
+        const unsigned long long x = i < n ? in[i] : 0ull;
+        unsigned long long incl = x;
+        for (int off = 1; off < 64; off <<= 1) {
+            const unsigned long long y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        unsigned long long before = run;
+        for (int w = 0; w < wave; w++) before += wsum[w];
+        if (i < n) out[i] = (int64_t)(before + incl - x);
+        unsigned long long tot = 0;
+        for (int w = 0; w < kWaves; w++) tot += wsum[w];
+        __syncthreads();
+        run += tot;
+    }
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = (int64_t)part[nb];
+}
+
 hipError_t launch_scan_tiles(uint32_t *blocksum, int64_t nb, uint32_t *d_total, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kBlock), 0, s, blocksum, nb, d_total);
+    return hipGetLastError();
+}
+
+int64_t scan_parts(int64_t n) { return compact_blocks(n) + 1; }
+
+hipError_t exclusive_scan_u32_i64(const uint32_t *in, int64_t n, int64_t *out,
+                                  unsigned long long *part, hipStream_t s) {
+    const int64_t nb = compact_blocks(n);
+    if (nb == 0) {
+        hipLaunchKernelGGL(k_fill_first_i64, dim3(1), dim3(64), 0, s, out);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_tile_sum_u32, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, part);
+    hipLaunchKernelGGL(k_scan_parts_u64, dim3(1), dim3(kBlock), 0, s, part, nb);
+    hipLaunchKernelGGL(k_tile_scan_u32, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, part, out, nb);
     return hipGetLastError();
 }
 

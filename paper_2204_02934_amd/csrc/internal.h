@@ -29,6 +29,9 @@ constexpr int kTraceSplit = 8;    // per-round size counters, one per XCD
 // non-zero iff worklist1 is non-empty there.
 constexpr int kRoundStride = 32;
 constexpr int kRtAlive = 16;
+// Persistent kernel only: device wall-clock stamps (two words each) taken by
+// workgroup 0 at the start of round r and after its two grid barriers.
+constexpr int kRtStamp0 = 18, kRtStamp1 = 20, kRtStamp2 = 22;
 
 // Section V-A: f = xorshift64* (Vigna's parameters 12, 25, 27 and multiplier
 // 2685821657736338717, arithmetic mod 2^64); h(i, v) = f(f(i) ^ f(v)).
@@ -39,18 +42,48 @@ __host__ __device__ __forceinline__ uint64_t xs64star(uint64_t x) {
     return x * 0x2545F4914F6CDD1Dull;
 }
 
+// Graphs of a batch: graph g owns the union's vertex ids [voff[g], voff[g+1]);
+// its tuples use graph-local ids and the graph's own id width gb[g], so a
+// batch computes exactly what each graph computes alone (there are no edges
+// between graphs).  voff == nullptr means a single graph.
+struct BatchInfo {
+    const int64_t *voff = nullptr;  // device [G + 1]
+    const uint32_t *gb = nullptr;   // device [G]
+    int32_t G = 0;
+    int32_t steps = 0;              // binary-search steps, ceil(log2(G + 1))
+};
+
 // What a kernel needs to build the packed tuple of one round.
 struct TupleParams {
     uint64_t f_iter;  // f((seed << 32) ^ iter): the per-round half of h
     uint64_t pmask;   // 2^(32-b) - 1, or 0 when b = 32
     uint32_t b;       // id bits, the smallest b with 2^b >= n + 2
+    BatchInfo batch;
 };
+
+// Graph of union vertex v (fixed trip count, the same in every lane).
+__device__ __forceinline__ int32_t graph_of(const BatchInfo &bt, int64_t v) {
+    int32_t lo = 0, hi = bt.G;
+    for (int k = 0; k < bt.steps; k++) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (bt.voff[mid] <= v) lo = mid; else hi = mid;
+    }
+    return lo;
+}
 
 // Section V-C: (priority << b) | (v + 1); the priority keeps the low 32 - b
 // bits of h.
 __device__ __forceinline__ uint32_t make_tuple(const TupleParams &p, uint32_t v) {
-    const uint64_t h = xs64star(p.f_iter ^ xs64star((uint64_t)v));
-    return (uint32_t)(((h & p.pmask) << p.b) | (uint64_t)(v + 1u));
+    uint64_t l = v, pmask = p.pmask;
+    uint32_t b = p.b;
+    if (p.batch.voff) {
+        const int32_t g = graph_of(p.batch, v);
+        l = (uint64_t)((int64_t)v - p.batch.voff[g]);
+        b = p.batch.gb[g];
+        pmask = b >= 32 ? 0ull : ((1ull << (32 - b)) - 1ull);
+    }
+    const uint64_t h = xs64star(p.f_iter ^ xs64star(l));
+    return (uint32_t)(((h & pmask) << b) | (l + 1u));
 }
 
 int id_bits(int64_t n);
@@ -79,11 +112,19 @@ struct Workspace {
     uint32_t *scalars = nullptr;  // [kScalars]
     unsigned long long *degs = nullptr;  // [2][kTraceCap][2] row-length sums per sweep
     uint32_t *blocksum = nullptr; // [compact_blocks(n) + 1]
+    uint32_t *bar = nullptr;      // [kBarWords] persistent-kernel barrier state
     // aggregation only
     int32_t *label = nullptr;     // [n] aggregate labels, -1 = none
     int32_t *list = nullptr;      // [n] ordered vertex lists
     uint8_t *flag = nullptr;      // [n]
     int32_t *aggsize = nullptr;   // [n]
+    // coarsening only
+    struct {
+        uint32_t *cnt = nullptr;
+        int64_t *moff = nullptr;
+        int32_t *members = nullptr;
+        unsigned long long *part = nullptr;
+    } q;
 };
 
 size_t workspace_bytes(int64_t n, int op);
@@ -91,8 +132,9 @@ bool carve(void *base, size_t bytes, int64_t n, int op, Workspace *ws);
 
 // Launch-plan knobs; never change results.
 struct Plan {
-    int lanes = 0;   // lanes per CSR row (power of two <= 64); 0 = automatic
-    int blocks = 0;  // workgroups per sweep (<= kMaxBlocks); 0 = automatic
+    int lanes = 0;       // lanes per CSR row (power of two <= 64); 0 = automatic
+    int blocks = 0;      // workgroups per sweep (<= kMaxBlocks); 0 = automatic
+    int persistent = 1;  // 1: one cooperative launch per MIS-2 run; 0: two launches per round
 };
 
 // One sweep's worklists.  Wavefront w owns slots [w*seg, w*seg + cnt[w]) of
@@ -116,7 +158,31 @@ struct SegIO {
     int64_t S;
 };
 
+// Arguments of the persistent round kernel.  bar: [kMaxBlocks] per-workgroup
+// epoch flags, then the published epoch at [kMaxBlocks], the abort word at
+// [kMaxBlocks + 16] and the executed round count at [kMaxBlocks + 32]; all
+// zero before the launch.
+constexpr int kBarWords = kMaxBlocks + 64;
+struct RoundsArgs {
+    BatchInfo batch;
+    int32_t *wl1[2];
+    int32_t *wl2[2];
+    uint32_t *cnt1[2];
+    uint32_t *cnt2[2];
+    uint32_t *rt;
+    unsigned long long *degs;  // [kTraceCap][2] or null
+    uint32_t *bar;
+    int64_t n, seg, S;
+    uint64_t seed, pmask;
+    uint32_t b;
+    int masked;
+    int max_rounds;
+};
+
 // mis2_kernels.hip
+int rounds_max_blocks(int lanes, int num_cus);
+hipError_t launch_rounds(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
+                         uint32_t *T, uint32_t *M, const RoundsArgs &a, hipStream_t s);
 hipError_t launch_init_tuples(const TupleParams &tp, int64_t n, uint32_t *T, hipStream_t s);
 hipError_t launch_init_masked(int blocks, const TupleParams &tp, int64_t n, const int32_t *label,
                               uint32_t *T, uint32_t *M, const SegIO &io, hipStream_t s);
@@ -143,8 +209,24 @@ hipError_t compact_u32_eq(const uint32_t *a, uint32_t value, int64_t n, int32_t 
                           uint32_t *d_count, uint32_t *blocksum, hipStream_t s);
 hipError_t compact_u8_nz(const uint8_t *a, int64_t n, int32_t *out, uint32_t *d_count,
                          uint32_t *blocksum, hipStream_t s);
+// Exclusive prefix sum of n u32 values into int64 out[0..n]; part needs
+// scan_parts(n) entries.
+int64_t scan_parts(int64_t n);
+hipError_t exclusive_scan_u32_i64(const uint32_t *in, int64_t n, int64_t *out,
+                                  unsigned long long *part, hipStream_t s);
 // Exclusive scan of blocksum[0..nb) in place; total -> blocksum[nb], *d_total.
 hipError_t launch_scan_tiles(uint32_t *blocksum, int64_t nb, uint32_t *d_total, hipStream_t s);
+
+// quotient.hip: coarse graph of an aggregation.
+struct QuotientWs {
+    uint32_t *cnt;              // [n_agg] member / row counts
+    int64_t *moff;              // [n_agg + 1] member offsets
+    int32_t *members;           // [n]
+    unsigned long long *part;   // [scan_parts(n)]
+};
+hipError_t quotient_graph(const int64_t *row_ptr, const int32_t *col, int64_t n, const int32_t *agg,
+                          int64_t n_agg, int64_t *crow, int32_t *ccol, const QuotientWs &q,
+                          hipStream_t s);
 
 // aggregate.hip
 hipError_t launch_label_roots(int64_t n, const int64_t *row_ptr, const int32_t *col,
@@ -177,6 +259,8 @@ struct mis2_ctx {
     mis2::Plan plan;
     std::vector<int64_t> trace[2];  // per-round |wl1|, |wl2| of the last run(s)
     std::vector<mis2_sweep_record> sweeps;  // launches of the last call
+    std::vector<float> stamp_ms[2];         // persistent kernel: per-round sweep times
+    double wall_khz = 100000.0;             // device wall-clock rate
     std::vector<hipEvent_t> events;         // profiling event pool
     size_t events_used = 0;
 };

@@ -132,6 +132,71 @@ __device__ __forceinline__ void load_rows(const SegIO &io, const Seg &sg, int64_
     }
 }
 
+// Rows longer than this many column indices are streamed by the whole
+// wavefront (8 loads per lane in flight) instead of by their L-lane group,
+// so one high-degree row does not hold the wavefront for len / L steps.
+template <int L>
+__device__ __forceinline__ int64_t heavy_threshold() {
+    return L >= 64 ? 1024 : (int64_t)32 * L;
+}
+constexpr int kCoopLoads = 8;  // loads per lane per cooperative step
+
+// Minimum of T over the column indices [s, e), by the whole wavefront.
+__device__ __forceinline__ uint32_t coop_min_T(const int32_t *__restrict__ col,
+                                               const uint32_t *__restrict__ T, int64_t s,
+                                               int64_t e) {
+    const int lane = (int)(threadIdx.x & 63u);
+    uint32_t m = kOut;
+    for (int64_t b = s; b < e; b += 64 * kCoopLoads) {
+        int32_t x[kCoopLoads];
+#pragma unroll
+        for (int k = 0; k < kCoopLoads; k++) {
+            const int64_t j = b + (int64_t)k * 64 + lane;
+            x[k] = col[j < e ? j : s];
+        }
+        uint32_t t[kCoopLoads];
+#pragma unroll
+        for (int k = 0; k < kCoopLoads; k++) t[k] = T[x[k]];
+#pragma unroll
+        for (int k = 0; k < kCoopLoads; k++)
+            if (b + (int64_t)k * 64 + lane < e) m = min(m, t[k]);
+    }
+    for (int off = 32; off > 0; off >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, off, 64));
+    return m;
+}
+
+// Any M_w == OUT and all M_w in {t0, absent} over [s, e), by the whole wavefront.
+__device__ __forceinline__ void coop_decide(const int32_t *__restrict__ col,
+                                            const uint32_t *__restrict__ M, int64_t s, int64_t e,
+                                            uint32_t t0, int &any_out, int &all_eq) {
+    const int lane = (int)(threadIdx.x & 63u);
+    int ao = 0, ae = 1;
+    for (int64_t b = s; b < e; b += 64 * kCoopLoads) {
+        int32_t x[kCoopLoads];
+#pragma unroll
+        for (int k = 0; k < kCoopLoads; k++) {
+            const int64_t j = b + (int64_t)k * 64 + lane;
+            x[k] = col[j < e ? j : s];
+        }
+        uint32_t mw[kCoopLoads];
+#pragma unroll
+        for (int k = 0; k < kCoopLoads; k++) mw[k] = M[x[k]];
+#pragma unroll
+        for (int k = 0; k < kCoopLoads; k++) {
+            if (b + (int64_t)k * 64 + lane < e) {
+                ao |= (mw[k] == kOut);
+                ae &= (mw[k] == t0) | (mw[k] == kAbsent);
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        ao |= __shfl_xor(ao, off, 64);
+        ae &= __shfl_xor(ae, off, 64);
+    }
+    any_out = ao;
+    all_eq = ae;
+}
+
 // Refresh Column over the wavefront's segment: U rows per lane group per
 // step, so that U independent row streams are in flight.  Loads are issued
 // unconditionally from clamped, always valid addresses and their results
@@ -165,6 +230,21 @@ __device__ __forceinline__ uint32_t sweep_column(const int64_t *__restrict__ row
             if (!ok[u]) e[u] = s[u];
             if (sub != 0) m[u] = kOut;
             if (sub == 0) dsum += (unsigned long long)(e[u] - s[u]);
+        }
+        // high-degree rows: the whole wavefront streams each one in turn
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            uint64_t heavy = __ballot(sub == 0 && e[u] - s[u] > heavy_threshold<L>());
+            while (heavy) {
+                const int src = __ffsll((unsigned long long)heavy) - 1;
+                heavy &= heavy - 1;
+                const int64_t hs = __shfl(s[u], src, 64), he = __shfl(e[u], src, 64);
+                const uint32_t hm = coop_min_T(col, T, hs, he);
+                if ((lane & ~(L - 1)) == (src & ~(L - 1))) {
+                    m[u] = (sub == 0) ? min(m[u], hm) : kOut;
+                    e[u] = s[u];  // its group skips the row below
+                }
+            }
         }
         const int64_t steps = wave_max_len<U>(s, e);
         for (int64_t c0 = 0; c0 < steps; c0 += L) {
@@ -232,6 +312,26 @@ __device__ __forceinline__ uint32_t sweep_decide(const int64_t *__restrict__ row
             all_eq[u] = (sub != 0) | (mv[u] == t0[u]);
             if (sub == 0) dsum += (unsigned long long)(e[u] - s[u]);
         }
+        // high-degree rows: the whole wavefront streams each one in turn
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            uint64_t heavy = __ballot(sub == 0 && e[u] - s[u] > heavy_threshold<L>());
+            while (heavy) {
+                const int src = __ffsll((unsigned long long)heavy) - 1;
+                heavy &= heavy - 1;
+                const int64_t hs = __shfl(s[u], src, 64), he = __shfl(e[u], src, 64);
+                const uint32_t ht0 = __shfl(t0[u], src, 64);
+                int hao, hae;
+                coop_decide(col, M, hs, he, ht0, hao, hae);
+                if ((lane & ~(L - 1)) == (src & ~(L - 1))) {
+                    if (sub == 0) {
+                        any_out[u] |= hao;
+                        all_eq[u] &= hae;
+                    }
+                    e[u] = s[u];  // its group skips the row below
+                }
+            }
+        }
         const int64_t steps = wave_max_len<U>(s, e);
         for (int64_t c0 = 0; c0 < steps; c0 += L) {
             const int64_t c = c0 + sub;
@@ -276,6 +376,284 @@ __device__ __forceinline__ uint32_t sweep_decide(const int64_t *__restrict__ row
     return kept;
 }
 
+// ---------------------------------------------------------------------------
+// Flat ("merge path") sweeps.  A wavefront takes its rows 64 at a time, one
+// per lane, lays their column indices out as one flat range (offsets and
+// starts in LDS) and lets every lane stream kFlatEP consecutive indices of
+// that range per step.  All loads of a step are independent, so a batch of
+// 64 rows needs about 2 + 2 * ceil(edges / (64 * kFlatEP)) dependent memory
+// steps instead of one chain per row.  Each lane folds its edges into a
+// partial result per row it touches and merges it into the row's LDS slot
+// with an order-free atomic (min, or, and).  High-degree rows are handled
+// first by the whole wavefront (coop_min_T / coop_decide) and leave the
+// flat range.
+// ---------------------------------------------------------------------------
+constexpr int kFlatEP = 8;     // consecutive edges per lane per step
+constexpr int kFlatRows = 64;  // rows per batch (one per lane)
+constexpr int64_t kFlatHeavy = 4096;  // rows longer than this take the cooperative path
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Per-wavefront LDS of a flat batch.
+struct FlatLds {
+    uint32_t off[kFlatRows + 1];  // flat offsets of the compacted non-empty rows
+    int64_t start[kFlatRows];     // their first column index
+    uint32_t t0[kFlatRows];       // their T_v (Decide Set)
+    uint32_t acc[kFlatRows];      // min (Refresh Column) or any-OUT (Decide Set)
+    uint32_t acc2[kFlatRows];     // all-equal (Decide Set)
+};
+
+// Loads the batch's rows (one per lane), compacts the non-empty light rows
+// into the LDS table and returns this lane's table index (-1 if none).
+// total: flat length of the batch.
+__device__ __forceinline__ int flat_table(FlatLds &sh, int64_t s, int64_t len, bool light,
+                                          uint32_t &total) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const bool in = light && len > 0;
+    const uint64_t mask = __ballot(in);
+    const int idx = (int)__popcll(mask & lanes_below(lane));
+    // exclusive prefix of the lengths over the compacted rows
+    uint32_t l32 = in ? (uint32_t)len : 0u;
+    uint32_t incl = l32;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    total = (uint32_t)__shfl((int)incl, 63, 64);
+    if (in) {
+        sh.off[idx] = incl - l32;
+        sh.start[idx] = s;
+    }
+    if (lane == 0) sh.off[__popcll(mask)] = total;
+    return in ? idx : -1;
+}
+
+// Row of flat edge f: the last table row whose offset is <= f (7 fixed steps).
+__device__ __forceinline__ int flat_row(const FlatLds &sh, int nrows, uint32_t f) {
+    int lo = 0, hi = nrows;
+    for (int k = 0; k < 7; k++) {
+        const int mid = (lo + hi) >> 1;
+        if (mid > lo && sh.off[mid] <= f) lo = mid; else if (mid > lo) hi = mid;
+    }
+    return lo;
+}
+
+template <int U>
+__device__ __forceinline__ uint32_t flat_column(const int64_t *__restrict__ row_ptr,
+                                                const int32_t *__restrict__ col,
+                                                const uint32_t *__restrict__ T,
+                                                uint32_t *__restrict__ M, const SegIO &io,
+                                                const Seg &sg, FlatLds &sh) {
+    const int lane = (int)(threadIdx.x & 63u);
+    uint32_t kept = 0;
+    unsigned long long dsum = 0;
+    for (int64_t i0 = 0; i0 < sg.count; i0 += kFlatRows) {
+        const int64_t i = i0 + lane;
+        const bool ok = i < sg.count;
+        const int64_t ic = ok ? i : sg.count - 1;
+        const int32_t v = io.wl_in ? io.wl_in[sg.base + ic] : (int32_t)(sg.base + ic);
+        const int64_t s = row_ptr[v], e = row_ptr[v + 1];
+        uint32_t m = T[v];
+        const int64_t len = ok ? e - s : 0;
+        dsum += (unsigned long long)len;
+        // high-degree rows: the whole wavefront, one at a time
+        uint64_t heavy = __ballot(len > kFlatHeavy);
+        while (heavy) {
+            const int src = __ffsll((unsigned long long)heavy) - 1;
+            heavy &= heavy - 1;
+            const uint32_t hm = coop_min_T(col, T, __shfl(s, src, 64), __shfl(e, src, 64));
+            if (lane == src) m = min(m, hm);
+        }
+        uint32_t total;
+        const int me = flat_table(sh, s, len, len <= kFlatHeavy, total);
+        const int nrows = (int)__popcll(__ballot(me >= 0));
+        if (me >= 0) sh.acc[me] = kOut;
+        wave_lds_sync();
+        for (uint32_t c0 = 0; c0 < total; c0 += 64 * kFlatEP) {
+            const uint32_t f0 = c0 + (uint32_t)lane * kFlatEP;
+            int r = f0 < total ? flat_row(sh, nrows, f0) : 0;
+            int32_t x[kFlatEP];
+            int rr[kFlatEP];
+#pragma unroll
+            for (int j = 0; j < kFlatEP; j++) {
+                const uint32_t f = f0 + j;
+                if (f < total && r + 1 < nrows && sh.off[r + 1] <= f) r++;
+                rr[j] = r;
+                x[j] = col[f < total ? sh.start[r] + (int64_t)(f - sh.off[r]) : 0];
+            }
+            uint32_t t[kFlatEP];
+#pragma unroll
+            for (int j = 0; j < kFlatEP; j++) t[j] = T[x[j]];
+            uint32_t part = kOut;
+            int pr = rr[0];
+#pragma unroll
+            for (int j = 0; j < kFlatEP; j++) {
+                if (f0 + j < total) {
+                    if (rr[j] != pr) {
+                        atomicMin(&sh.acc[pr], part);
+                        part = kOut;
+                        pr = rr[j];
+                    }
+                    part = min(part, t[j]);
+                }
+            }
+            if (f0 < total) atomicMin(&sh.acc[pr], part);
+        }
+        wave_lds_sync();
+        if (me >= 0) m = min(m, sh.acc[me]);
+        bool keep = false;
+        if (ok) {
+            if (m == kIn) m = kOut;
+            M[v] = m;
+            keep = (m != kOut);
+        }
+        seg_append(io, sg, keep, v, kept);
+        wave_lds_sync();
+    }
+    if (io.deg_sum) wave_degsum(io.deg_sum, dsum);
+    return kept;
+}
+
+template <int U>
+__device__ __forceinline__ uint32_t flat_decide(const int64_t *__restrict__ row_ptr,
+                                                const int32_t *__restrict__ col,
+                                                uint32_t *__restrict__ T,
+                                                const uint32_t *__restrict__ M,
+                                                const TupleParams &next, const SegIO &io,
+                                                const Seg &sg, FlatLds &sh) {
+    const int lane = (int)(threadIdx.x & 63u);
+    uint32_t kept = 0;
+    unsigned long long dsum = 0;
+    for (int64_t i0 = 0; i0 < sg.count; i0 += kFlatRows) {
+        const int64_t i = i0 + lane;
+        const bool ok = i < sg.count;
+        const int64_t ic = ok ? i : sg.count - 1;
+        const int32_t v = io.wl_in ? io.wl_in[sg.base + ic] : (int32_t)(sg.base + ic);
+        const int64_t s = row_ptr[v], e = row_ptr[v + 1];
+        const uint32_t t0 = T[v];
+        const uint32_t mv = M[v];
+        int any_out = mv == kOut;
+        int all_eq = mv == t0;
+        const int64_t len = ok ? e - s : 0;
+        dsum += (unsigned long long)len;
+        uint64_t heavy = __ballot(len > kFlatHeavy);
+        while (heavy) {
+            const int src = __ffsll((unsigned long long)heavy) - 1;
+            heavy &= heavy - 1;
+            int hao, hae;
+            coop_decide(col, M, __shfl(s, src, 64), __shfl(e, src, 64), __shfl(t0, src, 64), hao,
+                        hae);
+            if (lane == src) {
+                any_out |= hao;
+                all_eq &= hae;
+            }
+        }
+        uint32_t total;
+        const int me = flat_table(sh, s, len, len <= kFlatHeavy, total);
+        const int nrows = (int)__popcll(__ballot(me >= 0));
+        if (me >= 0) {
+            sh.t0[me] = t0;
+            sh.acc[me] = 0u;
+            sh.acc2[me] = 1u;
+        }
+        wave_lds_sync();
+        for (uint32_t c0 = 0; c0 < total; c0 += 64 * kFlatEP) {
+            const uint32_t f0 = c0 + (uint32_t)lane * kFlatEP;
+            int r = f0 < total ? flat_row(sh, nrows, f0) : 0;
+            int32_t x[kFlatEP];
+            int rr[kFlatEP];
+#pragma unroll
+            for (int j = 0; j < kFlatEP; j++) {
+                const uint32_t f = f0 + j;
+                if (f < total && r + 1 < nrows && sh.off[r + 1] <= f) r++;
+                rr[j] = r;
+                x[j] = col[f < total ? sh.start[r] + (int64_t)(f - sh.off[r]) : 0];
+            }
+            uint32_t mw[kFlatEP];
+#pragma unroll
+            for (int j = 0; j < kFlatEP; j++) mw[j] = M[x[j]];
+            int pr = rr[0];
+            uint32_t pt0 = sh.t0[pr];
+            uint32_t pao = 0u, pae = 1u;
+#pragma unroll
+            for (int j = 0; j < kFlatEP; j++) {
+                if (f0 + j < total) {
+                    if (rr[j] != pr) {
+                        if (pao) atomicOr(&sh.acc[pr], 1u);
+                        if (!pae) atomicAnd(&sh.acc2[pr], 0u);
+                        pao = 0u;
+                        pae = 1u;
+                        pr = rr[j];
+                        pt0 = sh.t0[pr];
+                    }
+                    pao |= (mw[j] == kOut);
+                    pae &= (mw[j] == pt0) | (mw[j] == kAbsent);
+                }
+            }
+            if (f0 < total) {
+                if (pao) atomicOr(&sh.acc[pr], 1u);
+                if (!pae) atomicAnd(&sh.acc2[pr], 0u);
+            }
+        }
+        wave_lds_sync();
+        if (me >= 0) {
+            any_out |= (int)sh.acc[me];
+            all_eq &= (int)sh.acc2[me];
+        }
+        bool keep = false;
+        if (ok) {
+            uint32_t nt;
+            if (any_out) {
+                nt = kOut;
+            } else if (all_eq) {
+                nt = kIn;
+            } else {
+                nt = make_tuple(next, (uint32_t)v);
+                keep = true;
+            }
+            T[v] = nt;
+        }
+        seg_append(io, sg, keep, v, kept);
+        wave_lds_sync();
+    }
+    if (io.deg_sum) wave_degsum(io.deg_sum, dsum);
+    return kept;
+}
+
+// lanes == 0 in the plan selects the flat sweeps.
+template <int L>
+__device__ __forceinline__ uint32_t any_column(const int64_t *__restrict__ row_ptr,
+                                               const int32_t *__restrict__ col,
+                                               const uint32_t *__restrict__ T,
+                                               uint32_t *__restrict__ M, const SegIO &io,
+                                               const Seg &sg) {
+    if constexpr (L == 0) {
+        __shared__ FlatLds sh[kBlock / 64];
+        return flat_column<kUnroll>(row_ptr, col, T, M, io, sg, sh[threadIdx.x >> 6]);
+    } else {
+        return sweep_column<L, kUnroll>(row_ptr, col, T, M, io, sg);
+    }
+}
+
+template <int L>
+__device__ __forceinline__ uint32_t any_decide(const int64_t *__restrict__ row_ptr,
+                                               const int32_t *__restrict__ col,
+                                               uint32_t *__restrict__ T,
+                                               const uint32_t *__restrict__ M,
+                                               const TupleParams &next, const SegIO &io,
+                                               const Seg &sg) {
+    if constexpr (L == 0) {
+        __shared__ FlatLds sh[kBlock / 64];
+        return flat_decide<kUnroll>(row_ptr, col, T, M, next, io, sg, sh[threadIdx.x >> 6]);
+    } else {
+        return sweep_decide<L, kUnroll>(row_ptr, col, T, M, next, io, sg);
+    }
+}
+
 template <int L>
 __global__ __launch_bounds__(kBlock) void k_refresh_column(const int64_t *__restrict__ row_ptr,
                                                            const int32_t *__restrict__ col,
@@ -285,7 +663,7 @@ __global__ __launch_bounds__(kBlock) void k_refresh_column(const int64_t *__rest
     if (blockIdx.x == 0 && threadIdx.x < kRoundStride && io.round_zero)
         io.round_zero[threadIdx.x] = 0u;
     const Seg sg = seg_of(io, w);
-    const uint32_t kept = sweep_column<L, kUnroll>(row_ptr, col, T, M, io, sg);
+    const uint32_t kept = any_column<L>(row_ptr, col, T, M, io, sg);
     seg_finish(io, w, kept);
 }
 
@@ -297,8 +675,132 @@ __global__ __launch_bounds__(kBlock) void k_decide(const int64_t *__restrict__ r
                                                    TupleParams next, SegIO io) {
     const int64_t w = wave_id();
     const Seg sg = seg_of(io, w);
-    const uint32_t kept = sweep_decide<L, kUnroll>(row_ptr, col, T, M, next, io, sg);
+    const uint32_t kept = any_decide<L>(row_ptr, col, T, M, next, io, sg);
     seg_finish(io, w, kept);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent form: one cooperative launch runs every round of Algorithm 1.
+// The grid synchronises twice per round (after Refresh Column and after
+// Decide Set) with an epoch barrier: each workgroup publishes its epoch in
+// its own flag word, workgroup 0 waits for all flags and publishes the epoch,
+// and everyone waits for that.  Writes are released and acquired at device
+// (agent) scope around the flags, so M and T written before a barrier are
+// seen after it.  Every wait is bounded by a wall-clock limit; a timeout sets
+// an abort word that makes every later wait return at once, so all
+// wavefronts always leave the kernel.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kBarrierTimeoutTicks = 2000000000ull;  // wall clock ticks (about 20 s at 100 MHz)
+
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Device wall clock (constant rate) into two round-table words.
+__device__ __forceinline__ void stamp(uint32_t *p) {
+    const uint64_t t = wall_clock64();
+    p[0] = (uint32_t)t;
+    p[1] = (uint32_t)(t >> 32);
+}
+
+// Returns false if the barrier timed out (or had timed out before).
+__device__ bool grid_barrier(uint32_t *flags, uint32_t *gen, uint32_t *abort_word,
+                             uint32_t epoch) {
+    __shared__ uint32_t ok_s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();  // release this workgroup's writes
+        st_agent(&flags[blockIdx.x], epoch);
+    }
+    if (blockIdx.x == 0) {
+        const uint64_t t0 = wall_clock64();
+        for (uint32_t b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
+            while (ld_agent(&flags[b]) < epoch) {
+                if (ld_agent(abort_word) || wall_clock64() - t0 > kBarrierTimeoutTicks) {
+                    st_agent(abort_word, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) st_agent(gen, epoch);
+    }
+    if (threadIdx.x == 0) {
+        const uint64_t t0 = wall_clock64();
+        while (ld_agent(gen) < epoch) {
+            if (ld_agent(abort_word) || wall_clock64() - t0 > kBarrierTimeoutTicks) {
+                st_agent(abort_word, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __threadfence();  // acquire everyone's writes
+        ok_s = ld_agent(abort_word) == 0u;
+    }
+    __syncthreads();
+    return ok_s != 0u;
+}
+
+template <int L>
+__global__ __launch_bounds__(kBlock) void k_rounds(const int64_t *__restrict__ row_ptr,
+                                                   const int32_t *__restrict__ col,
+                                                   uint32_t *__restrict__ T,
+                                                   uint32_t *__restrict__ M, RoundsArgs a) {
+    const int64_t w = wave_id();
+    uint32_t *flags = a.bar;
+    uint32_t *gen = a.bar + kMaxBlocks;
+    uint32_t *abort_word = a.bar + kMaxBlocks + 16;
+    uint32_t epoch = 0;
+    int r = 0;
+    for (;;) {
+        const int cur = r & 1, nxt = cur ^ 1;
+        const bool first = (r == 0);
+        uint32_t *row_next = a.rt + (size_t)(r + 1) * kRoundStride;
+        SegIO cio{first ? (a.masked ? a.wl1[0] : nullptr) : a.wl2[cur],
+                  first ? (a.masked ? a.cnt1[0] : nullptr) : a.cnt2[cur],
+                  a.wl2[nxt],
+                  a.cnt2[nxt],
+                  row_next + kTraceSplit,
+                  nullptr,
+                  row_next + kRoundStride,
+                  a.degs ? a.degs + 2 * r + 1 : nullptr,
+                  a.n,
+                  a.seg,
+                  a.S};
+        if (blockIdx.x == 0 && threadIdx.x < kRoundStride) cio.round_zero[threadIdx.x] = 0u;
+        uint32_t *row_cur = a.rt + (size_t)r * kRoundStride;
+        if (blockIdx.x == 0 && threadIdx.x == 0) stamp(row_cur + kRtStamp0);
+        Seg sg = seg_of(cio, w);
+        uint32_t kept = any_column<L>(row_ptr, col, T, M, cio, sg);
+        seg_finish(cio, w, kept);
+        if (!grid_barrier(flags, gen, abort_word, ++epoch)) break;
+        if (blockIdx.x == 0 && threadIdx.x == 0) stamp(row_cur + kRtStamp1);
+        SegIO dio{first ? (a.masked ? a.wl1[0] : nullptr) : a.wl1[cur],
+                  first ? (a.masked ? a.cnt1[0] : nullptr) : a.cnt1[cur],
+                  a.wl1[nxt],
+                  a.cnt1[nxt],
+                  row_next,
+                  row_next + kRtAlive,
+                  nullptr,
+                  a.degs ? a.degs + 2 * r : nullptr,
+                  a.n,
+                  a.seg,
+                  a.S};
+        const TupleParams next{xs64star((a.seed << 32) ^ (uint64_t)(r + 1)), a.pmask, a.b, a.batch};
+        sg = seg_of(dio, w);
+        kept = any_decide<L>(row_ptr, col, T, M, next, dio, sg);
+        seg_finish(dio, w, kept);
+        if (!grid_barrier(flags, gen, abort_word, ++epoch)) break;
+        if (blockIdx.x == 0 && threadIdx.x == 0) stamp(row_cur + kRtStamp2);
+        r++;
+        if (ld_agent(row_next + kRtAlive) == 0u || r + 2 >= a.max_rounds) break;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st_agent(a.bar + kMaxBlocks + 32, (uint32_t)r);
 }
 
 // Round-0 tuples for every vertex.
@@ -415,7 +917,7 @@ int id_bits(int64_t n) {
 }
 
 TupleParams tuple_params(int64_t n, uint64_t seed, uint64_t iter) {
-    TupleParams p;
+    TupleParams p{};
     p.b = (uint32_t)id_bits(n);
     const int pb = 32 - (int)p.b;
     p.pmask = pb <= 0 ? 0ull : ((1ull << pb) - 1ull);
@@ -425,6 +927,7 @@ TupleParams tuple_params(int64_t n, uint64_t seed, uint64_t iter) {
 
 #define MIS2_LANE_DISPATCH(L, KERNEL, ...)                                              \
     switch (L) {                                                                        \
+        case 0: hipLaunchKernelGGL(KERNEL<0>, __VA_ARGS__); break;                      \
         case 1: hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__); break;                      \
         case 2: hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__); break;                      \
         case 4: hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__); break;                      \
@@ -461,6 +964,51 @@ hipError_t launch_init_masked(int blocks, const TupleParams &tp, int64_t n, cons
                               uint32_t *T, uint32_t *M, const SegIO &io, hipStream_t s) {
     hipLaunchKernelGGL(k_init_masked, dim3(blocks), dim3(kBlock), 0, s, tp, n, label, T, M, io);
     return hipGetLastError();
+}
+
+template <int L>
+hipError_t launch_rounds_t(int blocks, const int64_t *row_ptr, const int32_t *col, uint32_t *T,
+                           uint32_t *M, const RoundsArgs &a, hipStream_t s) {
+    const int64_t *rp = row_ptr;
+    const int32_t *cl = col;
+    uint32_t *t = T, *m = M;
+    RoundsArgs aa = a;
+    void *args[] = {(void *)&rp, (void *)&cl, (void *)&t, (void *)&m, (void *)&aa};
+    return hipLaunchCooperativeKernel((const void *)k_rounds<L>, dim3(blocks), dim3(kBlock), args,
+                                      0, s);
+}
+
+int rounds_max_blocks(int lanes, int num_cus) {
+    int per_cu = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (lanes) {
+        case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rounds<0>, kBlock, 0); break;
+        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rounds<1>, kBlock, 0); break;
+        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rounds<2>, kBlock, 0); break;
+        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rounds<4>, kBlock, 0); break;
+        case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rounds<8>, kBlock, 0); break;
+        case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rounds<16>, kBlock, 0); break;
+        case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rounds<32>, kBlock, 0); break;
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rounds<64>, kBlock, 0); break;
+        default: break;
+    }
+    if (e != hipSuccess || per_cu <= 0) return 0;
+    return per_cu * num_cus;
+}
+
+hipError_t launch_rounds(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
+                         uint32_t *T, uint32_t *M, const RoundsArgs &a, hipStream_t s) {
+    switch (lanes) {
+        case 0: return launch_rounds_t<0>(blocks, row_ptr, col, T, M, a, s);
+        case 1: return launch_rounds_t<1>(blocks, row_ptr, col, T, M, a, s);
+        case 2: return launch_rounds_t<2>(blocks, row_ptr, col, T, M, a, s);
+        case 4: return launch_rounds_t<4>(blocks, row_ptr, col, T, M, a, s);
+        case 8: return launch_rounds_t<8>(blocks, row_ptr, col, T, M, a, s);
+        case 16: return launch_rounds_t<16>(blocks, row_ptr, col, T, M, a, s);
+        case 32: return launch_rounds_t<32>(blocks, row_ptr, col, T, M, a, s);
+        case 64: return launch_rounds_t<64>(blocks, row_ptr, col, T, M, a, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 int64_t status_blocks(int64_t n) { return n <= 0 ? 0 : (n + kCountTile - 1) / kCountTile; }

@@ -1,0 +1,225 @@
+// quotient.hip -- coarse graph of an aggregation, for multilevel coarsening on gfx950.
+//
+// The paper coarsens recursively (Sections I and II) without saying how the
+// next graph is formed.  Here it is the quotient graph: vertices are the
+// aggregates, and a is adjacent to c iff some edge (u, w) has agg u = a,
+// agg w = c and a != c.  Rows come out with ascending, distinct columns.
+//
+// Member lists are built by a counting sort (their order does not matter:
+// every coarse row is a sorted set).  One workgroup then handles one coarse
+// row: it gathers the aggregate ids of its members' neighbours into LDS and
+// sorts them with a bitonic network (up to kQCap candidates), or, for rows
+// with more candidates, sweeps the coarse id space in windows of
+// 32*kQCap ids with an LDS bitmap, which emits ids in increasing order.  The
+// same kernel runs twice: once to count each row, once (after a prefix sum)
+// to write it.
+#include "internal.h"
+
+namespace mis2 {
+
+namespace {
+
+constexpr int kQCap = 4096;                  // candidates sorted in LDS per coarse row
+constexpr int64_t kQWindow = 32 * kQCap;     // coarse ids per bitmap window
+constexpr int kWaves = kBlock / 64;
+
+__global__ __launch_bounds__(kBlock) void k_member_count(int64_t n, const int32_t *__restrict__ agg,
+                                                         uint32_t *__restrict__ cnt) {
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * kBlock)
+        atomicAdd(&cnt[agg[v]], 1u);
+}
+
+__global__ __launch_bounds__(kBlock) void k_member_scatter(int64_t n, const int32_t *__restrict__ agg,
+                                                           const int64_t *__restrict__ moff,
+                                                           uint32_t *__restrict__ cursor,
+                                                           int32_t *__restrict__ members) {
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * kBlock) {
+        const int32_t a = agg[v];
+        const uint32_t pos = atomicAdd(&cursor[a], 1u);
+        members[moff[a] + pos] = (int32_t)v;
+    }
+}
+
+// Sum over the workgroup (all threads must call it; result in every thread).
+__device__ __forceinline__ unsigned long long block_sum(unsigned long long x,
+                                                        unsigned long long *scratch) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63u) == 0) scratch[threadIdx.x >> 6] = x;
+    __syncthreads();
+    unsigned long long t = 0;
+    for (int w = 0; w < kWaves; w++) t += scratch[w];
+    return t;
+}
+
+// Exclusive prefix of x over the workgroup in thread order; *total gets the
+// sum.  All threads must call it.
+__device__ __forceinline__ uint32_t block_excl(uint32_t x, uint32_t *scratch, uint32_t *total) {
+    const int lane = (int)(threadIdx.x & 63u), wave = (int)(threadIdx.x >> 6);
+    uint32_t incl = x;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    __syncthreads();
+    if (lane == 63) scratch[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, t = 0;
+    for (int w = 0; w < kWaves; w++) {
+        if (w < wave) before += scratch[w];
+        t += scratch[w];
+    }
+    *total = t;
+    return before + incl - x;
+}
+
+// FILL = false: ccnt[a] = number of distinct coarse neighbours of row a.
+// FILL = true:  ccol[crow[a] ...] = those neighbours in increasing order.
+template <bool FILL>
+__global__ __launch_bounds__(kBlock) void k_coarse_rows(const int64_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ col,
+                                                        const int32_t *__restrict__ agg,
+                                                        int64_t n_agg,
+                                                        const int64_t *__restrict__ moff,
+                                                        const int32_t *__restrict__ members,
+                                                        uint32_t *__restrict__ ccnt,
+                                                        const int64_t *__restrict__ crow,
+                                                        int32_t *__restrict__ ccol) {
+    __shared__ uint32_t buf[kQCap];
+    __shared__ unsigned long long red[kWaves];
+    __shared__ uint32_t scan_s[kWaves];
+    __shared__ uint32_t fill_s;
+    const int tid = (int)threadIdx.x;
+    for (int64_t a = blockIdx.x; a < n_agg; a += gridDim.x) {
+        const int64_t m0 = moff[a], m1 = moff[a + 1];
+        unsigned long long cand = 0;
+        for (int64_t i = m0 + tid; i < m1; i += kBlock) {
+            const int32_t v = members[i];
+            cand += (unsigned long long)(row_ptr[v + 1] - row_ptr[v]);
+        }
+        cand = block_sum(cand, red);
+        uint32_t distinct = 0;
+        if (cand <= (unsigned long long)kQCap) {
+            // gather the candidate ids (self excluded) into LDS
+            if (tid == 0) fill_s = 0;
+            __syncthreads();
+            for (int64_t i = m0 + tid; i < m1; i += kBlock) {
+                const int32_t v = members[i];
+                for (int64_t j = row_ptr[v], e = row_ptr[v + 1]; j < e; j++) {
+                    const int32_t c = agg[col[j]];
+                    if ((int64_t)c != a) buf[atomicAdd(&fill_s, 1u)] = (uint32_t)c;
+                }
+            }
+            __syncthreads();
+            const uint32_t m = fill_s;
+            uint32_t P = 1;
+            while (P < m) P <<= 1;
+            for (uint32_t i = m + tid; i < P; i += kBlock) buf[i] = 0xFFFFFFFFu;
+            __syncthreads();
+            // bitonic sort of buf[0..P)
+            for (uint32_t k = 2; k <= P; k <<= 1) {
+                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                    for (uint32_t i = tid; i < P; i += kBlock) {
+                        const uint32_t ixj = i ^ j;
+                        if (ixj > i) {
+                            const uint32_t x = buf[i], y = buf[ixj];
+                            const bool up = (i & k) == 0;
+                            if ((x > y) == up) {
+                                buf[i] = y;
+                                buf[ixj] = x;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            // distinct values, in order
+            uint32_t run = 0;
+            for (uint32_t c0 = 0; c0 < m; c0 += kBlock) {
+                const uint32_t i = c0 + tid;
+                const bool first = i < m && (i == 0 || buf[i] != buf[i - 1]);
+                uint32_t tot;
+                const uint32_t pos = block_excl(first ? 1u : 0u, scan_s, &tot);
+                if (FILL && first) ccol[crow[a] + run + pos] = (int32_t)buf[i];
+                run += tot;
+            }
+            distinct = run;
+        } else {
+            // bitmap windows over the coarse id space
+            uint32_t run = 0;
+            for (int64_t lo = 0; lo < n_agg; lo += kQWindow) {
+                for (int i = tid; i < kQCap; i += kBlock) buf[i] = 0u;
+                __syncthreads();
+                for (int64_t i = m0; i < m1; i++) {
+                    const int32_t v = members[i];
+                    for (int64_t j = row_ptr[v] + tid, e = row_ptr[v + 1]; j < e; j += kBlock) {
+                        const int64_t c = agg[col[j]];
+                        if (c != a && c >= lo && c < lo + kQWindow) {
+                            const int64_t o = c - lo;
+                            atomicOr(&buf[o >> 5], 1u << (o & 31));
+                        }
+                    }
+                }
+                __syncthreads();
+                for (int c0 = 0; c0 < kQCap; c0 += kBlock) {
+                    const int wi = c0 + tid;
+                    const uint32_t word = buf[wi];
+                    uint32_t tot;
+                    const uint32_t pos = block_excl((uint32_t)__popc(word), scan_s, &tot);
+                    if (FILL) {
+                        uint32_t wv = word, k = 0;
+                        while (wv) {
+                            const int bit = __ffs(wv) - 1;
+                            wv &= wv - 1;
+                            ccol[crow[a] + run + pos + k] = (int32_t)(lo + (int64_t)wi * 32 + bit);
+                            k++;
+                        }
+                    }
+                    run += tot;
+                }
+                __syncthreads();
+            }
+            distinct = run;
+        }
+        if (!FILL && tid == 0) ccnt[a] = distinct;
+        __syncthreads();
+    }
+}
+
+int grid_for(int64_t work, int per_block, int cap) {
+    int64_t b = (work + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+}  // namespace
+
+hipError_t quotient_graph(const int64_t *row_ptr, const int32_t *col, int64_t n, const int32_t *agg,
+                          int64_t n_agg, int64_t *crow, int32_t *ccol, const QuotientWs &q,
+                          hipStream_t s) {
+    hipError_t e;
+    if ((e = launch_fill_u32(q.cnt, 0u, n_agg, s)) != hipSuccess) return e;
+    if (n > 0)
+        hipLaunchKernelGGL(k_member_count, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, n,
+                           agg, q.cnt);
+    if ((e = exclusive_scan_u32_i64(q.cnt, n_agg, q.moff, q.part, s)) != hipSuccess) return e;
+    if ((e = launch_fill_u32(q.cnt, 0u, n_agg, s)) != hipSuccess) return e;
+    if (n > 0)
+        hipLaunchKernelGGL(k_member_scatter, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s,
+                           n, agg, q.moff, q.cnt, q.members);
+    const int blocks = grid_for(n_agg, 1, 16384);
+    if (n_agg > 0)
+        hipLaunchKernelGGL(k_coarse_rows<false>, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col,
+                           agg, n_agg, q.moff, q.members, q.cnt, (const int64_t *)nullptr,
+                           (int32_t *)nullptr);
+    if ((e = exclusive_scan_u32_i64(q.cnt, n_agg, crow, q.part, s)) != hipSuccess) return e;
+    if (n_agg > 0)
+        hipLaunchKernelGGL(k_coarse_rows<true>, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col,
+                           agg, n_agg, q.moff, q.members, q.cnt, crow, ccol);
+    return hipGetLastError();
+}
+
+}  // namespace mis2

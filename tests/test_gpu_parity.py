@@ -83,13 +83,14 @@ def test_mis2_parity_seeds(ctx, seed):
     _check_mis2(ctx, rp, c, seed, "seed%d" % seed)
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("lanes", [-1, 1, 2, 4, 8, 16, 32, 64])
 def test_mis2_every_lane_plan(api, lanes):
     for blocks in (1, 13, 0):
-        c = api.Context(0, lanes=lanes, blocks=blocks)
-        for name in ("grid27_ragged", "chunglu_50k", "star70"):
-            rp, cc = dict(SMALL)[name]
-            _check_mis2(c, rp, cc, 0, "%s L%d B%d" % (name, lanes, blocks))
+        for persistent in (True, False):
+            c = api.Context(0, lanes=lanes, blocks=blocks, persistent=persistent)
+            for name in ("grid27_ragged", "chunglu_50k", "star70"):
+                rp, cc = dict(SMALL)[name]
+                _check_mis2(c, rp, cc, 0, "%s L%d B%d P%d" % (name, lanes, blocks, persistent))
 
 
 def test_mis2_repeatable(ctx):
@@ -116,12 +117,25 @@ def test_aggregate_parity_small(ctx, name):
     _check_agg(ctx, rp, c, 0, name)
 
 
-@pytest.mark.parametrize("lanes", [1, 8, 64])
+@pytest.mark.parametrize("lanes", [-1, 1, 8, 64])
 def test_aggregate_lane_plans(api, lanes):
-    c = api.Context(0, lanes=lanes, blocks=7)
-    for name in ("grid27_ragged", "chunglu_50k", "path101"):
-        rp, cc = dict(SMALL)[name]
-        _check_agg(c, rp, cc, 3, name)
+    for persistent in (True, False):
+        c = api.Context(0, lanes=lanes, blocks=7, persistent=persistent)
+        for name in ("grid27_ragged", "chunglu_50k", "path101"):
+            rp, cc = dict(SMALL)[name]
+            _check_agg(c, rp, cc, 3, name)
+
+
+def test_persistent_and_launched_rounds_agree(api):
+    rp, cc = dict(SMALL)["grid27_30"]
+    a = api.Context(0, persistent=True)
+    b = api.Context(0, persistent=False)
+    sa, na, ia = a.mis2(rp, cc, 5)
+    sb, nb, ib = b.mis2(rp, cc, 5)
+    assert np.array_equal(sa.cpu().numpy(), sb.cpu().numpy()) and (na, ia) == (nb, ib)
+    assert np.array_equal(a.last_trace(0), b.last_trace(0))
+    assert any(r["kind"] == 2 for r in a.last_sweeps())
+    assert not any(r["kind"] == 2 for r in b.last_sweeps())
 
 
 def test_aggregate_empty(ctx):
@@ -151,18 +165,71 @@ def test_c1_grid2d_64(ctx):
     _check_agg(ctx, rp, c, 0, "C1")
 
 
-def test_c2_grid27_100(ctx):
+def test_c2_grid27_100(ctx, api):
     rp, c = _c2()
     _say("C2 27-point 100^3", rp.size - 1, int(rp[-1]))
     _check_mis2(ctx, rp, c, 0, "C2")
     _check_agg(ctx, rp, c, 0, "C2")
+    for lanes in (-1, 4):
+        for persistent in (True, False):
+            other = api.Context(0, persistent=persistent, lanes=lanes)
+            _check_mis2(other, rp, c, 0, "C2 lanes %d persistent %d" % (lanes, persistent))
 
 
-def test_c3_chung_lu_4m(ctx):
+def test_c3_chung_lu_4m(ctx, api):
     rp, c = _c3()
     _say("C3 Chung-Lu", rp.size - 1, int(rp[-1]))
     _check_mis2(ctx, rp, c, 0, "C3")
     _check_agg(ctx, rp, c, 0, "C3")
+    flat = api.Context(0, lanes=-1)
+    _check_mis2(flat, rp, c, 0, "C3 flat")
+
+
+# ---------------------------------------------------------------- quotient / multilevel
+@pytest.mark.parametrize("name", ["grid2d_ragged", "grid27_30", "chunglu_50k", "dropped7_20",
+                                  "union", "er3", "star70", "edgeless100"])
+def test_quotient_parity(ctx, name):
+    rp, c = dict(SMALL)[name]
+    agg, na = oracle.aggregate(rp, c, 0)
+    crow, ccol = ctx.quotient(rp, c, agg, na)
+    orow, ocol = oracle.quotient(rp, c, agg, na)
+    assert np.array_equal(crow.cpu().numpy(), orow), name
+    assert np.array_equal(ccol.cpu().numpy(), ocol), name
+
+
+def test_quotient_big_rows_use_bitmap_windows(ctx):
+    # a star's single aggregate row has more candidates than fit the LDS sort
+    # when the aggregation is a fixed, hand-made labelling
+    n = 20000
+    rp, c = graphs.star(n, 0)
+    agg = np.arange(n, dtype=np.int32) % 7000
+    agg[0] = 0
+    crow, ccol = ctx.quotient(rp, c, agg, 7000)
+    orow, ocol = oracle.quotient(rp, c, agg, 7000)
+    assert np.array_equal(crow.cpu().numpy(), orow)
+    assert np.array_equal(ccol.cpu().numpy(), ocol)
+
+
+@pytest.mark.parametrize("name,stop", [("grid27_30", 100), ("chunglu_50k", 1000),
+                                       ("dropped7_20", 50), ("grid2d_64", 1000)])
+def test_coarsen_parity(ctx, name, stop):
+    rp, c = dict(SMALL)[name] if name in dict(SMALL) else _c1()
+    levels = ctx.coarsen(rp, c, seed=0, stop_below=stop)
+    want = oracle.coarsen(rp, c, seed=0, stop_below=stop)
+    assert len(levels) == len(want), name
+    for got, exp in zip(levels, want):
+        assert (got["n"], got["nnz"], got["n_agg"]) == (exp["n"], exp["nnz"], exp["n_agg"])
+        assert np.array_equal(got["agg"].cpu().numpy(), exp["agg"])
+
+
+def test_coarsen_c2_full(ctx):
+    rp, c = _c2()
+    levels = ctx.coarsen(rp, c, seed=0, stop_below=1000)
+    want = oracle.coarsen(rp, c, seed=0, stop_below=1000)
+    assert [(l["n"], l["nnz"], l["n_agg"]) for l in levels] == \
+        [(l["n"], l["nnz"], l["n_agg"]) for l in want]
+    for got, exp in zip(levels, want):
+        assert np.array_equal(got["agg"].cpu().numpy(), exp["agg"])
 
 
 # ---------------------------------------------------------------- error paths
