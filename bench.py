@@ -5,7 +5,11 @@ graph (default workload: 3D 27-point Laplacian graph on a 100^3 grid, 1M
 vertices, 25.46M stored entries, int64 row offsets, int32 columns, seed 0).
 Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c2|c3|c4|c5]
+
+c4 (batched multilevel coarsening of 512 subdomains, against a per-graph
+loop) and c5 (serving with Poisson arrivals, p50/p99 latency) print their own
+JSON line with the same keys.
 
 value = graph nnz / step time (nnz/s).  roofline: the sweep kernel with the
 largest share of GPU time, its algorithmic bytes per launch (exact, from an
@@ -57,6 +61,147 @@ def sweep_bytes(rec, identity):
     return 4 * rec["edges"] + per_row * rec["rows"] + 4 * rec["rows_out"]
 
 
+def c5_pool(count, seed=3, n_lo=1_000, n_hi=10_000_000):
+    """Serving jobs: n log-uniform on [n_lo, n_hi]; 40% 2D 5-point (side
+    round(sqrt n)), 40% 3D 27-point (side round(cbrt n)), 20% Chung-Lu (n,
+    mean degree 16, exponent 2.1, cap min(20000, n - 1))."""
+    import numpy as np
+    from paper_2204_02934_amd import graphs
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+        kind = rng.choice(3, p=[0.4, 0.4, 0.2])
+        if kind == 0:
+            s = max(2, int(round(n ** 0.5)))
+            out.append(("2d5", graphs.grid2d_5pt(s, s)))
+        elif kind == 1:
+            s = max(2, int(round(n ** (1 / 3))))
+            out.append(("3d27", graphs.grid3d_27pt(s, s, s)))
+        else:
+            out.append(("chunglu", graphs.chung_lu(n, 16.0, 2.1, min(20000, n - 1), seed=100 + i)))
+    return out
+
+
+def run_c4(args):
+    """Batched multilevel coarsening of 512 dropped-edge 7-point subdomains
+    (mis2_aggregate_batched, one call) against the same library called per
+    graph on one stream (mis2_coarsen in a loop)."""
+    import numpy as np
+    import torch
+    from paper_2204_02934_amd import api, graphs
+    gs = graphs.batch_subdomains(num=512, lo=8, hi=48, p_drop=0.1, seed=2)
+    rp_h, col_h = graphs.disjoint_union(gs)
+    voff = np.cumsum([0] + [g[0].size - 1 for g in gs]).astype(np.int64)
+    n, nnz = rp_h.size - 1, int(rp_h[-1])
+    log("c4: %d graphs, union n=%d nnz=%d" % (len(gs), n, nnz))
+    dev = torch.device("cuda", 0)
+    rp, col = api.as_device_csr(rp_h, col_h, dev)
+    per = [api.as_device_csr(a, b, dev) for a, b in gs]
+    per_nnz = [int(a[-1]) for a, _ in gs]
+    ctx = api.Context(0)
+    for _ in range(args.warmup):
+        ctx.aggregate_batched(rp, col, voff, seed=args.seed, stop_below=1000, nnz=nnz)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.aggregate_batched(rp, col, voff, seed=args.seed, stop_below=1000, nnz=nnz)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    # per-graph loop (one pass after one warm pass)
+    for (a, b), z in zip(per, per_nnz):
+        ctx.coarsen(a, b, seed=args.seed, stop_below=1000, nnz=z)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (a, b), z in zip(per, per_nnz):
+        ctx.coarsen(a, b, seed=args.seed, stop_below=1000, nnz=z)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    log("c4: batched %.2f ms, per-graph loop %.2f ms" % (1e3 * t_batch, 1e3 * t_loop))
+    return {
+        "metric": "MIS-2+aggregation graph nnz/s and HBM GB/s fraction",
+        "value": nnz / t_batch, "unit": "nnz/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t_batch, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "512 dropped-edge (p=0.1) 3D 7-point subdomains, side U{8..48}, "
+                               "multilevel MIS-2 aggregation to < 1000 vertices, batched",
+                   "n": n, "nnz": nnz, "graphs": len(gs), "seed": args.seed},
+        "per_graph_loop_ms": 1e3 * t_loop,
+        "per_graph_loop_nnz_per_s": nnz / t_loop,
+        "batched_speedup": t_loop / t_batch,
+    }
+
+
+def run_c5(args):
+    """Serving: Poisson arrivals of coarsening jobs into a mis2_server, at
+    0.5x and 0.8x of the saturation rate measured with every job queued at
+    once.  Latency = completion - arrival (host monotonic clock)."""
+    import numpy as np
+    import torch
+    from paper_2204_02934_amd import api
+    pool = c5_pool(args.c5_jobs)
+    dev = torch.device("cuda", 0)
+    jobs = []
+    for kind, (a, b) in pool:
+        d = api.as_device_csr(a, b, dev)
+        jobs.append((kind, d, a.size - 1, int(a[-1])))
+    tot_nnz = sum(j[3] for j in jobs)
+    vmax = max(j[2] for j in jobs)
+    emax = max(j[3] for j in jobs)
+    srv = api.Server(max_vertices=max(4 * vmax, 1 << 20), max_nnz=max(4 * emax, 1 << 22),
+                     max_graphs=256, seed=args.seed, stop_below=1000)
+    log("c5: %d jobs, sum nnz %d, largest n %d" % (len(jobs), tot_nnz, vmax))
+
+    def run(rate, rng):
+        n_jobs = len(jobs)
+        if rate is None:
+            arrive = np.zeros(n_jobs)
+        else:
+            arrive = np.cumsum(rng.exponential(1.0 / rate, n_jobs))
+        done_at = {}
+        t0 = time.perf_counter()
+        nxt = 0
+        while len(done_at) < n_jobs:
+            now = time.perf_counter() - t0
+            while nxt < n_jobs and arrive[nxt] <= now:
+                _, (a, b), _, z = jobs[nxt]
+                srv.submit(a, b, tag=nxt, nnz=z)
+                nxt += 1
+            pending = srv.step()
+            for r in srv.poll():
+                done_at[r["tag"]] = time.perf_counter() - t0
+            if pending == 0 and nxt < n_jobs:
+                time.sleep(max(0.0, min(arrive[nxt] - (time.perf_counter() - t0), 0.05)))
+        wall = time.perf_counter() - t0
+        lat = np.array([done_at[i] - arrive[i] for i in range(n_jobs)])
+        return wall, lat
+
+    run(None, None)  # warm-up
+    wall_sat, _ = run(None, None)
+    sat = len(jobs) / wall_sat
+    log("c5: saturation %.2f jobs/s (%.3f s for the pool)" % (sat, wall_sat))
+    res = {}
+    for frac in (0.5, 0.8):
+        wall, lat = run(frac * sat, np.random.default_rng(3))
+        res["%.1fx" % frac] = {"qps": frac * sat, "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                               "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                               "nnz_per_s": tot_nnz / wall, "wall_s": wall}
+        log("c5 %.1fx: %s" % (frac, json.dumps(res["%.1fx" % frac])))
+    srv.close()
+    return {
+        "metric": "MIS-2+aggregation graph nnz/s and HBM GB/s fraction",
+        "value": tot_nnz / wall_sat, "unit": "nnz/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1e3 * wall_sat, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "serving: %d multilevel coarsening jobs, n log-uniform [1e3, 1e7], "
+                               "2D 5-pt / 3D 27-pt / Chung-Lu 40/40/20, Poisson arrivals"
+                               % len(jobs), "jobs": len(jobs), "sum_nnz": tot_nnz,
+                   "seed": args.seed},
+        "saturation_jobs_per_s": sat,
+        "poisson": res,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,10 +213,17 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run three device-to-device copies of MIB MiB (a known-size "
                          "kernel for scaling hardware byte counters)")
+    ap.add_argument("--c5-jobs", type=int, default=32, help="serving: jobs in the pool")
     args = ap.parse_args()
     if args.gpus != 1:
         raise SystemExit("bench.py measures one GPU: this build has no multi-GPU path "
                          "(--gpus %d requested)" % args.gpus)
+    if args.workload in ("c4", "c5"):
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        out = run_c4(args) if args.workload == "c4" else run_c5(args)
+        print(json.dumps(out), flush=True)
+        return
 
     import numpy as np
     import torch

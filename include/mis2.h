@@ -55,11 +55,12 @@ extern "C" {
 #define MIS2_OPT_VALIDATE      0  /* 1: check the CSR on the GPU before each call (default 0) */
 #define MIS2_OPT_LANES_PER_ROW 1  /* 0 = automatic; -1 = flat (merge-path) sweeps; else 1, 2, 4,
                                      8, 16, 32 or 64 lanes per CSR row */
-#define MIS2_OPT_GRID_BLOCKS   2  /* 0 = automatic; else the number of 256-thread workgroups per sweep */
+#define MIS2_OPT_GRID_BLOCKS   2  /* 0 = automatic; else 1..8192 256-thread workgroups per sweep */
 #define MIS2_OPT_PROFILE       3  /* 1: time every sweep launch with HIP events on the call's stream */
 #define MIS2_OPT_ACCOUNT       4  /* 1: sweeps also sum the CSR row lengths they visit (extra atomics) */
-#define MIS2_OPT_PERSISTENT    5  /* 1 (default): all rounds of a MIS-2 run in one cooperative launch;
-                                     0: two launches per round (also the fallback) */
+#define MIS2_OPT_PERSISTENT    5  /* 0 (default): two launches per round; 1: all rounds of a MIS-2
+                                     run in one cooperative launch (falls back to 0 when the
+                                     grid cannot be co-resident) */
 
 typedef struct mis2_ctx mis2_ctx;
 
@@ -205,6 +206,103 @@ int mis2_coarsen_workspace_bytes(int64_t n, int64_t nnz, size_t *bytes);
 int mis2_coarsen(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int64_t stop_below,
                  int32_t max_levels, int32_t *agg_out, int64_t agg_cap, int64_t *level_n,
                  int64_t *level_nnz, int64_t *level_nagg, int32_t *n_levels, void *stream);
+
+/* Bytes of device workspace mis2_aggregate_batched needs for n_graphs graphs
+ * whose union has n vertices and nnz stored entries (written to *bytes). */
+int mis2_batch_workspace_bytes(int32_t n_graphs, int64_t n, int64_t nnz, size_t *bytes);
+
+/*
+ * mis2_aggregate_batched -- mis2_coarsen for many graphs in one call.
+ *
+ * The graphs of the batch are given as their disjoint union g: graph k owns
+ * the union's vertices [vtx_off[k], vtx_off[k+1]) and its rows there, with
+ * columns in union ids; no edge may join two graphs.  Each graph gets exactly
+ * what mis2_coarsen gives it alone (same seed, stop_below and max_levels):
+ * Algorithm 1's tuples use the graph's own vertex ids and id width b (Section
+ * V-C), and Algorithm 3's aggregate numbering is the graph's own.  Every
+ * level runs all still-coarsening graphs together as one union.
+ *
+ *   vtx_off     host, int64[n_graphs + 1], vtx_off[0] = 0, non-decreasing,
+ *               vtx_off[n_graphs] = g->n
+ *   agg_out     device out, int32[agg_cap]: one block per level.  Level 0's
+ *               block has g->n entries, the graph-local aggregate id of each
+ *               vertex (-1 for graphs with no level, i.e. fewer than
+ *               stop_below vertices); level l >= 1's block holds, in graph
+ *               order, the coarse vertices of the graphs with more than l
+ *               levels.  Blocks follow each other without gaps.
+ *   level_n, level_nnz, level_nagg
+ *               host out, int64[max_levels * n_graphs], entry l * n_graphs + k:
+ *               vertices, stored entries and aggregates of graph k's level-l
+ *               input (0 past its last level)
+ *   n_levels    host out, int32[n_graphs]: levels computed per graph
+ * Nothing is written to agg_out when no graph has a level.
+ * Needs a workspace of mis2_batch_workspace_bytes(n_graphs, g->n, g->nnz).
+ * MIS2_EINVAL for bad offsets; MIS2_ENOSPACE if agg_cap is too small.  Edges
+ * between graphs are not detected; they give wrong results (aggregates that
+ * would cross graphs are dropped as -1) but no out-of-bounds access.
+ */
+int mis2_aggregate_batched(mis2_ctx *ctx, const mis2_graph *g, int32_t n_graphs,
+                           const int64_t *vtx_off, uint64_t seed, int64_t stop_below,
+                           int32_t max_levels, int32_t *agg_out, int64_t agg_cap,
+                           int64_t *level_n, int64_t *level_nnz, int64_t *level_nagg,
+                           int32_t *n_levels, void *stream);
+
+/*
+ * Serving: continuous batching of coarsening jobs.
+ *
+ * A server owns a device arena (caller-allocated, 256-byte aligned, of
+ * mis2_server_bytes() bytes) for a union of at most max_vertices vertices,
+ * max_nnz stored entries and max_graphs graphs, plus its own context on
+ * `device`.  Each job is mis2_coarsen of one graph with the server's seed,
+ * stop_below and max_levels, and gets exactly mis2_coarsen's labels and level
+ * sizes.  mis2_server_step admits queued jobs first come first served while
+ * the union fits the arena, copying their CSRs in, then runs one level of
+ * Algorithm 3 for every graph in the union at once (graphs at different levels
+ * side by side); graphs that go on stay in the union as their coarse graphs,
+ * so new jobs join at the next step.  Not thread-safe; one stream at a time.
+ */
+#define MIS2_SERVE_MAX_LEVELS 32
+
+typedef struct mis2_server mis2_server;
+
+typedef struct mis2_job_result {
+    int64_t tag;             /* the submit() tag */
+    int32_t n_levels;        /* levels computed */
+    int32_t truncated;       /* 1 if coarsening stopped because agg_out was full */
+    int64_t level_n[MIS2_SERVE_MAX_LEVELS];     /* vertices of each level's graph */
+    int64_t level_nnz[MIS2_SERVE_MAX_LEVELS];   /* stored entries */
+    int64_t level_nagg[MIS2_SERVE_MAX_LEVELS];  /* aggregates */
+} mis2_job_result;
+
+/* Arena bytes for the given capacities (written to *bytes, host). */
+int mis2_server_bytes(int64_t max_vertices, int64_t max_nnz, int32_t max_graphs, size_t *bytes);
+
+/* max_levels in [1, MIS2_SERVE_MAX_LEVELS]; max_vertices <= 2^31 - 3.
+ * MIS2_EINVAL for bad capacities or an arena that is too small or misaligned. */
+int mis2_server_create(mis2_server **srv, int device, void *arena, size_t arena_bytes,
+                       int64_t max_vertices, int64_t max_nnz, int32_t max_graphs, uint64_t seed,
+                       int64_t stop_below, int32_t max_levels);
+void mis2_server_destroy(mis2_server *srv);
+const char *mis2_server_last_error(const mis2_server *srv);
+
+/* Queue a job.  g: device CSR that must stay valid (and unchanged) until the
+ * job is admitted, i.e. until a later mis2_server_step returns.  agg_out:
+ * device int32[agg_cap], at least g->n; receives each level's labels one
+ * after the other, as mis2_coarsen's agg_out (a job whose next level might
+ * not fit stops early with truncated = 1).  Jobs with fewer than stop_below
+ * vertices finish at once with no level.  MIS2_ENOSPACE if the graph alone
+ * exceeds the server's capacities. */
+int mis2_server_submit(mis2_server *srv, const mis2_graph *g, int32_t *agg_out, int64_t agg_cap,
+                       int64_t tag);
+
+/* One step (admission + one level of every admitted graph) on `stream`;
+ * returns after the stream has finished it.  *n_pending (host, may be NULL):
+ * jobs queued or still coarsening afterwards. */
+int mis2_server_step(mis2_server *srv, void *stream, int32_t *n_pending);
+
+/* Finished jobs since the last poll, in completion order, at most cap of
+ * them; *count gets how many were written. */
+int mis2_server_poll(mis2_server *srv, mis2_job_result *out, int32_t cap, int32_t *count);
 
 #ifdef __cplusplus
 }

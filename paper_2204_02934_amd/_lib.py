@@ -31,8 +31,12 @@ EXPORTS = (
     "mis2_create", "mis2_destroy", "mis2_last_error", "mis2_set_option",
     "mis2_workspace_bytes", "mis2_set_workspace", "mis2_run", "mis2_last_trace",
     "mis2_aggregate", "mis2_last_sweeps", "mis2_quotient", "mis2_coarsen_workspace_bytes",
-    "mis2_coarsen",
+    "mis2_coarsen", "mis2_batch_workspace_bytes", "mis2_aggregate_batched",
+    "mis2_server_bytes", "mis2_server_create", "mis2_server_destroy", "mis2_server_last_error",
+    "mis2_server_submit", "mis2_server_step", "mis2_server_poll",
 )
+
+MIS2_SERVE_MAX_LEVELS = 32
 
 
 class Mis2Graph(ctypes.Structure):
@@ -44,6 +48,14 @@ class Mis2SweepRecord(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("phase", ctypes.c_int32), ("round", ctypes.c_int32),
                 ("lanes", ctypes.c_int32), ("rows", ctypes.c_int64), ("rows_out", ctypes.c_int64),
                 ("edges", ctypes.c_int64), ("ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
+class Mis2JobResult(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_int64), ("n_levels", ctypes.c_int32),
+                ("truncated", ctypes.c_int32),
+                ("level_n", ctypes.c_int64 * MIS2_SERVE_MAX_LEVELS),
+                ("level_nnz", ctypes.c_int64 * MIS2_SERVE_MAX_LEVELS),
+                ("level_nagg", ctypes.c_int64 * MIS2_SERVE_MAX_LEVELS)]
 
 
 class Mis2Error(RuntimeError):
@@ -84,6 +96,21 @@ def load():
         "mis2_coarsen": (ctypes.c_int, [vp, gp, u64, i64, i32, vp, i64, ctypes.POINTER(i64),
                                         ctypes.POINTER(i64), ctypes.POINTER(i64),
                                         ctypes.POINTER(i32), vp]),
+        "mis2_server_bytes": (ctypes.c_int, [i64, i64, i32, ctypes.POINTER(ctypes.c_size_t)]),
+        "mis2_server_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.c_size_t,
+                                              i64, i64, i32, u64, i64, i32]),
+        "mis2_server_destroy": (None, [vp]),
+        "mis2_server_last_error": (ctypes.c_char_p, [vp]),
+        "mis2_server_submit": (ctypes.c_int, [vp, gp, vp, i64, i64]),
+        "mis2_server_step": (ctypes.c_int, [vp, vp, ctypes.POINTER(i32)]),
+        "mis2_server_poll": (ctypes.c_int, [vp, ctypes.POINTER(Mis2JobResult), i32,
+                                            ctypes.POINTER(i32)]),
+        "mis2_batch_workspace_bytes": (ctypes.c_int, [i32, i64, i64,
+                                                      ctypes.POINTER(ctypes.c_size_t)]),
+        "mis2_aggregate_batched": (ctypes.c_int, [vp, gp, i32, ctypes.POINTER(i64), u64, i64, i32,
+                                                  vp, i64, ctypes.POINTER(i64),
+                                                  ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                                  ctypes.POINTER(i32), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

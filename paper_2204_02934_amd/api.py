@@ -40,7 +40,7 @@ class Context:
     on demand (allocation happens outside the library calls)."""
 
     def __init__(self, device=None, validate=False, lanes=0, blocks=0, profile=False,
-                 account=False, persistent=True):
+                 account=False, persistent=False):
         self.lib = _lib.load()
         if device is None:
             device = torch.cuda.current_device()
@@ -169,6 +169,58 @@ class Context:
             off += ln[i]
         return out
 
+    def aggregate_batched(self, row_ptr, col, vtx_off, seed=0, stop_below=1000, max_levels=64,
+                          stream=None, nnz=None):
+        """Multilevel coarsening of every graph of a disjoint union in one call
+        (mis2_aggregate_batched).  vtx_off: host int64[G + 1] vertex offsets of
+        the graphs in the union.  Returns, per graph, the list of its levels as
+        dicts {n, nnz, n_agg, agg (int32 graph-local labels on the GPU)}."""
+        g, keep = self.graph(row_ptr, col, nnz)
+        voff = np.ascontiguousarray(np.asarray(vtx_off, dtype=np.int64))
+        G = voff.size - 1
+        b = ctypes.c_size_t(0)
+        _check(self.lib, self.ptr,
+               self.lib.mis2_batch_workspace_bytes(G, g.n, g.nnz, ctypes.byref(b)))
+        self._ensure_bytes(b.value)
+        cap = max(2 * g.n, 1)
+        agg = torch.empty(cap, dtype=torch.int32, device=self.device)
+        k = max(max_levels, 1) * max(G, 1)
+        ln = (ctypes.c_int64 * k)()
+        lz = (ctypes.c_int64 * k)()
+        la = (ctypes.c_int64 * k)()
+        nl = (ctypes.c_int32 * max(G, 1))()
+        vo = voff.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        while True:
+            rc = self.lib.mis2_aggregate_batched(self.ptr, ctypes.byref(g), G, vo,
+                                                 ctypes.c_uint64(seed), int(stop_below),
+                                                 int(max_levels), ctypes.c_void_p(agg.data_ptr()),
+                                                 agg.numel(), ln, lz, la, nl,
+                                                 _stream_ptr(stream, self.device))
+            if rc == _lib.MIS2_ENOSPACE and b"agg_cap" in self.lib.mis2_last_error(self.ptr):
+                agg = torch.empty(2 * agg.numel(), dtype=torch.int32, device=self.device)
+                continue
+            break
+        _check(self.lib, self.ptr, rc)
+        del keep
+        out = [[] for _ in range(G)]
+        off = 0
+        for lv in range(max(nl[i] for i in range(G)) if G else 0):
+            for i in range(G):
+                if lv == 0:
+                    n_i = int(voff[i + 1] - voff[i])
+                    if nl[i] > 0:
+                        out[i].append({"n": ln[i], "nnz": lz[i], "n_agg": la[i],
+                                       "agg": agg[off + int(voff[i]):off + int(voff[i + 1])]})
+                    continue
+                if nl[i] > lv:
+                    e = lv * G + i
+                    out[i].append({"n": ln[e], "nnz": lz[e], "n_agg": la[e],
+                                   "agg": agg[off:off + ln[e]]})
+                    off += ln[e]
+            if lv == 0:
+                off += g.n
+        return out
+
     def last_trace(self, phase=0, cap=4096):
         """Per-round (|worklist1|, |worklist2|) of the last call, int64[rounds, 2]."""
         buf = (ctypes.c_int64 * (2 * cap))()
@@ -191,6 +243,87 @@ class Context:
             out.append({"kind": r.kind, "phase": r.phase, "round": r.round, "lanes": r.lanes,
                         "rows": r.rows, "rows_out": r.rows_out, "edges": r.edges, "ms": r.ms})
         return out
+
+
+class Server:
+    """A mis2_server: continuous batching of multilevel coarsening jobs.  The
+    arena is one torch allocation sized for the given union capacities."""
+
+    def __init__(self, max_vertices, max_nnz, max_graphs=1024, seed=0, stop_below=1000,
+                 max_levels=_lib.MIS2_SERVE_MAX_LEVELS, device=None):
+        self.lib = _lib.load()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        b = ctypes.c_size_t(0)
+        rc = self.lib.mis2_server_bytes(int(max_vertices), int(max_nnz), int(max_graphs),
+                                        ctypes.byref(b))
+        if rc != _lib.MIS2_OK:
+            raise Mis2Error(rc, "bad server capacities")
+        self.arena = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+        self.ptr = ctypes.c_void_p()
+        rc = self.lib.mis2_server_create(ctypes.byref(self.ptr), self.device.index or 0,
+                                         ctypes.c_void_p(self.arena.data_ptr()), b.value,
+                                         int(max_vertices), int(max_nnz), int(max_graphs),
+                                         ctypes.c_uint64(seed), int(stop_below), int(max_levels))
+        if rc != _lib.MIS2_OK:
+            raise Mis2Error(rc, "mis2_server_create failed")
+        self._jobs = {}  # tag -> (graph tensors, agg tensor), kept alive until polled
+
+    def _check(self, rc):
+        if rc != _lib.MIS2_OK:
+            msg = self.lib.mis2_server_last_error(self.ptr)
+            raise Mis2Error(rc, msg.decode() if msg else "")
+
+    def submit(self, row_ptr, col, tag, agg_cap=None, nnz=None):
+        """Queue one coarsening job (device or host CSR); its labels land in a
+        device int32 tensor returned by poll()."""
+        rp, cc = as_device_csr(row_ptr, col, self.device)
+        n = rp.numel() - 1
+        if nnz is None:
+            nnz = int(rp[-1].item())
+        cap = max(2 * n, 1) if agg_cap is None else agg_cap
+        agg = torch.empty(cap, dtype=torch.int32, device=self.device)
+        g = Mis2Graph(n, nnz, rp.data_ptr(), cc.data_ptr())
+        self._check(self.lib.mis2_server_submit(self.ptr, ctypes.byref(g),
+                                                ctypes.c_void_p(agg.data_ptr()), cap, int(tag)))
+        self._jobs[int(tag)] = (rp, cc, agg)
+
+    def step(self, stream=None):
+        """One admission + level step; returns the number of jobs still queued
+        or coarsening."""
+        k = ctypes.c_int32(0)
+        self._check(self.lib.mis2_server_step(self.ptr, _stream_ptr(stream, self.device),
+                                              ctypes.byref(k)))
+        return k.value
+
+    def poll(self, cap=4096):
+        """Finished jobs: list of dicts {tag, levels: [{n, nnz, n_agg, agg}], truncated}."""
+        buf = (_lib.Mis2JobResult * cap)()
+        k = ctypes.c_int32(0)
+        self._check(self.lib.mis2_server_poll(self.ptr, buf, cap, ctypes.byref(k)))
+        out = []
+        for i in range(k.value):
+            r = buf[i]
+            _, _, agg = self._jobs.pop(int(r.tag))
+            levels, off = [], 0
+            for lv in range(r.n_levels):
+                levels.append({"n": r.level_n[lv], "nnz": r.level_nnz[lv],
+                               "n_agg": r.level_nagg[lv], "agg": agg[off:off + r.level_n[lv]]})
+                off += r.level_n[lv]
+            out.append({"tag": r.tag, "levels": levels, "truncated": bool(r.truncated)})
+        return out
+
+    def close(self):
+        if self.ptr:
+            self.lib.mis2_server_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _default = {}

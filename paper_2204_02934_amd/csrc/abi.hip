@@ -35,6 +35,13 @@ int fail(mis2_ctx *ctx, int code, const char *fmt, ...) {
                         __FILE__, __LINE__);                                                \
     } while (0)
 
+// Tuple parameters of a round, carrying the graphs of a batched run.
+TupleParams tparams(const mis2_ctx *ctx, int64_t n, uint64_t seed, uint64_t iter) {
+    TupleParams p = tuple_params(n, seed, iter);
+    p.batch = ctx->batch;
+    return p;
+}
+
 int check_graph_args(mis2_ctx *ctx, const mis2_graph *g) {
     if (!ctx) return MIS2_EINVAL;
     if (!g) return fail(ctx, MIS2_EINVAL, "graph is NULL");
@@ -182,8 +189,9 @@ int run_rounds_persistent(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, con
     if (cap < gm.blocks) return kFallBack;  // geometry() sizes the default plan to fit
     unsigned long long *degs = ws.degs + (size_t)phase * kTraceCap * 2;
     HIP_TRY(ctx, launch_fill_u32(ws.bar, 0u, kBarWords, s));
-    const TupleParams tp = tuple_params(g->n, seed, 0);
+    const TupleParams tp = tparams(ctx, g->n, seed, 0);
     RoundsArgs a;
+    a.batch = ctx->batch;
     a.wl1[0] = ws.wl1[0];
     a.wl1[1] = ws.wl1[1];
     a.wl2[0] = ws.wl2[0];
@@ -292,7 +300,7 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
                          g->n,
                          gm.seg,
                          gm.S};
-            const TupleParams next = tuple_params(g->n, seed, (uint64_t)round + 1);
+            const TupleParams next = tparams(ctx, g->n, seed, (uint64_t)round + 1);
             Launch lc{0, phase, round, lanes, nullptr, nullptr};
             Launch ld{1, phase, round, lanes, nullptr, nullptr};
             if (ctx->profile) {
@@ -572,7 +580,7 @@ int mis2_run(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, uint8_t *status,
     ctx->events_used = 0;
     std::vector<Launch> launches;
     const Geometry gm = geometry(ctx, g->n, lanes_for(ctx, g));
-    HIP_TRY(ctx, launch_init_tuples(tuple_params(g->n, seed, 0), g->n, ws.T, s));
+    HIP_TRY(ctx, launch_init_tuples(tparams(ctx, g->n, seed, 0), g->n, ws.T, s));
     int32_t iters = 0;
     if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, &iters, &launches))) return rc;
     HIP_TRY(ctx, launch_status(g->n, ws.T, status, ws.blocksum, ws.scalars + kS_Roots, s));
@@ -609,9 +617,13 @@ int mis2_last_sweeps(const mis2_ctx *ctx, mis2_sweep_record *out, int32_t cap, i
 
 namespace {
 
-// Algorithm 3 on a validated graph with n > 0 and a carved workspace.
+// Algorithm 3 on a validated graph with n > 0 and a carved workspace.  In a
+// batched run (ctx->batch set) P1 / P2 (device, [G + 1] each) receive the
+// per-graph root bounds of phases 1 and 2 (see batch.hip) and agg_id holds
+// union-wide aggregate ids.
 int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *agg_id,
-                   int64_t *n_agg, uint8_t *roots, const Workspace &ws, hipStream_t s) {
+                   int64_t *n_agg, uint8_t *roots, const Workspace &ws, hipStream_t s,
+                   uint32_t *P1 = nullptr, uint32_t *P2 = nullptr) {
     int rc;
     const int64_t n = g->n;
     uint32_t *sc = ws.scalars;
@@ -621,7 +633,7 @@ int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
 
     // Phase 1: MIS-2 of G; roots numbered by increasing id, each labelled with
     // its neighbours.
-    HIP_TRY(ctx, launch_init_tuples(tuple_params(n, seed, 0), n, ws.T, s));
+    HIP_TRY(ctx, launch_init_tuples(tparams(ctx, n, seed, 0), n, ws.T, s));
     int32_t it1 = 0, it2 = 0;
     if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, &it1, &launches))) return rc;
     HIP_TRY(ctx, launch_fill_u32(sc, 0u, kScalars, s));
@@ -630,6 +642,9 @@ int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
     HIP_TRY(ctx, compact_u32_eq(ws.T, kIn, n, ws.list, sc + kS_Count1, ws.blocksum, s));
     HIP_TRY(ctx, launch_label_roots(n, g->row_ptr, g->col, ws.list, sc + kS_Count1, nullptr, false,
                                     ws.label, ws.aggsize, roots, 1, s));
+    if (P1)
+        HIP_TRY(ctx, launch_graph_bounds(ws.list, sc + kS_Count1, ctx->batch.voff, ctx->batch.G,
+                                         P1, s));
 
     // Phase 2: MIS-2 of the subgraph induced by the unlabelled vertices (same
     // ids and b, round counter from 0); roots with >= 2 unlabelled neighbours
@@ -637,13 +652,16 @@ int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
     HIP_TRY(ctx, launch_fill_u32(ws.rt, 0u, kRoundStride, s));
     SegIO act_io{nullptr, nullptr, ws.wl1[0], ws.cnt1[0], ws.rt, nullptr, nullptr, nullptr,
                  n, gm.seg, gm.S};
-    HIP_TRY(ctx, launch_init_masked(gm.blocks, tuple_params(n, seed, 0), n, ws.label, ws.T, ws.M,
+    HIP_TRY(ctx, launch_init_masked(gm.blocks, tparams(ctx, n, seed, 0), n, ws.label, ws.T, ws.M,
                                     act_io, s));
     if ((rc = run_rounds(ctx, g, seed, ws, gm, true, 1, s, &it2, &launches))) return rc;
     HIP_TRY(ctx, launch_accept_phase2(n, g->row_ptr, g->col, ws.T, ws.label, ws.flag, s));
     HIP_TRY(ctx, compact_u8_nz(ws.flag, n, ws.list, sc + kS_Count2, ws.blocksum, s));
     HIP_TRY(ctx, launch_label_roots(n, g->row_ptr, g->col, ws.list, sc + kS_Count2,
                                     sc + kS_Count1, true, ws.label, ws.aggsize, roots, 2, s));
+    if (P2)
+        HIP_TRY(ctx, launch_graph_bounds(ws.list, sc + kS_Count2, ctx->batch.voff, ctx->batch.G,
+                                         P2, s));
 
     // Phase 3: each unlabelled vertex joins its best-coupled aggregate, all
     // counted on the labels frozen after phase 2.
@@ -688,7 +706,116 @@ size_t coarsen_bytes(int64_t n, int64_t nnz) {
     return workspace_bytes(n, MIS2_OP_COARSEN) + 2 * (align_up(8 * (un + 1)) + align_up(4 * unz));
 }
 
+// Clears ctx->batch when a batched call returns.
+struct BatchScope {
+    mis2_ctx *ctx;
+    ~BatchScope() { ctx->batch = BatchInfo{}; }
+};
+
 }  // namespace
+
+namespace mis2 {
+
+size_t batch_bytes(int32_t G, int64_t n, int64_t nnz) {
+    const size_t ug = (size_t)G + 1;
+    return coarsen_bytes(n, nnz) + align_up(4 * (size_t)n) + 3 * align_up(8 * ug) +
+           3 * align_up(4 * ug) + 2 * align_up(ug);
+}
+
+BatchArena carve_batch_arena(void *base, int32_t G, int64_t n, int64_t nnz) {
+    BatchArena a;
+    a.head = workspace_bytes(n, MIS2_OP_COARSEN);
+    char *p = (char *)base + a.head;
+    auto take = [&](size_t sz) {
+        char *r = p;
+        p += align_up(sz);
+        return (void *)r;
+    };
+    for (int i = 0; i < 2; i++) {
+        a.crow[i] = (int64_t *)take(8 * ((size_t)n + 1));
+        a.ccol[i] = (int32_t *)take(4 * (size_t)nnz);
+    }
+    const size_t ug = (size_t)G + 1;
+    a.map = (int32_t *)take(4 * (size_t)n);
+    a.voff = (int64_t *)take(8 * ug);
+    a.newoff = (int64_t *)take(8 * ug);
+    a.bnd = (int64_t *)take(8 * ug);
+    a.gb = (uint32_t *)take(4 * ug);
+    a.P1 = (uint32_t *)take(4 * ug);
+    a.P2 = (uint32_t *)take(4 * ug);
+    a.cont = (uint8_t *)take(ug);
+    a.live = (uint8_t *)take(ug);
+    return a;
+}
+
+int batch_level(mis2_ctx *ctx, const mis2_graph &cur, uint64_t seed, int64_t stop_below,
+                int32_t *agg_dst, const BatchArena &ar, int64_t *crow_next, int32_t *ccol_next,
+                BatchLevel *bl, hipStream_t s) {
+    int rc;
+    const int32_t cg = (int32_t)bl->voff.size() - 1;
+    std::vector<uint32_t> gb(cg);
+    for (int32_t i = 0; i < cg; i++) gb[i] = (uint32_t)id_bits(bl->voff[i + 1] - bl->voff[i]);
+    HIP_TRY(ctx, hipMemcpyAsync(ar.voff, bl->voff.data(), 8 * ((size_t)cg + 1),
+                                hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ar.gb, gb.data(), 4 * (size_t)cg, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, launch_gather_i64(cur.row_ptr, ar.voff, (int64_t)cg + 1, ar.bnd, s));
+    BatchInfo bt;
+    bt.voff = ar.voff;
+    bt.gb = ar.gb;
+    bt.G = cg;
+    while ((int64_t{1} << bt.steps) < (int64_t)cg + 1) bt.steps++;
+    BatchScope scope{ctx};
+    ctx->batch = bt;
+
+    Workspace ws;
+    if (!carve(ctx->ws, ar.head, cur.n, MIS2_OP_COARSEN, &ws))
+        return fail(ctx, MIS2_ENOSPACE, "workspace carve failed");
+    int64_t na_all = 0;
+    if ((rc = aggregate_impl(ctx, &cur, seed, agg_dst, &na_all, nullptr, ws, s, ar.P1, ar.P2)))
+        return rc;
+    std::vector<uint32_t> P1(cg + 1), P2(cg + 1);
+    std::vector<int64_t> bnd(cg + 1);
+    HIP_TRY(ctx, hipMemcpyAsync(P1.data(), ar.P1, 4 * ((size_t)cg + 1), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(P2.data(), ar.P2, 4 * ((size_t)cg + 1), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(bnd.data(), ar.bnd, 8 * ((size_t)cg + 1), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+
+    bl->nagg.assign(cg, 0);
+    bl->nnz.assign(cg, 0);
+    bl->cont.assign(cg, 0);
+    std::vector<int64_t> newoff(cg + 1, 0);
+    bl->next_voff.assign(1, 0);
+    for (int32_t i = 0; i < cg; i++) {
+        const int64_t ni = bl->voff[i + 1] - bl->voff[i];
+        const int64_t na = (int64_t)(P1[i + 1] - P1[i]) + (int64_t)(P2[i + 1] - P2[i]);
+        bl->nagg[i] = na;
+        bl->nnz[i] = bnd[i + 1] - bnd[i];
+        bl->cont[i] = bl->live[i] && bl->allow[i] && na != ni && na > 0 && na >= stop_below;
+        newoff[i + 1] = newoff[i] + (bl->cont[i] ? na : 0);
+        if (bl->cont[i]) bl->next_voff.push_back(newoff[i + 1]);
+    }
+    const int64_t n_next = newoff[cg];
+    HIP_TRY(ctx, hipMemcpyAsync(ar.cont, bl->cont.data(), (size_t)cg, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ar.live, bl->live.data(), (size_t)cg, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ar.newoff, newoff.data(), 8 * ((size_t)cg + 1),
+                                hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, launch_batch_local(cur.n, bt, ar.P1, ar.P2, agg_dst, ar.live, ar.cont, ar.newoff,
+                                    n_next > 0 ? ar.map : nullptr, s));
+    bl->n_next = n_next;
+    bl->nnz_next = 0;
+    if (n_next > 0) {
+        QuotientWs q{ws.q.cnt, ws.q.moff, ws.q.members, ws.q.part};
+        HIP_TRY(ctx, quotient_graph(cur.row_ptr, cur.col, cur.n, ar.map, n_next, crow_next,
+                                    ccol_next, q, s));
+        HIP_TRY(ctx, hipMemcpyAsync(&ctx->pinned[0], crow_next + n_next, sizeof(int64_t),
+                                    hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (n_next > 0) memcpy(&bl->nnz_next, ctx->pinned, sizeof(int64_t));
+    return MIS2_OK;
+}
+
+}  // namespace mis2
 
 extern "C" {
 
@@ -792,6 +919,93 @@ int mis2_coarsen(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int64_t stop
         cur.nnz = cnnz;
         cur.row_ptr = crow[lv & 1];
         cur.col = ccol[lv & 1];
+    }
+    return MIS2_OK;
+}
+
+int mis2_batch_workspace_bytes(int32_t n_graphs, int64_t n, int64_t nnz, size_t *bytes) {
+    if (!bytes || n_graphs < 0 || n < 0 || nnz < 0) return MIS2_EINVAL;
+    *bytes = batch_bytes(n_graphs, n, nnz);
+    return MIS2_OK;
+}
+
+int mis2_aggregate_batched(mis2_ctx *ctx, const mis2_graph *g, int32_t n_graphs,
+                           const int64_t *vtx_off, uint64_t seed, int64_t stop_below,
+                           int32_t max_levels, int32_t *agg_out, int64_t agg_cap,
+                           int64_t *level_n, int64_t *level_nnz, int64_t *level_nagg,
+                           int32_t *n_levels, void *stream) {
+    int rc = check_graph_args(ctx, g);
+    if (rc) return rc;
+    const int32_t G = n_graphs;
+    if (G < 0 || !vtx_off || max_levels < 0 || agg_cap < 0 || (G > 0 && !n_levels) ||
+        (G > 0 && max_levels > 0 && (!level_n || !level_nnz || !level_nagg)))
+        return fail(ctx, MIS2_EINVAL, "bad batched coarsening arguments");
+    if (vtx_off[0] != 0 || vtx_off[G] != g->n)
+        return fail(ctx, MIS2_EINVAL, "vtx_off must run from 0 to n");
+    for (int32_t i = 0; i < G; i++)
+        if (vtx_off[i + 1] < vtx_off[i]) return fail(ctx, MIS2_EINVAL, "vtx_off decreases at %d", i);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    for (int32_t i = 0; i < G; i++) n_levels[i] = 0;
+    for (int64_t i = 0; i < (int64_t)G * max_levels; i++) level_n[i] = level_nnz[i] = level_nagg[i] = 0;
+    if (G == 0 || g->n == 0 || max_levels == 0) return MIS2_OK;
+    const size_t need = batch_bytes(G, g->n, g->nnz);
+    if (!ctx->ws || ctx->ws_bytes < need)
+        return fail(ctx, MIS2_ENOSPACE, "batched workspace of %zu bytes needed, %zu set", need,
+                    ctx->ws ? ctx->ws_bytes : (size_t)0);
+    const BatchArena ar = carve_batch_arena(ctx->ws, G, g->n, g->nnz);
+    {
+        Workspace ws;
+        if (!carve(ctx->ws, ar.head, g->n, MIS2_OP_COARSEN, &ws))
+            return fail(ctx, MIS2_ENOSPACE, "workspace carve failed");
+        if ((rc = maybe_validate(ctx, g, ws, s))) return rc;
+    }
+
+    // graphs of the current union: their ids in the call and vertex offsets
+    BatchLevel bl;
+    std::vector<int32_t> ids(G);
+    bl.voff.assign(vtx_off, vtx_off + G + 1);
+    bl.live.resize(G);
+    bl.allow.resize(G);
+    for (int32_t i = 0; i < G; i++) {
+        ids[i] = i;
+        const int64_t ni = bl.voff[i + 1] - bl.voff[i];
+        bl.live[i] = ni > 0 && ni >= stop_below;
+    }
+    if (std::find(bl.live.begin(), bl.live.end(), 1) == bl.live.end()) return MIS2_OK;
+    mis2_graph cur = *g;
+    int64_t off = 0;
+    for (int32_t lv = 0; lv < max_levels; lv++) {
+        const int32_t cg = (int32_t)ids.size();
+        if (off + cur.n > agg_cap)
+            return fail(ctx, MIS2_ENOSPACE, "agg_cap %lld too small for level %d",
+                        (long long)agg_cap, lv);
+        for (int32_t i = 0; i < cg; i++) bl.allow[i] = lv + 1 < max_levels;
+        const int nx = (lv + 1) & 1;
+        if ((rc = batch_level(ctx, cur, seed, stop_below, agg_out + off, ar, ar.crow[nx],
+                              ar.ccol[nx], &bl, s)))
+            return rc;
+        std::vector<int32_t> next_ids;
+        for (int32_t i = 0; i < cg; i++) {
+            if (bl.live[i]) {
+                const int64_t k = (int64_t)lv * G + ids[i];
+                level_n[k] = bl.voff[i + 1] - bl.voff[i];
+                level_nnz[k] = bl.nnz[i];
+                level_nagg[k] = bl.nagg[i];
+                n_levels[ids[i]] = lv + 1;
+            }
+            if (bl.cont[i]) next_ids.push_back(ids[i]);
+        }
+        off += cur.n;
+        if (next_ids.empty()) break;
+        ids = next_ids;
+        bl.voff = bl.next_voff;
+        bl.live.assign(ids.size(), 1);
+        bl.allow.resize(ids.size());
+        cur.n = bl.n_next;
+        cur.nnz = bl.nnz_next;
+        cur.row_ptr = ar.crow[nx];
+        cur.col = ar.ccol[nx];
     }
     return MIS2_OK;
 }

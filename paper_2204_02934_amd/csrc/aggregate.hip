@@ -200,11 +200,57 @@ __device__ __forceinline__ bool better(int c1, int s1, int a1, int c2, int s2, i
 
 constexpr int32_t kPad = -2;  // label of a padding lane; never equals an aggregate id
 
-// One group of L lanes per unaggregated row of the wavefront's segment.
-// Lane j of chunk c1 holds the tent label of neighbour c1*L + j; its
-// coupling is the number of equal labels over all chunks of the row, counted
-// with in-group broadcasts.  The group's best candidate is then reduced with
-// the candidate order above.
+// Short rows: lane j of the group holds the tent labels of neighbours
+// k*L + j for k < K, all loaded before any is used.  Every lane broadcasts
+// its K labels to the group once; each lane counts, for each of its own
+// labels, the equal ones among all L*K (its coupling), and keeps its best
+// candidate in the order above.
+template <int L, int K>
+__device__ __forceinline__ void p3_short(const int32_t *__restrict__ col,
+                                         const int32_t *__restrict__ label,
+                                         const int32_t *__restrict__ aggsize, int64_t s, int64_t e,
+                                         int sub, int &bc, int &bs, int &ba) {
+    int32_t x[K], a[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int64_t j = s + k * L + sub;
+        x[k] = col[j < e ? j : 0];
+    }
+#pragma unroll
+    for (int k = 0; k < K; k++) a[k] = label[x[k]];
+#pragma unroll
+    for (int k = 0; k < K; k++)
+        if (s + k * L + sub >= e) a[k] = kPad;
+    int cnt[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) cnt[k] = 0;
+#pragma unroll
+    for (int t = 0; t < L; t++) {
+#pragma unroll
+        for (int k2 = 0; k2 < K; k2++) {
+            const int32_t b = __shfl(a[k2], t, L);
+#pragma unroll
+            for (int k = 0; k < K; k++) cnt[k] += (b == a[k]);
+        }
+    }
+    int sz[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) sz[k] = aggsize[a[k] >= 0 ? a[k] : 0];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        if (a[k] >= 0 && better(cnt[k], sz[k], a[k], bc, bs, ba)) {
+            bc = cnt[k];
+            bs = sz[k];
+            ba = a[k];
+        }
+    }
+}
+
+// One group of L lanes per unaggregated row of the wavefront's segment.  A
+// wavefront whose rows all fit K chunks of L takes p3_short; otherwise lane
+// j of chunk c1 holds the tent label of neighbour c1*L + j and its coupling
+// is counted over all chunks of the row with in-group broadcasts.  The
+// group's best candidate is then reduced with the candidate order above.
 template <int L>
 __global__ __launch_bounds__(kBlock) void k_phase3(const int64_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col,
@@ -212,6 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_phase3(const int64_t *__restrict__ r
                                                    const int32_t *__restrict__ aggsize,
                                                    SegIO io, int32_t *__restrict__ agg_out,
                                                    uint32_t *__restrict__ err) {
+    constexpr int K = L >= 32 ? 1 : (32 / L > 8 ? 8 : 32 / L);
     const int64_t w = wave_id();
     if (w >= io.S) return;
     const int64_t count = io.cnt_in[w];
@@ -234,23 +281,27 @@ __global__ __launch_bounds__(kBlock) void k_phase3(const int64_t *__restrict__ r
         int64_t wmax = chunks;
         for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off, 64));
         int bc = 0, bs = 0x7FFFFFFF, ba = 0x7FFFFFFF;
-        for (int64_t c1 = 0; c1 < wmax; c1++) {
-            const int64_t j = s + c1 * L + sub;
-            const int32_t a = (c1 < chunks && j < e) ? label[col[j]] : kPad;
-            int cnt = 0;
-            for (int64_t c2 = 0; c2 < wmax; c2++) {
-                const int64_t j2 = s + c2 * L + sub;
-                const int32_t a2 =
-                    c2 == c1 ? a : ((c2 < chunks && j2 < e) ? label[col[j2]] : kPad);
+        if (wmax > 0 && wmax <= K) {
+            p3_short<L, K>(col, label, aggsize, s, e, sub, bc, bs, ba);
+        } else {
+            for (int64_t c1 = 0; c1 < wmax; c1++) {
+                const int64_t j = s + c1 * L + sub;
+                const int32_t a = (c1 < chunks && j < e) ? label[col[j]] : kPad;
+                int cnt = 0;
+                for (int64_t c2 = 0; c2 < wmax; c2++) {
+                    const int64_t j2 = s + c2 * L + sub;
+                    const int32_t a2 =
+                        c2 == c1 ? a : ((c2 < chunks && j2 < e) ? label[col[j2]] : kPad);
 #pragma unroll
-                for (int t = 0; t < L; t++) cnt += (__shfl(a2, t, L) == a);
-            }
-            if (a >= 0) {
-                const int sz = aggsize[a];
-                if (better(cnt, sz, a, bc, bs, ba)) {
-                    bc = cnt;
-                    bs = sz;
-                    ba = a;
+                    for (int t = 0; t < L; t++) cnt += (__shfl(a2, t, L) == a);
+                }
+                if (a >= 0) {
+                    const int sz = aggsize[a];
+                    if (better(cnt, sz, a, bc, bs, ba)) {
+                        bc = cnt;
+                        bs = sz;
+                        ba = a;
+                    }
                 }
             }
         }

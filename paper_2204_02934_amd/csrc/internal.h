@@ -97,7 +97,7 @@ enum Scalar {
     kS_Err = 5,     // error bits
 };
 
-constexpr int kMaxBlocks = 2048;              // most workgroups of a sweep grid
+constexpr int kMaxBlocks = 8192;              // most workgroups of a sweep grid
 constexpr int kMaxWaves = kMaxBlocks * (kBlock / 64);
 
 // The caller's workspace, carved into arrays (all 256-byte aligned).
@@ -134,7 +134,7 @@ bool carve(void *base, size_t bytes, int64_t n, int op, Workspace *ws);
 struct Plan {
     int lanes = 0;       // lanes per CSR row (power of two <= 64); 0 = automatic
     int blocks = 0;      // workgroups per sweep (<= kMaxBlocks); 0 = automatic
-    int persistent = 1;  // 1: one cooperative launch per MIS-2 run; 0: two launches per round
+    int persistent = 0;  // 1: one cooperative launch per MIS-2 run; 0: two launches per round
 };
 
 // One sweep's worklists.  Wavefront w owns slots [w*seg, w*seg + cnt[w]) of
@@ -228,6 +228,16 @@ hipError_t quotient_graph(const int64_t *row_ptr, const int32_t *col, int64_t n,
                           int64_t n_agg, int64_t *crow, int32_t *ccol, const QuotientWs &q,
                           hipStream_t s);
 
+// batch.hip: graph-local numbering of a union's aggregates.
+hipError_t launch_graph_bounds(const int32_t *list, const uint32_t *d_count, const int64_t *voff,
+                               int32_t G, uint32_t *P, hipStream_t s);
+hipError_t launch_batch_local(int64_t n, const BatchInfo &bt, const uint32_t *P1,
+                              const uint32_t *P2, int32_t *agg, const uint8_t *live,
+                              const uint8_t *cont, const int64_t *newoff, int32_t *map,
+                              hipStream_t s);
+hipError_t launch_gather_i64(const int64_t *src, const int64_t *idx, int64_t count, int64_t *out,
+                             hipStream_t s);
+
 // aggregate.hip
 hipError_t launch_label_roots(int64_t n, const int64_t *row_ptr, const int32_t *col,
                               const int32_t *roots, const uint32_t *d_count,
@@ -243,6 +253,43 @@ hipError_t launch_phase3(int lanes, int blocks, const int64_t *row_ptr, const in
                          const int32_t *label, const int32_t *aggsize, const SegIO &io,
                          int32_t *agg_out, uint32_t *err, hipStream_t s);
 
+// Batched coarsening (abi.hip).  The arena is the caller's workspace: the
+// coarsening workspace of the union, two coarse-union CSR buffers, the
+// coarse-id map and the per-graph tables.
+struct BatchArena {
+    size_t head;           // bytes of the coarsening workspace at the start
+    int64_t *crow[2];      // [n + 1]
+    int32_t *ccol[2];      // [nnz]
+    int32_t *map;          // [n]
+    int64_t *voff, *newoff, *bnd;  // [G + 1]
+    uint32_t *gb, *P1, *P2;        // [G + 1]
+    uint8_t *cont, *live;          // [G + 1]
+};
+size_t batch_bytes(int32_t G, int64_t n, int64_t nnz);
+BatchArena carve_batch_arena(void *base, int32_t G, int64_t n, int64_t nnz);
+
+// One level of a union of graphs.  In: voff (the graphs' vertex offsets in
+// the union), live (graph takes part: its labels are kept), allow (graph may
+// go on to another level).  Out: per-graph aggregate counts and stored
+// entries, cont (graph goes on), and the coarse union of the graphs that go
+// on (next_voff, n_next, nnz_next) in crow_next / ccol_next.  agg_dst gets
+// graph-local labels (-1 for graphs that are not live).
+struct BatchLevel {
+    std::vector<int64_t> voff;
+    std::vector<uint8_t> live, allow;
+    std::vector<int64_t> nagg, nnz;
+    std::vector<uint8_t> cont;
+    std::vector<int64_t> next_voff;
+    int64_t n_next = 0, nnz_next = 0;
+};
+
+}  // namespace mis2
+
+struct mis2_ctx;
+namespace mis2 {
+int batch_level(mis2_ctx *ctx, const mis2_graph &cur, uint64_t seed, int64_t stop_below,
+                int32_t *agg_dst, const BatchArena &ar, int64_t *crow_next, int32_t *ccol_next,
+                BatchLevel *bl, hipStream_t s);
 }  // namespace mis2
 
 // Context (abi.hip).
@@ -257,6 +304,7 @@ struct mis2_ctx {
     int profile = 0;
     int account = 0;
     mis2::Plan plan;
+    mis2::BatchInfo batch;  // graphs of the union being processed (batched calls only)
     std::vector<int64_t> trace[2];  // per-round |wl1|, |wl2| of the last run(s)
     std::vector<mis2_sweep_record> sweeps;  // launches of the last call
     std::vector<float> stamp_ms[2];         // persistent kernel: per-round sweep times

@@ -5,6 +5,9 @@
 // aggregates, and a is adjacent to c iff some edge (u, w) has agg u = a,
 // agg w = c and a != c.  Rows come out with ascending, distinct columns.
 //
+// A vertex with agg < 0 belongs to no coarse vertex (a batched run uses this
+// for graphs that stop coarsening) and edges to it are dropped.
+//
 // Member lists are built by a counting sort (their order does not matter:
 // every coarse row is a sorted set).  One workgroup then handles one coarse
 // row: it gathers the aggregate ids of its members' neighbours into LDS and
@@ -26,8 +29,10 @@ constexpr int kWaves = kBlock / 64;
 __global__ __launch_bounds__(kBlock) void k_member_count(int64_t n, const int32_t *__restrict__ agg,
                                                          uint32_t *__restrict__ cnt) {
     for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * kBlock)
-        atomicAdd(&cnt[agg[v]], 1u);
+         v += (int64_t)gridDim.x * kBlock) {
+        const int32_t a = agg[v];
+        if (a >= 0) atomicAdd(&cnt[a], 1u);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_member_scatter(int64_t n, const int32_t *__restrict__ agg,
@@ -37,6 +42,7 @@ __global__ __launch_bounds__(kBlock) void k_member_scatter(int64_t n, const int3
     for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * kBlock) {
         const int32_t a = agg[v];
+        if (a < 0) continue;
         const uint32_t pos = atomicAdd(&cursor[a], 1u);
         members[moff[a] + pos] = (int32_t)v;
     }
@@ -109,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows(const int64_t *__restric
                 const int32_t v = members[i];
                 for (int64_t j = row_ptr[v], e = row_ptr[v + 1]; j < e; j++) {
                     const int32_t c = agg[col[j]];
-                    if ((int64_t)c != a) buf[atomicAdd(&fill_s, 1u)] = (uint32_t)c;
+                    if (c >= 0 && (int64_t)c != a) buf[atomicAdd(&fill_s, 1u)] = (uint32_t)c;
                 }
             }
             __syncthreads();

@@ -85,7 +85,7 @@ def test_mis2_parity_seeds(ctx, seed):
 
 @pytest.mark.parametrize("lanes", [-1, 1, 2, 4, 8, 16, 32, 64])
 def test_mis2_every_lane_plan(api, lanes):
-    for blocks in (1, 13, 0):
+    for blocks in (1, 13, 0, 8192):
         for persistent in (True, False):
             c = api.Context(0, lanes=lanes, blocks=blocks, persistent=persistent)
             for name in ("grid27_ragged", "chunglu_50k", "star70"):
