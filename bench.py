@@ -49,6 +49,37 @@ def workload(name):
     raise SystemExit("unknown workload " + name)
 
 
+def kernel_sources_digest():
+    """SHA-256 over the HIP sources and headers the sweeps are built from, so a
+    stored hardware-counter measurement is used only for the code it measured."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2204_02934_amd", "csrc", "*.hip")) +
+                   glob.glob(os.path.join(ROOT, "paper_2204_02934_amd", "csrc", "*.h")))
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from profiles/traffic_<workload>.json
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE runs of this bench, scaled by the
+    same counters on a plain device copy of known size), or None when there is
+    no such measurement for the current sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("sources_sha256") != kernel_sources_digest():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
 def sweep_bytes(rec, identity):
     """Algorithmic bytes of one sweep launch: column indices of the visited
     rows, per-row terms (row extents 8, worklist entry 4 unless the list is
@@ -377,7 +408,8 @@ def main():
                    "step": "mis2_run + mis2_aggregate, graph resident in HBM",
                    "index_types": "int64 row offsets, int32 columns"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": measured_traffic(args.workload, dom),
                      "kernel": dom, "launches_per_step": d["launches"],
                      "bytes_per_launch": d["bytes"] / d["launches"],
                      "mean_launch_ms": d["ms"] / d["launches"]},

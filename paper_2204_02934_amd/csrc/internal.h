@@ -23,15 +23,21 @@ constexpr int kBlock = 256;       // threads per workgroup (4 wave64s)
 constexpr int kTraceCap = 4096;   // most rounds of one MIS-2 run
 constexpr int kRing = 4;          // per-round counter slots, slot = round % kRing
 constexpr int kScalars = 64;      // misc device scalars
-constexpr int kTraceSplit = 8;    // per-round size counters, one per XCD
-// Round table: row r holds the size of worklist1 (entries 0..7, summed) and
-// worklist2 (8..15) at the start of round r, and at entry 16 a flag that is
-// non-zero iff worklist1 is non-empty there.
-constexpr int kRoundStride = 32;
-constexpr int kRtAlive = 16;
-// Persistent kernel only: device wall-clock stamps (two words each) taken by
-// workgroup 0 at the start of round r and after its two grid barriers.
-constexpr int kRtStamp0 = 18, kRtStamp1 = 20, kRtStamp2 = 22;
+// Round table: row r holds the size of worklist1 (word 0) and worklist2
+// (word 1) at the start of round r and, for the persistent kernel, device
+// wall-clock stamps (two words each) taken by workgroup 0 at the start of
+// round r and after its two grid barriers.
+constexpr int kRoundStride = 8;
+constexpr int kRtStamp0 = 2, kRtStamp1 = 4, kRtStamp2 = 6;
+// Size counters.  The sweeps of round r add each workgroup's kept count to
+// one of kSplit counters per list, each in its own 128-byte line (atomics on
+// one line serialise across the whole chip), in ring slot (r + 1) % kRing.
+// A slot holds worklist1's counters, then worklist2's.
+constexpr int kSplit = 64;
+constexpr int kCtrLine = 32;                     // words per counter (one cache line)
+constexpr int kCtrList = kSplit * kCtrLine;      // words per list of a slot
+constexpr int kCtrSlot = 2 * kCtrList;           // words per slot
+constexpr int kCtrRing = 4;                      // slots
 
 // Section V-A: f = xorshift64* (Vigna's parameters 12, 25, 27 and multiplier
 // 2685821657736338717, arithmetic mod 2^64); h(i, v) = f(f(i) ^ f(v)).
@@ -109,6 +115,7 @@ struct Workspace {
     uint32_t *cnt1[2] = {};       // [kMaxWaves] per-wave sizes of wl1[i]
     uint32_t *cnt2[2] = {};       // [kMaxWaves] per-wave sizes of wl2[i]
     uint32_t *rt = nullptr;       // [kTraceCap + 2][kRoundStride] round table
+    uint32_t *ctr = nullptr;      // [kCtrRing][kCtrSlot] size counters
     uint32_t *scalars = nullptr;  // [kScalars]
     unsigned long long *degs = nullptr;  // [2][kTraceCap][2] row-length sums per sweep
     uint32_t *blocksum = nullptr; // [compact_blocks(n) + 1]
@@ -139,19 +146,22 @@ struct Plan {
 
 // One sweep's worklists.  Wavefront w owns slots [w*seg, w*seg + cnt[w]) of
 // each list.  cnt_in == nullptr means the identity lists (w's whole vertex
-// range).  trace_out (may be null) points at kTraceSplit counters whose sum
-// becomes the output size; alive_out (may be null) is set to 1 by
-// wavefronts that keep a row; round_zero (may be null) is a round-table row
-// cleared for a later round; deg_sum (may be null) accumulates the visited
-// CSR row lengths.
+// range).  trace_out (may be null) points at the kSplit counters (stride
+// kCtrLine) whose sum becomes the output size; ctr_zero (may be null) is a
+// counter slot that workgroup 0 clears for a later round; sum_in / rt_row
+// (may be null): workgroup 0 sums the counter slot sum_in into the
+// round-table row rt_row (worklist1's sum for both lists if sum_same);
+// deg_sum (may be null) accumulates the visited CSR row lengths.
 struct SegIO {
     const int32_t *wl_in;
     const uint32_t *cnt_in;
     int32_t *wl_out;
     uint32_t *cnt_out;
     uint32_t *trace_out;
-    uint32_t *alive_out;
-    uint32_t *round_zero;  // may be null: kRoundStride entries the sweep clears
+    uint32_t *ctr_zero;
+    const uint32_t *sum_in;
+    uint32_t *rt_row;
+    int sum_same;
     unsigned long long *deg_sum;
     int64_t n;
     int64_t seg;
@@ -170,6 +180,7 @@ struct RoundsArgs {
     uint32_t *cnt1[2];
     uint32_t *cnt2[2];
     uint32_t *rt;
+    uint32_t *ctr;
     unsigned long long *degs;  // [kTraceCap][2] or null
     uint32_t *bar;
     int64_t n, seg, S;
@@ -299,6 +310,7 @@ struct mis2_ctx {
     void *ws = nullptr;
     size_t ws_bytes = 0;
     uint32_t *pinned = nullptr;  // host-pinned scalars for read-back
+    uint32_t *pinned_ctr = nullptr;  // host-pinned [2][kCtrList]: worklist1 counters per chunk
     std::string err;
     int validate = 0;
     int profile = 0;

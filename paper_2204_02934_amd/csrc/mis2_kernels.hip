@@ -87,14 +87,13 @@ __device__ __forceinline__ void seg_append(const SegIO &io, const Seg &sg, bool 
     kept += (uint32_t)__popcll(mask);
 }
 
-// Ends a sweep: the wavefront's count, the alive flag, and the workgroup's
-// total added to one of 8 trace counters (spread so that same-address
-// atomics do not serialise the whole grid).  All threads must call it.
+// Ends a sweep: the wavefront's count, and the workgroup's total added to one
+// of kSplit size counters, each on its own cache line (one shared word or
+// line would serialise thousands of workgroups).  All threads must call it.
 __device__ __forceinline__ void seg_finish(const SegIO &io, int64_t w, uint32_t kept) {
     __shared__ uint32_t part[kBlock / 64];
     if ((threadIdx.x & 63u) == 0) {
         if (w < io.S) io.cnt_out[w] = kept;
-        if (kept && io.alive_out) *io.alive_out = 1u;
         part[threadIdx.x >> 6] = kept;
     }
     if (!io.trace_out) return;
@@ -102,7 +101,31 @@ __device__ __forceinline__ void seg_finish(const SegIO &io, int64_t w, uint32_t 
     if (threadIdx.x == 0) {
         uint32_t t = 0;
         for (int k = 0; k < kBlock / 64; k++) t += part[k];
-        if (t) atomicAdd(&io.trace_out[blockIdx.x % kTraceSplit], t);
+        if (t) atomicAdd(&io.trace_out[(blockIdx.x % kSplit) * kCtrLine], t);
+    }
+}
+
+// Sum of the kSplit counters of one list (wavefront 0 of the workgroup; the
+// result is in every lane of that wavefront).
+__device__ __forceinline__ uint32_t ctr_sum(const uint32_t *list) {
+    uint32_t x = list[(threadIdx.x & 63u) * kCtrLine];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Workgroup 0's round bookkeeping at the start of a Refresh Column sweep:
+// clear a counter slot for a later round, and record this round's sizes.
+__device__ __forceinline__ void round_books(const SegIO &io) {
+    if (blockIdx.x != 0) return;
+    if (io.ctr_zero && threadIdx.x < 2 * kSplit)
+        io.ctr_zero[(threadIdx.x / kSplit) * kCtrList + (threadIdx.x % kSplit) * kCtrLine] = 0u;
+    if (io.sum_in && threadIdx.x < 64) {
+        const uint32_t a = ctr_sum(io.sum_in);
+        const uint32_t b = io.sum_same ? a : ctr_sum(io.sum_in + kCtrList);
+        if (threadIdx.x == 0) {
+            io.rt_row[0] = a;
+            io.rt_row[1] = b;
+        }
     }
 }
 
@@ -686,8 +709,7 @@ __global__ __launch_bounds__(kBlock) void k_refresh_column(const int64_t *__rest
                                                            const uint32_t *__restrict__ T,
                                                            uint32_t *__restrict__ M, SegIO io) {
     const int64_t w = wave_id();
-    if (blockIdx.x == 0 && threadIdx.x < kRoundStride && io.round_zero)
-        io.round_zero[threadIdx.x] = 0u;
+    round_books(io);
     const Seg sg = seg_of(io, w);
     const uint32_t kept = any_column<L>(row_ptr, col, T, M, io, sg);
     seg_finish(io, w, kept);
@@ -777,28 +799,38 @@ __global__ __launch_bounds__(kBlock) void k_rounds(const int64_t *__restrict__ r
                                                    const int32_t *__restrict__ col,
                                                    uint32_t *__restrict__ T,
                                                    uint32_t *__restrict__ M, RoundsArgs a) {
+    __shared__ uint32_t alive_s;
     const int64_t w = wave_id();
     uint32_t *flags = a.bar;
     uint32_t *gen = a.bar + kMaxBlocks;
     uint32_t *abort_word = a.bar + kMaxBlocks + 16;
     uint32_t epoch = 0;
     int r = 0;
+    // round 0 sizes: the masked start's counters (slot 0); the host wrote
+    // them for the identity start
+    if (blockIdx.x == 0 && threadIdx.x < 64 && a.masked) {
+        const uint32_t c = ctr_sum(a.ctr);
+        if (threadIdx.x == 0) {
+            a.rt[0] = c;
+            a.rt[1] = c;
+        }
+    }
     for (;;) {
         const int cur = r & 1, nxt = cur ^ 1;
         const bool first = (r == 0);
-        uint32_t *row_next = a.rt + (size_t)(r + 1) * kRoundStride;
-        SegIO cio{first ? (a.masked ? a.wl1[0] : nullptr) : a.wl2[cur],
-                  first ? (a.masked ? a.cnt1[0] : nullptr) : a.cnt2[cur],
-                  a.wl2[nxt],
-                  a.cnt2[nxt],
-                  row_next + kTraceSplit,
-                  nullptr,
-                  row_next + kRoundStride,
-                  a.degs ? a.degs + 2 * r + 1 : nullptr,
-                  a.n,
-                  a.seg,
-                  a.S};
-        if (blockIdx.x == 0 && threadIdx.x < kRoundStride) cio.round_zero[threadIdx.x] = 0u;
+        uint32_t *slot_next = a.ctr + (size_t)((r + 1) % kCtrRing) * kCtrSlot;
+        SegIO cio{};
+        cio.wl_in = first ? (a.masked ? a.wl1[0] : nullptr) : a.wl2[cur];
+        cio.cnt_in = first ? (a.masked ? a.cnt1[0] : nullptr) : a.cnt2[cur];
+        cio.wl_out = a.wl2[nxt];
+        cio.cnt_out = a.cnt2[nxt];
+        cio.trace_out = slot_next + kCtrList;
+        cio.ctr_zero = a.ctr + (size_t)((r + 2) % kCtrRing) * kCtrSlot;
+        cio.deg_sum = a.degs ? a.degs + 2 * r + 1 : nullptr;
+        cio.n = a.n;
+        cio.seg = a.seg;
+        cio.S = a.S;
+        round_books(cio);
         uint32_t *row_cur = a.rt + (size_t)r * kRoundStride;
         if (blockIdx.x == 0 && threadIdx.x == 0) stamp(row_cur + kRtStamp0);
         Seg sg = seg_of(cio, w);
@@ -806,17 +838,16 @@ __global__ __launch_bounds__(kBlock) void k_rounds(const int64_t *__restrict__ r
         seg_finish(cio, w, kept);
         if (!grid_barrier(flags, gen, abort_word, ++epoch)) break;
         if (blockIdx.x == 0 && threadIdx.x == 0) stamp(row_cur + kRtStamp1);
-        SegIO dio{first ? (a.masked ? a.wl1[0] : nullptr) : a.wl1[cur],
-                  first ? (a.masked ? a.cnt1[0] : nullptr) : a.cnt1[cur],
-                  a.wl1[nxt],
-                  a.cnt1[nxt],
-                  row_next,
-                  row_next + kRtAlive,
-                  nullptr,
-                  a.degs ? a.degs + 2 * r : nullptr,
-                  a.n,
-                  a.seg,
-                  a.S};
+        SegIO dio{};
+        dio.wl_in = first ? (a.masked ? a.wl1[0] : nullptr) : a.wl1[cur];
+        dio.cnt_in = first ? (a.masked ? a.cnt1[0] : nullptr) : a.cnt1[cur];
+        dio.wl_out = a.wl1[nxt];
+        dio.cnt_out = a.cnt1[nxt];
+        dio.trace_out = slot_next;
+        dio.deg_sum = a.degs ? a.degs + 2 * r : nullptr;
+        dio.n = a.n;
+        dio.seg = a.seg;
+        dio.S = a.S;
         const TupleParams next{xs64star((a.seed << 32) ^ (uint64_t)(r + 1)), a.pmask, a.b, a.batch};
         sg = seg_of(dio, w);
         kept = any_decide<L>(row_ptr, col, T, M, next, dio, sg);
@@ -824,7 +855,22 @@ __global__ __launch_bounds__(kBlock) void k_rounds(const int64_t *__restrict__ r
         if (!grid_barrier(flags, gen, abort_word, ++epoch)) break;
         if (blockIdx.x == 0 && threadIdx.x == 0) stamp(row_cur + kRtStamp2);
         r++;
-        if (ld_agent(row_next + kRtAlive) == 0u || r + 2 >= a.max_rounds) break;
+        // sizes at the start of round r; every workgroup needs worklist1's
+        if (threadIdx.x < 64) {
+            const uint32_t c1 = ctr_sum(slot_next);
+            const uint32_t c2 = ctr_sum(slot_next + kCtrList);
+            if (threadIdx.x == 0) {
+                alive_s = c1;
+                if (blockIdx.x == 0) {
+                    a.rt[(size_t)r * kRoundStride] = c1;
+                    a.rt[(size_t)r * kRoundStride + 1] = c2;
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t alive = alive_s;
+        __syncthreads();
+        if (alive == 0u || r + 2 >= a.max_rounds) break;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) st_agent(a.bar + kMaxBlocks + 32, (uint32_t)r);
 }
