@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 
 #include "internal.h"
 
@@ -138,15 +139,21 @@ Geometry geometry(const mis2_ctx *ctx, int64_t n, int lanes) {
 }
 
 // Per-round sizes as recorded by the sweeps in the round table (rows
-// 0..rounds-1); the first round with an empty worklist1 ends the run.
-int read_trace(mis2_ctx *ctx, const mis2_graph *g, const Workspace &ws, bool masked, int phase,
-               int rounds, hipStream_t s, int32_t *iters_out) {
-    std::vector<uint32_t> rt((size_t)rounds * kRoundStride);
-    if (rounds > 0) {
-        HIP_TRY(ctx, hipMemcpyAsync(rt.data(), ws.rt, rt.size() * sizeof(uint32_t),
+// 0..rounds-1): queue_trace copies them to pinned memory on the stream; after
+// the call's final synchronisation parse_trace turns them into ctx->trace and
+// the round count (the first round with an empty worklist1 ends the run).
+int queue_trace(mis2_ctx *ctx, const Workspace &ws, int phase, int rounds, hipStream_t s) {
+    ctx->trace_rounds[phase] = rounds;
+    if (rounds > 0)
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned_rt + (size_t)phase * (kTraceCap + 2) * kRoundStride,
+                                    ws.rt, (size_t)rounds * kRoundStride * sizeof(uint32_t),
                                     hipMemcpyDeviceToHost, s));
-    }
-    HIP_TRY(ctx, hipStreamSynchronize(s));
+    return MIS2_OK;
+}
+
+int32_t parse_trace(mis2_ctx *ctx, int phase) {
+    const int rounds = ctx->trace_rounds[phase];
+    const uint32_t *rt = ctx->pinned_rt + (size_t)phase * (kTraceCap + 2) * kRoundStride;
     std::vector<int64_t> &tr = ctx->trace[phase];
     tr.clear();
     std::vector<float> &st = ctx->stamp_ms[phase];
@@ -155,7 +162,7 @@ int read_trace(mis2_ctx *ctx, const mis2_graph *g, const Workspace &ws, bool mas
         const uint32_t *p = &rt[(size_t)row * kRoundStride + word];
         return (double)((uint64_t)p[0] | ((uint64_t)p[1] << 32));
     };
-    for (int q = 0; q < rounds; q++) {
+    for (int q = 0; q < rounds && ctx->stamps_valid[phase]; q++) {
         const double t0 = stamp_at(q, kRtStamp0), t1 = stamp_at(q, kRtStamp1),
                      t2 = stamp_at(q, kRtStamp2);
         st.push_back((float)((t1 - t0) / ctx->wall_khz));
@@ -168,8 +175,7 @@ int read_trace(mis2_ctx *ctx, const mis2_graph *g, const Workspace &ws, bool mas
         tr.push_back(c1);
         tr.push_back(c2);
     }
-    *iters_out = r;
-    return MIS2_OK;
+    return r;
 }
 
 constexpr int kFallBack = 1;
@@ -185,6 +191,7 @@ int run_rounds_persistent(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, con
     HIP_TRY(ctx, launch_fill_u32(ws.bar, 0u, kBarWords, s));
     const TupleParams tp = tparams(ctx, g->n, seed, 0);
     RoundsArgs a;
+    memset(&a, 0, sizeof a);
     a.batch = ctx->batch;
     a.wl1[0] = ws.wl1[0];
     a.wl1[1] = ws.wl1[1];
@@ -220,10 +227,14 @@ int run_rounds_persistent(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, con
     if (ctx->pinned[32 + 16])
         return fail(ctx, MIS2_EINTERNAL, "grid barrier timed out in the round kernel");
     const int rounds = (int)ctx->pinned[32 + 32];
-    int rc = read_trace(ctx, g, ws, masked, phase, rounds, s, iters_out);
+    ctx->stamps_valid[phase] = 1;
+    // the row of the round that ended the run is written too
+    int rc = queue_trace(ctx, ws, phase, std::min(rounds + 1, kTraceCap), s);
     if (rc) return rc;
-    if (*iters_out >= rounds && rounds + 2 >= kTraceCap)
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (parse_trace(ctx, phase) >= rounds && rounds + 2 >= kTraceCap)
         return fail(ctx, MIS2_EINTERNAL, "more than %d rounds", kTraceCap - 2);
+    *iters_out = rounds;
     for (int r = 0; r < rounds; r++) {
         launches->push_back(Launch{0, phase, r, lanes, nullptr, nullptr, true});
         launches->push_back(Launch{1, phase, r, lanes, nullptr, nullptr, true});
@@ -237,14 +248,49 @@ int run_rounds_persistent(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, con
 // active vertices already in wl1[0] / cnt1[0] (induced subgraph; T and M
 // already initialised).
 //
-// Rounds are issued without waiting: every sweep reads its worklist sizes
-// from device memory, so a round issued after the last one finds empty
-// worklists and does nothing.  Rounds go out in chunks of kChunk; after each
-// chunk the host copies worklist1's size counters for the next round to
-// pinned memory and waits only for the previous chunk's copy, so the GPU
-// always has the next chunk queued.  The per-round sizes the sweeps record
-// give the round count afterwards.
-constexpr int kChunk = 2;
+// The launched round kernels read their round number from device memory, so
+// every round is issued with the same arguments, and a round issued after
+// the last one finds worklist1 empty and returns at once.  Workgroup 0 of
+// each Refresh Column stores (round, |worklist1|) in a host-pinned word as
+// the round starts; the host polls that word and keeps only a round or two
+// queued beyond the one running, so it stops issuing as soon as a round
+// reports an empty worklist1 and never sleeps in the driver.  (Measured on
+// gfx950 with ROCm 7.2: two direct launches cost the host 5 us, a two-kernel
+// HIP graph launch 16 us and a stream query 11 us, so rounds are launched
+// directly and the stream is queried only after a long wait.)  The per-round
+// sizes the sweeps record in the round table give the round count afterwards.
+constexpr double kProgressTimeoutS = 60.0;  // no round started for this long: give up
+constexpr double kQueryAfterS = 1e-3;       // check the stream for errors after this long idle
+
+RoundsArgs round_args(const mis2_ctx *ctx, const mis2_graph *g, uint64_t seed,
+                      const Workspace &ws, const Geometry &gm, bool masked,
+                      unsigned long long *degs) {
+    RoundsArgs a;
+    memset(&a, 0, sizeof a);
+    const TupleParams tp = tparams(ctx, g->n, seed, 0);
+    a.batch = ctx->batch;
+    for (int i = 0; i < 2; i++) {
+        a.wl1[i] = ws.wl1[i];
+        a.wl2[i] = ws.wl2[i];
+        a.cnt1[i] = ws.cnt1[i];
+        a.cnt2[i] = ws.cnt2[i];
+    }
+    a.rt = ws.rt;
+    a.ctr = ws.ctr;
+    a.rs = ws.rs;
+    a.alive_host = ctx->alive_host;
+    a.degs = ctx->account ? degs : nullptr;
+    a.bar = ws.bar;
+    a.n = g->n;
+    a.seg = gm.seg;
+    a.S = gm.S;
+    a.seed = seed;
+    a.pmask = tp.pmask;
+    a.b = tp.b;
+    a.masked = masked ? 1 : 0;
+    a.max_rounds = kTraceCap;
+    return a;
+}
 
 int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspace &ws,
                const Geometry &gm, bool masked, int phase, hipStream_t s, int32_t *iters_out,
@@ -254,54 +300,40 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
     if (ctx->account) HIP_TRY(ctx, launch_fill_u64(degs, 0ull, 2 * kTraceCap, s));
     // size counters: every ring slot zero except slot 0 of a masked start,
     // which holds its active count; each Refresh Column clears the slot two
-    // rounds ahead.  Round 0's sizes are n for the identity start.
+    // rounds ahead.
     HIP_TRY(ctx, launch_fill_u32(ws.ctr + (masked ? kCtrSlot : 0), 0u,
                                  (int64_t)(masked ? kCtrRing - 1 : kCtrRing) * kCtrSlot, s));
     if (!masked) HIP_TRY(ctx, launch_fill_u32(ws.rt, (uint32_t)g->n, 2, s));
-    hipEvent_t chunk_done[2] = {nullptr, nullptr};
-    for (int i = 0; i < 2; i++)
-        if (!(chunk_done[i] = take_event(ctx)))
-            return fail(ctx, MIS2_EHIP, "hipEventCreate failed");
+    HIP_TRY(ctx, launch_fill_u32(ws.rs, 0u, 2, s));
     if (ctx->plan.persistent) {
         int rc = run_rounds_persistent(ctx, g, seed, ws, gm, masked, phase, s, iters_out, launches,
                                        lanes);
         if (rc != kFallBack) return rc;
     }
-    int round = 0, chunk = 0;
+    const RoundsArgs a = round_args(ctx, g, seed, ws, gm, masked, degs);
+    __atomic_store_n(ctx->alive_host, ~0ull, __ATOMIC_RELEASE);
+    int round = 0;  // rounds issued
+    auto last_progress = std::chrono::steady_clock::now();
+    int last_seen = -2;
     for (;;) {
-        for (int k = 0; k < kChunk; k++, round++) {
+        const unsigned long long v = __atomic_load_n(ctx->alive_host, __ATOMIC_ACQUIRE);
+        int seen = -1;  // round of the latest Refresh Column that has started
+        uint32_t live = 1;
+        if (v != ~0ull) {
+            seen = (int)(v >> 32);
+            live = (uint32_t)v;
+        }
+        if (live == 0u) break;  // worklist1 empty: the run has ended at round `seen`
+        if (seen != last_seen) {
+            last_seen = seen;
+            last_progress = std::chrono::steady_clock::now();
+        }
+        // queue depth beyond the running round: two while rounds are big,
+        // one near the end (fewer rounds issued past it)
+        const int ahead = (seen < 0 || live >= 4096u) ? 2 : 1;
+        if (round - seen <= ahead) {
             if (round + 2 >= kTraceCap)
-                return fail(ctx, MIS2_EINTERNAL, "more than %d rounds", kTraceCap - 1);
-            const int cur = round & 1, nxt = cur ^ 1;
-            const bool first = (round == 0);
-            uint32_t *slot_next = ws.ctr + (size_t)((round + 1) % kCtrRing) * kCtrSlot;
-            SegIO col_io{};
-            col_io.wl_in = first ? (masked ? ws.wl1[0] : nullptr) : ws.wl2[cur];
-            col_io.cnt_in = first ? (masked ? ws.cnt1[0] : nullptr) : ws.cnt2[cur];
-            col_io.wl_out = ws.wl2[nxt];
-            col_io.cnt_out = ws.cnt2[nxt];
-            col_io.trace_out = slot_next + kCtrList;
-            col_io.ctr_zero = ws.ctr + (size_t)((round + 2) % kCtrRing) * kCtrSlot;
-            if (!first || masked) {
-                col_io.sum_in = ws.ctr + (size_t)(round % kCtrRing) * kCtrSlot;
-                col_io.rt_row = ws.rt + (size_t)round * kRoundStride;
-                col_io.sum_same = first ? 1 : 0;
-            }
-            col_io.deg_sum = ctx->account ? degs + 2 * round + 1 : nullptr;
-            col_io.n = g->n;
-            col_io.seg = gm.seg;
-            col_io.S = gm.S;
-            SegIO dec_io{};
-            dec_io.wl_in = first ? (masked ? ws.wl1[0] : nullptr) : ws.wl1[cur];
-            dec_io.cnt_in = first ? (masked ? ws.cnt1[0] : nullptr) : ws.cnt1[cur];
-            dec_io.wl_out = ws.wl1[nxt];
-            dec_io.cnt_out = ws.cnt1[nxt];
-            dec_io.trace_out = slot_next;
-            dec_io.deg_sum = ctx->account ? degs + 2 * round + 0 : nullptr;
-            dec_io.n = g->n;
-            dec_io.seg = gm.seg;
-            dec_io.S = gm.S;
-            const TupleParams next = tparams(ctx, g->n, seed, (uint64_t)round + 1);
+                return fail(ctx, MIS2_EINTERNAL, "more than %d rounds", kTraceCap - 2);
             Launch lc{0, phase, round, lanes, nullptr, nullptr};
             Launch ld{1, phase, round, lanes, nullptr, nullptr};
             if (ctx->profile) {
@@ -311,33 +343,33 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
                     return fail(ctx, MIS2_EHIP, "hipEventCreate failed");
                 HIP_TRY(ctx, hipEventRecord(lc.e0, s));
             }
-            HIP_TRY(ctx, launch_refresh_column(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
-                                               col_io, s));
+            HIP_TRY(ctx, launch_col_round(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
+                                          a, s));
             if (ctx->profile) {
                 HIP_TRY(ctx, hipEventRecord(lc.e1, s));
                 HIP_TRY(ctx, hipEventRecord(ld.e0, s));
             }
-            HIP_TRY(ctx, launch_decide(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M, next,
-                                       dec_io, s));
+            HIP_TRY(ctx, launch_dec_round(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
+                                          a, s));
             if (ctx->profile) HIP_TRY(ctx, hipEventRecord(ld.e1, s));
             launches->push_back(lc);
             launches->push_back(ld);
+            round++;
+            continue;
         }
-        // worklist1's counters for the round after this chunk
-        uint32_t *slot = ctx->pinned_ctr + (size_t)(chunk & 1) * kCtrList;
-        HIP_TRY(ctx, hipMemcpyAsync(slot, ws.ctr + (size_t)(round % kCtrRing) * kCtrSlot,
-                                    kCtrList * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(ctx, hipEventRecord(chunk_done[chunk & 1], s));
-        if (chunk > 0) {
-            HIP_TRY(ctx, hipEventSynchronize(chunk_done[(chunk - 1) & 1]));
-            const uint32_t *prev = ctx->pinned_ctr + (size_t)((chunk - 1) & 1) * kCtrList;
-            uint64_t alive = 0;
-            for (int k = 0; k < kSplit; k++) alive += prev[(size_t)k * kCtrLine];
-            if (alive == 0) break;
+        // the GPU is behind: wait for the next round to start
+        const double idle =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - last_progress).count();
+        if (idle > kQueryAfterS) {
+            const hipError_t q = hipStreamQuery(s);
+            if (q != hipSuccess && q != hipErrorNotReady) HIP_TRY(ctx, q);
         }
-        chunk++;
+        if (idle > kProgressTimeoutS)
+            return fail(ctx, MIS2_EHIP, "no MIS-2 round started for %.0f s", idle);
     }
-    return read_trace(ctx, g, ws, masked, phase, round, s, iters_out);
+    ctx->stamps_valid[phase] = 0;
+    *iters_out = round;  // rounds issued; parse_trace gives the count after the sync
+    return queue_trace(ctx, ws, phase, round, s);
 }
 
 // Fill ctx->sweeps from the launches of the finished call.
@@ -420,6 +452,7 @@ size_t workspace_bytes(int64_t n, int op) {
     b += align_up(4 * (size_t)kMaxWaves) * 4;           // cnt1[2], cnt2[2]
     b += align_up(4 * (size_t)(kTraceCap + 2) * kRoundStride);  // round table
     b += align_up(4 * (size_t)kCtrRing * kCtrSlot);     // size counters
+    b += align_up(4 * 2);                               // round numbers
     b += align_up(4 * kScalars);                        // scalars
     b += align_up(8 * 2 * 2 * (size_t)kTraceCap);       // degs
     b += align_up(4 * (size_t)(compact_blocks(n) + 1)); // blocksum
@@ -457,6 +490,7 @@ bool carve(void *base, size_t bytes, int64_t n, int op, Workspace *ws) {
     ws->cnt2[1] = (uint32_t *)take(4 * (size_t)kMaxWaves);
     ws->rt = (uint32_t *)take(4 * (size_t)(kTraceCap + 2) * kRoundStride);
     ws->ctr = (uint32_t *)take(4 * (size_t)kCtrRing * kCtrSlot);
+    ws->rs = (uint32_t *)take(4 * 2);
     ws->scalars = (uint32_t *)take(4 * kScalars);
     ws->degs = (unsigned long long *)take(8 * 2 * 2 * (size_t)kTraceCap);
     ws->blocksum = (uint32_t *)take(4 * (size_t)(compact_blocks(n) + 1));
@@ -509,6 +543,22 @@ int mis2_create(mis2_ctx **out, int device) {
         delete ctx;
         return MIS2_EHIP;
     }
+    // coherent, so the host sees the GPU's stores while kernels still run
+    if (hipHostMalloc((void **)&ctx->alive_host, 64, hipHostMallocCoherent) != hipSuccess) {
+        (void)hipHostFree(ctx->pinned);
+        (void)hipHostFree(ctx->pinned_ctr);
+        delete ctx;
+        return MIS2_EHIP;
+    }
+    if (hipHostMalloc((void **)&ctx->pinned_rt,
+                      2 * (size_t)(kTraceCap + 2) * kRoundStride * sizeof(uint32_t),
+                      hipHostMallocDefault) != hipSuccess) {
+        (void)hipHostFree(ctx->pinned);
+        (void)hipHostFree(ctx->pinned_ctr);
+        (void)hipHostFree(ctx->alive_host);
+        delete ctx;
+        return MIS2_EHIP;
+    }
     *out = ctx;
     return MIS2_OK;
 }
@@ -517,6 +567,8 @@ void mis2_destroy(mis2_ctx *ctx) {
     if (!ctx) return;
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->pinned_ctr) (void)hipHostFree(ctx->pinned_ctr);
+    if (ctx->alive_host) (void)hipHostFree(ctx->alive_host);
+    if (ctx->pinned_rt) (void)hipHostFree(ctx->pinned_rt);
     for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
     delete ctx;
 }
@@ -598,11 +650,10 @@ int mis2_run(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, uint8_t *status,
     int32_t iters = 0;
     if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, &iters, &launches))) return rc;
     HIP_TRY(ctx, launch_status(g->n, ws.T, status, ws.blocksum, ws.scalars + kS_Roots, s));
-    if (n_roots) {
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, ws.scalars + kS_Roots, 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(ctx, hipStreamSynchronize(s));
-        *n_roots = ctx->pinned[0];
-    }
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, ws.scalars + kS_Roots, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    iters = parse_trace(ctx, 0);
+    if (n_roots) *n_roots = ctx->pinned[0];
     if (n_iters) *n_iters = iters;
     return collect_sweeps(ctx, launches, ws, s);
 }
@@ -705,6 +756,8 @@ int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
 
     HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, sc, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
+    it1 = parse_trace(ctx, 0);
+    it2 = parse_trace(ctx, 1);
     if (ctx->pinned[kS_Err])
         return fail(ctx, MIS2_EINTERNAL, "phase-3 vertex without an aggregated neighbour");
     if (n_agg) *n_agg = (int64_t)ctx->pinned[kS_Count1] + (int64_t)ctx->pinned[kS_Count2];

@@ -116,6 +116,7 @@ struct Workspace {
     uint32_t *cnt2[2] = {};       // [kMaxWaves] per-wave sizes of wl2[i]
     uint32_t *rt = nullptr;       // [kTraceCap + 2][kRoundStride] round table
     uint32_t *ctr = nullptr;      // [kCtrRing][kCtrSlot] size counters
+    uint32_t *rs = nullptr;       // [2] round numbers of the launched round kernels
     uint32_t *scalars = nullptr;  // [kScalars]
     unsigned long long *degs = nullptr;  // [2][kTraceCap][2] row-length sums per sweep
     uint32_t *blocksum = nullptr; // [compact_blocks(n) + 1]
@@ -147,21 +148,14 @@ struct Plan {
 // One sweep's worklists.  Wavefront w owns slots [w*seg, w*seg + cnt[w]) of
 // each list.  cnt_in == nullptr means the identity lists (w's whole vertex
 // range).  trace_out (may be null) points at the kSplit counters (stride
-// kCtrLine) whose sum becomes the output size; ctr_zero (may be null) is a
-// counter slot that workgroup 0 clears for a later round; sum_in / rt_row
-// (may be null): workgroup 0 sums the counter slot sum_in into the
-// round-table row rt_row (worklist1's sum for both lists if sum_same);
-// deg_sum (may be null) accumulates the visited CSR row lengths.
+// kCtrLine) whose sum becomes the output size; deg_sum (may be null)
+// accumulates the visited CSR row lengths.
 struct SegIO {
     const int32_t *wl_in;
     const uint32_t *cnt_in;
     int32_t *wl_out;
     uint32_t *cnt_out;
     uint32_t *trace_out;
-    uint32_t *ctr_zero;
-    const uint32_t *sum_in;
-    uint32_t *rt_row;
-    int sum_same;
     unsigned long long *deg_sum;
     int64_t n;
     int64_t seg;
@@ -173,6 +167,13 @@ struct SegIO {
 // [kMaxBlocks + 16] and the executed round count at [kMaxBlocks + 32]; all
 // zero before the launch.
 constexpr int kBarWords = kMaxBlocks + 64;
+// Also the arguments of the launched round kernels (k_col_round /
+// k_dec_round), which take their round number from rs: rs[0] is the round of
+// the next Refresh Column, rs[1] that of the next Decide Set (each kernel
+// advances the other's word), so every round is launched with the same
+// arguments.
+// alive_host (may be null): host-pinned word where workgroup 0 of every
+// Refresh Column stores (round << 32) | |worklist1| at the start of its round.
 struct RoundsArgs {
     BatchInfo batch;
     int32_t *wl1[2];
@@ -181,6 +182,8 @@ struct RoundsArgs {
     uint32_t *cnt2[2];
     uint32_t *rt;
     uint32_t *ctr;
+    uint32_t *rs;
+    unsigned long long *alive_host;
     unsigned long long *degs;  // [kTraceCap][2] or null
     uint32_t *bar;
     int64_t n, seg, S;
@@ -194,14 +197,13 @@ struct RoundsArgs {
 int rounds_max_blocks(int lanes, int num_cus);
 hipError_t launch_rounds(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                          uint32_t *T, uint32_t *M, const RoundsArgs &a, hipStream_t s);
+hipError_t launch_col_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
+                            const uint32_t *T, uint32_t *M, const RoundsArgs &a, hipStream_t s);
+hipError_t launch_dec_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
+                            uint32_t *T, const uint32_t *M, const RoundsArgs &a, hipStream_t s);
 hipError_t launch_init_tuples(const TupleParams &tp, int64_t n, uint32_t *T, hipStream_t s);
 hipError_t launch_init_masked(int blocks, const TupleParams &tp, int64_t n, const int32_t *label,
                               uint32_t *T, uint32_t *M, const SegIO &io, hipStream_t s);
-hipError_t launch_refresh_column(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
-                                 const uint32_t *T, uint32_t *M, const SegIO &io, hipStream_t s);
-hipError_t launch_decide(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
-                         uint32_t *T, const uint32_t *M, const TupleParams &next, const SegIO &io,
-                         hipStream_t s);
 int64_t status_blocks(int64_t n);
 hipError_t launch_status(int64_t n, const uint32_t *T, uint8_t *status, uint32_t *blocksum,
                          uint32_t *d_total, hipStream_t s);
@@ -311,6 +313,10 @@ struct mis2_ctx {
     size_t ws_bytes = 0;
     uint32_t *pinned = nullptr;  // host-pinned scalars for read-back
     uint32_t *pinned_ctr = nullptr;  // host-pinned [2][kCtrList]: worklist1 counters per chunk
+    unsigned long long *alive_host = nullptr;  // host-pinned: (round << 32) | |worklist1|
+    uint32_t *pinned_rt = nullptr;  // host-pinned [2][kTraceCap + 2][kRoundStride] round tables
+    int trace_rounds[2] = {0, 0};   // rows of pinned_rt copied per phase
+    int stamps_valid[2] = {0, 0};   // the rows hold persistent-kernel stamps
     std::string err;
     int validate = 0;
     int profile = 0;

@@ -113,20 +113,12 @@ __device__ __forceinline__ uint32_t ctr_sum(const uint32_t *list) {
     return x;
 }
 
-// Workgroup 0's round bookkeeping at the start of a Refresh Column sweep:
-// clear a counter slot for a later round, and record this round's sizes.
-__device__ __forceinline__ void round_books(const SegIO &io) {
-    if (blockIdx.x != 0) return;
-    if (io.ctr_zero && threadIdx.x < 2 * kSplit)
-        io.ctr_zero[(threadIdx.x / kSplit) * kCtrList + (threadIdx.x % kSplit) * kCtrLine] = 0u;
-    if (io.sum_in && threadIdx.x < 64) {
-        const uint32_t a = ctr_sum(io.sum_in);
-        const uint32_t b = io.sum_same ? a : ctr_sum(io.sum_in + kCtrList);
-        if (threadIdx.x == 0) {
-            io.rt_row[0] = a;
-            io.rt_row[1] = b;
-        }
-    }
+// Workgroup 0 clears the counter slot of round r + 2 at the start of round
+// r's Refresh Column (nobody reads or writes that slot during round r).
+__device__ __forceinline__ void clear_slot(uint32_t *ctr, int r) {
+    if (blockIdx.x == 0 && threadIdx.x < 2 * kSplit)
+        ctr[(size_t)((r + 2) % kCtrRing) * kCtrSlot + (threadIdx.x / kSplit) * kCtrList +
+            (threadIdx.x % kSplit) * kCtrLine] = 0u;
 }
 
 // Largest row length among the rows this lane's group holds, over the
@@ -703,24 +695,114 @@ __device__ __forceinline__ uint32_t any_decide(const int64_t *__restrict__ row_p
     }
 }
 
+// ---------------------------------------------------------------------------
+// Launched rounds with the round number in device memory.  Each sweep first
+// sums worklist1's size counters of its round (every workgroup, one load per
+// lane of one wavefront); a round whose worklist1 is empty -- or that would
+// pass the round cap -- does nothing, so rounds issued past the end of the
+// run cost one short launch each.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ SegIO round_col_io(const RoundsArgs &a, int r) {
+    const int cur = r & 1, nxt = cur ^ 1;
+    const bool first = r == 0;
+    SegIO io{};
+    io.wl_in = first ? (a.masked ? a.wl1[0] : nullptr) : a.wl2[cur];
+    io.cnt_in = first ? (a.masked ? a.cnt1[0] : nullptr) : a.cnt2[cur];
+    io.wl_out = a.wl2[nxt];
+    io.cnt_out = a.cnt2[nxt];
+    io.trace_out = a.ctr + (size_t)((r + 1) % kCtrRing) * kCtrSlot + kCtrList;
+    io.deg_sum = a.degs ? a.degs + 2 * r + 1 : nullptr;
+    io.n = a.n;
+    io.seg = a.seg;
+    io.S = a.S;
+    return io;
+}
+
+__device__ __forceinline__ SegIO round_dec_io(const RoundsArgs &a, int r) {
+    const int cur = r & 1, nxt = cur ^ 1;
+    const bool first = r == 0;
+    SegIO io{};
+    io.wl_in = first ? (a.masked ? a.wl1[0] : nullptr) : a.wl1[cur];
+    io.cnt_in = first ? (a.masked ? a.cnt1[0] : nullptr) : a.cnt1[cur];
+    io.wl_out = a.wl1[nxt];
+    io.cnt_out = a.cnt1[nxt];
+    io.trace_out = a.ctr + (size_t)((r + 1) % kCtrRing) * kCtrSlot;
+    io.deg_sum = a.degs ? a.degs + 2 * r : nullptr;
+    io.n = a.n;
+    io.seg = a.seg;
+    io.S = a.S;
+    return io;
+}
+
+// Sizes of worklist1 / worklist2 at the start of round r (wavefront 0; the
+// identity start has n of each, a masked start its active count in slot 0).
+__device__ __forceinline__ void round_sizes(const RoundsArgs &a, int r, uint32_t &c1,
+                                            uint32_t &c2) {
+    if (r == 0 && !a.masked) {
+        c1 = c2 = (uint32_t)a.n;
+        return;
+    }
+    const uint32_t *slot = a.ctr + (size_t)(r % kCtrRing) * kCtrSlot;
+    c1 = ctr_sum(slot);
+    c2 = r == 0 ? c1 : ctr_sum(slot + kCtrList);
+}
+
 template <int L>
-__global__ __launch_bounds__(kBlock) void k_refresh_column(const int64_t *__restrict__ row_ptr,
-                                                           const int32_t *__restrict__ col,
-                                                           const uint32_t *__restrict__ T,
-                                                           uint32_t *__restrict__ M, SegIO io) {
+__global__ __launch_bounds__(kBlock) void k_col_round(const int64_t *__restrict__ row_ptr,
+                                                      const int32_t *__restrict__ col,
+                                                      const uint32_t *__restrict__ T,
+                                                      uint32_t *__restrict__ M, RoundsArgs a) {
+    __shared__ uint32_t live_s;
+    const int r = (int)a.rs[0];
+    if (threadIdx.x < 64) {
+        uint32_t c1, c2;
+        round_sizes(a, r, c1, c2);
+        if (threadIdx.x == 0) {
+            const bool capped = r + 2 >= a.max_rounds;
+            live_s = capped ? 0u : c1;
+            if (blockIdx.x == 0) {
+                if (!capped) {
+                    a.rt[(size_t)r * kRoundStride] = c1;
+                    a.rt[(size_t)r * kRoundStride + 1] = c2;
+                }
+                a.rs[1] = (uint32_t)r;
+                if (a.alive_host)
+                    __hip_atomic_store(a.alive_host,
+                                       ((unsigned long long)(uint32_t)r << 32) | (capped ? 1u : c1),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+    }
+    clear_slot(a.ctr, r);
+    __syncthreads();
+    if (live_s == 0u) return;
+    const SegIO io = round_col_io(a, r);
     const int64_t w = wave_id();
-    round_books(io);
     const Seg sg = seg_of(io, w);
     const uint32_t kept = any_column<L>(row_ptr, col, T, M, io, sg);
     seg_finish(io, w, kept);
 }
 
 template <int L>
-__global__ __launch_bounds__(kBlock) void k_decide(const int64_t *__restrict__ row_ptr,
-                                                   const int32_t *__restrict__ col,
-                                                   uint32_t *__restrict__ T,
-                                                   const uint32_t *__restrict__ M,
-                                                   TupleParams next, SegIO io) {
+__global__ __launch_bounds__(kBlock) void k_dec_round(const int64_t *__restrict__ row_ptr,
+                                                      const int32_t *__restrict__ col,
+                                                      uint32_t *__restrict__ T,
+                                                      const uint32_t *__restrict__ M,
+                                                      RoundsArgs a) {
+    __shared__ uint32_t live_s;
+    const int r = (int)a.rs[1];
+    if (threadIdx.x < 64) {
+        uint32_t c1, c2;
+        round_sizes(a, r, c1, c2);
+        if (threadIdx.x == 0) {
+            live_s = r + 2 >= a.max_rounds ? 0u : c1;
+            if (blockIdx.x == 0) a.rs[0] = (uint32_t)r + 1u;
+        }
+    }
+    __syncthreads();
+    if (live_s == 0u) return;
+    const SegIO io = round_dec_io(a, r);
+    const TupleParams next{xs64star((a.seed << 32) ^ (uint64_t)(r + 1)), a.pmask, a.b, a.batch};
     const int64_t w = wave_id();
     const Seg sg = seg_of(io, w);
     const uint32_t kept = any_decide<L>(row_ptr, col, T, M, next, io, sg);
@@ -816,21 +898,9 @@ __global__ __launch_bounds__(kBlock) void k_rounds(const int64_t *__restrict__ r
         }
     }
     for (;;) {
-        const int cur = r & 1, nxt = cur ^ 1;
-        const bool first = (r == 0);
         uint32_t *slot_next = a.ctr + (size_t)((r + 1) % kCtrRing) * kCtrSlot;
-        SegIO cio{};
-        cio.wl_in = first ? (a.masked ? a.wl1[0] : nullptr) : a.wl2[cur];
-        cio.cnt_in = first ? (a.masked ? a.cnt1[0] : nullptr) : a.cnt2[cur];
-        cio.wl_out = a.wl2[nxt];
-        cio.cnt_out = a.cnt2[nxt];
-        cio.trace_out = slot_next + kCtrList;
-        cio.ctr_zero = a.ctr + (size_t)((r + 2) % kCtrRing) * kCtrSlot;
-        cio.deg_sum = a.degs ? a.degs + 2 * r + 1 : nullptr;
-        cio.n = a.n;
-        cio.seg = a.seg;
-        cio.S = a.S;
-        round_books(cio);
+        const SegIO cio = round_col_io(a, r);
+        clear_slot(a.ctr, r);
         uint32_t *row_cur = a.rt + (size_t)r * kRoundStride;
         if (blockIdx.x == 0 && threadIdx.x == 0) stamp(row_cur + kRtStamp0);
         Seg sg = seg_of(cio, w);
@@ -838,16 +908,7 @@ __global__ __launch_bounds__(kBlock) void k_rounds(const int64_t *__restrict__ r
         seg_finish(cio, w, kept);
         if (!grid_barrier(flags, gen, abort_word, ++epoch)) break;
         if (blockIdx.x == 0 && threadIdx.x == 0) stamp(row_cur + kRtStamp1);
-        SegIO dio{};
-        dio.wl_in = first ? (a.masked ? a.wl1[0] : nullptr) : a.wl1[cur];
-        dio.cnt_in = first ? (a.masked ? a.cnt1[0] : nullptr) : a.cnt1[cur];
-        dio.wl_out = a.wl1[nxt];
-        dio.cnt_out = a.cnt1[nxt];
-        dio.trace_out = slot_next;
-        dio.deg_sum = a.degs ? a.degs + 2 * r : nullptr;
-        dio.n = a.n;
-        dio.seg = a.seg;
-        dio.S = a.S;
+        const SegIO dio = round_dec_io(a, r);
         const TupleParams next{xs64star((a.seed << 32) ^ (uint64_t)(r + 1)), a.pmask, a.b, a.batch};
         sg = seg_of(dio, w);
         kept = any_decide<L>(row_ptr, col, T, M, next, dio, sg);
@@ -1010,19 +1071,17 @@ TupleParams tuple_params(int64_t n, uint64_t seed, uint64_t iter) {
         default: return hipErrorInvalidValue;                                           \
     }
 
-hipError_t launch_refresh_column(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
-                                 const uint32_t *T, uint32_t *M, const SegIO &io,
-                                 hipStream_t s) {
-    MIS2_LANE_DISPATCH(lanes, k_refresh_column, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col, T,
-                       M, io);
+hipError_t launch_col_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
+                            const uint32_t *T, uint32_t *M, const RoundsArgs &a, hipStream_t s) {
+    MIS2_LANE_DISPATCH(lanes, k_col_round, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col, T, M,
+                       a);
     return hipGetLastError();
 }
 
-hipError_t launch_decide(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
-                         uint32_t *T, const uint32_t *M, const TupleParams &next, const SegIO &io,
-                         hipStream_t s) {
-    MIS2_LANE_DISPATCH(lanes, k_decide, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col, T, M,
-                       next, io);
+hipError_t launch_dec_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
+                            uint32_t *T, const uint32_t *M, const RoundsArgs &a, hipStream_t s) {
+    MIS2_LANE_DISPATCH(lanes, k_dec_round, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col, T, M,
+                       a);
     return hipGetLastError();
 }
 

@@ -100,6 +100,26 @@ def test_mis2_repeatable(ctx):
         assert np.array_equal(ctx.mis2(rp, c, 0)[0].cpu().numpy(), first)
 
 
+def test_repeated_calls_on_device_graph(api):
+    # the same device arrays again and again (the case a cache or a stale
+    # round counter would break): every call must match the oracle, trace
+    # included
+    import torch
+    c = api.Context(0)
+    for name in ("grid27_ragged", "chunglu_50k", "star70"):
+        rp, cc = dict(SMALL)[name]
+        drp, dcc = api.as_device_csr(rp, cc, torch.device("cuda", 0))
+        o = oracle.mis2_ex(rp, cc, 3)
+        oa, ona = oracle.aggregate(rp, cc, 3)
+        for k in range(4):
+            st, nr, it = c.mis2(drp, dcc, 3)
+            assert np.array_equal(st.cpu().numpy(), o["status"]), (name, k)
+            assert it == o["n_iters"]
+            assert np.array_equal(c.last_trace(0), o["trace"][:, :2]), (name, k)
+            agg, na = c.aggregate(drp, dcc, 3)
+            assert na == ona and np.array_equal(agg.cpu().numpy(), oa), (name, k)
+
+
 def _check_agg(ctx, rp, c, seed=0, name=""):
     agg, na, roots = ctx.aggregate(rp, c, seed, want_roots=True)
     d = oracle.aggregate(rp, c, seed, detail=True)
