@@ -64,11 +64,12 @@ def kernel_sources_digest():
     return h.hexdigest()
 
 
-def measured_traffic(workload, kernel):
+def measured_traffic(workload, kernel, launches_per_step):
     """HBM bytes per launch of `kernel` from profiles/traffic_<workload>.json
     (rocprofv3 FETCH_SIZE and WRITE_SIZE runs of this bench, scaled by the
-    same counters on a plain device copy of known size), or None when there is
-    no such measurement for the current sources."""
+    same counters on a plain device copy of known size; bytes per step over
+    the launches per step counted here), or None when there is no such
+    measurement for the current sources."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
     if not os.path.exists(path):
         return None
@@ -77,7 +78,9 @@ def measured_traffic(workload, kernel):
     if t.get("sources_sha256") != kernel_sources_digest():
         return None
     k = t.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("hbm_bytes_per_launch")
+    if k is None or "hbm_bytes_per_step" not in k:
+        return None
+    return k["hbm_bytes_per_step"] / launches_per_step
 
 
 def sweep_bytes(rec, identity):
@@ -409,7 +412,7 @@ def main():
                    "index_types": "int64 row offsets, int32 columns"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": measured_traffic(args.workload, dom),
+                     "traffic": measured_traffic(args.workload, dom, d["launches"]),
                      "kernel": dom, "launches_per_step": d["launches"],
                      "bytes_per_launch": d["bytes"] / d["launches"],
                      "mean_launch_ms": d["ms"] / d["launches"]},
