@@ -248,9 +248,8 @@ int run_rounds_persistent(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, con
 // active vertices already in wl1[0] / cnt1[0] (induced subgraph; T and M
 // already initialised).
 //
-// The launched round kernels read their round number from device memory, so
-// every round is issued with the same arguments, and a round issued after
-// the last one finds worklist1 empty and returns at once.  Workgroup 0 of
+// A round issued after the last one finds empty per-wavefront lists and
+// does nothing.  Workgroup 0 of
 // each Refresh Column stores (round, |worklist1|) in a host-pinned word as
 // the round starts; the host polls that word and keeps only a round or two
 // queued beyond the one running, so it stops issuing as soon as a round
@@ -277,7 +276,6 @@ RoundsArgs round_args(const mis2_ctx *ctx, const mis2_graph *g, uint64_t seed,
     }
     a.rt = ws.rt;
     a.ctr = ws.ctr;
-    a.rs = ws.rs;
     a.alive_host = ctx->alive_host;
     a.degs = ctx->account ? degs : nullptr;
     a.bar = ws.bar;
@@ -304,7 +302,6 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
     HIP_TRY(ctx, launch_fill_u32(ws.ctr + (masked ? kCtrSlot : 0), 0u,
                                  (int64_t)(masked ? kCtrRing - 1 : kCtrRing) * kCtrSlot, s));
     if (!masked) HIP_TRY(ctx, launch_fill_u32(ws.rt, (uint32_t)g->n, 2, s));
-    HIP_TRY(ctx, launch_fill_u32(ws.rs, 0u, 2, s));
     if (ctx->plan.persistent) {
         int rc = run_rounds_persistent(ctx, g, seed, ws, gm, masked, phase, s, iters_out, launches,
                                        lanes);
@@ -344,13 +341,13 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
                 HIP_TRY(ctx, hipEventRecord(lc.e0, s));
             }
             HIP_TRY(ctx, launch_col_round(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
-                                          a, s));
+                                          a, round, s));
             if (ctx->profile) {
                 HIP_TRY(ctx, hipEventRecord(lc.e1, s));
                 HIP_TRY(ctx, hipEventRecord(ld.e0, s));
             }
             HIP_TRY(ctx, launch_dec_round(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
-                                          a, s));
+                                          a, round, s));
             if (ctx->profile) HIP_TRY(ctx, hipEventRecord(ld.e1, s));
             launches->push_back(lc);
             launches->push_back(ld);
@@ -452,7 +449,6 @@ size_t workspace_bytes(int64_t n, int op) {
     b += align_up(4 * (size_t)kMaxWaves) * 4;           // cnt1[2], cnt2[2]
     b += align_up(4 * (size_t)(kTraceCap + 2) * kRoundStride);  // round table
     b += align_up(4 * (size_t)kCtrRing * kCtrSlot);     // size counters
-    b += align_up(4 * 2);                               // round numbers
     b += align_up(4 * kScalars);                        // scalars
     b += align_up(8 * 2 * 2 * (size_t)kTraceCap);       // degs
     b += align_up(4 * (size_t)(compact_blocks(n) + 1)); // blocksum
@@ -490,7 +486,6 @@ bool carve(void *base, size_t bytes, int64_t n, int op, Workspace *ws) {
     ws->cnt2[1] = (uint32_t *)take(4 * (size_t)kMaxWaves);
     ws->rt = (uint32_t *)take(4 * (size_t)(kTraceCap + 2) * kRoundStride);
     ws->ctr = (uint32_t *)take(4 * (size_t)kCtrRing * kCtrSlot);
-    ws->rs = (uint32_t *)take(4 * 2);
     ws->scalars = (uint32_t *)take(4 * kScalars);
     ws->degs = (unsigned long long *)take(8 * 2 * 2 * (size_t)kTraceCap);
     ws->blocksum = (uint32_t *)take(4 * (size_t)(compact_blocks(n) + 1));

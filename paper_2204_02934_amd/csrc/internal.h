@@ -116,7 +116,6 @@ struct Workspace {
     uint32_t *cnt2[2] = {};       // [kMaxWaves] per-wave sizes of wl2[i]
     uint32_t *rt = nullptr;       // [kTraceCap + 2][kRoundStride] round table
     uint32_t *ctr = nullptr;      // [kCtrRing][kCtrSlot] size counters
-    uint32_t *rs = nullptr;       // [2] round numbers of the launched round kernels
     uint32_t *scalars = nullptr;  // [kScalars]
     unsigned long long *degs = nullptr;  // [2][kTraceCap][2] row-length sums per sweep
     uint32_t *blocksum = nullptr; // [compact_blocks(n) + 1]
@@ -168,10 +167,7 @@ struct SegIO {
 // zero before the launch.
 constexpr int kBarWords = kMaxBlocks + 64;
 // Also the arguments of the launched round kernels (k_col_round /
-// k_dec_round), which take their round number from rs: rs[0] is the round of
-// the next Refresh Column, rs[1] that of the next Decide Set (each kernel
-// advances the other's word), so every round is launched with the same
-// arguments.
+// k_dec_round, which take the round number as a second argument).
 // alive_host (may be null): host-pinned word where workgroup 0 of every
 // Refresh Column stores (round << 32) | |worklist1| at the start of its round.
 struct RoundsArgs {
@@ -182,7 +178,6 @@ struct RoundsArgs {
     uint32_t *cnt2[2];
     uint32_t *rt;
     uint32_t *ctr;
-    uint32_t *rs;
     unsigned long long *alive_host;
     unsigned long long *degs;  // [kTraceCap][2] or null
     uint32_t *bar;
@@ -198,9 +193,11 @@ int rounds_max_blocks(int lanes, int num_cus);
 hipError_t launch_rounds(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                          uint32_t *T, uint32_t *M, const RoundsArgs &a, hipStream_t s);
 hipError_t launch_col_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
-                            const uint32_t *T, uint32_t *M, const RoundsArgs &a, hipStream_t s);
+                            const uint32_t *T, uint32_t *M, const RoundsArgs &a, int r,
+                            hipStream_t s);
 hipError_t launch_dec_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
-                            uint32_t *T, const uint32_t *M, const RoundsArgs &a, hipStream_t s);
+                            uint32_t *T, const uint32_t *M, const RoundsArgs &a, int r,
+                            hipStream_t s);
 hipError_t launch_init_tuples(const TupleParams &tp, int64_t n, uint32_t *T, hipStream_t s);
 hipError_t launch_init_masked(int blocks, const TupleParams &tp, int64_t n, const int32_t *label,
                               uint32_t *T, uint32_t *M, const SegIO &io, hipStream_t s);

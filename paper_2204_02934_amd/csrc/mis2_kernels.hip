@@ -140,19 +140,24 @@ __device__ __forceinline__ void load_rows(const SegIO &io, const Seg &sg, int64_
                                           int32_t (&v)[U], bool (&ok)[U]) {
     constexpr int G = 64 / L;
     const int lane = (int)(threadIdx.x & 63u);
-    int64_t ic[U];
+    // The list slot address does not depend on the count (slots past the
+    // segment's end are clamped into the array, and what they hold is not
+    // used), so the entries load in the same trip as the wavefront's count.
+    int64_t slot[U];
 #pragma unroll
-    for (int u = 0; u < U; u++) {
-        const int64_t i = i0 + u * G + lane / L;
-        ok[u] = i < sg.count;
-        ic[u] = ok[u] ? i : sg.count - 1;
-    }
+    for (int u = 0; u < U; u++) slot[u] = min(sg.base + i0 + u * G + lane / L, io.n - 1);
+    int32_t x[U];
     if (io.wl_in) {
 #pragma unroll
-        for (int u = 0; u < U; u++) v[u] = io.wl_in[sg.base + ic[u]];
+        for (int u = 0; u < U; u++) x[u] = io.wl_in[slot[u]];
     } else {
 #pragma unroll
-        for (int u = 0; u < U; u++) v[u] = (int32_t)(sg.base + ic[u]);
+        for (int u = 0; u < U; u++) x[u] = (int32_t)slot[u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        ok[u] = i0 + u * G + lane / L < sg.count;
+        v[u] = ok[u] ? x[u] : 0;  // vertex 0: a valid address for the lanes without a row
     }
 }
 
@@ -696,11 +701,9 @@ __device__ __forceinline__ uint32_t any_decide(const int64_t *__restrict__ row_p
 }
 
 // ---------------------------------------------------------------------------
-// Launched rounds with the round number in device memory.  Each sweep first
-// sums worklist1's size counters of its round (every workgroup, one load per
-// lane of one wavefront); a round whose worklist1 is empty -- or that would
-// pass the round cap -- does nothing, so rounds issued past the end of the
-// run cost one short launch each.
+// Launched rounds.  A round past the end of the run finds empty per-wavefront
+// lists and does nothing; workgroup 0 of each Refresh Column records the
+// round's sizes and reports |worklist1| to the host.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ SegIO round_col_io(const RoundsArgs &a, int r) {
     const int cur = r & 1, nxt = cur ^ 1;
@@ -751,31 +754,20 @@ template <int L>
 __global__ __launch_bounds__(kBlock) void k_col_round(const int64_t *__restrict__ row_ptr,
                                                       const int32_t *__restrict__ col,
                                                       const uint32_t *__restrict__ T,
-                                                      uint32_t *__restrict__ M, RoundsArgs a) {
-    __shared__ uint32_t live_s;
-    const int r = (int)a.rs[0];
-    if (threadIdx.x < 64) {
+                                                      uint32_t *__restrict__ M, RoundsArgs a,
+                                                      int r) {
+    if (blockIdx.x == 0 && threadIdx.x < 64) {
         uint32_t c1, c2;
         round_sizes(a, r, c1, c2);
         if (threadIdx.x == 0) {
-            const bool capped = r + 2 >= a.max_rounds;
-            live_s = capped ? 0u : c1;
-            if (blockIdx.x == 0) {
-                if (!capped) {
-                    a.rt[(size_t)r * kRoundStride] = c1;
-                    a.rt[(size_t)r * kRoundStride + 1] = c2;
-                }
-                a.rs[1] = (uint32_t)r;
-                if (a.alive_host)
-                    __hip_atomic_store(a.alive_host,
-                                       ((unsigned long long)(uint32_t)r << 32) | (capped ? 1u : c1),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            }
+            a.rt[(size_t)r * kRoundStride] = c1;
+            a.rt[(size_t)r * kRoundStride + 1] = c2;
+            if (a.alive_host)
+                __hip_atomic_store(a.alive_host, ((unsigned long long)(uint32_t)r << 32) | c1,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
     clear_slot(a.ctr, r);
-    __syncthreads();
-    if (live_s == 0u) return;
     const SegIO io = round_col_io(a, r);
     const int64_t w = wave_id();
     const Seg sg = seg_of(io, w);
@@ -788,19 +780,7 @@ __global__ __launch_bounds__(kBlock) void k_dec_round(const int64_t *__restrict_
                                                       const int32_t *__restrict__ col,
                                                       uint32_t *__restrict__ T,
                                                       const uint32_t *__restrict__ M,
-                                                      RoundsArgs a) {
-    __shared__ uint32_t live_s;
-    const int r = (int)a.rs[1];
-    if (threadIdx.x < 64) {
-        uint32_t c1, c2;
-        round_sizes(a, r, c1, c2);
-        if (threadIdx.x == 0) {
-            live_s = r + 2 >= a.max_rounds ? 0u : c1;
-            if (blockIdx.x == 0) a.rs[0] = (uint32_t)r + 1u;
-        }
-    }
-    __syncthreads();
-    if (live_s == 0u) return;
+                                                      RoundsArgs a, int r) {
     const SegIO io = round_dec_io(a, r);
     const TupleParams next{xs64star((a.seed << 32) ^ (uint64_t)(r + 1)), a.pmask, a.b, a.batch};
     const int64_t w = wave_id();
@@ -1072,16 +1052,18 @@ TupleParams tuple_params(int64_t n, uint64_t seed, uint64_t iter) {
     }
 
 hipError_t launch_col_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
-                            const uint32_t *T, uint32_t *M, const RoundsArgs &a, hipStream_t s) {
+                            const uint32_t *T, uint32_t *M, const RoundsArgs &a, int r,
+                            hipStream_t s) {
     MIS2_LANE_DISPATCH(lanes, k_col_round, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col, T, M,
-                       a);
+                       a, r);
     return hipGetLastError();
 }
 
 hipError_t launch_dec_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
-                            uint32_t *T, const uint32_t *M, const RoundsArgs &a, hipStream_t s) {
+                            uint32_t *T, const uint32_t *M, const RoundsArgs &a, int r,
+                            hipStream_t s) {
     MIS2_LANE_DISPATCH(lanes, k_dec_round, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col, T, M,
-                       a);
+                       a, r);
     return hipGetLastError();
 }
 
