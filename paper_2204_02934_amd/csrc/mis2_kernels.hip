@@ -349,6 +349,8 @@ __device__ __forceinline__ uint32_t sweep_decide(const int64_t *__restrict__ row
             any_out[u] = (sub == 0) & (mv[u] == kOut);
             all_eq[u] = (sub != 0) | (mv[u] == t0[u]);
             if (sub == 0) dsum += (unsigned long long)(e[u] - s[u]);
+            // M_v = OUT already decides the row (OUT), whatever the neighbours hold
+            if (mv[u] == kOut) e[u] = s[u];
         }
         // high-degree rows: the whole wavefront streams each one in turn
 #pragma unroll
@@ -584,8 +586,9 @@ __device__ __forceinline__ uint32_t flat_decide(const int64_t *__restrict__ row_
         const uint32_t mv = M[v];
         int any_out = mv == kOut;
         int all_eq = mv == t0;
-        const int64_t len = ok ? e - s : 0;
-        dsum += (unsigned long long)len;
+        dsum += (unsigned long long)(ok ? e - s : 0);
+        // M_v = OUT already decides the row (OUT), whatever the neighbours hold
+        const int64_t len = ok && mv != kOut ? e - s : 0;
         uint64_t heavy = __ballot(len > kFlatHeavy);
         while (heavy) {
             const int src = __ffsll((unsigned long long)heavy) - 1;
