@@ -461,6 +461,7 @@ size_t workspace_bytes(int64_t n, int op) {
         b += align_up(4 * un) * 2;                      // quotient counts, members
         b += align_up(8 * (un + 1));                    // member offsets
         b += align_up(8 * (size_t)scan_parts(n));       // scan partials
+        b += align_up(4 * un) + align_up(4);            // large coarse rows and their count
     }
     return b;
 }
@@ -501,6 +502,8 @@ bool carve(void *base, size_t bytes, int64_t n, int op, Workspace *ws) {
         ws->q.members = (int32_t *)take(4 * un);
         ws->q.moff = (int64_t *)take(8 * (un + 1));
         ws->q.part = (unsigned long long *)take(8 * (size_t)scan_parts(n));
+        ws->q.big = (int32_t *)take(4 * un);
+        ws->q.big_count = (uint32_t *)take(4);
     }
     return true;
 }
@@ -766,7 +769,7 @@ int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
 int quotient_impl(mis2_ctx *ctx, const mis2_graph *g, const int32_t *agg, int64_t n_agg,
                   int64_t *crow, int32_t *ccol, int64_t *nnz_out, const Workspace &ws,
                   hipStream_t s) {
-    QuotientWs q{ws.q.cnt, ws.q.moff, ws.q.members, ws.q.part};
+    QuotientWs q{ws.q.cnt, ws.q.moff, ws.q.members, ws.q.part, ws.q.big, ws.q.big_count};
     HIP_TRY(ctx, quotient_graph(g->row_ptr, g->col, g->n, agg, n_agg, crow, ccol, q, s));
     int64_t nnz = 0;
     HIP_TRY(ctx, hipMemcpyAsync(&ctx->pinned[0], crow + n_agg, sizeof(int64_t),
@@ -794,7 +797,7 @@ namespace mis2 {
 
 size_t batch_bytes(int32_t G, int64_t n, int64_t nnz) {
     const size_t ug = (size_t)G + 1;
-    return coarsen_bytes(n, nnz) + align_up(4 * (size_t)n) + 3 * align_up(8 * ug) +
+    return coarsen_bytes(n, nnz) + 2 * align_up(4 * (size_t)n) + 3 * align_up(8 * ug) +
            3 * align_up(4 * ug) + 2 * align_up(ug);
 }
 
@@ -813,6 +816,7 @@ BatchArena carve_batch_arena(void *base, int32_t G, int64_t n, int64_t nnz) {
     }
     const size_t ug = (size_t)G + 1;
     a.map = (int32_t *)take(4 * (size_t)n);
+    a.gid = (int32_t *)take(4 * (size_t)n);
     a.voff = (int64_t *)take(8 * ug);
     a.newoff = (int64_t *)take(8 * ug);
     a.bnd = (int64_t *)take(8 * ug);
@@ -840,6 +844,8 @@ int batch_level(mis2_ctx *ctx, const mis2_graph &cur, uint64_t seed, int64_t sto
     bt.gb = ar.gb;
     bt.G = cg;
     while ((int64_t{1} << bt.steps) < (int64_t)cg + 1) bt.steps++;
+    HIP_TRY(ctx, launch_graph_ids(cur.n, bt, ar.gid, s));
+    bt.gid = ar.gid;
     BatchScope scope{ctx};
     ctx->batch = bt;
 
@@ -880,7 +886,7 @@ int batch_level(mis2_ctx *ctx, const mis2_graph &cur, uint64_t seed, int64_t sto
     bl->n_next = n_next;
     bl->nnz_next = 0;
     if (n_next > 0) {
-        QuotientWs q{ws.q.cnt, ws.q.moff, ws.q.members, ws.q.part};
+        QuotientWs q{ws.q.cnt, ws.q.moff, ws.q.members, ws.q.part, ws.q.big, ws.q.big_count};
         HIP_TRY(ctx, quotient_graph(cur.row_ptr, cur.col, cur.n, ar.map, n_next, crow_next,
                                     ccol_next, q, s));
         HIP_TRY(ctx, hipMemcpyAsync(&ctx->pinned[0], crow_next + n_next, sizeof(int64_t),

@@ -67,6 +67,15 @@ __global__ __launch_bounds__(kBlock) void k_batch_local(int64_t n, BatchInfo bt,
     }
 }
 
+// gid[v] = graph of union vertex v (by binary search over the offsets).
+__global__ __launch_bounds__(kBlock) void k_graph_ids(int64_t n, BatchInfo bt,
+                                                      int32_t *__restrict__ gid) {
+    bt.gid = nullptr;
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * kBlock)
+        gid[v] = graph_of(bt, v);
+}
+
 // out[i] = src[idx[i]], i < count.
 __global__ __launch_bounds__(kBlock) void k_gather_i64(const int64_t *__restrict__ src,
                                                        const int64_t *__restrict__ idx,
@@ -98,6 +107,12 @@ hipError_t launch_batch_local(int64_t n, const BatchInfo &bt, const uint32_t *P1
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_local, dim3(grid_of(n, 8192)), dim3(kBlock), 0, s, n, bt, P1, P2,
                        agg, live, cont, newoff, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_graph_ids(int64_t n, const BatchInfo &bt, int32_t *gid, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_graph_ids, dim3(grid_of(n, 8192)), dim3(kBlock), 0, s, n, bt, gid);
     return hipGetLastError();
 }
 

@@ -55,6 +55,7 @@ __host__ __device__ __forceinline__ uint64_t xs64star(uint64_t x) {
 struct BatchInfo {
     const int64_t *voff = nullptr;  // device [G + 1]
     const uint32_t *gb = nullptr;   // device [G]
+    const int32_t *gid = nullptr;   // device [n]: graph of each union vertex (or null)
     int32_t G = 0;
     int32_t steps = 0;              // binary-search steps, ceil(log2(G + 1))
 };
@@ -67,8 +68,10 @@ struct TupleParams {
     BatchInfo batch;
 };
 
-// Graph of union vertex v (fixed trip count, the same in every lane).
+// Graph of union vertex v: one load from the per-vertex table when there is
+// one, else a binary search (fixed trip count, the same in every lane).
 __device__ __forceinline__ int32_t graph_of(const BatchInfo &bt, int64_t v) {
+    if (bt.gid) return bt.gid[v];
     int32_t lo = 0, hi = bt.G;
     for (int k = 0; k < bt.steps; k++) {
         const int32_t mid = (lo + hi) >> 1;
@@ -131,6 +134,8 @@ struct Workspace {
         int64_t *moff = nullptr;
         int32_t *members = nullptr;
         unsigned long long *part = nullptr;
+        int32_t *big = nullptr;
+        uint32_t *big_count = nullptr;
     } q;
 };
 
@@ -233,6 +238,8 @@ struct QuotientWs {
     int64_t *moff;              // [n_agg + 1] member offsets
     int32_t *members;           // [n]
     unsigned long long *part;   // [scan_parts(n)]
+    int32_t *big;               // [n_agg] coarse rows left to whole workgroups
+    uint32_t *big_count;        // [1]
 };
 hipError_t quotient_graph(const int64_t *row_ptr, const int32_t *col, int64_t n, const int32_t *agg,
                           int64_t n_agg, int64_t *crow, int32_t *ccol, const QuotientWs &q,
@@ -247,6 +254,7 @@ hipError_t launch_batch_local(int64_t n, const BatchInfo &bt, const uint32_t *P1
                               hipStream_t s);
 hipError_t launch_gather_i64(const int64_t *src, const int64_t *idx, int64_t count, int64_t *out,
                              hipStream_t s);
+hipError_t launch_graph_ids(int64_t n, const BatchInfo &bt, int32_t *gid, hipStream_t s);
 
 // aggregate.hip
 hipError_t launch_label_roots(int64_t n, const int64_t *row_ptr, const int32_t *col,
@@ -271,6 +279,7 @@ struct BatchArena {
     int64_t *crow[2];      // [n + 1]
     int32_t *ccol[2];      // [nnz]
     int32_t *map;          // [n]
+    int32_t *gid;          // [n]
     int64_t *voff, *newoff, *bnd;  // [G + 1]
     uint32_t *gb, *P1, *P2;        // [G + 1]
     uint8_t *cont, *live;          // [G + 1]

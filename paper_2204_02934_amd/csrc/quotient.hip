@@ -9,13 +9,15 @@
 // for graphs that stop coarsening) and edges to it are dropped.
 //
 // Member lists are built by a counting sort (their order does not matter:
-// every coarse row is a sorted set).  One workgroup then handles one coarse
-// row: it gathers the aggregate ids of its members' neighbours into LDS and
-// sorts them with a bitonic network (up to kQCap candidates), or, for rows
-// with more candidates, sweeps the coarse id space in windows of
-// 32*kQCap ids with an LDS bitmap, which emits ids in increasing order.  The
-// same kernel runs twice: once to count each row, once (after a prefix sum)
-// to write it.
+// every coarse row is a sorted set).  A coarse row whose members have at most
+// kWCap stored entries in all is handled by one wavefront: it gathers the
+// aggregate ids of the members' neighbours into its own LDS buffer, sorts
+// them with a bitonic network and keeps the first of each run.  Larger rows
+// are listed and handled by a whole workgroup each: the same gather and sort
+// for up to kQCap candidates, else a sweep over the coarse id space in
+// windows of 32*kQCap ids with an LDS bitmap, which emits ids in increasing
+// order.  Both kernels run twice: once to count each row, once (after a
+// prefix sum) to write it.
 #include "internal.h"
 
 namespace mis2 {
@@ -25,6 +27,110 @@ namespace {
 constexpr int kQCap = 4096;                  // candidates sorted in LDS per coarse row
 constexpr int64_t kQWindow = 32 * kQCap;     // coarse ids per bitmap window
 constexpr int kWaves = kBlock / 64;
+constexpr int kWCap = 512;                   // candidates of a row handled by one wavefront
+constexpr int kWEdges = 8;                   // entries per lane loaded together
+
+__device__ __forceinline__ uint64_t below_mask(int lane) {
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Coarse rows with at most kWCap candidates, one wavefront each (the others
+// are appended to big[] by the counting pass).  FILL = false: ccnt[a];
+// FILL = true: ccol[crow[a] ...].
+template <bool FILL>
+__global__ __launch_bounds__(kBlock) void k_coarse_rows_wave(
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const int32_t *__restrict__ agg, int64_t n_agg, const int64_t *__restrict__ moff,
+    const int32_t *__restrict__ members, uint32_t *__restrict__ ccnt,
+    const int64_t *__restrict__ crow, int32_t *__restrict__ ccol, int32_t *__restrict__ big,
+    uint32_t *__restrict__ big_count) {
+    __shared__ uint32_t bufs[kWaves][kWCap];
+    uint32_t *buf = bufs[threadIdx.x >> 6];
+    const int lane = (int)(threadIdx.x & 63u);
+    const int64_t nw = (int64_t)gridDim.x * kWaves;
+    for (int64_t a = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); a < n_agg; a += nw) {
+        const int64_t m0 = moff[a], m1 = moff[a + 1];
+        // candidates: stored entries of all members
+        unsigned long long cand = 0;
+        for (int64_t i = m0 + lane; i < m1; i += 64) {
+            const int32_t v = members[i];
+            cand += (unsigned long long)(row_ptr[v + 1] - row_ptr[v]);
+        }
+        for (int off = 32; off > 0; off >>= 1) cand += __shfl_xor(cand, off, 64);
+        if (cand > (unsigned long long)kWCap) {
+            if (!FILL && lane == 0) big[atomicAdd(big_count, 1u)] = (int32_t)a;
+            continue;
+        }
+        // gather: each lane takes one member at a time and loads kWEdges of
+        // its entries together; survivors are appended in ballot order
+        uint32_t m = 0;
+        for (int64_t i0 = m0; i0 < m1; i0 += 64) {
+            const int64_t i = i0 + lane;
+            int64_t s = 0, e = 0;
+            if (i < m1) {
+                const int32_t v = members[i];
+                s = row_ptr[v];
+                e = row_ptr[v + 1];
+            }
+            int64_t len = e - s, lmax = len;
+            for (int off = 32; off > 0; off >>= 1) lmax = max(lmax, __shfl_xor(lmax, off, 64));
+            for (int64_t c0 = 0; c0 < lmax; c0 += kWEdges) {
+                int32_t x[kWEdges];
+#pragma unroll
+                for (int k = 0; k < kWEdges; k++) x[k] = col[c0 + k < len ? s + c0 + k : 0];
+                int32_t c[kWEdges];
+#pragma unroll
+                for (int k = 0; k < kWEdges; k++) c[k] = agg[x[k]];
+#pragma unroll
+                for (int k = 0; k < kWEdges; k++) {
+                    const bool keep = c0 + k < len && c[k] >= 0 && (int64_t)c[k] != a;
+                    const uint64_t mask = __ballot(keep);
+                    if (keep) buf[m + (uint32_t)__popcll(mask & below_mask(lane))] = (uint32_t)c[k];
+                    m += (uint32_t)__popcll(mask);
+                }
+            }
+        }
+        uint32_t P = 1;
+        while (P < m) P <<= 1;
+        for (uint32_t i = m + lane; i < P; i += 64) buf[i] = 0xFFFFFFFFu;
+        wave_sync();
+        // bitonic sort of buf[0..P)
+        for (uint32_t k = 2; k <= P; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                for (uint32_t i = lane; i < P; i += 64) {
+                    const uint32_t ixj = i ^ j;
+                    if (ixj > i) {
+                        const uint32_t x = buf[i], y = buf[ixj];
+                        const bool up = (i & k) == 0;
+                        if ((x > y) == up) {
+                            buf[i] = y;
+                            buf[ixj] = x;
+                        }
+                    }
+                }
+                wave_sync();
+            }
+        }
+        // the first of each run of equal values, in order
+        uint32_t run = 0;
+        for (uint32_t c0 = 0; c0 < m; c0 += 64) {
+            const uint32_t i = c0 + (uint32_t)lane;
+            const bool first = i < m && (i == 0 || buf[i] != buf[i - 1]);
+            const uint64_t mask = __ballot(first);
+            if (FILL && first)
+                ccol[crow[a] + run + (uint32_t)__popcll(mask & below_mask(lane))] = (int32_t)buf[i];
+            run += (uint32_t)__popcll(mask);
+        }
+        if (!FILL && lane == 0) ccnt[a] = run;
+        wave_sync();
+    }
+}
 
 __global__ __launch_bounds__(kBlock) void k_member_count(int64_t n, const int32_t *__restrict__ agg,
                                                          uint32_t *__restrict__ cnt) {
@@ -83,6 +189,7 @@ __device__ __forceinline__ uint32_t block_excl(uint32_t x, uint32_t *scratch, ui
 
 // FILL = false: ccnt[a] = number of distinct coarse neighbours of row a.
 // FILL = true:  ccol[crow[a] ...] = those neighbours in increasing order.
+// The listed (large) coarse rows big[0 .. *big_count), one workgroup each.
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_coarse_rows(const int64_t *__restrict__ row_ptr,
                                                         const int32_t *__restrict__ col,
@@ -92,13 +199,17 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows(const int64_t *__restric
                                                         const int32_t *__restrict__ members,
                                                         uint32_t *__restrict__ ccnt,
                                                         const int64_t *__restrict__ crow,
-                                                        int32_t *__restrict__ ccol) {
+                                                        int32_t *__restrict__ ccol,
+                                                        const int32_t *__restrict__ big,
+                                                        const uint32_t *__restrict__ big_count) {
     __shared__ uint32_t buf[kQCap];
     __shared__ unsigned long long red[kWaves];
     __shared__ uint32_t scan_s[kWaves];
     __shared__ uint32_t fill_s;
     const int tid = (int)threadIdx.x;
-    for (int64_t a = blockIdx.x; a < n_agg; a += gridDim.x) {
+    const int64_t nbig = *big_count;
+    for (int64_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
+        const int64_t a = big[bi];
         const int64_t m0 = moff[a], m1 = moff[a + 1];
         unsigned long long cand = 0;
         for (int64_t i = m0 + tid; i < m1; i += kBlock) {
@@ -216,15 +327,27 @@ hipError_t quotient_graph(const int64_t *row_ptr, const int32_t *col, int64_t n,
     if (n > 0)
         hipLaunchKernelGGL(k_member_scatter, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s,
                            n, agg, q.moff, q.cnt, q.members);
-    const int blocks = grid_for(n_agg, 1, 16384);
-    if (n_agg > 0)
-        hipLaunchKernelGGL(k_coarse_rows<false>, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col,
+    const int wblocks = grid_for(n_agg, kWaves, 8192);
+    const int bblocks = 1024;
+    if ((e = launch_fill_u32(q.big_count, 0u, 1, s)) != hipSuccess) return e;
+    if (n_agg > 0) {
+        hipLaunchKernelGGL(k_coarse_rows_wave<false>, dim3(wblocks), dim3(kBlock), 0, s, row_ptr,
+                           col, agg, n_agg, q.moff, q.members, q.cnt, (const int64_t *)nullptr,
+                           (int32_t *)nullptr, q.big, q.big_count);
+        hipLaunchKernelGGL(k_coarse_rows<false>, dim3(bblocks), dim3(kBlock), 0, s, row_ptr, col,
                            agg, n_agg, q.moff, q.members, q.cnt, (const int64_t *)nullptr,
-                           (int32_t *)nullptr);
+                           (int32_t *)nullptr, (const int32_t *)q.big,
+                           (const uint32_t *)q.big_count);
+    }
     if ((e = exclusive_scan_u32_i64(q.cnt, n_agg, crow, q.part, s)) != hipSuccess) return e;
-    if (n_agg > 0)
-        hipLaunchKernelGGL(k_coarse_rows<true>, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col,
-                           agg, n_agg, q.moff, q.members, q.cnt, crow, ccol);
+    if (n_agg > 0) {
+        hipLaunchKernelGGL(k_coarse_rows_wave<true>, dim3(wblocks), dim3(kBlock), 0, s, row_ptr,
+                           col, agg, n_agg, q.moff, q.members, q.cnt, crow, ccol, q.big,
+                           q.big_count);
+        hipLaunchKernelGGL(k_coarse_rows<true>, dim3(bblocks), dim3(kBlock), 0, s, row_ptr, col,
+                           agg, n_agg, q.moff, q.members, q.cnt, crow, ccol,
+                           (const int32_t *)q.big, (const uint32_t *)q.big_count);
+    }
     return hipGetLastError();
 }
 
