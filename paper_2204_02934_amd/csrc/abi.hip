@@ -72,12 +72,12 @@ int lanes_for(const mis2_ctx *ctx, const mis2_graph *g) {
 }
 
 // Workgroups of the segmented sweeps: a multiple of 8 (one run of logical
-// blocks per XCD), about 512 vertices per workgroup, at most kMaxBlocks.
+// blocks per XCD), about 320 vertices per workgroup, at most kMaxBlocks.
 // Measured on gfx950 with the 27-point 100^3 graph: 2048 workgroups ran
-// MIS-2 in 0.53 ms, 4096 in 0.58 ms, 8192 in 0.72 ms.
+// MIS-2 in 0.49 ms, 3072 in 0.46 ms, 4096 in 0.47 ms.
 int blocks_for(const mis2_ctx *ctx, int64_t n) {
     if (ctx->plan.blocks) return ctx->plan.blocks;
-    int64_t b = (n + 511) / 512;
+    int64_t b = (n + 319) / 320;
     b = (b + 7) / 8 * 8;
     return (int)std::max<int64_t>(8, std::min<int64_t>(b, kMaxBlocks));
 }

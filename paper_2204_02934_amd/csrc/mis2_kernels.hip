@@ -34,8 +34,10 @@ constexpr int kUnroll = 4;  // rows per lane in flight (flat sweeps)
 // 2 * kRows * kChunks<L> independent loads per lane are in flight (32 column
 // indices per row for L <= 4).  Measured on gfx950 with the 27-point 100^3
 // graph: one chunk per batch took 55 us per full Refresh Column sweep, eight
-// chunks 30 us.
-constexpr int kRows = 2;
+// chunks 30 us.  One row per group (rather than 2 or 4) keeps the sweeps at
+// 64-80 registers, so more wavefronts stay resident: MIS-2 took 0.46 ms
+// against 0.49 ms with 2 rows and 0.61 ms with 4.
+constexpr int kRows = 1;
 template <int L>
 constexpr int kChunks = L >= 32 ? 1 : (32 / L > 8 ? 8 : 32 / L);
 
