@@ -245,18 +245,29 @@ __device__ __forceinline__ uint32_t sweep_column(const int64_t *__restrict__ row
     const int sub = lane & (L - 1);
     uint32_t kept = 0;
     unsigned long long dsum = 0;
-    for (int64_t i0 = 0; i0 < sg.count; i0 += G * U) {
-        int32_t v[U];
-        bool ok[U];
-        int64_t s[U], e[U];
-        uint32_t m[U];
-        load_rows<L, U>(io, sg, i0, v, ok);
+    // The rows of step i + 1 (list entries, extents, own T) are loaded while
+    // step i's column indices and gathers are in flight.
+    int32_t v[U];
+    bool ok[U];
+    int64_t s[U], e[U];
+    uint32_t m[U];
+    if (sg.count > 0) {
+        load_rows<L, U>(io, sg, 0, v, ok);
 #pragma unroll
         for (int u = 0; u < U; u++) {
             s[u] = row_ptr[v[u]];
             e[u] = row_ptr[v[u] + 1];
             m[u] = T[v[u]];
         }
+    }
+    for (int64_t i0 = 0; i0 < sg.count; i0 += G * U) {
+        const bool more = i0 + G * U < sg.count;
+        int32_t vn[U];
+        bool okn[U];
+        int64_t sn[U] = {}, en[U] = {};
+        uint32_t mn[U] = {};
+        if (more) load_rows<L, U>(io, sg, i0 + G * U, vn, okn);
+        bool fetched = !more;
 #pragma unroll
         for (int u = 0; u < U; u++) {
             if (!ok[u]) e[u] = s[u];
@@ -288,6 +299,15 @@ __device__ __forceinline__ uint32_t sweep_column(const int64_t *__restrict__ row
                     const int64_t j = s[u] + c0 + k * L + sub;
                     x[u][k] = col[j < e[u] ? j : 0];
                 }
+            if (!fetched) {
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    sn[u] = row_ptr[vn[u]];
+                    en[u] = row_ptr[vn[u] + 1];
+                    mn[u] = T[vn[u]];
+                }
+                fetched = true;
+            }
             uint32_t t[U][K];
 #pragma unroll
             for (int u = 0; u < U; u++)
@@ -298,6 +318,14 @@ __device__ __forceinline__ uint32_t sweep_column(const int64_t *__restrict__ row
 #pragma unroll
                 for (int k = 0; k < K; k++)
                     if (s[u] + c0 + k * L + sub < e[u]) m[u] = min(m[u], t[u][k]);
+        }
+        if (!fetched) {
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                sn[u] = row_ptr[vn[u]];
+                en[u] = row_ptr[vn[u] + 1];
+                mn[u] = T[vn[u]];
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -311,6 +339,16 @@ __device__ __forceinline__ uint32_t sweep_column(const int64_t *__restrict__ row
                 keep = (m[u] != kOut);
             }
             seg_append(io, sg, keep, v[u], kept);
+        }
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                v[u] = vn[u];
+                ok[u] = okn[u];
+                s[u] = sn[u];
+                e[u] = en[u];
+                m[u] = mn[u];
+            }
         }
     }
     if (io.deg_sum) wave_degsum(io.deg_sum, dsum);
@@ -331,13 +369,14 @@ __device__ __forceinline__ uint32_t sweep_decide(const int64_t *__restrict__ row
     const int sub = lane & (L - 1);
     uint32_t kept = 0;
     unsigned long long dsum = 0;
-    for (int64_t i0 = 0; i0 < sg.count; i0 += G * U) {
-        int32_t v[U];
-        bool ok[U];
-        int64_t s[U], e[U];
-        uint32_t t0[U], mv[U];
-        int any_out[U], all_eq[U];
-        load_rows<L, U>(io, sg, i0, v, ok);
+    // The rows of step i + 1 are loaded while step i's gathers are in flight
+    // (as in sweep_column).
+    int32_t v[U];
+    bool ok[U];
+    int64_t s[U], e[U];
+    uint32_t t0[U], mv[U];
+    if (sg.count > 0) {
+        load_rows<L, U>(io, sg, 0, v, ok);
 #pragma unroll
         for (int u = 0; u < U; u++) {
             s[u] = row_ptr[v[u]];
@@ -345,6 +384,16 @@ __device__ __forceinline__ uint32_t sweep_decide(const int64_t *__restrict__ row
             t0[u] = T[v[u]];
             mv[u] = M[v[u]];
         }
+    }
+    for (int64_t i0 = 0; i0 < sg.count; i0 += G * U) {
+        const bool more = i0 + G * U < sg.count;
+        int32_t vn[U];
+        bool okn[U];
+        int64_t sn[U] = {}, en[U] = {};
+        uint32_t tn[U] = {}, mvn[U] = {};
+        if (more) load_rows<L, U>(io, sg, i0 + G * U, vn, okn);
+        bool fetched = !more;
+        int any_out[U], all_eq[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
             if (!ok[u]) e[u] = s[u];
@@ -384,6 +433,16 @@ __device__ __forceinline__ uint32_t sweep_decide(const int64_t *__restrict__ row
                     const int64_t j = s[u] + c0 + k * L + sub;
                     x[u][k] = col[j < e[u] ? j : 0];
                 }
+            if (!fetched) {
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    sn[u] = row_ptr[vn[u]];
+                    en[u] = row_ptr[vn[u] + 1];
+                    tn[u] = T[vn[u]];
+                    mvn[u] = M[vn[u]];
+                }
+                fetched = true;
+            }
             uint32_t mw[U][K];
 #pragma unroll
             for (int u = 0; u < U; u++)
@@ -398,6 +457,15 @@ __device__ __forceinline__ uint32_t sweep_decide(const int64_t *__restrict__ row
                         all_eq[u] &= (mw[u][k] == t0[u]) | (mw[u][k] == kAbsent);
                     }
                 }
+        }
+        if (!fetched) {
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                sn[u] = row_ptr[vn[u]];
+                en[u] = row_ptr[vn[u] + 1];
+                tn[u] = T[vn[u]];
+                mvn[u] = M[vn[u]];
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -420,6 +488,17 @@ __device__ __forceinline__ uint32_t sweep_decide(const int64_t *__restrict__ row
                 T[v[u]] = nt;
             }
             seg_append(io, sg, keep, v[u], kept);
+        }
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                v[u] = vn[u];
+                ok[u] = okn[u];
+                s[u] = sn[u];
+                e[u] = en[u];
+                t0[u] = tn[u];
+                mv[u] = mvn[u];
+            }
         }
     }
     if (io.deg_sum) wave_degsum(io.deg_sum, dsum);
