@@ -204,6 +204,7 @@ int run_rounds_persistent(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, con
     a.rt = ws.rt;
     a.ctr = ws.ctr;
     a.degs = ctx->account ? degs : nullptr;
+    a.dsplit = ctx->account ? ws.dsplit : nullptr;
     a.bar = ws.bar;
     a.n = g->n;
     a.seg = gm.seg;
@@ -278,6 +279,7 @@ RoundsArgs round_args(const mis2_ctx *ctx, const mis2_graph *g, uint64_t seed,
     a.ctr = ws.ctr;
     a.alive_host = ctx->alive_host;
     a.degs = ctx->account ? degs : nullptr;
+    a.dsplit = ctx->account ? ws.dsplit : nullptr;
     a.bar = ws.bar;
     a.n = g->n;
     a.seg = gm.seg;
@@ -295,7 +297,10 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
                std::vector<Launch> *launches) {
     const int lanes = lanes_for(ctx, g);
     unsigned long long *degs = ws.degs + (size_t)phase * kTraceCap * 2;
-    if (ctx->account) HIP_TRY(ctx, launch_fill_u64(degs, 0ull, 2 * kTraceCap, s));
+    if (ctx->account) {
+        HIP_TRY(ctx, launch_fill_u64(degs, 0ull, 2 * kTraceCap, s));
+        HIP_TRY(ctx, launch_fill_u64(ws.dsplit, 0ull, 2 * (int64_t)kSplit * 16, s));
+    }
     // size counters: every ring slot zero except slot 0 of a masked start,
     // which holds its active count; each Refresh Column clears the slot two
     // rounds ahead.
@@ -338,17 +343,11 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
                 ld.e0 = take_event(ctx), ld.e1 = take_event(ctx);
                 if (!lc.e0 || !lc.e1 || !ld.e0 || !ld.e1)
                     return fail(ctx, MIS2_EHIP, "hipEventCreate failed");
-                HIP_TRY(ctx, hipEventRecord(lc.e0, s));
             }
             HIP_TRY(ctx, launch_col_round(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
-                                          a, round, s));
-            if (ctx->profile) {
-                HIP_TRY(ctx, hipEventRecord(lc.e1, s));
-                HIP_TRY(ctx, hipEventRecord(ld.e0, s));
-            }
+                                          a, round, s, lc.e0, lc.e1));
             HIP_TRY(ctx, launch_dec_round(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
-                                          a, round, s));
-            if (ctx->profile) HIP_TRY(ctx, hipEventRecord(ld.e1, s));
+                                          a, round, s, ld.e0, ld.e1));
             launches->push_back(lc);
             launches->push_back(ld);
             round++;
@@ -451,6 +450,7 @@ size_t workspace_bytes(int64_t n, int op) {
     b += align_up(4 * (size_t)kCtrRing * kCtrSlot);     // size counters
     b += align_up(4 * kScalars);                        // scalars
     b += align_up(8 * 2 * 2 * (size_t)kTraceCap);       // degs
+    b += align_up(8 * 2 * (size_t)kSplit * 16);         // their partial sums
     b += align_up(4 * (size_t)(compact_blocks(n) + 1)); // blocksum
     b += align_up(4 * (size_t)kBarWords);               // barrier state
     if (op != MIS2_OP_MIS2) {
@@ -489,6 +489,7 @@ bool carve(void *base, size_t bytes, int64_t n, int op, Workspace *ws) {
     ws->ctr = (uint32_t *)take(4 * (size_t)kCtrRing * kCtrSlot);
     ws->scalars = (uint32_t *)take(4 * kScalars);
     ws->degs = (unsigned long long *)take(8 * 2 * 2 * (size_t)kTraceCap);
+    ws->dsplit = (unsigned long long *)take(8 * 2 * (size_t)kSplit * 16);
     ws->blocksum = (uint32_t *)take(4 * (size_t)(compact_blocks(n) + 1));
     ws->bar = (uint32_t *)take(4 * (size_t)kBarWords);
     if (op != MIS2_OP_MIS2) {

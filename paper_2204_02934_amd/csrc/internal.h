@@ -121,6 +121,7 @@ struct Workspace {
     uint32_t *ctr = nullptr;      // [kCtrRing][kCtrSlot] size counters
     uint32_t *scalars = nullptr;  // [kScalars]
     unsigned long long *degs = nullptr;  // [2][kTraceCap][2] row-length sums per sweep
+    unsigned long long *dsplit = nullptr;  // [2][kSplit][16] their partial sums in flight
     uint32_t *blocksum = nullptr; // [compact_blocks(n) + 1]
     uint32_t *bar = nullptr;      // [kBarWords] persistent-kernel barrier state
     // aggregation only
@@ -185,6 +186,7 @@ struct RoundsArgs {
     uint32_t *ctr;
     unsigned long long *alive_host;
     unsigned long long *degs;  // [kTraceCap][2] or null
+    unsigned long long *dsplit;  // [2][kSplit][16] partial row-length sums, or null
     uint32_t *bar;
     int64_t n, seg, S;
     uint64_t seed, pmask;
@@ -197,12 +199,14 @@ struct RoundsArgs {
 int rounds_max_blocks(int lanes, int num_cus);
 hipError_t launch_rounds(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                          uint32_t *T, uint32_t *M, const RoundsArgs &a, hipStream_t s);
+// e0 / e1 (may be null): events stamped by the launch itself at the kernel's
+// start and end.
 hipError_t launch_col_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                             const uint32_t *T, uint32_t *M, const RoundsArgs &a, int r,
-                            hipStream_t s);
+                            hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_dec_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                             uint32_t *T, const uint32_t *M, const RoundsArgs &a, int r,
-                            hipStream_t s);
+                            hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_init_tuples(const TupleParams &tp, int64_t n, uint32_t *T, hipStream_t s);
 hipError_t launch_init_masked(int blocks, const TupleParams &tp, int64_t n, const int32_t *label,
                               uint32_t *T, uint32_t *M, const SegIO &io, hipStream_t s);

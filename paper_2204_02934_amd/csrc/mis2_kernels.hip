@@ -22,6 +22,8 @@
 // Inside a wavefront a group of L lanes (a power of two up to 64) streams one
 // row's column indices (Section V-D uses SIMD lanes for the same coalescing)
 // and combines partial results with cross-lane shuffles.
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 
 namespace mis2 {
@@ -55,11 +57,30 @@ __device__ __forceinline__ int64_t wave_id() {
     return lb * (kBlock / 64) + (threadIdx.x >> 6);
 }
 
-// Sum of the L-lane groups' row lengths over the wavefront, added to *sum by
-// lane 0 (accounting runs only).
-__device__ __forceinline__ void wave_degsum(unsigned long long *sum, unsigned long long d) {
+// Sum of the L-lane groups' row lengths over the workgroup, added to one of
+// kSplit partial sums (stride kDegLine words, one cache line each) by thread
+// 0 (accounting runs only; fold_deg collects the partial sums).  All threads
+// must call it.
+constexpr int kDegLine = 16;
+__device__ __forceinline__ void wave_degsum(unsigned long long *split, unsigned long long d) {
+    __shared__ unsigned long long part[kBlock / 64];
     for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
-    if ((threadIdx.x & 63u) == 0 && d) atomicAdd(sum, d);
+    if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int k = 0; k < kBlock / 64; k++) t += part[k];
+        if (t) atomicAdd(&split[(blockIdx.x % kSplit) * kDegLine], t);
+    }
+}
+
+// *target += the kSplit partial sums, which are cleared (threads 0..63 of
+// one workgroup).
+__device__ __forceinline__ void fold_deg(unsigned long long *split, unsigned long long *target) {
+    unsigned long long x = split[(threadIdx.x & 63u) * kDegLine];
+    split[(threadIdx.x & 63u) * kDegLine] = 0ull;
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (threadIdx.x == 0) *target += x;
 }
 
 // The rows of wavefront w: either its identity range or its list segment.
@@ -798,7 +819,7 @@ __device__ __forceinline__ SegIO round_col_io(const RoundsArgs &a, int r) {
     io.wl_out = a.wl2[nxt];
     io.cnt_out = a.cnt2[nxt];
     io.trace_out = a.ctr + (size_t)((r + 1) % kCtrRing) * kCtrSlot + kCtrList;
-    io.deg_sum = a.degs ? a.degs + 2 * r + 1 : nullptr;
+    io.deg_sum = a.dsplit ? a.dsplit + (size_t)kSplit * kDegLine : nullptr;
     io.n = a.n;
     io.seg = a.seg;
     io.S = a.S;
@@ -814,7 +835,7 @@ __device__ __forceinline__ SegIO round_dec_io(const RoundsArgs &a, int r) {
     io.wl_out = a.wl1[nxt];
     io.cnt_out = a.cnt1[nxt];
     io.trace_out = a.ctr + (size_t)((r + 1) % kCtrRing) * kCtrSlot;
-    io.deg_sum = a.degs ? a.degs + 2 * r : nullptr;
+    io.deg_sum = a.dsplit;
     io.n = a.n;
     io.seg = a.seg;
     io.S = a.S;
@@ -972,6 +993,8 @@ __global__ __launch_bounds__(kBlock) void k_rounds(const int64_t *__restrict__ r
         seg_finish(cio, w, kept);
         if (!grid_barrier(flags, gen, abort_word, ++epoch)) break;
         if (blockIdx.x == 0 && threadIdx.x == 0) stamp(row_cur + kRtStamp1);
+        if (a.dsplit && blockIdx.x == 0 && threadIdx.x < 64)
+            fold_deg(a.dsplit + (size_t)kSplit * kDegLine, a.degs + 2 * r + 1);
         const SegIO dio = round_dec_io(a, r);
         const TupleParams next{xs64star((a.seed << 32) ^ (uint64_t)(r + 1)), a.pmask, a.b, a.batch};
         sg = seg_of(dio, w);
@@ -979,6 +1002,7 @@ __global__ __launch_bounds__(kBlock) void k_rounds(const int64_t *__restrict__ r
         seg_finish(dio, w, kept);
         if (!grid_barrier(flags, gen, abort_word, ++epoch)) break;
         if (blockIdx.x == 0 && threadIdx.x == 0) stamp(row_cur + kRtStamp2);
+        if (a.dsplit && blockIdx.x == 0 && threadIdx.x < 64) fold_deg(a.dsplit, a.degs + 2 * r);
         r++;
         // sizes at the start of round r; every workgroup needs worklist1's
         if (threadIdx.x < 64) {
@@ -998,6 +1022,11 @@ __global__ __launch_bounds__(kBlock) void k_rounds(const int64_t *__restrict__ r
         if (alive == 0u || r + 2 >= a.max_rounds) break;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) st_agent(a.bar + kMaxBlocks + 32, (uint32_t)r);
+}
+
+__global__ __launch_bounds__(64) void k_fold_deg(unsigned long long *split,
+                                                 unsigned long long *target) {
+    fold_deg(split, target);
 }
 
 // Round-0 tuples for every vertex.
@@ -1135,19 +1164,43 @@ TupleParams tuple_params(int64_t n, uint64_t seed, uint64_t iter) {
         default: return hipErrorInvalidValue;                                           \
     }
 
+// With e0 / e1 the launch records its own start and end (the events time
+// the kernel alone, not the gap before it).
+#define MIS2_LANE_DISPATCH_TIMED(L, KERNEL, GRID, BLOCK, S, E0, E1, ...)                 \
+    if (E0) {                                                                           \
+        switch (L) {                                                                    \
+            case 0: hipExtLaunchKernelGGL(KERNEL<0>, GRID, BLOCK, 0, S, E0, E1, 0, __VA_ARGS__); break;  \
+            case 1: hipExtLaunchKernelGGL(KERNEL<1>, GRID, BLOCK, 0, S, E0, E1, 0, __VA_ARGS__); break;  \
+            case 2: hipExtLaunchKernelGGL(KERNEL<2>, GRID, BLOCK, 0, S, E0, E1, 0, __VA_ARGS__); break;  \
+            case 4: hipExtLaunchKernelGGL(KERNEL<4>, GRID, BLOCK, 0, S, E0, E1, 0, __VA_ARGS__); break;  \
+            case 8: hipExtLaunchKernelGGL(KERNEL<8>, GRID, BLOCK, 0, S, E0, E1, 0, __VA_ARGS__); break;  \
+            case 16: hipExtLaunchKernelGGL(KERNEL<16>, GRID, BLOCK, 0, S, E0, E1, 0, __VA_ARGS__); break; \
+            case 32: hipExtLaunchKernelGGL(KERNEL<32>, GRID, BLOCK, 0, S, E0, E1, 0, __VA_ARGS__); break; \
+            case 64: hipExtLaunchKernelGGL(KERNEL<64>, GRID, BLOCK, 0, S, E0, E1, 0, __VA_ARGS__); break; \
+            default: return hipErrorInvalidValue;                                       \
+        }                                                                               \
+    } else {                                                                            \
+        MIS2_LANE_DISPATCH(L, KERNEL, GRID, BLOCK, 0, S, __VA_ARGS__);                  \
+    }
+
 hipError_t launch_col_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                             const uint32_t *T, uint32_t *M, const RoundsArgs &a, int r,
-                            hipStream_t s) {
-    MIS2_LANE_DISPATCH(lanes, k_col_round, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col, T, M,
-                       a, r);
+                            hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    MIS2_LANE_DISPATCH_TIMED(lanes, k_col_round, dim3(blocks), dim3(kBlock), s, e0, e1, row_ptr,
+                             col, T, M, a, r);
+    if (a.dsplit) {
+        hipLaunchKernelGGL(k_fold_deg, dim3(1), dim3(64), 0, s, a.dsplit + (size_t)kSplit * kDegLine,
+                           a.degs + 2 * r + 1);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_dec_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                             uint32_t *T, const uint32_t *M, const RoundsArgs &a, int r,
-                            hipStream_t s) {
-    MIS2_LANE_DISPATCH(lanes, k_dec_round, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col, T, M,
-                       a, r);
+                            hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    MIS2_LANE_DISPATCH_TIMED(lanes, k_dec_round, dim3(blocks), dim3(kBlock), s, e0, e1, row_ptr,
+                             col, T, M, a, r);
+    if (a.dsplit) hipLaunchKernelGGL(k_fold_deg, dim3(1), dim3(64), 0, s, a.dsplit, a.degs + 2 * r);
     return hipGetLastError();
 }
 
