@@ -746,12 +746,19 @@ int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
     SegIO p3_io{};
     p3_io.wl_in = ws.wl2[0];
     p3_io.cnt_in = ws.cnt2[0];
+    p3_io.wl_out = ws.wl1[1];  // long rows, for the second kernel
+    p3_io.cnt_out = ws.cnt1[1];
     p3_io.n = n;
     p3_io.seg = gm.seg;
     p3_io.S = gm.S;
+    SegIO long_io = p3_io;
+    long_io.wl_in = ws.wl1[1];
+    long_io.cnt_in = ws.cnt1[1];
+    long_io.wl_out = nullptr;
+    long_io.cnt_out = nullptr;
     const int p3_lanes = lanes_for(ctx, g) > 0 ? lanes_for(ctx, g) : 4;
     HIP_TRY(ctx, launch_phase3(p3_lanes, gm.blocks, g->row_ptr, g->col, ws.label,
-                               ws.aggsize, p3_io, agg_id, sc + kS_Err, s));
+                               ws.aggsize, p3_io, long_io, agg_id, sc + kS_Err, s));
 
     HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, sc, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));

@@ -190,6 +190,17 @@ __global__ __launch_bounds__(kBlock) void k_list_unlabelled(int64_t n,
     if (lane == 0 && w < io.S) io.cnt_out[w] = kept;
 }
 
+__device__ __forceinline__ uint64_t lanes_below_p3(int lane) {
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Orders the wavefront's LDS accesses before and after it.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Candidate order of phase 3: larger coupling first, then smaller aggsize,
 // then smaller aggregate id.  Returns true if (c1, s1, a1) beats (c2, s2, a2).
 __device__ __forceinline__ bool better(int c1, int s1, int a1, int c2, int s2, int a2) {
@@ -246,11 +257,10 @@ __device__ __forceinline__ void p3_short(const int32_t *__restrict__ col,
     }
 }
 
-// One group of L lanes per unaggregated row of the wavefront's segment.  A
-// wavefront whose rows all fit K chunks of L takes p3_short; otherwise lane
-// j of chunk c1 holds the tent label of neighbour c1*L + j and its coupling
-// is counted over all chunks of the row with in-group broadcasts.  The
-// group's best candidate is then reduced with the candidate order above.
+// One group of L lanes per unaggregated row of the wavefront's segment.  Rows
+// of at most K chunks of L entries take p3_short; longer rows are listed, in
+// order, in the wavefront's segment of io.wl_out for k_phase3_long.  The
+// group's best candidate is reduced with the candidate order above.
 template <int L>
 __global__ __launch_bounds__(kBlock) void k_phase3(const int64_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col,
@@ -266,6 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_phase3(const int64_t *__restrict__ r
     constexpr int G = 64 / L;
     const int lane = (int)(threadIdx.x & 63u);
     const int sub = lane & (L - 1);
+    uint32_t kept = 0;
     for (int64_t i0 = 0; i0 < count; i0 += G) {
         const int64_t i = i0 + lane / L;
         const bool valid = i < count;
@@ -276,35 +287,12 @@ __global__ __launch_bounds__(kBlock) void k_phase3(const int64_t *__restrict__ r
             s = row_ptr[v];
             e = row_ptr[v + 1];
         }
-        // every lane of the wavefront runs the same number of chunk steps
-        int64_t chunks = (e - s + L - 1) / L;
-        int64_t wmax = chunks;
+        const bool is_long = e - s > (int64_t)K * L;
+        const int64_t es = is_long ? s : e;  // long rows are left to k_phase3_long
+        int64_t wmax = (es - s + L - 1) / L;
         for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off, 64));
         int bc = 0, bs = 0x7FFFFFFF, ba = 0x7FFFFFFF;
-        if (wmax > 0 && wmax <= K) {
-            p3_short<L, K>(col, label, aggsize, s, e, sub, bc, bs, ba);
-        } else {
-            for (int64_t c1 = 0; c1 < wmax; c1++) {
-                const int64_t j = s + c1 * L + sub;
-                const int32_t a = (c1 < chunks && j < e) ? label[col[j]] : kPad;
-                int cnt = 0;
-                for (int64_t c2 = 0; c2 < wmax; c2++) {
-                    const int64_t j2 = s + c2 * L + sub;
-                    const int32_t a2 =
-                        c2 == c1 ? a : ((c2 < chunks && j2 < e) ? label[col[j2]] : kPad);
-#pragma unroll
-                    for (int t = 0; t < L; t++) cnt += (__shfl(a2, t, L) == a);
-                }
-                if (a >= 0) {
-                    const int sz = aggsize[a];
-                    if (better(cnt, sz, a, bc, bs, ba)) {
-                        bc = cnt;
-                        bs = sz;
-                        ba = a;
-                    }
-                }
-            }
-        }
+        if (wmax > 0) p3_short<L, K>(col, label, aggsize, s, es, sub, bc, bs, ba);
 #pragma unroll
         for (int off = L / 2; off > 0; off >>= 1) {
             const int oc = __shfl_xor(bc, off, L);
@@ -316,7 +304,127 @@ __global__ __launch_bounds__(kBlock) void k_phase3(const int64_t *__restrict__ r
                 ba = oa;
             }
         }
-        if (valid && sub == 0) {
+        if (valid && sub == 0 && !is_long) {
+            if (bc > 0)
+                agg_out[v] = ba;
+            else
+                atomicOr(err, 1u);
+        }
+        const bool keep = valid && sub == 0 && is_long;
+        const uint64_t mask = __ballot(keep);
+        if (keep) io.wl_out[sbase + kept + (uint32_t)__popcll(mask & lanes_below_p3(lane))] = v;
+        kept += (uint32_t)__popcll(mask);
+    }
+    if (lane == 0) io.cnt_out[w] = kept;
+}
+
+// Long unaggregated rows, one at a time per wavefront: the couplings are
+// counted in an LDS hash map (aggregate id -> count; kP3Slots slots, so any
+// row of up to kP3Slots entries fits), then the wavefront reduces its entries
+// with the candidate order.  Rows longer than that count each label against
+// the whole row, 64 labels at a time.
+constexpr int kP3Slots = 2048;
+__device__ __forceinline__ uint32_t p3hash(uint32_t a) { return (a * 2654435761u) >> 21; }
+
+__device__ __forceinline__ void p3_reduce(int &bc, int &bs, int &ba) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const int oc = __shfl_xor(bc, off, 64);
+        const int os = __shfl_xor(bs, off, 64);
+        const int oa = __shfl_xor(ba, off, 64);
+        if (better(oc, os, oa, bc, bs, ba)) {
+            bc = oc;
+            bs = os;
+            ba = oa;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_phase3_long(const int64_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ col,
+                                                        const int32_t *__restrict__ label,
+                                                        const int32_t *__restrict__ aggsize,
+                                                        SegIO io, int32_t *__restrict__ agg_out,
+                                                        uint32_t *__restrict__ err) {
+    static_assert(kP3Slots == 2048, "p3hash yields 11 bits");
+    constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+    __shared__ uint32_t keys_s[kBlock / 64][kP3Slots];
+    __shared__ uint32_t cnts_s[kBlock / 64][kP3Slots];
+    const int64_t w = wave_id();
+    if (w >= io.S) return;
+    uint32_t *keys = keys_s[threadIdx.x >> 6];
+    uint32_t *cnts = cnts_s[threadIdx.x >> 6];
+    const int lane = (int)(threadIdx.x & 63u);
+    const int64_t count = io.cnt_in[w];
+    const int64_t sbase = w * io.seg;
+    for (int64_t i = 0; i < count; i++) {
+        const int32_t v = io.wl_in[sbase + i];
+        const int64_t s = row_ptr[v], e = row_ptr[v + 1];
+        int bc = 0, bs = 0x7FFFFFFF, ba = 0x7FFFFFFF;
+        if (e - s <= kP3Slots) {
+            for (int k = lane; k < kP3Slots; k += 64) {
+                keys[k] = kEmpty;
+                cnts[k] = 0u;
+            }
+            wave_lds_sync();
+            for (int64_t j0 = s; j0 < e; j0 += 64 * kCoopLoads) {
+                int32_t x[kCoopLoads];
+#pragma unroll
+                for (int k = 0; k < kCoopLoads; k++) {
+                    const int64_t j = j0 + (int64_t)k * 64 + lane;
+                    x[k] = col[j < e ? j : s];
+                }
+                int32_t a[kCoopLoads];
+#pragma unroll
+                for (int k = 0; k < kCoopLoads; k++) a[k] = label[x[k]];
+#pragma unroll
+                for (int k = 0; k < kCoopLoads; k++) {
+                    if (j0 + (int64_t)k * 64 + lane < e && a[k] >= 0) {
+                        const uint32_t key = (uint32_t)a[k];
+                        uint32_t h = p3hash(key);
+                        for (;;) {  // the map has a slot for every entry of the row
+                            const uint32_t prev = atomicCAS(&keys[h], kEmpty, key);
+                            if (prev == kEmpty || prev == key) break;
+                            h = (h + 1) & (kP3Slots - 1);
+                        }
+                        atomicAdd(&cnts[h], 1u);
+                    }
+                }
+            }
+            wave_lds_sync();
+            for (int k = lane; k < kP3Slots; k += 64) {
+                const uint32_t key = keys[k];
+                if (key != kEmpty) {
+                    const int c = (int)cnts[k], sz = aggsize[key];
+                    if (better(c, sz, (int)key, bc, bs, ba)) {
+                        bc = c;
+                        bs = sz;
+                        ba = (int)key;
+                    }
+                }
+            }
+            wave_lds_sync();
+        } else {
+            for (int64_t c1 = s; c1 < e; c1 += 64) {
+                const int64_t j = c1 + lane;
+                const int32_t a = j < e ? label[col[j]] : kPad;
+                int cnt = 0;
+                for (int64_t c2 = s; c2 < e; c2 += 64) {
+                    const int64_t j2 = c2 + lane;
+                    const int32_t a2 = j2 < e ? label[col[j2]] : kPad;
+                    for (int t = 0; t < 64; t++) cnt += (__shfl(a2, t, 64) == a);
+                }
+                if (a >= 0) {
+                    const int sz = aggsize[a];
+                    if (better(cnt, sz, a, bc, bs, ba)) {
+                        bc = cnt;
+                        bs = sz;
+                        ba = a;
+                    }
+                }
+            }
+        }
+        p3_reduce(bc, bs, ba);
+        if (lane == 0) {
             if (bc > 0)
                 agg_out[v] = ba;
             else
@@ -379,9 +487,11 @@ hipError_t launch_list_unlabelled(int blocks, int64_t n, const int32_t *label, c
 
 hipError_t launch_phase3(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                          const int32_t *label, const int32_t *aggsize, const SegIO &io,
-                         int32_t *agg_out, uint32_t *err, hipStream_t s) {
+                         const SegIO &io_long, int32_t *agg_out, uint32_t *err, hipStream_t s) {
     MIS2_P3_DISPATCH(lanes, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col, label, aggsize, io,
                      agg_out, err);
+    hipLaunchKernelGGL(k_phase3_long, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col, label,
+                       aggsize, io_long, agg_out, err);
     return hipGetLastError();
 }
 

@@ -271,9 +271,11 @@ hipError_t launch_accept_phase2(int64_t n, const int64_t *row_ptr, const int32_t
 hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStream_t s);
 hipError_t launch_list_unlabelled(int blocks, int64_t n, const int32_t *label, const SegIO &io,
                                   hipStream_t s);
+// io: the unaggregated rows (wl_in / cnt_in) and the list of long rows it
+// leaves (wl_out / cnt_out); io_long: that list as input.
 hipError_t launch_phase3(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                          const int32_t *label, const int32_t *aggsize, const SegIO &io,
-                         int32_t *agg_out, uint32_t *err, hipStream_t s);
+                         const SegIO &io_long, int32_t *agg_out, uint32_t *err, hipStream_t s);
 
 // Batched coarsening (abi.hip).  The arena is the caller's workspace: the
 // coarsening workspace of the union, two coarse-union CSR buffers, the

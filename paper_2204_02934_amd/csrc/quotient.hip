@@ -10,9 +10,9 @@
 //
 // Member lists are built by a counting sort (their order does not matter:
 // every coarse row is a sorted set).  A coarse row whose members have at most
-// kWCap stored entries in all is handled by one wavefront: it gathers the
-// aggregate ids of the members' neighbours into its own LDS buffer, sorts
-// them with a bitonic network and keeps the first of each run.  Larger rows
+// kWCap stored entries in all is handled by one wavefront: it puts the
+// aggregate ids of the members' neighbours into an LDS hash set and sorts the
+// distinct ones.  Larger rows
 // are listed and handled by a whole workgroup each: the same gather and sort
 // for up to kQCap candidates, else a sweep over the coarse id space in
 // windows of 32*kQCap ids with an LDS bitmap, which emits ids in increasing
@@ -27,8 +27,10 @@ namespace {
 constexpr int kQCap = 4096;                  // candidates sorted in LDS per coarse row
 constexpr int64_t kQWindow = 32 * kQCap;     // coarse ids per bitmap window
 constexpr int kWaves = kBlock / 64;
-constexpr int kWCap = 512;                   // candidates of a row handled by one wavefront
+constexpr int kWCap = 1024;                  // candidates of a row handled by one wavefront
 constexpr int kWEdges = 8;                   // entries per lane loaded together
+constexpr int kShortRow = 64;                // member rows read by one thread (bitmap path)
+constexpr uint32_t kLongCap = 1024;          // long member rows listed in LDS (bitmap path)
 
 __device__ __forceinline__ uint64_t below_mask(int lane) {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -41,8 +43,15 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Coarse rows with at most kWCap candidates, one wavefront each (the others
-// are appended to big[] by the counting pass).  FILL = false: ccnt[a];
-// FILL = true: ccol[crow[a] ...].
+// are appended to big[] by the counting pass).  The candidates go into a
+// per-wavefront LDS hash set (open addressing, kWCap slots, so it never
+// fills); each id that enters it is also appended to a list.  The distinct
+// ids are then sorted -- in registers with a 64-lane bitonic network when
+// there are at most 64, in LDS otherwise -- and the set is emptied by
+// clearing just their slots.  FILL = false: ccnt[a]; FILL = true:
+// ccol[crow[a] ...].
+__device__ __forceinline__ uint32_t qhash(uint32_t c) { return (c * 2654435761u) >> 22; }
+
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_coarse_rows_wave(
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
@@ -50,11 +59,20 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows_wave(
     const int32_t *__restrict__ members, uint32_t *__restrict__ ccnt,
     const int64_t *__restrict__ crow, int32_t *__restrict__ ccol, int32_t *__restrict__ big,
     uint32_t *__restrict__ big_count) {
-    __shared__ uint32_t bufs[kWaves][kWCap];
-    uint32_t *buf = bufs[threadIdx.x >> 6];
+    static_assert(kWCap == 1024, "qhash yields 10 bits");
+    constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+    __shared__ uint32_t tabs[kWaves][kWCap];
+    __shared__ uint32_t lists[kWaves][kWCap];
+    __shared__ uint32_t nums[kWaves];
+    const int wv = (int)(threadIdx.x >> 6);
+    uint32_t *tab = tabs[wv];
+    uint32_t *list = lists[wv];
     const int lane = (int)(threadIdx.x & 63u);
     const int64_t nw = (int64_t)gridDim.x * kWaves;
-    for (int64_t a = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); a < n_agg; a += nw) {
+    for (int i = lane; i < kWCap; i += 64) tab[i] = kEmpty;
+    if (lane == 0) nums[wv] = 0u;
+    wave_sync();
+    for (int64_t a = (int64_t)blockIdx.x * kWaves + wv; a < n_agg; a += nw) {
         const int64_t m0 = moff[a], m1 = moff[a + 1];
         // candidates: stored entries of all members
         unsigned long long cand = 0;
@@ -67,9 +85,8 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows_wave(
             if (!FILL && lane == 0) big[atomicAdd(big_count, 1u)] = (int32_t)a;
             continue;
         }
-        // gather: each lane takes one member at a time and loads kWEdges of
-        // its entries together; survivors are appended in ballot order
-        uint32_t m = 0;
+        // gather into the set: each lane takes one member at a time and
+        // loads kWEdges of its entries together
         for (int64_t i0 = m0; i0 < m1; i0 += 64) {
             const int64_t i = i0 + lane;
             int64_t s = 0, e = 0;
@@ -89,45 +106,71 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows_wave(
                 for (int k = 0; k < kWEdges; k++) c[k] = agg[x[k]];
 #pragma unroll
                 for (int k = 0; k < kWEdges; k++) {
-                    const bool keep = c0 + k < len && c[k] >= 0 && (int64_t)c[k] != a;
-                    const uint64_t mask = __ballot(keep);
-                    if (keep) buf[m + (uint32_t)__popcll(mask & below_mask(lane))] = (uint32_t)c[k];
-                    m += (uint32_t)__popcll(mask);
-                }
-            }
-        }
-        uint32_t P = 1;
-        while (P < m) P <<= 1;
-        for (uint32_t i = m + lane; i < P; i += 64) buf[i] = 0xFFFFFFFFu;
-        wave_sync();
-        // bitonic sort of buf[0..P)
-        for (uint32_t k = 2; k <= P; k <<= 1) {
-            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                for (uint32_t i = lane; i < P; i += 64) {
-                    const uint32_t ixj = i ^ j;
-                    if (ixj > i) {
-                        const uint32_t x = buf[i], y = buf[ixj];
-                        const bool up = (i & k) == 0;
-                        if ((x > y) == up) {
-                            buf[i] = y;
-                            buf[ixj] = x;
+                    if (c0 + k < len && c[k] >= 0 && (int64_t)c[k] != a) {
+                        const uint32_t key = (uint32_t)c[k];
+                        uint32_t h = qhash(key);
+                        for (;;) {  // the set has room for every candidate, so this ends
+                            const uint32_t prev = atomicCAS(&tab[h], kEmpty, key);
+                            if (prev == kEmpty) {
+                                list[atomicAdd(&nums[wv], 1u)] = key;
+                                break;
+                            }
+                            if (prev == key) break;
+                            h = (h + 1) & (kWCap - 1);
                         }
                     }
                 }
-                wave_sync();
             }
         }
-        // the first of each run of equal values, in order
-        uint32_t run = 0;
-        for (uint32_t c0 = 0; c0 < m; c0 += 64) {
-            const uint32_t i = c0 + (uint32_t)lane;
-            const bool first = i < m && (i == 0 || buf[i] != buf[i - 1]);
-            const uint64_t mask = __ballot(first);
-            if (FILL && first)
-                ccol[crow[a] + run + (uint32_t)__popcll(mask & below_mask(lane))] = (int32_t)buf[i];
-            run += (uint32_t)__popcll(mask);
+        wave_sync();
+        const uint32_t m = nums[wv];
+        // empty the set again: clear the slot of each distinct id (its probe
+        // run holds it exactly once; other lanes' clears only leave holes)
+        for (uint32_t i = lane; i < m; i += 64) {
+            const uint32_t key = list[i];
+            uint32_t h = qhash(key);
+            while (tab[h] != key) h = (h + 1) & (kWCap - 1);
+            tab[h] = kEmpty;
         }
-        if (!FILL && lane == 0) ccnt[a] = run;
+        if (m <= 64) {
+            // one id per lane; bitonic network over lane order with shuffles
+            uint32_t x = (uint32_t)lane < m ? list[lane] : kEmpty;
+            for (int k = 2; k <= 64; k <<= 1) {
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    const uint32_t y = (uint32_t)__shfl_xor((int)x, j, 64);
+                    const bool lower = (lane & j) == 0;
+                    const bool up = (lane & k) == 0;
+                    x = (lower == up) ? min(x, y) : max(x, y);
+                }
+            }
+            if (FILL && (uint32_t)lane < m) ccol[crow[a] + lane] = (int32_t)x;
+        } else {
+            uint32_t P = 1;
+            while (P < m) P <<= 1;
+            for (uint32_t i = m + lane; i < P; i += 64) list[i] = kEmpty;
+            wave_sync();
+            for (uint32_t k = 2; k <= P; k <<= 1) {
+                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                    for (uint32_t i = lane; i < P; i += 64) {
+                        const uint32_t ixj = i ^ j;
+                        if (ixj > i) {
+                            const uint32_t x = list[i], y = list[ixj];
+                            const bool up = (i & k) == 0;
+                            if ((x > y) == up) {
+                                list[i] = y;
+                                list[ixj] = x;
+                            }
+                        }
+                    }
+                    wave_sync();
+                }
+            }
+            if (FILL)
+                for (uint32_t i = lane; i < m; i += 64) ccol[crow[a] + i] = (int32_t)list[i];
+        }
+        if (!FILL && lane == 0) ccnt[a] = m;
+        wave_sync();
+        if (lane == 0) nums[wv] = 0u;
         wave_sync();
     }
 }
@@ -206,6 +249,8 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows(const int64_t *__restric
     __shared__ unsigned long long red[kWaves];
     __shared__ uint32_t scan_s[kWaves];
     __shared__ uint32_t fill_s;
+    __shared__ uint32_t longm[kLongCap];
+    __shared__ uint32_t nlong_s;
     const int tid = (int)threadIdx.x;
     const int64_t nbig = *big_count;
     for (int64_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
@@ -264,18 +309,66 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows(const int64_t *__restric
             }
             distinct = run;
         } else {
-            // bitmap windows over the coarse id space
+            // bitmap windows over the coarse id space.  Members with short
+            // rows are read one per thread; members with long rows (listed
+            // once, in LDS) by the whole workgroup each.
+            if (tid == 0) nlong_s = 0u;
+            __syncthreads();
+            for (int64_t i = m0 + tid; i < m1; i += kBlock) {
+                const int32_t v = members[i];
+                if (row_ptr[v + 1] - row_ptr[v] > kShortRow) {
+                    const uint32_t k = atomicAdd(&nlong_s, 1u);
+                    if (k < kLongCap) longm[k] = (uint32_t)(i - m0);
+                }
+            }
+            __syncthreads();
+            const uint32_t nlong = nlong_s;
             uint32_t run = 0;
             for (int64_t lo = 0; lo < n_agg; lo += kQWindow) {
                 for (int i = tid; i < kQCap; i += kBlock) buf[i] = 0u;
                 __syncthreads();
-                for (int64_t i = m0; i < m1; i++) {
+                for (int64_t i = m0 + tid; i < m1; i += kBlock) {
                     const int32_t v = members[i];
+                    const int64_t rs = row_ptr[v], len = row_ptr[v + 1] - rs;
+                    if (len > kShortRow) continue;
+                    for (int64_t c0 = 0; c0 < len; c0 += kWEdges) {
+                        int32_t x[kWEdges];
+#pragma unroll
+                        for (int k = 0; k < kWEdges; k++) x[k] = col[c0 + k < len ? rs + c0 + k : rs];
+                        int32_t c[kWEdges];
+#pragma unroll
+                        for (int k = 0; k < kWEdges; k++) c[k] = agg[x[k]];
+#pragma unroll
+                        for (int k = 0; k < kWEdges; k++) {
+                            const int64_t ck = c[k];
+                            if (c0 + k < len && ck != a && ck >= lo && ck < lo + kQWindow) {
+                                const int64_t o = ck - lo;
+                                atomicOr(&buf[o >> 5], 1u << (o & 31));
+                            }
+                        }
+                    }
+                }
+                for (uint32_t t = 0; t < (nlong <= kLongCap ? nlong : 0u); t++) {
+                    const int32_t v = members[m0 + longm[t]];
                     for (int64_t j = row_ptr[v] + tid, e = row_ptr[v + 1]; j < e; j += kBlock) {
                         const int64_t c = agg[col[j]];
                         if (c != a && c >= lo && c < lo + kQWindow) {
                             const int64_t o = c - lo;
                             atomicOr(&buf[o >> 5], 1u << (o & 31));
+                        }
+                    }
+                }
+                if (nlong > kLongCap) {  // too many long members to list: scan them all
+                    for (int64_t i = m0; i < m1; i++) {
+                        const int32_t v = members[i];
+                        if (row_ptr[v + 1] - row_ptr[v] <= kShortRow) continue;
+                        for (int64_t j = row_ptr[v] + tid, e = row_ptr[v + 1]; j < e;
+                             j += kBlock) {
+                            const int64_t c = agg[col[j]];
+                            if (c != a && c >= lo && c < lo + kQWindow) {
+                                const int64_t o = c - lo;
+                                atomicOr(&buf[o >> 5], 1u << (o & 31));
+                            }
                         }
                     }
                 }

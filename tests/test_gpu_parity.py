@@ -230,6 +230,21 @@ def test_quotient_big_rows_use_bitmap_windows(ctx):
     assert np.array_equal(ccol.cpu().numpy(), ocol)
 
 
+def test_quotient_many_long_members(ctx):
+    # one aggregate of 1100 vertices whose rows are all long (70 entries):
+    # more long members than the workgroup path lists in LDS
+    left, right = 1100, 70
+    u = np.repeat(np.arange(left), right)
+    w = left + np.tile(np.arange(right), left)
+    rp, c = graphs.from_edges(left + right, u, w)
+    agg = np.zeros(left + right, np.int32)
+    agg[left:] = 1 + np.arange(right)
+    crow, ccol = ctx.quotient(rp, c, agg, right + 1)
+    orow, ocol = oracle.quotient(rp, c, agg, right + 1)
+    assert np.array_equal(crow.cpu().numpy(), orow)
+    assert np.array_equal(ccol.cpu().numpy(), ocol)
+
+
 @pytest.mark.parametrize("name,stop", [("grid27_30", 100), ("chunglu_50k", 1000),
                                        ("dropped7_20", 50), ("grid2d_64", 1000)])
 def test_coarsen_parity(ctx, name, stop):
