@@ -376,6 +376,22 @@ def main():
 
     rounds_mis = 1 + max(r["round"] for r in recs_mis if r["kind"] in (0, 1)) if recs_mis else 0
 
+    # device-copy ceiling on this machine: 256 MiB device-to-device copies
+    cb = 256 << 20
+    src = torch.ones(cb, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * cb * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9  # bytes read + written
+    del src, dst
+    log("device copy ceiling: %.0f GB/s" % copy_gbps)
+
     # CPU baseline: the oracle, single-threaded, on a bounded sample
     cpu = None
     if not args.no_cpu:
@@ -413,6 +429,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": measured_traffic(args.workload, dom, d["launches"]),
+                     "copy_ceiling": copy_gbps, "frac_of_copy_ceiling": achieved / copy_gbps,
                      "kernel": dom, "launches_per_step": d["launches"],
                      "bytes_per_launch": d["bytes"] / d["launches"],
                      "mean_launch_ms": d["ms"] / d["launches"]},
