@@ -83,16 +83,38 @@ def measured_traffic(workload, kernel, launches_per_step):
     return k["hbm_bytes_per_step"] / launches_per_step
 
 
-def sweep_bytes(rec, identity):
+def sweep_bytes(rec, identity, written=0):
     """Algorithmic bytes of one sweep launch: column indices of the visited
     rows, per-row terms (row extents 8, worklist entry 4 unless the list is
     the identity, own value 4, written value 4, plus the compulsory first
     touch of the gathered value 4 (Refresh Column) or read of M_v and T_v
-    (Decide Set)), and the compacted worklist written."""
+    (Decide Set)), and the compacted worklist written.  A Refresh Column
+    that rewrites long rows without their OUT neighbours also writes those
+    `written` column indices (and a length per rewritten row, not counted:
+    at most one per 32 indices), and one that reads such rows reads a length
+    per row as well."""
     per_row = 20 if rec["kind"] == 0 else 24
     if identity:
         per_row -= 4
-    return 4 * rec["edges"] + per_row * rec["rows"] + 4 * rec["rows_out"]
+    b = 4 * rec["edges"] + per_row * rec["rows"] + 4 * rec["rows_out"]
+    if rec["kind"] == 0:
+        b += 4 * written
+        if rec.get("compact", 0) == 2:
+            b += 4 * rec["rows"]
+    return b
+
+
+def compaction_writes(recs):
+    """Column indices each compacting Refresh Column wrote into compacted
+    rows (counted by the accounting pass)."""
+    return [max(r.get("written", 0), 0) if r["kind"] == 0 else 0 for r in recs]
+
+
+def gather_bytes(rec):
+    """Bytes one sweep would add if every neighbour-value gather went to HBM
+    (4 per visited edge) instead of the compulsory first touch counted in
+    sweep_bytes: the upper-bound variant of the algorithmic model."""
+    return 4 * rec["edges"] if rec["kind"] in (0, 1) else 0
 
 
 def c5_pool(count, seed=3, n_lo=1_000, n_hi=10_000_000):
@@ -282,7 +304,7 @@ def main():
         log("calibration copies: 3 x %d MiB" % args.calibrate_copy)
 
     ctx = api.Context(0)
-    ctx.ensure_workspace(n, 1)
+    ctx.ensure_workspace(n, 1, nnz)
     torch.cuda.synchronize()
 
     def step(c):
@@ -316,7 +338,7 @@ def main():
     # algorithmic bytes per launch (untimed accounting run; results are
     # deterministic, so every timed step visits the same rows)
     acc = api.Context(0, account=True)
-    acc.ensure_workspace(n, 1)
+    acc.ensure_workspace(n, 1, nnz)
     acc.mis2(rp, col, args.seed, nnz=nnz)
     recs_mis = acc.last_sweeps()
     acc.aggregate(rp, col, args.seed, nnz=nnz)
@@ -325,7 +347,7 @@ def main():
 
     # launch durations: a second timed loop with HIP events around each sweep
     prof = api.Context(0, profile=True)
-    prof.ensure_workspace(n, 1)
+    prof.ensure_workspace(n, 1, nnz)
     step(prof)
     torch.cuda.synchronize()
     dur = [0.0] * len(accounted)
@@ -351,20 +373,25 @@ def main():
     launches = []
     for call in (range(0, len(recs_mis)), range(len(recs_mis), len(accounted))):
         recs = [accounted[i] for i in call]
+        wr = dict(zip(call, compaction_writes(recs)))
         persistent = [i for i in call if accounted[i]["kind"] == 2]
         for i in call:
             r = accounted[i]
             if r["kind"] == 2:
-                b = sum(sweep_bytes(q, q["phase"] == 0 and q["round"] == 0)
-                        for q in recs if q["kind"] in (0, 1) and q["phase"] == r["phase"])
-                launches.append((kinds[2], b, dur[i]))
+                sw = [j for j in call if accounted[j]["kind"] in (0, 1)
+                      and accounted[j]["phase"] == r["phase"]]
+                b = sum(sweep_bytes(accounted[j], accounted[j]["phase"] == 0 and
+                                    accounted[j]["round"] == 0, wr[j]) for j in sw)
+                launches.append((kinds[2], b, sum(gather_bytes(accounted[j]) for j in sw), dur[i]))
             elif not persistent:
-                launches.append((kinds[r["kind"]], sweep_bytes(r, r["phase"] == 0 and r["round"] == 0),
-                                 dur[i]))
+                launches.append((kinds[r["kind"]],
+                                 sweep_bytes(r, r["phase"] == 0 and r["round"] == 0, wr[i]),
+                                 gather_bytes(r), dur[i]))
     per_kind = {}
-    for k, b, ms in launches:
-        e = per_kind.setdefault(k, {"bytes": 0, "ms": 0.0, "launches": 0})
+    for k, b, g, ms in launches:
+        e = per_kind.setdefault(k, {"bytes": 0, "bytes_upper": 0, "ms": 0.0, "launches": 0})
         e["bytes"] += b
+        e["bytes_upper"] += b + g
         e["ms"] += ms
         e["launches"] += 1
     dom = max(per_kind, key=lambda k: per_kind[k]["ms"])
@@ -432,6 +459,8 @@ def main():
                      "copy_ceiling": copy_gbps, "frac_of_copy_ceiling": achieved / copy_gbps,
                      "kernel": dom, "launches_per_step": d["launches"],
                      "bytes_per_launch": d["bytes"] / d["launches"],
+                     "bytes_per_launch_upper": d["bytes_upper"] / d["launches"],
+                     "achieved_upper": d["bytes_upper"] / (d["ms"] * 1e-3) / 1e9,
                      "mean_launch_ms": d["ms"] / d["launches"]},
         "cpu_baseline": cpu,
         "mis2_ms": 1e3 * float(np.median(t_mis)),

@@ -61,6 +61,13 @@ extern "C" {
 #define MIS2_OPT_PERSISTENT    5  /* 0 (default): two launches per round; 1: all rounds of a MIS-2
                                      run in one cooperative launch (falls back to 0 when the
                                      grid cannot be co-resident) */
+#define MIS2_OPT_COMPACT       6  /* 1 (default): when the workspace has room (see
+                                     mis2_workspace_bytes_csr) and the graph has rows longer
+                                     than the cooperative threshold (32 entries per lane of
+                                     the lane plan, 1024 at 64 lanes), Refresh Column rewrites
+                                     those rows without their OUT neighbours and reads the
+                                     shorter rows in later rounds; 0: never (lane plans > 0
+                                     only; results are the same either way) */
 
 typedef struct mis2_ctx mis2_ctx;
 
@@ -88,6 +95,18 @@ int mis2_set_option(mis2_ctx *ctx, int option, int64_t value);
 /* Bytes of device workspace that operation `op` (MIS2_OP_*) needs for a
  * graph with n vertices; written to *bytes (host).  Depends on n only. */
 int mis2_workspace_bytes(int64_t n, int op, size_t *bytes);
+
+/* Bytes of device workspace for operation `op` on a graph with n vertices
+ * and nnz stored entries that also hold the compacted adjacency of Refresh
+ * Column (4 * nnz + 4 * n bytes more than mis2_workspace_bytes, aligned);
+ * written to *bytes (host).  A workspace of at least this size lets
+ * mis2_run and mis2_aggregate read the long rows (MIS2_OPT_COMPACT), from
+ * round 2 of a MIS-2 run on (round 0 of the phase-2 induced subgraph), as
+ * only the neighbours whose tuple was not yet OUT when the row was last
+ * swept: OUT is final and never lowers a minimum, so results are the same
+ * with either size.  mis2_coarsen and mis2_aggregate_batched compact in
+ * buffers of their own workspaces that are idle during the aggregation. */
+int mis2_workspace_bytes_csr(int64_t n, int64_t nnz, int op, size_t *bytes);
 
 /* Hand the context a caller-owned device workspace of `bytes` bytes,
  * 256-byte aligned.  It stays in use until replaced or the context is
@@ -135,7 +154,11 @@ typedef struct mis2_sweep_record {
     int64_t rows_out;  /* entries kept for the next round */
     int64_t edges;     /* sum of the processed CSR row lengths with MIS2_OPT_ACCOUNT, else -1 */
     float ms;          /* launch duration with MIS2_OPT_PROFILE, else -1 */
-    int32_t reserved;
+    int32_t compact;   /* Refresh Column and compacted rows (see MIS2_OPT_COMPACT): 0 = none,
+                          1 = read the CSR's rows and rewrote the long ones compacted,
+                          2 = read the long rows in compacted form and rewrote them */
+    int64_t written;   /* Refresh Column with MIS2_OPT_ACCOUNT: column indices written into
+                          compacted rows; else -1 */
 } mis2_sweep_record;
 
 /* Copy up to `cap` records of the last call's sweep launches to host array

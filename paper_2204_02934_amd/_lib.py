@@ -25,11 +25,12 @@ MIS2_OPT_GRID_BLOCKS = 2
 MIS2_OPT_PROFILE = 3
 MIS2_OPT_ACCOUNT = 4
 MIS2_OPT_PERSISTENT = 5
+MIS2_OPT_COMPACT = 6
 
 # Every symbol include/mis2.h declares.
 EXPORTS = (
     "mis2_create", "mis2_destroy", "mis2_last_error", "mis2_set_option",
-    "mis2_workspace_bytes", "mis2_set_workspace", "mis2_run", "mis2_last_trace",
+    "mis2_workspace_bytes", "mis2_workspace_bytes_csr", "mis2_set_workspace", "mis2_run", "mis2_last_trace",
     "mis2_aggregate", "mis2_last_sweeps", "mis2_quotient", "mis2_coarsen_workspace_bytes",
     "mis2_coarsen", "mis2_batch_workspace_bytes", "mis2_aggregate_batched",
     "mis2_server_bytes", "mis2_server_create", "mis2_server_destroy", "mis2_server_last_error",
@@ -47,7 +48,8 @@ class Mis2Graph(ctypes.Structure):
 class Mis2SweepRecord(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("phase", ctypes.c_int32), ("round", ctypes.c_int32),
                 ("lanes", ctypes.c_int32), ("rows", ctypes.c_int64), ("rows_out", ctypes.c_int64),
-                ("edges", ctypes.c_int64), ("ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
+                ("edges", ctypes.c_int64), ("ms", ctypes.c_float), ("compact", ctypes.c_int32),
+                ("written", ctypes.c_int64)]
 
 
 class Mis2JobResult(ctypes.Structure):
@@ -84,6 +86,8 @@ def load():
         "mis2_last_error": (ctypes.c_char_p, [vp]),
         "mis2_set_option": (ctypes.c_int, [vp, ctypes.c_int, i64]),
         "mis2_workspace_bytes": (ctypes.c_int, [i64, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+        "mis2_workspace_bytes_csr": (ctypes.c_int, [i64, i64, ctypes.c_int,
+                                                    ctypes.POINTER(ctypes.c_size_t)]),
         "mis2_set_workspace": (ctypes.c_int, [vp, vp, ctypes.c_size_t]),
         "mis2_run": (ctypes.c_int, [vp, gp, u64, vp, ctypes.POINTER(i64), ctypes.POINTER(i32), vp]),
         "mis2_last_trace": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(i64), i32,

@@ -40,7 +40,7 @@ class Context:
     on demand (allocation happens outside the library calls)."""
 
     def __init__(self, device=None, validate=False, lanes=0, blocks=0, profile=False,
-                 account=False, persistent=False):
+                 account=False, persistent=False, compact=True):
         self.lib = _lib.load()
         if device is None:
             device = torch.cuda.current_device()
@@ -54,6 +54,7 @@ class Context:
         self.set_option(_lib.MIS2_OPT_PROFILE, int(profile))
         self.set_option(_lib.MIS2_OPT_ACCOUNT, int(account))
         self.set_option(_lib.MIS2_OPT_PERSISTENT, int(persistent))
+        self.set_option(_lib.MIS2_OPT_COMPACT, int(compact))
 
     def __del__(self):
         lib = getattr(self, "lib", None)
@@ -64,13 +65,19 @@ class Context:
     def set_option(self, option, value):
         _check(self.lib, self.ptr, self.lib.mis2_set_option(self.ptr, option, int(value)))
 
-    def workspace_bytes(self, n, op):
+    def workspace_bytes(self, n, op, nnz=None):
+        """mis2_workspace_bytes, or with nnz mis2_workspace_bytes_csr (room for
+        the compacted adjacency as well)."""
         b = ctypes.c_size_t(0)
-        _check(self.lib, self.ptr, self.lib.mis2_workspace_bytes(int(n), op, ctypes.byref(b)))
+        if nnz is None:
+            rc = self.lib.mis2_workspace_bytes(int(n), op, ctypes.byref(b))
+        else:
+            rc = self.lib.mis2_workspace_bytes_csr(int(n), int(nnz), op, ctypes.byref(b))
+        _check(self.lib, self.ptr, rc)
         return b.value
 
-    def ensure_workspace(self, n, op):
-        need = self.workspace_bytes(n, op)
+    def ensure_workspace(self, n, op, nnz=None):
+        need = self.workspace_bytes(n, op, nnz)
         if self._ws is None or self._ws.numel() < need:
             # torch's caching allocator returns 512-byte aligned blocks
             self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
@@ -88,7 +95,7 @@ class Context:
     def mis2(self, row_ptr, col, seed=0, stream=None, nnz=None):
         """Algorithm 1.  Returns (status uint8[n] on the GPU, n_roots, n_iters)."""
         g, keep = self.graph(row_ptr, col, nnz)
-        self.ensure_workspace(g.n, _lib.MIS2_OP_MIS2)
+        self.ensure_workspace(g.n, _lib.MIS2_OP_MIS2, g.nnz)
         status = torch.empty(max(g.n, 1), dtype=torch.uint8, device=self.device)
         nr, ni = ctypes.c_int64(0), ctypes.c_int32(0)
         rc = self.lib.mis2_run(self.ptr, ctypes.byref(g), ctypes.c_uint64(seed),
@@ -102,7 +109,7 @@ class Context:
         """Algorithm 3.  Returns (agg int32[n] on the GPU, n_agg) or, with
         want_roots, (agg, n_agg, roots uint8[n])."""
         g, keep = self.graph(row_ptr, col, nnz)
-        self.ensure_workspace(g.n, _lib.MIS2_OP_AGGREGATE)
+        self.ensure_workspace(g.n, _lib.MIS2_OP_AGGREGATE, g.nnz)
         agg = torch.empty(max(g.n, 1), dtype=torch.int32, device=self.device)
         roots = torch.empty(max(g.n, 1), dtype=torch.uint8, device=self.device) if want_roots else None
         na = ctypes.c_int64(0)
@@ -233,7 +240,7 @@ class Context:
     def last_sweeps(self, cap=8192):
         """Sweep launches of the last call: list of dicts (kind 0 = Refresh
         Column, 1 = Decide Set; edges / ms are -1 unless accounting /
-        profiling is on)."""
+        profiling is on; compact as mis2_sweep_record.compact)."""
         buf = (_lib.Mis2SweepRecord * cap)()
         k = ctypes.c_int32(0)
         _check(self.lib, self.ptr, self.lib.mis2_last_sweeps(self.ptr, buf, cap, ctypes.byref(k)))
@@ -241,7 +248,8 @@ class Context:
         for i in range(min(k.value, cap)):
             r = buf[i]
             out.append({"kind": r.kind, "phase": r.phase, "round": r.round, "lanes": r.lanes,
-                        "rows": r.rows, "rows_out": r.rows_out, "edges": r.edges, "ms": r.ms})
+                        "rows": r.rows, "rows_out": r.rows_out, "edges": r.edges, "ms": r.ms,
+                        "compact": r.compact, "written": r.written})
         return out
 
 

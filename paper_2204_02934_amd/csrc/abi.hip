@@ -101,6 +101,12 @@ int get_workspace(mis2_ctx *ctx, const mis2_graph *g, int op, Workspace *ws) {
                     ctx->ws ? ctx->ws_bytes : (size_t)0);
     if (!carve(ctx->ws, ctx->ws_bytes, g->n, op, ws))
         return fail(ctx, MIS2_ENOSPACE, "workspace carve failed");
+    // the compacted adjacency, when the workspace has room for it past the end
+    if (ctx->ws_bytes >= need + compact_bytes(g->n, g->nnz)) {
+        char *tail = (char *)ctx->ws + need;
+        ws->colc = (int32_t *)tail;
+        ws->lenc = (int32_t *)(tail + align_up(4 * (size_t)std::max<int64_t>(g->nnz, 1)));
+    }
     return MIS2_OK;
 }
 
@@ -117,7 +123,9 @@ struct Launch {
     int kind, phase, round, lanes;
     hipEvent_t e0, e1;
     bool persistent = false;  // a sweep inside a persistent launch (timed by device stamps)
+    int compact = 0;          // mis2_sweep_record.compact
 };
+
 
 // Segment geometry of a run: S wavefronts, seg vertices each.
 struct Geometry {
@@ -180,6 +188,10 @@ int32_t parse_trace(mis2_ctx *ctx, int phase) {
 
 constexpr int kFallBack = 1;
 
+RoundsArgs round_args(const mis2_ctx *ctx, const mis2_graph *g, uint64_t seed,
+                      const Workspace &ws, const Geometry &gm, bool masked,
+                      unsigned long long *degs, int lanes);
+
 // All rounds in one cooperative launch (k_rounds).  Returns kFallBack when
 // the grid cannot be made co-resident, so the caller issues rounds instead.
 int run_rounds_persistent(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspace &ws,
@@ -187,33 +199,12 @@ int run_rounds_persistent(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, con
                           int32_t *iters_out, std::vector<Launch> *launches, int lanes) {
     const int cap = rounds_max_blocks(lanes, ctx->num_cus);
     if (cap < gm.blocks) return kFallBack;  // geometry() sizes the default plan to fit
-    unsigned long long *degs = ws.degs + (size_t)phase * kTraceCap * 2;
+    unsigned long long *degs = ws.degs + (size_t)phase * kTraceCap * kDegStride;
     HIP_TRY(ctx, launch_fill_u32(ws.bar, 0u, kBarWords, s));
-    const TupleParams tp = tparams(ctx, g->n, seed, 0);
-    RoundsArgs a;
-    memset(&a, 0, sizeof a);
-    a.batch = ctx->batch;
-    a.wl1[0] = ws.wl1[0];
-    a.wl1[1] = ws.wl1[1];
-    a.wl2[0] = ws.wl2[0];
-    a.wl2[1] = ws.wl2[1];
-    a.cnt1[0] = ws.cnt1[0];
-    a.cnt1[1] = ws.cnt1[1];
-    a.cnt2[0] = ws.cnt2[0];
-    a.cnt2[1] = ws.cnt2[1];
-    a.rt = ws.rt;
-    a.ctr = ws.ctr;
-    a.degs = ctx->account ? degs : nullptr;
-    a.dsplit = ctx->account ? ws.dsplit : nullptr;
-    a.bar = ws.bar;
-    a.n = g->n;
-    a.seg = gm.seg;
-    a.S = gm.S;
-    a.seed = seed;
-    a.pmask = tp.pmask;
-    a.b = tp.b;
-    a.masked = masked ? 1 : 0;
-    a.max_rounds = kTraceCap;
+    RoundsArgs a = round_args(ctx, g, seed, ws, gm, masked, degs, lanes);
+    a.alive_host = nullptr;  // the host waits for the whole launch
+    a.colc = nullptr;        // the single launch does not compact
+    a.lenc = nullptr;
     Launch lp{2, phase, -1, lanes, nullptr, nullptr};
     if (ctx->profile) {
         lp.e0 = take_event(ctx), lp.e1 = take_event(ctx);
@@ -264,7 +255,7 @@ constexpr double kQueryAfterS = 1e-3;       // check the stream for errors after
 
 RoundsArgs round_args(const mis2_ctx *ctx, const mis2_graph *g, uint64_t seed,
                       const Workspace &ws, const Geometry &gm, bool masked,
-                      unsigned long long *degs) {
+                      unsigned long long *degs, int lanes) {
     RoundsArgs a;
     memset(&a, 0, sizeof a);
     const TupleParams tp = tparams(ctx, g->n, seed, 0);
@@ -281,6 +272,7 @@ RoundsArgs round_args(const mis2_ctx *ctx, const mis2_graph *g, uint64_t seed,
     a.degs = ctx->account ? degs : nullptr;
     a.dsplit = ctx->account ? ws.dsplit : nullptr;
     a.bar = ws.bar;
+    a.lflag = ws.lflag;
     a.n = g->n;
     a.seg = gm.seg;
     a.S = gm.S;
@@ -289,16 +281,26 @@ RoundsArgs round_args(const mis2_ctx *ctx, const mis2_graph *g, uint64_t seed,
     a.b = tp.b;
     a.masked = masked ? 1 : 0;
     a.max_rounds = kTraceCap;
+    // compacted Refresh Column rows (L-lane sweeps only; the flat sweeps
+    // read the CSR as given)
+    if (ws.colc && ws.lenc && lanes > 0 && ctx->plan.compact && g->nnz > 0) {
+        a.colc = ws.colc;
+        a.lenc = ws.lenc;
+    }
     return a;
 }
 
+// long_rows: for an unmasked run, out: 1 if round 0 met rows longer than the
+// cooperative threshold, 0 if not (or if the run ended before round 1
+// started); for a masked run, in: the value of the unmasked run of the same
+// graph.  Refresh Column compacts (launch modes 1 then 2) only when it is 1.
 int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspace &ws,
                const Geometry &gm, bool masked, int phase, hipStream_t s, int32_t *iters_out,
-               std::vector<Launch> *launches) {
+               std::vector<Launch> *launches, int *long_rows) {
     const int lanes = lanes_for(ctx, g);
-    unsigned long long *degs = ws.degs + (size_t)phase * kTraceCap * 2;
+    unsigned long long *degs = ws.degs + (size_t)phase * kTraceCap * kDegStride;
     if (ctx->account) {
-        HIP_TRY(ctx, launch_fill_u64(degs, 0ull, 2 * kTraceCap, s));
+        HIP_TRY(ctx, launch_fill_u64(degs, 0ull, kDegStride * kTraceCap, s));
         HIP_TRY(ctx, launch_fill_u64(ws.dsplit, 0ull, 2 * (int64_t)kSplit * 16, s));
     }
     // size counters: every ring slot zero except slot 0 of a masked start,
@@ -307,12 +309,18 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
     HIP_TRY(ctx, launch_fill_u32(ws.ctr + (masked ? kCtrSlot : 0), 0u,
                                  (int64_t)(masked ? kCtrRing - 1 : kCtrRing) * kCtrSlot, s));
     if (!masked) HIP_TRY(ctx, launch_fill_u32(ws.rt, (uint32_t)g->n, 2, s));
+    if (!masked) HIP_TRY(ctx, launch_fill_u32(ws.lflag, 0u, (int64_t)kSplit * kCtrLine, s));
     if (ctx->plan.persistent) {
+        if (!masked) *long_rows = 0;
         int rc = run_rounds_persistent(ctx, g, seed, ws, gm, masked, phase, s, iters_out, launches,
                                        lanes);
         if (rc != kFallBack) return rc;
     }
-    const RoundsArgs a = round_args(ctx, g, seed, ws, gm, masked, degs);
+    const RoundsArgs a = round_args(ctx, g, seed, ws, gm, masked, degs, lanes);
+    // compaction: unknown (-1) until round 1 reports what round 0 met
+    int longs = masked ? (*long_rows > 0 ? 1 : 0) : -1;
+    const int cfrom = masked ? 0 : kCompactFrom;
+    int cstart = -1;  // first compacting round
     __atomic_store_n(ctx->alive_host, ~0ull, __ATOMIC_RELEASE);
     int round = 0;  // rounds issued
     auto last_progress = std::chrono::steady_clock::now();
@@ -323,7 +331,8 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
         uint32_t live = 1;
         if (v != ~0ull) {
             seen = (int)(v >> 32);
-            live = (uint32_t)v;
+            live = (uint32_t)v & ~kLongRowsBit;
+            if (longs < 0 && seen >= 1) longs = ((uint32_t)v & kLongRowsBit) ? 1 : 0;
         }
         if (live == 0u) break;  // worklist1 empty: the run has ended at round `seen`
         if (seen != last_seen) {
@@ -331,12 +340,19 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
             last_progress = std::chrono::steady_clock::now();
         }
         // queue depth beyond the running round: two while rounds are big,
-        // one near the end (fewer rounds issued past it)
+        // one near the end (fewer rounds issued past it); a round that could
+        // compact waits until the host knows whether it should
         const int ahead = (seen < 0 || live >= 4096u) ? 2 : 1;
-        if (round - seen <= ahead) {
+        const bool can_compact = a.colc != nullptr && round >= cfrom;
+        if (round - seen <= ahead && !(can_compact && longs < 0)) {
             if (round + 2 >= kTraceCap)
                 return fail(ctx, MIS2_EINTERNAL, "more than %d rounds", kTraceCap - 2);
-            Launch lc{0, phase, round, lanes, nullptr, nullptr};
+            int mode = 0;
+            if (can_compact && longs > 0) {
+                if (cstart < 0) cstart = round;
+                mode = round == cstart ? 1 : 2;
+            }
+            Launch lc{0, phase, round, lanes, nullptr, nullptr, false, mode};
             Launch ld{1, phase, round, lanes, nullptr, nullptr};
             if (ctx->profile) {
                 lc.e0 = take_event(ctx), lc.e1 = take_event(ctx);
@@ -345,7 +361,7 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
                     return fail(ctx, MIS2_EHIP, "hipEventCreate failed");
             }
             HIP_TRY(ctx, launch_col_round(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
-                                          a, round, s, lc.e0, lc.e1));
+                                          a, round, mode, s, lc.e0, lc.e1));
             HIP_TRY(ctx, launch_dec_round(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
                                           a, round, s, ld.e0, ld.e1));
             launches->push_back(lc);
@@ -363,6 +379,7 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
         if (idle > kProgressTimeoutS)
             return fail(ctx, MIS2_EHIP, "no MIS-2 round started for %.0f s", idle);
     }
+    if (!masked) *long_rows = longs > 0 ? 1 : 0;
     ctx->stamps_valid[phase] = 0;
     *iters_out = round;  // rounds issued; parse_trace gives the count after the sync
     return queue_trace(ctx, ws, phase, round, s);
@@ -374,7 +391,7 @@ int collect_sweeps(mis2_ctx *ctx, const std::vector<Launch> &launches, const Wor
     ctx->sweeps.clear();
     std::vector<unsigned long long> degs;
     if (ctx->account) {
-        degs.resize((size_t)2 * kTraceCap * 2);
+        degs.resize((size_t)2 * kTraceCap * kDegStride);
         HIP_TRY(ctx, hipMemcpyAsync(degs.data(), ws.degs, degs.size() * sizeof(unsigned long long),
                                     hipMemcpyDeviceToHost, s));
         HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -395,10 +412,12 @@ int collect_sweeps(mis2_ctx *ctx, const std::vector<Launch> &launches, const Wor
             for (int r = 0; r < rounds; r++) {
                 rec.rows += tr[2 * r] + tr[2 * r + 1];
                 if (ctx->account)
-                    rec.edges += (int64_t)degs[((size_t)l.phase * kTraceCap + r) * 2] +
-                                 (int64_t)degs[((size_t)l.phase * kTraceCap + r) * 2 + 1];
+                    rec.edges += (int64_t)degs[((size_t)l.phase * kTraceCap + r) * kDegStride] +
+                                 (int64_t)degs[((size_t)l.phase * kTraceCap + r) * kDegStride + 1];
             }
             rec.rows_out = rounds;
+            rec.compact = l.compact;
+            rec.written = ctx->account ? 0 : -1;
             rec.ms = -1.0f;
             if (ctx->profile && l.e0 && l.e1) {
                 float ms = 0.f;
@@ -418,8 +437,10 @@ int collect_sweeps(mis2_ctx *ctx, const std::vector<Launch> &launches, const Wor
         const int list = l.kind == 0 ? 1 : 0;
         rec.rows = tr[2 * l.round + list];
         rec.rows_out = l.round + 1 < rounds ? tr[2 * (l.round + 1) + list] : 0;
-        rec.edges = ctx->account ? (int64_t)degs[((size_t)l.phase * kTraceCap + l.round) * 2 + list]
-                                 : -1;
+        const size_t di = ((size_t)l.phase * kTraceCap + l.round) * kDegStride;
+        rec.edges = ctx->account ? (int64_t)degs[di + list] : -1;
+        rec.written = ctx->account && l.kind == 0 ? (int64_t)degs[di + 2] : -1;
+        rec.compact = l.compact;
         rec.ms = -1.0f;
         if (ctx->profile && l.e0 && l.e1) {
             float ms = 0.f;
@@ -439,6 +460,10 @@ int collect_sweeps(mis2_ctx *ctx, const std::vector<Launch> &launches, const Wor
 
 namespace mis2 {
 
+size_t compact_bytes(int64_t n, int64_t nnz) {
+    return align_up(4 * (size_t)std::max<int64_t>(nnz, 1)) + align_up(4 * (size_t)std::max<int64_t>(n, 0));
+}
+
 size_t workspace_bytes(int64_t n, int op) {
     if (n < 0) return 0;
     const size_t un = (size_t)n;
@@ -449,10 +474,11 @@ size_t workspace_bytes(int64_t n, int op) {
     b += align_up(4 * (size_t)(kTraceCap + 2) * kRoundStride);  // round table
     b += align_up(4 * (size_t)kCtrRing * kCtrSlot);     // size counters
     b += align_up(4 * kScalars);                        // scalars
-    b += align_up(8 * 2 * 2 * (size_t)kTraceCap);       // degs
+    b += align_up(8 * 2 * kDegStride * (size_t)kTraceCap);  // degs
     b += align_up(8 * 2 * (size_t)kSplit * 16);         // their partial sums
     b += align_up(4 * (size_t)(compact_blocks(n) + 1)); // blocksum
     b += align_up(4 * (size_t)kBarWords);               // barrier state
+    b += align_up(4 * (size_t)kSplit * kCtrLine);       // long-row flags
     if (op != MIS2_OP_MIS2) {
         b += align_up(4 * un) * 3;                      // label, list, aggsize
         b += align_up(un);                              // flag
@@ -488,10 +514,11 @@ bool carve(void *base, size_t bytes, int64_t n, int op, Workspace *ws) {
     ws->rt = (uint32_t *)take(4 * (size_t)(kTraceCap + 2) * kRoundStride);
     ws->ctr = (uint32_t *)take(4 * (size_t)kCtrRing * kCtrSlot);
     ws->scalars = (uint32_t *)take(4 * kScalars);
-    ws->degs = (unsigned long long *)take(8 * 2 * 2 * (size_t)kTraceCap);
+    ws->degs = (unsigned long long *)take(8 * 2 * kDegStride * (size_t)kTraceCap);
     ws->dsplit = (unsigned long long *)take(8 * 2 * (size_t)kSplit * 16);
     ws->blocksum = (uint32_t *)take(4 * (size_t)(compact_blocks(n) + 1));
     ws->bar = (uint32_t *)take(4 * (size_t)kBarWords);
+    ws->lflag = (uint32_t *)take(4 * (size_t)kSplit * kCtrLine);
     if (op != MIS2_OP_MIS2) {
         ws->label = (int32_t *)take(4 * un);
         ws->list = (int32_t *)take(4 * un);
@@ -603,6 +630,9 @@ int mis2_set_option(mis2_ctx *ctx, int option, int64_t value) {
         case MIS2_OPT_ACCOUNT:
             ctx->account = value != 0;
             return MIS2_OK;
+        case MIS2_OPT_COMPACT:
+            ctx->plan.compact = value != 0;
+            return MIS2_OK;
         default:
             return fail(ctx, MIS2_EINVAL, "unknown option %d", option);
     }
@@ -611,6 +641,13 @@ int mis2_set_option(mis2_ctx *ctx, int option, int64_t value) {
 int mis2_workspace_bytes(int64_t n, int op, size_t *bytes) {
     if (!bytes || n < 0 || op < MIS2_OP_MIS2 || op > MIS2_OP_COARSEN) return MIS2_EINVAL;
     *bytes = workspace_bytes(n, op);
+    return MIS2_OK;
+}
+
+int mis2_workspace_bytes_csr(int64_t n, int64_t nnz, int op, size_t *bytes) {
+    if (!bytes || n < 0 || nnz < 0 || op < MIS2_OP_MIS2 || op > MIS2_OP_COARSEN)
+        return MIS2_EINVAL;
+    *bytes = workspace_bytes(n, op) + compact_bytes(n, nnz);
     return MIS2_OK;
 }
 
@@ -647,7 +684,9 @@ int mis2_run(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, uint8_t *status,
     const Geometry gm = geometry(ctx, g->n, lanes_for(ctx, g));
     HIP_TRY(ctx, launch_init_tuples(tparams(ctx, g->n, seed, 0), g->n, ws.T, s));
     int32_t iters = 0;
-    if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, &iters, &launches))) return rc;
+    int long_rows = 0;
+    if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, &iters, &launches, &long_rows)))
+        return rc;
     HIP_TRY(ctx, launch_status(g->n, ws.T, status, ws.blocksum, ws.scalars + kS_Roots, s));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, ws.scalars + kS_Roots, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -699,7 +738,9 @@ int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
     // its neighbours.
     HIP_TRY(ctx, launch_init_tuples(tparams(ctx, n, seed, 0), n, ws.T, s));
     int32_t it1 = 0, it2 = 0;
-    if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, &it1, &launches))) return rc;
+    int long_rows = 0;
+    if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, &it1, &launches, &long_rows)))
+        return rc;
     HIP_TRY(ctx, launch_fill_u32(sc, 0u, kScalars, s));
     HIP_TRY(ctx, launch_fill_i32(ws.label, -1, n, s));
     if (roots) HIP_TRY(ctx, launch_fill_u8(roots, 0, n, s));
@@ -724,7 +765,8 @@ int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
     act_io.S = gm.S;
     HIP_TRY(ctx, launch_init_masked(gm.blocks, tparams(ctx, n, seed, 0), n, ws.label, ws.T, ws.M,
                                     act_io, s));
-    if ((rc = run_rounds(ctx, g, seed, ws, gm, true, 1, s, &it2, &launches))) return rc;
+    if ((rc = run_rounds(ctx, g, seed, ws, gm, true, 1, s, &it2, &launches, &long_rows)))
+        return rc;
     HIP_TRY(ctx, launch_accept_phase2(n, g->row_ptr, g->col, ws.T, ws.label, ws.flag, s));
     HIP_TRY(ctx, compact_u8_nz(ws.flag, n, ws.list, sc + kS_Count2, ws.blocksum, s));
     HIP_TRY(ctx, launch_label_roots(n, g->row_ptr, g->col, ws.list, sc + kS_Count2,
@@ -860,6 +902,9 @@ int batch_level(mis2_ctx *ctx, const mis2_graph &cur, uint64_t seed, int64_t sto
     Workspace ws;
     if (!carve(ctx->ws, ar.head, cur.n, MIS2_OP_COARSEN, &ws))
         return fail(ctx, MIS2_ENOSPACE, "workspace carve failed");
+    // the next level's graph buffers are idle until the quotient below
+    ws.colc = ccol_next;
+    ws.lenc = (int32_t *)crow_next;
     int64_t na_all = 0;
     if ((rc = aggregate_impl(ctx, &cur, seed, agg_dst, &na_all, nullptr, ws, s, ar.P1, ar.P2)))
         return rc;
@@ -992,6 +1037,10 @@ int mis2_coarsen(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int64_t stop
         Workspace ws;
         if (!carve(ctx->ws, head, cur.n, MIS2_OP_COARSEN, &ws))
             return fail(ctx, MIS2_ENOSPACE, "workspace carve failed");
+        // the coarse-graph buffers the quotient of this level writes are idle
+        // until then: they hold the compacted adjacency meanwhile
+        ws.colc = ccol[(lv + 1) & 1];
+        ws.lenc = (int32_t *)crow[(lv + 1) & 1];
         int64_t na = 0;
         if ((rc = aggregate_impl(ctx, &cur, seed, agg_out + off, &na, nullptr, ws, s))) return rc;
         level_n[lv] = cur.n;

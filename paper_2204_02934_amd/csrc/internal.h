@@ -106,6 +106,10 @@ enum Scalar {
     kS_Err = 5,     // error bits
 };
 
+// Accounting sums per round: Decide Set's row lengths, Refresh Column's,
+// and the column indices Refresh Column wrote into compacted rows.
+constexpr int kDegStride = 4;
+
 constexpr int kMaxBlocks = 8192;              // most workgroups of a sweep grid
 constexpr int kMaxWaves = kMaxBlocks * (kBlock / 64);
 
@@ -120,10 +124,15 @@ struct Workspace {
     uint32_t *rt = nullptr;       // [kTraceCap + 2][kRoundStride] round table
     uint32_t *ctr = nullptr;      // [kCtrRing][kCtrSlot] size counters
     uint32_t *scalars = nullptr;  // [kScalars]
-    unsigned long long *degs = nullptr;  // [2][kTraceCap][2] row-length sums per sweep
+    unsigned long long *degs = nullptr;  // [2][kTraceCap][kDegStride] row-length sums per sweep
     unsigned long long *dsplit = nullptr;  // [2][kSplit][16] their partial sums in flight
     uint32_t *blocksum = nullptr; // [compact_blocks(n) + 1]
     uint32_t *bar = nullptr;      // [kBarWords] persistent-kernel barrier state
+    // compacted adjacency of Refresh Column (both null: none), from a
+    // workspace tail or from buffers the caller is not using during the call
+    int32_t *colc = nullptr;      // [nnz]
+    int32_t *lenc = nullptr;      // [n]
+    uint32_t *lflag = nullptr;    // [kSplit * kCtrLine] long-row flags of round 0
     // aggregation only
     int32_t *label = nullptr;     // [n] aggregate labels, -1 = none
     int32_t *list = nullptr;      // [n] ordered vertex lists
@@ -141,6 +150,8 @@ struct Workspace {
 };
 
 size_t workspace_bytes(int64_t n, int op);
+// Extra bytes for the compacted adjacency of Refresh Column (colc, lenc).
+size_t compact_bytes(int64_t n, int64_t nnz);
 bool carve(void *base, size_t bytes, int64_t n, int op, Workspace *ws);
 
 // Launch-plan knobs; never change results.
@@ -148,6 +159,7 @@ struct Plan {
     int lanes = 0;       // lanes per CSR row (power of two <= 64); 0 = automatic
     int blocks = 0;      // workgroups per sweep (<= kMaxBlocks); 0 = automatic
     int persistent = 0;  // 1: one cooperative launch per MIS-2 run; 0: two launches per round
+    int compact = 1;     // 1: Refresh Column skips OUT neighbours when the workspace has room
 };
 
 // One sweep's worklists.  Wavefront w owns slots [w*seg, w*seg + cnt[w]) of
@@ -165,6 +177,20 @@ struct SegIO {
     int64_t n;
     int64_t seg;
     int64_t S;
+    // Refresh Column only.  Compacted adjacency: the row of v keeps, at
+    // [row_ptr[v], row_ptr[v] + len[v]), the column indices whose T was not
+    // OUT when the row was last swept.  ccol_in / lenc_in (both null: read
+    // the CSR's own rows) are the rows to read; ccol_out / lenc_out (null: no
+    // writes) receive the kept rows' compacted form (the same arrays: a row
+    // is rewritten in place by the lane group that reads it).
+    const int32_t *ccol_in;
+    const int32_t *lenc_in;
+    int32_t *ccol_out;
+    int32_t *lenc_out;
+    // Refresh Column of round 0 (unmasked): a wavefront that meets a row
+    // longer than the cooperative threshold sets one of kSplit flags
+    // (stride kCtrLine), or null.
+    uint32_t *long_flag;
 };
 
 // Arguments of the persistent round kernel.  bar: [kMaxBlocks] per-workgroup
@@ -185,9 +211,12 @@ struct RoundsArgs {
     uint32_t *rt;
     uint32_t *ctr;
     unsigned long long *alive_host;
-    unsigned long long *degs;  // [kTraceCap][2] or null
+    unsigned long long *degs;  // [kTraceCap][kDegStride] or null
     unsigned long long *dsplit;  // [2][kSplit][16] partial row-length sums, or null
     uint32_t *bar;
+    int32_t *colc;   // [nnz] compacted rows, or null (no compaction)
+    int32_t *lenc;   // [n] their lengths
+    uint32_t *lflag; // [kSplit][kCtrLine] set by round 0 when a row is long (zero at the start)
     int64_t n, seg, S;
     uint64_t seed, pmask;
     uint32_t b;
@@ -195,14 +224,26 @@ struct RoundsArgs {
     int max_rounds;
 };
 
+// Refresh Column drops OUT neighbours from the long rows it keeps from this
+// round on (unmasked runs): no vertex is OUT before round 0's Decide Set and
+// few are before round 1's, so earlier rewrites would copy nearly whole
+// rows.  A masked run starts with every absent vertex OUT and compacts from
+// round 0.
+constexpr int kCompactFrom = 2;
+// Bit of the host-reported |worklist1| word that says round 0 met rows long
+// enough for the cooperative pass (|worklist1| < 2^31 always).
+constexpr uint32_t kLongRowsBit = 0x80000000u;
+
 // mis2_kernels.hip
 int rounds_max_blocks(int lanes, int num_cus);
 hipError_t launch_rounds(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                          uint32_t *T, uint32_t *M, const RoundsArgs &a, hipStream_t s);
 // e0 / e1 (may be null): events stamped by the launch itself at the kernel's
 // start and end.
+// mode: 0 plain, 1 write compacted rows from the CSR's, 2 read and rewrite
+// them (1 and 2 need lanes > 0 and a.colc / a.lenc).
 hipError_t launch_col_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
-                            const uint32_t *T, uint32_t *M, const RoundsArgs &a, int r,
+                            const uint32_t *T, uint32_t *M, const RoundsArgs &a, int r, int mode,
                             hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_dec_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                             uint32_t *T, const uint32_t *M, const RoundsArgs &a, int r,

@@ -62,25 +62,48 @@ __device__ __forceinline__ int64_t wave_id() {
 // 0 (accounting runs only; fold_deg collects the partial sums).  All threads
 // must call it.
 constexpr int kDegLine = 16;
-__device__ __forceinline__ void wave_degsum(unsigned long long *split, unsigned long long d) {
-    __shared__ unsigned long long part[kBlock / 64];
-    for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
-    if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = d;
+// A second figure w (column indices written into compacted rows) goes to
+// word 1 of the same lines.
+__device__ __forceinline__ void wave_degsum(unsigned long long *split, unsigned long long d,
+                                            unsigned long long w = 0) {
+    __shared__ unsigned long long part[2][kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        d += __shfl_xor(d, off, 64);
+        w += __shfl_xor(w, off, 64);
+    }
+    if ((threadIdx.x & 63u) == 0) {
+        part[0][threadIdx.x >> 6] = d;
+        part[1][threadIdx.x >> 6] = w;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int k = 0; k < kBlock / 64; k++) t += part[k];
+        unsigned long long t = 0, tw = 0;
+        for (int k = 0; k < kBlock / 64; k++) {
+            t += part[0][k];
+            tw += part[1][k];
+        }
         if (t) atomicAdd(&split[(blockIdx.x % kSplit) * kDegLine], t);
+        if (tw) atomicAdd(&split[(blockIdx.x % kSplit) * kDegLine + 1], tw);
     }
 }
 
-// *target += the kSplit partial sums, which are cleared (threads 0..63 of
-// one workgroup).
-__device__ __forceinline__ void fold_deg(unsigned long long *split, unsigned long long *target) {
+// *target += the kSplit partial sums (word 0 of each line) and, when
+// target_w is not null, *target_w += those of word 1; both are cleared
+// (threads 0..63 of one workgroup).
+__device__ __forceinline__ void fold_deg(unsigned long long *split, unsigned long long *target,
+                                         unsigned long long *target_w) {
     unsigned long long x = split[(threadIdx.x & 63u) * kDegLine];
+    unsigned long long y = split[(threadIdx.x & 63u) * kDegLine + 1];
     split[(threadIdx.x & 63u) * kDegLine] = 0ull;
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    if (threadIdx.x == 0) *target += x;
+    split[(threadIdx.x & 63u) * kDegLine + 1] = 0ull;
+    for (int off = 32; off > 0; off >>= 1) {
+        x += __shfl_xor(x, off, 64);
+        y += __shfl_xor(y, off, 64);
+    }
+    if (threadIdx.x == 0) {
+        *target += x;
+        if (target_w) *target_w += y;
+    }
 }
 
 // The rows of wavefront w: either its identity range or its list segment.
@@ -194,17 +217,22 @@ __device__ __forceinline__ int64_t heavy_threshold() {
 constexpr int kCoopLoads = 8;  // loads per lane per cooperative step
 
 // Minimum of T over the column indices [s, e), by the whole wavefront.
-__device__ __forceinline__ uint32_t coop_min_T(const int32_t *__restrict__ col,
-                                               const uint32_t *__restrict__ T, int64_t s,
-                                               int64_t e) {
+// With out != null the indices whose T is not OUT are also written, in
+// order, to out[s ...] (out may be the array read: every store lands at or
+// below the position of an index already loaded), and *written gets their
+// count.
+__device__ __forceinline__ uint32_t coop_min_T(const int32_t *col, const uint32_t *__restrict__ T,
+                                               int64_t s, int64_t e, int32_t *out = nullptr,
+                                               uint32_t *written = nullptr) {
     const int lane = (int)(threadIdx.x & 63u);
     uint32_t m = kOut;
+    uint32_t wc = 0;
     for (int64_t b = s; b < e; b += 64 * kCoopLoads) {
         int32_t x[kCoopLoads];
 #pragma unroll
         for (int k = 0; k < kCoopLoads; k++) {
             const int64_t j = b + (int64_t)k * 64 + lane;
-            x[k] = col[j < e ? j : s];
+            x[k] = col[j < e ? j : s];  // entry s exists: the row is not empty
         }
         uint32_t t[kCoopLoads];
 #pragma unroll
@@ -212,7 +240,17 @@ __device__ __forceinline__ uint32_t coop_min_T(const int32_t *__restrict__ col,
 #pragma unroll
         for (int k = 0; k < kCoopLoads; k++)
             if (b + (int64_t)k * 64 + lane < e) m = min(m, t[k]);
+        if (out) {
+#pragma unroll
+            for (int k = 0; k < kCoopLoads; k++) {
+                const bool kp = b + (int64_t)k * 64 + lane < e && t[k] != kOut;
+                const uint64_t bal = __ballot(kp);
+                if (kp) out[s + wc + (uint32_t)__popcll(bal & lanes_below(lane))] = x[k];
+                wc += (uint32_t)__popcll(bal);
+            }
+        }
     }
+    if (written) *written = wc;
     for (int off = 32; off > 0; off >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, off, 64));
     return m;
 }
@@ -255,7 +293,16 @@ __device__ __forceinline__ void coop_decide(const int32_t *__restrict__ col,
 // unconditionally from clamped, always valid addresses and their results
 // selected afterwards: a predicated load would become a branch with a full
 // wait after it and serialise the streams.
-template <int L, int U, int K>
+//
+// Long rows (more than heavy_threshold<L>() entries when the CSR's, the rows
+// the whole wavefront streams) may carry a compacted form: with io.ccol_out
+// set, the cooperative pass rewrites each long row it sweeps without its OUT
+// entries (T = OUT is final and never lowers a minimum) and records the
+// length; with RD, rows that were long in the CSR are read from that form.
+// A row stays a superset of its live neighbours whether or not it was
+// rewritten in the last round, so short rows and rows that shrank below the
+// threshold are simply read as they are.
+template <int L, int U, int K, bool RD, bool WR>
 __device__ __forceinline__ uint32_t sweep_column(const int64_t *__restrict__ row_ptr,
                                                  const int32_t *__restrict__ col,
                                                  const uint32_t *__restrict__ T,
@@ -264,14 +311,19 @@ __device__ __forceinline__ uint32_t sweep_column(const int64_t *__restrict__ row
     constexpr int G = 64 / L;  // rows per wavefront per unrolled slot
     const int lane = (int)(threadIdx.x & 63u);
     const int sub = lane & (L - 1);
+    const int32_t *colc = io.ccol_in;
+    const int32_t *lenc = io.lenc_in;
+    int32_t *wout = WR ? io.ccol_out : nullptr;
     uint32_t kept = 0;
-    unsigned long long dsum = 0;
+    unsigned long long dsum = 0, wsum = 0;
     // The rows of step i + 1 (list entries, extents, own T) are loaded while
     // step i's column indices and gathers are in flight.
     int32_t v[U];
     bool ok[U];
     int64_t s[U], e[U];
     uint32_t m[U];
+    int32_t lc[U];  // RD: compacted length (meaningful for rows long in the CSR)
+    bool cf[U];     // RD: the row is read from its compacted form
     if (sg.count > 0) {
         load_rows<L, U>(io, sg, 0, v, ok);
 #pragma unroll
@@ -279,6 +331,7 @@ __device__ __forceinline__ uint32_t sweep_column(const int64_t *__restrict__ row
             s[u] = row_ptr[v[u]];
             e[u] = row_ptr[v[u] + 1];
             m[u] = T[v[u]];
+            lc[u] = RD ? lenc[v[u]] : 0;
         }
     }
     for (int64_t i0 = 0; i0 < sg.count; i0 += G * U) {
@@ -287,11 +340,18 @@ __device__ __forceinline__ uint32_t sweep_column(const int64_t *__restrict__ row
         bool okn[U];
         int64_t sn[U] = {}, en[U] = {};
         uint32_t mn[U] = {};
+        int32_t lcn[U] = {};
         if (more) load_rows<L, U>(io, sg, i0 + G * U, vn, okn);
         bool fetched = !more;
+        uint32_t wc[U];  // entries of a rewritten long row
+        bool wrote[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
             if (!ok[u]) e[u] = s[u];
+            cf[u] = RD && e[u] - s[u] > heavy_threshold<L>();
+            if (cf[u]) e[u] = s[u] + lc[u];
+            wc[u] = 0;
+            wrote[u] = false;
             if (sub != 0) m[u] = kOut;
             if (sub == 0) dsum += (unsigned long long)(e[u] - s[u]);
         }
@@ -299,14 +359,25 @@ __device__ __forceinline__ uint32_t sweep_column(const int64_t *__restrict__ row
 #pragma unroll
         for (int u = 0; u < U; u++) {
             uint64_t heavy = __ballot(sub == 0 && e[u] - s[u] > heavy_threshold<L>());
+            // round 0 reports that the graph has such rows (compaction pays
+            // only for them)
+            if (!RD && !WR && heavy && io.long_flag && lane == 0)
+                io.long_flag[(blockIdx.x % kSplit) * kCtrLine] = 1u;
             while (heavy) {
                 const int src = __ffsll((unsigned long long)heavy) - 1;
                 heavy &= heavy - 1;
                 const int64_t hs = __shfl(s[u], src, 64), he = __shfl(e[u], src, 64);
-                const uint32_t hm = coop_min_T(col, T, hs, he);
+                uint32_t hm, hw = 0;
+                if (RD && __shfl((int)cf[u], src, 64) != 0)
+                    hm = coop_min_T(colc, T, hs, he, wout, &hw);
+                else
+                    hm = coop_min_T(col, T, hs, he, wout, &hw);
+                if (WR && lane == 0) wsum += hw;
                 if ((lane & ~(L - 1)) == (src & ~(L - 1))) {
                     m[u] = (sub == 0) ? min(m[u], hm) : kOut;
                     e[u] = s[u];  // its group skips the row below
+                    wc[u] = hw;
+                    wrote[u] = WR;
                 }
             }
         }
@@ -314,18 +385,24 @@ __device__ __forceinline__ uint32_t sweep_column(const int64_t *__restrict__ row
         for (int64_t c0 = 0; c0 < steps; c0 += (int64_t)L * K) {
             int32_t x[U][K];
 #pragma unroll
-            for (int u = 0; u < U; u++)
+            for (int u = 0; u < U; u++) {
+                const int32_t *rs = (RD && cf[u]) ? colc : col;
 #pragma unroll
                 for (int k = 0; k < K; k++) {
                     const int64_t j = s[u] + c0 + k * L + sub;
-                    x[u][k] = col[j < e[u] ? j : 0];
+                    x[u][k] = rs[j < e[u] ? j : 0];
+                    // entry 0 of the compacted array may never have been
+                    // written: lanes past the row's end gather at vertex 0
+                    if (RD && j >= e[u]) x[u][k] = 0;
                 }
+            }
             if (!fetched) {
 #pragma unroll
                 for (int u = 0; u < U; u++) {
                     sn[u] = row_ptr[vn[u]];
                     en[u] = row_ptr[vn[u] + 1];
                     mn[u] = T[vn[u]];
+                    lcn[u] = RD ? lenc[vn[u]] : 0;
                 }
                 fetched = true;
             }
@@ -346,6 +423,7 @@ __device__ __forceinline__ uint32_t sweep_column(const int64_t *__restrict__ row
                 sn[u] = row_ptr[vn[u]];
                 en[u] = row_ptr[vn[u] + 1];
                 mn[u] = T[vn[u]];
+                lcn[u] = RD ? lenc[vn[u]] : 0;
             }
         }
 #pragma unroll
@@ -358,6 +436,7 @@ __device__ __forceinline__ uint32_t sweep_column(const int64_t *__restrict__ row
                 if (m[u] == kIn) m[u] = kOut;
                 M[v[u]] = m[u];
                 keep = (m[u] != kOut);
+                if (WR && keep && wrote[u]) io.lenc_out[v[u]] = (int32_t)wc[u];
             }
             seg_append(io, sg, keep, v[u], kept);
         }
@@ -369,10 +448,11 @@ __device__ __forceinline__ uint32_t sweep_column(const int64_t *__restrict__ row
                 s[u] = sn[u];
                 e[u] = en[u];
                 m[u] = mn[u];
+                lc[u] = lcn[u];
             }
         }
     }
-    if (io.deg_sum) wave_degsum(io.deg_sum, dsum);
+    if (io.deg_sum) wave_degsum(io.deg_sum, dsum, wsum);
     return kept;
 }
 
@@ -776,7 +856,7 @@ __device__ __forceinline__ uint32_t flat_decide(const int64_t *__restrict__ row_
 }
 
 // lanes == 0 in the plan selects the flat sweeps.
-template <int L>
+template <int L, bool RD = false, bool WR = false>
 __device__ __forceinline__ uint32_t any_column(const int64_t *__restrict__ row_ptr,
                                                const int32_t *__restrict__ col,
                                                const uint32_t *__restrict__ T,
@@ -786,7 +866,7 @@ __device__ __forceinline__ uint32_t any_column(const int64_t *__restrict__ row_p
         __shared__ FlatLds sh[kBlock / 64];
         return flat_column<kUnroll>(row_ptr, col, T, M, io, sg, sh[threadIdx.x >> 6]);
     } else {
-        return sweep_column<L, kRows, kChunks<L>>(row_ptr, col, T, M, io, sg);
+        return sweep_column<L, kRows, kChunks<L>, RD, WR>(row_ptr, col, T, M, io, sg);
     }
 }
 
@@ -823,6 +903,7 @@ __device__ __forceinline__ SegIO round_col_io(const RoundsArgs &a, int r) {
     io.n = a.n;
     io.seg = a.seg;
     io.S = a.S;
+    if (r == 0 && !a.masked) io.long_flag = a.lflag;
     return io;
 }
 
@@ -855,29 +936,72 @@ __device__ __forceinline__ void round_sizes(const RoundsArgs &a, int r, uint32_t
     c2 = r == 0 ? c1 : ctr_sum(slot + kCtrList);
 }
 
+// Refresh Column of round r.  Workgroup 0 records the round's sizes and
+// reports (r, |worklist1|) to the host, with bit 31 of the low word set from
+// round 1 on when round 0 met rows long enough for the cooperative pass.
+// RD / WR: read / write the compacted rows.
+template <int L, bool RD, bool WR>
+__device__ __forceinline__ void col_round(const int64_t *__restrict__ row_ptr,
+                                          const int32_t *__restrict__ col,
+                                          const uint32_t *__restrict__ T, uint32_t *__restrict__ M,
+                                          const RoundsArgs &a, int r) {
+    if (blockIdx.x == 0 && threadIdx.x < 64) {
+        uint32_t c1, c2;
+        round_sizes(a, r, c1, c2);
+        const uint32_t longs = (r >= 1 && !a.masked && a.lflag) ? ctr_sum(a.lflag) : 0u;
+        if (threadIdx.x == 0) {
+            a.rt[(size_t)r * kRoundStride] = c1;
+            a.rt[(size_t)r * kRoundStride + 1] = c2;
+            if (a.alive_host)
+                __hip_atomic_store(a.alive_host,
+                                   ((unsigned long long)(uint32_t)r << 32) | c1 |
+                                       (longs ? kLongRowsBit : 0u),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+    clear_slot(a.ctr, r);
+    SegIO io = round_col_io(a, r);
+    if (RD) {
+        io.ccol_in = a.colc;
+        io.lenc_in = a.lenc;
+    }
+    if (WR) {
+        io.ccol_out = a.colc;
+        io.lenc_out = a.lenc;
+    }
+    const int64_t w = wave_id();
+    const Seg sg = seg_of(io, w);
+    const uint32_t kept = any_column<L, RD, WR>(row_ptr, col, T, M, io, sg);
+    seg_finish(io, w, kept);
+}
+
 template <int L>
 __global__ __launch_bounds__(kBlock) void k_col_round(const int64_t *__restrict__ row_ptr,
                                                       const int32_t *__restrict__ col,
                                                       const uint32_t *__restrict__ T,
                                                       uint32_t *__restrict__ M, RoundsArgs a,
                                                       int r) {
-    if (blockIdx.x == 0 && threadIdx.x < 64) {
-        uint32_t c1, c2;
-        round_sizes(a, r, c1, c2);
-        if (threadIdx.x == 0) {
-            a.rt[(size_t)r * kRoundStride] = c1;
-            a.rt[(size_t)r * kRoundStride + 1] = c2;
-            if (a.alive_host)
-                __hip_atomic_store(a.alive_host, ((unsigned long long)(uint32_t)r << 32) | c1,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
-    }
-    clear_slot(a.ctr, r);
-    const SegIO io = round_col_io(a, r);
-    const int64_t w = wave_id();
-    const Seg sg = seg_of(io, w);
-    const uint32_t kept = any_column<L>(row_ptr, col, T, M, io, sg);
-    seg_finish(io, w, kept);
+    col_round<L, false, false>(row_ptr, col, T, M, a, r);
+}
+
+// The first compacting round: reads the CSR's rows, writes compacted ones.
+template <int L>
+__global__ __launch_bounds__(kBlock) void k_col_round_w(const int64_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ col,
+                                                        const uint32_t *__restrict__ T,
+                                                        uint32_t *__restrict__ M, RoundsArgs a,
+                                                        int r) {
+    col_round<L, false, true>(row_ptr, col, T, M, a, r);
+}
+
+// Later compacting rounds: read compacted rows and rewrite the long ones.
+template <int L>
+__global__ __launch_bounds__(kBlock) void k_col_round_rw(const int64_t *__restrict__ row_ptr,
+                                                         const int32_t *__restrict__ col,
+                                                         const uint32_t *__restrict__ T,
+                                                         uint32_t *__restrict__ M, RoundsArgs a,
+                                                         int r) {
+    col_round<L, true, true>(row_ptr, col, T, M, a, r);
 }
 
 template <int L>
@@ -994,7 +1118,8 @@ __global__ __launch_bounds__(kBlock) void k_rounds(const int64_t *__restrict__ r
         if (!grid_barrier(flags, gen, abort_word, ++epoch)) break;
         if (blockIdx.x == 0 && threadIdx.x == 0) stamp(row_cur + kRtStamp1);
         if (a.dsplit && blockIdx.x == 0 && threadIdx.x < 64)
-            fold_deg(a.dsplit + (size_t)kSplit * kDegLine, a.degs + 2 * r + 1);
+            fold_deg(a.dsplit + (size_t)kSplit * kDegLine, a.degs + kDegStride * r + 1,
+                     a.degs + kDegStride * r + 2);
         const SegIO dio = round_dec_io(a, r);
         const TupleParams next{xs64star((a.seed << 32) ^ (uint64_t)(r + 1)), a.pmask, a.b, a.batch};
         sg = seg_of(dio, w);
@@ -1002,7 +1127,8 @@ __global__ __launch_bounds__(kBlock) void k_rounds(const int64_t *__restrict__ r
         seg_finish(dio, w, kept);
         if (!grid_barrier(flags, gen, abort_word, ++epoch)) break;
         if (blockIdx.x == 0 && threadIdx.x == 0) stamp(row_cur + kRtStamp2);
-        if (a.dsplit && blockIdx.x == 0 && threadIdx.x < 64) fold_deg(a.dsplit, a.degs + 2 * r);
+        if (a.dsplit && blockIdx.x == 0 && threadIdx.x < 64)
+            fold_deg(a.dsplit, a.degs + kDegStride * r, nullptr);
         r++;
         // sizes at the start of round r; every workgroup needs worklist1's
         if (threadIdx.x < 64) {
@@ -1025,8 +1151,9 @@ __global__ __launch_bounds__(kBlock) void k_rounds(const int64_t *__restrict__ r
 }
 
 __global__ __launch_bounds__(64) void k_fold_deg(unsigned long long *split,
-                                                 unsigned long long *target) {
-    fold_deg(split, target);
+                                                 unsigned long long *target,
+                                                 unsigned long long *target_w) {
+    fold_deg(split, target, target_w);
 }
 
 // Round-0 tuples for every vertex.
@@ -1184,13 +1311,22 @@ TupleParams tuple_params(int64_t n, uint64_t seed, uint64_t iter) {
     }
 
 hipError_t launch_col_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
-                            const uint32_t *T, uint32_t *M, const RoundsArgs &a, int r,
+                            const uint32_t *T, uint32_t *M, const RoundsArgs &a, int r, int mode,
                             hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    MIS2_LANE_DISPATCH_TIMED(lanes, k_col_round, dim3(blocks), dim3(kBlock), s, e0, e1, row_ptr,
-                             col, T, M, a, r);
+    if (mode != 0 && (lanes <= 0 || !a.colc || !a.lenc)) return hipErrorInvalidValue;
+    if (mode == 1) {
+        MIS2_LANE_DISPATCH_TIMED(lanes, k_col_round_w, dim3(blocks), dim3(kBlock), s, e0, e1,
+                                 row_ptr, col, T, M, a, r);
+    } else if (mode == 2) {
+        MIS2_LANE_DISPATCH_TIMED(lanes, k_col_round_rw, dim3(blocks), dim3(kBlock), s, e0, e1,
+                                 row_ptr, col, T, M, a, r);
+    } else {
+        MIS2_LANE_DISPATCH_TIMED(lanes, k_col_round, dim3(blocks), dim3(kBlock), s, e0, e1,
+                                 row_ptr, col, T, M, a, r);
+    }
     if (a.dsplit) {
         hipLaunchKernelGGL(k_fold_deg, dim3(1), dim3(64), 0, s, a.dsplit + (size_t)kSplit * kDegLine,
-                           a.degs + 2 * r + 1);
+                           a.degs + kDegStride * r + 1, a.degs + kDegStride * r + 2);
     }
     return hipGetLastError();
 }
@@ -1200,7 +1336,9 @@ hipError_t launch_dec_round(int lanes, int blocks, const int64_t *row_ptr, const
                             hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     MIS2_LANE_DISPATCH_TIMED(lanes, k_dec_round, dim3(blocks), dim3(kBlock), s, e0, e1, row_ptr,
                              col, T, M, a, r);
-    if (a.dsplit) hipLaunchKernelGGL(k_fold_deg, dim3(1), dim3(64), 0, s, a.dsplit, a.degs + 2 * r);
+    if (a.dsplit)
+        hipLaunchKernelGGL(k_fold_deg, dim3(1), dim3(64), 0, s, a.dsplit, a.degs + kDegStride * r,
+                           (unsigned long long *)nullptr);
     return hipGetLastError();
 }
 
