@@ -12,6 +12,7 @@ from .oracle import (  # noqa: F401
     mis2,
     mis2_ex,
     aggregate,
+    aggregate_basic,
     quotient,
     coarsen,
 )

@@ -387,6 +387,82 @@ int oracle_aggregate(int64_t n, const int64_t *row_ptr, const int32_t *col,
 }
 
 /* ------------------------------------------------------------------------- */
+/* Algorithm 2 (Section III-B): basic MIS-2 coarsening.                       */
+/*                                                                           */
+/*   agg[n]      out: aggregate of every vertex, numbered 0..n_agg-1          */
+/*   n_agg       out: |MIS-2| (every aggregate has one root)                  */
+/*   roots[n]    out, may be NULL: 1 = root, 0 otherwise                      */
+/*   joined      out, may be NULL: vertices that joined a neighbour's         */
+/*               aggregate in the second loop                                 */
+/* Each MIS-2 vertex becomes a root, and the root with its neighbours one    */
+/* aggregate (roots numbered in increasing vertex id, as in Alg. 3).  Every  */
+/* vertex left over then joins the aggregate of a neighbour.                 */
+/* Reading: "any neighbour" is the smallest aggregate id among the           */
+/* neighbours aggregated by the first loop (the second loop is a parallel    */
+/* for, so it reads the first loop's labels, not its own writes).            */
+/* Returns 0; -1 on bad arguments; -5 if a leftover vertex has no aggregated */
+/* neighbour (maximality of the MIS-2 rules it out).                         */
+/* ------------------------------------------------------------------------- */
+int oracle_aggregate_basic(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                           uint64_t seed, int32_t *agg, int64_t *n_agg,
+                           uint8_t *roots, int64_t *joined)
+{
+    if (n < 0 || !n_agg || (n > 0 && (!row_ptr || !agg)))
+        return -1;
+    if (joined) *joined = 0;
+    if (n == 0) { *n_agg = 0; return 0; }
+
+    uint8_t *st = (uint8_t *)calloc((size_t)n, 1);
+    int32_t *first = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int rc = 0;
+    if (!st || !first) { rc = -1; goto done; }
+    if (roots) memset(roots, 0, (size_t)n);
+
+    /* M <- MIS2(G) */
+    int32_t it = 0;
+    rc = oracle_mis2_ex(n, row_ptr, col, NULL, seed, NULL, 0, st, &it,
+                        NULL, 0, NULL, NULL, NULL, 0);
+    if (rc) goto done;
+
+    /* for v in M: build the aggregate from v and its neighbours */
+    for (int64_t v = 0; v < n; v++) first[v] = -1;
+    int64_t na = 0;
+    for (int64_t v = 0; v < n; v++) {
+        if (!st[v]) continue;
+        if (first[v] != -1) { rc = -5; goto done; }
+        first[v] = (int32_t)na;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+            int64_t w = col[e];
+            if (first[w] != -1) { rc = -5; goto done; }  /* roots are >= 3 apart */
+            first[w] = (int32_t)na;
+        }
+        if (roots) roots[v] = 1;
+        na++;
+    }
+
+    /* for v in V not aggregated: join the aggregate of a neighbour */
+    int64_t nj = 0;
+    for (int64_t v = 0; v < n; v++) {
+        agg[v] = first[v];
+        if (first[v] != -1) continue;
+        int32_t best = -1;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+            int32_t a = first[col[e]];
+            if (a >= 0 && (best < 0 || a < best)) best = a;
+        }
+        if (best < 0) { rc = -5; goto done; }
+        agg[v] = best;
+        nj++;
+    }
+    *n_agg = na;
+    if (joined) *joined = nj;
+
+done:
+    free(st); free(first);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Coarse graph for the next level of a multilevel coarsening.  The paper     */
 /* coarsens recursively (Sections I and II) but does not say how the coarse  */
 /* graph is formed.  Reading: the quotient graph -- vertices are the          */

@@ -60,6 +60,9 @@ def _get():
         lib.oracle_aggregate_ex.argtypes = [
             ctypes.c_int64, _i64p, _i32p, ctypes.c_uint64, _i32p, _i64p, _i64p, _u8p,
             _i64p, _i64p, ctypes.c_int32]
+        lib.oracle_aggregate_basic.restype = ctypes.c_int
+        lib.oracle_aggregate_basic.argtypes = [
+            ctypes.c_int64, _i64p, _i32p, ctypes.c_uint64, _i32p, _i64p, _u8p, _i64p]
         lib.oracle_quotient.restype = ctypes.c_int64
         lib.oracle_quotient.argtypes = [
             ctypes.c_int64, _i64p, _i32p, _i32p, ctypes.c_int64, _i64p, _i32p, ctypes.c_int64]
@@ -168,6 +171,27 @@ def aggregate(row_ptr, col, seed=0, detail=False):
             "iters2": int(info[4]), "m2": int(info[5]), "unagg1": int(info[6]),
             "roots": roots[:n], "trace1": t1[:min(int(info[3]), TRACE_CAP)].copy(),
             "trace2": t2[:min(int(info[4]), TRACE_CAP)].copy()}
+
+
+def aggregate_basic(row_ptr, col, seed=0, detail=False):
+    """Alg. 2 (basic MIS-2 coarsening): returns (agg int32[n], n_agg) or,
+    with detail, a dict that also holds the root marks and the number of
+    vertices that joined a neighbour's aggregate."""
+    row_ptr, col = _csr(row_ptr, col)
+    n = row_ptr.size - 1
+    agg = np.zeros(max(n, 1), np.int32)
+    nagg = ctypes.c_int64(0)
+    roots = np.zeros(max(n, 1), np.uint8)
+    joined = ctypes.c_int64(0)
+    rc = _get().oracle_aggregate_basic(
+        n, _ptr(row_ptr, _i64p), _ptr(col, _i32p), seed, _ptr(agg, _i32p),
+        ctypes.byref(nagg), _ptr(roots, _u8p), ctypes.byref(joined))
+    if rc:
+        raise OracleError("oracle_aggregate_basic returned %d" % rc)
+    if not detail:
+        return agg[:n], int(nagg.value)
+    return {"agg": agg[:n], "n_agg": int(nagg.value), "roots": roots[:n],
+            "joined": int(joined.value)}
 
 
 def quotient(row_ptr, col, agg, n_agg):

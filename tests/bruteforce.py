@@ -9,8 +9,9 @@
   Removal lags one round behind the IN decision, exactly as in Algorithm 1,
   where a neighbourhood sees an IN only in the next round's Refresh Column.
   Distances are computed on the explicit squared graph, not by two sweeps.
-* Aggregation invariants of Algorithm 3 (Section III-B) and the quotient
-  graph by explicit pair sets.
+* Aggregation invariants of Algorithm 3 (Section III-B), Algorithm 2's
+  aggregates from its statement, and the quotient graph by explicit pair
+  sets.
 
 Pure Python on small graphs only.
 """
@@ -173,6 +174,52 @@ def check_aggregation(row_ptr, col, agg, n_agg, roots1, roots2):
                     stack.append(y)
         if seen != ms:
             return "aggregate %d is not connected" % a
+    return None
+
+
+def check_basic_coarsening(row_ptr, col, agg, n_agg, roots):
+    """Algorithm 2 from its statement: the roots are an MIS-2; each root with
+    its neighbours is one aggregate (numbered by increasing root id); every
+    other vertex takes, among the aggregates that hold one of its
+    neighbours, the one with the smallest id.  Returns an error string or
+    None."""
+    n = len(row_ptr) - 1
+    adj = adjacency(row_ptr, col)
+    agg = [int(a) for a in agg]
+    roots = sorted(roots)
+    if n_agg != len(roots):
+        return "n_agg %d != %d roots" % (n_agg, len(roots))
+    if check_mis2(adj, roots):
+        return "roots are not an MIS-2"
+    ball = {k: adj[r] | {r} for k, r in enumerate(roots)}  # the first loop's aggregates
+    for k, b in ball.items():
+        for u in b:
+            if agg[u] != k:
+                return "vertex %d of root %d's neighbourhood has label %d" % (u, roots[k], agg[u])
+    covered = set().union(*ball.values()) if ball else set()
+    for v in range(n):
+        if v in covered:
+            continue
+        touching = [k for k, b in ball.items() if adj[v] & b]
+        if not touching:
+            return "leftover vertex %d touches no aggregate" % v
+        if agg[v] != min(touching):
+            return "leftover vertex %d joined %d, expected %d" % (v, agg[v], min(touching))
+    members = {}
+    for v in range(n):
+        members.setdefault(agg[v], set()).add(v)
+    if sorted(members) != list(range(n_agg)):
+        return "labels are not exactly 0..n_agg-1"
+    for k, ms in members.items():
+        seen, stack = {roots[k]}, [roots[k]]
+        while stack:
+            x = stack.pop()
+            for y in adj[x]:
+                if y in ms and y not in seen:
+                    seen.add(y)
+                    stack.append(y)
+        if seen != ms:
+            return "aggregate %d is not connected to its root" % k
     return None
 
 
