@@ -189,6 +189,27 @@ int mis2_aggregate(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
                    int64_t *n_agg, uint8_t *roots, void *stream);
 
 /*
+ * mis2_aggregate_basic -- Algorithm 2 (Section III-B): basic MIS-2 coarsening.
+ *
+ * Every vertex of an MIS-2 of G becomes a root; each root and its neighbours
+ * form one aggregate, numbered 0..n_agg-1 in increasing root id (as phase 1
+ * of mis2_aggregate).  Every vertex left over then joins the aggregate of a
+ * neighbour: the smallest aggregate id among its neighbours aggregated by
+ * the first step (the paper leaves the choice open; this one is
+ * deterministic and reads only the first step's labels).
+ *
+ *   agg_id    device out, int32[n]: aggregate of every vertex
+ *   n_agg     host out (may be NULL): |MIS-2|
+ *   roots     device out, uint8[n] (may be NULL): 1 = root, 0 otherwise
+ * Needs a workspace of mis2_workspace_bytes(n, MIS2_OP_AGGREGATE) (or the
+ * _csr size for compacted long rows).  MIS2_EINTERNAL if a leftover vertex
+ * has no aggregated neighbour (the maximality of the MIS-2 rules this out).
+ * The per-round sizes of its MIS-2 are phase 0 of mis2_last_trace.
+ */
+int mis2_aggregate_basic(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *agg_id,
+                         int64_t *n_agg, uint8_t *roots, void *stream);
+
+/*
  * mis2_quotient -- the coarse graph of an aggregation, for multilevel
  * coarsening.  The paper coarsens recursively (Sections I and II) but does
  * not say how the coarse graph is formed; here it is the quotient graph:

@@ -30,8 +30,9 @@ MIS2_OPT_COMPACT = 6
 # Every symbol include/mis2.h declares.
 EXPORTS = (
     "mis2_create", "mis2_destroy", "mis2_last_error", "mis2_set_option",
-    "mis2_workspace_bytes", "mis2_workspace_bytes_csr", "mis2_set_workspace", "mis2_run", "mis2_last_trace",
-    "mis2_aggregate", "mis2_last_sweeps", "mis2_quotient", "mis2_coarsen_workspace_bytes",
+    "mis2_workspace_bytes", "mis2_workspace_bytes_csr", "mis2_set_workspace", "mis2_run",
+    "mis2_last_trace", "mis2_aggregate", "mis2_aggregate_basic", "mis2_last_sweeps",
+    "mis2_quotient", "mis2_coarsen_workspace_bytes",
     "mis2_coarsen", "mis2_batch_workspace_bytes", "mis2_aggregate_batched",
     "mis2_server_bytes", "mis2_server_create", "mis2_server_destroy", "mis2_server_last_error",
     "mis2_server_submit", "mis2_server_step", "mis2_server_poll",
@@ -93,6 +94,7 @@ def load():
         "mis2_last_trace": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(i64), i32,
                                            ctypes.POINTER(i32)]),
         "mis2_aggregate": (ctypes.c_int, [vp, gp, u64, vp, ctypes.POINTER(i64), vp, vp]),
+        "mis2_aggregate_basic": (ctypes.c_int, [vp, gp, u64, vp, ctypes.POINTER(i64), vp, vp]),
         "mis2_last_sweeps": (ctypes.c_int, [vp, ctypes.POINTER(Mis2SweepRecord), i32,
                                             ctypes.POINTER(i32)]),
         "mis2_quotient": (ctypes.c_int, [vp, gp, vp, i64, vp, vp, ctypes.POINTER(i64), vp]),

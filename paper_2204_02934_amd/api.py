@@ -123,6 +123,24 @@ class Context:
             return agg[:g.n], na.value, roots[:g.n]
         return agg[:g.n], na.value
 
+    def aggregate_basic(self, row_ptr, col, seed=0, stream=None, nnz=None, want_roots=False):
+        """Algorithm 2 (basic MIS-2 coarsening).  Returns (agg int32[n] on the
+        GPU, n_agg) or, with want_roots, (agg, n_agg, roots uint8[n])."""
+        g, keep = self.graph(row_ptr, col, nnz)
+        self.ensure_workspace(g.n, _lib.MIS2_OP_AGGREGATE, g.nnz)
+        agg = torch.empty(max(g.n, 1), dtype=torch.int32, device=self.device)
+        roots = torch.empty(max(g.n, 1), dtype=torch.uint8, device=self.device) if want_roots else None
+        na = ctypes.c_int64(0)
+        rc = self.lib.mis2_aggregate_basic(self.ptr, ctypes.byref(g), ctypes.c_uint64(seed),
+                                           ctypes.c_void_p(agg.data_ptr()), ctypes.byref(na),
+                                           ctypes.c_void_p(roots.data_ptr() if roots is not None else 0),
+                                           _stream_ptr(stream, self.device))
+        _check(self.lib, self.ptr, rc)
+        del keep
+        if want_roots:
+            return agg[:g.n], na.value, roots[:g.n]
+        return agg[:g.n], na.value
+
     def _ensure_bytes(self, need):
         if self._ws is None or self._ws.numel() < need:
             self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)

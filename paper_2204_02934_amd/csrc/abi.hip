@@ -724,6 +724,68 @@ namespace {
 // batched run (ctx->batch set) P1 / P2 (device, [G + 1] each) receive the
 // per-graph root bounds of phases 1 and 2 (see batch.hip) and agg_id holds
 // union-wide aggregate ids.
+// The first step of Algorithms 2 and 3: the MIS-2 of G, its roots listed in
+// increasing id (ws.list, count in scalar kS_Count1, cleared scalars
+// otherwise) and each root's closed neighbourhood labelled with the root's
+// rank (ws.label, -1 elsewhere; ws.aggsize of each root); roots[v] = 1 for
+// a root when roots is not null.
+int phase1_labels(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspace &ws,
+                  const Geometry &gm, hipStream_t s, uint8_t *roots, int32_t *iters,
+                  std::vector<Launch> *launches, int *long_rows) {
+    int rc;
+    const int64_t n = g->n;
+    uint32_t *sc = ws.scalars;
+    HIP_TRY(ctx, launch_init_tuples(tparams(ctx, n, seed, 0), n, ws.T, s));
+    if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, iters, launches, long_rows)))
+        return rc;
+    HIP_TRY(ctx, launch_fill_u32(sc, 0u, kScalars, s));
+    HIP_TRY(ctx, launch_fill_i32(ws.label, -1, n, s));
+    if (roots) HIP_TRY(ctx, launch_fill_u8(roots, 0, n, s));
+    HIP_TRY(ctx, compact_u32_eq(ws.T, kIn, n, ws.list, sc + kS_Count1, ws.blocksum, s));
+    HIP_TRY(ctx, launch_label_roots(n, g->row_ptr, g->col, ws.list, sc + kS_Count1, nullptr, false,
+                                    ws.label, ws.aggsize, roots, 1, s));
+    return MIS2_OK;
+}
+
+// Algorithm 2: phase1_labels, then every vertex still unlabelled joins the
+// smallest aggregate id among its neighbours' labels.
+int aggregate_basic_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *agg_id,
+                         int64_t *n_agg, uint8_t *roots, const Workspace &ws, hipStream_t s) {
+    int rc;
+    const int64_t n = g->n;
+    uint32_t *sc = ws.scalars;
+    ctx->events_used = 0;
+    std::vector<Launch> launches;
+    const int lanes = lanes_for(ctx, g);
+    const Geometry gm = geometry(ctx, n, lanes);
+    int32_t it = 0;
+    int long_rows = 0;
+    if ((rc = phase1_labels(ctx, g, seed, ws, gm, s, roots, &it, &launches, &long_rows))) return rc;
+    HIP_TRY(ctx, launch_copy_i32(ws.label, agg_id, n, s));
+    SegIO left_io{};
+    left_io.wl_out = ws.wl2[0];
+    left_io.cnt_out = ws.cnt2[0];
+    left_io.n = n;
+    left_io.seg = gm.seg;
+    left_io.S = gm.S;
+    HIP_TRY(ctx, launch_list_unlabelled(gm.blocks, n, ws.label, left_io, s));
+    SegIO join_io{};
+    join_io.wl_in = ws.wl2[0];
+    join_io.cnt_in = ws.cnt2[0];
+    join_io.n = n;
+    join_io.seg = gm.seg;
+    join_io.S = gm.S;
+    HIP_TRY(ctx, launch_join_min(lanes > 0 ? lanes : 4, gm.blocks, g->row_ptr, g->col, ws.label,
+                                 join_io, agg_id, sc + kS_Err, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, sc, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    parse_trace(ctx, 0);
+    if (ctx->pinned[kS_Err])
+        return fail(ctx, MIS2_EINTERNAL, "a vertex without an aggregated neighbour");
+    if (n_agg) *n_agg = (int64_t)ctx->pinned[kS_Count1];
+    return collect_sweeps(ctx, launches, ws, s);
+}
+
 int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *agg_id,
                    int64_t *n_agg, uint8_t *roots, const Workspace &ws, hipStream_t s,
                    uint32_t *P1 = nullptr, uint32_t *P2 = nullptr) {
@@ -736,17 +798,10 @@ int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
 
     // Phase 1: MIS-2 of G; roots numbered by increasing id, each labelled with
     // its neighbours.
-    HIP_TRY(ctx, launch_init_tuples(tparams(ctx, n, seed, 0), n, ws.T, s));
     int32_t it1 = 0, it2 = 0;
     int long_rows = 0;
-    if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, &it1, &launches, &long_rows)))
+    if ((rc = phase1_labels(ctx, g, seed, ws, gm, s, roots, &it1, &launches, &long_rows)))
         return rc;
-    HIP_TRY(ctx, launch_fill_u32(sc, 0u, kScalars, s));
-    HIP_TRY(ctx, launch_fill_i32(ws.label, -1, n, s));
-    if (roots) HIP_TRY(ctx, launch_fill_u8(roots, 0, n, s));
-    HIP_TRY(ctx, compact_u32_eq(ws.T, kIn, n, ws.list, sc + kS_Count1, ws.blocksum, s));
-    HIP_TRY(ctx, launch_label_roots(n, g->row_ptr, g->col, ws.list, sc + kS_Count1, nullptr, false,
-                                    ws.label, ws.aggsize, roots, 1, s));
     if (P1)
         HIP_TRY(ctx, launch_graph_bounds(ws.list, sc + kS_Count1, ctx->batch.voff, ctx->batch.G,
                                          P1, s));
@@ -972,6 +1027,26 @@ int mis2_aggregate(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
     if ((rc = get_workspace(ctx, g, MIS2_OP_AGGREGATE, &ws))) return rc;
     if ((rc = maybe_validate(ctx, g, ws, s))) return rc;
     return aggregate_impl(ctx, g, seed, agg_id, n_agg, roots, ws, s);
+}
+
+int mis2_aggregate_basic(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *agg_id,
+                         int64_t *n_agg, uint8_t *roots, void *stream) {
+    int rc = check_graph_args(ctx, g);
+    if (rc) return rc;
+    if (g->n > 0 && !agg_id) return fail(ctx, MIS2_EINVAL, "agg_id is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    ctx->trace[0].clear();
+    ctx->trace[1].clear();
+    ctx->sweeps.clear();
+    if (g->n == 0) {
+        if (n_agg) *n_agg = 0;
+        return MIS2_OK;
+    }
+    Workspace ws;
+    if ((rc = get_workspace(ctx, g, MIS2_OP_AGGREGATE, &ws))) return rc;
+    if ((rc = maybe_validate(ctx, g, ws, s))) return rc;
+    return aggregate_basic_impl(ctx, g, seed, agg_id, n_agg, roots, ws, s);
 }
 
 int mis2_quotient(mis2_ctx *ctx, const mis2_graph *g, const int32_t *agg_id, int64_t n_agg,

@@ -433,6 +433,105 @@ __global__ __launch_bounds__(kBlock) void k_phase3_long(const int64_t *__restric
     }
 }
 
+// ---------------------------------------------------------------------------
+// Algorithm 2's second loop: every vertex left unaggregated by the first loop
+// joins the aggregate of a neighbour -- the smallest aggregate id among its
+// neighbours' first-loop labels.  The labels are read as unsigned, so -1
+// (unaggregated) is above every id and never wins.  The labels read are
+// the frozen first-loop ones (label); the result goes to agg_out, so rows
+// are independent.
+// ---------------------------------------------------------------------------
+
+// Smallest label (as unsigned) over the column indices [s, e), by the whole
+// wavefront.
+__device__ __forceinline__ uint32_t coop_min_label(const int32_t *__restrict__ col,
+                                                   const int32_t *__restrict__ label, int64_t s,
+                                                   int64_t e) {
+    const int lane = (int)(threadIdx.x & 63u);
+    uint32_t m = 0xFFFFFFFFu;
+    for (int64_t b = s; b < e; b += 64 * kCoopLoads) {
+        int32_t x[kCoopLoads];
+#pragma unroll
+        for (int k = 0; k < kCoopLoads; k++) {
+            const int64_t j = b + (int64_t)k * 64 + lane;
+            x[k] = col[j < e ? j : s];
+        }
+        uint32_t a[kCoopLoads];
+#pragma unroll
+        for (int k = 0; k < kCoopLoads; k++) a[k] = (uint32_t)label[x[k]];
+#pragma unroll
+        for (int k = 0; k < kCoopLoads; k++)
+            if (b + (int64_t)k * 64 + lane < e) m = min(m, a[k]);
+    }
+    for (int off = 32; off > 0; off >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, off, 64));
+    return m;
+}
+
+// One group of L lanes per row of the wavefront's segment of io.wl_in (the
+// unaggregated vertices), K chunks of L column indices loaded before their
+// labels are gathered; rows longer than 32 * L go to the whole wavefront.
+// A vertex with no aggregated neighbour sets bit 1 of *err.
+template <int L>
+__global__ __launch_bounds__(kBlock) void k_join_min(const int64_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col,
+                                                     const int32_t *__restrict__ label,
+                                                     SegIO io, int32_t *__restrict__ agg_out,
+                                                     uint32_t *__restrict__ err) {
+    constexpr int K = L >= 32 ? 1 : (32 / L > 8 ? 8 : 32 / L);
+    constexpr int G = 64 / L;
+    constexpr int64_t kLong = L >= 64 ? 1024 : (int64_t)32 * L;
+    const int64_t w = wave_id();
+    if (w >= io.S) return;
+    const int64_t count = io.cnt_in[w];
+    const int64_t sbase = w * io.seg;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int sub = lane & (L - 1);
+    for (int64_t i0 = 0; i0 < count; i0 += G) {
+        const int64_t i = i0 + lane / L;
+        const bool valid = i < count;
+        const int32_t v = io.wl_in[sbase + (valid ? i : count - 1)];
+        const int64_t s = row_ptr[v];
+        int64_t e = valid ? row_ptr[v + 1] : s;
+        uint32_t m = 0xFFFFFFFFu;
+        uint64_t heavy = __ballot(sub == 0 && e - s > kLong);
+        while (heavy) {
+            const int src = __ffsll((unsigned long long)heavy) - 1;
+            heavy &= heavy - 1;
+            const uint32_t hm =
+                coop_min_label(col, label, __shfl(s, src, 64), __shfl(e, src, 64));
+            if ((lane & ~(L - 1)) == (src & ~(L - 1))) {
+                m = min(m, hm);
+                e = s;  // its group skips the row below
+            }
+        }
+        int64_t wmax = e - s;
+        for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off, 64));
+        for (int64_t c0 = 0; c0 < wmax; c0 += (int64_t)L * K) {
+            int32_t x[K];
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const int64_t j = s + c0 + k * L + sub;
+                x[k] = col[j < e ? j : 0];
+            }
+            uint32_t a[K];
+#pragma unroll
+            for (int k = 0; k < K; k++) a[k] = (uint32_t)label[x[k]];
+#pragma unroll
+            for (int k = 0; k < K; k++)
+                if (s + c0 + k * L + sub < e) m = min(m, a[k]);
+        }
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1)
+            m = min(m, (uint32_t)__shfl_xor((int)m, off, L));
+        if (valid && sub == 0) {
+            if (m == 0xFFFFFFFFu)
+                atomicOr(err, 2u);
+            else
+                agg_out[v] = (int32_t)m;
+        }
+    }
+}
+
 int grid_for(int64_t work, int per_block, int cap) {
     int64_t b = (work + per_block - 1) / per_block;
     if (b < 1) b = 1;
@@ -484,6 +583,26 @@ hipError_t launch_list_unlabelled(int blocks, int64_t n, const int32_t *label, c
         case 64: hipLaunchKernelGGL(k_phase3<64>, __VA_ARGS__); break;                 \
         default: return hipErrorInvalidValue;                                          \
     }
+
+#define MIS2_JOIN_DISPATCH(L, ...)                                                     \
+    switch (L) {                                                                       \
+        case 1: hipLaunchKernelGGL(k_join_min<1>, __VA_ARGS__); break;                 \
+        case 2: hipLaunchKernelGGL(k_join_min<2>, __VA_ARGS__); break;                 \
+        case 4: hipLaunchKernelGGL(k_join_min<4>, __VA_ARGS__); break;                 \
+        case 8: hipLaunchKernelGGL(k_join_min<8>, __VA_ARGS__); break;                 \
+        case 16: hipLaunchKernelGGL(k_join_min<16>, __VA_ARGS__); break;               \
+        case 32: hipLaunchKernelGGL(k_join_min<32>, __VA_ARGS__); break;               \
+        case 64: hipLaunchKernelGGL(k_join_min<64>, __VA_ARGS__); break;               \
+        default: return hipErrorInvalidValue;                                          \
+    }
+
+hipError_t launch_join_min(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
+                           const int32_t *label, const SegIO &io, int32_t *agg_out,
+                           uint32_t *err, hipStream_t s) {
+    MIS2_JOIN_DISPATCH(lanes, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col, label, io, agg_out,
+                       err);
+    return hipGetLastError();
+}
 
 hipError_t launch_phase3(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                          const int32_t *label, const int32_t *aggsize, const SegIO &io,

@@ -314,6 +314,12 @@ hipError_t launch_list_unlabelled(int blocks, int64_t n, const int32_t *label, c
                                   hipStream_t s);
 // io: the unaggregated rows (wl_in / cnt_in) and the list of long rows it
 // leaves (wl_out / cnt_out); io_long: that list as input.
+// Algorithm 2's second loop over the unaggregated vertices listed in io
+// (wl_in / cnt_in): agg_out[v] = the smallest first-loop label among v's
+// neighbours; bit 1 of *err if there is none.
+hipError_t launch_join_min(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
+                           const int32_t *label, const SegIO &io, int32_t *agg_out,
+                           uint32_t *err, hipStream_t s);
 hipError_t launch_phase3(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                          const int32_t *label, const int32_t *aggsize, const SegIO &io,
                          const SegIO &io_long, int32_t *agg_out, uint32_t *err, hipStream_t s);
