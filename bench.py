@@ -270,6 +270,9 @@ def main():
                     help="first run three device-to-device copies of MIB MiB (a known-size "
                          "kernel for scaling hardware byte counters)")
     ap.add_argument("--c5-jobs", type=int, default=32, help="serving: jobs in the pool")
+    ap.add_argument("--aggregation", choices=("alg3", "alg2"), default="alg3",
+                    help="c1-c3: the aggregation of the step, MIS-2 based aggregation "
+                         "(mis2_aggregate) or basic MIS-2 coarsening (mis2_aggregate_basic)")
     args = ap.parse_args()
     if args.gpus != 1:
         raise SystemExit("bench.py measures one GPU: this build has no multi-GPU path "
@@ -287,7 +290,10 @@ def main():
     from paper_2204_02934_amd import api
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    agg_call = "aggregate" if args.aggregation == "alg3" else "aggregate_basic"
     name, (rp_h, col_h) = workload(args.workload)
+    if args.aggregation == "alg2":
+        name = name.replace("MIS-2 + MIS-2 aggregation", "MIS-2 + basic MIS-2 coarsening")
     n, nnz = rp_h.size - 1, int(rp_h[-1])
     log("workload:", name, "n=%d nnz=%d" % (n, nnz))
     dev = torch.device("cuda", 0)
@@ -309,7 +315,7 @@ def main():
 
     def step(c):
         c.mis2(rp, col, args.seed, nnz=nnz)
-        c.aggregate(rp, col, args.seed, nnz=nnz)
+        getattr(c, agg_call)(rp, col, args.seed, nnz=nnz)
 
     for _ in range(args.warmup):
         step(ctx)
@@ -325,7 +331,7 @@ def main():
         a = time.perf_counter()
         ctx.mis2(rp, col, args.seed, nnz=nnz)
         b = time.perf_counter()
-        ctx.aggregate(rp, col, args.seed, nnz=nnz)
+        getattr(ctx, agg_call)(rp, col, args.seed, nnz=nnz)
         c = time.perf_counter()
         t_mis.append(b - a)
         t_agg.append(c - b)
@@ -341,7 +347,7 @@ def main():
     acc.ensure_workspace(n, 1, nnz)
     acc.mis2(rp, col, args.seed, nnz=nnz)
     recs_mis = acc.last_sweeps()
-    acc.aggregate(rp, col, args.seed, nnz=nnz)
+    getattr(acc, agg_call)(rp, col, args.seed, nnz=nnz)
     recs_agg = acc.last_sweeps()
     accounted = recs_mis + recs_agg
 
@@ -355,7 +361,7 @@ def main():
     for _ in range(args.steps):
         prof.mis2(rp, col, args.seed, nnz=nnz)
         r1 = prof.last_sweeps()
-        prof.aggregate(rp, col, args.seed, nnz=nnz)
+        getattr(prof, agg_call)(rp, col, args.seed, nnz=nnz)
         r2 = prof.last_sweeps()
         recs = r1 + r2
         assert len(recs) == len(accounted)
@@ -427,14 +433,15 @@ def main():
         tc0 = time.perf_counter()
         while True:
             oracle.mis2(rp_h, col_h, args.seed)
-            oracle.aggregate(rp_h, col_h, args.seed)
+            getattr(oracle, agg_call)(rp_h, col_h, args.seed)
             reps += 1
             if time.perf_counter() - tc0 > 8.0 or reps >= 20:
                 break
         tcpu = (time.perf_counter() - tc0) / reps
         cpu = {"value": nnz / tcpu, "unit": "nnz/s", "cores": 1, "kind": "oracle",
-               "sample": "%d full steps (MIS-2 + aggregation) of the same graph, %.2f s each"
-                         % (reps, tcpu)}
+               "sample": "%d full steps (MIS-2 + %s) of the same graph, %.2f s each"
+                         % (reps, "aggregation" if args.aggregation == "alg3"
+                            else "basic coarsening", tcpu)}
         log("cpu oracle: %.3f s/step" % tcpu)
 
     out = {
@@ -451,11 +458,13 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": name, "n": n, "nnz": nnz, "seed": args.seed,
-                   "step": "mis2_run + mis2_aggregate, graph resident in HBM",
+                   "step": "mis2_run + %s, graph resident in HBM" % (
+                       "mis2_aggregate" if args.aggregation == "alg3" else "mis2_aggregate_basic"),
                    "index_types": "int64 row offsets, int32 columns"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": measured_traffic(args.workload, dom, d["launches"]),
+                     "traffic": measured_traffic(args.workload + ("" if args.aggregation == "alg3"
+                                                                  else "_alg2"), dom, d["launches"]),
                      "copy_ceiling": copy_gbps, "frac_of_copy_ceiling": achieved / copy_gbps,
                      "kernel": dom, "launches_per_step": d["launches"],
                      "bytes_per_launch": d["bytes"] / d["launches"],
