@@ -11,6 +11,10 @@ from .oracle import (  # noqa: F401
     pack,
     mis2,
     mis2_ex,
+    mis2_ablation,
+    xorshift64,
+    PRIO_FIXED,
+    PRIO_XORSHIFT,
     aggregate,
     aggregate_basic,
     quotient,

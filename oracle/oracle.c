@@ -50,6 +50,35 @@ uint64_t oracle_hash(uint64_t seed, uint64_t iter, uint64_t v)
     return oracle_xorshift64star(oracle_xorshift64star(i) ^ oracle_xorshift64star(v));
 }
 
+/* Section V-A, Table I ("Xor Hash"): f is 64-bit xorshift instead.
+ * Reading: the paper defines xorshift* as xorshift followed by a linear
+ * congruential step, so this xorshift is the first stage of the xorshift*
+ * above -- shifts 12, 25, 27 with no multiplication.  (On the 7-point 100^3
+ * Laplacian it gives 19 rounds where Table I reports 20; Marsaglia's triple
+ * 13, 7, 17 would give 10.) */
+uint64_t oracle_xorshift64(uint64_t x)
+{
+    x ^= x >> 12;
+    x ^= x << 25;
+    x ^= x >> 27;
+    return x;
+}
+
+/* Priority choices of the Section V-A comparison (Table I), for
+ * oracle_mis2_ablation: */
+#define ORACLE_PRIO_FIXED    1  /* Bell et al.: priorities drawn once (round 0's hash in every round) */
+#define ORACLE_PRIO_XORSHIFT 2  /* f = xorshift instead of xorshift* */
+
+static uint64_t oracle_priority(uint64_t seed, uint64_t iter, uint64_t v, int pflags)
+{
+    if (pflags & ORACLE_PRIO_FIXED) iter = 0;
+    if (pflags & ORACLE_PRIO_XORSHIFT) {
+        uint64_t i = (seed << 32) ^ iter;
+        return oracle_xorshift64(oracle_xorshift64(i) ^ oracle_xorshift64(v));
+    }
+    return oracle_hash(seed, iter, v);
+}
+
 /* Section V-C, Eq. (1): b = ceil(log2(|V| + 2)), i.e. the smallest integer b
  * with 2^b >= |V| + 2, computed with integers only. */
 int oracle_id_bits(int64_t n)
@@ -90,6 +119,14 @@ uint32_t oracle_pack(uint64_t prio, int64_t v, int b)
  *                              T after Decide Set
  * Returns 0, -1 on bad arguments, -6 if injected priorities ran out.
  */
+static int mis2_core(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                     const uint8_t *active, uint64_t seed,
+                     const uint64_t *prio, int32_t prio_rounds,
+                     uint8_t *status, int32_t *n_iters,
+                     int64_t *trace, int32_t trace_cap,
+                     uint32_t *T_hist, uint32_t *M_hist, uint32_t *D_hist,
+                     int32_t hist_cap, int pflags);
+
 int oracle_mis2_ex(int64_t n, const int64_t *row_ptr, const int32_t *col,
                    const uint8_t *active, uint64_t seed,
                    const uint64_t *prio, int32_t prio_rounds,
@@ -97,6 +134,34 @@ int oracle_mis2_ex(int64_t n, const int64_t *row_ptr, const int32_t *col,
                    int64_t *trace, int32_t trace_cap,
                    uint32_t *T_hist, uint32_t *M_hist, uint32_t *D_hist,
                    int32_t hist_cap)
+{
+    return mis2_core(n, row_ptr, col, active, seed, prio, prio_rounds, status, n_iters,
+                     trace, trace_cap, T_hist, M_hist, D_hist, hist_cap, 0);
+}
+
+/*
+ * Algorithm 1 with the priorities of the Section V-A comparison (Table I):
+ * pflags = 0 is Algorithm 1 itself, ORACLE_PRIO_FIXED draws the priorities
+ * once (Bell et al.), ORACLE_PRIO_XORSHIFT uses xorshift as f.  The other
+ * optimizations of Section V (worklists, packed tuples, SIMD) change how
+ * much work a round does, not what it computes, so they have no switch here.
+ * Outputs as in oracle_mis2_ex.
+ */
+int oracle_mis2_ablation(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                         uint64_t seed, int pflags, uint8_t *status, int32_t *n_iters,
+                         int64_t *trace, int32_t trace_cap)
+{
+    return mis2_core(n, row_ptr, col, NULL, seed, NULL, 0, status, n_iters,
+                     trace, trace_cap, NULL, NULL, NULL, 0, pflags);
+}
+
+static int mis2_core(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                     const uint8_t *active, uint64_t seed,
+                     const uint64_t *prio, int32_t prio_rounds,
+                     uint8_t *status, int32_t *n_iters,
+                     int64_t *trace, int32_t trace_cap,
+                     uint32_t *T_hist, uint32_t *M_hist, uint32_t *D_hist,
+                     int32_t hist_cap, int pflags)
 {
     if (n < 0 || (n > 0 && (!row_ptr || !status || !n_iters)))
         return -1;
@@ -150,7 +215,7 @@ int oracle_mis2_ex(int64_t n, const int64_t *row_ptr, const int32_t *col,
                 if (iter >= prio_rounds) { rc = -6; goto done; }
                 p = prio[(int64_t)iter * n + v];
             } else {
-                p = oracle_hash(seed, (uint64_t)iter, (uint64_t)v);
+                p = oracle_priority(seed, (uint64_t)iter, (uint64_t)v, pflags);
             }
             T[v] = oracle_pack(p, v, b);
         }

@@ -60,6 +60,12 @@ def _get():
         lib.oracle_aggregate_ex.argtypes = [
             ctypes.c_int64, _i64p, _i32p, ctypes.c_uint64, _i32p, _i64p, _i64p, _u8p,
             _i64p, _i64p, ctypes.c_int32]
+        lib.oracle_xorshift64.restype = ctypes.c_uint64
+        lib.oracle_xorshift64.argtypes = [ctypes.c_uint64]
+        lib.oracle_mis2_ablation.restype = ctypes.c_int
+        lib.oracle_mis2_ablation.argtypes = [
+            ctypes.c_int64, _i64p, _i32p, ctypes.c_uint64, ctypes.c_int, _u8p, _i32p, _i64p,
+            ctypes.c_int32]
         lib.oracle_aggregate_basic.restype = ctypes.c_int
         lib.oracle_aggregate_basic.argtypes = [
             ctypes.c_int64, _i64p, _i32p, ctypes.c_uint64, _i32p, _i64p, _u8p, _i64p]
@@ -171,6 +177,31 @@ def aggregate(row_ptr, col, seed=0, detail=False):
             "iters2": int(info[4]), "m2": int(info[5]), "unagg1": int(info[6]),
             "roots": roots[:n], "trace1": t1[:min(int(info[3]), TRACE_CAP)].copy(),
             "trace2": t2[:min(int(info[4]), TRACE_CAP)].copy()}
+
+
+PRIO_FIXED = 1     # priorities drawn once (Bell et al.)
+PRIO_XORSHIFT = 2  # f = xorshift instead of xorshift* (Table I's "Xor Hash")
+
+
+def xorshift64(x):
+    return int(_get().oracle_xorshift64(x & 0xFFFFFFFFFFFFFFFF))
+
+
+def mis2_ablation(row_ptr, col, seed=0, pflags=0):
+    """Alg. 1 with the priorities of the Section V-A comparison: returns
+    (status u8[n], n_iters, trace int64[rounds, 4])."""
+    row_ptr, col = _csr(row_ptr, col)
+    n = row_ptr.size - 1
+    status = np.zeros(max(n, 1), np.uint8)
+    it = ctypes.c_int32(0)
+    trace = np.zeros((TRACE_CAP, 4), np.int64)
+    rc = _get().oracle_mis2_ablation(n, _ptr(row_ptr, _i64p), _ptr(col, _i32p), seed, pflags,
+                                     _ptr(status, _u8p), ctypes.byref(it), _ptr(trace, _i64p),
+                                     TRACE_CAP)
+    if rc:
+        raise OracleError("oracle_mis2_ablation returned %d" % rc)
+    r = it.value
+    return status[:n], r, trace[:min(r, TRACE_CAP)].copy()
 
 
 def aggregate_basic(row_ptr, col, seed=0, detail=False):

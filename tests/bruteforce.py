@@ -27,6 +27,16 @@ def xs64star(x):
     return (x * 0x2545F4914F6CDD1D) & MASK64
 
 
+def xs64(x):
+    """xorshift64 as xorshift*'s first stage (shifts 12, 25, 27, no
+    multiplication): the "Xor Hash" of Table I."""
+    x &= MASK64
+    x ^= x >> 12
+    x ^= (x << 25) & MASK64
+    x ^= x >> 27
+    return x
+
+
 def prio_hash(seed, it, v):
     """h(iter, v) = f(f(iter) xor f(v)) (Section V-A), iter offset by seed << 32."""
     return xs64star(xs64star(((seed << 32) ^ it) & MASK64) ^ xs64star(v))
