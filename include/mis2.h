@@ -133,6 +133,36 @@ int mis2_set_workspace(mis2_ctx *ctx, void *dev_ptr, size_t bytes);
 int mis2_run(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, uint8_t *status,
              int64_t *n_roots, int32_t *n_iters, void *stream);
 
+/*
+ * mis2_run_ablation -- Algorithm 1 with the optimizations of Section V taken
+ * away, for the comparison of Fig. 2 and Table I.  flags (bitwise or):
+ */
+#define MIS2_ABL_FIXED_PRIORITY 1   /* priorities drawn once, round 0's hash in every round
+                                       (Bell et al.); changes the result */
+#define MIS2_ABL_XORSHIFT       2   /* f = xorshift (shifts 12, 25, 27, no multiplication) instead
+                                       of xorshift* (Table I's "Xor Hash"); changes the result */
+#define MIS2_ABL_NO_WORKLISTS   4   /* every round sweeps every vertex (Section V-B taken away) */
+#define MIS2_ABL_UNPACKED       8   /* three-field tuples (status, priority, id) in three arrays
+                                       (Section V-C taken away) */
+#define MIS2_ABL_ONE_LANE      16   /* one lane per CSR row (Section V-D taken away) */
+#define MIS2_ABL_SIMPLE        32   /* the simple kernels even with none of the flags above */
+#define MIS2_ABL_ALL_FLAGS     63
+/*
+ * With none of flags 1, 2, 4, 8 or 32 the production kernels run (as mis2_run,
+ * with one lane per row under MIS2_ABL_ONE_LANE).  Otherwise simple kernels
+ * run: one lane per row, a plain loop over each row, packed or three-field
+ * tuples, worklists or every vertex.  The priority field of a three-field
+ * tuple holds the same bits as the packed tuple, so only flags 1 and 2
+ * change the result; the others change only the work done.  Outputs as in
+ * mis2_run; per-round sizes and launch records as after mis2_run.  Needs a
+ * workspace of mis2_ablation_workspace_bytes(n, flags).
+ */
+int mis2_run_ablation(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int flags,
+                      uint8_t *status, int64_t *n_roots, int32_t *n_iters, void *stream);
+
+/* Bytes of device workspace mis2_run_ablation needs (written to *bytes, host). */
+int mis2_ablation_workspace_bytes(int64_t n, int flags, size_t *bytes);
+
 /* Per-round worklist sizes of the last mis2_run (or of the two MIS-2 runs
  * of the last mis2_aggregate, phase 1 then phase 2): host out
  * sizes[r*2 + 0] = |worklist1|, sizes[r*2 + 1] = |worklist2| at the start of

@@ -26,12 +26,19 @@ MIS2_OPT_PROFILE = 3
 MIS2_OPT_ACCOUNT = 4
 MIS2_OPT_PERSISTENT = 5
 MIS2_OPT_COMPACT = 6
+MIS2_ABL_FIXED_PRIORITY = 1
+MIS2_ABL_XORSHIFT = 2
+MIS2_ABL_NO_WORKLISTS = 4
+MIS2_ABL_UNPACKED = 8
+MIS2_ABL_ONE_LANE = 16
+MIS2_ABL_SIMPLE = 32
 
 # Every symbol include/mis2.h declares.
 EXPORTS = (
     "mis2_create", "mis2_destroy", "mis2_last_error", "mis2_set_option",
     "mis2_workspace_bytes", "mis2_workspace_bytes_csr", "mis2_set_workspace", "mis2_run",
     "mis2_last_trace", "mis2_aggregate", "mis2_aggregate_basic", "mis2_last_sweeps",
+    "mis2_run_ablation", "mis2_ablation_workspace_bytes",
     "mis2_quotient", "mis2_coarsen_workspace_bytes",
     "mis2_coarsen", "mis2_batch_workspace_bytes", "mis2_aggregate_batched",
     "mis2_server_bytes", "mis2_server_create", "mis2_server_destroy", "mis2_server_last_error",
@@ -95,6 +102,10 @@ def load():
                                            ctypes.POINTER(i32)]),
         "mis2_aggregate": (ctypes.c_int, [vp, gp, u64, vp, ctypes.POINTER(i64), vp, vp]),
         "mis2_aggregate_basic": (ctypes.c_int, [vp, gp, u64, vp, ctypes.POINTER(i64), vp, vp]),
+        "mis2_run_ablation": (ctypes.c_int, [vp, gp, u64, ctypes.c_int, vp, ctypes.POINTER(i64),
+                                             ctypes.POINTER(i32), vp]),
+        "mis2_ablation_workspace_bytes": (ctypes.c_int, [i64, ctypes.c_int,
+                                                         ctypes.POINTER(ctypes.c_size_t)]),
         "mis2_last_sweeps": (ctypes.c_int, [vp, ctypes.POINTER(Mis2SweepRecord), i32,
                                             ctypes.POINTER(i32)]),
         "mis2_quotient": (ctypes.c_int, [vp, gp, vp, i64, vp, vp, ctypes.POINTER(i64), vp]),

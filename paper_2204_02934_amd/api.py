@@ -123,6 +123,23 @@ class Context:
             return agg[:g.n], na.value, roots[:g.n]
         return agg[:g.n], na.value
 
+    def mis2_ablation(self, row_ptr, col, seed=0, flags=0, stream=None, nnz=None):
+        """Algorithm 1 with Section V's optimizations taken away (MIS2_ABL_*
+        flags).  Returns (status uint8[n] on the GPU, n_roots, n_iters)."""
+        g, keep = self.graph(row_ptr, col, nnz)
+        b = ctypes.c_size_t(0)
+        _check(self.lib, self.ptr,
+               self.lib.mis2_ablation_workspace_bytes(g.n, int(flags), ctypes.byref(b)))
+        self._ensure_bytes(max(b.value, self.workspace_bytes(g.n, _lib.MIS2_OP_MIS2, g.nnz)))
+        status = torch.empty(max(g.n, 1), dtype=torch.uint8, device=self.device)
+        nr, ni = ctypes.c_int64(0), ctypes.c_int32(0)
+        rc = self.lib.mis2_run_ablation(self.ptr, ctypes.byref(g), ctypes.c_uint64(seed), int(flags),
+                                        ctypes.c_void_p(status.data_ptr()), ctypes.byref(nr),
+                                        ctypes.byref(ni), _stream_ptr(stream, self.device))
+        _check(self.lib, self.ptr, rc)
+        del keep
+        return status[:g.n], nr.value, ni.value
+
     def aggregate_basic(self, row_ptr, col, seed=0, stream=None, nnz=None, want_roots=False):
         """Algorithm 2 (basic MIS-2 coarsening).  Returns (agg int32[n] on the
         GPU, n_agg) or, with want_roots, (agg, n_agg, roots uint8[n])."""

@@ -294,10 +294,18 @@ RoundsArgs round_args(const mis2_ctx *ctx, const mis2_graph *g, uint64_t seed,
 // cooperative threshold, 0 if not (or if the run ended before round 1
 // started); for a masked run, in: the value of the unmasked run of the same
 // graph.  Refresh Column compacts (launch modes 1 then 2) only when it is 1.
+// The ablation kernels' configuration (null: the production kernels).
+struct AblRun {
+    bool unpacked = false;  // three-field tuples
+    bool all = false;       // every vertex every round
+    int pflags = 0;         // kAblFixed | kAblXorshift
+    AblTuples T, M;
+};
+
 int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspace &ws,
                const Geometry &gm, bool masked, int phase, hipStream_t s, int32_t *iters_out,
-               std::vector<Launch> *launches, int *long_rows) {
-    const int lanes = lanes_for(ctx, g);
+               std::vector<Launch> *launches, int *long_rows, const AblRun *abl = nullptr) {
+    const int lanes = abl ? 1 : lanes_for(ctx, g);
     unsigned long long *degs = ws.degs + (size_t)phase * kTraceCap * kDegStride;
     if (ctx->account) {
         HIP_TRY(ctx, launch_fill_u64(degs, 0ull, kDegStride * kTraceCap, s));
@@ -310,13 +318,20 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
                                  (int64_t)(masked ? kCtrRing - 1 : kCtrRing) * kCtrSlot, s));
     if (!masked) HIP_TRY(ctx, launch_fill_u32(ws.rt, (uint32_t)g->n, 2, s));
     if (!masked) HIP_TRY(ctx, launch_fill_u32(ws.lflag, 0u, (int64_t)kSplit * kCtrLine, s));
-    if (ctx->plan.persistent) {
+    if (ctx->plan.persistent && !abl) {
         if (!masked) *long_rows = 0;
         int rc = run_rounds_persistent(ctx, g, seed, ws, gm, masked, phase, s, iters_out, launches,
                                        lanes);
         if (rc != kFallBack) return rc;
     }
-    const RoundsArgs a = round_args(ctx, g, seed, ws, gm, masked, degs, lanes);
+    RoundsArgs a = round_args(ctx, g, seed, ws, gm, masked, degs, lanes);
+    if (abl) {
+        a.colc = nullptr;
+        a.lenc = nullptr;
+        a.degs = nullptr;
+        a.dsplit = nullptr;
+        a.abl = abl->pflags;
+    }
     // compaction: unknown (-1) until round 1 reports what round 0 met
     int longs = masked ? (*long_rows > 0 ? 1 : 0) : -1;
     const int cfrom = masked ? 0 : kCompactFrom;
@@ -360,10 +375,17 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
                 if (!lc.e0 || !lc.e1 || !ld.e0 || !ld.e1)
                     return fail(ctx, MIS2_EHIP, "hipEventCreate failed");
             }
-            HIP_TRY(ctx, launch_col_round(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
-                                          a, round, mode, s, lc.e0, lc.e1));
-            HIP_TRY(ctx, launch_dec_round(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
-                                          a, round, s, ld.e0, ld.e1));
+            if (abl) {
+                HIP_TRY(ctx, launch_abl_round(0, abl->unpacked, abl->all, gm.blocks, g->row_ptr,
+                                              g->col, abl->T, abl->M, a, round, s, lc.e0, lc.e1));
+                HIP_TRY(ctx, launch_abl_round(1, abl->unpacked, abl->all, gm.blocks, g->row_ptr,
+                                              g->col, abl->T, abl->M, a, round, s, ld.e0, ld.e1));
+            } else {
+                HIP_TRY(ctx, launch_col_round(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
+                                              a, round, mode, s, lc.e0, lc.e1));
+                HIP_TRY(ctx, launch_dec_round(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
+                                              a, round, s, ld.e0, ld.e1));
+            }
             launches->push_back(lc);
             launches->push_back(ld);
             round++;
@@ -459,6 +481,17 @@ int collect_sweeps(mis2_ctx *ctx, const std::vector<Launch> &launches, const Wor
 }  // namespace
 
 namespace mis2 {
+
+// The ablation flags that take the ablation kernels (the others run the
+// production kernels).
+constexpr int kAblFamily = MIS2_ABL_FIXED_PRIORITY | MIS2_ABL_XORSHIFT | MIS2_ABL_NO_WORKLISTS |
+                           MIS2_ABL_UNPACKED | MIS2_ABL_SIMPLE;
+
+size_t ablation_bytes(int64_t n, int flags) {
+    size_t b = workspace_bytes(n, MIS2_OP_MIS2);
+    if (flags & MIS2_ABL_UNPACKED) b += 4 * align_up(4 * (size_t)std::max<int64_t>(n, 0));
+    return b;
+}
 
 size_t compact_bytes(int64_t n, int64_t nnz) {
     return align_up(4 * (size_t)std::max<int64_t>(nnz, 1)) + align_up(4 * (size_t)std::max<int64_t>(n, 0));
@@ -687,6 +720,81 @@ int mis2_run(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, uint8_t *status,
     int long_rows = 0;
     if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, &iters, &launches, &long_rows)))
         return rc;
+    HIP_TRY(ctx, launch_status(g->n, ws.T, status, ws.blocksum, ws.scalars + kS_Roots, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, ws.scalars + kS_Roots, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    iters = parse_trace(ctx, 0);
+    if (n_roots) *n_roots = ctx->pinned[0];
+    if (n_iters) *n_iters = iters;
+    return collect_sweeps(ctx, launches, ws, s);
+}
+
+int mis2_ablation_workspace_bytes(int64_t n, int flags, size_t *bytes) {
+    if (!bytes || n < 0 || (flags & ~MIS2_ABL_ALL_FLAGS)) return MIS2_EINVAL;
+    *bytes = ablation_bytes(n, flags);
+    return MIS2_OK;
+}
+
+int mis2_run_ablation(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int flags,
+                      uint8_t *status, int64_t *n_roots, int32_t *n_iters, void *stream) {
+    int rc = check_graph_args(ctx, g);
+    if (rc) return rc;
+    if (flags & ~MIS2_ABL_ALL_FLAGS) return fail(ctx, MIS2_EINVAL, "unknown ablation flags 0x%x", flags);
+    if (!(flags & kAblFamily)) {
+        // the production kernels, with one lane per row on request
+        const int keep_lanes = ctx->plan.lanes;
+        if (flags & MIS2_ABL_ONE_LANE) ctx->plan.lanes = 1;
+        rc = mis2_run(ctx, g, seed, status, n_roots, n_iters, stream);
+        ctx->plan.lanes = keep_lanes;
+        return rc;
+    }
+    if (g->n > 0 && !status) return fail(ctx, MIS2_EINVAL, "status is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    ctx->trace[0].clear();
+    ctx->trace[1].clear();
+    ctx->sweeps.clear();
+    if (g->n == 0) {
+        if (n_roots) *n_roots = 0;
+        if (n_iters) *n_iters = 0;
+        return MIS2_OK;
+    }
+    const size_t need = ablation_bytes(g->n, flags);
+    if (!ctx->ws || ctx->ws_bytes < need)
+        return fail(ctx, MIS2_ENOSPACE, "ablation workspace of %zu bytes needed, %zu set", need,
+                    ctx->ws ? ctx->ws_bytes : (size_t)0);
+    Workspace ws;
+    if (!carve(ctx->ws, ctx->ws_bytes, g->n, MIS2_OP_MIS2, &ws))
+        return fail(ctx, MIS2_ENOSPACE, "workspace carve failed");
+    if ((rc = maybe_validate(ctx, g, ws, s))) return rc;
+    AblRun abl;
+    abl.unpacked = (flags & MIS2_ABL_UNPACKED) != 0;
+    abl.all = (flags & MIS2_ABL_NO_WORKLISTS) != 0;
+    abl.pflags = ((flags & MIS2_ABL_FIXED_PRIORITY) ? kAblFixed : 0) |
+                 ((flags & MIS2_ABL_XORSHIFT) ? kAblXorshift : 0);
+    abl.T.s = ws.T;
+    abl.M.s = ws.M;
+    if (abl.unpacked) {
+        // three more arrays per tuple set, past the MIS-2 workspace
+        char *tail = (char *)ctx->ws + workspace_bytes(g->n, MIS2_OP_MIS2);
+        uint32_t *x[4];
+        for (int k = 0; k < 4; k++) x[k] = (uint32_t *)(tail + (size_t)k * align_up(4 * (size_t)g->n));
+        abl.T.p = x[0];
+        abl.T.i = x[1];
+        abl.M.p = x[2];
+        abl.M.i = x[3];
+    }
+    ctx->events_used = 0;
+    std::vector<Launch> launches;
+    const Geometry gm = geometry(ctx, g->n, 1);
+    RoundsArgs ia = round_args(ctx, g, seed, ws, gm, false, nullptr, 1);
+    ia.abl = abl.pflags;
+    HIP_TRY(ctx, launch_abl_init(abl.unpacked, abl.T, ia, s));
+    int32_t iters = 0;
+    int long_rows = 0;
+    if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, &iters, &launches, &long_rows, &abl)))
+        return rc;
+    // IN is 0 in the packed tuple and in the status field alike
     HIP_TRY(ctx, launch_status(g->n, ws.T, status, ws.blocksum, ws.scalars + kS_Roots, s));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, ws.scalars + kS_Roots, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));

@@ -217,6 +217,7 @@ struct RoundsArgs {
     int32_t *colc;   // [nnz] compacted rows, or null (no compaction)
     int32_t *lenc;   // [n] their lengths
     uint32_t *lflag; // [kSplit][kCtrLine] set by round 0 when a row is long (zero at the start)
+    int abl;         // ablation kernels only: kAblFixed | kAblXorshift
     int64_t n, seg, S;
     uint64_t seed, pmask;
     uint32_t b;
@@ -230,6 +231,18 @@ struct RoundsArgs {
 // rows.  A masked run starts with every absent vertex OUT and compacts from
 // round 0.
 constexpr int kCompactFrom = 2;
+// Priority choices of the ablation kernels (Section V-A, Table I).
+constexpr int kAblFixed = 1;     // priorities drawn once (Bell et al.)
+constexpr int kAblXorshift = 2;  // f = xorshift (xorshift*'s first stage)
+
+// Tuples of the ablation kernels: packed (s only, as T / M) or three
+// fields (status, priority, id) in three arrays.
+struct AblTuples {
+    uint32_t *s = nullptr;
+    uint32_t *p = nullptr;
+    uint32_t *i = nullptr;
+};
+
 // Bit of the host-reported |worklist1| word that says round 0 met rows long
 // enough for the cooperative pass (|worklist1| < 2^31 always).
 constexpr uint32_t kLongRowsBit = 0x80000000u;
@@ -240,6 +253,14 @@ hipError_t launch_rounds(int lanes, int blocks, const int64_t *row_ptr, const in
                          uint32_t *T, uint32_t *M, const RoundsArgs &a, hipStream_t s);
 // e0 / e1 (may be null): events stamped by the launch itself at the kernel's
 // start and end.
+// Ablation kernels (one lane per row): round 0's tuples, and the Refresh
+// Column (kind 0) / Decide Set (kind 1) of round r; e0 / e1 (may be null)
+// are recorded around the launch.
+hipError_t launch_abl_init(bool unpacked, const AblTuples &t, const RoundsArgs &a, hipStream_t s);
+hipError_t launch_abl_round(int kind, bool unpacked, bool all, int blocks,
+                            const int64_t *row_ptr, const int32_t *col, const AblTuples &T,
+                            const AblTuples &M, const RoundsArgs &a, int r, hipStream_t s,
+                            hipEvent_t e0, hipEvent_t e1);
 // mode: 0 plain, 1 write compacted rows from the CSR's, 2 read and rewrite
 // them (1 and 2 need lanes > 0 and a.colc / a.lenc).
 hipError_t launch_col_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,

@@ -940,11 +940,7 @@ __device__ __forceinline__ void round_sizes(const RoundsArgs &a, int r, uint32_t
 // reports (r, |worklist1|) to the host, with bit 31 of the low word set from
 // round 1 on when round 0 met rows long enough for the cooperative pass.
 // RD / WR: read / write the compacted rows.
-template <int L, bool RD, bool WR>
-__device__ __forceinline__ void col_round(const int64_t *__restrict__ row_ptr,
-                                          const int32_t *__restrict__ col,
-                                          const uint32_t *__restrict__ T, uint32_t *__restrict__ M,
-                                          const RoundsArgs &a, int r) {
+__device__ __forceinline__ void round_start(const RoundsArgs &a, int r) {
     if (blockIdx.x == 0 && threadIdx.x < 64) {
         uint32_t c1, c2;
         round_sizes(a, r, c1, c2);
@@ -960,6 +956,14 @@ __device__ __forceinline__ void col_round(const int64_t *__restrict__ row_ptr,
         }
     }
     clear_slot(a.ctr, r);
+}
+
+template <int L, bool RD, bool WR>
+__device__ __forceinline__ void col_round(const int64_t *__restrict__ row_ptr,
+                                          const int32_t *__restrict__ col,
+                                          const uint32_t *__restrict__ T, uint32_t *__restrict__ M,
+                                          const RoundsArgs &a, int r) {
+    round_start(a, r);
     SegIO io = round_col_io(a, r);
     if (RD) {
         io.ccol_in = a.colc;
@@ -1261,6 +1265,196 @@ int grid_for(int64_t work, int per_block, int cap) {
     return (int)b;
 }
 
+
+// ---------------------------------------------------------------------------
+// Ablation kernels (Section V, Fig. 2 and Table I): Algorithm 1 with the
+// optimizations of Section V taken away, one lane per CSR row and plain
+// loops over each row.
+//   UNPACKED: three-field tuples (status, priority, id) in three arrays
+//             (status 0 = IN, 1 = undecided, 2 = OUT; Section V-C's
+//             alternative) instead of one packed 32-bit word
+//   ALL:      every round sweeps every vertex (Bell et al.; no worklists);
+//             Decide Set leaves decided vertices as they are
+//   a.abl:    kAblFixed = priorities drawn once (round 0's hash in every
+//             round), kAblXorshift = f is xorshift*'s first stage (no
+//             multiplication) instead of xorshift*
+// The priority field holds the same low 32 - b bits of the hash as the
+// packed tuple, so the two forms order vertices alike.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t xs64(uint64_t x) {
+    x ^= x >> 12;
+    x ^= x << 25;
+    x ^= x >> 27;
+    return x;
+}
+
+__device__ __forceinline__ uint64_t abl_f(uint64_t x, int abl) {
+    return (abl & kAblXorshift) ? xs64(x) : xs64star(x);
+}
+
+// Priority bits of vertex v in round r.
+__device__ __forceinline__ uint32_t abl_prio(const RoundsArgs &a, int r, uint32_t v) {
+    const uint64_t it = (a.abl & kAblFixed) ? 0ull : (uint64_t)r;
+    const uint64_t h = abl_f(abl_f((a.seed << 32) ^ it, a.abl) ^ abl_f((uint64_t)v, a.abl), a.abl);
+    return (uint32_t)(h & a.pmask);
+}
+
+struct Tup3 {
+    uint32_t s, p, i;
+};
+constexpr uint32_t kSt3In = 0, kSt3Und = 1, kSt3Out = 2;
+
+template <bool UNPACKED>
+struct AblTuple;
+
+template <>
+struct AblTuple<false> {  // packed: (priority << b) | (id + 1), IN = 0, OUT = UINT_MAX
+    using T = uint32_t;
+    static __device__ __forceinline__ T load(const AblTuples &t, int64_t v) { return t.s[v]; }
+    static __device__ __forceinline__ void store(const AblTuples &t, int64_t v, T x) { t.s[v] = x; }
+    static __device__ __forceinline__ bool less(T x, T y) { return x < y; }
+    static __device__ __forceinline__ bool eq(T x, T y) { return x == y; }
+    static __device__ __forceinline__ bool is_in(T x) { return x == kIn; }
+    static __device__ __forceinline__ bool is_out(T x) { return x == kOut; }
+    static __device__ __forceinline__ T in() { return kIn; }
+    static __device__ __forceinline__ T out() { return kOut; }
+    static __device__ __forceinline__ T fresh(const RoundsArgs &a, int r, uint32_t v) {
+        return (uint32_t)(((uint64_t)abl_prio(a, r, v) << a.b) | (uint64_t)(v + 1u));
+    }
+};
+
+template <>
+struct AblTuple<true> {  // (status, priority, id) compared in that order
+    using T = Tup3;
+    static __device__ __forceinline__ T load(const AblTuples &t, int64_t v) {
+        return Tup3{t.s[v], t.p[v], t.i[v]};
+    }
+    static __device__ __forceinline__ void store(const AblTuples &t, int64_t v, T x) {
+        t.s[v] = x.s;
+        t.p[v] = x.p;
+        t.i[v] = x.i;
+    }
+    static __device__ __forceinline__ bool less(T x, T y) {
+        if (x.s != y.s) return x.s < y.s;
+        if (x.p != y.p) return x.p < y.p;
+        return x.i < y.i;
+    }
+    static __device__ __forceinline__ bool eq(T x, T y) {
+        return x.s == y.s && x.p == y.p && x.i == y.i;
+    }
+    static __device__ __forceinline__ bool is_in(T x) { return x.s == kSt3In; }
+    static __device__ __forceinline__ bool is_out(T x) { return x.s == kSt3Out; }
+    static __device__ __forceinline__ T in() { return Tup3{kSt3In, 0u, 0u}; }
+    static __device__ __forceinline__ T out() { return Tup3{kSt3Out, 0u, 0u}; }
+    static __device__ __forceinline__ T fresh(const RoundsArgs &a, int r, uint32_t v) {
+        return Tup3{kSt3Und, abl_prio(a, r, v), v};
+    }
+};
+
+// Round 0's tuples for every vertex.
+template <bool UNPACKED>
+__global__ __launch_bounds__(kBlock) void k_abl_init(AblTuples t, RoundsArgs a) {
+    using Tu = AblTuple<UNPACKED>;
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < a.n;
+         v += (int64_t)gridDim.x * kBlock)
+        Tu::store(t, v, Tu::fresh(a, 0, (uint32_t)v));
+}
+
+// Row v of the wavefront's rows i0 + lane (the identity range or the list
+// segment); count >= 1.
+__device__ __forceinline__ int32_t abl_row(const SegIO &io, const Seg &sg, int64_t i) {
+    const int64_t ic = i < sg.count ? i : sg.count - 1;
+    return io.wl_in ? io.wl_in[sg.base + ic] : (int32_t)(sg.base + ic);
+}
+
+// Longest row length over the wavefront: the loop over a row runs this many
+// steps in every lane (a wave-uniform trip count).
+__device__ __forceinline__ int64_t abl_wave_max(int64_t len) {
+    for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
+    return len;
+}
+
+template <bool UNPACKED, bool ALL>
+__global__ __launch_bounds__(kBlock) void k_abl_col(const int64_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ col, AblTuples T,
+                                                    AblTuples M, RoundsArgs a, int r) {
+    using Tu = AblTuple<UNPACKED>;
+    round_start(a, r);
+    SegIO io = round_col_io(a, r);
+    if (ALL) {
+        io.wl_in = nullptr;
+        io.cnt_in = nullptr;
+    }
+    const int64_t w = wave_id();
+    const Seg sg = seg_of(io, w);
+    const int lane = (int)(threadIdx.x & 63u);
+    uint32_t kept = 0;
+    for (int64_t i0 = 0; i0 < sg.count; i0 += 64) {
+        const int64_t i = i0 + lane;
+        const bool ok = i < sg.count;
+        const int32_t v = abl_row(io, sg, i);
+        const int64_t s = row_ptr[v], e = ok ? row_ptr[v + 1] : s;
+        typename Tu::T m = Tu::load(T, v);
+        const int64_t steps = abl_wave_max(e - s);
+        for (int64_t c = 0; c < steps; c++) {
+            const int64_t j = s + c;
+            const typename Tu::T t = Tu::load(T, col[j < e ? j : 0]);
+            if (j < e && Tu::less(t, m)) m = t;
+        }
+        if (Tu::is_in(m)) m = Tu::out();
+        if (ok) Tu::store(M, v, m);
+        seg_append(io, sg, ok && !Tu::is_out(m), v, kept);
+    }
+    seg_finish(io, w, kept);
+}
+
+template <bool UNPACKED, bool ALL>
+__global__ __launch_bounds__(kBlock) void k_abl_dec(const int64_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ col, AblTuples T,
+                                                    AblTuples M, RoundsArgs a, int r) {
+    using Tu = AblTuple<UNPACKED>;
+    SegIO io = round_dec_io(a, r);
+    if (ALL) {
+        io.wl_in = nullptr;
+        io.cnt_in = nullptr;
+    }
+    const int64_t w = wave_id();
+    const Seg sg = seg_of(io, w);
+    const int lane = (int)(threadIdx.x & 63u);
+    uint32_t kept = 0;
+    for (int64_t i0 = 0; i0 < sg.count; i0 += 64) {
+        const int64_t i = i0 + lane;
+        const int32_t v = abl_row(io, sg, i);
+        const typename Tu::T t0 = Tu::load(T, v);
+        const bool act = i < sg.count && !(ALL && (Tu::is_in(t0) || Tu::is_out(t0)));
+        const typename Tu::T mv = Tu::load(M, v);
+        bool any_out = Tu::is_out(mv), all_eq = Tu::eq(mv, t0);
+        const int64_t s = row_ptr[v], e = act ? row_ptr[v + 1] : s;
+        const int64_t steps = abl_wave_max(e - s);
+        for (int64_t c = 0; c < steps; c++) {
+            const int64_t j = s + c;
+            const typename Tu::T mw = Tu::load(M, col[j < e ? j : 0]);
+            if (j < e) {
+                any_out |= Tu::is_out(mw);
+                all_eq &= Tu::eq(mw, t0);
+            }
+        }
+        bool keep = false;
+        if (act) {
+            if (any_out) {
+                Tu::store(T, v, Tu::out());
+            } else if (all_eq) {
+                Tu::store(T, v, Tu::in());
+            } else {
+                Tu::store(T, v, Tu::fresh(a, r + 1, (uint32_t)v));
+                keep = true;
+            }
+        }
+        seg_append(io, sg, keep, v, kept);
+    }
+    seg_finish(io, w, kept);
+}
+
 }  // namespace
 
 int id_bits(int64_t n) {
@@ -1444,6 +1638,48 @@ hipError_t launch_validate(int64_t n, int64_t nnz, const int64_t *row_ptr, const
     hipLaunchKernelGGL(k_validate, dim3(grid_for(n > 0 ? n : 1, kBlock, 4096)), dim3(kBlock), 0,
                        s, n, nnz, row_ptr, col, err);
     return hipGetLastError();
+}
+
+
+hipError_t launch_abl_init(bool unpacked, const AblTuples &t, const RoundsArgs &a,
+                           hipStream_t s) {
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((a.n + kBlock - 1) / kBlock, 8192));
+    if (unpacked)
+        hipLaunchKernelGGL(k_abl_init<true>, dim3(grid), dim3(kBlock), 0, s, t, a);
+    else
+        hipLaunchKernelGGL(k_abl_init<false>, dim3(grid), dim3(kBlock), 0, s, t, a);
+    return hipGetLastError();
+}
+
+template <bool U, bool A>
+void abl_round_t(int kind, int blocks, const int64_t *row_ptr, const int32_t *col,
+                 const AblTuples &T, const AblTuples &M, const RoundsArgs &a, int r,
+                 hipStream_t s) {
+    if (kind == 0)
+        k_abl_col<U, A><<<dim3(blocks), dim3(kBlock), 0, s>>>(row_ptr, col, T, M, a, r);
+    else
+        k_abl_dec<U, A><<<dim3(blocks), dim3(kBlock), 0, s>>>(row_ptr, col, T, M, a, r);
+}
+
+hipError_t launch_abl_round(int kind, bool unpacked, bool all, int blocks,
+                            const int64_t *row_ptr, const int32_t *col, const AblTuples &T,
+                            const AblTuples &M, const RoundsArgs &a, int r, hipStream_t s,
+                            hipEvent_t e0, hipEvent_t e1) {
+    if (e0) {
+        const hipError_t er = hipEventRecord(e0, s);
+        if (er != hipSuccess) return er;
+    }
+    if (unpacked) {
+        if (all) abl_round_t<true, true>(kind, blocks, row_ptr, col, T, M, a, r, s);
+        else abl_round_t<true, false>(kind, blocks, row_ptr, col, T, M, a, r, s);
+    } else {
+        if (all) abl_round_t<false, true>(kind, blocks, row_ptr, col, T, M, a, r, s);
+        else abl_round_t<false, false>(kind, blocks, row_ptr, col, T, M, a, r, s);
+    }
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    if (e1) return hipEventRecord(e1, s);
+    return hipSuccess;
 }
 
 }  // namespace mis2
