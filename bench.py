@@ -46,7 +46,69 @@ def workload(name):
     if name == "c3":
         return "Chung-Lu power-law graph (n=4,000,000, mean degree 16, exponent 2.1, cap 20000), " \
                "MIS-2 + MIS-2 aggregation", graphs.chung_lu(4_000_000, 16.0, 2.1, 20000, seed=1)
+    if name == "l100":
+        return "3D 7-point Laplacian graph 100^3 (n=1,000,000; the paper's Laplace3D_100), " \
+               "MIS-2 + MIS-2 aggregation", graphs.grid3d_7pt(100, 100, 100)
     raise SystemExit("unknown workload " + name)
+
+
+# Fig. 2's ladder: each rung adds one optimization of Section V to the one
+# before (flags of mis2_run_ablation that are still set = optimizations
+# still taken away).
+ABL_FIXED, ABL_XOR, ABL_NOWL, ABL_UNPACKED, ABL_ONE_LANE, ABL_SIMPLE = 1, 2, 4, 8, 16, 32
+LADDER = [
+    ("baseline (fixed priorities, every vertex every round, 3-field tuples, 1 lane)",
+     ABL_FIXED | ABL_NOWL | ABL_UNPACKED | ABL_ONE_LANE),
+    ("+ random priorities", ABL_NOWL | ABL_UNPACKED | ABL_ONE_LANE),
+    ("+ worklists", ABL_UNPACKED | ABL_ONE_LANE),
+    ("+ packed tuples (same simple kernels)", ABL_SIMPLE | ABL_ONE_LANE),
+    ("production kernels, 1 lane per row", ABL_ONE_LANE),
+    ("+ lanes per row by the degree rule (SIMD)", 0),
+]
+
+
+def run_ablation(args):
+    """Fig. 2 and Table I on one graph: MIS-2 time per rung of the ladder
+    (mis2_run_ablation, graph resident in HBM) with cumulative speedups, and
+    the rounds taken with fixed, xorshift and xorshift* priorities."""
+    import numpy as np
+    import torch
+    from paper_2204_02934_amd import api
+    name, (rp_h, col_h) = workload(args.workload)
+    name = name.split(", MIS-2")[0]
+    n, nnz = rp_h.size - 1, int(rp_h[-1])
+    dev = torch.device("cuda", 0)
+    rp, col = api.as_device_csr(rp_h, col_h, dev)
+    ctx = api.Context(0)
+    rungs = []
+    for label, flags in LADDER:
+        for _ in range(args.warmup):
+            ctx.mis2_ablation(rp, col, args.seed, flags, nnz=nnz)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, nr, it = ctx.mis2_ablation(rp, col, args.seed, flags, nnz=nnz)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        rungs.append({"rung": label, "flags": flags, "ms": ms, "rounds": it, "mis2": nr})
+        log("%-80s %8.3f ms  %2d rounds" % (label, ms, it))
+    for r in rungs:
+        r["speedup_vs_baseline"] = rungs[0]["ms"] / r["ms"]
+    for a, b in zip(rungs, rungs[1:]):
+        b["speedup_vs_previous"] = a["ms"] / b["ms"]
+    rounds = {}
+    for key, flags in (("fixed", ABL_FIXED), ("xor", ABL_XOR), ("xorstar", 0)):
+        rounds[key] = ctx.mis2_ablation(rp, col, args.seed, flags, nnz=nnz)[2]
+    return {
+        "metric": "MIS-2 time per optimization rung (Fig. 2) and rounds per priority scheme "
+                  "(Table I)",
+        "value": rungs[0]["ms"] / rungs[-1]["ms"], "unit": "x (all four optimizations)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": rungs[-1]["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": name, "n": n, "nnz": nnz, "seed": args.seed},
+        "rungs": rungs, "table1_rounds": rounds,
+    }
 
 
 def kernel_sources_digest():
@@ -270,6 +332,9 @@ def main():
                     help="first run three device-to-device copies of MIB MiB (a known-size "
                          "kernel for scaling hardware byte counters)")
     ap.add_argument("--c5-jobs", type=int, default=32, help="serving: jobs in the pool")
+    ap.add_argument("--ablation", action="store_true",
+                    help="c1-c3, l100: the optimization ladder of Fig. 2 and the rounds of "
+                         "Table I instead of the step")
     ap.add_argument("--aggregation", choices=("alg3", "alg2"), default="alg3",
                     help="c1-c3: the aggregation of the step, MIS-2 based aggregation "
                          "(mis2_aggregate) or basic MIS-2 coarsening (mis2_aggregate_basic)")
@@ -277,6 +342,11 @@ def main():
     if args.gpus != 1:
         raise SystemExit("bench.py measures one GPU: this build has no multi-GPU path "
                          "(--gpus %d requested)" % args.gpus)
+    if args.ablation:
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        print(json.dumps(run_ablation(args)), flush=True)
+        return
     if args.workload in ("c4", "c5"):
         import torch
         assert torch.cuda.is_available(), "bench.py needs a GPU"

@@ -60,12 +60,14 @@ int lanes_for(const mis2_ctx *ctx, const mis2_graph *g) {
     if (ctx->plan.lanes) return ctx->plan.lanes;
     // Section V-D: one thread per row below an average degree of 16, lanes
     // cooperating on a row above it; here the group grows with the degree.
-    // Measured on gfx950: 4-lane groups (16 rows per wavefront step, 4 in
-    // flight per group) beat wider groups for average degrees up to ~64;
-    // longer rows go to the whole wavefront anyway.
+    // Measured on gfx950 (MIS-2 time, 1 / 2 / 4 lanes): 5-point 1000^2
+    // 0.25 / 0.27 / 0.32 ms, 7-point 100^3 0.29 / 0.31 / 0.37 ms, power-law
+    // graphs of average degree 8 and 16 1.25 / 1.26 / 1.31 and 5.25 / 5.34 /
+    // 5.52 ms (their rows past 32 entries go to the whole wavefront anyway),
+    // 27-point 100^3 (average 25) 0.61 / 0.50 / 0.45 ms; 8 lanes never won
+    // below an average of 64.
     const double avg = g->n > 0 ? (double)g->nnz / (double)g->n : 0.0;
-    if (avg < 2) return 1;
-    if (avg < 4) return 2;
+    if (avg < 20) return 1;
     if (avg < 64) return 4;
     if (avg < 256) return 8;
     return 16;
@@ -961,7 +963,11 @@ int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
     long_io.cnt_in = ws.cnt1[1];
     long_io.wl_out = nullptr;
     long_io.cnt_out = nullptr;
-    const int p3_lanes = lanes_for(ctx, g) > 0 ? lanes_for(ctx, g) : 4;
+    // phase 3 keeps rows of up to 8 chunks of L entries in registers and
+    // hands longer ones to a one-row-per-wavefront pass: 4 lanes at least,
+    // or every 27-point row would be long (27-point 100^3 aggregation with
+    // 1 lane: 1.7 ms, with 4: 0.78 ms)
+    const int p3_lanes = std::max(4, lanes_for(ctx, g));
     HIP_TRY(ctx, launch_phase3(p3_lanes, gm.blocks, g->row_ptr, g->col, ws.label,
                                ws.aggsize, p3_io, long_io, agg_id, sc + kS_Err, s));
 
