@@ -18,5 +18,8 @@ from .oracle import (  # noqa: F401
     aggregate,
     aggregate_basic,
     quotient,
+    color_jp,
+    cgs_plan,
+    cgs_apply,
     coarsen,
 )

@@ -577,3 +577,184 @@ int64_t oracle_quotient(int64_t n, const int64_t *row_ptr, const int32_t *col,
     free(p);
     return m;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Algorithm 4 (Section III-C): cluster multicolor Gauss-Seidel.              */
+/*                                                                           */
+/* Setup: coarsen the graph (Algorithm 3), take each row's aggregate as its  */
+/* cluster, colour the coarse graph, and order the rows by colour, then by   */
+/* cluster, then by row: clusters of one colour share no edge, so updating   */
+/* them in parallel is the same as updating them one after the other.       */
+/* Apply: for each colour in turn, each of its clusters updates its rows in  */
+/* order with the Gauss-Seidel step.                                         */
+/*                                                                           */
+/* Reading (colouring): the paper takes the colouring from other work.  Here  */
+/* it is Jones-Plassmann with fixed priorities, the packed tuple of          */
+/* h(seed, 0, v) (Sections V-A, V-C): each round every uncoloured vertex     */
+/* whose tuple is below those of all its uncoloured neighbours takes the     */
+/* smallest colour no coloured neighbour has.                                */
+/* Reading (update): the listing writes x_i <- r / A_ii with                 */
+/* r = b_i - A_i x; the Gauss-Seidel step it describes is                    */
+/* x_i <- (b_i - sum over j != i of A_ij x_j) / A_ii, summed in CSR order.   */
+/* Reading (order): rows of a cluster in increasing id; clusters of a colour */
+/* in increasing id; the symmetric sweep runs the reverse order afterwards   */
+/* (colours backward, rows of each cluster backward).                        */
+/* ------------------------------------------------------------------------- */
+
+/* Jones-Plassmann colouring.  color[n] out (0-based), *n_colors out.
+ * Returns 0, -1 on bad arguments. */
+int oracle_color_jp(int64_t n, const int64_t *row_ptr, const int32_t *col, uint64_t seed,
+                    int32_t *color, int32_t *n_colors, int32_t *rounds)
+{
+    if (n < 0 || !n_colors || (n > 0 && (!row_ptr || !color)))
+        return -1;
+    *n_colors = 0;
+    if (rounds) *rounds = 0;
+    if (n == 0) return 0;
+    int b = oracle_id_bits(n);
+    if (b > 32) return -1;
+    uint32_t *pr = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+    int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    uint8_t *used = (uint8_t *)calloc((size_t)n + 1, 1);
+    if (!pr || !next || !used) { free(pr); free(next); free(used); return -1; }
+    for (int64_t v = 0; v < n; v++) {
+        pr[v] = oracle_pack(oracle_hash(seed, 0, (uint64_t)v), v, b);
+        color[v] = -1;
+    }
+    int64_t left = n;
+    int32_t r = 0, nc = 0;
+    while (left > 0) {
+        /* decisions of this round read the colours of the round start */
+        for (int64_t v = 0; v < n; v++) {
+            next[v] = color[v];
+            if (color[v] != -1) continue;
+            int local_min = 1;
+            for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+                int64_t w = col[e];
+                if (color[w] == -1 && pr[w] < pr[v]) local_min = 0;
+            }
+            if (!local_min) continue;
+            for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++)
+                if (color[col[e]] >= 0) used[color[col[e]]] = 1;
+            int32_t c = 0;
+            while (used[c]) c++;
+            next[v] = c;
+            if (c + 1 > nc) nc = c + 1;
+            for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++)
+                if (color[col[e]] >= 0) used[color[col[e]]] = 0;
+        }
+        for (int64_t v = 0; v < n; v++) {
+            if (color[v] == -1 && next[v] != -1) left--;
+            color[v] = next[v];
+        }
+        r++;
+    }
+    *n_colors = nc;
+    if (rounds) *rounds = r;
+    free(pr); free(next); free(used);
+    return 0;
+}
+
+/* The sweep order of Algorithm 4.  point = 0: clusters are the aggregates of
+ * Algorithm 3 and the coarse (quotient) graph is coloured; point = 1: every
+ * row is its own cluster and the graph itself is coloured (point multicolor
+ * Gauss-Seidel).
+ *   cluster[n]        out: cluster of each row
+ *   cluster_color[n]  out: colour of each cluster (first *n_clusters)
+ *   rows[n]           out: rows in sweep order
+ *   cluster_off[n+1]  out: the k-th cluster of the sweep order holds
+ *                     rows[cluster_off[k] .. cluster_off[k+1])
+ *   color_off[n+1]    out: colour c holds the sweep-order clusters
+ *                     [color_off[c], color_off[c+1])
+ * Returns 0, -1 on bad arguments, -5 if a step fails. */
+int oracle_cgs_plan(int64_t n, const int64_t *row_ptr, const int32_t *col, uint64_t seed,
+                    int point, int32_t *cluster, int32_t *cluster_color, int32_t *rows,
+                    int64_t *cluster_off, int64_t *color_off, int64_t *n_clusters,
+                    int32_t *n_colors)
+{
+    if (n < 0 || !n_clusters || !n_colors ||
+        (n > 0 && (!row_ptr || !cluster || !cluster_color || !rows || !cluster_off || !color_off)))
+        return -1;
+    *n_clusters = 0;
+    *n_colors = 0;
+    if (n == 0) { if (cluster_off) cluster_off[0] = 0; if (color_off) color_off[0] = 0; return 0; }
+    int rc = 0;
+    int64_t nc = 0;
+    int64_t *crow = NULL;
+    int32_t *ccol = NULL;
+    int64_t *size = NULL, *start = NULL;
+    int64_t nnz = row_ptr[n];
+    if (point) {
+        for (int64_t v = 0; v < n; v++) cluster[v] = (int32_t)v;
+        nc = n;
+        rc = oracle_color_jp(n, row_ptr, col, seed, cluster_color, n_colors, NULL);
+        if (rc) goto done;
+    } else {
+        rc = oracle_aggregate(n, row_ptr, col, seed, cluster, &nc);
+        if (rc) goto done;
+        crow = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nc + 1));
+        ccol = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+        if (!crow || !ccol) { rc = -1; goto done; }
+        if (oracle_quotient(n, row_ptr, col, cluster, nc, crow, ccol, nnz) < 0) { rc = -5; goto done; }
+        rc = oracle_color_jp(nc, crow, ccol, seed, cluster_color, n_colors, NULL);
+        if (rc) goto done;
+    }
+    *n_clusters = nc;
+    /* clusters by colour, then id; rows of a cluster by id */
+    size = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
+    start = (int64_t *)malloc(sizeof(int64_t) * (size_t)nc);
+    if (!size || !start) { rc = -1; goto done; }
+    for (int64_t v = 0; v < n; v++) size[cluster[v]]++;
+    int64_t k = 0, pos = 0;
+    color_off[0] = 0;
+    for (int32_t c = 0; c < *n_colors; c++) {
+        for (int64_t a = 0; a < nc; a++) {
+            if (cluster_color[a] != c) continue;
+            cluster_off[k] = pos;
+            start[a] = pos;
+            pos += size[a];
+            k++;
+        }
+        color_off[c + 1] = k;
+    }
+    cluster_off[k] = pos;
+    for (int64_t v = 0; v < n; v++) rows[start[cluster[v]]++] = (int32_t)v;
+done:
+    free(crow); free(ccol); free(size); free(start);
+    return rc;
+}
+
+/* Gauss-Seidel step of row i (see the reading above).  val[nnz] are the
+ * off-diagonal entries in CSR order, diag[n] the diagonal. */
+static void oracle_gs_row(int64_t i, const int64_t *row_ptr, const int32_t *col,
+                          const double *val, const double *diag, const double *b, double *x)
+{
+    double r = b[i];
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++)
+        r -= val[e] * x[col[e]];
+    x[i] = r / diag[i];
+}
+
+/* sweeps applications of Algorithm 4 to x (in place), forward only or,
+ * with symmetric, forward then backward.  The plan is oracle_cgs_plan's. */
+int oracle_cgs_apply(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                     const double *diag, const int32_t *rows, const int64_t *cluster_off,
+                     const int64_t *color_off, int32_t n_colors, const double *b, double *x,
+                     int32_t sweeps, int symmetric)
+{
+    if (n < 0 || sweeps < 0 || (n > 0 && (!row_ptr || !diag || !rows || !cluster_off ||
+                                          !color_off || !b || !x)))
+        return -1;
+    for (int32_t s = 0; s < sweeps; s++) {
+        for (int32_t c = 0; c < n_colors; c++)
+            for (int64_t k = color_off[c]; k < color_off[c + 1]; k++)
+                for (int64_t t = cluster_off[k]; t < cluster_off[k + 1]; t++)
+                    oracle_gs_row(rows[t], row_ptr, col, val, diag, b, x);
+        if (!symmetric) continue;
+        for (int32_t c = n_colors - 1; c >= 0; c--)
+            for (int64_t k = color_off[c + 1] - 1; k >= color_off[c]; k--)
+                for (int64_t t = cluster_off[k + 1] - 1; t >= cluster_off[k]; t--)
+                    oracle_gs_row(rows[t], row_ptr, col, val, diag, b, x);
+    }
+    return 0;
+}

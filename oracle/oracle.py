@@ -31,7 +31,7 @@ def build_oracle(force=True):
     if not force and os.path.exists(_LIB):
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC",
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-Wall", "-Wextra", "-fPIC",
                            "-shared", _SRC, "-o", tmp])
     os.replace(tmp, _LIB)
     _lib = None
@@ -66,6 +66,18 @@ def _get():
         lib.oracle_mis2_ablation.argtypes = [
             ctypes.c_int64, _i64p, _i32p, ctypes.c_uint64, ctypes.c_int, _u8p, _i32p, _i64p,
             ctypes.c_int32]
+        _f64p = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_color_jp.restype = ctypes.c_int
+        lib.oracle_color_jp.argtypes = [ctypes.c_int64, _i64p, _i32p, ctypes.c_uint64, _i32p,
+                                        _i32p, _i32p]
+        lib.oracle_cgs_plan.restype = ctypes.c_int
+        lib.oracle_cgs_plan.argtypes = [ctypes.c_int64, _i64p, _i32p, ctypes.c_uint64,
+                                        ctypes.c_int, _i32p, _i32p, _i32p, _i64p, _i64p, _i64p,
+                                        _i32p]
+        lib.oracle_cgs_apply.restype = ctypes.c_int
+        lib.oracle_cgs_apply.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, _i32p,
+                                         _i64p, _i64p, ctypes.c_int32, _f64p, _f64p,
+                                         ctypes.c_int32, ctypes.c_int]
         lib.oracle_aggregate_basic.restype = ctypes.c_int
         lib.oracle_aggregate_basic.argtypes = [
             ctypes.c_int64, _i64p, _i32p, ctypes.c_uint64, _i32p, _i64p, _u8p, _i64p]
@@ -223,6 +235,68 @@ def aggregate_basic(row_ptr, col, seed=0, detail=False):
         return agg[:n], int(nagg.value)
     return {"agg": agg[:n], "n_agg": int(nagg.value), "roots": roots[:n],
             "joined": int(joined.value)}
+
+
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+def color_jp(row_ptr, col, seed=0):
+    """Jones-Plassmann colouring with fixed hash priorities (the reading of
+    Algorithm 4's colouring): returns (color int32[n], n_colors, rounds)."""
+    row_ptr, col = _csr(row_ptr, col)
+    n = row_ptr.size - 1
+    color = np.zeros(max(n, 1), np.int32)
+    nc, r = ctypes.c_int32(0), ctypes.c_int32(0)
+    rc = _get().oracle_color_jp(n, _ptr(row_ptr, _i64p), _ptr(col, _i32p), seed,
+                                _ptr(color, _i32p), ctypes.byref(nc), ctypes.byref(r))
+    if rc:
+        raise OracleError("oracle_color_jp returned %d" % rc)
+    return color[:n], nc.value, r.value
+
+
+def cgs_plan(row_ptr, col, seed=0, point=False):
+    """Algorithm 4's setup: dict with cluster (int32[n]), cluster_color,
+    rows (sweep order), cluster_off, color_off, n_clusters, n_colors."""
+    row_ptr, col = _csr(row_ptr, col)
+    n = row_ptr.size - 1
+    cl = np.zeros(max(n, 1), np.int32)
+    cc = np.zeros(max(n, 1), np.int32)
+    rows = np.zeros(max(n, 1), np.int32)
+    coff = np.zeros(n + 1, np.int64)
+    koff = np.zeros(n + 1, np.int64)
+    ncl, nco = ctypes.c_int64(0), ctypes.c_int32(0)
+    rc = _get().oracle_cgs_plan(n, _ptr(row_ptr, _i64p), _ptr(col, _i32p), seed, int(point),
+                                _ptr(cl, _i32p), _ptr(cc, _i32p), _ptr(rows, _i32p),
+                                _ptr(coff, _i64p), _ptr(koff, _i64p), ctypes.byref(ncl),
+                                ctypes.byref(nco))
+    if rc:
+        raise OracleError("oracle_cgs_plan returned %d" % rc)
+    k, c = ncl.value, nco.value
+    return {"cluster": cl[:n], "cluster_color": cc[:k], "rows": rows[:n],
+            "cluster_off": coff[:k + 1], "color_off": koff[:c + 1], "n_clusters": k,
+            "n_colors": c}
+
+
+def cgs_apply(row_ptr, col, val, diag, plan, b, x0, sweeps=1, symmetric=False):
+    """sweeps applications of Algorithm 4 to a copy of x0 (float64)."""
+    row_ptr, col = _csr(row_ptr, col)
+    n = row_ptr.size - 1
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    diag = np.ascontiguousarray(diag, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.array(x0, dtype=np.float64, copy=True)
+    rows = np.ascontiguousarray(plan["rows"], dtype=np.int32)
+    coff = np.ascontiguousarray(plan["cluster_off"], dtype=np.int64)
+    koff = np.ascontiguousarray(plan["color_off"], dtype=np.int64)
+    if val.size == 0:
+        val = np.zeros(1)
+    rc = _get().oracle_cgs_apply(n, _ptr(row_ptr, _i64p), _ptr(col, _i32p), _ptr(val, _f64p),
+                                 _ptr(diag, _f64p), _ptr(rows, _i32p), _ptr(coff, _i64p),
+                                 _ptr(koff, _i64p), plan["n_colors"], _ptr(b, _f64p),
+                                 _ptr(x, _f64p), sweeps, int(symmetric))
+    if rc:
+        raise OracleError("oracle_cgs_apply returned %d" % rc)
+    return x
 
 
 def quotient(row_ptr, col, agg, n_agg):

@@ -236,3 +236,24 @@ def disjoint_union(graphs):
         off_v += n
         off_e += int(rp[-1])
     return np.concatenate(rps), (np.concatenate(cols) if cols else np.zeros(0)).astype(np.int32)
+
+
+def matrix_values(row_ptr, col, seed=0, shift=0.1):
+    """Seeded values for a CSR pattern, to make a symmetric, strictly
+    diagonally dominant M-matrix (the kind of system the Gauss-Seidel of
+    Algorithm 4 is run on): off-diagonal entry (i, j) = -w with w uniform in
+    [0.5, 1.5) drawn from the unordered pair {i, j}, and diagonal entry i =
+    shift + the sum of its row's w.  Returns (val float64[nnz], diag
+    float64[n])."""
+    n = row_ptr.size - 1
+    r = np.repeat(np.arange(n, dtype=np.uint64), np.diff(row_ptr).astype(np.int64))
+    c = col.astype(np.uint64)
+    lo, hi = np.minimum(r, c), np.maximum(r, c)
+    with np.errstate(over="ignore"):
+        z = lo * np.uint64(0x9E3779B97F4A7C15) ^ hi ^ (np.uint64(seed) << np.uint64(32))
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z ^= z >> np.uint64(31)
+    w = 0.5 + (z >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+    diag = shift + np.bincount(r.astype(np.int64), weights=w, minlength=n)
+    return -w, diag
