@@ -163,6 +163,52 @@ int mis2_run_ablation(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int fla
 /* Bytes of device workspace mis2_run_ablation needs (written to *bytes, host). */
 int mis2_ablation_workspace_bytes(int64_t n, int flags, size_t *bytes);
 
+/*
+ * Cluster multicolor Gauss-Seidel (Algorithm 4, Section III-C).
+ *
+ * Setup coarsens the graph with mis2_aggregate (each row's aggregate is its
+ * cluster; point != 0: every row is its own cluster, "point multicolor
+ * Gauss-Seidel"), colours the coarse (quotient) graph -- the paper leaves
+ * the colouring to other work; here Jones-Plassmann with the fixed priorities
+ * of h(seed, 0, v) packed as in Section V-C: each round every uncoloured
+ * vertex below all its uncoloured neighbours takes the smallest colour no
+ * coloured neighbour has -- and orders the rows by colour, then cluster id,
+ * then row id.  Apply runs that order: colour by colour, clusters of one
+ * colour in parallel (they share no edge), the rows of a cluster one after
+ * the other, each with x_i = (b_i - sum over j != i of A_ij x_j) / A_ii in
+ * CSR order (no fused multiply-add); the symmetric form runs the order
+ * forward, then backward.
+ */
+typedef struct mis2_cgs_plan {
+    int64_t n;              /* rows (set by the caller) */
+    int64_t n_clusters;     /* out */
+    int32_t n_colors;       /* out */
+    int32_t *cluster;       /* device out, int32[n]: cluster of each row */
+    int32_t *cluster_color; /* device out, int32[n]: colour of cluster a at [a] (a < n_clusters) */
+    int32_t *rows;          /* device out, int32[n]: rows in sweep order */
+    int64_t *cluster_off;   /* device out, int64[n + 1]: the k-th cluster of the sweep order holds
+                               rows[cluster_off[k] .. cluster_off[k+1]) */
+    int64_t *color_off;     /* host out, int64[n + 1]: colour c holds the sweep-order clusters
+                               [color_off[c], color_off[c+1]) */
+} mis2_cgs_plan;
+
+/* Bytes of device workspace mis2_cgs_setup needs (written to *bytes, host). */
+int mis2_cgs_workspace_bytes(int64_t n, int64_t nnz, size_t *bytes);
+
+/* Fill a plan for graph g (the caller allocates its arrays, sizes above).
+ * Synchronises the stream (the colouring reads a count back each round). */
+int mis2_cgs_setup(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int point,
+                   mis2_cgs_plan *plan, void *stream);
+
+/* sweeps applications of the plan to x (device, double[n], in place) for the
+ * matrix with off-diagonal entries val (device, double[nnz], in g's CSR order)
+ * and diagonal diag (device, double[n]); b: device, double[n].  symmetric != 0:
+ * each sweep runs forward and then backward.  Enqueues the launches and
+ * returns (no synchronisation); needs no workspace. */
+int mis2_cgs_apply(mis2_ctx *ctx, const mis2_graph *g, const double *val, const double *diag,
+                   const mis2_cgs_plan *plan, const double *b, double *x, int32_t sweeps,
+                   int symmetric, void *stream);
+
 /* Per-round worklist sizes of the last mis2_run (or of the two MIS-2 runs
  * of the last mis2_aggregate, phase 1 then phase 2): host out
  * sizes[r*2 + 0] = |worklist1|, sizes[r*2 + 1] = |worklist2| at the start of

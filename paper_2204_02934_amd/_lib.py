@@ -38,7 +38,8 @@ EXPORTS = (
     "mis2_create", "mis2_destroy", "mis2_last_error", "mis2_set_option",
     "mis2_workspace_bytes", "mis2_workspace_bytes_csr", "mis2_set_workspace", "mis2_run",
     "mis2_last_trace", "mis2_aggregate", "mis2_aggregate_basic", "mis2_last_sweeps",
-    "mis2_run_ablation", "mis2_ablation_workspace_bytes",
+    "mis2_run_ablation", "mis2_ablation_workspace_bytes", "mis2_cgs_workspace_bytes",
+    "mis2_cgs_setup", "mis2_cgs_apply",
     "mis2_quotient", "mis2_coarsen_workspace_bytes",
     "mis2_coarsen", "mis2_batch_workspace_bytes", "mis2_aggregate_batched",
     "mis2_server_bytes", "mis2_server_create", "mis2_server_destroy", "mis2_server_last_error",
@@ -51,6 +52,13 @@ MIS2_SERVE_MAX_LEVELS = 32
 class Mis2Graph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+
+
+class Mis2CgsPlan(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_clusters", ctypes.c_int64),
+                ("n_colors", ctypes.c_int32), ("cluster", ctypes.c_void_p),
+                ("cluster_color", ctypes.c_void_p), ("rows", ctypes.c_void_p),
+                ("cluster_off", ctypes.c_void_p), ("color_off", ctypes.POINTER(ctypes.c_int64))]
 
 
 class Mis2SweepRecord(ctypes.Structure):
@@ -102,6 +110,11 @@ def load():
                                            ctypes.POINTER(i32)]),
         "mis2_aggregate": (ctypes.c_int, [vp, gp, u64, vp, ctypes.POINTER(i64), vp, vp]),
         "mis2_aggregate_basic": (ctypes.c_int, [vp, gp, u64, vp, ctypes.POINTER(i64), vp, vp]),
+        "mis2_cgs_workspace_bytes": (ctypes.c_int, [i64, i64, ctypes.POINTER(ctypes.c_size_t)]),
+        "mis2_cgs_setup": (ctypes.c_int, [vp, gp, u64, ctypes.c_int, ctypes.POINTER(Mis2CgsPlan),
+                                          vp]),
+        "mis2_cgs_apply": (ctypes.c_int, [vp, gp, vp, vp, ctypes.POINTER(Mis2CgsPlan), vp, vp,
+                                          i32, ctypes.c_int, vp]),
         "mis2_run_ablation": (ctypes.c_int, [vp, gp, u64, ctypes.c_int, vp, ctypes.POINTER(i64),
                                              ctypes.POINTER(i32), vp]),
         "mis2_ablation_workspace_bytes": (ctypes.c_int, [i64, ctypes.c_int,

@@ -123,6 +123,39 @@ class Context:
             return agg[:g.n], na.value, roots[:g.n]
         return agg[:g.n], na.value
 
+    def cgs_setup(self, row_ptr, col, seed=0, point=False, stream=None, nnz=None):
+        """Algorithm 4's setup (mis2_cgs_setup): returns a CgsPlan holding the
+        device arrays cluster, cluster_color, rows, cluster_off and the host
+        colour offsets."""
+        g, keep = self.graph(row_ptr, col, nnz)
+        b = ctypes.c_size_t(0)
+        _check(self.lib, self.ptr, self.lib.mis2_cgs_workspace_bytes(g.n, g.nnz, ctypes.byref(b)))
+        self._ensure_bytes(b.value)
+        n = g.n
+        dev = self.device
+        plan = CgsPlan(n, dev)
+        rc = self.lib.mis2_cgs_setup(self.ptr, ctypes.byref(g), ctypes.c_uint64(seed), int(point),
+                                     ctypes.byref(plan.c), _stream_ptr(stream, dev))
+        _check(self.lib, self.ptr, rc)
+        plan.keep = keep
+        return plan
+
+    def cgs_apply(self, row_ptr, col, val, diag, plan, b, x, sweeps=1, symmetric=False,
+                  stream=None, nnz=None):
+        """sweeps applications of Algorithm 4 to x (float64 CUDA tensor, in
+        place) for the matrix with off-diagonal values val and diagonal diag."""
+        g, keep = self.graph(row_ptr, col, nnz)
+        tensors = [val, diag, b, x]
+        for t in tensors:
+            assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+        rc = self.lib.mis2_cgs_apply(self.ptr, ctypes.byref(g), ctypes.c_void_p(val.data_ptr()),
+                                     ctypes.c_void_p(diag.data_ptr()), ctypes.byref(plan.c),
+                                     ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                     int(sweeps), int(symmetric), _stream_ptr(stream, self.device))
+        _check(self.lib, self.ptr, rc)
+        del keep
+        return x
+
     def mis2_ablation(self, row_ptr, col, seed=0, flags=0, stream=None, nnz=None):
         """Algorithm 1 with Section V's optimizations taken away (MIS2_ABL_*
         flags).  Returns (status uint8[n] on the GPU, n_roots, n_iters)."""
@@ -286,6 +319,33 @@ class Context:
                         "rows": r.rows, "rows_out": r.rows_out, "edges": r.edges, "ms": r.ms,
                         "compact": r.compact, "written": r.written})
         return out
+
+
+class CgsPlan:
+    """The arrays of a mis2_cgs_plan (device tensors and host colour offsets)."""
+
+    def __init__(self, n, device):
+        m = max(n, 1)
+        self.cluster = torch.empty(m, dtype=torch.int32, device=device)
+        self.cluster_color = torch.empty(m, dtype=torch.int32, device=device)
+        self.rows = torch.empty(m, dtype=torch.int32, device=device)
+        self.cluster_off = torch.empty(n + 1, dtype=torch.int64, device=device)
+        self.color_off = np.zeros(n + 1, np.int64)
+        self.c = _lib.Mis2CgsPlan()
+        self.c.n = n
+        self.c.cluster = self.cluster.data_ptr()
+        self.c.cluster_color = self.cluster_color.data_ptr()
+        self.c.rows = self.rows.data_ptr()
+        self.c.cluster_off = self.cluster_off.data_ptr()
+        self.c.color_off = self.color_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+    @property
+    def n_clusters(self):
+        return self.c.n_clusters
+
+    @property
+    def n_colors(self):
+        return self.c.n_colors
 
 
 class Server:

@@ -1004,6 +1004,15 @@ size_t coarsen_bytes(int64_t n, int64_t nnz) {
     return workspace_bytes(n, MIS2_OP_COARSEN) + 2 * (align_up(8 * (un + 1)) + align_up(4 * unz));
 }
 
+// mis2_cgs_setup: the coarsening workspace, then the colouring and ordering
+// arrays (see the carve there).
+size_t cgs_bytes(int64_t n, int64_t nnz) {
+    const size_t un = (size_t)n;
+    return coarsen_bytes(n, nnz) + 7 * align_up(4 * un) + align_up(8 * (un + 1)) +
+           align_up(8 * (size_t)scan_parts(n)) + align_up(4 * (size_t)(compact_blocks(n) + 1)) +
+           align_up(4 * (un + 1)) + align_up(4 * 64);
+}
+
 // Clears ctx->batch when a batched call returns.
 struct BatchScope {
     mis2_ctx *ctx;
@@ -1177,6 +1186,143 @@ int mis2_quotient(mis2_ctx *ctx, const mis2_graph *g, const int32_t *agg_id, int
     if ((rc = get_workspace(ctx, g, MIS2_OP_COARSEN, &ws))) return rc;
     if ((rc = maybe_validate(ctx, g, ws, s))) return rc;
     return quotient_impl(ctx, g, agg_id, n_agg, coarse_row_ptr, coarse_col, coarse_nnz, ws, s);
+}
+
+int mis2_cgs_workspace_bytes(int64_t n, int64_t nnz, size_t *bytes) {
+    if (!bytes || n < 0 || nnz < 0) return MIS2_EINVAL;
+    *bytes = cgs_bytes(n, nnz);
+    return MIS2_OK;
+}
+
+int mis2_cgs_setup(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int point,
+                   mis2_cgs_plan *plan, void *stream) {
+    int rc = check_graph_args(ctx, g);
+    if (rc) return rc;
+    if (!plan || plan->n != g->n || !plan->color_off ||
+        (g->n > 0 && (!plan->cluster || !plan->cluster_color || !plan->rows || !plan->cluster_off)))
+        return fail(ctx, MIS2_EINVAL, "bad plan (arrays of n = graph's n entries)");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const int64_t n = g->n;
+    plan->n_clusters = 0;
+    plan->n_colors = 0;
+    plan->color_off[0] = 0;
+    if (n == 0) return MIS2_OK;
+    const size_t need = cgs_bytes(n, g->nnz);
+    if (!ctx->ws || ctx->ws_bytes < need)
+        return fail(ctx, MIS2_ENOSPACE, "cluster Gauss-Seidel workspace of %zu bytes needed, %zu set",
+                    need, ctx->ws ? ctx->ws_bytes : (size_t)0);
+    const size_t head = workspace_bytes(n, MIS2_OP_COARSEN);
+    Workspace ws;
+    if (!carve(ctx->ws, head, n, MIS2_OP_COARSEN, &ws))
+        return fail(ctx, MIS2_ENOSPACE, "workspace carve failed");
+    if ((rc = maybe_validate(ctx, g, ws, s))) return rc;
+    char *p = (char *)ctx->ws + head;
+    auto take = [&](size_t sz) {
+        char *r = p;
+        p += align_up(sz);
+        return (void *)r;
+    };
+    int64_t *crow[2];
+    int32_t *ccol[2];
+    for (int i = 0; i < 2; i++) {
+        crow[i] = (int64_t *)take(8 * ((size_t)n + 1));
+        ccol[i] = (int32_t *)take(4 * (size_t)g->nnz);
+    }
+    const size_t un = (size_t)n;
+    uint32_t *pr = (uint32_t *)take(4 * un);
+    int32_t *cround = (int32_t *)take(4 * un);
+    uint32_t *cnt = (uint32_t *)take(4 * un);
+    int64_t *moff = (int64_t *)take(8 * (un + 1));
+    uint32_t *cursor = (uint32_t *)take(4 * un);
+    int32_t *members = (int32_t *)take(4 * un);
+    int32_t *corder = (int32_t *)take(4 * un);
+    uint32_t *ssz = (uint32_t *)take(4 * un);
+    unsigned long long *part = (unsigned long long *)take(8 * (size_t)scan_parts(n));
+    uint32_t *blocksum = (uint32_t *)take(4 * (size_t)(compact_blocks(n) + 1));
+    uint32_t *hist = (uint32_t *)take(4 * (un + 1));
+    uint32_t *scal = (uint32_t *)take(4 * 64);
+
+    // clusters and the graph to colour
+    mis2_graph cg = *g;
+    int64_t nc = n;
+    if (!point) {
+        ws.colc = ccol[1];  // idle until the quotient, as in mis2_coarsen
+        ws.lenc = (int32_t *)crow[1];
+        if ((rc = aggregate_impl(ctx, g, seed, plan->cluster, &nc, nullptr, ws, s))) return rc;
+        int64_t cnnz = 0;
+        if ((rc = quotient_impl(ctx, g, plan->cluster, nc, crow[0], ccol[0], &cnnz, ws, s)))
+            return rc;
+        cg = mis2_graph{nc, cnnz, crow[0], ccol[0]};
+    } else {
+        HIP_TRY(ctx, launch_iota(n, plan->cluster, s));
+    }
+    // Jones-Plassmann colouring of cg; every round colours at least the
+    // smallest uncoloured tuple, so at most nc rounds
+    HIP_TRY(ctx, launch_jp_init(nc, tuple_params(nc, seed, 0), pr, cround, plan->cluster_color, s));
+    HIP_TRY(ctx, launch_fill_u32(scal, 0u, 64, s));
+    for (int r = 0;; r++) {
+        if (r > nc) return fail(ctx, MIS2_EINTERNAL, "colouring made no progress");
+        HIP_TRY(ctx, launch_fill_u32(scal, 0u, 1, s));
+        HIP_TRY(ctx, launch_jp_round(nc, cg.row_ptr, cg.col, pr, cround, plan->cluster_color, r,
+                                     scal, scal + 1, s));
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, scal, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        if (ctx->pinned[0] == 0) break;
+    }
+    const int32_t n_colors = (int32_t)ctx->pinned[1] + 1;
+    // rows of each cluster in increasing id
+    HIP_TRY(ctx, launch_fill_u32(cnt, 0u, nc, s));
+    HIP_TRY(ctx, launch_count_of(n, plan->cluster, cnt, s));
+    HIP_TRY(ctx, exclusive_scan_u32_i64(cnt, nc, moff, part, s));
+    HIP_TRY(ctx, launch_fill_u32(cursor, 0u, nc, s));
+    HIP_TRY(ctx, launch_sorted_members(n, plan->cluster, nc, moff, cursor, members, s));
+    // clusters by colour, then id
+    std::vector<uint32_t> h((size_t)n_colors);
+    HIP_TRY(ctx, launch_fill_u32(hist, 0u, n_colors, s));
+    HIP_TRY(ctx, launch_color_hist(nc, plan->cluster_color, n_colors, hist, s));
+    HIP_TRY(ctx, hipMemcpyAsync(h.data(), hist, 4 * (size_t)n_colors, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    for (int32_t c = 0; c < n_colors; c++) plan->color_off[c + 1] = plan->color_off[c] + h[c];
+    if (plan->color_off[n_colors] != nc)
+        return fail(ctx, MIS2_EINTERNAL, "colour histogram does not add up");
+    for (int32_t c = 0; c < n_colors; c++)
+        HIP_TRY(ctx, compact_u32_eq((const uint32_t *)plan->cluster_color, (uint32_t)c, nc,
+                                    corder + plan->color_off[c], scal + 2, blocksum, s));
+    HIP_TRY(ctx, launch_gather_sizes(nc, corder, cnt, ssz, s));
+    HIP_TRY(ctx, exclusive_scan_u32_i64(ssz, nc, plan->cluster_off, part, s));
+    HIP_TRY(ctx, launch_place_rows(nc, corder, moff, members, plan->cluster_off, plan->rows, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    plan->n_clusters = nc;
+    plan->n_colors = n_colors;
+    return MIS2_OK;
+}
+
+int mis2_cgs_apply(mis2_ctx *ctx, const mis2_graph *g, const double *val, const double *diag,
+                   const mis2_cgs_plan *plan, const double *b, double *x, int32_t sweeps,
+                   int symmetric, void *stream) {
+    int rc = check_graph_args(ctx, g);
+    if (rc) return rc;
+    if (!plan || plan->n != g->n || sweeps < 0 || plan->n_colors < 0 || !plan->color_off)
+        return fail(ctx, MIS2_EINVAL, "bad plan or sweep count");
+    if (g->n > 0 && (!diag || !b || !x || !plan->rows || !plan->cluster_off ||
+                     (g->nnz > 0 && !val)))
+        return fail(ctx, MIS2_EINVAL, "null pointer");
+    if (g->n > 0 && plan->color_off[plan->n_colors] != plan->n_clusters)
+        return fail(ctx, MIS2_EINVAL, "plan's colour offsets do not cover its clusters");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const int64_t *co = plan->color_off;
+    for (int32_t t = 0; t < sweeps; t++) {
+        for (int32_t c = 0; c < plan->n_colors; c++)
+            HIP_TRY(ctx, launch_cgs_sweep(g->row_ptr, g->col, val, diag, b, x, plan->rows,
+                                          plan->cluster_off, co[c], co[c + 1], false, s));
+        if (!symmetric) continue;
+        for (int32_t c = plan->n_colors - 1; c >= 0; c--)
+            HIP_TRY(ctx, launch_cgs_sweep(g->row_ptr, g->col, val, diag, b, x, plan->rows,
+                                          plan->cluster_off, co[c], co[c + 1], true, s));
+    }
+    return MIS2_OK;
 }
 
 int mis2_coarsen_workspace_bytes(int64_t n, int64_t nnz, size_t *bytes) {

@@ -253,6 +253,31 @@ hipError_t launch_rounds(int lanes, int blocks, const int64_t *row_ptr, const in
                          uint32_t *T, uint32_t *M, const RoundsArgs &a, hipStream_t s);
 // e0 / e1 (may be null): events stamped by the launch itself at the kernel's
 // start and end.
+// cgs.hip: Algorithm 4 (cluster multicolor Gauss-Seidel).
+hipError_t launch_jp_init(int64_t n, const TupleParams &tp, uint32_t *pr, int32_t *cround,
+                          int32_t *color, hipStream_t s);
+hipError_t launch_jp_round(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                           const uint32_t *pr, int32_t *cround, int32_t *color, int r,
+                           uint32_t *d_left, uint32_t *d_maxc, hipStream_t s);
+hipError_t launch_iota(int64_t n, int32_t *out, hipStream_t s);
+hipError_t launch_count_of(int64_t n, const int32_t *key, uint32_t *cnt, hipStream_t s);
+hipError_t launch_color_hist(int64_t n, const int32_t *color, int32_t n_colors, uint32_t *hist,
+                             hipStream_t s);
+// members[moff[a] .. moff[a+1]) = the rows of cluster a in increasing id
+// (cursor zero on entry).
+hipError_t launch_sorted_members(int64_t n, const int32_t *cluster, int64_t nc,
+                                 const int64_t *moff, uint32_t *cursor, int32_t *members,
+                                 hipStream_t s);
+hipError_t launch_gather_sizes(int64_t nk, const int32_t *order, const uint32_t *cnt,
+                               uint32_t *out, hipStream_t s);
+hipError_t launch_place_rows(int64_t nk, const int32_t *order, const int64_t *moff,
+                             const int32_t *members, const int64_t *cluster_off, int32_t *rows,
+                             hipStream_t s);
+hipError_t launch_cgs_sweep(const int64_t *row_ptr, const int32_t *col, const double *val,
+                            const double *diag, const double *b, double *x, const int32_t *rows,
+                            const int64_t *cluster_off, int64_t k0, int64_t k1, bool backward,
+                            hipStream_t s);
+
 // Ablation kernels (one lane per row): round 0's tuples, and the Refresh
 // Column (kind 0) / Decide Set (kind 1) of round r; e0 / e1 (may be null)
 // are recorded around the launch.
