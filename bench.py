@@ -111,6 +111,81 @@ def run_ablation(args):
     }
 
 
+def run_cgs(args):
+    """Algorithm 4 on one graph: setup time (coarsening, colouring, ordering)
+    and symmetric sweep time for cluster and point multicolor Gauss-Seidel,
+    and the symmetric sweeps each needs, as a stationary iteration, to bring
+    ||b - A x|| / ||b|| below 1e-8 (the paper measures GMRES iterations with
+    these sweeps as preconditioner; GMRES is not part of this library)."""
+    import numpy as np
+    import torch
+    from paper_2204_02934_amd import api, graphs
+    name, (rp_h, col_h) = workload(args.workload)
+    name = name.split(", MIS-2")[0]
+    n, nnz = rp_h.size - 1, int(rp_h[-1])
+    dev = torch.device("cuda", 0)
+    rp, col = api.as_device_csr(rp_h, col_h, dev)
+    val_h, diag_h = graphs.matrix_values(rp_h, col_h, args.seed, shift=1.0)
+    val = torch.as_tensor(val_h, device=dev)
+    diag = torch.as_tensor(diag_h, device=dev)
+    b = torch.as_tensor(np.random.default_rng(args.seed).standard_normal(n), device=dev)
+    rows = torch.repeat_interleave(torch.arange(n, device=dev), torch.diff(rp))
+    colg = col[:nnz].long()
+
+    def rel_residual(x):
+        ax = diag * x
+        ax.index_add_(0, rows, val * x[colg])
+        return float(torch.linalg.norm(b - ax) / torch.linalg.norm(b))
+
+    ctx = api.Context(0)
+    out = {}
+    for kind, point in (("cluster", False), ("point", True)):
+        ctx.cgs_setup(rp, col, args.seed, point=point, nnz=nnz)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            plan = ctx.cgs_setup(rp, col, args.seed, point=point, nnz=nnz)
+        torch.cuda.synchronize()
+        setup_ms = 1e3 * (time.perf_counter() - t0) / reps
+        x = torch.zeros(n, dtype=torch.float64, device=dev)
+        ctx.cgs_apply(rp, col, val, diag, plan, b, x, sweeps=2, symmetric=True, nnz=nnz)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.cgs_apply(rp, col, val, diag, plan, b, x, sweeps=args.steps, symmetric=True, nnz=nnz)
+        torch.cuda.synchronize()
+        sweep_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        x.zero_()
+        sweeps, res = 0, 1.0
+        while res > 1e-8 and sweeps < 4000:
+            ctx.cgs_apply(rp, col, val, diag, plan, b, x, sweeps=10, symmetric=True, nnz=nnz)
+            sweeps += 10
+            res = rel_residual(x)
+            if sweeps % 200 == 0:
+                log("%s: %d sweeps, residual %.3e" % (kind, sweeps, res))
+        # one symmetric sweep reads each row twice: col 4 B and val 8 B per
+        # entry, diag, b, rows and the x gathers (first touch 8 B per row),
+        # and writes x (8 B per row)
+        sweep_bytes = 2 * (12 * nnz + (8 + 8 + 4 + 8 + 8) * n)
+        out[kind] = {"setup_ms": setup_ms, "sgs_sweep_ms": sweep_ms, "clusters": plan.n_clusters,
+                     "colors": plan.n_colors, "sweeps_to_1e-8": sweeps, "final_residual": res,
+                     "sweep_gbps": sweep_bytes / (sweep_ms * 1e-3) / 1e9}
+        log("%s: setup %.3f ms, %d clusters, %d colours, SGS sweep %.3f ms, %d sweeps to 1e-8"
+            % (kind, setup_ms, plan.n_clusters, plan.n_colors, sweep_ms, sweeps))
+    c, p = out["cluster"], out["point"]
+    return {
+        "metric": "cluster multicolor SGS: time to 1e-8 relative residual (Algorithm 4)",
+        "value": c["setup_ms"] + c["sgs_sweep_ms"] * c["sweeps_to_1e-8"], "unit": "ms",
+        "n_gpus": 1, "steps": args.steps, "warmup": 2, "ms_per_step": c["sgs_sweep_ms"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": name, "n": n, "nnz": nnz, "seed": args.seed,
+                   "matrix": "symmetric M-matrix, off-diagonals -U[0.5,1.5), diagonal = row sum + 1"},
+        "cluster": c, "point": p,
+        "point_time_to_1e-8_ms": p["setup_ms"] + p["sgs_sweep_ms"] * p["sweeps_to_1e-8"],
+    }
+
+
 def kernel_sources_digest():
     """SHA-256 over the HIP sources and headers the sweeps are built from, so a
     stored hardware-counter measurement is used only for the code it measured."""
@@ -335,6 +410,9 @@ def main():
     ap.add_argument("--ablation", action="store_true",
                     help="c1-c3, l100: the optimization ladder of Fig. 2 and the rounds of "
                          "Table I instead of the step")
+    ap.add_argument("--cgs", action="store_true",
+                    help="c1, c2, l100: cluster vs point multicolor Gauss-Seidel (Algorithm 4) "
+                         "instead of the step")
     ap.add_argument("--aggregation", choices=("alg3", "alg2"), default="alg3",
                     help="c1-c3: the aggregation of the step, MIS-2 based aggregation "
                          "(mis2_aggregate) or basic MIS-2 coarsening (mis2_aggregate_basic)")
@@ -342,6 +420,11 @@ def main():
     if args.gpus != 1:
         raise SystemExit("bench.py measures one GPU: this build has no multi-GPU path "
                          "(--gpus %d requested)" % args.gpus)
+    if args.cgs:
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        print(json.dumps(run_cgs(args)), flush=True)
+        return
     if args.ablation:
         import torch
         assert torch.cuda.is_available(), "bench.py needs a GPU"

@@ -186,6 +186,7 @@ typedef struct mis2_cgs_plan {
     int32_t *cluster;       /* device out, int32[n]: cluster of each row */
     int32_t *cluster_color; /* device out, int32[n]: colour of cluster a at [a] (a < n_clusters) */
     int32_t *rows;          /* device out, int32[n]: rows in sweep order */
+    int32_t *pos;           /* device out, int32[n]: sweep position of each row (rows[pos[i]] == i) */
     int64_t *cluster_off;   /* device out, int64[n + 1]: the k-th cluster of the sweep order holds
                                rows[cluster_off[k] .. cluster_off[k+1]) */
     int64_t *color_off;     /* host out, int64[n + 1]: colour c holds the sweep-order clusters

@@ -58,7 +58,7 @@ class Mis2CgsPlan(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("n_clusters", ctypes.c_int64),
                 ("n_colors", ctypes.c_int32), ("cluster", ctypes.c_void_p),
                 ("cluster_color", ctypes.c_void_p), ("rows", ctypes.c_void_p),
-                ("cluster_off", ctypes.c_void_p), ("color_off", ctypes.POINTER(ctypes.c_int64))]
+                ("pos", ctypes.c_void_p), ("cluster_off", ctypes.c_void_p), ("color_off", ctypes.POINTER(ctypes.c_int64))]
 
 
 class Mis2SweepRecord(ctypes.Structure):

@@ -125,7 +125,7 @@ class Context:
 
     def cgs_setup(self, row_ptr, col, seed=0, point=False, stream=None, nnz=None):
         """Algorithm 4's setup (mis2_cgs_setup): returns a CgsPlan holding the
-        device arrays cluster, cluster_color, rows, cluster_off and the host
+        device arrays cluster, cluster_color, rows, pos, cluster_off and the host
         colour offsets."""
         g, keep = self.graph(row_ptr, col, nnz)
         b = ctypes.c_size_t(0)
@@ -329,6 +329,7 @@ class CgsPlan:
         self.cluster = torch.empty(m, dtype=torch.int32, device=device)
         self.cluster_color = torch.empty(m, dtype=torch.int32, device=device)
         self.rows = torch.empty(m, dtype=torch.int32, device=device)
+        self.pos = torch.empty(m, dtype=torch.int32, device=device)
         self.cluster_off = torch.empty(n + 1, dtype=torch.int64, device=device)
         self.color_off = np.zeros(n + 1, np.int64)
         self.c = _lib.Mis2CgsPlan()
@@ -336,6 +337,7 @@ class CgsPlan:
         self.c.cluster = self.cluster.data_ptr()
         self.c.cluster_color = self.cluster_color.data_ptr()
         self.c.rows = self.rows.data_ptr()
+        self.c.pos = self.pos.data_ptr()
         self.c.cluster_off = self.cluster_off.data_ptr()
         self.c.color_off = self.color_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
 

@@ -1199,7 +1199,8 @@ int mis2_cgs_setup(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int point,
     int rc = check_graph_args(ctx, g);
     if (rc) return rc;
     if (!plan || plan->n != g->n || !plan->color_off ||
-        (g->n > 0 && (!plan->cluster || !plan->cluster_color || !plan->rows || !plan->cluster_off)))
+        (g->n > 0 && (!plan->cluster || !plan->cluster_color || !plan->rows || !plan->pos ||
+                      !plan->cluster_off)))
         return fail(ctx, MIS2_EINVAL, "bad plan (arrays of n = graph's n entries)");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -1292,6 +1293,7 @@ int mis2_cgs_setup(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int point,
     HIP_TRY(ctx, launch_gather_sizes(nc, corder, cnt, ssz, s));
     HIP_TRY(ctx, exclusive_scan_u32_i64(ssz, nc, plan->cluster_off, part, s));
     HIP_TRY(ctx, launch_place_rows(nc, corder, moff, members, plan->cluster_off, plan->rows, s));
+    HIP_TRY(ctx, launch_scatter_pos(n, plan->rows, plan->pos, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     plan->n_clusters = nc;
     plan->n_colors = n_colors;
@@ -1305,7 +1307,7 @@ int mis2_cgs_apply(mis2_ctx *ctx, const mis2_graph *g, const double *val, const 
     if (rc) return rc;
     if (!plan || plan->n != g->n || sweeps < 0 || plan->n_colors < 0 || !plan->color_off)
         return fail(ctx, MIS2_EINVAL, "bad plan or sweep count");
-    if (g->n > 0 && (!diag || !b || !x || !plan->rows || !plan->cluster_off ||
+    if (g->n > 0 && (!diag || !b || !x || !plan->rows || !plan->pos || !plan->cluster_off ||
                      (g->nnz > 0 && !val)))
         return fail(ctx, MIS2_EINVAL, "null pointer");
     if (g->n > 0 && plan->color_off[plan->n_colors] != plan->n_clusters)
@@ -1313,14 +1315,18 @@ int mis2_cgs_apply(mis2_ctx *ctx, const mis2_graph *g, const double *val, const 
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     const int64_t *co = plan->color_off;
+    // every cluster a single row (cluster_off[k] == k): one lane per row
+    const bool point = plan->n_clusters == g->n;
+    auto pass = [&](int32_t c, bool backward) {
+        return point ? launch_cgs_point(g->row_ptr, g->col, val, diag, b, x, plan->rows, co[c],
+                                        co[c + 1], s)
+                     : launch_cgs_sweep(g->row_ptr, g->col, val, diag, b, x, plan->rows, plan->pos,
+                                        plan->cluster_off, co[c], co[c + 1], backward, s);
+    };
     for (int32_t t = 0; t < sweeps; t++) {
-        for (int32_t c = 0; c < plan->n_colors; c++)
-            HIP_TRY(ctx, launch_cgs_sweep(g->row_ptr, g->col, val, diag, b, x, plan->rows,
-                                          plan->cluster_off, co[c], co[c + 1], false, s));
+        for (int32_t c = 0; c < plan->n_colors; c++) HIP_TRY(ctx, pass(c, false));
         if (!symmetric) continue;
-        for (int32_t c = plan->n_colors - 1; c >= 0; c--)
-            HIP_TRY(ctx, launch_cgs_sweep(g->row_ptr, g->col, val, diag, b, x, plan->rows,
-                                          plan->cluster_off, co[c], co[c + 1], true, s));
+        for (int32_t c = plan->n_colors - 1; c >= 0; c--) HIP_TRY(ctx, pass(c, true));
     }
     return MIS2_OK;
 }

@@ -273,10 +273,14 @@ hipError_t launch_gather_sizes(int64_t nk, const int32_t *order, const uint32_t 
 hipError_t launch_place_rows(int64_t nk, const int32_t *order, const int64_t *moff,
                              const int32_t *members, const int64_t *cluster_off, int32_t *rows,
                              hipStream_t s);
+hipError_t launch_scatter_pos(int64_t n, const int32_t *rows, int32_t *pos, hipStream_t s);
 hipError_t launch_cgs_sweep(const int64_t *row_ptr, const int32_t *col, const double *val,
                             const double *diag, const double *b, double *x, const int32_t *rows,
-                            const int64_t *cluster_off, int64_t k0, int64_t k1, bool backward,
-                            hipStream_t s);
+                            const int32_t *pos, const int64_t *cluster_off, int64_t k0, int64_t k1,
+                            bool backward, hipStream_t s);
+hipError_t launch_cgs_point(const int64_t *row_ptr, const int32_t *col, const double *val,
+                            const double *diag, const double *b, double *x, const int32_t *rows,
+                            int64_t t0, int64_t t1, hipStream_t s);
 
 // Ablation kernels (one lane per row): round 0's tuples, and the Refresh
 // Column (kind 0) / Decide Set (kind 1) of round r; e0 / e1 (may be null)

@@ -48,6 +48,10 @@ def _plan_matches(plan, want, name):
     assert np.array_equal(plan.cluster_color.cpu().numpy()[:k], want["cluster_color"]), name
     assert np.array_equal(plan.rows.cpu().numpy()[:len(want["rows"])], want["rows"]), name
     assert np.array_equal(plan.cluster_off.cpu().numpy()[:k + 1], want["cluster_off"]), name
+    n = len(want["rows"])
+    inv = np.empty(n, np.int32)
+    inv[want["rows"]] = np.arange(n, dtype=np.int32)
+    assert np.array_equal(plan.pos.cpu().numpy()[:n], inv), name
     assert np.array_equal(plan.color_off[:c + 1], want["color_off"]), name
 
 
