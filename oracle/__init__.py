@@ -21,5 +21,6 @@ from .oracle import (  # noqa: F401
     color_jp,
     cgs_plan,
     cgs_apply,
+    galerkin,
     coarsen,
 )

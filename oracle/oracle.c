@@ -18,8 +18,11 @@
  * graphs, breadth-first validity checks of the definitions (Section I),
  * closed-form special cases, exhaustive packing checks (Section V-C, Eq. 1),
  * brute-force aggregation invariants (Section III-B, Alg. 3) and Table III
- * counts (soft: the paper does not fix the hash bits, see oracle_hash).
+ * counts (soft: the paper does not fix the hash bits, see oracle_hash); for
+ * the Galerkin coarse operator, the dense product P^T A P, its special cases
+ * and exact rounding on integer-valued matrices.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -756,5 +759,73 @@ int oracle_cgs_apply(int64_t n, const int64_t *row_ptr, const int32_t *col, cons
                 for (int64_t t = cluster_off[k + 1] - 1; t >= cluster_off[k]; t--)
                     oracle_gs_row(rows[t], row_ptr, col, val, diag, b, x);
     }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Galerkin coarse operator of an aggregation (a multigrid hookup: Section   */
+/* VI-E sets up smoothed-aggregation multigrid on these aggregates).         */
+/*                                                                           */
+/* Reading: the tentative prolongator for the constant near-null space,      */
+/* P[i][a] = 1/sqrt(n_a) when agg(i) = a (n_a = members of a), so that       */
+/* P^T P = I, and the coarse operator A_c = P^T A P:                         */
+/*   (A_c)[a][b] = (sum of A[i][j] over i in a, j in b) / sqrt(n_a * n_b).   */
+/* A is given as the graph's CSR with off-diagonal values val (CSR order)    */
+/* and a diagonal diag.  The off-diagonal part of A_c is laid out on the     */
+/* quotient graph (rows by aggregate, ascending columns, no self); its       */
+/* diagonal gets the fine diagonal and every coupling inside an aggregate.   */
+/* Reading (summation order): each sum runs over the fine rows i in         */
+/* increasing id, and within row i first diag_i (for the diagonal), then its */
+/* entries in CSR order, starting from 0.0; the scaling is one division by   */
+/* sqrt((double)n_a * n_b) (the product is exact below 2^53).                */
+/* ------------------------------------------------------------------------- */
+static int64_t oracle_find_col(const int32_t *c, int64_t lo, int64_t hi, int32_t key)
+{
+    /* plain binary search: position of key in the ascending c[lo .. hi) */
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (c[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+int oracle_galerkin(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                    const double *diag, const int32_t *agg, int64_t n_agg,
+                    const int64_t *crow_ptr, const int32_t *ccol, double *cval, double *cdiag)
+{
+    if (n < 0 || n_agg < 0 || (n > 0 && (!row_ptr || !agg || !diag)) || !crow_ptr ||
+        (n_agg > 0 && !cdiag))
+        return -1;
+    int64_t cnnz = crow_ptr[n_agg];
+    if (cnnz > 0 && (!ccol || !cval)) return -1;
+    int64_t *size = (int64_t *)calloc((size_t)(n_agg > 0 ? n_agg : 1), sizeof(int64_t));
+    if (!size) return -1;
+    for (int64_t i = 0; i < n; i++) {
+        if (agg[i] < 0 || agg[i] >= n_agg) { free(size); return -2; }
+        size[agg[i]]++;
+    }
+    for (int64_t e = 0; e < cnnz; e++) cval[e] = 0.0;
+    for (int64_t a = 0; a < n_agg; a++) cdiag[a] = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        int32_t a = agg[i];
+        cdiag[a] = cdiag[a] + diag[i];
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++) {
+            int32_t b = agg[col[e]];
+            if (b == a) {
+                cdiag[a] = cdiag[a] + val[e];
+                continue;
+            }
+            int64_t p = oracle_find_col(ccol, crow_ptr[a], crow_ptr[a + 1], b);
+            if (p >= crow_ptr[a + 1] || ccol[p] != b) { free(size); return -3; }
+            cval[p] = cval[p] + val[e];
+        }
+    }
+    for (int64_t a = 0; a < n_agg; a++) {
+        for (int64_t p = crow_ptr[a]; p < crow_ptr[a + 1]; p++)
+            cval[p] = cval[p] / sqrt((double)size[a] * (double)size[ccol[p]]);
+        if (size[a] > 0) cdiag[a] = cdiag[a] / sqrt((double)size[a] * (double)size[a]);
+    }
+    free(size);
     return 0;
 }

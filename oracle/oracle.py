@@ -32,7 +32,7 @@ def build_oracle(force=True):
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
     subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-Wall", "-Wextra", "-fPIC",
-                           "-shared", _SRC, "-o", tmp])
+                           "-shared", _SRC, "-o", tmp, "-lm"])
     os.replace(tmp, _LIB)
     _lib = None
     return _LIB
@@ -84,6 +84,9 @@ def _get():
         lib.oracle_quotient.restype = ctypes.c_int64
         lib.oracle_quotient.argtypes = [
             ctypes.c_int64, _i64p, _i32p, _i32p, ctypes.c_int64, _i64p, _i32p, ctypes.c_int64]
+        lib.oracle_galerkin.restype = ctypes.c_int
+        lib.oracle_galerkin.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, _i32p,
+                                        ctypes.c_int64, _i64p, _i32p, _f64p, _f64p]
         _lib = lib
     return _lib
 
@@ -315,6 +318,35 @@ def quotient(row_ptr, col, agg, n_agg):
     if m < 0:
         raise OracleError("oracle_quotient returned %d" % m)
     return crow, ccol[:m].copy()
+
+
+def galerkin(row_ptr, col, val, diag, agg, n_agg, crow=None, ccol=None):
+    """Galerkin coarse operator P^T A P of an aggregation with the tentative
+    prolongator P[i][agg i] = 1/sqrt(|agg i|): returns (crow, ccol, cval,
+    cdiag) with the off-diagonal part on the quotient graph (computed here
+    unless given) and the coarse diagonal."""
+    row_ptr, col = _csr(row_ptr, col)
+    n = row_ptr.size - 1
+    agg = np.ascontiguousarray(agg, dtype=np.int32)
+    if crow is None:
+        crow, ccol = quotient(row_ptr, col, agg, n_agg)
+    crow = np.ascontiguousarray(crow, dtype=np.int64)
+    ccol = np.ascontiguousarray(ccol, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    diag = np.ascontiguousarray(diag, dtype=np.float64)
+    cval = np.zeros(max(int(crow[-1]), 1), np.float64)
+    cdiag = np.zeros(max(n_agg, 1), np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    if n_agg == 0:
+        return crow, ccol, np.zeros(0), np.zeros(0)
+    rc = _get().oracle_galerkin(n, _ptr(row_ptr, _i64p), _ptr(col if col.size else np.zeros(1, np.int32), _i32p),
+                                _ptr(val if val.size else np.zeros(1), dp), _ptr(diag if diag.size else np.zeros(1), dp),
+                                _ptr(agg if agg.size else np.zeros(1, np.int32), _i32p), n_agg,
+                                _ptr(crow, _i64p), _ptr(ccol if ccol.size else np.zeros(1, np.int32), _i32p),
+                                _ptr(cval, dp), _ptr(cdiag, dp))
+    if rc != 0:
+        raise OracleError("oracle_galerkin returned %d" % rc)
+    return crow, ccol, cval[:int(crow[-1])].copy(), cdiag[:n_agg].copy()
 
 
 def coarsen(row_ptr, col, seed=0, stop_below=1000, max_levels=64):
