@@ -305,6 +305,38 @@ int mis2_aggregate_basic(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int3
 int mis2_quotient(mis2_ctx *ctx, const mis2_graph *g, const int32_t *agg_id, int64_t n_agg,
                   int64_t *coarse_row_ptr, int32_t *coarse_col, int64_t *coarse_nnz, void *stream);
 
+/*
+ * mis2_galerkin -- the Galerkin coarse operator of an aggregation, the
+ * multigrid hookup of the aggregates (Section VI-E builds smoothed-aggregation
+ * multigrid on them; the paper takes the operator from its multigrid
+ * package).  With the tentative prolongator for the constant near-null space,
+ * P[i][a] = 1/sqrt(n_a) when agg_id[i] = a (n_a = members of a), it computes
+ * A_c = P^T A P:  (A_c)[a][b] = (sum of A[i][j] over i in a, j in b)
+ * / sqrt(n_a * n_b).  Each sum runs over the fine rows in increasing id,
+ * within a row its diagonal first and then its entries in CSR order, from
+ * 0.0, followed by one division (IEEE fp64, no fused multiply-add), so the
+ * result does not depend on the launch.
+ *
+ *   g            the fine graph; A's off-diagonal entries are val (device,
+ *                double[g->nnz], in g's CSR order), its diagonal diag (device,
+ *                double[g->n])
+ *   agg_id       device, int32[n]: labels in [0, coarse->n)
+ *   coarse       the quotient graph of agg_id (as from mis2_quotient):
+ *                coarse->n = number of aggregates
+ *   coarse_val   device out, double[coarse->nnz]: A_c off the diagonal, in the
+ *                coarse graph's CSR order
+ *   coarse_diag  device out, double[coarse->n]: A_c's diagonal (the fine
+ *                diagonal plus every coupling inside an aggregate)
+ * Needs a workspace of mis2_galerkin_workspace_bytes(n, coarse->n).
+ * Synchronises the stream.  MIS2_EINVAL if a label or coarse column is outside
+ * [0, coarse->n) (nothing is written) or if the coarse graph lacks a coupling
+ * of the aggregation (the outputs are then incomplete).
+ */
+int mis2_galerkin_workspace_bytes(int64_t n, int64_t n_agg, size_t *bytes);
+int mis2_galerkin(mis2_ctx *ctx, const mis2_graph *g, const double *val, const double *diag,
+                  const int32_t *agg_id, const mis2_graph *coarse, double *coarse_val,
+                  double *coarse_diag, void *stream);
+
 /* Bytes of device workspace mis2_coarsen needs for a graph with n vertices
  * and nnz stored entries (written to *bytes, host). */
 int mis2_coarsen_workspace_bytes(int64_t n, int64_t nnz, size_t *bytes);

@@ -40,7 +40,7 @@ EXPORTS = (
     "mis2_last_trace", "mis2_aggregate", "mis2_aggregate_basic", "mis2_last_sweeps",
     "mis2_run_ablation", "mis2_ablation_workspace_bytes", "mis2_cgs_workspace_bytes",
     "mis2_cgs_setup", "mis2_cgs_apply",
-    "mis2_quotient", "mis2_coarsen_workspace_bytes",
+    "mis2_quotient", "mis2_galerkin_workspace_bytes", "mis2_galerkin", "mis2_coarsen_workspace_bytes",
     "mis2_coarsen", "mis2_batch_workspace_bytes", "mis2_aggregate_batched",
     "mis2_server_bytes", "mis2_server_create", "mis2_server_destroy", "mis2_server_last_error",
     "mis2_server_submit", "mis2_server_step", "mis2_server_poll",
@@ -122,6 +122,8 @@ def load():
         "mis2_last_sweeps": (ctypes.c_int, [vp, ctypes.POINTER(Mis2SweepRecord), i32,
                                             ctypes.POINTER(i32)]),
         "mis2_quotient": (ctypes.c_int, [vp, gp, vp, i64, vp, vp, ctypes.POINTER(i64), vp]),
+        "mis2_galerkin_workspace_bytes": (ctypes.c_int, [i64, i64, ctypes.POINTER(ctypes.c_size_t)]),
+        "mis2_galerkin": (ctypes.c_int, [vp, gp, vp, vp, vp, gp, vp, vp, vp]),
         "mis2_coarsen_workspace_bytes": (ctypes.c_int, [i64, i64, ctypes.POINTER(ctypes.c_size_t)]),
         "mis2_coarsen": (ctypes.c_int, [vp, gp, u64, i64, i32, vp, i64, ctypes.POINTER(i64),
                                         ctypes.POINTER(i64), ctypes.POINTER(i64),

@@ -214,6 +214,29 @@ class Context:
         del keep
         return crow, ccol[:cnnz.value]
 
+    def galerkin(self, row_ptr, col, val, diag, agg, crow, ccol, stream=None, nnz=None):
+        """Galerkin coarse operator P^T A P of an aggregation (mis2_galerkin)
+        with the tentative prolongator P[i][agg i] = 1/sqrt(|agg i|): returns
+        (off-diagonal values in the coarse graph's CSR order, diagonal), float64
+        on the GPU.  (crow, ccol) is the quotient graph, as from quotient()."""
+        g, keep = self.graph(row_ptr, col, nnz)
+        cg, ckeep = self.graph(crow, ccol)
+        for t in (val, diag):
+            assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+        agg = torch.as_tensor(agg).to(device=self.device, dtype=torch.int32).contiguous()
+        b = ctypes.c_size_t(0)
+        _check(self.lib, self.ptr, self.lib.mis2_galerkin_workspace_bytes(g.n, cg.n, ctypes.byref(b)))
+        self._ensure_bytes(b.value)
+        cval = torch.empty(max(cg.nnz, 1), dtype=torch.float64, device=self.device)
+        cdiag = torch.empty(max(cg.n, 1), dtype=torch.float64, device=self.device)
+        rc = self.lib.mis2_galerkin(self.ptr, ctypes.byref(g), ctypes.c_void_p(val.data_ptr()),
+                                    ctypes.c_void_p(diag.data_ptr()), ctypes.c_void_p(agg.data_ptr()),
+                                    ctypes.byref(cg), ctypes.c_void_p(cval.data_ptr()),
+                                    ctypes.c_void_p(cdiag.data_ptr()), _stream_ptr(stream, self.device))
+        _check(self.lib, self.ptr, rc)
+        del keep, ckeep
+        return cval[:cg.nnz], cdiag[:cg.n]
+
     def coarsen(self, row_ptr, col, seed=0, stop_below=1000, max_levels=64, stream=None, nnz=None):
         """Multilevel coarsening: list of per-level dicts {n, nnz, n_agg, agg
         (int32 labels on the GPU)}."""

@@ -1188,6 +1188,81 @@ int mis2_quotient(mis2_ctx *ctx, const mis2_graph *g, const int32_t *agg_id, int
     return quotient_impl(ctx, g, agg_id, n_agg, coarse_row_ptr, coarse_col, coarse_nnz, ws, s);
 }
 
+// mis2_galerkin: member counts, offsets, cursors and lists, scan partials
+// and a flag word; at least what validating the fine graph needs.
+static size_t galerkin_bytes(int64_t n, int64_t n_agg) {
+    const size_t ua = (size_t)n_agg;
+    const size_t own = 2 * align_up(4 * ua) + align_up(8 * (ua + 1)) + align_up(4 * (size_t)n) +
+                       align_up(8 * (size_t)scan_parts(n_agg)) + align_up(256);
+    return std::max(own, workspace_bytes(n, MIS2_OP_MIS2));
+}
+
+int mis2_galerkin_workspace_bytes(int64_t n, int64_t n_agg, size_t *bytes) {
+    if (!bytes || n < 0 || n_agg < 0) return MIS2_EINVAL;
+    *bytes = galerkin_bytes(n, n_agg);
+    return MIS2_OK;
+}
+
+int mis2_galerkin(mis2_ctx *ctx, const mis2_graph *g, const double *val, const double *diag,
+                  const int32_t *agg, const mis2_graph *coarse, double *coarse_val,
+                  double *coarse_diag, void *stream) {
+    int rc = check_graph_args(ctx, g);
+    if (rc) return rc;
+    if ((rc = check_graph_args(ctx, coarse))) return rc;
+    const int64_t n = g->n, na = coarse->n;
+    if (na > n || (n > 0 && na == 0)) return fail(ctx, MIS2_EINVAL, "coarse n out of range");
+    if ((n > 0 && (!diag || !agg || !coarse_diag)) || (g->nnz > 0 && !val) ||
+        (coarse->nnz > 0 && !coarse_val))
+        return fail(ctx, MIS2_EINVAL, "null pointer");
+    if (n == 0) return MIS2_OK;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const size_t need = galerkin_bytes(n, na);
+    if (!ctx->ws || ctx->ws_bytes < need)
+        return fail(ctx, MIS2_ENOSPACE, "Galerkin workspace of %zu bytes needed, %zu set", need,
+                    ctx->ws ? ctx->ws_bytes : (size_t)0);
+    char *p = (char *)ctx->ws;
+    auto take = [&](size_t sz) {
+        char *r = p;
+        p += align_up(sz);
+        return (void *)r;
+    };
+    uint32_t *cnt = (uint32_t *)take(4 * (size_t)na);
+    uint32_t *cursor = (uint32_t *)take(4 * (size_t)na);
+    int64_t *moff = (int64_t *)take(8 * ((size_t)na + 1));
+    int32_t *members = (int32_t *)take(4 * (size_t)n);
+    unsigned long long *part = (unsigned long long *)take(8 * (size_t)scan_parts(na));
+    uint32_t *flag = (uint32_t *)take(256);
+    if (ctx->validate) {
+        // both graphs, before the arrays below are filled (same memory)
+        Workspace ws;
+        if ((rc = get_workspace(ctx, g, MIS2_OP_MIS2, &ws))) return rc;
+        if ((rc = maybe_validate(ctx, g, ws, s))) return rc;
+        if ((rc = get_workspace(ctx, coarse, MIS2_OP_MIS2, &ws))) return rc;
+        if ((rc = maybe_validate(ctx, coarse, ws, s))) return rc;
+    }
+    // ids in range before anything indexes by them
+    HIP_TRY(ctx, launch_fill_u32(flag, 0u, 1, s));
+    HIP_TRY(ctx, launch_check_ids(n, agg, coarse->nnz, coarse->col, na, flag, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (ctx->pinned[0] & 1u) return fail(ctx, MIS2_EINVAL, "aggregate id outside [0, %lld)", (long long)na);
+    if (ctx->pinned[0] & 2u) return fail(ctx, MIS2_EINVAL, "coarse column outside [0, %lld)", (long long)na);
+    // members of each aggregate by increasing id
+    HIP_TRY(ctx, launch_fill_u32(cnt, 0u, na, s));
+    HIP_TRY(ctx, launch_count_of(n, agg, cnt, s));
+    HIP_TRY(ctx, exclusive_scan_u32_i64(cnt, na, moff, part, s));
+    HIP_TRY(ctx, launch_fill_u32(cursor, 0u, na, s));
+    HIP_TRY(ctx, launch_sorted_members(n, agg, na, moff, cursor, members, s));
+    HIP_TRY(ctx, launch_galerkin(g->row_ptr, g->col, val, diag, agg, na, moff, members,
+                                 coarse->row_ptr, coarse->col, coarse_val, coarse_diag, flag, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (ctx->pinned[0] & 4u)
+        return fail(ctx, MIS2_EINVAL, "the coarse graph lacks a coupling of the aggregation");
+    return MIS2_OK;
+}
+
 int mis2_cgs_workspace_bytes(int64_t n, int64_t nnz, size_t *bytes) {
     if (!bytes || n < 0 || nnz < 0) return MIS2_EINVAL;
     *bytes = cgs_bytes(n, nnz);

@@ -1,0 +1,176 @@
+// galerkin.hip -- Galerkin coarse operator of an aggregation on gfx950, the
+// multigrid hookup of the aggregates (Section VI-E sets up smoothed-aggregation
+// multigrid on them).
+//
+// With the tentative prolongator for the constant near-null space,
+// P[i][a] = 1/sqrt(n_a) when row i is in aggregate a (n_a members), the coarse
+// operator is A_c = P^T A P:
+//     (A_c)[a][b] = (sum of A[i][j] over i in a, j in b) / sqrt(n_a * n_b).
+// Its off-diagonal part lives on the quotient graph (rows by aggregate,
+// ascending columns, no self); its diagonal takes the fine diagonal and every
+// coupling inside an aggregate.  Every sum runs over the fine rows in
+// increasing id -- within a row, its diagonal first, then its entries in CSR
+// order -- from 0.0, and is divided once by sqrt(n_a * n_b) (the product is
+// exact), so the result is one fixed sequence of roundings.
+//
+// One wavefront per coarse row a.  Its members (counting-sorted by id) are
+// walked in order; a member's items (its diagonal, then its entries) are taken
+// 64 at a time, one per lane.  Each lane finds the coarse column of its item
+// (binary search in the coarse row), and the chunk is folded into the row's
+// accumulators in lane order: for each column, the lowest lane holding it adds
+// the chunk's items of that column one after the other.  Accumulators (and
+// the coarse row's columns) live in LDS for rows of at most kGCap columns,
+// else in the output arrays themselves.  A final pass does the division.
+#include "internal.h"
+
+namespace mis2 {
+
+namespace {
+
+constexpr int kGCap = 511;  // coarse columns of a row held in LDS
+constexpr int kGWaves = kBlock / 64;
+
+struct GStage {
+    double acc[kGCap + 1];  // [0, d): the row's columns, [d]: its diagonal
+    int32_t cols[kGCap];
+};
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// flag[0] |= 1 when an aggregate id is outside [0, n_agg); flag[0] |= 2 when a
+// coarse column is.
+__global__ __launch_bounds__(kBlock) void k_check_ids(int64_t n, const int32_t *__restrict__ agg,
+                                                      int64_t cnnz,
+                                                      const int32_t *__restrict__ ccol,
+                                                      int64_t n_agg, uint32_t *flag) {
+    uint32_t bad = 0;
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n || v < cnnz;
+         v += (int64_t)gridDim.x * kBlock) {
+        if (v < n && (agg[v] < 0 || agg[v] >= n_agg)) bad |= 1u;
+        if (v < cnnz && (ccol[v] < 0 || ccol[v] >= n_agg)) bad |= 2u;
+    }
+    if (bad) atomicOr(flag, bad);
+}
+
+// flag[0] |= 4 when an entry's aggregate pair is missing from the coarse row.
+__global__ __launch_bounds__(kBlock) void k_galerkin(
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const double *__restrict__ val, const double *__restrict__ diag,
+    const int32_t *__restrict__ agg, int64_t n_agg, const int64_t *__restrict__ moff,
+    const int32_t *__restrict__ members, const int64_t *__restrict__ crow,
+    const int32_t *__restrict__ ccol, double *cval, double *cdiag, uint32_t *flag) {
+#pragma clang fp contract(off)
+    __shared__ GStage stage[kGWaves];
+    const int lane = threadIdx.x & 63;
+    GStage &S = stage[threadIdx.x >> 6];
+    const int64_t a = (int64_t)blockIdx.x * kGWaves + (threadIdx.x >> 6);
+    if (a >= n_agg) return;
+    const int64_t c0 = crow[a], c1 = crow[a + 1];
+    const int d = (int)(c1 - c0);
+    const int64_t m0 = moff[a], m1 = moff[a + 1];
+    const bool small = d <= kGCap;
+    double *acc = small ? S.acc : cval + c0;
+    double *accd = small ? &S.acc[d] : cdiag + a;
+    const int32_t *cs = small ? S.cols : ccol + c0;
+    for (int p = lane; p < d; p += 64) {
+        if (small) S.cols[p] = ccol[c0 + p];
+        acc[p] = 0.0;
+    }
+    if (lane == 0) *accd = 0.0;
+    const int top = d > 0 ? 1 << (31 - __builtin_clz((unsigned)d)) : 0;
+    wave_sync();
+    uint32_t missing = 0;
+    for (int64_t k = m0; k < m1; k++) {
+        const int32_t i = members[k];
+        const int64_t rs = row_ptr[i], items = 1 + (row_ptr[i + 1] - rs);
+        for (int64_t t0 = 0; t0 < items; t0 += 64) {
+            const int64_t t = t0 + lane;
+            int p = -1;  // -1: no item; d: the diagonal
+            double v = 0.0;
+            if (t < items) {
+                if (t == 0) {
+                    p = d;
+                    v = diag[i];
+                } else {
+                    const int64_t e = rs + t - 1;
+                    const int32_t b = agg[col[e]];
+                    v = val[e];
+                    if (b == (int32_t)a) {
+                        p = d;
+                    } else {
+                        int lo = 0;  // entries of cs below b
+                        for (int st = top; st > 0; st >>= 1)
+                            if (lo + st <= d && cs[lo + st - 1] < b) lo += st;
+                        if (lo < d && cs[lo] == b) p = lo;
+                        else missing = 4u;
+                    }
+                }
+            }
+            const int cnt = (int)(items - t0 < 64 ? items - t0 : 64);
+            double my = p >= 0 ? (p == d ? *accd : acc[p]) : 0.0;
+            bool leader = p >= 0;
+            for (int w = 0; w < cnt; w++) {
+                const int pw = __builtin_amdgcn_readlane(p, w);
+                const double vw = lane_bcast(v, w);
+                const bool match = pw == p;
+                if (w < lane && match) leader = false;
+                const double sum = my + vw;
+                my = (w >= lane && match) ? sum : my;
+            }
+            if (leader) {
+                if (p == d) *accd = my;
+                else acc[p] = my;
+            }
+            wave_sync();
+        }
+    }
+    // the division by sqrt(n_a * n_b)
+    const double na = (double)(m1 - m0);
+    for (int p = lane; p < d; p += 64) {
+        const int32_t b = cs[p];
+        const double nb = (double)(moff[b + 1] - moff[b]);
+        cval[c0 + p] = acc[p] / sqrt(na * nb);
+    }
+    if (lane == 0) cdiag[a] = m1 > m0 ? *accd / sqrt(na * na) : *accd;
+    if (missing) atomicOr(flag, missing);
+}
+
+int grid_for(int64_t work, int cap) {
+    const int64_t g = (work + kBlock - 1) / kBlock;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+}  // namespace
+
+hipError_t launch_check_ids(int64_t n, const int32_t *agg, int64_t cnnz, const int32_t *ccol,
+                            int64_t n_agg, uint32_t *flag, hipStream_t s) {
+    if (n <= 0 && cnnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_ids, dim3(grid_for(std::max(n, cnnz), 4096)), dim3(kBlock), 0, s,
+                       n, agg, cnnz, ccol, n_agg, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_galerkin(const int64_t *row_ptr, const int32_t *col, const double *val,
+                           const double *diag, const int32_t *agg, int64_t n_agg,
+                           const int64_t *moff, const int32_t *members, const int64_t *crow,
+                           const int32_t *ccol, double *cval, double *cdiag, uint32_t *flag,
+                           hipStream_t s) {
+    if (n_agg <= 0) return hipSuccess;
+    const int64_t blocks = (n_agg + kGWaves - 1) / kGWaves;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_galerkin, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, val,
+                       diag, agg, n_agg, moff, members, crow, ccol, cval, cdiag, flag);
+    return hipGetLastError();
+}
+
+}  // namespace mis2

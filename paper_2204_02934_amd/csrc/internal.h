@@ -274,6 +274,15 @@ hipError_t launch_place_rows(int64_t nk, const int32_t *order, const int64_t *mo
                              const int32_t *members, const int64_t *cluster_off, int32_t *rows,
                              hipStream_t s);
 hipError_t launch_scatter_pos(int64_t n, const int32_t *rows, int32_t *pos, hipStream_t s);
+// galerkin.hip: *flag |= 1 (an aggregate id outside [0, n_agg)), 2 (a coarse
+// column outside it), 4 (a coupling missing from the coarse graph).
+hipError_t launch_check_ids(int64_t n, const int32_t *agg, int64_t cnnz, const int32_t *ccol,
+                            int64_t n_agg, uint32_t *flag, hipStream_t s);
+hipError_t launch_galerkin(const int64_t *row_ptr, const int32_t *col, const double *val,
+                           const double *diag, const int32_t *agg, int64_t n_agg,
+                           const int64_t *moff, const int32_t *members, const int64_t *crow,
+                           const int32_t *ccol, double *cval, double *cdiag, uint32_t *flag,
+                           hipStream_t s);
 hipError_t launch_cgs_sweep(const int64_t *row_ptr, const int32_t *col, const double *val,
                             const double *diag, const double *b, double *x, const int32_t *rows,
                             const int32_t *pos, const int64_t *cluster_off, int64_t k0, int64_t k1,
