@@ -111,6 +111,82 @@ def run_ablation(args):
     }
 
 
+def galerkin_bytes(n, nnz, na, cnnz):
+    """Bytes mis2_galerkin must move: the fine CSR, values, diagonal and labels
+    once (8 + 4 + 8 + 8 + 4 B per row and entry as they apply), each entry's
+    neighbour label (4 B), the member lists (4 + 8 B), the coarse rows (8 + 4 B)
+    and the coarse values and diagonal written (8 B each)."""
+    return (8 * n + 12 * nnz + 8 * n + 4 * n + 4 * nnz + 4 * n + 8 * na +
+            8 * na + 4 * cnnz + 8 * cnnz + 8 * na)
+
+
+def run_galerkin(args):
+    """An aggregation multigrid hierarchy on the GPU: per level, Algorithm 3,
+    the quotient graph and the Galerkin operator P^T A P (tentative
+    prolongator), until fewer than 1000 rows remain."""
+    import numpy as np
+    import torch
+    from paper_2204_02934_amd import api, graphs
+    name, (rp_h, col_h) = workload(args.workload)
+    name = name.split(", MIS-2")[0]
+    dev = torch.device("cuda", 0)
+    val_h, diag_h = graphs.matrix_values(rp_h, col_h, args.seed, shift=1.0)
+    ctx = api.Context(0)
+
+    def hierarchy():
+        rp, col = api.as_device_csr(rp_h, col_h, dev)
+        val, diag = torch.as_tensor(val_h, device=dev), torch.as_tensor(diag_h, device=dev)
+        levels = []
+        while rp.numel() - 1 >= 1000:
+            n, nnz = rp.numel() - 1, int(rp[-1].item())
+            t0 = time.perf_counter()
+            agg, na = ctx.aggregate(rp, col, args.seed, nnz=nnz)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            crow, ccol = ctx.quotient(rp, col, agg, na, nnz=nnz)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            cval, cdiag = ctx.galerkin(rp, col, val, diag, agg, crow, ccol, nnz=nnz)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            levels.append({"n": n, "nnz": nnz, "n_agg": na, "coarse_nnz": int(ccol.numel()),
+                           "aggregate_ms": 1e3 * (t1 - t0), "quotient_ms": 1e3 * (t2 - t1),
+                           "galerkin_ms": 1e3 * (t3 - t2)})
+            if na == n:
+                break
+            rp, col, val, diag = crow, ccol, cval, cdiag
+        return levels
+
+    for _ in range(max(args.warmup, 1)):
+        hierarchy()
+    runs = [hierarchy() for _ in range(args.steps)]
+    best = min(runs, key=lambda lv: sum(l["aggregate_ms"] + l["quotient_ms"] + l["galerkin_ms"]
+                                        for l in lv))
+    total = [sum(l["aggregate_ms"] + l["quotient_ms"] + l["galerkin_ms"] for l in lv) for lv in runs]
+    l0 = best[0]
+    gb = galerkin_bytes(l0["n"], l0["nnz"], l0["n_agg"], l0["coarse_nnz"])
+    for i, l in enumerate(best):
+        log("level %d: n %d nnz %d -> %d aggregates, %d coarse entries; aggregate %.3f ms, "
+            "quotient %.3f ms, Galerkin %.3f ms" % (i, l["n"], l["nnz"], l["n_agg"], l["coarse_nnz"],
+                                                   l["aggregate_ms"], l["quotient_ms"], l["galerkin_ms"]))
+    return {
+        "metric": "aggregation multigrid setup: levels of Algorithm 3 + quotient + Galerkin P^T A P",
+        "value": float(np.median(total)), "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": max(args.warmup, 1), "ms_per_step": float(np.median(total)),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": name, "n": int(rp_h.size - 1), "nnz": int(rp_h[-1]), "seed": args.seed,
+                   "levels": len(best), "stop_below": 1000,
+                   "matrix": "symmetric M-matrix, off-diagonals -U[0.5,1.5), diagonal = row sum + 1"},
+        "levels": best,
+        "galerkin_level0": {"ms_wall": l0["galerkin_ms"], "bytes": gb,
+                            "achieved_gbps_wall": gb / (l0["galerkin_ms"] * 1e-3) / 1e9,
+                            "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                            "note": "wall time of the call: a range check, a counting sort of the "
+                                    "members, the operator kernel and two read-backs"},
+    }
+
+
 def cgs_sweep_bytes(n, nnz, point):
     """Bytes one symmetric sweep (forward, then backward) must move: per
     direction the off-diagonal entries once (col 4 B + val 8 B), and per row
@@ -422,6 +498,9 @@ def main():
     ap.add_argument("--ablation", action="store_true",
                     help="c1-c3, l100: the optimization ladder of Fig. 2 and the rounds of "
                          "Table I instead of the step")
+    ap.add_argument("--galerkin", action="store_true",
+                    help="an aggregation multigrid hierarchy (Algorithm 3, quotient graph, "
+                         "Galerkin P^T A P per level) instead of the step")
     ap.add_argument("--cgs", action="store_true",
                     help="c1, c2, l100: cluster vs point multicolor Gauss-Seidel (Algorithm 4) "
                          "instead of the step")
@@ -432,6 +511,11 @@ def main():
     if args.gpus != 1:
         raise SystemExit("bench.py measures one GPU: this build has no multi-GPU path "
                          "(--gpus %d requested)" % args.gpus)
+    if args.galerkin:
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        print(json.dumps(run_galerkin(args)), flush=True)
+        return
     if args.cgs:
         import torch
         assert torch.cuda.is_available(), "bench.py needs a GPU"

@@ -14,9 +14,11 @@
 // exact), so the result is one fixed sequence of roundings.
 //
 // One wavefront per coarse row a.  Its members (counting-sorted by id) are
-// walked in order; a member's items (its diagonal, then its entries) are taken
-// 64 at a time, one per lane.  Each lane finds the coarse column of its item
-// (binary search in the coarse row), and the chunk is folded into the row's
+// walked in order, 64 at a time; their items (a member's diagonal, then its
+// entries), in that order, are taken 64 at a time, one per lane.  Each lane
+// finds the coarse column of its item (binary search in the coarse row; the
+// member holding the item by binary search over the batch's item offsets),
+// and the chunk is folded into the row's
 // accumulators in lane order: for each column, the lowest lane holding it adds
 // the chunk's items of that column one after the other.  Accumulators (and
 // the coarse row's columns) live in LDS for rows of at most kGCap columns,
@@ -33,12 +35,21 @@ constexpr int kGWaves = kBlock / 64;
 struct GStage {
     double acc[kGCap + 1];  // [0, d): the row's columns, [d]: its diagonal
     int32_t cols[kGCap];
+    int64_t off[65];        // item offsets of a batch of 64 members
+    int64_t rs[64];         // their CSR starts
+    int32_t mi[64];         // their ids
 };
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int64_t lane_bcast64(int64_t v, int l) {
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
 __device__ __forceinline__ double lane_bcast(double v, int l) {
@@ -90,19 +101,39 @@ __global__ __launch_bounds__(kBlock) void k_galerkin(
     const int top = d > 0 ? 1 << (31 - __builtin_clz((unsigned)d)) : 0;
     wave_sync();
     uint32_t missing = 0;
-    for (int64_t k = m0; k < m1; k++) {
-        const int32_t i = members[k];
-        const int64_t rs = row_ptr[i], items = 1 + (row_ptr[i + 1] - rs);
-        for (int64_t t0 = 0; t0 < items; t0 += 64) {
+    // members 64 at a time (lane j: member k0 + j); their items, in member
+    // order, 64 at a time (lane q: item t0 + q of the batch)
+    for (int64_t k0 = m0; k0 < m1; k0 += 64) {
+        const bool mv = k0 + lane < m1;
+        const int32_t mi = mv ? members[k0 + lane] : 0;
+        const int64_t rs = mv ? row_ptr[mi] : 0;
+        const int64_t cnt_i = mv ? 1 + (row_ptr[mi + 1] - rs) : 0;
+        int64_t incl = cnt_i;
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            const int64_t o = __shfl_up(incl, dd, 64);
+            if (lane >= dd) incl += o;
+        }
+        S.off[lane + 1] = incl;
+        S.rs[lane] = rs;
+        S.mi[lane] = mi;
+        if (lane == 0) S.off[0] = 0;
+        const int64_t total = lane_bcast64(incl, 63);
+        wave_sync();
+        for (int64_t t0 = 0; t0 < total; t0 += 64) {
             const int64_t t = t0 + lane;
             int p = -1;  // -1: no item; d: the diagonal
             double v = 0.0;
-            if (t < items) {
-                if (t == 0) {
+            if (t < total) {
+                int kr = 0;  // the member holding item t
+                for (int st = 32; st > 0; st >>= 1)
+                    if (S.off[kr + st] <= t) kr += st;
+                const int64_t o = t - S.off[kr];
+                const int32_t i = S.mi[kr];
+                if (o == 0) {
                     p = d;
                     v = diag[i];
                 } else {
-                    const int64_t e = rs + t - 1;
+                    const int64_t e = S.rs[kr] + o - 1;
                     const int32_t b = agg[col[e]];
                     v = val[e];
                     if (b == (int32_t)a) {
@@ -116,7 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_galerkin(
                     }
                 }
             }
-            const int cnt = (int)(items - t0 < 64 ? items - t0 : 64);
+            const int cnt = (int)(total - t0 < 64 ? total - t0 : 64);
             double my = p >= 0 ? (p == d ? *accd : acc[p]) : 0.0;
             bool leader = p >= 0;
             for (int w = 0; w < cnt; w++) {
