@@ -136,22 +136,21 @@ __global__ __launch_bounds__(kBlock) void k_scatter_members(int64_t n,
 
 constexpr int64_t kSmallCluster = 64;
 
-// Each cluster of at most kSmallCluster members: insertion sort by its lane
-// (position by counting, then a shift: no loop leaves on a value it computes).
+// Each cluster of 2 .. kSmallCluster members: one wavefront, one member per
+// lane; a member's place is the number of smaller ones (ids are distinct),
+// counted across the lanes.  Every lane has its member in a register before
+// any is written back.
 __global__ __launch_bounds__(kBlock) void k_sort_small(int64_t nc, const int64_t *__restrict__ moff,
                                                        int32_t *__restrict__ members) {
-    for (int64_t a = (int64_t)blockIdx.x * kBlock + threadIdx.x; a < nc;
-         a += (int64_t)gridDim.x * kBlock) {
-        const int64_t s = moff[a], e = moff[a + 1];
-        if (e - s > kSmallCluster) continue;
-        for (int64_t i = s + 1; i < e; i++) {
-            const int32_t x = members[i];
-            int64_t above = 0;  // sorted members before i that are larger than x
-            for (int64_t t = s; t < i; t++) above += members[t] > x;
-            for (int64_t t = i; t > i - above; t--) members[t] = members[t - 1];
-            members[i - above] = x;
-        }
-    }
+    const int lane = threadIdx.x & 63;
+    const int64_t a = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (a >= nc) return;
+    const int64_t s = moff[a], m = moff[a + 1] - s;
+    if (m < 2 || m > kSmallCluster) return;
+    const int32_t x = lane < m ? members[s + lane] : 0x7fffffff;
+    int rank = 0;
+    for (int w = 0; w < (int)m; w++) rank += __builtin_amdgcn_readlane(x, w) < x;
+    if (lane < m) members[s + rank] = x;
 }
 
 // Each larger cluster: one workgroup sorts it in place with a bitonic
@@ -566,10 +565,12 @@ hipError_t launch_color_hist(int64_t n, const int32_t *color, int32_t n_colors, 
 hipError_t launch_sorted_members(int64_t n, const int32_t *cluster, int64_t nc,
                                  const int64_t *moff, uint32_t *cursor, int32_t *members,
                                  hipStream_t s) {
-    if (n <= 0) return hipSuccess;
+    if (n <= 0 || nc <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_scatter_members, dim3(grid_of(n, 8192)), dim3(kBlock), 0, s, n, cluster,
                        moff, cursor, members);
-    hipLaunchKernelGGL(k_sort_small, dim3(grid_of(nc, 8192)), dim3(kBlock), 0, s, nc, moff,
+    const int64_t sblocks = (nc + kBlock / 64 - 1) / (kBlock / 64);
+    if (sblocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sort_small, dim3((unsigned)sblocks), dim3(kBlock), 0, s, nc, moff,
                        members);
     hipLaunchKernelGGL(k_sort_large, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(nc, 1024))),
                        dim3(kBlock), 0, s, nc, moff, members);

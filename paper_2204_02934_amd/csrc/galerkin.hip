@@ -19,8 +19,9 @@
 // finds the coarse column of its item (binary search in the coarse row; the
 // member holding the item by binary search over the batch's item offsets),
 // and the chunk is folded into the row's
-// accumulators in lane order: for each column, the lowest lane holding it adds
-// the chunk's items of that column one after the other.  Accumulators (and
+// accumulators in item order: the chunk is sorted by (column, lane) with a
+// 64-lane bitonic network, and the first lane of each column's run adds the
+// run's items one after the other.  Accumulators (and
 // the coarse row's columns) live in LDS for rows of at most kGCap columns,
 // else in the output arrays themselves.  A final pass does the division.
 #include "internal.h"
@@ -147,20 +148,36 @@ __global__ __launch_bounds__(kBlock) void k_galerkin(
                     }
                 }
             }
-            const int cnt = (int)(total - t0 < 64 ? total - t0 : 64);
-            double my = p >= 0 ? (p == d ? *accd : acc[p]) : 0.0;
-            bool leader = p >= 0;
-            for (int w = 0; w < cnt; w++) {
-                const int pw = __builtin_amdgcn_readlane(p, w);
-                const double vw = lane_bcast(v, w);
-                const bool match = pw == p;
-                if (w < lane && match) leader = false;
-                const double sum = my + vw;
-                my = (w >= lane && match) ? sum : my;
+            // sort the chunk by (column, lane): each column's items become one
+            // run of lanes, still in item order
+            uint64_t key = p >= 0 ? ((uint64_t)(uint32_t)p << 6) | (uint32_t)lane : ~0ull;
+            for (int k = 2; k <= 64; k <<= 1)
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    const uint64_t other = __shfl_xor(key, j, 64);
+                    const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+                    key = keep_min ? (key < other ? key : other) : (key > other ? key : other);
+                }
+            const bool valid = key != ~0ull;
+            const int sp = valid ? (int)(key >> 6) : -1;
+            const double sv = __shfl(v, (int)(key & 63), 64);
+            const int prev = __shfl_up(sp, 1, 64);
+            const bool head = valid && (lane == 0 || prev != sp);
+            // the run of the head at lane r ends at the next head (or the
+            // first invalid lane)
+            const uint64_t heads = __ballot(head) | __ballot(!valid);
+            const uint64_t after = lane == 63 ? 0ull : heads & (~0ull << (lane + 1));
+            const int run = head ? (after ? __ffsll((unsigned long long)after) - 1 : 64) - lane : 0;
+            int longest = run;
+            for (int o = 32; o > 0; o >>= 1) longest = max(longest, __shfl_xor(longest, o, 64));
+            double my = head ? (sp == d ? *accd : acc[sp]) : 0.0;
+            for (int j = 0; j < longest; j++) {
+                const double vj = __shfl(sv, lane + j < 64 ? lane + j : 63, 64);
+                const double sum = my + vj;
+                my = j < run ? sum : my;
             }
-            if (leader) {
-                if (p == d) *accd = my;
-                else acc[p] = my;
+            if (head) {
+                if (sp == d) *accd = my;
+                else acc[sp] = my;
             }
             wave_sync();
         }
