@@ -77,10 +77,15 @@ int lanes_for(const mis2_ctx *ctx, const mis2_graph *g) {
 // blocks per XCD), about 320 vertices per workgroup, at most kMaxBlocks.
 // Measured on gfx950 with the 27-point 100^3 graph: 2048 workgroups ran
 // MIS-2 in 0.49 ms, 3072 in 0.46 ms, 4096 in 0.47 ms.
+// One workgroup (4 wavefronts) per about 640 vertices, in whole multiples of
+// the 256 compute units once there are that many: on a 10^6-row graph 1536
+// workgroups, six per CU, all resident at once, so every round (most are
+// short) is one wave of dispatch with no partial second one.  Smaller graphs
+// take one workgroup per 320 vertices (a multiple of 8, one per XCD).
 int blocks_for(const mis2_ctx *ctx, int64_t n) {
     if (ctx->plan.blocks) return ctx->plan.blocks;
-    int64_t b = (n + 319) / 320;
-    b = (b + 7) / 8 * 8;
+    int64_t b = (n + 639) / 640;
+    b = b >= 256 ? (b + 128) / 256 * 256 : std::min<int64_t>(256, ((n + 319) / 320 + 7) / 8 * 8);
     return (int)std::max<int64_t>(8, std::min<int64_t>(b, kMaxBlocks));
 }
 
