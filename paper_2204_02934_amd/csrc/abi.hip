@@ -793,7 +793,17 @@ int mis2_run_ablation(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int fla
     }
     ctx->events_used = 0;
     std::vector<Launch> launches;
-    const Geometry gm = geometry(ctx, g->n, 1);
+    Geometry gm = geometry(ctx, g->n, 1);
+    const int simple_flags = MIS2_ABL_FIXED_PRIORITY | MIS2_ABL_XORSHIFT | MIS2_ABL_NO_WORKLISTS |
+                             MIS2_ABL_UNPACKED | MIS2_ABL_SIMPLE;
+    if ((flags & simple_flags) && !ctx->plan.blocks) {
+        // the simple kernels (one lane per row, a plain loop) hide latency with
+        // threads: one workgroup per 320 vertices, a multiple of 8
+        gm.blocks = (int)std::max<int64_t>(8, std::min<int64_t>(((g->n + 319) / 320 + 7) / 8 * 8,
+                                                                kMaxBlocks));
+        gm.S = (int64_t)gm.blocks * (kBlock / 64);
+        gm.seg = std::max<int64_t>(1, (g->n + gm.S - 1) / gm.S);
+    }
     RoundsArgs ia = round_args(ctx, g, seed, ws, gm, false, nullptr, 1);
     ia.abl = abl.pflags;
     HIP_TRY(ctx, launch_abl_init(abl.unpacked, abl.T, ia, s));
