@@ -102,3 +102,42 @@ def test_cgs_full_27_point_100_cube(ctx):
 def test_cgs_empty_graph(ctx):
     plan = ctx.cgs_setup(np.zeros(1, np.int64), np.zeros(0, np.int32))
     assert plan.n_clusters == 0 and plan.n_colors == 0
+
+
+def test_cgs_validated_and_stale_workspace():
+    # a validating context, a workspace full of 0xFF bytes before each setup,
+    # and a larger graph after a smaller one: plans and sweeps stay exact
+    import torch
+    from paper_2204_02934_amd import api
+    c = api.Context(0, validate=True)
+    dev = torch.device("cuda", 0)
+    for rp, cc in [graphs.grid2d_5pt(20, 17), graphs.chung_lu(5000, 8.0, 2.1, 600, seed=2),
+                   graphs.grid3d_27pt(9, 9, 8)]:
+        n = rp.size - 1
+        for point in (False, True):
+            if c._ws is not None:
+                c._ws.fill_(0xFF)
+            plan = c.cgs_setup(rp, cc, seed=5, point=point)
+            want = oracle.cgs_plan(rp, cc, 5, point=point)
+            _plan_matches(plan, want, "validated")
+            val, diag = graphs.matrix_values(rp, cc, 3)
+            b = np.linspace(-1.0, 1.0, n)
+            x = torch.zeros(n, dtype=torch.float64, device=dev)
+            c.cgs_apply(rp, cc, torch.as_tensor(val, device=dev), torch.as_tensor(diag, device=dev),
+                        plan, torch.as_tensor(b, device=dev), x, sweeps=2, symmetric=True)
+            ref = oracle.cgs_apply(rp, cc, val, diag, want, b, np.zeros(n), sweeps=2, symmetric=True)
+            assert np.array_equal(x.cpu().numpy(), ref)
+
+
+def test_cgs_rejects_bad_plans(ctx):
+    import torch
+    from paper_2204_02934_amd._lib import Mis2Error
+    rp, cc = graphs.grid2d_5pt(8, 8)
+    plan = ctx.cgs_setup(rp, cc)
+    plan.c.n = 10  # not the graph's n
+    dev = torch.device("cuda", 0)
+    val, diag = graphs.matrix_values(rp, cc, 0)
+    x = torch.zeros(64, dtype=torch.float64, device=dev)
+    with pytest.raises(Mis2Error):
+        ctx.cgs_apply(rp, cc, torch.as_tensor(val, device=dev), torch.as_tensor(diag, device=dev),
+                      plan, torch.zeros(64, dtype=torch.float64, device=dev), x)

@@ -123,3 +123,24 @@ def test_galerkin_on_the_gpu_hierarchy(ctx):
     _, _, wval, wdiag = oracle.galerkin(rp, cc, val, diag, a, na, crow.cpu().numpy(),
                                         ccol.cpu().numpy())
     assert np.array_equal(cval.cpu().numpy(), wval) and np.array_equal(cdiag.cpu().numpy(), wdiag)
+
+
+def test_galerkin_validated_stale_workspace_and_sizes():
+    # a validating context, a workspace of 0xFF bytes before each call, and
+    # graphs of growing and shrinking size on one context
+    import torch
+    from paper_2204_02934_amd import api
+    c = api.Context(0, validate=True)
+    dev = torch.device("cuda", 0)
+    for name in ("grid2d", "chunglu_50k", "path101", "grid27_20", "star300"):
+        rp, cc = GRAPHS[name]()
+        val, diag = graphs.matrix_values(rp, cc, 7)
+        agg, na = oracle.aggregate(rp, cc, 1)
+        crow, ccol = oracle.quotient(rp, cc, agg, na)
+        if c._ws is not None:
+            c._ws.fill_(0xFF)
+        cval, cdiag = c.galerkin(rp, cc, torch.as_tensor(val if val.size else np.zeros(1), device=dev),
+                                 torch.as_tensor(diag, device=dev), agg, crow, ccol)
+        _, _, wval, wdiag = oracle.galerkin(rp, cc, val, diag, agg, na, crow, ccol)
+        assert np.array_equal(cval.cpu().numpy(), wval), name
+        assert np.array_equal(cdiag.cpu().numpy(), wdiag), name
