@@ -1270,7 +1270,8 @@ int mis2_galerkin(mis2_ctx *ctx, const mis2_graph *g, const double *val, const d
     HIP_TRY(ctx, launch_fill_u32(cursor, 0u, na, s));
     HIP_TRY(ctx, launch_sorted_members(n, agg, na, moff, cursor, members, s));
     HIP_TRY(ctx, launch_galerkin(g->row_ptr, g->col, val, diag, agg, na, moff, members,
-                                 coarse->row_ptr, coarse->col, coarse_val, coarse_diag, flag, s));
+                                 coarse->row_ptr, coarse->col, coarse_val, coarse_diag, flag,
+                                 g->nnz, s));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     if (ctx->pinned[0] & 4u)

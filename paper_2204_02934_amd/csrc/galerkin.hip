@@ -74,13 +74,63 @@ __global__ __launch_bounds__(kBlock) void k_check_ids(int64_t n, const int32_t *
     if (bad) atomicOr(flag, bad);
 }
 
+// The slot of coarse column b in the ascending cs[0 .. d) (top: the largest
+// power of two <= d); -1, and *missing = 4, when b is not there.
+__device__ __forceinline__ int coarse_slot(const int32_t *cs, int d, int top, int32_t b,
+                                           uint32_t *missing) {
+    int lo = 0;  // entries of cs below b
+    for (int st = top; st > 0; st >>= 1)
+        if (lo + st <= d && cs[lo + st - 1] < b) lo += st;
+    if (lo < d && cs[lo] == b) return lo;
+    *missing = 4u;
+    return -1;
+}
+
+// Folds a chunk (lane q: slot p, -1 for none, d for the diagonal; value v) into
+// the accumulators in lane order.  The chunk is sorted by (slot, lane) with a
+// 64-lane bitonic network, so each slot's items form one run of lanes, still
+// in lane order, and the run's first lane adds them one after the other.
+__device__ __forceinline__ void fold_chunk(int p, double v, int d, double *acc, double *accd,
+                                           int lane) {
+#pragma clang fp contract(off)
+    uint64_t key = p >= 0 ? ((uint64_t)(uint32_t)p << 6) | (uint32_t)lane : ~0ull;
+    for (int k = 2; k <= 64; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint64_t other = __shfl_xor(key, j, 64);
+            const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+            key = keep_min ? (key < other ? key : other) : (key > other ? key : other);
+        }
+    const bool valid = key != ~0ull;
+    const int sp = valid ? (int)(key >> 6) : -1;
+    const double sv = __shfl(v, (int)(key & 63), 64);
+    const int prev = __shfl_up(sp, 1, 64);
+    const bool head = valid && (lane == 0 || prev != sp);
+    // the run of the head at lane r ends at the next head (or the first
+    // invalid lane)
+    const uint64_t heads = __ballot(head) | __ballot(!valid);
+    const uint64_t after = lane == 63 ? 0ull : heads & (~0ull << (lane + 1));
+    const int run = head ? (after ? __ffsll((unsigned long long)after) - 1 : 64) - lane : 0;
+    int longest = run;
+    for (int o = 32; o > 0; o >>= 1) longest = max(longest, __shfl_xor(longest, o, 64));
+    double my = head ? (sp == d ? *accd : acc[sp]) : 0.0;
+    for (int j = 0; j < longest; j++) {
+        const double vj = __shfl(sv, lane + j < 64 ? lane + j : 63, 64);
+        const double sum = my + vj;
+        my = j < run ? sum : my;
+    }
+    if (head) {
+        if (sp == d) *accd = my;
+        else acc[sp] = my;
+    }
+}
+
 // flag[0] |= 4 when an entry's aggregate pair is missing from the coarse row.
 __global__ __launch_bounds__(kBlock) void k_galerkin(
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const double *__restrict__ val, const double *__restrict__ diag,
     const int32_t *__restrict__ agg, int64_t n_agg, const int64_t *__restrict__ moff,
     const int32_t *__restrict__ members, const int64_t *__restrict__ crow,
-    const int32_t *__restrict__ ccol, double *cval, double *cdiag, uint32_t *flag) {
+    const int32_t *__restrict__ ccol, double *cval, double *cdiag, uint32_t *flag, int64_t nnz) {
 #pragma clang fp contract(off)
     __shared__ GStage stage[kGWaves];
     const int lane = threadIdx.x & 63;
@@ -120,66 +170,44 @@ __global__ __launch_bounds__(kBlock) void k_galerkin(
         if (lane == 0) S.off[0] = 0;
         const int64_t total = lane_bcast64(incl, 63);
         wave_sync();
-        for (int64_t t0 = 0; t0 < total; t0 += 64) {
-            const int64_t t = t0 + lane;
-            int p = -1;  // -1: no item; d: the diagonal
-            double v = 0.0;
-            if (t < total) {
-                int kr = 0;  // the member holding item t
-                for (int st = 32; st > 0; st >>= 1)
-                    if (S.off[kr + st] <= t) kr += st;
-                const int64_t o = t - S.off[kr];
-                const int32_t i = S.mi[kr];
-                if (o == 0) {
-                    p = d;
-                    v = diag[i];
-                } else {
-                    const int64_t e = S.rs[kr] + o - 1;
-                    const int32_t b = agg[col[e]];
-                    v = val[e];
-                    if (b == (int32_t)a) {
-                        p = d;
-                    } else {
-                        int lo = 0;  // entries of cs below b
-                        for (int st = top; st > 0; st >>= 1)
-                            if (lo + st <= d && cs[lo + st - 1] < b) lo += st;
-                        if (lo < d && cs[lo] == b) p = lo;
-                        else missing = 4u;
-                    }
+        // two chunks per step, A = items t0 .. t0+63 and B = the next 64: their
+        // loads are issued together from clamped valid addresses, then A is
+        // folded and B after it
+        for (int64_t t0 = 0; t0 < total; t0 += 128) {
+            const int64_t ta = t0 + lane, tb = t0 + 64 + lane;
+            const bool ina = ta < total, inb = tb < total;
+            const int64_t tac = ina ? ta : 0, tbc = inb ? tb : 0;
+            int kra = 0, krb = 0;  // the members holding the items
+            for (int st = 32; st > 0; st >>= 1) {
+                if (S.off[kra + st] <= tac) kra += st;
+                if (S.off[krb + st] <= tbc) krb += st;
+            }
+            const int64_t oa = tac - S.off[kra], ob = tbc - S.off[krb];
+            const bool da = oa == 0, db = ob == 0;  // the member's diagonal
+            const double dga = diag[S.mi[kra]], dgb = diag[S.mi[krb]];
+            int pa = ina ? d : -1, pb = inb ? d : -1;  // -1: no item; d: the diagonal
+            double va = dga, vb = dgb;
+            if (nnz > 0) {
+                const int64_t ea = ina && !da ? S.rs[kra] + oa - 1 : 0;
+                const int64_t eb = inb && !db ? S.rs[krb] + ob - 1 : 0;
+                const int32_t ca = col[ea], cb = col[eb];
+                const double xa = val[ea], xb = val[eb];
+                const int32_t ba = agg[ca], bb = agg[cb];
+                if (ina && !da) {
+                    va = xa;
+                    if (ba != (int32_t)a) pa = coarse_slot(cs, d, top, ba, &missing);
+                }
+                if (inb && !db) {
+                    vb = xb;
+                    if (bb != (int32_t)a) pb = coarse_slot(cs, d, top, bb, &missing);
                 }
             }
-            // sort the chunk by (column, lane): each column's items become one
-            // run of lanes, still in item order
-            uint64_t key = p >= 0 ? ((uint64_t)(uint32_t)p << 6) | (uint32_t)lane : ~0ull;
-            for (int k = 2; k <= 64; k <<= 1)
-                for (int j = k >> 1; j > 0; j >>= 1) {
-                    const uint64_t other = __shfl_xor(key, j, 64);
-                    const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
-                    key = keep_min ? (key < other ? key : other) : (key > other ? key : other);
-                }
-            const bool valid = key != ~0ull;
-            const int sp = valid ? (int)(key >> 6) : -1;
-            const double sv = __shfl(v, (int)(key & 63), 64);
-            const int prev = __shfl_up(sp, 1, 64);
-            const bool head = valid && (lane == 0 || prev != sp);
-            // the run of the head at lane r ends at the next head (or the
-            // first invalid lane)
-            const uint64_t heads = __ballot(head) | __ballot(!valid);
-            const uint64_t after = lane == 63 ? 0ull : heads & (~0ull << (lane + 1));
-            const int run = head ? (after ? __ffsll((unsigned long long)after) - 1 : 64) - lane : 0;
-            int longest = run;
-            for (int o = 32; o > 0; o >>= 1) longest = max(longest, __shfl_xor(longest, o, 64));
-            double my = head ? (sp == d ? *accd : acc[sp]) : 0.0;
-            for (int j = 0; j < longest; j++) {
-                const double vj = __shfl(sv, lane + j < 64 ? lane + j : 63, 64);
-                const double sum = my + vj;
-                my = j < run ? sum : my;
-            }
-            if (head) {
-                if (sp == d) *accd = my;
-                else acc[sp] = my;
-            }
+            fold_chunk(pa, va, d, acc, accd, lane);
             wave_sync();
+            if (t0 + 64 < total) {
+                fold_chunk(pb, vb, d, acc, accd, lane);
+                wave_sync();
+            }
         }
     }
     // the division by sqrt(n_a * n_b)
@@ -212,12 +240,12 @@ hipError_t launch_galerkin(const int64_t *row_ptr, const int32_t *col, const dou
                            const double *diag, const int32_t *agg, int64_t n_agg,
                            const int64_t *moff, const int32_t *members, const int64_t *crow,
                            const int32_t *ccol, double *cval, double *cdiag, uint32_t *flag,
-                           hipStream_t s) {
+                           int64_t nnz, hipStream_t s) {
     if (n_agg <= 0) return hipSuccess;
     const int64_t blocks = (n_agg + kGWaves - 1) / kGWaves;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_galerkin, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, val,
-                       diag, agg, n_agg, moff, members, crow, ccol, cval, cdiag, flag);
+                       diag, agg, n_agg, moff, members, crow, ccol, cval, cdiag, flag, nnz);
     return hipGetLastError();
 }
 

@@ -282,7 +282,7 @@ hipError_t launch_galerkin(const int64_t *row_ptr, const int32_t *col, const dou
                            const double *diag, const int32_t *agg, int64_t n_agg,
                            const int64_t *moff, const int32_t *members, const int64_t *crow,
                            const int32_t *ccol, double *cval, double *cdiag, uint32_t *flag,
-                           hipStream_t s);
+                           int64_t nnz, hipStream_t s);
 hipError_t launch_cgs_sweep(const int64_t *row_ptr, const int32_t *col, const double *val,
                             const double *diag, const double *b, double *x, const int32_t *rows,
                             const int32_t *pos, const int64_t *cluster_off, int64_t k0, int64_t k1,
