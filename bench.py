@@ -509,7 +509,7 @@ def main():
                          "(mis2_aggregate) or basic MIS-2 coarsening (mis2_aggregate_basic)")
     args = ap.parse_args()
     if args.gpus != 1:
-        raise SystemExit("bench.py measures one GPU: this build has no multi-GPU path "
+        raise SystemExit("bench.py measures one GPU: the library has no multi-GPU path "
                          "(--gpus %d requested)" % args.gpus)
     if args.galerkin:
         import torch

@@ -53,12 +53,6 @@ __device__ __forceinline__ int64_t lane_bcast64(int64_t v, int l) {
     return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-__device__ __forceinline__ double lane_bcast(double v, int l) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
-}
-
 // flag[0] |= 1 when an aggregate id is outside [0, n_agg); flag[0] |= 2 when a
 // coarse column is.
 __global__ __launch_bounds__(kBlock) void k_check_ids(int64_t n, const int32_t *__restrict__ agg,

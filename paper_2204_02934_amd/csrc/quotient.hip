@@ -32,10 +32,6 @@ constexpr int kWEdges = 8;                   // entries per lane loaded together
 constexpr int kShortRow = 64;                // member rows read by one thread (bitmap path)
 constexpr uint32_t kLongCap = 1024;          // long member rows listed in LDS (bitmap path)
 
-__device__ __forceinline__ uint64_t below_mask(int lane) {
-    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
-
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
