@@ -39,11 +39,17 @@ def build_oracle(force=True):
 
 
 def _get():
+    """The oracle library, loaded once.  MIS2_ORACLE_LIB names another build
+    of oracle.c to load instead (the mutation tests plant mistakes in copies
+    and check that the pins catch them)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build_oracle()
-        lib = ctypes.CDLL(_LIB)
+        path = os.environ.get("MIS2_ORACLE_LIB")
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB):
+                build_oracle()
+        lib = ctypes.CDLL(path)
         lib.oracle_xorshift64star.restype = ctypes.c_uint64
         lib.oracle_xorshift64star.argtypes = [ctypes.c_uint64]
         lib.oracle_hash.restype = ctypes.c_uint64
