@@ -84,17 +84,20 @@ __device__ __forceinline__ int coarse_slot(const int32_t *cs, int d, int top, in
 // the accumulators in lane order.  The chunk is sorted by (slot, lane) with a
 // 64-lane bitonic network, so each slot's items form one run of lanes, still
 // in lane order, and the run's first lane adds them one after the other.
+// Key = slot * 64 + lane in a K-bit word (32 bits while d < 2^25).
+template <typename K>
 __device__ __forceinline__ void fold_chunk(int p, double v, int d, double *acc, double *accd,
                                            int lane) {
 #pragma clang fp contract(off)
-    uint64_t key = p >= 0 ? ((uint64_t)(uint32_t)p << 6) | (uint32_t)lane : ~0ull;
+    const K none = ~(K)0;
+    K key = p >= 0 ? ((K)(uint32_t)p << 6) | (K)(uint32_t)lane : none;
     for (int k = 2; k <= 64; k <<= 1)
         for (int j = k >> 1; j > 0; j >>= 1) {
-            const uint64_t other = __shfl_xor(key, j, 64);
+            const K other = __shfl_xor(key, j, 64);
             const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
             key = keep_min ? (key < other ? key : other) : (key > other ? key : other);
         }
-    const bool valid = key != ~0ull;
+    const bool valid = key != none;
     const int sp = valid ? (int)(key >> 6) : -1;
     const double sv = __shfl(v, (int)(key & 63), 64);
     const int prev = __shfl_up(sp, 1, 64);
@@ -144,6 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_galerkin(
     }
     if (lane == 0) *accd = 0.0;
     const int top = d > 0 ? 1 << (31 - __builtin_clz((unsigned)d)) : 0;
+    const bool narrow = d < (1 << 25);  // slot * 64 + lane fits 31 bits
     wave_sync();
     uint32_t missing = 0;
     // members 64 at a time (lane j: member k0 + j); their items, in member
@@ -196,10 +200,12 @@ __global__ __launch_bounds__(kBlock) void k_galerkin(
                     if (bb != (int32_t)a) pb = coarse_slot(cs, d, top, bb, &missing);
                 }
             }
-            fold_chunk(pa, va, d, acc, accd, lane);
+            if (narrow) fold_chunk<uint32_t>(pa, va, d, acc, accd, lane);
+            else fold_chunk<uint64_t>(pa, va, d, acc, accd, lane);
             wave_sync();
             if (t0 + 64 < total) {
-                fold_chunk(pb, vb, d, acc, accd, lane);
+                if (narrow) fold_chunk<uint32_t>(pb, vb, d, acc, accd, lane);
+                else fold_chunk<uint64_t>(pb, vb, d, acc, accd, lane);
                 wave_sync();
             }
         }
