@@ -321,10 +321,14 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
     // size counters: every ring slot zero except slot 0 of a masked start,
     // which holds its active count; each Refresh Column clears the slot two
     // rounds ahead.
-    HIP_TRY(ctx, launch_fill_u32(ws.ctr + (masked ? kCtrSlot : 0), 0u,
-                                 (int64_t)(masked ? kCtrRing - 1 : kCtrRing) * kCtrSlot, s));
-    if (!masked) HIP_TRY(ctx, launch_fill_u32(ws.rt, (uint32_t)g->n, 2, s));
-    if (!masked) HIP_TRY(ctx, launch_fill_u32(ws.lflag, 0u, (int64_t)kSplit * kCtrLine, s));
+    {
+        FillSpans f;
+        f.add(ws.ctr + (masked ? kCtrSlot : 0), 0u,
+              (int64_t)(masked ? kCtrRing - 1 : kCtrRing) * kCtrSlot);
+        if (!masked) f.add(ws.rt, (uint32_t)g->n, 2);
+        if (!masked) f.add(ws.lflag, 0u, (int64_t)kSplit * kCtrLine);
+        HIP_TRY(ctx, launch_fill_spans(f, s));
+    }
     if (ctx->plan.persistent && !abl) {
         if (!masked) *long_rows = 0;
         int rc = run_rounds_persistent(ctx, g, seed, ws, gm, masked, phase, s, iters_out, launches,
@@ -863,8 +867,12 @@ int phase1_labels(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Works
     HIP_TRY(ctx, launch_init_tuples(tparams(ctx, n, seed, 0), n, ws.T, s));
     if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, iters, launches, long_rows)))
         return rc;
-    HIP_TRY(ctx, launch_fill_u32(sc, 0u, kScalars, s));
-    HIP_TRY(ctx, launch_fill_i32(ws.label, -1, n, s));
+    {
+        FillSpans f;
+        f.add(sc, 0u, kScalars);
+        f.add((uint32_t *)ws.label, 0xFFFFFFFFu, n);  // -1
+        HIP_TRY(ctx, launch_fill_spans(f, s));
+    }
     if (roots) HIP_TRY(ctx, launch_fill_u8(roots, 0, n, s));
     HIP_TRY(ctx, compact_u32_eq(ws.T, kIn, n, ws.list, sc + kS_Count1, ws.blocksum, s));
     HIP_TRY(ctx, launch_label_roots(n, g->row_ptr, g->col, ws.list, sc + kS_Count1, nullptr, false,

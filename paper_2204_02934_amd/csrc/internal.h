@@ -314,6 +314,22 @@ int64_t status_blocks(int64_t n);
 hipError_t launch_status(int64_t n, const uint32_t *T, uint8_t *status, uint32_t *blocksum,
                          uint32_t *d_total, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
+// up to kFillSpans fills of 32-bit words (p[k][0 .. n[k]) = v[k]) in one launch
+constexpr int kFillSpans = 4;
+struct FillSpans {
+    uint32_t *p[kFillSpans];
+    uint32_t v[kFillSpans];
+    int64_t n[kFillSpans];
+    int k = 0;
+    void add(uint32_t *ptr, uint32_t value, int64_t count) {
+        if (count <= 0) return;
+        p[k] = ptr;
+        v[k] = value;
+        n[k] = count;
+        k++;
+    }
+};
+hipError_t launch_fill_spans(const FillSpans &f, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t count, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, uint8_t value, int64_t count, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long value, int64_t count,

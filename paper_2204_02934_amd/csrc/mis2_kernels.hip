@@ -1230,6 +1230,24 @@ __global__ __launch_bounds__(kBlock) void k_fill(V *__restrict__ p, V value, int
         p[i] = value;
 }
 
+// Up to kFillSpans fills of 32-bit words in one launch (one dispatch instead
+// of one per array at the start of a run).
+__global__ __launch_bounds__(kBlock) void k_fill_spans(FillSpans f) {
+    int64_t total = 0;
+    for (int k = 0; k < f.k; k++) total += f.n[k];
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * kBlock) {
+        int64_t o = t;
+        int k = 0;  // the span of word t (a fixed trip count: no early exit)
+        for (int q = 0; q + 1 < kFillSpans; q++)
+            if (k == q && q + 1 < f.k && o >= f.n[q]) {
+                o -= f.n[q];
+                k = q + 1;
+            }
+        f.p[k][o] = f.v[k];
+    }
+}
+
 // CSR checks: bit 0 row_ptr[0] != 0, bit 1 decreasing or out-of-range
 // row_ptr, bit 2 row_ptr[n] != nnz, bit 3 column out of range, bit 4
 // self-loop.
@@ -1608,6 +1626,14 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_for(count, kBlock, 8192)), dim3(kBlock), 0, s,
                        p, value, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_spans(const FillSpans &f, hipStream_t s) {
+    int64_t total = 0;
+    for (int k = 0; k < f.k; k++) total += f.n[k];
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_spans, dim3(grid_for(total, kBlock, 8192)), dim3(kBlock), 0, s, f);
     return hipGetLastError();
 }
 
