@@ -301,3 +301,20 @@ def test_workspace_too_small(api):
     assert b"workspace" in c.lib.mis2_last_error(c.ptr)
     with pytest.raises(Mis2Error):
         c.set_option(_lib.MIS2_OPT_LANES_PER_ROW, 3)
+
+
+@pytest.mark.parametrize("k", [12, 17, 20])
+def test_tuple_width_boundaries(ctx, k):
+    # b = the smallest integer with 2^b >= n + 2 grows by one from n = 2^k - 2
+    # to n = 2^k - 1, and the priority field shrinks by one bit: sizes on
+    # both sides, on paths and on power-law graphs
+    for n in (2 ** k - 3, 2 ** k - 2, 2 ** k - 1, 2 ** k):
+        _say("tuple width", k, n)
+        gs = [("path", graphs.path(n))]
+        if k < 20:
+            gs.append(("chunglu", graphs.chung_lu(n, 8.0, 2.1, 200, seed=k)))
+        for name, (rp, c) in gs:
+            _check_mis2(ctx, rp, c, 3, "%s %d" % (name, n))
+            agg, na = ctx.aggregate(rp, c, 3)
+            oa, ona = oracle.aggregate(rp, c, 3)
+            assert na == ona and np.array_equal(agg.cpu().numpy(), oa), (name, n)
