@@ -80,6 +80,89 @@ __device__ __forceinline__ int coarse_slot(const int32_t *cs, int d, int top, in
     return -1;
 }
 
+// Lane l's view of lane l ^ J (32-bit), in registers where the pattern allows:
+// DPP quad permutes for 1 and 2, DPP row shifts (lane l reads l + J, or l - J)
+// for 4 and 8, a swizzle within 32 lanes for 16, a permute for 32.
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t x, int lane) {
+    if constexpr (J == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
+    } else if constexpr (J == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
+    } else if constexpr (J == 4 || J == 8) {
+        const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x100 + J, 0xF, 0xF, false);
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x110 + J, 0xF, 0xF, false);
+        return (lane & J) ? dn : up;
+    } else if constexpr (J == 16) {
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, (16 << 10) | 0x1F);
+    } else {
+        return (uint32_t)__shfl_xor((int)x, J, 64);
+    }
+}
+
+// lane l's view of lane l + 1 (wave_shl1) and of lane l - 1 (wave_shr1)
+__device__ __forceinline__ uint32_t from_next(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x130, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t from_prev(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x138, 0xF, 0xF, false);
+}
+
+template <int K, int J>
+__device__ __forceinline__ uint32_t bitonic_step(uint32_t key, int lane) {
+    const uint32_t other = lane_xor<J>(key, lane);
+    const bool keep_min = ((lane & J) == 0) == ((lane & K) == 0);
+    return keep_min ? (key < other ? key : other) : (key > other ? key : other);
+}
+
+template <int K, int J>
+__device__ __forceinline__ uint32_t bitonic_merge(uint32_t key, int lane) {
+    key = bitonic_step<K, J>(key, lane);
+    if constexpr (J > 1) key = bitonic_merge<K, J / 2>(key, lane);
+    return key;
+}
+
+// The 32-bit form of fold_chunk below, with register cross-lane moves.
+__device__ __forceinline__ void fold_chunk32(int p, double v, int d, double *acc, double *accd,
+                                             int lane) {
+#pragma clang fp contract(off)
+    uint32_t key = p >= 0 ? ((uint32_t)p << 6) | (uint32_t)lane : ~0u;
+    key = bitonic_merge<2, 1>(key, lane);
+    key = bitonic_merge<4, 2>(key, lane);
+    key = bitonic_merge<8, 4>(key, lane);
+    key = bitonic_merge<16, 8>(key, lane);
+    key = bitonic_merge<32, 16>(key, lane);
+    key = bitonic_merge<64, 32>(key, lane);
+    const bool valid = key != ~0u;
+    const int sp = valid ? (int)(key >> 6) : -1;
+    const double sv = __shfl(v, (int)(key & 63), 64);
+    const int prev = (int)from_prev((uint32_t)sp);
+    const bool head = valid && (lane == 0 || prev != sp);
+    const uint64_t heads = __ballot(head) | __ballot(!valid);
+    const uint64_t after = lane == 63 ? 0ull : heads & (~0ull << (lane + 1));
+    const int run = head ? (after ? __ffsll((unsigned long long)after) - 1 : 64) - lane : 0;
+    uint32_t lg = (uint32_t)run;
+    lg = max(lg, lane_xor<1>(lg, lane));
+    lg = max(lg, lane_xor<2>(lg, lane));
+    lg = max(lg, lane_xor<4>(lg, lane));
+    lg = max(lg, lane_xor<8>(lg, lane));
+    lg = max(lg, lane_xor<16>(lg, lane));
+    lg = max(lg, lane_xor<32>(lg, lane));
+    const int longest = (int)__builtin_amdgcn_readfirstlane(lg);
+    double my = head ? (sp == d ? *accd : acc[sp]) : 0.0;
+    uint32_t lo = __double2loint(sv), hi = __double2hiint(sv);  // lane l: item l + j
+    for (int j = 0; j < longest; j++) {
+        const double sum = my + __hiloint2double((int)hi, (int)lo);
+        my = j < run ? sum : my;
+        lo = from_next(lo);
+        hi = from_next(hi);
+    }
+    if (head) {
+        if (sp == d) *accd = my;
+        else acc[sp] = my;
+    }
+}
+
 // Folds a chunk (lane q: slot p, -1 for none, d for the diagonal; value v) into
 // the accumulators in lane order.  The chunk is sorted by (slot, lane) with a
 // 64-lane bitonic network, so each slot's items form one run of lanes, still
@@ -200,11 +283,11 @@ __global__ __launch_bounds__(kBlock) void k_galerkin(
                     if (bb != (int32_t)a) pb = coarse_slot(cs, d, top, bb, &missing);
                 }
             }
-            if (narrow) fold_chunk<uint32_t>(pa, va, d, acc, accd, lane);
+            if (narrow) fold_chunk32(pa, va, d, acc, accd, lane);
             else fold_chunk<uint64_t>(pa, va, d, acc, accd, lane);
             wave_sync();
             if (t0 + 64 < total) {
-                if (narrow) fold_chunk<uint32_t>(pb, vb, d, acc, accd, lane);
+                if (narrow) fold_chunk32(pb, vb, d, acc, accd, lane);
                 else fold_chunk<uint64_t>(pb, vb, d, acc, accd, lane);
                 wave_sync();
             }
