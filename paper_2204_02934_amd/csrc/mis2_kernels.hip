@@ -50,6 +50,89 @@ __device__ __forceinline__ uint64_t lanes_below(int lane) {
 // Global wavefront id with the XCD-aware block order: workgroups are handed to
 // the 8 XCDs round-robin, so logical block (b % 8) * (B / 8) + b / 8 gives
 // each XCD a contiguous run of logical blocks (when B is a multiple of 8).
+// Lane l's view of lane l ^ J (32-bit) in registers where the pattern allows
+// (an LDS permute costs a round trip per step of a reduction): DPP quad
+// permutes for 1 and 2, DPP row shifts (lane l reads l + J, or l - J) for 4
+// and 8, a swizzle within 32 lanes for 16, a permute for 32.
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t x) {
+    if constexpr (J == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
+    } else if constexpr (J == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
+    } else if constexpr (J == 4 || J == 8) {
+        const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x100 + J, 0xF, 0xF, false);
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x110 + J, 0xF, 0xF, false);
+        return (threadIdx.x & J) ? dn : up;
+    } else if constexpr (J == 16) {
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, (16 << 10) | 0x1F);
+    } else {
+        return (uint32_t)__shfl_xor((int)x, J, 64);
+    }
+}
+
+// min, or and and over aligned groups of L lanes (L a power of two <= 64)
+template <int L>
+__device__ __forceinline__ uint32_t group_min(uint32_t x) {
+    if constexpr (L >= 64) x = min(x, lane_xor<32>(x));
+    if constexpr (L >= 32) x = min(x, lane_xor<16>(x));
+    if constexpr (L >= 16) x = min(x, lane_xor<8>(x));
+    if constexpr (L >= 8) x = min(x, lane_xor<4>(x));
+    if constexpr (L >= 4) x = min(x, lane_xor<2>(x));
+    if constexpr (L >= 2) x = min(x, lane_xor<1>(x));
+    return x;
+}
+
+template <int L>
+__device__ __forceinline__ uint32_t group_or(uint32_t x) {
+    if constexpr (L >= 64) x |= lane_xor<32>(x);
+    if constexpr (L >= 32) x |= lane_xor<16>(x);
+    if constexpr (L >= 16) x |= lane_xor<8>(x);
+    if constexpr (L >= 8) x |= lane_xor<4>(x);
+    if constexpr (L >= 4) x |= lane_xor<2>(x);
+    if constexpr (L >= 2) x |= lane_xor<1>(x);
+    return x;
+}
+
+template <int L>
+__device__ __forceinline__ uint32_t group_sum(uint32_t x) {
+    if constexpr (L >= 64) x += lane_xor<32>(x);
+    if constexpr (L >= 32) x += lane_xor<16>(x);
+    if constexpr (L >= 16) x += lane_xor<8>(x);
+    if constexpr (L >= 8) x += lane_xor<4>(x);
+    if constexpr (L >= 4) x += lane_xor<2>(x);
+    if constexpr (L >= 2) x += lane_xor<1>(x);
+    return x;
+}
+
+template <int J>
+__device__ __forceinline__ int64_t lane_xor64(int64_t x) {
+    const uint32_t lo = lane_xor<J>((uint32_t)(uint64_t)x);
+    const uint32_t hi = lane_xor<J>((uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int64_t wave_max64(int64_t m) {
+    m = max(m, lane_xor64<32>(m));
+    m = max(m, lane_xor64<16>(m));
+    m = max(m, lane_xor64<8>(m));
+    m = max(m, lane_xor64<4>(m));
+    m = max(m, lane_xor64<2>(m));
+    m = max(m, lane_xor64<1>(m));
+    return m;
+}
+
+template <int L>
+__device__ __forceinline__ uint32_t group_and(uint32_t x) {
+    if constexpr (L >= 64) x &= lane_xor<32>(x);
+    if constexpr (L >= 32) x &= lane_xor<16>(x);
+    if constexpr (L >= 16) x &= lane_xor<8>(x);
+    if constexpr (L >= 8) x &= lane_xor<4>(x);
+    if constexpr (L >= 4) x &= lane_xor<2>(x);
+    if constexpr (L >= 2) x &= lane_xor<1>(x);
+    return x;
+}
+
 __device__ __forceinline__ int64_t wave_id() {
     const int64_t B = gridDim.x;
     const int64_t b = blockIdx.x;
@@ -154,9 +237,7 @@ __device__ __forceinline__ void seg_finish(const SegIO &io, int64_t w, uint32_t 
 // Sum of the kSplit counters of one list (wavefront 0 of the workgroup; the
 // result is in every lane of that wavefront).
 __device__ __forceinline__ uint32_t ctr_sum(const uint32_t *list) {
-    uint32_t x = list[(threadIdx.x & 63u) * kCtrLine];
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
+    return group_sum<64>(list[(threadIdx.x & 63u) * kCtrLine]);
 }
 
 // Workgroup 0 clears the counter slot of round r + 2 at the start of round
@@ -174,8 +255,7 @@ __device__ __forceinline__ int64_t wave_max_len(const int64_t (&s)[U], const int
     int64_t m = 0;
 #pragma unroll
     for (int u = 0; u < U; u++) m = max(m, e[u] - s[u]);
-    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
-    return m;
+    return wave_max64(m);
 }
 
 // The U rows of this lane group for the step starting at row i0 of the
@@ -251,8 +331,7 @@ __device__ __forceinline__ uint32_t coop_min_T(const int32_t *col, const uint32_
         }
     }
     if (written) *written = wc;
-    for (int off = 32; off > 0; off >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, off, 64));
-    return m;
+    return group_min<64>(m);
 }
 
 // Any M_w == OUT and all M_w in {t0, absent} over [s, e), by the whole wavefront.
@@ -279,12 +358,8 @@ __device__ __forceinline__ void coop_decide(const int32_t *__restrict__ col,
             }
         }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        ao |= __shfl_xor(ao, off, 64);
-        ae &= __shfl_xor(ae, off, 64);
-    }
-    any_out = ao;
-    all_eq = ae;
+    any_out = (int)group_or<64>((uint32_t)ao);
+    all_eq = (int)group_and<64>((uint32_t)ae);
 }
 
 // Refresh Column over the wavefront's segment: U rows per lane group per
@@ -428,9 +503,7 @@ __device__ __forceinline__ uint32_t sweep_column(const int64_t *__restrict__ row
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
-#pragma unroll
-            for (int off = L / 2; off > 0; off >>= 1)
-                m[u] = min(m[u], (uint32_t)__shfl_xor((int)m[u], off, L));
+            m[u] = group_min<L>(m[u]);
             bool keep = false;
             if (ok[u] && sub == 0) {
                 if (m[u] == kIn) m[u] = kOut;
@@ -570,11 +643,8 @@ __device__ __forceinline__ uint32_t sweep_decide(const int64_t *__restrict__ row
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
-#pragma unroll
-            for (int off = L / 2; off > 0; off >>= 1) {
-                any_out[u] |= __shfl_xor(any_out[u], off, L);
-                all_eq[u] &= __shfl_xor(all_eq[u], off, L);
-            }
+            any_out[u] = group_or<L>((uint32_t)any_out[u]);
+            all_eq[u] = group_and<L>((uint32_t)all_eq[u]);
             bool keep = false;
             if (ok[u] && sub == 0) {
                 uint32_t nt;
