@@ -281,7 +281,7 @@ def kernel_sources_digest():
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2204_02934_amd", "csrc")
-    files = [os.path.join(csrc, f) for f in ("abi.hip", "internal.h", "mis2_kernels.hip")]
+    files = [os.path.join(csrc, f) for f in ("abi.hip", "internal.h", "lanes.h", "mis2_kernels.hip")]
     for f in files:
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode())

@@ -8,6 +8,7 @@
 // phase 2 (the "tentative" labels) and writes a separate output array, so
 // every row is decided independently.
 #include "internal.h"
+#include "lanes.h"
 
 namespace mis2 {
 
@@ -54,8 +55,7 @@ __device__ __forceinline__ int coop_label(const int32_t *__restrict__ col,
             }
         }
     }
-    for (int off = 32; off > 0; off >>= 1) took += __shfl_xor(took, off, 64);
-    return took;
+    return group_sum_i<64>(took);
 }
 
 // roots[0..*d_count) get ids base + k; their neighbours (all of them, or only
@@ -109,8 +109,7 @@ __global__ __launch_bounds__(kBlock) void k_label_roots(const int64_t *__restric
                 took++;
             }
         }
-#pragma unroll
-        for (int off = L / 2; off > 0; off >>= 1) took += __shfl_xor(took, off, L);
+        took = group_sum_i<L>(took);
         if (ok && sub == 0) {
             label[r] = id;
             aggsize[id] = 1 + took + heavy_took;
@@ -157,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_accept_phase2(int64_t n,
                 for (int k = 0; k < kCoopLoads; k++)
                     cnt += (b + (int64_t)k * 64 + lane < e) & (lb[k] == -1);
             }
-            for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+            cnt = group_sum_i<64>(cnt);
             if (lane == t) f = cnt >= 2;
         }
         if (v < n) flag[v] = f;
@@ -207,6 +206,28 @@ __device__ __forceinline__ bool better(int c1, int s1, int a1, int c2, int s2, i
     if (c1 != c2) return c1 > c2;
     if (s1 != s2) return s1 < s2;
     return a1 < a2;
+}
+
+// The best (coupling, size, id) candidate over each aligned group of L lanes,
+// in every lane of the group.
+template <int J>
+__device__ __forceinline__ void p3_best_step(int &bc, int &bs, int &ba) {
+    const int oc = lane_xor_i<J>(bc), os = lane_xor_i<J>(bs), oa = lane_xor_i<J>(ba);
+    if (better(oc, os, oa, bc, bs, ba)) {
+        bc = oc;
+        bs = os;
+        ba = oa;
+    }
+}
+
+template <int L>
+__device__ __forceinline__ void p3_group_best(int &bc, int &bs, int &ba) {
+    if constexpr (L >= 64) p3_best_step<32>(bc, bs, ba);
+    if constexpr (L >= 32) p3_best_step<16>(bc, bs, ba);
+    if constexpr (L >= 16) p3_best_step<8>(bc, bs, ba);
+    if constexpr (L >= 8) p3_best_step<4>(bc, bs, ba);
+    if constexpr (L >= 4) p3_best_step<2>(bc, bs, ba);
+    if constexpr (L >= 2) p3_best_step<1>(bc, bs, ba);
 }
 
 constexpr int32_t kPad = -2;  // label of a padding lane; never equals an aggregate id
@@ -289,21 +310,10 @@ __global__ __launch_bounds__(kBlock) void k_phase3(const int64_t *__restrict__ r
         }
         const bool is_long = e - s > (int64_t)K * L;
         const int64_t es = is_long ? s : e;  // long rows are left to k_phase3_long
-        int64_t wmax = (es - s + L - 1) / L;
-        for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off, 64));
+        const int64_t wmax = group_max64<64>((es - s + L - 1) / L);
         int bc = 0, bs = 0x7FFFFFFF, ba = 0x7FFFFFFF;
         if (wmax > 0) p3_short<L, K>(col, label, aggsize, s, es, sub, bc, bs, ba);
-#pragma unroll
-        for (int off = L / 2; off > 0; off >>= 1) {
-            const int oc = __shfl_xor(bc, off, L);
-            const int os = __shfl_xor(bs, off, L);
-            const int oa = __shfl_xor(ba, off, L);
-            if (better(oc, os, oa, bc, bs, ba)) {
-                bc = oc;
-                bs = os;
-                ba = oa;
-            }
-        }
+        p3_group_best<L>(bc, bs, ba);
         if (valid && sub == 0 && !is_long) {
             if (bc > 0)
                 agg_out[v] = ba;
@@ -327,16 +337,7 @@ constexpr int kP3Slots = 2048;
 __device__ __forceinline__ uint32_t p3hash(uint32_t a) { return (a * 2654435761u) >> 21; }
 
 __device__ __forceinline__ void p3_reduce(int &bc, int &bs, int &ba) {
-    for (int off = 32; off > 0; off >>= 1) {
-        const int oc = __shfl_xor(bc, off, 64);
-        const int os = __shfl_xor(bs, off, 64);
-        const int oa = __shfl_xor(ba, off, 64);
-        if (better(oc, os, oa, bc, bs, ba)) {
-            bc = oc;
-            bs = os;
-            ba = oa;
-        }
-    }
+    p3_group_best<64>(bc, bs, ba);
 }
 
 __global__ __launch_bounds__(kBlock) void k_phase3_long(const int64_t *__restrict__ row_ptr,
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(kBlock) void k_phase3_long(const int64_t *__restric
                 for (int64_t c2 = s; c2 < e; c2 += 64) {
                     const int64_t j2 = c2 + lane;
                     const int32_t a2 = j2 < e ? label[col[j2]] : kPad;
-                    for (int t = 0; t < 64; t++) cnt += (__shfl(a2, t, 64) == a);
+                    for (int t = 0; t < 64; t++) cnt += (__builtin_amdgcn_readlane(a2, t) == a);
                 }
                 if (a >= 0) {
                     const int sz = aggsize[a];
@@ -463,8 +464,7 @@ __device__ __forceinline__ uint32_t coop_min_label(const int32_t *__restrict__ c
         for (int k = 0; k < kCoopLoads; k++)
             if (b + (int64_t)k * 64 + lane < e) m = min(m, a[k]);
     }
-    for (int off = 32; off > 0; off >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, off, 64));
-    return m;
+    return group_min<64>(m);
 }
 
 // One group of L lanes per row of the wavefront's segment of io.wl_in (the
@@ -504,8 +504,7 @@ __global__ __launch_bounds__(kBlock) void k_join_min(const int64_t *__restrict__
                 e = s;  // its group skips the row below
             }
         }
-        int64_t wmax = e - s;
-        for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off, 64));
+        const int64_t wmax = group_max64<64>(e - s);
         for (int64_t c0 = 0; c0 < wmax; c0 += (int64_t)L * K) {
             int32_t x[K];
 #pragma unroll
@@ -520,9 +519,7 @@ __global__ __launch_bounds__(kBlock) void k_join_min(const int64_t *__restrict__
             for (int k = 0; k < K; k++)
                 if (s + c0 + k * L + sub < e) m = min(m, a[k]);
         }
-#pragma unroll
-        for (int off = L / 2; off > 0; off >>= 1)
-            m = min(m, (uint32_t)__shfl_xor((int)m, off, L));
+        m = group_min<L>(m);
         if (valid && sub == 0) {
             if (m == 0xFFFFFFFFu)
                 atomicOr(err, 2u);

@@ -25,6 +25,7 @@
 // the coarse row's columns) live in LDS for rows of at most kGCap columns,
 // else in the output arrays themselves.  A final pass does the division.
 #include "internal.h"
+#include "lanes.h"
 
 namespace mis2 {
 
@@ -80,37 +81,9 @@ __device__ __forceinline__ int coarse_slot(const int32_t *cs, int d, int top, in
     return -1;
 }
 
-// Lane l's view of lane l ^ J (32-bit), in registers where the pattern allows:
-// DPP quad permutes for 1 and 2, DPP row shifts (lane l reads l + J, or l - J)
-// for 4 and 8, a swizzle within 32 lanes for 16, a permute for 32.
-template <int J>
-__device__ __forceinline__ uint32_t lane_xor(uint32_t x, int lane) {
-    if constexpr (J == 1) {
-        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
-    } else if constexpr (J == 2) {
-        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
-    } else if constexpr (J == 4 || J == 8) {
-        const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x100 + J, 0xF, 0xF, false);
-        const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x110 + J, 0xF, 0xF, false);
-        return (lane & J) ? dn : up;
-    } else if constexpr (J == 16) {
-        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, (16 << 10) | 0x1F);
-    } else {
-        return (uint32_t)__shfl_xor((int)x, J, 64);
-    }
-}
-
-// lane l's view of lane l + 1 (wave_shl1) and of lane l - 1 (wave_shr1)
-__device__ __forceinline__ uint32_t from_next(uint32_t x) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x130, 0xF, 0xF, false);
-}
-__device__ __forceinline__ uint32_t from_prev(uint32_t x) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x138, 0xF, 0xF, false);
-}
-
 template <int K, int J>
 __device__ __forceinline__ uint32_t bitonic_step(uint32_t key, int lane) {
-    const uint32_t other = lane_xor<J>(key, lane);
+    const uint32_t other = lane_xor<J>(key);
     const bool keep_min = ((lane & J) == 0) == ((lane & K) == 0);
     return keep_min ? (key < other ? key : other) : (key > other ? key : other);
 }
@@ -141,14 +114,7 @@ __device__ __forceinline__ void fold_chunk32(int p, double v, int d, double *acc
     const uint64_t heads = __ballot(head) | __ballot(!valid);
     const uint64_t after = lane == 63 ? 0ull : heads & (~0ull << (lane + 1));
     const int run = head ? (after ? __ffsll((unsigned long long)after) - 1 : 64) - lane : 0;
-    uint32_t lg = (uint32_t)run;
-    lg = max(lg, lane_xor<1>(lg, lane));
-    lg = max(lg, lane_xor<2>(lg, lane));
-    lg = max(lg, lane_xor<4>(lg, lane));
-    lg = max(lg, lane_xor<8>(lg, lane));
-    lg = max(lg, lane_xor<16>(lg, lane));
-    lg = max(lg, lane_xor<32>(lg, lane));
-    const int longest = (int)__builtin_amdgcn_readfirstlane(lg);
+    const int longest = (int)__builtin_amdgcn_readfirstlane(group_max<64>((uint32_t)run));
     double my = head ? (sp == d ? *accd : acc[sp]) : 0.0;
     uint32_t lo = __double2loint(sv), hi = __double2hiint(sv);  // lane l: item l + j
     for (int j = 0; j < longest; j++) {

@@ -25,6 +25,7 @@
 #include <hip/hip_ext.h>
 
 #include "internal.h"
+#include "lanes.h"
 
 namespace mis2 {
 
@@ -50,89 +51,6 @@ __device__ __forceinline__ uint64_t lanes_below(int lane) {
 // Global wavefront id with the XCD-aware block order: workgroups are handed to
 // the 8 XCDs round-robin, so logical block (b % 8) * (B / 8) + b / 8 gives
 // each XCD a contiguous run of logical blocks (when B is a multiple of 8).
-// Lane l's view of lane l ^ J (32-bit) in registers where the pattern allows
-// (an LDS permute costs a round trip per step of a reduction): DPP quad
-// permutes for 1 and 2, DPP row shifts (lane l reads l + J, or l - J) for 4
-// and 8, a swizzle within 32 lanes for 16, a permute for 32.
-template <int J>
-__device__ __forceinline__ uint32_t lane_xor(uint32_t x) {
-    if constexpr (J == 1) {
-        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
-    } else if constexpr (J == 2) {
-        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
-    } else if constexpr (J == 4 || J == 8) {
-        const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x100 + J, 0xF, 0xF, false);
-        const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x110 + J, 0xF, 0xF, false);
-        return (threadIdx.x & J) ? dn : up;
-    } else if constexpr (J == 16) {
-        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, (16 << 10) | 0x1F);
-    } else {
-        return (uint32_t)__shfl_xor((int)x, J, 64);
-    }
-}
-
-// min, or and and over aligned groups of L lanes (L a power of two <= 64)
-template <int L>
-__device__ __forceinline__ uint32_t group_min(uint32_t x) {
-    if constexpr (L >= 64) x = min(x, lane_xor<32>(x));
-    if constexpr (L >= 32) x = min(x, lane_xor<16>(x));
-    if constexpr (L >= 16) x = min(x, lane_xor<8>(x));
-    if constexpr (L >= 8) x = min(x, lane_xor<4>(x));
-    if constexpr (L >= 4) x = min(x, lane_xor<2>(x));
-    if constexpr (L >= 2) x = min(x, lane_xor<1>(x));
-    return x;
-}
-
-template <int L>
-__device__ __forceinline__ uint32_t group_or(uint32_t x) {
-    if constexpr (L >= 64) x |= lane_xor<32>(x);
-    if constexpr (L >= 32) x |= lane_xor<16>(x);
-    if constexpr (L >= 16) x |= lane_xor<8>(x);
-    if constexpr (L >= 8) x |= lane_xor<4>(x);
-    if constexpr (L >= 4) x |= lane_xor<2>(x);
-    if constexpr (L >= 2) x |= lane_xor<1>(x);
-    return x;
-}
-
-template <int L>
-__device__ __forceinline__ uint32_t group_sum(uint32_t x) {
-    if constexpr (L >= 64) x += lane_xor<32>(x);
-    if constexpr (L >= 32) x += lane_xor<16>(x);
-    if constexpr (L >= 16) x += lane_xor<8>(x);
-    if constexpr (L >= 8) x += lane_xor<4>(x);
-    if constexpr (L >= 4) x += lane_xor<2>(x);
-    if constexpr (L >= 2) x += lane_xor<1>(x);
-    return x;
-}
-
-template <int J>
-__device__ __forceinline__ int64_t lane_xor64(int64_t x) {
-    const uint32_t lo = lane_xor<J>((uint32_t)(uint64_t)x);
-    const uint32_t hi = lane_xor<J>((uint32_t)((uint64_t)x >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-__device__ __forceinline__ int64_t wave_max64(int64_t m) {
-    m = max(m, lane_xor64<32>(m));
-    m = max(m, lane_xor64<16>(m));
-    m = max(m, lane_xor64<8>(m));
-    m = max(m, lane_xor64<4>(m));
-    m = max(m, lane_xor64<2>(m));
-    m = max(m, lane_xor64<1>(m));
-    return m;
-}
-
-template <int L>
-__device__ __forceinline__ uint32_t group_and(uint32_t x) {
-    if constexpr (L >= 64) x &= lane_xor<32>(x);
-    if constexpr (L >= 32) x &= lane_xor<16>(x);
-    if constexpr (L >= 16) x &= lane_xor<8>(x);
-    if constexpr (L >= 8) x &= lane_xor<4>(x);
-    if constexpr (L >= 4) x &= lane_xor<2>(x);
-    if constexpr (L >= 2) x &= lane_xor<1>(x);
-    return x;
-}
-
 __device__ __forceinline__ int64_t wave_id() {
     const int64_t B = gridDim.x;
     const int64_t b = blockIdx.x;
@@ -255,7 +173,7 @@ __device__ __forceinline__ int64_t wave_max_len(const int64_t (&s)[U], const int
     int64_t m = 0;
 #pragma unroll
     for (int u = 0; u < U; u++) m = max(m, e[u] - s[u]);
-    return wave_max64(m);
+    return group_max64<64>(m);
 }
 
 // The U rows of this lane group for the step starting at row i0 of the
