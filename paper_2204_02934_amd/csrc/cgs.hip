@@ -15,6 +15,7 @@
 // vertices picked in one round are never adjacent (each would be below the
 // other), so a round reads only colours fixed in earlier rounds.
 #include "internal.h"
+#include "lanes.h"
 
 namespace mis2 {
 
@@ -319,11 +320,10 @@ __global__ __launch_bounds__(kBlock, 6) void k_cgs_cluster(const int64_t *__rest
         const double bi = valid ? b[i] : 0.0;
         const double di = valid ? diag[i] : 1.0;
         const double xo = valid ? x[i] : 0.0;
-        int64_t incl = len;
-        for (int d = 1; d < 64; d <<= 1) {
-            const int64_t o = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += o;
-        }
+        // prefix of the lengths, each clamped to kCgsCap + 1: only prefixes up
+        // to kCgsCap are used, and those are exact
+        const int64_t incl =
+            (int64_t)wave_incl_scan((uint32_t)(len < kCgsCap + 1 ? len : kCgsCap + 1));
         // rows before the first one longer than 64, within kCgsCap entries
         const uint64_t longm = __ballot(valid && len > 64);
         const int first_long = longm ? __ffsll((unsigned long long)longm) - 1 : 64;

@@ -53,6 +53,19 @@ __device__ __forceinline__ uint32_t from_prev(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x138, 0xF, 0xF, false);
 }
 
+// Inclusive prefix sum over the 64 lanes: sums within each row of 16 lanes by
+// row shifts (lanes shifted in from outside the row read 0), then the totals
+// of rows 0 and 2 broadcast into rows 1 and 3, and that of rows 0-1 into 2-3.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);   // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);   // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);   // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);   // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return x;
+}
+
 // Reductions over aligned groups of L lanes (L a power of two <= 64); every
 // lane of a group gets the group's result.
 #define MIS2_GROUP_REDUCE(NAME, T, XOR, OP)                    \
