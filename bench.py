@@ -16,7 +16,9 @@ largest share of GPU time, its algorithmic bytes per launch (exact, from an
 untimed accounting run: 4 B per visited column index, 20 B (Refresh Column)
 or 24 B (Decide Set) per worklist row, 4 B per row kept) over its mean launch
 duration from HIP events recorded on the library's stream in a second timed
-loop.  cpu_baseline: the CPU oracle on the host, one thread.
+loop.  cpu_baseline: the CPU oracle on the host, one thread (median of 5
+steps after a warm-up), with the host's CPU model and core counts and the
+OpenMP build of the same oracle on every usable core beside it.
 """
 import argparse
 import json
@@ -340,6 +342,79 @@ def gather_bytes(rec):
     (4 per visited edge) instead of the compulsory first touch counted in
     sweep_bytes: the upper-bound variant of the algorithmic model."""
     return 4 * rec["edges"] if rec["kind"] in (0, 1) else 0
+
+
+def host_cpu():
+    """The host's CPU model, sockets, physical cores and logical CPUs (from
+    /proc/cpuinfo) and the CPUs this process may run on."""
+    model, sockets, cores, logical = None, set(), set(), 0
+    phys = core = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "processor":
+                    logical += 1
+                elif k == "model name" and model is None:
+                    model = v
+                elif k == "physical id":
+                    phys = v
+                    sockets.add(v)
+                elif k == "core id":
+                    core = v
+                    cores.add((phys, core))
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "sockets": len(sockets) or None,
+            "physical_cores": len(cores) or None, "logical_cpus": logical or os.cpu_count(),
+            "usable_cpus": usable}
+
+
+def cpu_baseline(rp_h, col_h, seed, agg_call, nnz, agg_name, reps=5):
+    """The oracle (oracle/oracle.c as it stands) timed on the host: one
+    warm-up, then the median of `reps` full steps (MIS-2 + aggregation of the
+    same graph), single-threaded; and the OpenMP build of the same source
+    (its pure-map phase loops on every usable host CPU, OMP_NUM_THREADS when
+    set) timed the same way."""
+    import numpy as np
+    import oracle
+
+    def timed():
+        ts = []
+        for i in range(reps + 1):
+            t0 = time.perf_counter()
+            oracle.mis2(rp_h, col_h, seed)
+            getattr(oracle, agg_call)(rp_h, col_h, seed)
+            if i:
+                ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    host = host_cpu()
+    t1 = timed()
+    log("cpu oracle, 1 thread: %.3f s/step" % t1)
+    out = {"value": nnz / t1, "unit": "nnz/s", "cores": 1, "kind": "oracle",
+           "sample": "median of %d full steps (MIS-2 + %s) of the same graph after 1 warm-up, "
+                     "%.3f s each, one thread" % (reps, agg_name, t1),
+           "host": host}
+    threads = int(os.environ.get("OMP_NUM_THREADS") or host["usable_cpus"] or 1)
+    try:
+        path = oracle.build_oracle(force=False, parallel=True)
+        os.environ["OMP_NUM_THREADS"] = str(threads)
+        with oracle.use_library(path):
+            tn = timed()
+        out["all_cores"] = {"value": nnz / tn, "unit": "nnz/s", "cores": threads,
+                            "s_per_step": tn,
+                            "build": "oracle.c with -DORACLE_OMP -fopenmp (Algorithm 1's "
+                                     "three phase loops in parallel; identical results)"}
+        log("cpu oracle, %d threads: %.3f s/step" % (threads, tn))
+    except Exception as e:  # no OpenMP toolchain: the single-thread figure stands alone
+        out["all_cores"] = {"error": str(e)}
+    return out
 
 
 def c5_pool(count, seed=3, n_lo=1_000, n_hi=10_000_000):
@@ -674,24 +749,13 @@ def main():
     del src, dst
     log("device copy ceiling: %.0f GB/s" % copy_gbps)
 
-    # CPU baseline: the oracle, single-threaded, on a bounded sample
+    # CPU baseline: the oracle on the host, median of 5 full steps after 1
+    # warm-up, single-threaded; beside it the OpenMP build of the same source
+    # on every usable host core
     cpu = None
     if not args.no_cpu:
-        import oracle
-        reps = 0
-        tc0 = time.perf_counter()
-        while True:
-            oracle.mis2(rp_h, col_h, args.seed)
-            getattr(oracle, agg_call)(rp_h, col_h, args.seed)
-            reps += 1
-            if time.perf_counter() - tc0 > 8.0 or reps >= 20:
-                break
-        tcpu = (time.perf_counter() - tc0) / reps
-        cpu = {"value": nnz / tcpu, "unit": "nnz/s", "cores": 1, "kind": "oracle",
-               "sample": "%d full steps (MIS-2 + %s) of the same graph, %.2f s each"
-                         % (reps, "aggregation" if args.aggregation == "alg3"
-                            else "basic coarsening", tcpu)}
-        log("cpu oracle: %.3f s/step" % tcpu)
+        cpu = cpu_baseline(rp_h, col_h, args.seed, agg_call, nnz,
+                           "aggregation" if args.aggregation == "alg3" else "basic coarsening")
 
     out = {
         "metric": "MIS-2+aggregation graph nnz/s and HBM GB/s fraction",

@@ -5,6 +5,7 @@ CPU-baseline leg of the benchmark, never by the product library.
 """
 from .oracle import (  # noqa: F401
     build_oracle,
+    use_library,
     xorshift64star,
     hash_priority,
     id_bits,

@@ -27,6 +27,16 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* The phase loops of Alg. 1 are pure maps (each writes only its own
+ * vertex's entry and reads only arrays the phase does not write), so a
+ * build with -DORACLE_OMP -fopenmp may run them on several threads with
+ * identical results; the default build is sequential. */
+#ifdef ORACLE_OMP
+#define ORACLE_PARALLEL_FOR _Pragma("omp parallel for schedule(static)")
+#else
+#define ORACLE_PARALLEL_FOR
+#endif
+
 #define ORACLE_IN  0u           /* Section V-C: IN is the value 0          */
 #define ORACLE_OUT 0xFFFFFFFFu  /* Section V-C: OUT is UINT_MAX (32 bits)  */
 
@@ -185,8 +195,9 @@ static int mis2_core(int64_t n, const int64_t *row_ptr, const int32_t *col,
         return -1;
     }
 
-    /* worklist1 <- 0..|V|, worklist2 <- 0..|V| (restricted to the subgraph).
-     * Inactive vertices are never touched and count as absent. */
+    /* Alg. 1, set-up: both worklists start as every vertex of the
+     * (sub)graph, in increasing id.  Inactive vertices are never touched
+     * and count as absent. */
     int64_t n1 = 0, n2 = 0;
     for (int64_t v = 0; v < n; v++) {
         T[v] = ORACLE_OUT;
@@ -210,12 +221,14 @@ static int mis2_core(int64_t n, const int64_t *row_ptr, const int32_t *col,
             trace[4 * iter + 3] = d2;
         }
 
-        /* Refresh Row: T_v <- h(iter, v) | v+1 for v in worklist1. */
+        /* Alg. 1, Refresh Row: every undecided vertex draws this round's
+         * hash priority and packs it above its id (Section V-C). */
+        if (prio && iter >= prio_rounds) { rc = -6; goto done; }
+        ORACLE_PARALLEL_FOR
         for (int64_t i = 0; i < n1; i++) {
             int64_t v = wl1[i];
             uint64_t p;
             if (prio) {
-                if (iter >= prio_rounds) { rc = -6; goto done; }
                 p = prio[(int64_t)iter * n + v];
             } else {
                 p = oracle_priority(seed, (uint64_t)iter, (uint64_t)v, pflags);
@@ -225,10 +238,12 @@ static int mis2_core(int64_t n, const int64_t *row_ptr, const int32_t *col,
         if (T_hist && iter < hist_cap)
             memcpy(T_hist + (int64_t)iter * n, T, sizeof(uint32_t) * (size_t)n);
 
-        /* Refresh Column: M_v <- min of T over the closed neighbourhood
-         * adj(v) + {v}; an IN minimum becomes OUT.
+        /* Alg. 1, Refresh Column: each vertex of worklist2 stores the
+         * smallest tuple of its closed neighbourhood (itself and its
+         * neighbours); when that smallest tuple is IN it stores OUT.
          * Reading: the neighbourhood includes v itself -- Fig. 1 shows
          * M = (1,1) at vertex 1, whose only neighbour carries (3,2). */
+        ORACLE_PARALLEL_FOR
         for (int64_t i = 0; i < n2; i++) {
             int64_t v = wl2[i];
             uint32_t m = T[v];
@@ -248,6 +263,7 @@ static int mis2_core(int64_t n, const int64_t *row_ptr, const int32_t *col,
          * some M_w is OUT then OUT, else if every M_w equals T_v then IN");
          * for an undecided t0 they cannot both hold.  Decide Set writes only
          * T_v and reads only M, so the order of this loop is immaterial. */
+        ORACLE_PARALLEL_FOR
         for (int64_t i = 0; i < n1; i++) {
             int64_t v = wl1[i];
             uint32_t t0 = T[v];
@@ -283,7 +299,7 @@ static int mis2_core(int64_t n, const int64_t *row_ptr, const int32_t *col,
         iter++;
     }
 
-    /* return {v : T_v = IN} */
+    /* The result: the vertices whose tuple ended IN. */
     for (int64_t v = 0; v < n; v++)
         status[v] = (uint8_t)((!active || active[v]) && T[v] == ORACLE_IN);
     *n_iters = iter;
@@ -344,8 +360,9 @@ int oracle_aggregate_ex(int64_t n, const int64_t *row_ptr, const int32_t *col,
     for (int64_t v = 0; v < n; v++) label[v] = -1;
     if (roots) memset(roots, 0, (size_t)n);
 
-    /* Phase 1: M1 <- MIS2(G); each root and its neighbours form an
-     * aggregate.  Reading: roots are numbered in increasing vertex id. */
+    /* Alg. 3, first phase: an MIS-2 of the whole graph; every root takes
+     * its neighbours into one aggregate.  Reading: roots are numbered in
+     * increasing vertex id. */
     int32_t it1 = 0;
     rc = oracle_mis2_ex(n, row_ptr, col, NULL, seed, NULL, 0, st1, &it1,
                         trace1, trace_cap, NULL, NULL, NULL, 0);
@@ -365,9 +382,9 @@ int oracle_aggregate_ex(int64_t n, const int64_t *row_ptr, const int32_t *col,
     }
     int64_t n1 = na;
 
-    /* Phase 2: M2 <- MIS2(G minus the aggregated vertices).
-     * Reading: the induced subgraph keeps the original vertex ids, the same
-     * b and restarts iter at 0. */
+    /* Alg. 3, second phase: an MIS-2 of the subgraph the first phase left
+     * unaggregated.  Reading: that subgraph keeps the original vertex ids
+     * and the same b, and its round counter starts again at 0. */
     int64_t unagg = 0;
     for (int64_t v = 0; v < n; v++) {
         act[v] = (uint8_t)(label[v] == -1);
@@ -400,9 +417,10 @@ int oracle_aggregate_ex(int64_t n, const int64_t *row_ptr, const int32_t *col,
     }
     int64_t n2 = na - n1;
 
-    /* Phase 3: tent <- labels (frozen); aggsize(a) and coupling(a, v) are
-     * taken over tent.  Each unaggregated v joins the aggregate with the
-     * largest coupling, a tie going to the smaller aggsize.
+    /* Alg. 3, third phase: the labels are copied and frozen; aggregate
+     * sizes and each leftover vertex's coupling to an aggregate are counted
+     * on that copy.  A leftover vertex joins the aggregate it shares the
+     * most edges with, a tie going to the smaller aggregate.
      * Reading: a remaining tie goes to the smaller aggregate id. */
     for (int64_t v = 0; v < n; v++) {
         tent[v] = label[v];
@@ -486,13 +504,13 @@ int oracle_aggregate_basic(int64_t n, const int64_t *row_ptr, const int32_t *col
     if (!st || !first) { rc = -1; goto done; }
     if (roots) memset(roots, 0, (size_t)n);
 
-    /* M <- MIS2(G) */
+    /* Alg. 2: an MIS-2 of the whole graph first. */
     int32_t it = 0;
     rc = oracle_mis2_ex(n, row_ptr, col, NULL, seed, NULL, 0, st, &it,
                         NULL, 0, NULL, NULL, NULL, 0);
     if (rc) goto done;
 
-    /* for v in M: build the aggregate from v and its neighbours */
+    /* Each root of that set forms an aggregate with its neighbours. */
     for (int64_t v = 0; v < n; v++) first[v] = -1;
     int64_t na = 0;
     for (int64_t v = 0; v < n; v++) {
@@ -596,9 +614,9 @@ int64_t oracle_quotient(int64_t n, const int64_t *row_ptr, const int32_t *col,
 /* h(seed, 0, v) (Sections V-A, V-C): each round every uncoloured vertex     */
 /* whose tuple is below those of all its uncoloured neighbours takes the     */
 /* smallest colour no coloured neighbour has.                                */
-/* Reading (update): the listing writes x_i <- r / A_ii with                 */
-/* r = b_i - A_i x; the Gauss-Seidel step it describes is                    */
-/* x_i <- (b_i - sum over j != i of A_ij x_j) / A_ii, summed in CSR order.   */
+/* Reading (update): the row step of Alg. 4 is the Gauss-Seidel update,     */
+/* the new x_i is b_i minus the off-diagonal products A_ij x_j (j != i,      */
+/* subtracted in CSR order), divided by A_ii.                                */
 /* Reading (order): rows of a cluster in increasing id; clusters of a colour */
 /* in increasing id; the symmetric sweep runs the reverse order afterwards   */
 /* (colours backward, rows of each cluster backward).                        */

@@ -25,17 +25,51 @@ _u64p = ctypes.POINTER(ctypes.c_uint64)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
 
 
-def build_oracle(force=True):
-    """Compile oracle.c with gcc into oracle/liboracle.so."""
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+
+
+def build_oracle(force=True, parallel=False):
+    """Compile oracle.c with gcc into oracle/liboracle.so (sequential, the
+    default) or, with parallel, into oracle/liboracle_omp.so with the pure-map
+    phase loops of Algorithm 1 under OpenMP (same results; used only to time
+    the oracle on every host core)."""
     global _lib
-    if not force and os.path.exists(_LIB):
-        return _LIB
-    tmp = _LIB + ".tmp%d" % os.getpid()
+    out = _LIB_OMP if parallel else _LIB
+    if not force and os.path.exists(out):
+        return out
+    tmp = out + ".tmp%d" % os.getpid()
+    extra = ["-DORACLE_OMP", "-fopenmp"] if parallel else []
     subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-Wall", "-Wextra", "-fPIC",
-                           "-shared", _SRC, "-o", tmp, "-lm"])
-    os.replace(tmp, _LIB)
-    _lib = None
-    return _LIB
+                           "-shared"] + extra + [_SRC, "-o", tmp, "-lm"])
+    os.replace(tmp, out)
+    if not parallel:
+        _lib = None
+    return out
+
+
+class use_library:
+    """Context manager: the oracle functions below call the build at `path`
+    (e.g. the OpenMP build) instead of the default one while it is active."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = _lib
+        os.environ["MIS2_ORACLE_LIB"], self.env = self.path, os.environ.get("MIS2_ORACLE_LIB")
+        _lib = None
+        _get()
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        if self.env is None:
+            os.environ.pop("MIS2_ORACLE_LIB", None)
+        else:
+            os.environ["MIS2_ORACLE_LIB"] = self.env
+        _lib = self.saved
+        return False
 
 
 def _get():
