@@ -418,25 +418,10 @@ def cpu_baseline(rp_h, col_h, seed, agg_call, nnz, agg_name, reps=5):
 
 
 def c5_pool(count, seed=3, n_lo=1_000, n_hi=10_000_000):
-    """Serving jobs: n log-uniform on [n_lo, n_hi]; 40% 2D 5-point (side
-    round(sqrt n)), 40% 3D 27-point (side round(cbrt n)), 20% Chung-Lu (n,
-    mean degree 16, exponent 2.1, cap min(20000, n - 1))."""
-    import numpy as np
+    """Serving jobs (graphs.serving_pool): n log-uniform on [n_lo, n_hi];
+    40% 2D 5-point, 40% 3D 27-point, 20% Chung-Lu."""
     from paper_2204_02934_amd import graphs
-    rng = np.random.default_rng(seed)
-    out = []
-    for i in range(count):
-        n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
-        kind = rng.choice(3, p=[0.4, 0.4, 0.2])
-        if kind == 0:
-            s = max(2, int(round(n ** 0.5)))
-            out.append(("2d5", graphs.grid2d_5pt(s, s)))
-        elif kind == 1:
-            s = max(2, int(round(n ** (1 / 3))))
-            out.append(("3d27", graphs.grid3d_27pt(s, s, s)))
-        else:
-            out.append(("chunglu", graphs.chung_lu(n, 16.0, 2.1, min(20000, n - 1), seed=100 + i)))
-    return out
+    return graphs.serving_pool(count, seed, n_lo, n_hi)
 
 
 def run_c4(args):

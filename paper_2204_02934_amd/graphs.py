@@ -224,6 +224,27 @@ def edgeless(n):
     return np.zeros(n + 1, np.int64), np.zeros(0, np.int32)
 
 
+
+def serving_pool(count, seed=3, n_lo=1_000, n_hi=10_000_000):
+    """Coarsening jobs of the serving workload: n log-uniform on [n_lo, n_hi];
+    40% 2D 5-point (side round(sqrt n)), 40% 3D 27-point (side round(cbrt n)),
+    20% Chung-Lu (n, mean degree 16, exponent 2.1, cap min(20000, n - 1)).
+    Returns [(kind, (row_ptr, col))]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+        kind = rng.choice(3, p=[0.4, 0.4, 0.2])
+        if kind == 0:
+            s = max(2, int(round(n ** 0.5)))
+            out.append(("2d5", grid2d_5pt(s, s)))
+        elif kind == 1:
+            s = max(2, int(round(n ** (1 / 3))))
+            out.append(("3d27", grid3d_27pt(s, s, s)))
+        else:
+            out.append(("chunglu", chung_lu(n, 16.0, 2.1, min(20000, n - 1), seed=100 + i)))
+    return out
+
 def disjoint_union(graphs):
     """Block-diagonal union; vertex ids of graph g are offset by the sizes of
     graphs 0..g-1."""

@@ -101,18 +101,17 @@ def test_batched_subdomains_small(ctx):
     _check(got, gs, 200, 64, 0)
 
 
-def test_batched_subdomains_full_sampled(ctx):
+def test_batched_subdomains_full(ctx):
     # 512 dropped-edge 7-point subdomains of side 8..48, multilevel to < 1000
-    # vertices; 24 graphs (the smallest, the largest and a seeded sample)
-    # checked against the oracle one by one
+    # vertices in one batched call; every graph is checked against the
+    # oracle run on that graph alone, level by level (about 15 s of CPU)
     gs = graphs.batch_subdomains(num=512, lo=8, hi=48, p_drop=0.1, seed=2)
     rp, c, voff = _union(gs)
     _say("C4 union n=%d nnz=%d" % (rp.size - 1, int(rp[-1])))
     got = ctx.aggregate_batched(rp, c, voff, seed=0, stop_below=1000)
     sizes = np.diff(voff)
-    rng = np.random.default_rng(9)
-    idx = sorted({int(np.argmin(sizes)), int(np.argmax(sizes))} |
-                 set(rng.choice(len(gs), 22, replace=False).tolist()))
-    _check(got, gs, 1000, 64, 0, idx)
     for i in range(len(gs)):
-        assert (len(got[i]) == 0) == (sizes[i] < 1000)
+        assert (len(got[i]) == 0) == (sizes[i] < 1000), i
+    _check(got, gs, 1000, 64, 0)
+    _say("C4: all %d graphs equal the oracle, %d levels in all"
+         % (len(gs), sum(len(g) for g in got)))

@@ -100,3 +100,37 @@ def test_server_rejects_oversized_and_truncates(api):
     want = oracle.coarsen(rp, c, seed=0, stop_below=100)[0]
     assert np.array_equal(r["levels"][0]["agg"].cpu().numpy(), want["agg"])
     srv.close()
+
+
+def test_server_recipe_pool_matches_oracle(api):
+    # the serving workload's own job mix: n log-uniform on [1e3, 1e7], 2D
+    # 5-point / 3D 27-point / Chung-Lu 40/40/20, multilevel to < 1000
+    # vertices.  The first 12 jobs of the seeded pool hold a 27-point job of
+    # 1.6M vertices, a Chung-Lu job of 0.9M vertices with hubs of 14k
+    # neighbours, and 5-point jobs of up to 0.87M vertices.  Capacity for
+    # about two large jobs at a time, two arrivals per step: later jobs queue
+    # and join the running union between levels.
+    pool = graphs.serving_pool(12, seed=3)
+    kinds = [k for k, _ in pool]
+    sizes = [g[0].size - 1 for _, g in pool]
+    assert any(k == "3d27" and n >= 1_000_000 for k, n in zip(kinds, sizes))
+    assert any(k == "chunglu" and int(np.diff(g[0]).max()) >= 10_000 for k, g in pool)
+    srv = api.Server(max_vertices=3_000_000, max_nnz=64_000_000, max_graphs=8, seed=0,
+                     stop_below=1000)
+    done, steps, nxt = {}, 0, 0
+    while len(done) < len(pool):
+        for _ in range(2):
+            if nxt < len(pool):
+                srv.submit(*pool[nxt][1], tag=nxt)
+                nxt += 1
+        srv.step()
+        steps += 1
+        for r in srv.poll():
+            done[r["tag"]] = r
+        assert steps < 400
+    _say("server: %d recipe jobs (%d vertices) in %d steps" % (len(pool), sum(sizes), steps))
+    for t, (kind, (rp, c)) in enumerate(pool):
+        assert not done[t]["truncated"], t
+        _say("job %d %s n=%d levels=%d" % (t, kind, rp.size - 1, len(done[t]["levels"])))
+        _check_job(done[t]["levels"], rp, c, 1000)
+    srv.close()
