@@ -337,6 +337,47 @@ def compaction_writes(recs):
     return [max(r.get("written", 0), 0) if r["kind"] == 0 else 0 for r in recs]
 
 
+KERNELS = {0: "refresh_column", 1: "decide", 2: "mis2_rounds_persistent", 3: "mis2_tail",
+           4: "refresh_column", 5: "decide"}
+
+
+def sweep_table(recs):
+    """Algorithmic bytes of every sweep of one call's accounting run, and the
+    upper-bound gather bytes: {(phase, kind, round): (bytes, gather bytes)}."""
+    out = {}
+    for r in recs:
+        if r["kind"] in (0, 1):
+            w = max(r.get("written", 0), 0) if r["kind"] == 0 else 0
+            out[(r["phase"], r["kind"], r["round"])] = (
+                sweep_bytes(r, r["phase"] == 0 and r["round"] == 0, w), gather_bytes(r))
+    return out
+
+
+def launch_costs(table, recs):
+    """(kernel, bytes, upper bytes, ms) of every launch of one profiled call:
+    a launched sweep is priced with its round's bytes, a persistent launch
+    (kind 2) with every sweep of its phase, the one-workgroup tail (kind 3)
+    with the sweeps of its phase from its first round on, and a round issued
+    after the end of the run (kinds 4, 5) with none."""
+    whole = {r["phase"] for r in recs if r["kind"] == 2}
+    tail = {r["phase"]: r["round"] for r in recs if r["kind"] == 3}
+    out = []
+    for r in recs:
+        k, ph = r["kind"], r["phase"]
+        if k in (0, 1):
+            if ph in whole or (ph in tail and r["round"] >= tail[ph]):
+                continue  # ran inside a persistent or tail launch
+            b, g = table.get((ph, k, r["round"]), (0, 0))
+            out.append((KERNELS[k], b, g, r["ms"]))
+        elif k in (2, 3):
+            first = 0 if k == 2 else r["round"]
+            sw = [v for (p, _, rd), v in table.items() if p == ph and rd >= first]
+            out.append((KERNELS[k], sum(v[0] for v in sw), sum(v[1] for v in sw), r["ms"]))
+        elif k in (4, 5):
+            out.append((KERNELS[k], 0, 0, r["ms"]))
+    return out
+
+
 def gather_bytes(rec):
     """Bytes one sweep would add if every neighbour-value gather went to HBM
     (4 per visited edge) instead of the compulsory first touch counted in
@@ -660,61 +701,61 @@ def main():
     recs_agg = acc.last_sweeps()
     accounted = recs_mis + recs_agg
 
-    # launch durations: a second timed loop with HIP events around each sweep
+    # launch durations: a second timed loop with HIP events around each
+    # launch; each launch is priced with the accounting run's bytes of the
+    # sweeps it ran (the round where the one-workgroup tail takes over may
+    # differ from run to run, the bytes of a round do not)
     prof = api.Context(0, profile=True)
     prof.ensure_workspace(n, 1, nnz)
     step(prof)
     torch.cuda.synchronize()
-    dur = [0.0] * len(accounted)
+    tables = [sweep_table(recs_mis), sweep_table(recs_agg)]
+    per_kind = {}
     tp0 = time.perf_counter()
     for _ in range(args.steps):
         prof.mis2(rp, col, args.seed, nnz=nnz)
         r1 = prof.last_sweeps()
         getattr(prof, agg_call)(rp, col, args.seed, nnz=nnz)
         r2 = prof.last_sweeps()
-        recs = r1 + r2
-        assert len(recs) == len(accounted)
-        for i, r in enumerate(recs):
-            assert (r["kind"], r["phase"], r["round"], r["rows"]) == \
-                (accounted[i]["kind"], accounted[i]["phase"], accounted[i]["round"],
-                 accounted[i]["rows"])
-            dur[i] += r["ms"]
+        for table, recs in zip(tables, (r1, r2)):
+            for k, b, g, ms in launch_costs(table, recs):
+                e = per_kind.setdefault(k, {"bytes": 0, "bytes_upper": 0, "ms": 0.0,
+                                            "launches": 0})
+                e["bytes"] += b
+                e["bytes_upper"] += b + g
+                e["ms"] += ms
+                e["launches"] += 1
     torch.cuda.synchronize()
     ms_profiled = 1e3 * (time.perf_counter() - tp0) / args.steps
-    dur = [d / args.steps for d in dur]
-    # per launch: (kernel, algorithmic bytes, mean ms).  A persistent launch
-    # covers every sweep of its phase; launched rounds are one kernel each.
-    kinds = {0: "refresh_column", 1: "decide", 2: "mis2_rounds_persistent"}
-    launches = []
-    for call in (range(0, len(recs_mis)), range(len(recs_mis), len(accounted))):
-        recs = [accounted[i] for i in call]
-        wr = dict(zip(call, compaction_writes(recs)))
-        persistent = [i for i in call if accounted[i]["kind"] == 2]
-        for i in call:
-            r = accounted[i]
-            if r["kind"] == 2:
-                sw = [j for j in call if accounted[j]["kind"] in (0, 1)
-                      and accounted[j]["phase"] == r["phase"]]
-                b = sum(sweep_bytes(accounted[j], accounted[j]["phase"] == 0 and
-                                    accounted[j]["round"] == 0, wr[j]) for j in sw)
-                launches.append((kinds[2], b, sum(gather_bytes(accounted[j]) for j in sw), dur[i]))
-            elif not persistent:
-                launches.append((kinds[r["kind"]],
-                                 sweep_bytes(r, r["phase"] == 0 and r["round"] == 0, wr[i]),
-                                 gather_bytes(r), dur[i]))
-    per_kind = {}
-    for k, b, g, ms in launches:
-        e = per_kind.setdefault(k, {"bytes": 0, "bytes_upper": 0, "ms": 0.0, "launches": 0})
-        e["bytes"] += b
-        e["bytes_upper"] += b + g
-        e["ms"] += ms
-        e["launches"] += 1
+    for e in per_kind.values():  # per step
+        for key in ("bytes", "bytes_upper", "ms", "launches"):
+            e[key] /= args.steps
     dom = max(per_kind, key=lambda k: per_kind[k]["ms"])
     d = per_kind[dom]
-    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9  # GB/s = mean bytes per launch / mean duration
+    # GB/s = the kernel's bytes per step / its GPU time per step (every launch
+    # of it, rounds issued after the end of a run included)
+    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
     sweep_ms = sum(v["ms"] for v in per_kind.values())
     sweep_bytes_total = sum(v["bytes"] for v in per_kind.values())
     log("per kind:", json.dumps(per_kind))
+
+    # the plan the tuner chose for this graph, and the step with the fixed
+    # degree rule (tuner off) for comparison
+    plan = ctx.last_plan()
+    tuning = ctx.last_tuning()
+    rule = api.Context(0, autotune=False)
+    rule.ensure_workspace(n, 1, nnz)
+    for _ in range(args.warmup):
+        step(rule)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(rule)
+    torch.cuda.synchronize()
+    rule_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    rule_plan = rule.last_plan()
+    log("plan %s (rule %s): %.3f ms/step with the tuned plan, %.3f ms with the rule"
+        % (plan, rule_plan, ms_per_step, rule_ms))
 
     rounds_mis = 1 + max(r["round"] for r in recs_mis if r["kind"] in (0, 1)) if recs_mis else 0
 
@@ -775,6 +816,16 @@ def main():
         "mis2_rounds": rounds_mis,
         "round_kernels_gpu_ms_per_step": sweep_ms,
         "round_kernels_bytes_per_step": sweep_bytes_total,
+        "round_kernels_gbps": sweep_bytes_total / (sweep_ms * 1e-3) / 1e9,
+        "step_algorithmic_gbps": sweep_bytes_total / (ms_per_step * 1e-3) / 1e9,
+        "step_algorithmic_frac": sweep_bytes_total / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+        "kernels_per_step": {k: {"launches": v["launches"], "ms": v["ms"], "bytes": v["bytes"]}
+                             for k, v in per_kind.items()},
+        "plan": {"lanes": plan["lanes"], "blocks": plan["blocks"],
+                 "source": ["rule", "tuned (cached)", "tuned"][plan["source"]],
+                 "tuning": tuning, "rule_plan": {"lanes": rule_plan["lanes"],
+                                                 "blocks": rule_plan["blocks"]},
+                 "rule_ms_per_step": rule_ms},
         "ms_per_step_profiled": ms_profiled,
     }
     print(json.dumps(out), flush=True)

@@ -53,8 +53,12 @@ extern "C" {
 
 /* Options, for mis2_set_option(). */
 #define MIS2_OPT_VALIDATE      0  /* 1: check the CSR on the GPU before each call (default 0) */
-#define MIS2_OPT_LANES_PER_ROW 1  /* 0 = automatic; -1 = flat (merge-path) sweeps; else 1, 2, 4,
-                                     8, 16, 32 or 64 lanes per CSR row */
+#define MIS2_OPT_LANES_PER_ROW 1  /* 0 = automatic; -1 = flat (merge-path) sweeps; -2 =
+                                     MIS2_LANES_STAGED; else 1, 2, 4, 8, 16, 32 or 64 lanes
+                                     per CSR row */
+#define MIS2_LANES_STAGED     (-2) /* one row per lane, each row's column indices staged in LDS
+                                     by 16-byte loads (rows of more than 32 entries go to the
+                                     whole wavefront) */
 #define MIS2_OPT_GRID_BLOCKS   2  /* 0 = automatic; else 1..8192 256-thread workgroups per sweep */
 #define MIS2_OPT_PROFILE       3  /* 1: time every sweep launch with HIP events on the call's stream */
 #define MIS2_OPT_ACCOUNT       4  /* 1: sweeps also sum the CSR row lengths they visit (extra atomics) */
@@ -68,6 +72,23 @@ extern "C" {
                                      those rows without their OUT neighbours and reads the
                                      shorter rows in later rounds; 0: never (lane plans > 0
                                      only; results are the same either way) */
+#define MIS2_OPT_TAIL          8  /* 1: once both worklists of a run hold fewer than 4096
+                                     vertices (round 2 on), its remaining rounds run in one
+                                     workgroup with the lists in LDS (one launch instead of
+                                     two per round, and no round issued past the end); 0
+                                     (default): every round is launched.  The plan tuner
+                                     tries both.  Results are the same either way. */
+#define MIS2_OPT_QUEUE_DEPTH   9  /* rounds the host keeps queued beyond the running one: 0
+                                     (default) = 2; else 1..8.  Deeper queues issue more
+                                     rounds past the end of a run (they find empty
+                                     worklists); results never change */
+#define MIS2_OPT_AUTOTUNE      7  /* 1 (default): while lanes and grid are automatic and the
+                                     launch is not persistent, each graph of at least 16384
+                                     vertices runs with the fastest of a few launch plans for
+                                     its class (half octave of n and degree histogram), timed
+                                     once per class and device on its first sight in the
+                                     process; 0: the fixed degree rule.  Plans never change
+                                     results. */
 
 typedef struct mis2_ctx mis2_ctx;
 
@@ -219,11 +240,24 @@ int mis2_last_trace(const mis2_ctx *ctx, int phase, int64_t *sizes, int32_t cap,
                     int32_t *rounds);
 
 /* One sweep launch of the last mis2_run / mis2_aggregate call. */
+/* One launch plan timed by the plan tuner (MIS2_OPT_AUTOTUNE). */
+typedef struct mis2_tune_record {
+    int32_t lanes;   /* lanes per row (MIS2_LANES_STAGED for the staged sweeps) */
+    int32_t blocks;  /* workgroups per sweep */
+    int32_t tail;    /* 1: the last rounds in one workgroup (MIS2_OPT_TAIL) */
+    float ms;        /* best of two timed MIS-2 runs of the graph, host wall clock */
+} mis2_tune_record;
+
 typedef struct mis2_sweep_record {
     int32_t kind;      /* 0 = Refresh Column (worklist2), 1 = Decide Set (worklist1),
                           2 = one persistent launch running every round of the phase
                           (then rows and edges are totals over its sweeps, rows_out is
-                          the round count, and the per-sweep records carry ms = -1) */
+                          the round count, and the per-sweep records carry ms = -1),
+                          3 = the one-workgroup tail launch (MIS2_OPT_TAIL) running the
+                          phase's rounds from `round` on (totals as for 2; its sweeps'
+                          records come before it, with ms = -1),
+                          4 / 5 = a Refresh Column / Decide Set launch of a round issued
+                          after the run had ended (it found empty worklists; rows 0) */
     int32_t phase;     /* 0 = MIS-2 of G; 1 = MIS-2 of the phase-2 induced subgraph */
     int32_t round;     /* round of Algorithm 1, from 0 (-1 for kind 2) */
     int32_t lanes;     /* lanes per CSR row used by the launch */
@@ -241,6 +275,22 @@ typedef struct mis2_sweep_record {
 /* Copy up to `cap` records of the last call's sweep launches to host array
  * `out`, in launch order; *count (host) receives the total number. */
 int mis2_last_sweeps(const mis2_ctx *ctx, mis2_sweep_record *out, int32_t cap, int32_t *count);
+
+/* Launch plan of the last mis2_run / mis2_aggregate / mis2_aggregate_basic on
+ * this context (the last level's for multilevel and batched calls): lanes per
+ * row (MIS2_LANES_STAGED for the staged sweeps), workgroups per sweep,
+ * whether the last rounds ran in one workgroup (MIS2_OPT_TAIL), and
+ * *source = 0 (set by options or the degree rule), 1 (tuned plan from the
+ * cache) or 2 (tuned during this call).  Any pointer may be NULL. */
+int mis2_last_plan(const mis2_ctx *ctx, int32_t *lanes, int32_t *blocks, int32_t *tail,
+                   int32_t *source);
+
+/* The candidate plans the last tuning on this context timed (see
+ * MIS2_OPT_AUTOTUNE): lanes 1, 2, 4, 8 and the staged sweeps, each at its
+ * grid rule, then the fastest with the one-workgroup tail when MIS2_OPT_TAIL
+ * is automatic; up to cap of them into out (host); *count = how many there
+ * were (0 if this context never tuned). */
+int mis2_last_tuning(const mis2_ctx *ctx, mis2_tune_record *out, int32_t cap, int32_t *count);
 
 /*
  * mis2_aggregate -- Algorithm 3 (Section III-B): MIS-2 based aggregation.

@@ -26,12 +26,16 @@ MIS2_OPT_PROFILE = 3
 MIS2_OPT_ACCOUNT = 4
 MIS2_OPT_PERSISTENT = 5
 MIS2_OPT_COMPACT = 6
+MIS2_OPT_AUTOTUNE = 7
+MIS2_OPT_TAIL = 8
+MIS2_OPT_QUEUE_DEPTH = 9
 MIS2_ABL_FIXED_PRIORITY = 1
 MIS2_ABL_XORSHIFT = 2
 MIS2_ABL_NO_WORKLISTS = 4
 MIS2_ABL_UNPACKED = 8
 MIS2_ABL_ONE_LANE = 16
 MIS2_ABL_SIMPLE = 32
+MIS2_LANES_STAGED = -2
 
 # Every symbol include/mis2.h declares.
 EXPORTS = (
@@ -44,6 +48,7 @@ EXPORTS = (
     "mis2_coarsen", "mis2_batch_workspace_bytes", "mis2_aggregate_batched",
     "mis2_server_bytes", "mis2_server_create", "mis2_server_destroy", "mis2_server_last_error",
     "mis2_server_submit", "mis2_server_step", "mis2_server_poll",
+    "mis2_last_plan", "mis2_last_tuning",
 )
 
 MIS2_SERVE_MAX_LEVELS = 32
@@ -66,6 +71,11 @@ class Mis2SweepRecord(ctypes.Structure):
                 ("lanes", ctypes.c_int32), ("rows", ctypes.c_int64), ("rows_out", ctypes.c_int64),
                 ("edges", ctypes.c_int64), ("ms", ctypes.c_float), ("compact", ctypes.c_int32),
                 ("written", ctypes.c_int64)]
+
+
+class Mis2TuneRecord(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_int32), ("blocks", ctypes.c_int32), ("tail", ctypes.c_int32),
+                ("ms", ctypes.c_float)]
 
 
 class Mis2JobResult(ctypes.Structure):
@@ -119,6 +129,10 @@ def load():
                                              ctypes.POINTER(i32), vp]),
         "mis2_ablation_workspace_bytes": (ctypes.c_int, [i64, ctypes.c_int,
                                                          ctypes.POINTER(ctypes.c_size_t)]),
+        "mis2_last_plan": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                          ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "mis2_last_tuning": (ctypes.c_int, [vp, ctypes.POINTER(Mis2TuneRecord), i32,
+                                            ctypes.POINTER(i32)]),
         "mis2_last_sweeps": (ctypes.c_int, [vp, ctypes.POINTER(Mis2SweepRecord), i32,
                                             ctypes.POINTER(i32)]),
         "mis2_quotient": (ctypes.c_int, [vp, gp, vp, i64, vp, vp, ctypes.POINTER(i64), vp]),

@@ -40,7 +40,8 @@ class Context:
     on demand (allocation happens outside the library calls)."""
 
     def __init__(self, device=None, validate=False, lanes=0, blocks=0, profile=False,
-                 account=False, persistent=False, compact=True):
+                 account=False, persistent=False, compact=True, autotune=True, tail=-1,
+                 queue_depth=0):
         self.lib = _lib.load()
         if device is None:
             device = torch.cuda.current_device()
@@ -55,6 +56,9 @@ class Context:
         self.set_option(_lib.MIS2_OPT_ACCOUNT, int(account))
         self.set_option(_lib.MIS2_OPT_PERSISTENT, int(persistent))
         self.set_option(_lib.MIS2_OPT_COMPACT, int(compact))
+        self.set_option(_lib.MIS2_OPT_AUTOTUNE, int(autotune))
+        self.set_option(_lib.MIS2_OPT_TAIL, int(tail))
+        self.set_option(_lib.MIS2_OPT_QUEUE_DEPTH, int(queue_depth))
 
     def __del__(self):
         lib = getattr(self, "lib", None)
@@ -327,6 +331,24 @@ class Context:
         k = min(r.value, cap)
         return np.ctypeslib.as_array(buf)[:2 * k].reshape(k, 2).copy()
 
+
+    def last_plan(self):
+        """Plan of the last call: {lanes (-2 = staged sweeps), blocks, tail (1
+        = last rounds in one workgroup), source (0 = options or the degree
+        rule, 1 = tuned plan from the cache, 2 = tuned during the call)}."""
+        a, b, t, c = (ctypes.c_int32(0) for _ in range(4))
+        _check(self.lib, self.ptr, self.lib.mis2_last_plan(self.ptr, ctypes.byref(a), ctypes.byref(b),
+                                                           ctypes.byref(t), ctypes.byref(c)))
+        return {"lanes": a.value, "blocks": b.value, "tail": t.value, "source": c.value}
+
+    def last_tuning(self, cap=64):
+        """Candidate plans the last tuning on this context timed: list of
+        {lanes, blocks, ms}."""
+        buf = (_lib.Mis2TuneRecord * cap)()
+        k = ctypes.c_int32(0)
+        _check(self.lib, self.ptr, self.lib.mis2_last_tuning(self.ptr, buf, cap, ctypes.byref(k)))
+        return [{"lanes": buf[i].lanes, "blocks": buf[i].blocks, "tail": buf[i].tail,
+                 "ms": buf[i].ms} for i in range(min(k.value, cap))]
 
     def last_sweeps(self, cap=8192):
         """Sweep launches of the last call: list of dicts (kind 0 = Refresh

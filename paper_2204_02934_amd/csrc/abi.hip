@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 
 #include "internal.h"
 
@@ -57,6 +58,8 @@ int check_graph_args(mis2_ctx *ctx, const mis2_graph *g) {
 // Lanes per row of the MIS-2 sweeps; 0 selects the flat (merge-path) sweeps.
 int lanes_for(const mis2_ctx *ctx, const mis2_graph *g) {
     if (ctx->plan.lanes == -1) return 0;
+    // the staged sweeps' 16-byte column loads need at least 4 entries
+    if (ctx->plan.lanes == kStagedLanes) return g->nnz >= 4 ? kStagedLanes : 1;
     if (ctx->plan.lanes) return ctx->plan.lanes;
     // Section V-D: one thread per row below an average degree of 16, lanes
     // cooperating on a row above it; here the group grows with the degree.
@@ -127,10 +130,11 @@ hipEvent_t take_event(mis2_ctx *ctx) {
 }
 
 struct Launch {
-    int kind, phase, round, lanes;
+    int kind, phase, round, lanes;  // kind 3: the tail kernel, from round `round` on
     hipEvent_t e0, e1;
     bool persistent = false;  // a sweep inside a persistent launch (timed by device stamps)
     int compact = 0;          // mis2_sweep_record.compact
+    int cstart = -1;          // tail: first compacting round (< 0: none)
 };
 
 
@@ -143,6 +147,13 @@ struct Geometry {
 Geometry geometry(const mis2_ctx *ctx, int64_t n, int lanes) {
     Geometry gm;
     gm.blocks = blocks_for(ctx, n);
+    if (!ctx->plan.blocks && lanes == kStagedLanes) {
+        // the staged sweeps' LDS slots limit the resident workgroups; one
+        // wave of dispatch per round
+        if (ctx->staged_blocks < 0) ctx->staged_blocks = sweep_resident_blocks(lanes, ctx->num_cus);
+        const int cap = ctx->staged_blocks / 8 * 8;
+        if (cap >= 8 && gm.blocks > cap) gm.blocks = cap;
+    }
     if (!ctx->plan.blocks && ctx->plan.persistent) {
         // the persistent launch needs every workgroup resident at once
         const int cap = rounds_max_blocks(lanes, ctx->num_cus) / 8 * 8;
@@ -167,6 +178,12 @@ int queue_trace(mis2_ctx *ctx, const Workspace &ws, int phase, int rounds, hipSt
 }
 
 int32_t parse_trace(mis2_ctx *ctx, int phase) {
+    if (ctx->tail_used[phase]) {
+        // rows written by the tail kernel, up to the one that ended the run
+        const unsigned long long e = __atomic_load_n(ctx->alive_host + 2 + phase, __ATOMIC_ACQUIRE);
+        if (e > 0 && e <= (unsigned long long)kTraceCap) ctx->trace_rounds[phase] = (int)e;
+        ctx->tail_used[phase] = 0;
+    }
     const int rounds = ctx->trace_rounds[phase];
     const uint32_t *rt = ctx->pinned_rt + (size_t)phase * (kTraceCap + 2) * kRoundStride;
     std::vector<int64_t> &tr = ctx->trace[phase];
@@ -281,6 +298,7 @@ RoundsArgs round_args(const mis2_ctx *ctx, const mis2_graph *g, uint64_t seed,
     a.bar = ws.bar;
     a.lflag = ws.lflag;
     a.n = g->n;
+    a.nnz = g->nnz;
     a.seg = gm.seg;
     a.S = gm.S;
     a.seed = seed;
@@ -347,7 +365,11 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
     int longs = masked ? (*long_rows > 0 ? 1 : 0) : -1;
     const int cfrom = masked ? 0 : kCompactFrom;
     int cstart = -1;  // first compacting round
+    __atomic_store_n(ctx->alive_host + 1, ~0ull, __ATOMIC_RELEASE);
     __atomic_store_n(ctx->alive_host, ~0ull, __ATOMIC_RELEASE);
+    ctx->tail_used[phase] = 0;
+    // the last rounds go to the one-workgroup tail once both worklists fit it
+    const bool tail_ok = ctx->plan.tail > 0 && !abl && lanes != 0 && g->nnz > 0;
     int round = 0;  // rounds issued
     auto last_progress = std::chrono::steady_clock::now();
     int last_seen = -2;
@@ -368,11 +390,47 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
         // queue depth beyond the running round: two while rounds are big,
         // one near the end (fewer rounds issued past it); a round that could
         // compact waits until the host knows whether it should
-        const int ahead = (seen < 0 || live >= 4096u) ? 2 : 1;
+        // Measured on gfx950 (mis2_run + mis2_aggregate): two rounds ahead
+        // throughout against two, then one once |worklist1| < 4096: 5-point
+        // 64^2 0.374 / 0.409 ms, 7-point 100^3 0.681 / 0.693 ms, C2 1.109 /
+        // 1.122 ms; three ahead 0.382, 0.695, 1.114 ms.  The round issued
+        // past the end costs less than the host gaps a shallow queue leaves
+        // between the short late rounds.
+        const int ahead = ctx->plan.ahead > 0 ? ctx->plan.ahead : 2;
         const bool can_compact = a.colc != nullptr && round >= cfrom;
         if (round - seen <= ahead && !(can_compact && longs < 0)) {
             if (round + 2 >= kTraceCap)
                 return fail(ctx, MIS2_EINTERNAL, "more than %d rounds", kTraceCap - 2);
+            if (tail_ok && round >= 1 && seen >= (masked ? 0 : 1) && live < (uint32_t)kTailCap &&
+                !(a.colc && longs < 0)) {
+                // worklist2 at round `seen` (word 1, written before word 0)
+                const unsigned long long w2 = __atomic_load_n(ctx->alive_host + 1, __ATOMIC_ACQUIRE);
+                if (w2 != ~0ull && (int)(w2 >> 32) == seen && (uint32_t)w2 < (uint32_t)kTailCap) {
+                    int cs = -1;  // first compacting round
+                    if (a.colc && longs > 0) cs = cstart >= 0 ? cstart : std::max(round, cfrom);
+                    Launch lt{3, phase, round, lanes, nullptr, nullptr};
+                    lt.cstart = cs;
+                    if (ctx->profile) {
+                        lt.e0 = take_event(ctx), lt.e1 = take_event(ctx);
+                        if (!lt.e0 || !lt.e1) return fail(ctx, MIS2_EHIP, "hipEventCreate failed");
+                    }
+                    __atomic_store_n(ctx->alive_host + 2 + phase, 0ull, __ATOMIC_RELEASE);
+                    uint32_t *rt_host =
+                        ctx->pinned_rt + (size_t)phase * (kTraceCap + 2) * kRoundStride;
+                    HIP_TRY(ctx, launch_tail(g->row_ptr, g->col, ws.T, ws.M, a, round, cs,
+                                             coop_threshold(lanes), rt_host,
+                                             ctx->alive_host + 2 + phase, s, lt.e0, lt.e1));
+                    launches->push_back(lt);
+                    if (!masked) *long_rows = longs > 0 ? 1 : 0;
+                    // the tail stamps its rounds' phases in the round table
+                    ctx->stamps_valid[phase] = 1;
+                    *iters_out = round;
+                    // rows before the tail's first round; the tail writes the rest
+                    int rc = queue_trace(ctx, ws, phase, round, s);
+                    ctx->tail_used[phase] = 1;
+                    return rc;
+                }
+            }
             int mode = 0;
             if (can_compact && longs > 0) {
                 if (cstart < 0) cstart = round;
@@ -439,7 +497,7 @@ int collect_sweeps(mis2_ctx *ctx, const std::vector<Launch> &launches, const Wor
             rec.kind = 2;
             rec.phase = l.phase;
             rec.round = -1;
-            rec.lanes = l.lanes;
+            rec.lanes = l.lanes == kStagedLanes ? MIS2_LANES_STAGED : l.lanes;
             rec.rows = 0;
             rec.edges = ctx->account ? 0 : -1;
             for (int r = 0; r < rounds; r++) {
@@ -460,13 +518,76 @@ int collect_sweeps(mis2_ctx *ctx, const std::vector<Launch> &launches, const Wor
             ctx->sweeps.push_back(rec);
             continue;
         }
-        if (l.round >= rounds) continue;  // issued after the run had finished
+        if (l.kind == 3) {
+            // the tail kernel: one record per sweep it ran (untimed), then its own
+            mis2_sweep_record sum;
+            memset(&sum, 0, sizeof sum);
+            sum.kind = 3;
+            sum.phase = l.phase;
+            sum.round = l.round;
+            sum.lanes = l.lanes == kStagedLanes ? MIS2_LANES_STAGED : l.lanes;
+            sum.edges = ctx->account ? 0 : -1;
+            sum.written = ctx->account ? 0 : -1;
+            sum.rows_out = std::max(0, rounds - l.round);
+            for (int r = l.round; r < rounds; r++) {
+                for (int kind = 0; kind < 2; kind++) {
+                    mis2_sweep_record rec;
+                    memset(&rec, 0, sizeof rec);
+                    rec.kind = kind;
+                    rec.phase = l.phase;
+                    rec.round = r;
+                    rec.lanes = sum.lanes;
+                    const int list = kind == 0 ? 1 : 0;
+                    rec.rows = tr[2 * r + list];
+                    rec.rows_out = r + 1 < rounds ? tr[2 * (r + 1) + list] : 0;
+                    const size_t di = ((size_t)l.phase * kTraceCap + r) * kDegStride;
+                    rec.edges = ctx->account ? (int64_t)degs[di + list] : -1;
+                    rec.written = ctx->account && kind == 0 ? (int64_t)degs[di + 2] : -1;
+                    rec.compact = kind == 0 && l.cstart >= 0 && r >= l.cstart
+                                      ? (r == l.cstart ? 1 : 2) : 0;
+                    rec.ms = -1.0f;
+                    const std::vector<float> &st = ctx->stamp_ms[l.phase];
+                    if (ctx->profile && (size_t)(2 * r + kind) < st.size()) rec.ms = st[2 * r + kind];
+                    ctx->sweeps.push_back(rec);
+                    sum.rows += rec.rows;
+                    if (ctx->account) sum.edges += rec.edges;
+                    if (ctx->account && kind == 0) sum.written += rec.written;
+                }
+            }
+            sum.ms = -1.0f;
+            if (ctx->profile && l.e0 && l.e1) {
+                float ms = 0.f;
+                HIP_TRY(ctx, hipEventElapsedTime(&ms, l.e0, l.e1));
+                sum.ms = ms;
+            }
+            ctx->sweeps.push_back(sum);
+            continue;
+        }
+        if (l.round >= rounds) {
+            // issued after the run had finished: found empty worklists
+            mis2_sweep_record rec;
+            memset(&rec, 0, sizeof rec);
+            rec.kind = l.kind == 0 ? 4 : 5;
+            rec.phase = l.phase;
+            rec.round = l.round;
+            rec.lanes = l.lanes == kStagedLanes ? MIS2_LANES_STAGED : l.lanes;
+            rec.edges = ctx->account ? 0 : -1;
+            rec.written = ctx->account ? 0 : -1;
+            rec.ms = -1.0f;
+            if (ctx->profile && l.e0 && l.e1) {
+                float ms = 0.f;
+                HIP_TRY(ctx, hipEventElapsedTime(&ms, l.e0, l.e1));
+                rec.ms = ms;
+            }
+            ctx->sweeps.push_back(rec);
+            continue;
+        }
         mis2_sweep_record rec;
         memset(&rec, 0, sizeof rec);
         rec.kind = l.kind;
         rec.phase = l.phase;
         rec.round = l.round;
-        rec.lanes = l.lanes;
+        rec.lanes = l.lanes == kStagedLanes ? MIS2_LANES_STAGED : l.lanes;
         const int list = l.kind == 0 ? 1 : 0;
         rec.rows = tr[2 * l.round + list];
         rec.rows_out = l.round + 1 < rounds ? tr[2 * (l.round + 1) + list] : 0;
@@ -488,6 +609,200 @@ int collect_sweeps(mis2_ctx *ctx, const std::vector<Launch> &launches, const Wor
     }
     return MIS2_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Plan tuner.  Launch plans (lanes per row, grid) never change results, only
+// time, and the best one depends on the graph: the degree rule of Section V-D
+// (lanes_for) is right for some graphs and not others.  A graph is
+// classified by its size and degree histogram (one small kernel, read back
+// once per graph and context); the first time a class is seen on a device,
+// a few candidate plans each run the graph's MIS-2 twice and the fastest is
+// kept for the class, process-wide, so every context on the device uses it.
+// ---------------------------------------------------------------------------
+constexpr int64_t kTuneMinN = 16384;   // smaller graphs keep the degree rule
+constexpr size_t kSeenCap = 32;        // graphs remembered per context
+
+struct TuneEntry {
+    GraphClass cls;
+    Plan plan;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tuned[64];    // per device
+
+int size_bucket(int64_t n) {
+    // floor(2 log2 n) from the integer log and the top bits
+    int lg = 0;
+    while ((n >> (lg + 1)) > 0) lg++;
+    const bool upper = lg >= 1 ? ((n >> (lg - 1)) & 1) != 0 : false;  // n >= 1.5 * 2^lg
+    return 2 * lg + (upper ? 1 : 0);
+}
+
+int host_deg_bin(uint64_t d) {
+    if (d == 0) return 0;
+    if (d <= 2) return 1;
+    if (d <= 4) return 2;
+    if (d <= 8) return 3;
+    if (d <= 16) return 4;
+    if (d <= 32) return 5;
+    if (d <= 128) return 6;
+    if (d <= 1024) return 7;
+    return 8;
+}
+
+// The class of g (cached per context by row_ptr, n and nnz).
+int classify(mis2_ctx *ctx, const mis2_graph *g, const Workspace &ws, hipStream_t s,
+             GraphClass *out) {
+    for (size_t i = ctx->seen.size(); i-- > 0;) {
+        const auto &e = ctx->seen[i];
+        if (e.row_ptr == g->row_ptr && e.n == g->n && e.nnz == g->nnz) {
+            *out = e.cls;
+            return MIS2_OK;
+        }
+    }
+    // partial rows go to the accounting sums' buffer (idle here; an
+    // accounting run clears it before use), then to pinned host memory
+    HIP_TRY(ctx, launch_degree_hist(g->n, g->row_ptr, ws.degs, s));
+    static_assert((size_t)kHistBlocks * kHistWords * 8 <= 2 * (size_t)kCtrList * 4,
+                  "histogram read-back fits the pinned counter buffer");
+    unsigned long long *h = (unsigned long long *)ctx->pinned_ctr;
+    HIP_TRY(ctx, hipMemcpyAsync(h, ws.degs, (size_t)kHistBlocks * kHistWords * 8,
+                                hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    unsigned long long cnt[kDegBins] = {}, mx = 0;
+    for (int b = 0; b < kHistBlocks; b++) {
+        for (int k = 0; k < kDegBins; k++) cnt[k] += h[(size_t)b * kHistWords + k];
+        mx = std::max(mx, h[(size_t)b * kHistWords + kDegBins]);
+    }
+    GraphClass c;
+    c.size_bucket = size_bucket(g->n);
+    for (int k = 0; k < kDegBins; k++)
+        c.share[k] = (uint8_t)((cnt[k] * 16 + (unsigned long long)g->n / 2) / (unsigned long long)g->n);
+    c.max_bin = host_deg_bin(mx);
+    if (ctx->seen.size() >= kSeenCap) ctx->seen.erase(ctx->seen.begin());
+    ctx->seen.push_back({g->row_ptr, g->n, g->nnz, c});
+    *out = c;
+    return MIS2_OK;
+}
+
+// Host wall time of one MIS-2 run of g (round 0 tuples, the rounds, a final
+// synchronisation) with the context's current plan.
+int time_mis2(mis2_ctx *ctx, const mis2_graph *g, const Workspace &ws, hipStream_t s,
+              double *sec) {
+    std::vector<Launch> launches;
+    const Geometry gm = geometry(ctx, g->n, lanes_for(ctx, g));
+    int32_t iters = 0;
+    int long_rows = 0;
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    const auto t0 = std::chrono::steady_clock::now();
+    HIP_TRY(ctx, launch_init_tuples(tparams(ctx, g->n, 0, 0), g->n, ws.T, s));
+    int rc = run_rounds(ctx, g, 0, ws, gm, false, 0, s, &iters, &launches, &long_rows);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    *sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return MIS2_OK;
+}
+
+int tune(mis2_ctx *ctx, const mis2_graph *g, const Workspace &ws, hipStream_t s, Plan *best) {
+    std::vector<Plan> cand;
+    for (int L : {1, 2, 4, 8}) {
+        Plan p = ctx->plan;
+        p.lanes = L;
+        cand.push_back(p);
+    }
+    if (g->nnz >= 4) {
+        Plan p = ctx->plan;
+        p.lanes = kStagedLanes;
+        cand.push_back(p);
+    }
+    const bool tune_tail = ctx->plan.tail < 0;
+    for (Plan &p : cand)
+        if (tune_tail) p.tail = 0;
+    const int saved_profile = ctx->profile, saved_account = ctx->account;
+    const Plan saved_plan = ctx->plan;
+    ctx->profile = 0;
+    ctx->account = 0;
+    ctx->tuning.clear();
+    double best_t = 0;
+    int rc = MIS2_OK;
+    for (size_t ci = 0; ci < cand.size() + (tune_tail ? 1 : 0); ci++) {
+        Plan p;
+        if (ci < cand.size()) {
+            p = cand[ci];
+        } else {
+            p = *best;  // the fastest so far, with its last rounds in the tail
+            p.tail = 1;
+        }
+        ctx->plan = p;
+        double t = 1e30;
+        for (int rep = 0; rep < 2 && rc == MIS2_OK; rep++) {
+            double x = 0;
+            rc = time_mis2(ctx, g, ws, s, &x);
+            t = std::min(t, x);
+        }
+        if (rc) break;
+        const Geometry gm = geometry(ctx, g->n, lanes_for(ctx, g));
+        ctx->tuning.push_back({p.lanes == kStagedLanes ? MIS2_LANES_STAGED : p.lanes, gm.blocks,
+                               p.tail > 0 ? 1 : 0, (float)(t * 1e3)});
+        if (ctx->tuning.size() == 1 || t < best_t) {
+            best_t = t;
+            *best = p;
+        }
+    }
+    ctx->plan = saved_plan;
+    ctx->profile = saved_profile;
+    ctx->account = saved_account;
+    return rc;
+}
+
+// Sets the plan of this call: the tuned plan of g's class when the context's
+// plan is automatic (tuning the class first if it is new), else the
+// context's own.  *saved receives the plan to restore after the call.
+int apply_plan(mis2_ctx *ctx, const mis2_graph *g, const Workspace &ws, hipStream_t s,
+               Plan *saved) {
+    *saved = ctx->plan;
+    ctx->last_source = 0;
+    const bool automatic = ctx->plan.lanes == 0 && ctx->plan.blocks == 0 && !ctx->plan.persistent;
+    if (!ctx->autotune || !automatic || g->n < kTuneMinN || ctx->device < 0 || ctx->device >= 64)
+        return MIS2_OK;
+    GraphClass c;
+    int rc = classify(ctx, g, ws, s, &c);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        for (const TuneEntry &e : g_tuned[ctx->device]) {
+            if (e.cls == c) {
+                ctx->plan = e.plan;
+                ctx->last_source = 1;
+                return MIS2_OK;
+            }
+        }
+    }
+    Plan best = ctx->plan;
+    if ((rc = tune(ctx, g, ws, s, &best))) return rc;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tuned[ctx->device].push_back({c, best});
+    }
+    ctx->plan = best;
+    ctx->last_source = 2;
+    return MIS2_OK;
+}
+
+// Restores the context's plan at the end of a call and records the one used.
+struct PlanScope {
+    mis2_ctx *ctx;
+    const mis2_graph *g;
+    Plan saved;
+    bool armed = false;
+    ~PlanScope() {
+        if (!armed) return;
+        const int L = lanes_for(ctx, g);
+        ctx->last_lanes = L == kStagedLanes ? MIS2_LANES_STAGED : L;
+        ctx->last_blocks = geometry(ctx, g->n, L).blocks;
+        ctx->last_tail = ctx->plan.tail > 0 ? 1 : 0;
+        ctx->plan = saved;
+    }
+};
 
 }  // namespace
 
@@ -592,6 +907,8 @@ int mis2_create(mis2_ctx **out, int device) {
         return MIS2_EINVAL;
     mis2_ctx *ctx = new mis2_ctx();
     ctx->device = device;
+    ctx->seen.reserve(kSeenCap + 1);
+    ctx->tuning.reserve(8);
     if (hipSetDevice(device) != hipSuccess) {
         delete ctx;
         return MIS2_EHIP;
@@ -655,10 +972,11 @@ int mis2_set_option(mis2_ctx *ctx, int option, int64_t value) {
             ctx->validate = value != 0;
             return MIS2_OK;
         case MIS2_OPT_LANES_PER_ROW:
-            if (value != 0 && value != -1 && (value < 1 || value > 64 || (value & (value - 1))))
+            if (value != 0 && value != -1 && value != MIS2_LANES_STAGED &&
+                (value < 1 || value > 64 || (value & (value - 1))))
                 return fail(ctx, MIS2_EINVAL,
-                            "lanes per row must be 0, -1 or a power of two <= 64");
-            ctx->plan.lanes = (int)value;
+                            "lanes per row must be 0, -1, -2 or a power of two <= 64");
+            ctx->plan.lanes = value == MIS2_LANES_STAGED ? kStagedLanes : (int)value;
             return MIS2_OK;
         case MIS2_OPT_GRID_BLOCKS:
             if (value < 0 || value > kMaxBlocks)
@@ -676,6 +994,18 @@ int mis2_set_option(mis2_ctx *ctx, int option, int64_t value) {
             return MIS2_OK;
         case MIS2_OPT_COMPACT:
             ctx->plan.compact = value != 0;
+            return MIS2_OK;
+        case MIS2_OPT_AUTOTUNE:
+            ctx->autotune = value != 0;
+            return MIS2_OK;
+        case MIS2_OPT_TAIL:
+            if (value < -1 || value > 1) return fail(ctx, MIS2_EINVAL, "tail must be -1, 0 or 1");
+            ctx->plan.tail = (int)value;
+            return MIS2_OK;
+        case MIS2_OPT_QUEUE_DEPTH:
+            if (value < 0 || value > 8)
+                return fail(ctx, MIS2_EINVAL, "queue depth must be in [0, 8]");
+            ctx->plan.ahead = (int)value;
             return MIS2_OK;
         default:
             return fail(ctx, MIS2_EINVAL, "unknown option %d", option);
@@ -722,6 +1052,9 @@ int mis2_run(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, uint8_t *status,
     Workspace ws;
     if ((rc = get_workspace(ctx, g, MIS2_OP_MIS2, &ws))) return rc;
     if ((rc = maybe_validate(ctx, g, ws, s))) return rc;
+    PlanScope ps{ctx, g, ctx->plan};
+    if ((rc = apply_plan(ctx, g, ws, s, &ps.saved))) return rc;
+    ps.armed = true;
 
     ctx->events_used = 0;
     std::vector<Launch> launches;
@@ -845,6 +1178,24 @@ int mis2_last_sweeps(const mis2_ctx *ctx, mis2_sweep_record *out, int32_t cap, i
     return MIS2_OK;
 }
 
+int mis2_last_plan(const mis2_ctx *ctx, int32_t *lanes, int32_t *blocks, int32_t *tail,
+                   int32_t *source) {
+    if (!ctx) return MIS2_EINVAL;
+    if (lanes) *lanes = ctx->last_lanes;
+    if (blocks) *blocks = ctx->last_blocks;
+    if (tail) *tail = ctx->last_tail;
+    if (source) *source = ctx->last_source;
+    return MIS2_OK;
+}
+
+int mis2_last_tuning(const mis2_ctx *ctx, mis2_tune_record *out, int32_t cap, int32_t *count) {
+    if (!ctx || cap < 0 || (cap > 0 && !out)) return MIS2_EINVAL;
+    const int32_t k = (int32_t)ctx->tuning.size();
+    for (int32_t i = 0; i < std::min(k, cap); i++) out[i] = ctx->tuning[i];
+    if (count) *count = k;
+    return MIS2_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -887,6 +1238,9 @@ int aggregate_basic_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int3
     int rc;
     const int64_t n = g->n;
     uint32_t *sc = ws.scalars;
+    PlanScope ps{ctx, g, ctx->plan};
+    if ((rc = apply_plan(ctx, g, ws, s, &ps.saved))) return rc;
+    ps.armed = true;
     ctx->events_used = 0;
     std::vector<Launch> launches;
     const int lanes = lanes_for(ctx, g);
@@ -908,7 +1262,7 @@ int aggregate_basic_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int3
     join_io.n = n;
     join_io.seg = gm.seg;
     join_io.S = gm.S;
-    HIP_TRY(ctx, launch_join_min(lanes > 0 ? lanes : 4, gm.blocks, g->row_ptr, g->col, ws.label,
+    HIP_TRY(ctx, launch_join_min(lanes > 0 ? group_lanes(lanes) : 4, gm.blocks, g->row_ptr, g->col, ws.label,
                                  join_io, agg_id, sc + kS_Err, s));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, sc, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -925,6 +1279,9 @@ int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
     int rc;
     const int64_t n = g->n;
     uint32_t *sc = ws.scalars;
+    PlanScope ps{ctx, g, ctx->plan};
+    if ((rc = apply_plan(ctx, g, ws, s, &ps.saved))) return rc;
+    ps.armed = true;
     ctx->events_used = 0;
     std::vector<Launch> launches;
     const Geometry gm = geometry(ctx, n, lanes_for(ctx, g));
@@ -990,7 +1347,7 @@ int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
     // hands longer ones to a one-row-per-wavefront pass: 4 lanes at least,
     // or every 27-point row would be long (27-point 100^3 aggregation with
     // 1 lane: 1.7 ms, with 4: 0.78 ms)
-    const int p3_lanes = std::max(4, lanes_for(ctx, g));
+    const int p3_lanes = std::max(4, group_lanes(lanes_for(ctx, g)));
     HIP_TRY(ctx, launch_phase3(p3_lanes, gm.blocks, g->row_ptr, g->col, ws.label,
                                ws.aggsize, p3_io, long_io, agg_id, sc + kS_Err, s));
 

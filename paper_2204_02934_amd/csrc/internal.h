@@ -155,11 +155,40 @@ size_t compact_bytes(int64_t n, int64_t nnz);
 bool carve(void *base, size_t bytes, int64_t n, int op, Workspace *ws);
 
 // Launch-plan knobs; never change results.
+// Plan value of the staged sweeps (one row per lane, each row's column
+// indices staged in LDS by 16-byte loads); the template argument L of the
+// sweep kernels takes it too.
+constexpr int kStagedLanes = 128;
+
+// Lanes per row of the group kernels that have no staged form (Algorithm 2's
+// join, phase 3 of Algorithm 3): 4 in place of the staged plan.
+__host__ __device__ constexpr int group_lanes(int lanes) {
+    return lanes == kStagedLanes ? 4 : lanes;
+}
+
+// Class of a graph for the plan tuner: its size (half octaves of n) and
+// degree histogram (the share of rows in each bin of deg_bin, in sixteenths,
+// and the bin of the largest degree).
+struct GraphClass {
+    int32_t size_bucket = 0;
+    uint8_t share[9] = {};
+    int32_t max_bin = 0;
+    bool operator==(const GraphClass &o) const {
+        if (size_bucket != o.size_bucket || max_bin != o.max_bin) return false;
+        for (int k = 0; k < 9; k++)
+            if (share[k] != o.share[k]) return false;
+        return true;
+    }
+};
+
 struct Plan {
-    int lanes = 0;       // lanes per CSR row (power of two <= 64); 0 = automatic
+    int lanes = 0;       // lanes per CSR row (power of two <= 64, or kStagedLanes); 0 = automatic
     int blocks = 0;      // workgroups per sweep (<= kMaxBlocks); 0 = automatic
     int persistent = 0;  // 1: one cooperative launch per MIS-2 run; 0: two launches per round
     int compact = 1;     // 1: Refresh Column skips OUT neighbours when the workspace has room
+    int tail = -1;       // 1: the last rounds (worklists of < kTailCap) run in one workgroup;
+                         // 0: never; -1: as the plan tuner finds (off untuned)
+    int ahead = 0;       // rounds queued beyond the running one (0: 2)
 };
 
 // One sweep's worklists.  Wavefront w owns slots [w*seg, w*seg + cnt[w]) of
@@ -191,6 +220,7 @@ struct SegIO {
     // longer than the cooperative threshold sets one of kSplit flags
     // (stride kCtrLine), or null.
     uint32_t *long_flag;
+    int64_t nnz;  // entries of the CSR (the staged sweeps' 16-byte loads stay below it)
 };
 
 // Arguments of the persistent round kernel.  bar: [kMaxBlocks] per-workgroup
@@ -219,6 +249,7 @@ struct RoundsArgs {
     uint32_t *lflag; // [kSplit][kCtrLine] set by round 0 when a row is long (zero at the start)
     int abl;         // ablation kernels only: kAblFixed | kAblXorshift
     int64_t n, seg, S;
+    int64_t nnz;
     uint64_t seed, pmask;
     uint32_t b;
     int masked;
@@ -248,7 +279,28 @@ struct AblTuples {
 constexpr uint32_t kLongRowsBit = 0x80000000u;
 
 // mis2_kernels.hip
+// Degree histogram of the plan tuner: kHistBlocks partial rows of kHistWords
+// (kDegBins row counts, then the largest degree) at part.
+constexpr int kDegBins = 9;
+constexpr int kHistWords = kDegBins + 1;
+constexpr int kHistBlocks = 64;
+hipError_t launch_degree_hist(int64_t n, const int64_t *row_ptr, unsigned long long *part,
+                              hipStream_t s);
 int rounds_max_blocks(int lanes, int num_cus);
+// Workgroups of a sweep grid that are resident at once (staged sweeps only; 0 otherwise).
+int sweep_resident_blocks(int lanes, int num_cus);
+// The last rounds of a run in one workgroup, from round r0 with both
+// worklists of at most kTailCap vertices (see k_tail).  cstart: first
+// compacting round (< 0: none); thr: the plan's cooperative threshold;
+// rt_host: this phase's host-pinned round table; end_host receives the
+// rounds of the run plus one.
+constexpr int kTailCap = 4096;
+hipError_t launch_tail(const int64_t *row_ptr, const int32_t *col, uint32_t *T, uint32_t *M,
+                       const RoundsArgs &a, int r0, int cstart, int64_t thr, uint32_t *rt_host,
+                       unsigned long long *end_host, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+// Rows longer than this go to the whole wavefront in the sweeps of `lanes`
+// (and only they are compacted).
+int64_t coop_threshold(int lanes);
 hipError_t launch_rounds(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                          uint32_t *T, uint32_t *M, const RoundsArgs &a, hipStream_t s);
 // e0 / e1 (may be null): events stamped by the launch itself at the kernel's
@@ -447,9 +499,13 @@ struct mis2_ctx {
     size_t ws_bytes = 0;
     uint32_t *pinned = nullptr;  // host-pinned scalars for read-back
     uint32_t *pinned_ctr = nullptr;  // host-pinned [2][kCtrList]: worklist1 counters per chunk
-    unsigned long long *alive_host = nullptr;  // host-pinned: (round << 32) | |worklist1|
+    unsigned long long *alive_host = nullptr;  // host-pinned [8]: (round << 32) | |worklist1|,
+                                               // (round << 32) | |worklist2|, tail row counts
     uint32_t *pinned_rt = nullptr;  // host-pinned [2][kTraceCap + 2][kRoundStride] round tables
     int trace_rounds[2] = {0, 0};   // rows of pinned_rt copied per phase
+    int tail_used[2] = {0, 0};      // the phase's last rounds ran in the tail kernel
+                                    // (it writes their rows of pinned_rt itself and the
+                                    // row count to alive_host[2 + phase])
     int stamps_valid[2] = {0, 0};   // the rows hold persistent-kernel stamps
     std::string err;
     int validate = 0;
@@ -463,4 +519,15 @@ struct mis2_ctx {
     double wall_khz = 100000.0;             // device wall-clock rate
     std::vector<hipEvent_t> events;         // profiling event pool
     size_t events_used = 0;
+    mutable int staged_blocks = -1;         // resident workgroups of the staged sweeps (-1: not yet asked)
+    // plan tuner
+    int autotune = 1;                        // MIS2_OPT_AUTOTUNE
+    struct SeenGraph {                       // graphs already classified (most recent last)
+        const int64_t *row_ptr;
+        int64_t n, nnz;
+        mis2::GraphClass cls;
+    };
+    std::vector<SeenGraph> seen;
+    int last_lanes = 0, last_blocks = 0, last_tail = 0, last_source = 0;  // plan of the last call
+    std::vector<mis2_tune_record> tuning;    // candidate timings of the last tuning
 };

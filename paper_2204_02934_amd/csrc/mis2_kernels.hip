@@ -24,6 +24,8 @@
 // and combines partial results with cross-lane shuffles.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "internal.h"
 #include "lanes.h"
 
@@ -595,6 +597,323 @@ __device__ __forceinline__ uint32_t sweep_decide(const int64_t *__restrict__ row
 }
 
 // ---------------------------------------------------------------------------
+// Staged sweeps: one row per lane.  A wavefront takes the rows of its segment
+// 64 at a time.  Groups of 4 lanes load each row's column indices with
+// 16-byte loads (up to kStagedCap entries, two loads per lane) into the row's
+// slot of LDS; then every lane walks its own row from LDS and gathers the
+// neighbour values.  The k-th gathers of consecutive rows are thereby issued
+// by consecutive lanes of one instruction (for a stencil graph: nearby
+// addresses, few cache lines per instruction), while the column indices are
+// read in whole 64-byte pieces.  Rows longer than kStagedCap entries go to
+// the whole wavefront, as in the L-lane sweeps.
+//
+// Measured on gfx950 (27-point 100^3 graph, round 0 of Refresh Column): 4
+// lanes per row took 34 us, the staged sweep with one lane per row (64 rows
+// per step) 26 us at 1024 workgroups; two lanes per row (32 rows per step,
+// half the LDS) 36 us at 1536 and 29 us at 2048 workgroups.  The slots take
+// 8.4 KB of LDS per wavefront, so 4 workgroups fit on a compute unit.
+// ---------------------------------------------------------------------------
+constexpr int kStagedCap = 32;     // column indices per LDS row slot
+constexpr int kStagedStride = 33;  // words per slot: a lane's k-th read hits bank (slot + k) % 32
+constexpr int kStagedUnroll = 13;  // gathers in flight per lane
+
+typedef int32_t v4i32 __attribute__((ext_vector_type(4), aligned(4)));
+
+// H lanes per row (1 or 2): 64 / H rows per step.
+template <int H>
+struct StagedLds {
+    int32_t idx[(64 / H) * kStagedStride];
+};
+
+// p[j .. j + 3] for 0 <= j < nnz (nnz >= 4): one 16-byte load from
+// min(j, nnz - 4), whose elements are moved down near the end of the array
+// so that element q is p[j + q] whenever j + q < nnz.  Elements past nnz are
+// not meaningful.  The move is register work only (no load in the branch).
+__device__ __forceinline__ v4i32 load4_clamped(const int32_t *p, int64_t j, int64_t nnz) {
+    const int64_t jj = min(j, nnz - 4);
+    v4i32 x = *(const v4i32 *)(p + jj);
+    const int64_t d = j - jj;
+    if (d == 1) {
+        x.x = x.y; x.y = x.z; x.z = x.w;
+    } else if (d == 2) {
+        x.x = x.z; x.y = x.w;
+    } else if (d == 3) {
+        x.x = x.w;
+    }
+    return x;
+}
+
+// Copies the column indices of the step's rows into their LDS slots: groups
+// of 4 lanes take one row each (16 rows per pass), `chunks` (1 or 2)
+// 16-byte loads per lane, 16 entries per chunk.  Row r's start s is held by
+// lane r * H; cf (same lanes) selects the compacted copy.  Entries past a
+// row's end are written too and never read.
+template <int H>
+__device__ __forceinline__ void stage_rows(StagedLds<H> &sh, const int32_t *col,
+                                           const int32_t *colc, const int64_t s, const int cf,
+                                           int chunks, int64_t nnz) {
+    constexpr int R = 64 / H;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int sub = lane & 3;
+#pragma unroll
+    for (int g = 0; g < R / 16; g++) {
+        const int rr = g * 16 + (lane >> 2);
+        const int64_t sr = __shfl(s, rr * H, 64);
+        const int rcf = __shfl(cf, rr * H, 64);
+        const int32_t *src = rcf ? colc : col;
+        v4i32 x[2];
+#pragma unroll
+        for (int c = 0; c < 2; c++)
+            if (c < chunks) x[c] = load4_clamped(src, sr + c * 16 + sub * 4, nnz);
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            if (c < chunks) {
+                int32_t *d = &sh.idx[rr * kStagedStride + c * 16 + sub * 4];
+                d[0] = x[c].x;
+                d[1] = x[c].y;
+                d[2] = x[c].z;
+                d[3] = x[c].w;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Refresh Column over the wavefront's segment, staged (see above), with H
+// lanes per row (lane h of a row gathers its entries h, h + H, ...).  RD /
+// WR: as in sweep_column, with "long" meaning more than kStagedCap entries
+// in the CSR.
+template <int H, bool RD, bool WR>
+__device__ __forceinline__ uint32_t sweep_column_staged(const int64_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ col,
+                                                        const uint32_t *__restrict__ T,
+                                                        uint32_t *__restrict__ M, const SegIO &io,
+                                                        const Seg &sg, StagedLds<H> &sh) {
+    constexpr int R = 64 / H;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int sub = lane & (H - 1);
+    const int32_t *colc = io.ccol_in;
+    const int32_t *lenc = io.lenc_in;
+    int32_t *wout = WR ? io.ccol_out : nullptr;
+    uint32_t kept = 0;
+    unsigned long long dsum = 0, wsum = 0;
+    int32_t v[1];
+    bool ok[1];
+    int64_t s = 0, e = 0;
+    uint32_t m = 0;
+    int32_t lc = 0;
+    if (sg.count > 0) {
+        load_rows<H, 1>(io, sg, 0, v, ok);
+        s = row_ptr[v[0]];
+        e = row_ptr[v[0] + 1];
+        m = T[v[0]];
+        lc = RD ? lenc[v[0]] : 0;
+    }
+    for (int64_t i0 = 0; i0 < sg.count; i0 += R) {
+        const bool more = i0 + R < sg.count;
+        int32_t vn[1] = {0};
+        bool okn[1] = {false};
+        if (more) load_rows<H, 1>(io, sg, i0 + R, vn, okn);
+        if (!ok[0]) e = s;
+        const int cf = RD && e - s > kStagedCap;
+        if (cf) e = s + lc;
+        if (sub == 0) dsum += (unsigned long long)(e - s);
+        uint32_t wc = 0;
+        bool wrote = false;
+        // long rows: the whole wavefront streams each one in turn
+        uint64_t heavy = __ballot(sub == 0 && e - s > kStagedCap);
+        if (!RD && !WR && heavy && io.long_flag && lane == 0)
+            io.long_flag[(blockIdx.x % kSplit) * kCtrLine] = 1u;
+        while (heavy) {
+            const int src = __ffsll((unsigned long long)heavy) - 1;
+            heavy &= heavy - 1;
+            const int64_t hs = __shfl(s, src, 64), he = __shfl(e, src, 64);
+            uint32_t hm, hw = 0;
+            if (RD && __shfl(cf, src, 64) != 0)
+                hm = coop_min_T(colc, T, hs, he, wout, &hw);
+            else
+                hm = coop_min_T(col, T, hs, he, wout, &hw);
+            if (WR && lane == 0) wsum += hw;
+            if ((lane & ~(H - 1)) == src) {
+                m = min(m, hm);
+                e = s;  // skipped below
+                wc = hw;
+                wrote = WR;
+            }
+        }
+        const int len = (int)(e - s);
+        const int maxlen = (int)group_max<64>((uint32_t)len);
+        if (maxlen > 0) stage_rows<H>(sh, col, colc, s, cf, maxlen > 16 ? 2 : 1, io.nnz);
+        // the next rows' extents and own values load while this step's
+        // gathers are in flight
+        int64_t sn = 0, en = 0;
+        uint32_t mn = 0;
+        int32_t lcn = 0;
+        if (more) {
+            sn = row_ptr[vn[0]];
+            en = row_ptr[vn[0] + 1];
+            mn = T[vn[0]];
+            lcn = RD ? lenc[vn[0]] : 0;
+        }
+        wave_lds_fence();
+        const int32_t *slot = &sh.idx[(lane / H) * kStagedStride];
+        for (int k0 = 0; k0 < maxlen; k0 += H * kStagedUnroll) {
+            int32_t x[kStagedUnroll];
+#pragma unroll
+            for (int u = 0; u < kStagedUnroll; u++) {
+                const int k = k0 + H * u + sub;
+                const int32_t y = slot[k < kStagedCap ? k : 0];
+                x[u] = k < len ? y : v[0];
+            }
+            uint32_t t[kStagedUnroll];
+#pragma unroll
+            for (int u = 0; u < kStagedUnroll; u++) t[u] = T[x[u]];
+#pragma unroll
+            for (int u = 0; u < kStagedUnroll; u++) m = min(m, t[u]);
+        }
+        m = group_min<H>(m);
+        bool keep = false;
+        if (ok[0] && sub == 0) {
+            if (m == kIn) m = kOut;
+            M[v[0]] = m;
+            keep = (m != kOut);
+            if (WR && keep && wrote) io.lenc_out[v[0]] = (int32_t)wc;
+        }
+        seg_append(io, sg, keep, v[0], kept);
+        wave_lds_fence();  // the slots are rewritten by the next step
+        if (more) {
+            v[0] = vn[0];
+            ok[0] = okn[0];
+            s = sn;
+            e = en;
+            m = mn;
+            lc = lcn;
+        }
+    }
+    if (io.deg_sum) wave_degsum(io.deg_sum, dsum, wsum);
+    return kept;
+}
+
+// Decide Set over the wavefront's segment, staged, with the next round's
+// Refresh Row for the vertices that stay undecided.
+template <int H>
+__device__ __forceinline__ uint32_t sweep_decide_staged(const int64_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ col,
+                                                        uint32_t *__restrict__ T,
+                                                        const uint32_t *__restrict__ M,
+                                                        const TupleParams &next, const SegIO &io,
+                                                        const Seg &sg, StagedLds<H> &sh) {
+    constexpr int R = 64 / H;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int sub = lane & (H - 1);
+    uint32_t kept = 0;
+    unsigned long long dsum = 0;
+    int32_t v[1];
+    bool ok[1];
+    int64_t s = 0, e = 0;
+    uint32_t t0 = 0, mv = 0;
+    if (sg.count > 0) {
+        load_rows<H, 1>(io, sg, 0, v, ok);
+        s = row_ptr[v[0]];
+        e = row_ptr[v[0] + 1];
+        t0 = T[v[0]];
+        mv = M[v[0]];
+    }
+    for (int64_t i0 = 0; i0 < sg.count; i0 += R) {
+        const bool more = i0 + R < sg.count;
+        int32_t vn[1] = {0};
+        bool okn[1] = {false};
+        if (more) load_rows<H, 1>(io, sg, i0 + R, vn, okn);
+        if (!ok[0]) e = s;
+        int any_out = (sub == 0) & (mv == kOut);
+        int all_eq = (sub != 0) | (mv == t0);
+        if (sub == 0) dsum += (unsigned long long)(e - s);
+        // M_v = OUT already decides the row (OUT), whatever the neighbours hold
+        if (mv == kOut) e = s;
+        uint64_t heavy = __ballot(sub == 0 && e - s > kStagedCap);
+        while (heavy) {
+            const int src = __ffsll((unsigned long long)heavy) - 1;
+            heavy &= heavy - 1;
+            const int64_t hs = __shfl(s, src, 64), he = __shfl(e, src, 64);
+            const uint32_t ht0 = __shfl(t0, src, 64);
+            int hao, hae;
+            coop_decide(col, M, hs, he, ht0, hao, hae);
+            if ((lane & ~(H - 1)) == src) {
+                if (sub == 0) {
+                    any_out |= hao;
+                    all_eq &= hae;
+                }
+                e = s;
+            }
+        }
+        const int len = (int)(e - s);
+        const int maxlen = (int)group_max<64>((uint32_t)len);
+        if (maxlen > 0) stage_rows<H>(sh, col, col, s, 0, maxlen > 16 ? 2 : 1, io.nnz);
+        int64_t sn = 0, en = 0;
+        uint32_t tn = 0, mvn = 0;
+        if (more) {
+            sn = row_ptr[vn[0]];
+            en = row_ptr[vn[0] + 1];
+            tn = T[vn[0]];
+            mvn = M[vn[0]];
+        }
+        wave_lds_fence();
+        const int32_t *slot = &sh.idx[(lane / H) * kStagedStride];
+        for (int k0 = 0; k0 < maxlen; k0 += H * kStagedUnroll) {
+            int32_t x[kStagedUnroll];
+#pragma unroll
+            for (int u = 0; u < kStagedUnroll; u++) {
+                const int k = k0 + H * u + sub;
+                const int32_t y = slot[k < kStagedCap ? k : 0];
+                x[u] = k < len ? y : v[0];
+            }
+            uint32_t mw[kStagedUnroll];
+#pragma unroll
+            for (int u = 0; u < kStagedUnroll; u++) mw[u] = M[x[u]];
+#pragma unroll
+            for (int u = 0; u < kStagedUnroll; u++) {
+                if (k0 + H * u + sub < len) {
+                    any_out |= (mw[u] == kOut);
+                    all_eq &= (mw[u] == t0) | (mw[u] == kAbsent);
+                }
+            }
+        }
+        any_out = (int)group_or<H>((uint32_t)any_out);
+        all_eq = (int)group_and<H>((uint32_t)all_eq);
+        bool keep = false;
+        if (ok[0] && sub == 0) {
+            uint32_t nt;
+            if (any_out) {
+                nt = kOut;
+            } else if (all_eq) {
+                nt = kIn;
+            } else {
+                nt = make_tuple(next, (uint32_t)v[0]);
+                keep = true;
+            }
+            T[v[0]] = nt;
+        }
+        seg_append(io, sg, keep, v[0], kept);
+        wave_lds_fence();
+        if (more) {
+            v[0] = vn[0];
+            ok[0] = okn[0];
+            s = sn;
+            e = en;
+            t0 = tn;
+            mv = mvn;
+        }
+    }
+    if (io.deg_sum) wave_degsum(io.deg_sum, dsum);
+    return kept;
+}
+
+// ---------------------------------------------------------------------------
 // Flat ("merge path") sweeps.  A wavefront takes its rows 64 at a time, one
 // per lane, lays their column indices out as one flat range (offsets and
 // starts in LDS) and lets every lane stream kFlatEP consecutive indices of
@@ -853,6 +1172,9 @@ __device__ __forceinline__ uint32_t any_column(const int64_t *__restrict__ row_p
     if constexpr (L == 0) {
         __shared__ FlatLds sh[kBlock / 64];
         return flat_column<kUnroll>(row_ptr, col, T, M, io, sg, sh[threadIdx.x >> 6]);
+    } else if constexpr (L == kStagedLanes) {
+        __shared__ StagedLds<1> sh[kBlock / 64];
+        return sweep_column_staged<1, RD, WR>(row_ptr, col, T, M, io, sg, sh[threadIdx.x >> 6]);
     } else {
         return sweep_column<L, kRows, kChunks<L>, RD, WR>(row_ptr, col, T, M, io, sg);
     }
@@ -868,6 +1190,9 @@ __device__ __forceinline__ uint32_t any_decide(const int64_t *__restrict__ row_p
     if constexpr (L == 0) {
         __shared__ FlatLds sh[kBlock / 64];
         return flat_decide<kUnroll>(row_ptr, col, T, M, next, io, sg, sh[threadIdx.x >> 6]);
+    } else if constexpr (L == kStagedLanes) {
+        __shared__ StagedLds<1> sh[kBlock / 64];
+        return sweep_decide_staged<1>(row_ptr, col, T, M, next, io, sg, sh[threadIdx.x >> 6]);
     } else {
         return sweep_decide<L, kRows, kChunks<L>>(row_ptr, col, T, M, next, io, sg);
     }
@@ -891,6 +1216,7 @@ __device__ __forceinline__ SegIO round_col_io(const RoundsArgs &a, int r) {
     io.n = a.n;
     io.seg = a.seg;
     io.S = a.S;
+    io.nnz = a.nnz;
     if (r == 0 && !a.masked) io.long_flag = a.lflag;
     return io;
 }
@@ -908,6 +1234,7 @@ __device__ __forceinline__ SegIO round_dec_io(const RoundsArgs &a, int r) {
     io.n = a.n;
     io.seg = a.seg;
     io.S = a.S;
+    io.nnz = a.nnz;
     return io;
 }
 
@@ -936,11 +1263,16 @@ __device__ __forceinline__ void round_start(const RoundsArgs &a, int r) {
         if (threadIdx.x == 0) {
             a.rt[(size_t)r * kRoundStride] = c1;
             a.rt[(size_t)r * kRoundStride + 1] = c2;
-            if (a.alive_host)
+            if (a.alive_host) {
+                // word 1: (round, |worklist2|), stored before word 0 so that a
+                // host that reads word 0 of round r finds word 1 of round r
+                __hip_atomic_store(a.alive_host + 1, ((unsigned long long)(uint32_t)r << 32) | c2,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 __hip_atomic_store(a.alive_host,
                                    ((unsigned long long)(uint32_t)r << 32) | c1 |
                                        (longs ? kLongRowsBit : 0u),
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                                   __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
         }
     }
     clear_slot(a.ctr, r);
@@ -1011,6 +1343,347 @@ __global__ __launch_bounds__(kBlock) void k_dec_round(const int64_t *__restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Tail: the last rounds of a run in one workgroup.  Once both worklists hold
+// at most kTailCap vertices, the round kernels would spend their time on
+// dispatching a full grid for a few thousand rows, and the host on issuing
+// them; one workgroup instead copies the per-wavefront lists into LDS and
+// runs Refresh Column, Decide Set and the compaction of both lists round
+// after round, with workgroup barriers between the phases (every wavefront
+// is on one compute unit, so the barriers order the global stores too),
+// until worklist1 is empty.  The arithmetic per row is that of the round
+// kernels: long rows (beyond kTailRowCap entries) go to a whole wavefront,
+// and rows longer than the plan's cooperative threshold are read and
+// rewritten in compacted form exactly as the launched rounds would.
+// ---------------------------------------------------------------------------
+constexpr int kTailThreads = 1024;
+constexpr int kTailWaves = kTailThreads / 64;
+constexpr int kTailRowCap = 32;  // longer rows: a whole wavefront each
+
+struct TailLds {
+    int32_t l1[kTailCap];
+    int32_t l2[kTailCap];
+    uint16_t off[kMaxBlocks];  // tail_gather: first list position of each workgroup's entries
+    uint8_t keep[kTailCap];
+    uint32_t wtot[kTailWaves];
+    unsigned long long wsum[kTailWaves][3];
+    uint32_t n1, n2;
+};
+
+// Exclusive prefix of x over the workgroup (in thread order); *total gets the
+// sum.  All threads call it; it ends with a barrier.
+__device__ __forceinline__ uint32_t tail_scan(TailLds &sh, uint32_t x, uint32_t *total) {
+    const int lane = (int)(threadIdx.x & 63u), w = (int)(threadIdx.x >> 6);
+    const uint32_t inc = wave_incl_scan(x);
+    if (lane == 63) sh.wtot[w] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int q = 0; q < kTailWaves; q++) {
+        const uint32_t c = sh.wtot[q];
+        before += q < w ? c : 0u;
+        all += c;
+    }
+    *total = all;
+    __syncthreads();
+    return before + inc - x;
+}
+
+// Sums over the workgroup of three counters (thread 0 gets them).
+__device__ __forceinline__ void tail_sum3(TailLds &sh, unsigned long long a, unsigned long long b,
+                                          unsigned long long c, unsigned long long *out) {
+    const int lane = (int)(threadIdx.x & 63u), w = (int)(threadIdx.x >> 6);
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+        c += __shfl_xor(c, off, 64);
+    }
+    if (lane == 0) {
+        sh.wsum[w][0] = a;
+        sh.wsum[w][1] = b;
+        sh.wsum[w][2] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = out[1] = out[2] = 0;
+        for (int q = 0; q < kTailWaves; q++)
+            for (int k = 0; k < 3; k++) out[k] += sh.wsum[q][k];
+    }
+    __syncthreads();
+}
+
+// Copies the per-wavefront segments of a worklist (S = 4 B segments of seg
+// slots, counts cnt; wavefronts 4b .. 4b + 3 belong to workgroup b) into dst
+// in segment order; returns the size (at most kTailCap, which the host
+// checked; more returns 0xFFFFFFFF).  Thread t first adds the counts of
+// workgroups tJ .. tJ + J - 1 (16-byte loads, all in flight at once), a
+// workgroup scan gives each workgroup its first position (kept in LDS as 16
+// bits), and then every thread copies up to kTailCap / kTailThreads entries:
+// a binary search in those positions finds an entry's workgroup, its four
+// counts its wavefront.
+__device__ uint32_t tail_gather(TailLds &sh, const int32_t *wl, const uint32_t *cnt, int64_t S,
+                                int64_t seg, int32_t *dst) {
+    constexpr int kJ = kMaxBlocks / kTailThreads;  // workgroups per thread, at most
+    const int B = (int)(S / 4);
+    const int J = (B + kTailThreads - 1) / kTailThreads;
+    const int tid = (int)threadIdx.x;
+    uint32_t tot[kJ];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int j = 0; j < kJ; j++) {
+        const int b = tid * J + j;
+        const bool ok = j < J && b < B;
+        const uint4 c = *(const uint4 *)(cnt + 4 * (size_t)(ok ? b : 0));
+        tot[j] = ok ? c.x + c.y + c.z + c.w : 0u;
+        mine += tot[j];
+    }
+    uint32_t total = 0;
+    uint32_t at = tail_scan(sh, mine, &total);
+    if (total > (uint32_t)kTailCap) return 0xFFFFFFFFu;  // the same in every thread
+#pragma unroll
+    for (int j = 0; j < kJ; j++) {
+        const int b = tid * J + j;
+        if (j < J && b < B) sh.off[b] = (uint16_t)at;
+        at += tot[j];
+    }
+    __syncthreads();
+    constexpr int kPer = kTailCap / kTailThreads;
+    int32_t val[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; i++) {
+        const uint32_t p = (uint32_t)(tid + i * kTailThreads);
+        // the last workgroup whose first position is <= p (a workgroup after
+        // an empty one starts where it starts, so this one holds entry p)
+        int lo = 0, hi = B - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if ((uint32_t)sh.off[mid] <= p) lo = mid; else hi = mid - 1;
+        }
+        const bool ok = p < total;
+        const uint4 c = *(const uint4 *)(cnt + 4 * (size_t)lo);
+        uint32_t q = ok ? p - (uint32_t)sh.off[lo] : 0u;
+        int w = 0;
+        if (q >= c.x) { q -= c.x; w = 1;
+            if (q >= c.y) { q -= c.y; w = 2;
+                if (q >= c.z) { q -= c.z; w = 3; } } }
+        // positions past the end read slot 0 (always within the list)
+        val[i] = wl[ok ? (4 * (int64_t)lo + w) * seg + q : 0];
+    }
+#pragma unroll
+    for (int i = 0; i < kPer; i++) {
+        const uint32_t p = (uint32_t)(tid + i * kTailThreads);
+        if (p < total) dst[p] = val[i];
+    }
+    __syncthreads();
+    return total;
+}
+
+// Keeps the entries of list[0, n) whose sh.keep flag is set, in order and in
+// place: entries are taken kTailThreads at a time, and each chunk is read
+// before any slot of it is written.  Returns the new size.
+__device__ uint32_t tail_compact(TailLds &sh, int32_t *list, uint32_t n) {
+    uint32_t kept = 0;
+    for (uint32_t i0 = 0; i0 < n; i0 += kTailThreads) {
+        const uint32_t i = i0 + threadIdx.x;
+        const bool keep = i < n && sh.keep[i] != 0;
+        const int32_t v = i < n ? list[i] : 0;
+        uint32_t total = 0;
+        const uint32_t pos = tail_scan(sh, keep ? 1u : 0u, &total);  // ends with a barrier
+        if (keep) list[kept + pos] = v;
+        kept += total;
+        __syncthreads();
+    }
+    return kept;
+}
+
+// Device wall clock (constant rate) into two round-table words.
+__device__ __forceinline__ void stamp(uint32_t *p) {
+    const uint64_t t = wall_clock64();
+    p[0] = (uint32_t)t;
+    p[1] = (uint32_t)(t >> 32);
+}
+
+struct TailArgs {
+    int r0;          // first round run here
+    int cstart;      // first compacting round (mode 1), later rounds mode 2; < 0: no compaction
+    int64_t thr;     // cooperative threshold of the launched plan (rows longer are compacted)
+    uint32_t *rt_host;               // host-pinned round table of this phase (rows >= r0)
+    unsigned long long *end_host;    // host-pinned: rounds + 1 of the run, written at the end
+};
+
+__global__ __launch_bounds__(kTailThreads) void k_tail(const int64_t *__restrict__ row_ptr,
+                                                       const int32_t *__restrict__ col,
+                                                       uint32_t *__restrict__ T,
+                                                       uint32_t *__restrict__ M, RoundsArgs a,
+                                                       TailArgs ta) {
+    __shared__ TailLds sh;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int tid = (int)threadIdx.x;
+    int r = ta.r0;
+    {
+        const int cur = r & 1;
+        const uint32_t c1 = tail_gather(sh, a.wl1[cur], a.cnt1[cur], a.S, a.seg, sh.l1);
+        const uint32_t c2 = tail_gather(sh, a.wl2[cur], a.cnt2[cur], a.S, a.seg, sh.l2);
+        if (tid == 0) {
+            sh.n1 = c1;
+            sh.n2 = c2;
+        }
+        __syncthreads();
+    }
+    for (;;) {
+        const uint32_t n1 = sh.n1, n2 = sh.n2;
+        uint32_t *rth = ta.rt_host + (size_t)r * kRoundStride;
+        if (tid == 0) {
+            a.rt[(size_t)r * kRoundStride] = n1;
+            a.rt[(size_t)r * kRoundStride + 1] = n2;
+            rth[0] = n1;
+            rth[1] = n2;
+            stamp(rth + kRtStamp0);  // wall-clock stamps of the round's phases
+        }
+        if (n1 == 0u || n1 == 0xFFFFFFFFu || n2 == 0xFFFFFFFFu || r + 2 >= a.max_rounds) break;
+        const bool rd = ta.cstart >= 0 && r > ta.cstart && a.colc;
+        const bool wr = ta.cstart >= 0 && r >= ta.cstart && a.colc;
+        // Refresh Column over worklist2
+        unsigned long long dcol = 0, dwr = 0;
+        for (uint32_t i0 = 0; i0 < n2; i0 += kTailThreads) {
+            const bool has = i0 + (uint32_t)tid < n2;
+            const int32_t v = has ? sh.l2[i0 + tid] : 0;
+            int64_t s = row_ptr[v], e = has ? row_ptr[v + 1] : s;
+            const bool cf = rd && e - s > ta.thr;
+            if (cf) e = s + a.lenc[v];
+            const int32_t *src = cf ? a.colc : col;
+            uint32_t m = T[v];
+            dcol += (unsigned long long)(e - s);
+            uint32_t wc = 0;
+            bool wrote = false;
+            uint64_t heavy = __ballot(e - s > kTailRowCap);
+            while (heavy) {
+                const int q = __ffsll((unsigned long long)heavy) - 1;
+                heavy &= heavy - 1;
+                const int64_t hs = __shfl(s, q, 64), he = __shfl(e, q, 64);
+                const bool hcf = __shfl((int)cf, q, 64) != 0;
+                // rewritten only where the launched rounds would rewrite it
+                const bool hw = wr && he - hs > ta.thr;
+                uint32_t hwc = 0;
+                const uint32_t hm = coop_min_T(hcf ? a.colc : col, T, hs, he,
+                                               hw ? a.colc : nullptr, hw ? &hwc : nullptr);
+                if (lane == 0) dwr += hwc;
+                if (lane == q) {
+                    m = min(m, hm);
+                    e = s;
+                    wc = hwc;
+                    wrote = hw;
+                }
+            }
+            {
+                // a short row's entries all load at once, from clamped valid
+                // addresses (entry 0 exists: the host runs the tail only when
+                // nnz > 0); slots past the row's end gather v itself
+                const int64_t hi = e > s ? e - 1 : 0;
+                int32_t x[kTailRowCap];
+#pragma unroll
+                for (int k = 0; k < kTailRowCap; k++) {
+                    const int32_t y = src[min(s + k, hi)];
+                    x[k] = s + k < e ? y : v;
+                }
+                uint32_t t[kTailRowCap];
+#pragma unroll
+                for (int k = 0; k < kTailRowCap; k++) t[k] = T[x[k]];
+#pragma unroll
+                for (int k = 0; k < kTailRowCap; k++) m = min(m, t[k]);
+            }
+            if (has) {
+                if (m == kIn) m = kOut;
+                M[v] = m;
+                sh.keep[i0 + tid] = m != kOut;
+                if (wrote && m != kOut) a.lenc[v] = (int32_t)wc;
+            }
+        }
+        __syncthreads();  // M of this round is complete
+        const uint32_t kept2 = tail_compact(sh, sh.l2, n2);
+        if (tid == 0) stamp(rth + kRtStamp1);
+        // Decide Set over worklist1, with the next round's tuples
+        const TupleParams next{xs64star((a.seed << 32) ^ (uint64_t)(r + 1)), a.pmask, a.b, a.batch};
+        unsigned long long ddec = 0;
+        for (uint32_t i0 = 0; i0 < n1; i0 += kTailThreads) {
+            const bool has = i0 + (uint32_t)tid < n1;
+            const int32_t v = has ? sh.l1[i0 + tid] : 0;
+            int64_t s = row_ptr[v], e = has ? row_ptr[v + 1] : s;
+            const uint32_t t0 = T[v], mv = M[v];
+            ddec += (unsigned long long)(e - s);
+            int any_out = mv == kOut, all_eq = mv == t0;
+            if (mv == kOut) e = s;
+            uint64_t heavy = __ballot(e - s > kTailRowCap);
+            while (heavy) {
+                const int q = __ffsll((unsigned long long)heavy) - 1;
+                heavy &= heavy - 1;
+                const int64_t hs = __shfl(s, q, 64), he = __shfl(e, q, 64);
+                const uint32_t ht0 = __shfl(t0, q, 64);
+                int hao, hae;
+                coop_decide(col, M, hs, he, ht0, hao, hae);
+                if (lane == q) {
+                    any_out |= hao;
+                    all_eq &= hae;
+                    e = s;
+                }
+            }
+            {
+                const int64_t hi = e > s ? e - 1 : 0;
+                int32_t x[kTailRowCap];
+#pragma unroll
+                for (int k = 0; k < kTailRowCap; k++) {
+                    const int32_t y = col[min(s + k, hi)];
+                    x[k] = s + k < e ? y : v;
+                }
+                uint32_t mw[kTailRowCap];
+#pragma unroll
+                for (int k = 0; k < kTailRowCap; k++) mw[k] = M[x[k]];
+#pragma unroll
+                for (int k = 0; k < kTailRowCap; k++) {
+                    if (s + k < e) {
+                        any_out |= (mw[k] == kOut);
+                        all_eq &= (mw[k] == t0) | (mw[k] == kAbsent);
+                    }
+                }
+            }
+            if (has) {
+                uint32_t nt;
+                bool keep = false;
+                if (any_out) {
+                    nt = kOut;
+                } else if (all_eq) {
+                    nt = kIn;
+                } else {
+                    nt = make_tuple(next, (uint32_t)v);
+                    keep = true;
+                }
+                T[v] = nt;
+                sh.keep[i0 + tid] = keep;
+            }
+        }
+        __syncthreads();
+        const uint32_t kept1 = tail_compact(sh, sh.l1, n1);
+        if (tid == 0) stamp(rth + kRtStamp2);
+        if (a.degs) {
+            unsigned long long tot[3];
+            tail_sum3(sh, ddec, dcol, dwr, tot);
+            if (tid == 0) {
+                a.degs[kDegStride * r] = tot[0];
+                a.degs[kDegStride * r + 1] = tot[1];
+                a.degs[kDegStride * r + 2] = tot[2];
+            }
+        }
+        if (tid == 0) {
+            sh.n1 = kept1;
+            sh.n2 = kept2;
+        }
+        __syncthreads();  // T of this round and the new sizes are complete
+        r++;
+    }
+    if (tid == 0)
+        __hip_atomic_store(ta.end_host, (unsigned long long)(r + 1), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// ---------------------------------------------------------------------------
 // Persistent form: one cooperative launch runs every round of Algorithm 1.
 // The grid synchronises twice per round (after Refresh Column and after
 // Decide Set) with an epoch barrier: each workgroup publishes its epoch in
@@ -1030,12 +1703,6 @@ __device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Device wall clock (constant rate) into two round-table words.
-__device__ __forceinline__ void stamp(uint32_t *p) {
-    const uint64_t t = wall_clock64();
-    p[0] = (uint32_t)t;
-    p[1] = (uint32_t)(t >> 32);
-}
 
 // Returns false if the barrier timed out (or had timed out before).
 __device__ bool grid_barrier(uint32_t *flags, uint32_t *gen, uint32_t *abort_word,
@@ -1488,6 +2155,7 @@ TupleParams tuple_params(int64_t n, uint64_t seed, uint64_t iter) {
         case 16: hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__); break;                    \
         case 32: hipLaunchKernelGGL(KERNEL<32>, __VA_ARGS__); break;                    \
         case 64: hipLaunchKernelGGL(KERNEL<64>, __VA_ARGS__); break;                    \
+        case kStagedLanes: hipLaunchKernelGGL(KERNEL<kStagedLanes>, __VA_ARGS__); break; \
         default: return hipErrorInvalidValue;                                           \
     }
 
@@ -1504,6 +2172,7 @@ TupleParams tuple_params(int64_t n, uint64_t seed, uint64_t iter) {
             case 16: hipExtLaunchKernelGGL(KERNEL<16>, GRID, BLOCK, 0, S, E0, E1, 0, __VA_ARGS__); break; \
             case 32: hipExtLaunchKernelGGL(KERNEL<32>, GRID, BLOCK, 0, S, E0, E1, 0, __VA_ARGS__); break; \
             case 64: hipExtLaunchKernelGGL(KERNEL<64>, GRID, BLOCK, 0, S, E0, E1, 0, __VA_ARGS__); break; \
+            case kStagedLanes: hipExtLaunchKernelGGL(KERNEL<kStagedLanes>, GRID, BLOCK, 0, S, E0, E1, 0, __VA_ARGS__); break; \
             default: return hipErrorInvalidValue;                                       \
         }                                                                               \
     } else {                                                                            \
@@ -1542,6 +2211,24 @@ hipError_t launch_dec_round(int lanes, int blocks, const int64_t *row_ptr, const
     return hipGetLastError();
 }
 
+hipError_t launch_tail(const int64_t *row_ptr, const int32_t *col, uint32_t *T, uint32_t *M,
+                       const RoundsArgs &a, int r0, int cstart, int64_t thr, uint32_t *rt_host,
+                       unsigned long long *end_host, hipStream_t s, hipEvent_t e0,
+                       hipEvent_t e1) {
+    TailArgs ta{r0, cstart, thr, rt_host, end_host};
+    if (e0)
+        hipExtLaunchKernelGGL(k_tail, dim3(1), dim3(kTailThreads), 0, s, e0, e1, 0, row_ptr, col, T,
+                              M, a, ta);
+    else
+        hipLaunchKernelGGL(k_tail, dim3(1), dim3(kTailThreads), 0, s, row_ptr, col, T, M, a, ta);
+    return hipGetLastError();
+}
+
+int64_t coop_threshold(int lanes) {
+    if (lanes == kStagedLanes) return kStagedCap;
+    return lanes >= 64 ? 1024 : (int64_t)32 * std::max(lanes, 1);
+}
+
 hipError_t launch_init_tuples(const TupleParams &tp, int64_t n, uint32_t *T, hipStream_t s) {
     hipLaunchKernelGGL(k_init_tuples, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, tp, n,
                        T);
@@ -1566,6 +2253,17 @@ hipError_t launch_rounds_t(int blocks, const int64_t *row_ptr, const int32_t *co
                                       0, s);
 }
 
+int sweep_resident_blocks(int lanes, int num_cus) {
+    int per_cu = 0, per_cu2 = 0;
+    hipError_t e = hipErrorInvalidValue, e2 = hipErrorInvalidValue;
+    if (lanes == kStagedLanes) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_col_round<kStagedLanes>, kBlock, 0);
+        e2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, k_dec_round<kStagedLanes>, kBlock, 0);
+    }
+    if (e != hipSuccess || e2 != hipSuccess || per_cu <= 0 || per_cu2 <= 0) return 0;
+    return std::min(per_cu, per_cu2) * num_cus;
+}
+
 int rounds_max_blocks(int lanes, int num_cus) {
     int per_cu = 0;
     hipError_t e = hipErrorInvalidValue;
@@ -1578,6 +2276,9 @@ int rounds_max_blocks(int lanes, int num_cus) {
         case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rounds<16>, kBlock, 0); break;
         case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rounds<32>, kBlock, 0); break;
         case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rounds<64>, kBlock, 0); break;
+        case kStagedLanes:
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rounds<kStagedLanes>, kBlock, 0);
+            break;
         default: break;
     }
     if (e != hipSuccess || per_cu <= 0) return 0;
@@ -1595,6 +2296,7 @@ hipError_t launch_rounds(int lanes, int blocks, const int64_t *row_ptr, const in
         case 16: return launch_rounds_t<16>(blocks, row_ptr, col, T, M, a, s);
         case 32: return launch_rounds_t<32>(blocks, row_ptr, col, T, M, a, s);
         case 64: return launch_rounds_t<64>(blocks, row_ptr, col, T, M, a, s);
+        case kStagedLanes: return launch_rounds_t<kStagedLanes>(blocks, row_ptr, col, T, M, a, s);
         default: return hipErrorInvalidValue;
     }
 }

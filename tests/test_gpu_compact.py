@@ -42,7 +42,9 @@ GRAPHS = {
 
 def _heavy_threshold(lanes):
     # rows longer than this are streamed by the whole wavefront (and only
-    # those are rewritten in compacted form)
+    # those are rewritten in compacted form); -2: the staged sweeps' LDS slot
+    if lanes == -2:
+        return 32
     return 1024 if lanes >= 64 else 32 * lanes
 
 
@@ -84,7 +86,7 @@ def test_compaction_on_and_off_match_oracle(api, name):
         _agg_matches(off, rp, cc, seed, name)
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 64])
+@pytest.mark.parametrize("lanes", [-2, 1, 2, 4, 8, 16, 64])
 def test_compaction_every_lane_plan(api, lanes):
     # chunglu_50k has rows past every lane plan's cooperative threshold, so
     # the whole-wavefront rewrite of long rows runs too
@@ -128,7 +130,7 @@ def test_compaction_needs_workspace_room(api):
         del ws
 
 
-@pytest.mark.parametrize("lanes", [1, 4])
+@pytest.mark.parametrize("lanes", [1, 4, -2])
 @pytest.mark.parametrize("name", ["grid27_30", "chunglu_50k", "dropped7_20"])
 def test_compacted_sweeps_visit_exactly_the_live_neighbours(api, name, lanes):
     # Refresh Column of round r reads, for each v of worklist2, the whole
@@ -169,7 +171,8 @@ def test_compacted_sweeps_visit_exactly_the_live_neighbours(api, name, lanes):
                     for r in range(o["n_iters"])]
 
 
-def test_stale_workspace_contents_do_not_matter(api):
+@pytest.mark.parametrize("lanes", [4, -2])
+def test_stale_workspace_contents_do_not_matter(api, lanes):
     # Lanes past a row's end must not gather through entries of the
     # compacted array that this run never wrote (here vertex 0's row, short,
     # so entry 0 keeps whatever the workspace held): fill the workspace with
@@ -183,7 +186,7 @@ def test_stale_workspace_contents_do_not_matter(api):
         gs.append(graphs.disjoint_union([graphs.erdos_renyi(n, float(min(0.5, 8.0 / n)), seed=k),
                                          graphs.star(300, 5)]))
     gs.append(GRAPHS["chunglu_50k"]())
-    c = api.Context(0, lanes=4)
+    c = api.Context(0, lanes=lanes)
     for i, (rp, cc) in enumerate(gs):
         n, nnz = rp.size - 1, int(rp[-1])
         c.ensure_workspace(n, _lib.MIS2_OP_AGGREGATE, nnz)

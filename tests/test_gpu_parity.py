@@ -83,7 +83,7 @@ def test_mis2_parity_seeds(ctx, seed):
     _check_mis2(ctx, rp, c, seed, "seed%d" % seed)
 
 
-@pytest.mark.parametrize("lanes", [-1, 1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("lanes", [-2, -1, 1, 2, 4, 8, 16, 32, 64])
 def test_mis2_every_lane_plan(api, lanes):
     for blocks in (1, 13, 0, 8192):
         for persistent in (True, False):
@@ -91,6 +91,15 @@ def test_mis2_every_lane_plan(api, lanes):
             for name in ("grid27_ragged", "chunglu_50k", "star70"):
                 rp, cc = dict(SMALL)[name]
                 _check_mis2(c, rp, cc, 0, "%s L%d B%d P%d" % (name, lanes, blocks, persistent))
+
+
+def test_staged_plan_on_tiny_graphs(api):
+    # fewer than 4 entries: the staged plan falls back to one lane per row
+    c = api.Context(0, lanes=-2)
+    for name, (rp, cc) in [("path2", graphs.path(2)), ("path3", graphs.path(3)),
+                           ("edgeless5", graphs.edgeless(5)), ("path4", graphs.path(4))]:
+        _check_mis2(c, rp, cc, 0, "staged " + name)
+        _check_agg(c, rp, cc, 0, "staged " + name)
 
 
 def test_mis2_repeatable(ctx):
@@ -137,7 +146,7 @@ def test_aggregate_parity_small(ctx, name):
     _check_agg(ctx, rp, c, 0, name)
 
 
-@pytest.mark.parametrize("lanes", [-1, 1, 8, 64])
+@pytest.mark.parametrize("lanes", [-2, -1, 1, 8, 64])
 def test_aggregate_lane_plans(api, lanes):
     for persistent in (True, False):
         c = api.Context(0, lanes=lanes, blocks=7, persistent=persistent)
@@ -190,10 +199,12 @@ def test_c2_grid27_100(ctx, api):
     _say("C2 27-point 100^3", rp.size - 1, int(rp[-1]))
     _check_mis2(ctx, rp, c, 0, "C2")
     _check_agg(ctx, rp, c, 0, "C2")
-    for lanes in (-1, 4):
+    for lanes in (-2, -1, 4):
         for persistent in (True, False):
             other = api.Context(0, persistent=persistent, lanes=lanes)
             _check_mis2(other, rp, c, 0, "C2 lanes %d persistent %d" % (lanes, persistent))
+    staged = api.Context(0, lanes=-2)
+    _check_agg(staged, rp, c, 0, "C2 staged")
 
 
 def test_c3_chung_lu_4m(ctx, api):
@@ -203,6 +214,9 @@ def test_c3_chung_lu_4m(ctx, api):
     _check_agg(ctx, rp, c, 0, "C3")
     flat = api.Context(0, lanes=-1)
     _check_mis2(flat, rp, c, 0, "C3 flat")
+    staged = api.Context(0, lanes=-2)
+    _check_mis2(staged, rp, c, 0, "C3 staged")
+    _check_agg(staged, rp, c, 0, "C3 staged")
 
 
 # ---------------------------------------------------------------- quotient / multilevel
