@@ -155,6 +155,30 @@ int mis2_run(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, uint8_t *status,
              int64_t *n_roots, int32_t *n_iters, void *stream);
 
 /*
+ * mis2_run_noalloc -- mis2_run for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as mis2_run, but the
+ * workspace is a static device array of the library (48 MiB, one copy per
+ * GPU, held until the process ends) instead of the one set with
+ * mis2_set_workspace, which is neither needed nor touched.  The call makes
+ * no hipMalloc, hipFree or other allocating call.  The array's device
+ * address is taken by mis2_create on each device.
+ *
+ * Limit: n <= mis2_run_noalloc_max_n() (about 2 million vertices); a larger
+ * graph returns MIS2_ENOSPACE before any GPU work.  MIS2_OPT_PROFILE must be
+ * off (MIS2_EINVAL otherwise: profiling creates events).
+ * Every call on one GPU shares that GPU's array: two calls that overlap in
+ * time on the same GPU (other threads, contexts or streams) race and may
+ * return wrong results.  Calls in sequence are safe: each run initialises
+ * every word it reads.
+ */
+int mis2_run_noalloc(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, uint8_t *status,
+                     int64_t *n_roots, int32_t *n_iters, void *stream);
+
+/* Largest n that mis2_run_noalloc accepts; written to *max_n (host). */
+int mis2_run_noalloc_max_n(int64_t *max_n);
+
+/*
  * mis2_run_ablation -- Algorithm 1 with the optimizations of Section V taken
  * away, for the comparison of Fig. 2 and Table I.  flags (bitwise or):
  */

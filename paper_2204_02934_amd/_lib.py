@@ -48,7 +48,7 @@ EXPORTS = (
     "mis2_coarsen", "mis2_batch_workspace_bytes", "mis2_aggregate_batched",
     "mis2_server_bytes", "mis2_server_create", "mis2_server_destroy", "mis2_server_last_error",
     "mis2_server_submit", "mis2_server_step", "mis2_server_poll",
-    "mis2_last_plan", "mis2_last_tuning",
+    "mis2_run_noalloc", "mis2_run_noalloc_max_n", "mis2_last_plan", "mis2_last_tuning",
 )
 
 MIS2_SERVE_MAX_LEVELS = 32
@@ -116,6 +116,9 @@ def load():
                                                     ctypes.POINTER(ctypes.c_size_t)]),
         "mis2_set_workspace": (ctypes.c_int, [vp, vp, ctypes.c_size_t]),
         "mis2_run": (ctypes.c_int, [vp, gp, u64, vp, ctypes.POINTER(i64), ctypes.POINTER(i32), vp]),
+        "mis2_run_noalloc": (ctypes.c_int, [vp, gp, u64, vp, ctypes.POINTER(i64),
+                                            ctypes.POINTER(i32), vp]),
+        "mis2_run_noalloc_max_n": (ctypes.c_int, [ctypes.POINTER(i64)]),
         "mis2_last_trace": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(i64), i32,
                                            ctypes.POINTER(i32)]),
         "mis2_aggregate": (ctypes.c_int, [vp, gp, u64, vp, ctypes.POINTER(i64), vp, vp]),

@@ -109,6 +109,23 @@ class Context:
         del keep
         return status[:g.n], nr.value, ni.value
 
+    def mis2_noalloc(self, row_ptr, col, status, seed=0, stream=None, nnz=None):
+        """Algorithm 1 through mis2_run_noalloc: the library's static device
+        scratch is the workspace and the call allocates nothing; the caller
+        passes the uint8 status tensor (>= n entries).  Returns (n_roots,
+        n_iters)."""
+        g, keep = self.graph(row_ptr, col, nnz)
+        if g.n > 0 and (status.dtype != torch.uint8 or status.numel() < g.n or
+                        status.device != self.device):
+            raise ValueError("status must be a uint8 tensor of >= n entries on " + str(self.device))
+        nr, ni = ctypes.c_int64(0), ctypes.c_int32(0)
+        rc = self.lib.mis2_run_noalloc(self.ptr, ctypes.byref(g), ctypes.c_uint64(seed),
+                                       ctypes.c_void_p(status.data_ptr()), ctypes.byref(nr),
+                                       ctypes.byref(ni), _stream_ptr(stream, self.device))
+        _check(self.lib, self.ptr, rc)
+        del keep
+        return nr.value, ni.value
+
     def aggregate(self, row_ptr, col, seed=0, stream=None, nnz=None, want_roots=False):
         """Algorithm 3.  Returns (agg int32[n] on the GPU, n_agg) or, with
         want_roots, (agg, n_agg, roots uint8[n])."""

@@ -897,6 +897,40 @@ bool carve(void *base, size_t bytes, int64_t n, int op, Workspace *ws) {
 
 }  // namespace mis2
 
+namespace {
+
+// Workspace of mis2_run_noalloc: a device global array, so that the call
+// allocates nothing.  Every GPU the library runs on holds its own copy until
+// the process ends.  In host code `scratch` names a host-side stand-in, not
+// device memory: its device address on each GPU is taken once, with that GPU
+// current, when the first context on it is created, and only that address
+// is handed to kernels and copies.
+constexpr size_t kScratchBytes = (size_t)48 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};  // device address of `scratch` per device
+
+// Called with `device` current.  Returns the HIP error of the address query.
+hipError_t take_scratch_address(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return hipSuccess;  // the call reports it
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) g_scratch_ptr[device] = ptr;
+    return e;
+}
+
+void *scratch_address(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
+
 extern "C" {
 
 int mis2_create(mis2_ctx **out, int device) {
@@ -910,6 +944,10 @@ int mis2_create(mis2_ctx **out, int device) {
     ctx->seen.reserve(kSeenCap + 1);
     ctx->tuning.reserve(8);
     if (hipSetDevice(device) != hipSuccess) {
+        delete ctx;
+        return MIS2_EHIP;
+    }
+    if (take_scratch_address(device) != hipSuccess) {
         delete ctx;
         return MIS2_EHIP;
     }
@@ -1071,6 +1109,50 @@ int mis2_run(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, uint8_t *status,
     if (n_roots) *n_roots = ctx->pinned[0];
     if (n_iters) *n_iters = iters;
     return collect_sweeps(ctx, launches, ws, s);
+}
+
+int mis2_run_noalloc_max_n(int64_t *max_n) {
+    if (!max_n) return MIS2_EINVAL;
+    int64_t lo = 0, hi = (int64_t)0x7FFFFFFE;
+    while (lo < hi) {  // largest n whose MIS-2 workspace fits the scratch array
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (workspace_bytes(mid, MIS2_OP_MIS2) <= kScratchBytes) lo = mid; else hi = mid - 1;
+    }
+    *max_n = lo;
+    return MIS2_OK;
+}
+
+int mis2_run_noalloc(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, uint8_t *status,
+                     int64_t *n_roots, int32_t *n_iters, void *stream) {
+    int rc = check_graph_args(ctx, g);
+    if (rc) return rc;
+    if (ctx->profile)
+        return fail(ctx, MIS2_EINVAL, "mis2_run_noalloc: profiling creates events; switch "
+                                      "MIS2_OPT_PROFILE off");
+    const size_t need = workspace_bytes(g->n, MIS2_OP_MIS2);
+    if (need > kScratchBytes) {
+        int64_t max_n = 0;
+        (void)mis2_run_noalloc_max_n(&max_n);
+        return fail(ctx, MIS2_ENOSPACE,
+                    "mis2_run_noalloc: n = %lld needs %zu bytes of workspace; the static scratch "
+                    "holds %zu (n <= %lld)", (long long)g->n, need, kScratchBytes,
+                    (long long)max_n);
+    }
+    void *ptr = scratch_address(ctx->device);
+    if (!ptr)
+        return fail(ctx, MIS2_EHIP, "mis2_run_noalloc: no scratch address for device %d",
+                    ctx->device);
+    // mis2_run with the scratch as the workspace; it writes every word it
+    // later reads (counters, round table and flags are filled by its first
+    // launch), so nothing from an earlier call leaks into this one
+    void *const saved = ctx->ws;
+    const size_t saved_bytes = ctx->ws_bytes;
+    ctx->ws = ptr;
+    ctx->ws_bytes = kScratchBytes;
+    rc = mis2_run(ctx, g, seed, status, n_roots, n_iters, stream);
+    ctx->ws = saved;
+    ctx->ws_bytes = saved_bytes;
+    return rc;
 }
 
 int mis2_ablation_workspace_bytes(int64_t n, int flags, size_t *bytes) {
