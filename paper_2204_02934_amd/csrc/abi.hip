@@ -168,9 +168,10 @@ Geometry geometry(const mis2_ctx *ctx, int64_t n, int lanes) {
 // 0..rounds-1): queue_trace copies them to pinned memory on the stream; after
 // the call's final synchronisation parse_trace turns them into ctx->trace and
 // the round count (the first round with an empty worklist1 ends the run).
-int queue_trace(mis2_ctx *ctx, const Workspace &ws, int phase, int rounds, hipStream_t s) {
+int queue_trace(mis2_ctx *ctx, const Workspace &ws, int phase, int rounds, hipStream_t s,
+                bool written = false) {
     ctx->trace_rounds[phase] = rounds;
-    if (rounds > 0)
+    if (rounds > 0 && !written)
         HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned_rt + (size_t)phase * (kTraceCap + 2) * kRoundStride,
                                     ws.rt, (size_t)rounds * kRoundStride * sizeof(uint32_t),
                                     hipMemcpyDeviceToHost, s));
@@ -291,6 +292,7 @@ RoundsArgs round_args(const mis2_ctx *ctx, const mis2_graph *g, uint64_t seed,
         a.cnt2[i] = ws.cnt2[i];
     }
     a.rt = ws.rt;
+    a.rt_host = nullptr;  // set by run_rounds for launched rounds
     a.ctr = ws.ctr;
     a.alive_host = ctx->alive_host;
     a.degs = ctx->account ? degs : nullptr;
@@ -354,6 +356,9 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
         if (rc != kFallBack) return rc;
     }
     RoundsArgs a = round_args(ctx, g, seed, ws, gm, masked, degs, lanes);
+    // workgroup 0 of each Refresh Column writes its round's sizes straight
+    // into the host-pinned round table of this phase
+    a.rt_host = ctx->pinned_rt + (size_t)phase * (kTraceCap + 2) * kRoundStride;
     if (abl) {
         a.colc = nullptr;
         a.lenc = nullptr;
@@ -425,8 +430,9 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
                     // the tail stamps its rounds' phases in the round table
                     ctx->stamps_valid[phase] = 1;
                     *iters_out = round;
-                    // rows before the tail's first round; the tail writes the rest
-                    int rc = queue_trace(ctx, ws, phase, round, s);
+                    // every row is in host memory already (the launched rounds
+                    // and the tail write them)
+                    int rc = queue_trace(ctx, ws, phase, round, s, true);
                     ctx->tail_used[phase] = 1;
                     return rc;
                 }
@@ -473,7 +479,7 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
     if (!masked) *long_rows = longs > 0 ? 1 : 0;
     ctx->stamps_valid[phase] = 0;
     *iters_out = round;  // rounds issued; parse_trace gives the count after the sync
-    return queue_trace(ctx, ws, phase, round, s);
+    return queue_trace(ctx, ws, phase, round, s, true);
 }
 
 // Fill ctx->sweeps from the launches of the finished call.
@@ -957,8 +963,9 @@ int mis2_create(mis2_ctx **out, int device) {
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
         ctx->wall_khz = (double)khz;
+    // coherent: kernels write scalars into it directly
     if (hipHostMalloc((void **)&ctx->pinned, (64 + 2 * kTraceCap) * sizeof(uint32_t),
-                      hipHostMallocDefault) != hipSuccess) {
+                      hipHostMallocCoherent) != hipSuccess) {
         delete ctx;
         return MIS2_EHIP;
     }
@@ -975,9 +982,10 @@ int mis2_create(mis2_ctx **out, int device) {
         delete ctx;
         return MIS2_EHIP;
     }
+    // coherent: the round kernels write their rows into it directly
     if (hipHostMalloc((void **)&ctx->pinned_rt,
                       2 * (size_t)(kTraceCap + 2) * kRoundStride * sizeof(uint32_t),
-                      hipHostMallocDefault) != hipSuccess) {
+                      hipHostMallocCoherent) != hipSuccess) {
         (void)hipHostFree(ctx->pinned);
         (void)hipHostFree(ctx->pinned_ctr);
         (void)hipHostFree(ctx->alive_host);
@@ -1102,11 +1110,11 @@ int mis2_run(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, uint8_t *status,
     int long_rows = 0;
     if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, &iters, &launches, &long_rows)))
         return rc;
-    HIP_TRY(ctx, launch_status(g->n, ws.T, status, ws.blocksum, ws.scalars + kS_Roots, s));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, ws.scalars + kS_Roots, 4, hipMemcpyDeviceToHost, s));
+    // the root count goes straight to the coherent host buffer (no copy)
+    HIP_TRY(ctx, launch_status(g->n, ws.T, status, ws.blocksum, ctx->pinned, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     iters = parse_trace(ctx, 0);
-    if (n_roots) *n_roots = ctx->pinned[0];
+    if (n_roots) *n_roots = __atomic_load_n(ctx->pinned, __ATOMIC_ACQUIRE);
     if (n_iters) *n_iters = iters;
     return collect_sweeps(ctx, launches, ws, s);
 }
@@ -1231,11 +1239,11 @@ int mis2_run_ablation(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int fla
     if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, &iters, &launches, &long_rows, &abl)))
         return rc;
     // IN is 0 in the packed tuple and in the status field alike
-    HIP_TRY(ctx, launch_status(g->n, ws.T, status, ws.blocksum, ws.scalars + kS_Roots, s));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, ws.scalars + kS_Roots, 4, hipMemcpyDeviceToHost, s));
+    // the root count goes straight to the coherent host buffer (no copy)
+    HIP_TRY(ctx, launch_status(g->n, ws.T, status, ws.blocksum, ctx->pinned, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     iters = parse_trace(ctx, 0);
-    if (n_roots) *n_roots = ctx->pinned[0];
+    if (n_roots) *n_roots = __atomic_load_n(ctx->pinned, __ATOMIC_ACQUIRE);
     if (n_iters) *n_iters = iters;
     return collect_sweeps(ctx, launches, ws, s);
 }

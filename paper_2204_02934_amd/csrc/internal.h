@@ -239,6 +239,7 @@ struct RoundsArgs {
     uint32_t *cnt1[2];
     uint32_t *cnt2[2];
     uint32_t *rt;
+    uint32_t *rt_host;   // host-pinned copy of the round table rows (may be null)
     uint32_t *ctr;
     unsigned long long *alive_host;
     unsigned long long *degs;  // [kTraceCap][kDegStride] or null

@@ -1263,6 +1263,11 @@ __device__ __forceinline__ void round_start(const RoundsArgs &a, int r) {
         if (threadIdx.x == 0) {
             a.rt[(size_t)r * kRoundStride] = c1;
             a.rt[(size_t)r * kRoundStride + 1] = c2;
+            if (a.rt_host) {
+                // the host reads the sizes after the call without a copy
+                a.rt_host[(size_t)r * kRoundStride] = c1;
+                a.rt_host[(size_t)r * kRoundStride + 1] = c2;
+            }
             if (a.alive_host) {
                 // word 1: (round, |worklist2|), stored before word 0 so that a
                 // host that reads word 0 of round r finds word 1 of round r
