@@ -23,5 +23,6 @@ from .oracle import (  # noqa: F401
     cgs_plan,
     cgs_apply,
     galerkin,
+    smoothed,
     coarsen,
 )

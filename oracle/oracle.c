@@ -847,3 +847,240 @@ int oracle_galerkin(int64_t n, const int64_t *row_ptr, const int32_t *col, const
     free(size);
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Smoothed aggregation (the multigrid setup of Section VI-E smooths the     */
+/* prolongator built on these aggregates; the paper takes the method from    */
+/* its multigrid package and prints no formula).                             */
+/* Reading: with the tentative prolongator of oracle_galerkin,               */
+/* P_tent[i][agg i] = 1/sqrt(n_a), the smoothed prolongator is the damped    */
+/* Jacobi step P = (I - omega D^-1 A) P_tent for a given omega (D = the      */
+/* diagonal of A), and the coarse operator is P^T A P.  Three sparse         */
+/* products, each with a fixed order of operations:                          */
+/*   P[i][a]  = (1{a = agg i} - (omega / d_i) * S) / sqrt(n_a), where S is    */
+/*              the sum of A_ij over j in N[i] with agg j = a: from 0.0, the  */
+/*              diagonal first, then row i's entries in CSR order;            */
+/*   AP[i][b] = sum of A_ij * P[j][b] over j in N[i] (i first, then row i's  */
+/*              entries in CSR order), from 0.0, absent P[j][b] skipped;      */
+/*   Ac[a][b] = sum of P[i][a] * AP[i][b] over the rows i that hold P[i][a],  */
+/*              in increasing i, from 0.0, absent AP[i][b] skipped.           */
+/* Patterns are structural and columns ascend in every row: P row i = the    */
+/* distinct aggregates of N[i]; AP row i = the union of the P rows of N[i];  */
+/* Ac row a = the union of the AP rows i with P[i][a] present.               */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int64_t *ptr;   /* [rows + 1] */
+    int32_t *col;
+    double *val;
+    int64_t nnz, cap;
+} oracle_csr;
+
+static int oracle_cmp_i32(const void *x, const void *y)
+{
+    int32_t a = *(const int32_t *)x, b = *(const int32_t *)y;
+    return a < b ? -1 : a > b ? 1 : 0;
+}
+
+/* Sorts c[0 .. k) and drops repeats; returns the count kept. */
+static int64_t oracle_sort_unique(int32_t *c, int64_t k)
+{
+    if (k <= 1) return k;
+    qsort(c, (size_t)k, sizeof(int32_t), oracle_cmp_i32);
+    int64_t m = 1;
+    for (int64_t t = 1; t < k; t++)
+        if (c[t] != c[m - 1]) c[m++] = c[t];
+    return m;
+}
+
+/* Appends columns c[0 .. k) as the next row of m (values 0.0). */
+static int oracle_csr_push(oracle_csr *m, int64_t row, const int32_t *c, int64_t k)
+{
+    if (m->nnz + k > m->cap) {
+        int64_t cap = m->cap * 2 + k + 16;
+        int32_t *nc = (int32_t *)realloc(m->col, (size_t)cap * sizeof(int32_t));
+        if (!nc) return -1;
+        m->col = nc;
+        double *nv = (double *)realloc(m->val, (size_t)cap * sizeof(double));
+        if (!nv) return -1;
+        m->val = nv;
+        m->cap = cap;
+    }
+    for (int64_t t = 0; t < k; t++) {
+        m->col[m->nnz + t] = c[t];
+        m->val[m->nnz + t] = 0.0;
+    }
+    m->nnz += k;
+    m->ptr[row + 1] = m->nnz;
+    return 0;
+}
+
+static void oracle_csr_free(oracle_csr *m)
+{
+    free(m->ptr);
+    free(m->col);
+    free(m->val);
+}
+
+/* Value of (row, c) in m, or NULL when absent. */
+static double *oracle_csr_at(const oracle_csr *m, int64_t row, int32_t c)
+{
+    int64_t p = oracle_find_col(m->col, m->ptr[row], m->ptr[row + 1], c);
+    if (p < m->ptr[row + 1] && m->col[p] == c) return &m->val[p];
+    return NULL;
+}
+
+/* Computes P and Ac (see above).  Outputs (any may be NULL to only count):
+ * prow[n+1], pcol / pval[p_cap]; crow[n_agg+1], ccol / cval[c_cap].
+ * *p_nnz and *c_nnz receive the entry counts.  Returns 0, -1 (bad
+ * argument or memory), -2 (label out of range), -4 (a capacity too small;
+ * the counts are still set). */
+int oracle_smoothed(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                    const double *diag, const int32_t *agg, int64_t n_agg, double omega,
+                    int64_t *prow, int32_t *pcol, double *pval, int64_t p_cap,
+                    int64_t *crow, int32_t *ccol, double *cval, int64_t c_cap,
+                    int64_t *p_nnz, int64_t *c_nnz)
+{
+    if (n < 0 || n_agg < 0 || (n > 0 && (!row_ptr || !agg || !diag)) || !p_nnz || !c_nnz)
+        return -1;
+    int rc = -1;
+    int64_t *size = (int64_t *)calloc((size_t)(n_agg > 0 ? n_agg : 1), sizeof(int64_t));
+    oracle_csr P = {0}, AP = {0}, C = {0}, R = {0};
+    int32_t *buf = NULL;
+    int64_t buf_cap = 0;
+    if (!size) goto out;
+    for (int64_t i = 0; i < n; i++) {
+        if (agg[i] < 0 || agg[i] >= n_agg) { rc = -2; goto out; }
+        size[agg[i]]++;
+    }
+    P.ptr = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    AP.ptr = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    C.ptr = (int64_t *)calloc((size_t)n_agg + 1, sizeof(int64_t));
+    R.ptr = (int64_t *)calloc((size_t)n_agg + 1, sizeof(int64_t));
+    if (!P.ptr || !AP.ptr || !C.ptr || !R.ptr) goto out;
+#define ORACLE_BUF(k)                                                            \
+    do {                                                                         \
+        if ((k) > buf_cap) {                                                     \
+            buf_cap = (k) * 2;                                                   \
+            int32_t *nb_ = (int32_t *)realloc(buf, (size_t)buf_cap * sizeof(int32_t)); \
+            if (!nb_) goto out;                                                  \
+            buf = nb_;                                                           \
+        }                                                                        \
+    } while (0)
+    /* P: pattern, then values */
+    for (int64_t i = 0; i < n; i++) {
+        int64_t k = 0, deg = row_ptr[i + 1] - row_ptr[i];
+        ORACLE_BUF(deg + 1);
+        buf[k++] = agg[i];
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++) buf[k++] = agg[col[e]];
+        k = oracle_sort_unique(buf, k);
+        if (oracle_csr_push(&P, i, buf, k)) goto out;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        double w = omega / diag[i];
+        for (int64_t p = P.ptr[i]; p < P.ptr[i + 1]; p++) {
+            int32_t a = P.col[p];
+            double s = 0.0;
+            if (agg[i] == a) s = s + diag[i];
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++)
+                if (agg[col[e]] == a) s = s + val[e];
+            double ind = agg[i] == a ? 1.0 : 0.0;
+            double t = w * s;
+            double r = ind - t;
+            P.val[p] = r / sqrt((double)size[a]);
+        }
+    }
+    /* AP = A P */
+    for (int64_t i = 0; i < n; i++) {
+        int64_t k = 0;
+        int64_t need = P.ptr[i + 1] - P.ptr[i];
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++)
+            need += P.ptr[col[e] + 1] - P.ptr[col[e]];
+        ORACLE_BUF(need + 1);
+        for (int64_t p = P.ptr[i]; p < P.ptr[i + 1]; p++) buf[k++] = P.col[p];
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++)
+            for (int64_t p = P.ptr[col[e]]; p < P.ptr[col[e] + 1]; p++) buf[k++] = P.col[p];
+        k = oracle_sort_unique(buf, k);
+        if (oracle_csr_push(&AP, i, buf, k)) goto out;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        for (int64_t q = AP.ptr[i]; q < AP.ptr[i + 1]; q++) {
+            int32_t b = AP.col[q];
+            double acc = 0.0;
+            double *pib = oracle_csr_at(&P, i, b);
+            if (pib) acc = acc + diag[i] * *pib;
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++) {
+                double *pjb = oracle_csr_at(&P, col[e], b);
+                if (pjb) acc = acc + val[e] * *pjb;
+            }
+            AP.val[q] = acc;
+        }
+    }
+    /* R: for each aggregate a, the rows i holding P[i][a], increasing i */
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t p = P.ptr[i]; p < P.ptr[i + 1]; p++) R.ptr[P.col[p] + 1]++;
+    for (int64_t a = 0; a < n_agg; a++) R.ptr[a + 1] += R.ptr[a];
+    R.nnz = R.ptr[n_agg];
+    R.col = (int32_t *)malloc((size_t)(R.nnz > 0 ? R.nnz : 1) * sizeof(int32_t));
+    if (!R.col) goto out;
+    {
+        int64_t *fill = (int64_t *)malloc((size_t)(n_agg > 0 ? n_agg : 1) * sizeof(int64_t));
+        if (!fill) goto out;
+        for (int64_t a = 0; a < n_agg; a++) fill[a] = R.ptr[a];
+        for (int64_t i = 0; i < n; i++)
+            for (int64_t p = P.ptr[i]; p < P.ptr[i + 1]; p++) R.col[fill[P.col[p]]++] = (int32_t)i;
+        free(fill);
+    }
+    /* Ac = P^T AP */
+    for (int64_t a = 0; a < n_agg; a++) {
+        int64_t k = 0, need = 0;
+        for (int64_t t = R.ptr[a]; t < R.ptr[a + 1]; t++)
+            need += AP.ptr[R.col[t] + 1] - AP.ptr[R.col[t]];
+        ORACLE_BUF(need + 1);
+        for (int64_t t = R.ptr[a]; t < R.ptr[a + 1]; t++)
+            for (int64_t q = AP.ptr[R.col[t]]; q < AP.ptr[R.col[t] + 1]; q++) buf[k++] = AP.col[q];
+        k = oracle_sort_unique(buf, k);
+        if (oracle_csr_push(&C, a, buf, k)) goto out;
+    }
+    for (int64_t a = 0; a < n_agg; a++) {
+        for (int64_t q = C.ptr[a]; q < C.ptr[a + 1]; q++) {
+            int32_t b = C.col[q];
+            double acc = 0.0;
+            for (int64_t t = R.ptr[a]; t < R.ptr[a + 1]; t++) {
+                int64_t i = R.col[t];
+                double *apb = oracle_csr_at(&AP, i, b);
+                if (apb) acc = acc + *oracle_csr_at(&P, i, (int32_t)a) * *apb;
+            }
+            C.val[q] = acc;
+        }
+    }
+#undef ORACLE_BUF
+    *p_nnz = P.nnz;
+    *c_nnz = C.nnz;
+    rc = 0;
+    if ((prow || pcol || pval) && (!prow || P.nnz > p_cap || (P.nnz > 0 && (!pcol || !pval))))
+        rc = -4;
+    if ((crow || ccol || cval) && (!crow || C.nnz > c_cap || (C.nnz > 0 && (!ccol || !cval))))
+        rc = -4;
+    if (rc == 0 && prow) {
+        memcpy(prow, P.ptr, ((size_t)n + 1) * sizeof(int64_t));
+        if (P.nnz > 0) {
+            memcpy(pcol, P.col, (size_t)P.nnz * sizeof(int32_t));
+            memcpy(pval, P.val, (size_t)P.nnz * sizeof(double));
+        }
+    }
+    if (rc == 0 && crow) {
+        memcpy(crow, C.ptr, ((size_t)n_agg + 1) * sizeof(int64_t));
+        if (C.nnz > 0) {
+            memcpy(ccol, C.col, (size_t)C.nnz * sizeof(int32_t));
+            memcpy(cval, C.val, (size_t)C.nnz * sizeof(double));
+        }
+    }
+out:
+    free(size);
+    free(buf);
+    oracle_csr_free(&P);
+    oracle_csr_free(&AP);
+    oracle_csr_free(&C);
+    oracle_csr_free(&R);
+    return rc;
+}

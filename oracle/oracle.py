@@ -127,6 +127,11 @@ def _get():
         lib.oracle_galerkin.restype = ctypes.c_int
         lib.oracle_galerkin.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, _i32p,
                                         ctypes.c_int64, _i64p, _i32p, _f64p, _f64p]
+        lib.oracle_smoothed.restype = ctypes.c_int
+        lib.oracle_smoothed.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, _i32p,
+                                        ctypes.c_int64, ctypes.c_double, _i64p, _i32p, _f64p,
+                                        ctypes.c_int64, _i64p, _i32p, _f64p, ctypes.c_int64,
+                                        _i64p, _i64p]
         _lib = lib
     return _lib
 
@@ -387,6 +392,41 @@ def galerkin(row_ptr, col, val, diag, agg, n_agg, crow=None, ccol=None):
     if rc != 0:
         raise OracleError("oracle_galerkin returned %d" % rc)
     return crow, ccol, cval[:int(crow[-1])].copy(), cdiag[:n_agg].copy()
+
+
+def smoothed(row_ptr, col, val, diag, agg, n_agg, omega):
+    """Smoothed aggregation with the damped-Jacobi prolongator
+    P = (I - omega D^-1 A) P_tent (P_tent as in galerkin) and the coarse
+    operator P^T A P (see oracle_smoothed for the order of operations).
+    Returns (prow, pcol, pval, crow, ccol, cval): P as an n x n_agg CSR and
+    the coarse operator as an n_agg x n_agg CSR, diagonal included, columns
+    ascending."""
+    row_ptr, col = _csr(row_ptr, col)
+    n = row_ptr.size - 1
+    agg = np.ascontiguousarray(agg, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    diag = np.ascontiguousarray(diag, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    one_i32, one_f64 = np.zeros(1, np.int32), np.zeros(1)
+    args = (n, _ptr(row_ptr, _i64p), _ptr(col if col.size else one_i32, _i32p),
+            _ptr(val if val.size else one_f64, dp), _ptr(diag if diag.size else one_f64, dp),
+            _ptr(agg if agg.size else one_i32, _i32p), n_agg, float(omega))
+    pn, cn = ctypes.c_int64(0), ctypes.c_int64(0)
+    lib = _get()
+    rc = lib.oracle_smoothed(*args, None, None, None, 0, None, None, None, 0,
+                             ctypes.byref(pn), ctypes.byref(cn))
+    if rc != 0:
+        raise OracleError("oracle_smoothed returned %d" % rc)
+    prow, crow = np.zeros(n + 1, np.int64), np.zeros(n_agg + 1, np.int64)
+    pcol, pval = np.zeros(max(pn.value, 1), np.int32), np.zeros(max(pn.value, 1))
+    ccol, cval = np.zeros(max(cn.value, 1), np.int32), np.zeros(max(cn.value, 1))
+    rc = lib.oracle_smoothed(*args, _ptr(prow, _i64p), _ptr(pcol, _i32p), _ptr(pval, dp),
+                             pcol.size, _ptr(crow, _i64p), _ptr(ccol, _i32p), _ptr(cval, dp),
+                             ccol.size, ctypes.byref(pn), ctypes.byref(cn))
+    if rc != 0:
+        raise OracleError("oracle_smoothed returned %d" % rc)
+    return (prow, pcol[:pn.value].copy(), pval[:pn.value].copy(), crow,
+            ccol[:cn.value].copy(), cval[:cn.value].copy())
 
 
 def coarsen(row_ptr, col, seed=0, stop_below=1000, max_levels=64):

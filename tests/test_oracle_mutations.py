@@ -18,6 +18,7 @@ BASIC = ["tests/test_oracle_basic.py"]
 ABL = ["tests/test_oracle_ablation.py"]
 CGS = ["tests/test_oracle_cgs.py"]
 GAL = ["tests/test_oracle_galerkin.py"]
+SMO = ["tests/test_oracle_smoothed.py"]
 
 # name: (pin files, text replaced (its first occurrence), replacement)
 MUTANTS = {
@@ -47,6 +48,12 @@ MUTANTS = {
                             "cval[p] = cval[p] / (sqrt((double)size[a]) * sqrt((double)size[ccol[p]]));"),
     "galerkin_diagonal_scale": (GAL, "cdiag[a] = cdiag[a] / sqrt((double)size[a] * (double)size[a]);",
                                 "cdiag[a] = cdiag[a] / sqrt((double)size[a]);"),
+    "smoothed_sign": (SMO, "double r = ind - t;", "double r = ind + t;"),
+    "smoothed_without_jacobi_scaling": (SMO, "double w = omega / diag[i];", "double w = omega;"),
+    "smoothed_without_diagonal": (SMO, "if (agg[i] == a) s = s + diag[i];", ";"),
+    "smoothed_ap_without_diagonal": (SMO, "if (pib) acc = acc + diag[i] * *pib;", ";"),
+    "smoothed_tentative_scale": (SMO, "P.val[p] = r / sqrt((double)size[a]);",
+                                 "P.val[p] = r / (double)size[a];"),
 }
 
 
