@@ -291,18 +291,21 @@ def kernel_sources_digest():
     return h.hexdigest()
 
 
-def measured_traffic(workload, kernel, launches_per_step):
+def measured_traffic(workload, kernel, launches_per_step, plan):
     """HBM bytes per launch of `kernel` from profiles/traffic_<workload>.json
-    (rocprofv3 FETCH_SIZE and WRITE_SIZE runs of this bench, scaled by the
-    same counters on a plain device copy of known size; bytes per step over
-    the launches per step counted here), or None when there is no such
-    measurement for the current sources."""
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE runs of this bench with an explicit
+    launch plan, scaled by the same counters on a plain device copy of known
+    size; bytes per step over the launches per step counted here), or None
+    when there is no such measurement for the current sources and plan."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
     if t.get("sources_sha256") != kernel_sources_digest():
+        return None
+    tp = t.get("plan", {})
+    if (tp.get("lanes"), tp.get("tail")) != (plan.get("lanes"), plan.get("tail")):
         return None
     k = t.get("kernels", {}).get(kernel)
     if k is None or "hbm_bytes_per_step" not in k:
@@ -499,7 +502,17 @@ def run_c4(args):
         ctx.coarsen(a, b, seed=args.seed, stop_below=1000, nnz=z)
     torch.cuda.synchronize()
     t_loop = time.perf_counter() - t0
-    log("c4: batched %.2f ms, per-graph loop %.2f ms" % (1e3 * t_batch, 1e3 * t_loop))
+    rule = api.Context(0, autotune=False)
+    for _ in range(args.warmup):
+        rule.aggregate_batched(rp, col, voff, seed=args.seed, stop_below=1000, nnz=nnz)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rule.aggregate_batched(rp, col, voff, seed=args.seed, stop_below=1000, nnz=nnz)
+    torch.cuda.synchronize()
+    t_rule = (time.perf_counter() - t0) / args.steps
+    log("c4: batched %.2f ms (degree rule %.2f ms), per-graph loop %.2f ms"
+        % (1e3 * t_batch, 1e3 * t_rule, 1e3 * t_loop))
     return {
         "metric": "MIS-2+aggregation graph nnz/s and HBM GB/s fraction",
         "value": nnz / t_batch, "unit": "nnz/s", "n_gpus": 1, "steps": args.steps,
@@ -511,42 +524,49 @@ def run_c4(args):
         "per_graph_loop_ms": 1e3 * t_loop,
         "per_graph_loop_nnz_per_s": nnz / t_loop,
         "batched_speedup": t_loop / t_batch,
+        "degree_rule_ms": 1e3 * t_rule,
+        "plan_last_level": ctx.last_plan(),
     }
 
 
 def run_c5(args):
-    """Serving: Poisson arrivals of coarsening jobs into a mis2_server, at
-    0.5x and 0.8x of the saturation rate measured with every job queued at
-    once.  Latency = completion - arrival (host monotonic clock)."""
+    """Serving: a seeded stream of coarsening jobs (each one of a pool of
+    distinct graphs of the serving mix) through a mis2_server.  Saturation:
+    the whole stream queued at once; then Poisson arrivals at 0.5x and 0.8x
+    of that rate.  Jobs arrive as host CSRs, copied to the GPU on a side
+    stream while the running level computes.  Latency = completion - arrival
+    (host monotonic clock).  Beside it, the same jobs through mis2_coarsen one
+    at a time on one stream (graphs already on the GPU): the plain per-graph
+    launch."""
     import numpy as np
     import torch
     from paper_2204_02934_amd import api
-    pool = c5_pool(args.c5_jobs)
+    pool = c5_pool(args.c5_graphs)
+    rng = np.random.default_rng(4)
+    pick = rng.integers(0, len(pool), args.c5_jobs)
     dev = torch.device("cuda", 0)
-    jobs = []
-    for kind, (a, b) in pool:
-        d = api.as_device_csr(a, b, dev)
-        jobs.append((kind, d, a.size - 1, int(a[-1])))
+    host = [(a, b, a.size - 1, int(a[-1])) for _, (a, b) in pool]
+    dev_graphs = [api.as_device_csr(a, b, dev) for _, (a, b) in pool]
+    jobs = [host[i] for i in pick]
     tot_nnz = sum(j[3] for j in jobs)
-    vmax = max(j[2] for j in jobs)
-    emax = max(j[3] for j in jobs)
+    vmax = max(j[2] for j in host)
+    emax = max(j[3] for j in host)
     srv = api.Server(max_vertices=max(4 * vmax, 1 << 20), max_nnz=max(4 * emax, 1 << 22),
                      max_graphs=256, seed=args.seed, stop_below=1000)
-    log("c5: %d jobs, sum nnz %d, largest n %d" % (len(jobs), tot_nnz, vmax))
+    log("c5: %d jobs over %d distinct graphs, sum nnz %d, largest n %d"
+        % (len(jobs), len(pool), tot_nnz, vmax))
 
     def run(rate, rng):
         n_jobs = len(jobs)
-        if rate is None:
-            arrive = np.zeros(n_jobs)
-        else:
-            arrive = np.cumsum(rng.exponential(1.0 / rate, n_jobs))
+        arrive = np.zeros(n_jobs) if rate is None else np.cumsum(rng.exponential(1.0 / rate,
+                                                                                 n_jobs))
         done_at = {}
         t0 = time.perf_counter()
         nxt = 0
         while len(done_at) < n_jobs:
             now = time.perf_counter() - t0
             while nxt < n_jobs and arrive[nxt] <= now:
-                _, (a, b), _, z = jobs[nxt]
+                a, b, _, z = jobs[nxt]
                 srv.submit(a, b, tag=nxt, nnz=z)
                 nxt += 1
             pending = srv.step()
@@ -558,29 +578,48 @@ def run_c5(args):
         lat = np.array([done_at[i] - arrive[i] for i in range(n_jobs)])
         return wall, lat
 
-    run(None, None)  # warm-up
-    wall_sat, _ = run(None, None)
+    run(None, None)  # warm-up (and the plan tuner's first sight of each union class)
+    wall_sat, lat_sat = run(None, None)
     sat = len(jobs) / wall_sat
-    log("c5: saturation %.2f jobs/s (%.3f s for the pool)" % (sat, wall_sat))
+    log("c5: saturation %.2f jobs/s (%.3f s for the stream)" % (sat, wall_sat))
     res = {}
     for frac in (0.5, 0.8):
         wall, lat = run(frac * sat, np.random.default_rng(3))
         res["%.1fx" % frac] = {"qps": frac * sat, "p50_ms": 1e3 * float(np.percentile(lat, 50)),
                                "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                               "max_ms": 1e3 * float(lat.max()),
                                "nnz_per_s": tot_nnz / wall, "wall_s": wall}
         log("c5 %.1fx: %s" % (frac, json.dumps(res["%.1fx" % frac])))
     srv.close()
+    # the plain per-graph launch: mis2_coarsen per job, one stream, graphs on the GPU
+    ctx = api.Context(0)
+    for i in sorted(set(pick.tolist())):  # warm pass over the distinct graphs
+        ctx.coarsen(*dev_graphs[i], seed=args.seed, stop_below=1000, nnz=host[i][3])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in pick:
+        ctx.coarsen(*dev_graphs[i], seed=args.seed, stop_below=1000, nnz=host[i][3])
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    log("c5: per-graph loop %.3f s (%.3g nnz/s)" % (t_loop, tot_nnz / t_loop))
     return {
         "metric": "MIS-2+aggregation graph nnz/s and HBM GB/s fraction",
         "value": tot_nnz / wall_sat, "unit": "nnz/s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": 1e3 * wall_sat, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": "serving: %d multilevel coarsening jobs, n log-uniform [1e3, 1e7], "
-                               "2D 5-pt / 3D 27-pt / Chung-Lu 40/40/20, Poisson arrivals"
-                               % len(jobs), "jobs": len(jobs), "sum_nnz": tot_nnz,
+        "config": {"workload": "serving: %d multilevel coarsening jobs over %d distinct graphs, "
+                               "n log-uniform [1e3, 1e7], 2D 5-pt / 3D 27-pt / Chung-Lu "
+                               "40/40/20, Poisson arrivals, host CSRs uploaded on a side "
+                               "stream" % (len(jobs), len(pool)),
+                   "jobs": len(jobs), "distinct_graphs": len(pool), "sum_nnz": tot_nnz,
                    "seed": args.seed},
         "saturation_jobs_per_s": sat,
+        "saturation_p50_ms": 1e3 * float(np.percentile(lat_sat, 50)),
+        "saturation_p99_ms": 1e3 * float(np.percentile(lat_sat, 99)),
         "poisson": res,
+        "per_graph_loop_s": t_loop,
+        "per_graph_nnz_per_s": tot_nnz / t_loop,
+        "served_vs_per_graph": t_loop / wall_sat,
     }
 
 
@@ -595,7 +634,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run three device-to-device copies of MIB MiB (a known-size "
                          "kernel for scaling hardware byte counters)")
-    ap.add_argument("--c5-jobs", type=int, default=32, help="serving: jobs in the pool")
+    ap.add_argument("--c5-jobs", type=int, default=200, help="serving: jobs in the stream")
+    ap.add_argument("--c5-graphs", type=int, default=48,
+                    help="serving: distinct graphs the jobs are drawn from")
     ap.add_argument("--ablation", action="store_true",
                     help="c1-c3, l100: the optimization ladder of Fig. 2 and the rounds of "
                          "Table I instead of the step")
@@ -605,6 +646,12 @@ def main():
     ap.add_argument("--cgs", action="store_true",
                     help="c1, c2, l100: cluster vs point multicolor Gauss-Seidel (Algorithm 4) "
                          "instead of the step")
+    ap.add_argument("--lanes", type=int, default=None,
+                    help="c1-c3: lanes per row of the sweeps (-2 = staged, -1 = flat) instead "
+                         "of the tuned plan")
+    ap.add_argument("--tail", type=int, default=None, choices=(0, 1),
+                    help="c1-c3: the one-workgroup tail off (0) or on (1) instead of the tuned "
+                         "choice")
     ap.add_argument("--aggregation", choices=("alg3", "alg2"), default="alg3",
                     help="c1-c3: the aggregation of the step, MIS-2 based aggregation "
                          "(mis2_aggregate) or basic MIS-2 coarsening (mis2_aggregate_basic)")
@@ -641,6 +688,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     agg_call = "aggregate" if args.aggregation == "alg3" else "aggregate_basic"
+    # an explicit launch plan (the tuner then stays out: profiler runs count
+    # the same kernels in every step)
+    plan_kw = {}
+    if args.lanes is not None:
+        plan_kw["lanes"] = args.lanes
+    if args.tail is not None:
+        plan_kw["tail"] = args.tail
     name, (rp_h, col_h) = workload(args.workload)
     if args.aggregation == "alg2":
         name = name.replace("MIS-2 + MIS-2 aggregation", "MIS-2 + basic MIS-2 coarsening")
@@ -659,7 +713,7 @@ def main():
         del src, dst
         log("calibration copies: 3 x %d MiB" % args.calibrate_copy)
 
-    ctx = api.Context(0)
+    ctx = api.Context(0, **plan_kw)
     ctx.ensure_workspace(n, 1, nnz)
     torch.cuda.synchronize()
 
@@ -693,7 +747,7 @@ def main():
 
     # algorithmic bytes per launch (untimed accounting run; results are
     # deterministic, so every timed step visits the same rows)
-    acc = api.Context(0, account=True)
+    acc = api.Context(0, account=True, **plan_kw)
     acc.ensure_workspace(n, 1, nnz)
     acc.mis2(rp, col, args.seed, nnz=nnz)
     recs_mis = acc.last_sweeps()
@@ -705,7 +759,7 @@ def main():
     # launch; each launch is priced with the accounting run's bytes of the
     # sweeps it ran (the round where the one-workgroup tail takes over may
     # differ from run to run, the bytes of a round do not)
-    prof = api.Context(0, profile=True)
+    prof = api.Context(0, profile=True, **plan_kw)
     prof.ensure_workspace(n, 1, nnz)
     step(prof)
     torch.cuda.synchronize()
@@ -743,19 +797,21 @@ def main():
     # degree rule (tuner off) for comparison
     plan = ctx.last_plan()
     tuning = ctx.last_tuning()
-    rule = api.Context(0, autotune=False)
-    rule.ensure_workspace(n, 1, nnz)
-    for _ in range(args.warmup):
-        step(rule)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(rule)
-    torch.cuda.synchronize()
-    rule_ms = 1e3 * (time.perf_counter() - t0) / args.steps
-    rule_plan = rule.last_plan()
-    log("plan %s (rule %s): %.3f ms/step with the tuned plan, %.3f ms with the rule"
-        % (plan, rule_plan, ms_per_step, rule_ms))
+    rule_ms, rule_plan = None, {"lanes": None, "blocks": None}
+    if not plan_kw:
+        rule = api.Context(0, autotune=False)
+        rule.ensure_workspace(n, 1, nnz)
+        for _ in range(args.warmup):
+            step(rule)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(rule)
+        torch.cuda.synchronize()
+        rule_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        rule_plan = rule.last_plan()
+        log("plan %s (rule %s): %.3f ms/step with the tuned plan, %.3f ms with the rule"
+            % (plan, rule_plan, ms_per_step, rule_ms))
 
     rounds_mis = 1 + max(r["round"] for r in recs_mis if r["kind"] in (0, 1)) if recs_mis else 0
 
@@ -803,7 +859,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": measured_traffic(args.workload + ("" if args.aggregation == "alg3"
-                                                                  else "_alg2"), dom, d["launches"]),
+                                                                  else "_alg2"), dom, d["launches"],
+                                                 plan),
                      "copy_ceiling": copy_gbps, "frac_of_copy_ceiling": achieved / copy_gbps,
                      "kernel": dom, "launches_per_step": d["launches"],
                      "bytes_per_launch": d["bytes"] / d["launches"],
@@ -822,7 +879,8 @@ def main():
         "kernels_per_step": {k: {"launches": v["launches"], "ms": v["ms"], "bytes": v["bytes"]}
                              for k, v in per_kind.items()},
         "plan": {"lanes": plan["lanes"], "blocks": plan["blocks"],
-                 "source": ["rule", "tuned (cached)", "tuned"][plan["source"]],
+                 "tail": plan["tail"],
+                 "source": ["rule or options", "tuned (cached)", "tuned"][plan["source"]],
                  "tuning": tuning, "rule_plan": {"lanes": rule_plan["lanes"],
                                                  "blocks": rule_plan["blocks"]},
                  "rule_ms_per_step": rule_ms},

@@ -380,6 +380,41 @@ int mis2_quotient(mis2_ctx *ctx, const mis2_graph *g, const int32_t *agg_id, int
                   int64_t *coarse_row_ptr, int32_t *coarse_col, int64_t *coarse_nnz, void *stream);
 
 /*
+ * mis2_smoothed -- smoothed aggregation on an aggregation of g (the
+ * multigrid setup of Section VI-E smooths the prolongator of the aggregates;
+ * the paper gives no formula): the damped-Jacobi prolongator
+ * P = (I - omega D^-1 A) P_tent, with P_tent[i][agg i] = 1/sqrt(n_a) as in
+ * mis2_galerkin, and the coarse operator A_c = P^T A P.
+ *
+ *   val, diag    device: A's off-diagonal values in g's CSR order, and its
+ *                diagonal (nonzero)
+ *   agg, n_agg   device labels in [0, n_agg), every aggregate non-empty
+ *   omega        the damping factor (finite)
+ *   prow/pcol/pval  device out: P as an n x n_agg CSR, p_cap entries of room
+ *                (n + nnz always suffice); row i holds the distinct
+ *                aggregates of i and its neighbours, ascending
+ *   crow/ccol/cval  device out: A_c as an n_agg x n_agg CSR (diagonal
+ *                included), c_cap entries of room, columns ascending
+ *   p_nnz, c_nnz host out: entries of P and A_c (-1 when not reached)
+ *   ws_need      host out (may be NULL): workspace bytes needed, when the
+ *                context's is too small
+ * Order of operations (bit-exact with the CPU reference): S = sum of A_ij
+ * over j in N[i] with agg j = a, the diagonal first, then CSR order, from
+ * 0.0; P[i][a] = (1{a = agg i} - (omega / d_i) * S) / sqrt(n_a); AP[i][b] =
+ * sum over j in N[i] (i first, then CSR order) of A_ij * P[j][b]; A_c[a][b] =
+ * sum over the rows i holding P[i][a], increasing, of P[i][a] * AP[i][b];
+ * each product rounded on its own.
+ * Errors: MIS2_ENOSPACE when p_cap, c_cap or the workspace is too small
+ * (the counts known so far are set; call again with more room) or when a row
+ * of A P or A_c has more than 2048 columns; MIS2_EINVAL for labels out of
+ * range.  Synchronises the stream several times (setup work).
+ */
+int mis2_smoothed(mis2_ctx *ctx, const mis2_graph *g, const double *val, const double *diag,
+                  const int32_t *agg, int64_t n_agg, double omega, int64_t *prow, int32_t *pcol,
+                  double *pval, int64_t p_cap, int64_t *crow, int32_t *ccol, double *cval,
+                  int64_t c_cap, int64_t *p_nnz, int64_t *c_nnz, size_t *ws_need, void *stream);
+
+/*
  * mis2_galerkin -- the Galerkin coarse operator of an aggregation, the
  * multigrid hookup of the aggregates (Section VI-E builds smoothed-aggregation
  * multigrid on them; the paper takes the operator from its multigrid

@@ -49,6 +49,7 @@ EXPORTS = (
     "mis2_server_bytes", "mis2_server_create", "mis2_server_destroy", "mis2_server_last_error",
     "mis2_server_submit", "mis2_server_step", "mis2_server_poll",
     "mis2_run_noalloc", "mis2_run_noalloc_max_n", "mis2_last_plan", "mis2_last_tuning",
+    "mis2_smoothed",
 )
 
 MIS2_SERVE_MAX_LEVELS = 32
@@ -132,6 +133,10 @@ def load():
                                              ctypes.POINTER(i32), vp]),
         "mis2_ablation_workspace_bytes": (ctypes.c_int, [i64, ctypes.c_int,
                                                          ctypes.POINTER(ctypes.c_size_t)]),
+        "mis2_smoothed": (ctypes.c_int, [vp, gp, vp, vp, vp, i64, ctypes.c_double, vp, vp, vp,
+                                         i64, vp, vp, vp, i64, ctypes.POINTER(i64),
+                                         ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t),
+                                         vp]),
         "mis2_last_plan": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                           ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "mis2_last_tuning": (ctypes.c_int, [vp, ctypes.POINTER(Mis2TuneRecord), i32,

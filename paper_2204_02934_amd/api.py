@@ -258,6 +258,48 @@ class Context:
         del keep, ckeep
         return cval[:cg.nnz], cdiag[:cg.n]
 
+    def smoothed(self, row_ptr, col, val, diag, agg, n_agg, omega, stream=None, nnz=None):
+        """Smoothed aggregation (mis2_smoothed): the prolongator
+        P = (I - omega D^-1 A) P_tent and the coarse operator P^T A P.  Returns
+        ((prow, pcol, pval), (crow, ccol, cval)), CSR arrays on the GPU."""
+        g, keep = self.graph(row_ptr, col, nnz)
+        for t in (val, diag):
+            assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+        agg = torch.as_tensor(agg).to(device=self.device, dtype=torch.int32).contiguous()
+        n = g.n
+        prow = torch.empty(n + 1, dtype=torch.int64, device=self.device)
+        crow = torch.empty(max(n_agg, 0) + 1, dtype=torch.int64, device=self.device)
+        p_cap = max(n + g.nnz, 1)  # P row i holds at most deg(i) + 1 entries
+        pcol = torch.empty(p_cap, dtype=torch.int32, device=self.device)
+        pval = torch.empty(p_cap, dtype=torch.float64, device=self.device)
+        c_cap = max(min(n_agg * n_agg, 32 * n_agg), 1)
+        ccol = torch.empty(c_cap, dtype=torch.int32, device=self.device)
+        cval = torch.empty(c_cap, dtype=torch.float64, device=self.device)
+        pn, cn, need = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_size_t(0)
+        for _ in range(6):
+            rc = self.lib.mis2_smoothed(
+                self.ptr, ctypes.byref(g), ctypes.c_void_p(val.data_ptr()),
+                ctypes.c_void_p(diag.data_ptr()), ctypes.c_void_p(agg.data_ptr()), int(n_agg),
+                ctypes.c_double(omega), ctypes.c_void_p(prow.data_ptr()),
+                ctypes.c_void_p(pcol.data_ptr()), ctypes.c_void_p(pval.data_ptr()), p_cap,
+                ctypes.c_void_p(crow.data_ptr()), ctypes.c_void_p(ccol.data_ptr()),
+                ctypes.c_void_p(cval.data_ptr()), c_cap, ctypes.byref(pn), ctypes.byref(cn),
+                ctypes.byref(need), _stream_ptr(stream, self.device))
+            if rc != _lib.MIS2_ENOSPACE:
+                break
+            if need.value:
+                self._ensure_bytes(need.value)
+            elif cn.value > c_cap:
+                c_cap = cn.value
+                ccol = torch.empty(c_cap, dtype=torch.int32, device=self.device)
+                cval = torch.empty(c_cap, dtype=torch.float64, device=self.device)
+            else:
+                break
+        _check(self.lib, self.ptr, rc)
+        del keep
+        return ((prow, pcol[:pn.value], pval[:pn.value]),
+                (crow, ccol[:cn.value], cval[:cn.value]))
+
     def coarsen(self, row_ptr, col, seed=0, stop_below=1000, max_levels=64, stream=None, nnz=None):
         """Multilevel coarsening: list of per-level dicts {n, nnz, n_agg, agg
         (int32 labels on the GPU)}."""
@@ -436,6 +478,8 @@ class Server:
         if rc != _lib.MIS2_OK:
             raise Mis2Error(rc, "mis2_server_create failed")
         self._jobs = {}  # tag -> (graph tensors, agg tensor), kept alive until polled
+        self._copy_stream = None  # uploads of host CSRs
+        self._uploads = []        # their events, waited for by the next step
 
     def _check(self, rc):
         if rc != _lib.MIS2_OK:
@@ -444,8 +488,26 @@ class Server:
 
     def submit(self, row_ptr, col, tag, agg_cap=None, nnz=None):
         """Queue one coarsening job (device or host CSR); its labels land in a
-        device int32 tensor returned by poll()."""
-        rp, cc = as_device_csr(row_ptr, col, self.device)
+        device int32 tensor returned by poll().  A host CSR is copied to the
+        GPU on a side stream, so the copy overlaps the level running on the
+        server's stream; the next step() waits for it before it admits jobs."""
+        if not torch.is_tensor(row_ptr) or row_ptr.device.type != "cuda":
+            rp_h = torch.as_tensor(np.asarray(row_ptr), dtype=torch.int64)
+            cc_h = torch.as_tensor(np.asarray(col), dtype=torch.int32)
+            if cc_h.numel() == 0:
+                cc_h = torch.zeros(1, dtype=torch.int32)
+            if self._copy_stream is None:
+                self._copy_stream = torch.cuda.Stream(device=self.device)
+            with torch.cuda.stream(self._copy_stream):
+                rp = rp_h.pin_memory().to(self.device, non_blocking=True)
+                cc = cc_h.pin_memory().to(self.device, non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(self._copy_stream)
+            self._uploads.append(ev)
+            if nnz is None:
+                nnz = int(rp_h[-1])
+        else:
+            rp, cc = as_device_csr(row_ptr, col, self.device)
         n = rp.numel() - 1
         if nnz is None:
             nnz = int(rp[-1].item())
@@ -459,6 +521,11 @@ class Server:
     def step(self, stream=None):
         """One admission + level step; returns the number of jobs still queued
         or coarsening."""
+        if self._uploads:
+            st = stream if stream is not None else torch.cuda.current_stream(self.device)
+            for ev in self._uploads:
+                st.wait_event(ev)
+            self._uploads = []
         k = ctypes.c_int32(0)
         self._check(self.lib.mis2_server_step(self.ptr, _stream_ptr(stream, self.device),
                                               ctypes.byref(k)))

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <mutex>
 
@@ -1731,6 +1732,173 @@ int mis2_galerkin(mis2_ctx *ctx, const mis2_graph *g, const double *val, const d
     HIP_TRY(ctx, hipStreamSynchronize(s));
     if (ctx->pinned[0] & 4u)
         return fail(ctx, MIS2_EINVAL, "the coarse graph lacks a coupling of the aggregation");
+    return MIS2_OK;
+}
+
+// Smoothed aggregation (see smoothed.hip).  Workspace: a fixed part, then
+// arrays sized by the entries of P and AP, known only as the call proceeds.
+namespace {
+struct SmoothedWs {
+    uint32_t *size, *cnt, *cursor, *flag;
+    unsigned long long *part;
+    int64_t *apptr, *moff;
+    int32_t *prow_of, *members, *apcol;
+    double *apval;
+};
+
+size_t smoothed_bytes(int64_t n, int64_t n_agg, int64_t p_nnz, int64_t ap_nnz) {
+    const size_t un = (size_t)std::max<int64_t>(n, 1), ua = (size_t)std::max<int64_t>(n_agg, 1);
+    size_t b = align_up(4 * ua) + align_up(4 * std::max(un, ua)) + align_up(4 * ua) + align_up(64);
+    b += align_up(8 * (size_t)scan_parts(std::max<int64_t>(n, n_agg)));
+    b += align_up(8 * (un + 1)) + align_up(8 * (ua + 1));
+    b += 2 * align_up(4 * (size_t)std::max<int64_t>(p_nnz, 1));
+    b += align_up(4 * (size_t)std::max<int64_t>(ap_nnz, 1)) +
+         align_up(8 * (size_t)std::max<int64_t>(ap_nnz, 1));
+    return b;
+}
+
+SmoothedWs carve_smoothed(void *base, int64_t n, int64_t n_agg, int64_t p_nnz, int64_t ap_nnz) {
+    const size_t un = (size_t)std::max<int64_t>(n, 1), ua = (size_t)std::max<int64_t>(n_agg, 1);
+    char *p = (char *)base;
+    auto take = [&](size_t sz) {
+        char *r = p;
+        p += align_up(sz);
+        return (void *)r;
+    };
+    SmoothedWs w;
+    w.size = (uint32_t *)take(4 * ua);
+    w.cnt = (uint32_t *)take(4 * std::max(un, ua));
+    w.cursor = (uint32_t *)take(4 * ua);
+    w.flag = (uint32_t *)take(64);
+    w.part = (unsigned long long *)take(8 * (size_t)scan_parts(std::max<int64_t>(n, n_agg)));
+    w.apptr = (int64_t *)take(8 * (un + 1));
+    w.moff = (int64_t *)take(8 * (ua + 1));
+    w.prow_of = (int32_t *)take(4 * (size_t)std::max<int64_t>(p_nnz, 1));
+    w.members = (int32_t *)take(4 * (size_t)std::max<int64_t>(p_nnz, 1));
+    w.apcol = (int32_t *)take(4 * (size_t)std::max<int64_t>(ap_nnz, 1));
+    w.apval = (double *)take(8 * (size_t)std::max<int64_t>(ap_nnz, 1));
+    return w;
+}
+
+// *out = the int64 at device address src, and the error flags (one sync).
+int read_total(mis2_ctx *ctx, const int64_t *src, const uint32_t *flag, int64_t *out,
+               uint32_t *flags, hipStream_t s) {
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, src, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned + 2, flag, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    *out = (int64_t)((uint64_t)ctx->pinned[0] | ((uint64_t)ctx->pinned[1] << 32));
+    *flags = ctx->pinned[2];
+    return MIS2_OK;
+}
+}  // namespace
+
+int mis2_smoothed(mis2_ctx *ctx, const mis2_graph *g, const double *val, const double *diag,
+                  const int32_t *agg, int64_t n_agg, double omega, int64_t *prow, int32_t *pcol,
+                  double *pval, int64_t p_cap, int64_t *crow, int32_t *ccol, double *cval,
+                  int64_t c_cap, int64_t *p_nnz, int64_t *c_nnz, size_t *ws_need, void *stream) {
+    int rc = check_graph_args(ctx, g);
+    if (rc) return rc;
+    if (p_nnz) *p_nnz = -1;
+    if (c_nnz) *c_nnz = -1;
+    if (ws_need) *ws_need = 0;
+    const int64_t n = g->n;
+    if (n_agg < 0 || (n > 0 && n_agg < 1) || n_agg > n || !prow || !crow || !p_nnz || !c_nnz ||
+        (n > 0 && (!diag || !agg)) || (g->nnz > 0 && !val) || !std::isfinite(omega))
+        return fail(ctx, MIS2_EINVAL, "mis2_smoothed: bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (n == 0) {
+        HIP_TRY(ctx, launch_fill_u64((unsigned long long *)prow, 0ull, 1, s));
+        HIP_TRY(ctx, launch_fill_u64((unsigned long long *)crow, 0ull, 1, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        *p_nnz = *c_nnz = 0;
+        return MIS2_OK;
+    }
+    size_t need = smoothed_bytes(n, n_agg, 0, 0);
+    if (!ctx->ws || ctx->ws_bytes < need) {
+        if (ws_need) *ws_need = need;
+        return fail(ctx, MIS2_ENOSPACE, "mis2_smoothed: workspace of %zu bytes needed", need);
+    }
+    SmoothedWs w = carve_smoothed(ctx->ws, n, n_agg, 0, 0);
+    uint32_t flags = 0;
+    // aggregate ids in range (checked before any is used as an index), and
+    // the aggregate sizes
+    HIP_TRY(ctx, launch_fill_u32(w.flag, 0u, 16, s));
+    HIP_TRY(ctx, launch_check_ids(n, agg, 0, nullptr, n_agg, w.flag, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, w.flag, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (ctx->pinned[0] & 1u)
+        return fail(ctx, MIS2_EINVAL, "mis2_smoothed: aggregate id outside [0, n_agg)");
+    HIP_TRY(ctx, launch_fill_u32(w.size, 0u, n_agg, s));
+    HIP_TRY(ctx, launch_count_of(n, agg, w.size, s));
+    // P: structure (count, offsets, columns), then values
+    HIP_TRY(ctx, launch_smoothed_sym(0, false, n, g->row_ptr, g->col, agg, nullptr, nullptr,
+                                     nullptr, nullptr, nullptr, w.cnt, nullptr, nullptr,
+                                     w.flag + 1, s));
+    HIP_TRY(ctx, exclusive_scan_u32_i64(w.cnt, n, prow, w.part, s));
+    int64_t pn = 0;
+    if ((rc = read_total(ctx, prow + n, w.flag + 1, &pn, &flags, s))) return rc;
+    *p_nnz = pn;
+    if (pn > (int64_t)0x7FFFFFFF)
+        return fail(ctx, MIS2_EINVAL, "mis2_smoothed: P has more than 2^31 - 1 entries");
+    if (pn > p_cap || (pn > 0 && (!pcol || !pval)))
+        return fail(ctx, MIS2_ENOSPACE, "mis2_smoothed: P has %lld entries, room for %lld",
+                    (long long)pn, (long long)p_cap);
+    need = smoothed_bytes(n, n_agg, pn, 0);
+    if (ctx->ws_bytes < need) {
+        if (ws_need) *ws_need = need;
+        return fail(ctx, MIS2_ENOSPACE, "mis2_smoothed: workspace of %zu bytes needed", need);
+    }
+    w = carve_smoothed(ctx->ws, n, n_agg, pn, 0);
+    HIP_TRY(ctx, launch_smoothed_sym(0, true, n, g->row_ptr, g->col, agg, nullptr, nullptr,
+                                     nullptr, nullptr, nullptr, nullptr, prow, pcol, w.flag + 1,
+                                     s));
+    HIP_TRY(ctx, launch_p_values(n, pn, g->row_ptr, g->col, val, diag, agg, w.size, omega, prow,
+                                 pcol, pval, w.prow_of, s));
+    // AP = A P
+    HIP_TRY(ctx, launch_smoothed_sym(1, false, n, g->row_ptr, g->col, agg, prow, pcol, nullptr,
+                                     nullptr, nullptr, w.cnt, nullptr, nullptr, w.flag + 1, s));
+    HIP_TRY(ctx, exclusive_scan_u32_i64(w.cnt, n, w.apptr, w.part, s));
+    int64_t apn = 0;
+    if ((rc = read_total(ctx, w.apptr + n, w.flag + 1, &apn, &flags, s))) return rc;
+    if (flags & 1u)
+        return fail(ctx, MIS2_ENOSPACE, "mis2_smoothed: a row of A P has more than 2048 columns");
+    need = smoothed_bytes(n, n_agg, pn, apn);
+    if (ctx->ws_bytes < need) {
+        if (ws_need) *ws_need = need;
+        return fail(ctx, MIS2_ENOSPACE, "mis2_smoothed: workspace of %zu bytes needed", need);
+    }
+    w = carve_smoothed(ctx->ws, n, n_agg, pn, apn);
+    HIP_TRY(ctx, launch_smoothed_sym(1, true, n, g->row_ptr, g->col, agg, prow, pcol, nullptr,
+                                     nullptr, nullptr, nullptr, w.apptr, w.apcol, w.flag + 1, s));
+    HIP_TRY(ctx, launch_ap_values(n, apn, g->row_ptr, g->col, val, diag, prow, pcol, pval,
+                                  w.apptr, w.apcol, w.apval, s));
+    // R_a: the P entries of column a in increasing order (hence increasing row)
+    HIP_TRY(ctx, launch_fill_u32(w.cnt, 0u, n_agg, s));
+    HIP_TRY(ctx, launch_count_of(pn, pcol, w.cnt, s));
+    HIP_TRY(ctx, exclusive_scan_u32_i64(w.cnt, n_agg, w.moff, w.part, s));
+    HIP_TRY(ctx, launch_fill_u32(w.cursor, 0u, n_agg, s));
+    HIP_TRY(ctx, launch_sorted_members(pn, pcol, n_agg, w.moff, w.cursor, w.members, s));
+    // Ac = P^T (A P)
+    HIP_TRY(ctx, launch_smoothed_sym(2, false, n_agg, g->row_ptr, g->col, agg, w.apptr, w.apcol,
+                                     w.moff, w.members, w.prow_of, w.cnt, nullptr, nullptr,
+                                     w.flag + 1, s));
+    HIP_TRY(ctx, exclusive_scan_u32_i64(w.cnt, n_agg, crow, w.part, s));
+    int64_t cn = 0;
+    if ((rc = read_total(ctx, crow + n_agg, w.flag + 1, &cn, &flags, s))) return rc;
+    if (flags & 1u)
+        return fail(ctx, MIS2_ENOSPACE,
+                    "mis2_smoothed: a row of the coarse operator has more than 2048 columns");
+    *c_nnz = cn;
+    if (cn > c_cap || (cn > 0 && (!ccol || !cval)))
+        return fail(ctx, MIS2_ENOSPACE, "mis2_smoothed: the coarse operator has %lld entries, "
+                    "room for %lld", (long long)cn, (long long)c_cap);
+    HIP_TRY(ctx, launch_smoothed_sym(2, true, n_agg, g->row_ptr, g->col, agg, w.apptr, w.apcol,
+                                     w.moff, w.members, w.prow_of, nullptr, crow, ccol,
+                                     w.flag + 1, s));
+    HIP_TRY(ctx, launch_c_values(n_agg, cn, w.moff, w.members, w.prow_of, pval, w.apptr, w.apcol,
+                                 w.apval, crow, ccol, cval, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
     return MIS2_OK;
 }
 

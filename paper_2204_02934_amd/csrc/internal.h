@@ -306,6 +306,28 @@ hipError_t launch_rounds(int lanes, int blocks, const int64_t *row_ptr, const in
                          uint32_t *T, uint32_t *M, const RoundsArgs &a, hipStream_t s);
 // e0 / e1 (may be null): events stamped by the launch itself at the kernel's
 // start and end.
+// smoothed.hip: smoothed aggregation.  kind 0: P rows (sources N[i], one
+// aggregate each), 1: AP rows (P rows of N[i]), 2: coarse rows (AP rows of
+// the rows holding P[i][a]); count pass (fill == false) writes count[r] and
+// sets *err |= 1 for a row of more than 2048 distinct columns; fill pass
+// writes the ascending columns at out_ptr[r].
+hipError_t launch_smoothed_sym(int kind, bool fill, int64_t rows, const int64_t *row_ptr,
+                               const int32_t *col, const int32_t *agg, const int64_t *sptr,
+                               const int32_t *scol, const int64_t *moff, const int32_t *members,
+                               const int32_t *prow_of, uint32_t *count, const int64_t *out_ptr,
+                               int32_t *out_col, uint32_t *err, hipStream_t s);
+hipError_t launch_p_values(int64_t n, int64_t p_nnz, const int64_t *row_ptr, const int32_t *col,
+                           const double *val, const double *diag, const int32_t *agg,
+                           const uint32_t *size, double omega, const int64_t *prow,
+                           const int32_t *pcol, double *pval, int32_t *prow_of, hipStream_t s);
+hipError_t launch_ap_values(int64_t n, int64_t ap_nnz, const int64_t *row_ptr, const int32_t *col,
+                            const double *val, const double *diag, const int64_t *prow,
+                            const int32_t *pcol, const double *pval, const int64_t *aptr,
+                            const int32_t *acol, double *aval, hipStream_t s);
+hipError_t launch_c_values(int64_t n_agg, int64_t c_nnz, const int64_t *moff,
+                           const int32_t *members, const int32_t *prow_of, const double *pval,
+                           const int64_t *aptr, const int32_t *acol, const double *aval,
+                           const int64_t *crow, const int32_t *ccol, double *cval, hipStream_t s);
 // cgs.hip: Algorithm 4 (cluster multicolor Gauss-Seidel).
 hipError_t launch_jp_init(int64_t n, const TupleParams &tp, uint32_t *pr, int32_t *cround,
                           int32_t *color, hipStream_t s);

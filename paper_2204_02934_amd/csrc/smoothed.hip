@@ -1,0 +1,391 @@
+// smoothed.hip -- smoothed aggregation on gfx950: the damped-Jacobi
+// prolongator P = (I - omega D^-1 A) P_tent of an aggregation and the coarse
+// operator P^T A P (the multigrid setup Section VI-E runs on these
+// aggregates smooths its prolongator; the paper prints no formula).
+//
+// P_tent[i][agg i] = 1/sqrt(n_a) as in galerkin.hip.  Three sparse products,
+// each with one fixed sequence of roundings:
+//   P[i][a]  = (1{a = agg i} - (omega / d_i) * S) / sqrt(n_a), S = the sum of
+//              A_ij over j in N[i] with agg j = a, from 0.0, the diagonal
+//              first, then row i's entries in CSR order;
+//   AP[i][b] = the sum of A_ij * P[j][b] over j in N[i] (i first, then row
+//              i's entries in CSR order), from 0.0, absent P[j][b] skipped;
+//   Ac[a][b] = the sum of P[i][a] * AP[i][b] over the rows i holding
+//              P[i][a], in increasing i, from 0.0, absent AP[i][b] skipped.
+// Patterns are structural, columns ascending: P row i = the distinct
+// aggregates of N[i]; AP row i = the union of the P rows of N[i]; Ac row a =
+// the union of the AP rows i with P[i][a].
+//
+// Structure (symbolic) kernels: one wavefront per output row.  The row's
+// candidate columns -- each source row's columns, sources in order -- are
+// inserted into an LDS hash set (kSetCap slots, open addressing with
+// compare-and-swap); a count pass records the number of distinct columns,
+// and after a prefix sum a fill pass lists the set's columns and places each
+// at its rank among them (so rows come out ascending).  A row with more than
+// kSetMax distinct columns sets an error flag.
+// Value (numeric) kernels: one thread per output entry, which finds its row
+// by binary search in the row offsets and folds its terms one after the
+// other in the stated order, each term one rounded product (the file is
+// compiled without contraction into fused multiply-adds).
+#include "internal.h"
+#include "lanes.h"
+
+#pragma clang fp contract(off)
+
+namespace mis2 {
+
+namespace {
+
+constexpr int kSetCap = 4096;       // LDS hash-set slots per wavefront
+constexpr int kSetMax = 2048;       // distinct columns a row may have (load factor 1/2)
+constexpr int kSThreads = 128;            // structure kernels: 2 wavefronts per workgroup
+constexpr int kSWaves = kSThreads / 64;     // (50 KB of LDS per workgroup)
+constexpr int32_t kEmpty = -1;
+
+int grid_of_s(int64_t work, int per_block, int cap) {
+    const int64_t b = (work + per_block - 1) / per_block;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
+}
+
+struct SetLds {
+    int32_t slot[kSetCap];
+    int32_t list[kSetMax];
+    int64_t src_lo[64];   // a batch of 64 source rows: first entry
+    int64_t src_end[65];  // inclusive prefix of their lengths (src_end[0] = 0)
+};
+
+__device__ __forceinline__ void wave_sync_s() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t set_hash(int32_t c) {
+    return ((uint32_t)c * 2654435761u) >> 20;  // 12 bits: kSetCap slots
+}
+
+// Inserts c (c >= 0) into the set; returns 1 if it was new, 0 if present,
+// and 2 if the set is full (the caller flags an error).
+__device__ __forceinline__ int set_insert(SetLds &sh, int32_t c) {
+    uint32_t h = set_hash(c) & (kSetCap - 1);
+    for (int probe = 0; probe < kSetCap; probe++) {
+        const int32_t old = atomicCAS(&sh.slot[h], kEmpty, c);
+        if (old == kEmpty) return 1;
+        if (old == c) return 0;
+        h = (h + 1) & (kSetCap - 1);
+    }
+    return 2;
+}
+
+// The three kinds of rows.  For output row r, sources(r) gives the source
+// rows in order; each source s contributes the columns col_of(s, k) for k in
+// [0, len(s)).
+//   kP:  sources = i, then i's neighbours; a source j contributes agg[j].
+//   kAP: sources = i, then i's neighbours; a source j contributes P row j.
+//   kC:  sources = the rows holding P[i][a] (members of R_a, increasing i);
+//        a source i contributes AP row i.
+enum { kP = 0, kAP = 1, kC = 2 };
+
+struct SymArgs {
+    int64_t rows;
+    // the graph
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const int32_t *agg;
+    // source CSR (P for kAP, AP for kC)
+    const int64_t *sptr;
+    const int32_t *scol;
+    // kC: the members of R_a as P entry indices, and the row of each P entry
+    const int64_t *moff;
+    const int32_t *members;
+    const int32_t *prow_of;
+    // output
+    uint32_t *count;          // count pass
+    const int64_t *out_ptr;   // fill pass
+    int32_t *out_col;
+    uint32_t *err;            // |= 1: a row with more than kSetMax columns
+};
+
+// Source rows of output row r: [first, last) of an index range, and the row
+// id of source index t.
+template <int K>
+__device__ __forceinline__ void source_range(const SymArgs &a, int64_t r, int64_t &first,
+                                             int64_t &last) {
+    if (K == kC) {
+        first = a.moff[r];
+        last = a.moff[r + 1];
+    } else {
+        first = a.row_ptr[r] - 1;  // index first - 1 ... stands for r itself
+        last = a.row_ptr[r + 1];
+    }
+}
+
+template <int K>
+__device__ __forceinline__ int64_t source_row(const SymArgs &a, int64_t r, int64_t t) {
+    if (K == kC) return a.prow_of[a.members[t]];
+    return t < a.row_ptr[r] ? r : (int64_t)a.col[t];
+}
+
+// Inserts every candidate column of output row r; returns the number of new
+// columns this lane inserted, and sets *full when the set overflowed.
+template <int K>
+__device__ uint32_t insert_row(SetLds &sh, const SymArgs &a, int64_t r, bool *full) {
+    const int lane = (int)(threadIdx.x & 63u);
+    uint32_t added = 0;
+    bool ovf = false;
+    int64_t first, last;
+    source_range<K>(a, r, first, last);
+    if (K == kP) {
+        // one column per source: 64 sources at a time
+        for (int64_t t0 = first; t0 < last; t0 += 64) {
+            const int64_t t = t0 + lane;
+            if (t < last) {
+                const int rc = set_insert(sh, a.agg[source_row<K>(a, r, t)]);
+                added += rc == 1;
+                ovf |= rc == 2;
+            }
+        }
+    } else {
+        for (int64_t t0 = first; t0 < last; t0 += 64) {
+            // a batch of up to 64 source rows: their extents and prefix
+            const int64_t t = t0 + lane;
+            int64_t lo = 0, len = 0;
+            if (t < last) {
+                const int64_t s = source_row<K>(a, r, t);
+                lo = a.sptr[s];
+                len = a.sptr[s + 1] - lo;
+            }
+            int64_t incl = len;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int64_t y = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += y;
+            }
+            sh.src_lo[lane] = lo;
+            sh.src_end[lane + 1] = incl;
+            if (lane == 0) sh.src_end[0] = 0;
+            wave_sync_s();
+            const int64_t total = sh.src_end[64];
+            for (int64_t k0 = 0; k0 < total; k0 += 64) {
+                const int64_t k = k0 + lane;
+                if (k < total) {
+                    // the source holding candidate k: last q with src_end[q] <= k
+                    int q = 0;
+                    for (int step = 32; step > 0; step >>= 1)
+                        if (q + step <= 63 && sh.src_end[q + step] <= k) q += step;
+                    const int rc = set_insert(sh, a.scol[sh.src_lo[q] + (k - sh.src_end[q])]);
+                    added += rc == 1;
+                    ovf |= rc == 2;
+                }
+            }
+            wave_sync_s();
+        }
+    }
+    *full = ovf;
+    return added;
+}
+
+template <int K, bool FILL>
+__global__ __launch_bounds__(kSThreads) void k_sym(SymArgs a) {
+    __shared__ SetLds sh_all[kSWaves];
+    SetLds &sh = sh_all[threadIdx.x >> 6];
+    const int lane = (int)(threadIdx.x & 63u);
+    const int64_t w0 = (int64_t)blockIdx.x * kSWaves + (threadIdx.x >> 6);
+    const int64_t stride = (int64_t)gridDim.x * kSWaves;
+    for (int64_t r = w0; r < a.rows; r += stride) {
+        for (int q = lane; q < kSetCap; q += 64) sh.slot[q] = kEmpty;
+        wave_sync_s();
+        bool full = false;
+        const uint32_t added = insert_row<K>(sh, a, r, &full);
+        wave_sync_s();
+        const uint32_t distinct = group_sum<64>(added);
+        const bool bad = __ballot(full) != 0 || distinct > (uint32_t)kSetMax;
+        if (!FILL) {
+            if (lane == 0) {
+                a.count[r] = bad ? 0u : distinct;
+                if (bad) atomicOr(a.err, 1u);
+            }
+            continue;
+        }
+        if (bad) continue;  // the count pass flagged it; the call fails
+        // list the set's columns, then place each at its rank
+        uint32_t n_list = 0;
+        for (int q0 = 0; q0 < kSetCap; q0 += 64) {
+            const int32_t c = sh.slot[q0 + lane];
+            const bool has = c != kEmpty;
+            const uint64_t m = __ballot(has);
+            if (has) sh.list[n_list + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = c;
+            n_list += (uint32_t)__popcll(m);
+        }
+        wave_sync_s();
+        int32_t *out = a.out_col + a.out_ptr[r];
+        for (uint32_t x0 = 0; x0 < n_list; x0 += 64) {
+            const uint32_t x = x0 + lane;
+            const int32_t c = x < n_list ? sh.list[x] : 0;
+            uint32_t rank = 0;
+            for (uint32_t y = 0; y < n_list; y++) rank += sh.list[y] < c;
+            if (x < n_list) out[rank] = c;
+        }
+        wave_sync_s();
+    }
+}
+
+// Row of entry e in a CSR of `rows` rows: the last r with ptr[r] <= e.
+__device__ __forceinline__ int64_t row_of(const int64_t *ptr, int64_t rows, int64_t e) {
+    int64_t lo = 0, hi = rows - 1;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (ptr[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Position of column c in the ascending cols[lo, hi), or -1.
+__device__ __forceinline__ int64_t find_col(const int32_t *cols, int64_t lo, int64_t hi,
+                                            int32_t c) {
+    int64_t l = lo, h = hi;
+    while (l < h) {
+        const int64_t mid = l + (h - l) / 2;
+        if (cols[mid] < c) l = mid + 1; else h = mid;
+    }
+    return (l < hi && cols[l] == c) ? l : -1;
+}
+
+// P values, one thread per entry (see the file comment).
+__global__ __launch_bounds__(kBlock) void k_p_values(int64_t n, const int64_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col,
+                                                     const double *__restrict__ val,
+                                                     const double *__restrict__ diag,
+                                                     const int32_t *__restrict__ agg,
+                                                     const uint32_t *__restrict__ size,
+                                                     double omega, const int64_t *__restrict__ prow,
+                                                     const int32_t *__restrict__ pcol,
+                                                     double *__restrict__ pval,
+                                                     int32_t *__restrict__ prow_of) {
+    const int64_t nnz = prow[n];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < nnz; p += stride) {
+        const int64_t i = row_of(prow, n, p);
+        const int32_t a = pcol[p];
+        double s = 0.0;
+        if (agg[i] == a) s = s + diag[i];
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++)
+            if (agg[col[e]] == a) s = s + val[e];
+        const double w = omega / diag[i];
+        const double ind = agg[i] == a ? 1.0 : 0.0;
+        const double t = w * s;
+        const double r = ind - t;
+        pval[p] = r / sqrt((double)size[a]);
+        prow_of[p] = (int32_t)i;
+    }
+}
+
+// AP values, one thread per entry.
+__global__ __launch_bounds__(kBlock) void k_ap_values(int64_t n, const int64_t *__restrict__ row_ptr,
+                                                      const int32_t *__restrict__ col,
+                                                      const double *__restrict__ val,
+                                                      const double *__restrict__ diag,
+                                                      const int64_t *__restrict__ prow,
+                                                      const int32_t *__restrict__ pcol,
+                                                      const double *__restrict__ pval,
+                                                      const int64_t *__restrict__ aptr,
+                                                      const int32_t *__restrict__ acol,
+                                                      double *__restrict__ aval) {
+    const int64_t nnz = aptr[n];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nnz; q += stride) {
+        const int64_t i = row_of(aptr, n, q);
+        const int32_t b = acol[q];
+        double acc = 0.0;
+        int64_t p = find_col(pcol, prow[i], prow[i + 1], b);
+        if (p >= 0) acc = acc + diag[i] * pval[p];
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++) {
+            const int32_t j = col[e];
+            p = find_col(pcol, prow[j], prow[j + 1], b);
+            if (p >= 0) acc = acc + val[e] * pval[p];
+        }
+        aval[q] = acc;
+    }
+}
+
+// Ac values, one thread per entry: rows of R_a in increasing id (members
+// hold P entry indices in increasing order, hence increasing row).
+__global__ __launch_bounds__(kBlock) void k_c_values(int64_t n_agg, const int64_t *__restrict__ moff,
+                                                     const int32_t *__restrict__ members,
+                                                     const int32_t *__restrict__ prow_of,
+                                                     const double *__restrict__ pval,
+                                                     const int64_t *__restrict__ aptr,
+                                                     const int32_t *__restrict__ acol,
+                                                     const double *__restrict__ aval,
+                                                     const int64_t *__restrict__ crow,
+                                                     const int32_t *__restrict__ ccol,
+                                                     double *__restrict__ cval) {
+    const int64_t nnz = crow[n_agg];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nnz; q += stride) {
+        const int64_t a = row_of(crow, n_agg, q);
+        const int32_t b = ccol[q];
+        double acc = 0.0;
+        for (int64_t t = moff[a]; t < moff[a + 1]; t++) {
+            const int32_t p = members[t];
+            const int64_t i = prow_of[p];
+            const int64_t u = find_col(acol, aptr[i], aptr[i + 1], b);
+            if (u >= 0) acc = acc + pval[p] * aval[u];
+        }
+        cval[q] = acc;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_smoothed_sym(int kind, bool fill, int64_t rows, const int64_t *row_ptr,
+                               const int32_t *col, const int32_t *agg, const int64_t *sptr,
+                               const int32_t *scol, const int64_t *moff, const int32_t *members,
+                               const int32_t *prow_of, uint32_t *count, const int64_t *out_ptr,
+                               int32_t *out_col, uint32_t *err, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    SymArgs a{rows, row_ptr, col, agg, sptr, scol, moff, members, prow_of, count, out_ptr,
+              out_col, err};
+    const dim3 grid(grid_of_s(rows, kSWaves, 8192)), block(kSThreads);
+    switch (kind * 2 + (fill ? 1 : 0)) {
+        case 0: hipLaunchKernelGGL((k_sym<kP, false>), grid, block, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_sym<kP, true>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_sym<kAP, false>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_sym<kAP, true>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_sym<kC, false>), grid, block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_sym<kC, true>), grid, block, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_p_values(int64_t n, int64_t p_nnz, const int64_t *row_ptr, const int32_t *col,
+                           const double *val, const double *diag, const int32_t *agg,
+                           const uint32_t *size, double omega, const int64_t *prow,
+                           const int32_t *pcol, double *pval, int32_t *prow_of, hipStream_t s) {
+    if (n <= 0 || p_nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_p_values, dim3(grid_of_s(p_nnz, kBlock, 16384)), dim3(kBlock), 0, s, n,
+                       row_ptr, col, val, diag, agg, size, omega, prow, pcol, pval, prow_of);
+    return hipGetLastError();
+}
+
+hipError_t launch_ap_values(int64_t n, int64_t ap_nnz, const int64_t *row_ptr, const int32_t *col,
+                            const double *val, const double *diag, const int64_t *prow,
+                            const int32_t *pcol, const double *pval, const int64_t *aptr,
+                            const int32_t *acol, double *aval, hipStream_t s) {
+    if (n <= 0 || ap_nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ap_values, dim3(grid_of_s(ap_nnz, kBlock, 16384)), dim3(kBlock), 0, s, n,
+                       row_ptr, col, val, diag, prow, pcol, pval, aptr, acol, aval);
+    return hipGetLastError();
+}
+
+hipError_t launch_c_values(int64_t n_agg, int64_t c_nnz, const int64_t *moff,
+                           const int32_t *members, const int32_t *prow_of, const double *pval,
+                           const int64_t *aptr, const int32_t *acol, const double *aval,
+                           const int64_t *crow, const int32_t *ccol, double *cval, hipStream_t s) {
+    if (n_agg <= 0 || c_nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_c_values, dim3(grid_of_s(c_nnz, kBlock, 16384)), dim3(kBlock), 0, s,
+                       n_agg, moff, members, prow_of, pval, aptr, acol, aval, crow, ccol, cval);
+    return hipGetLastError();
+}
+
+}  // namespace mis2
