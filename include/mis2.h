@@ -87,8 +87,10 @@ extern "C" {
                                      vertices runs with the fastest of a few launch plans for
                                      its class (half octave of n and degree histogram), timed
                                      once per class and device on its first sight in the
-                                     process; 0: the fixed degree rule.  Plans never change
-                                     results. */
+                                     process; 2: the plan of a class tuned before in the
+                                     process, never a tuning run (a class not seen yet takes
+                                     the degree rule); 0: the fixed degree rule.  Plans never
+                                     change results. */
 
 typedef struct mis2_ctx mis2_ctx;
 
@@ -522,6 +524,10 @@ int mis2_aggregate_batched(mis2_ctx *ctx, const mis2_graph *g, int32_t n_graphs,
  * Algorithm 3 for every graph in the union at once (graphs at different levels
  * side by side); graphs that go on stay in the union as their coarse graphs,
  * so new jobs join at the next step.  Not thread-safe; one stream at a time.
+ * A union's make-up changes from step to step, so the server's context never
+ * runs a tuning pass inside a step (MIS2_OPT_AUTOTUNE = 2): a union takes the
+ * plan of its class when that class was tuned earlier in the process, else
+ * the degree rule.
  */
 #define MIS2_SERVE_MAX_LEVELS 32
 

@@ -784,6 +784,7 @@ int apply_plan(mis2_ctx *ctx, const mis2_graph *g, const Workspace &ws, hipStrea
             }
         }
     }
+    if (ctx->autotune == 2) return MIS2_OK;  // lookup only: the degree rule
     Plan best = ctx->plan;
     if ((rc = tune(ctx, g, ws, s, &best))) return rc;
     {
@@ -1043,7 +1044,8 @@ int mis2_set_option(mis2_ctx *ctx, int option, int64_t value) {
             ctx->plan.compact = value != 0;
             return MIS2_OK;
         case MIS2_OPT_AUTOTUNE:
-            ctx->autotune = value != 0;
+            if (value < 0 || value > 2) return fail(ctx, MIS2_EINVAL, "autotune must be 0, 1 or 2");
+            ctx->autotune = (int)value;
             return MIS2_OK;
         case MIS2_OPT_TAIL:
             if (value < -1 || value > 1) return fail(ctx, MIS2_EINVAL, "tail must be -1, 0 or 1");

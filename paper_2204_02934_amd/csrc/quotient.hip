@@ -12,12 +12,14 @@
 // every coarse row is a sorted set).  A coarse row whose members have at most
 // kWCap stored entries in all is handled by one wavefront: it puts the
 // aggregate ids of the members' neighbours into an LDS hash set and sorts the
-// distinct ones.  Larger rows
-// are listed and handled by a whole workgroup each: the same gather and sort
+// distinct ones (member rows longer than kWShort are read by the whole
+// wavefront).  Larger rows are listed and handled by a whole workgroup each,
+// whose threads share the members' entries evenly: the same gather and sort
 // for up to kQCap candidates, else a sweep over the coarse id space in
-// windows of 32*kQCap ids with an LDS bitmap, which emits ids in increasing
-// order.  Both kernels run twice: once to count each row, once (after a
-// prefix sum) to write it.
+// windows of 32*kBitWords ids with an LDS bitmap, which emits ids in
+// increasing order and, after the first window, visits only the range the
+// row's candidates span.  Both kernels run twice: once to count each row,
+// once (after a prefix sum) to write it.
 #include "internal.h"
 
 namespace mis2 {
@@ -25,12 +27,12 @@ namespace mis2 {
 namespace {
 
 constexpr int kQCap = 4096;                  // candidates sorted in LDS per coarse row
-constexpr int64_t kQWindow = 32 * kQCap;     // coarse ids per bitmap window
+constexpr int kBitWords = 12288;             // LDS bitmap words (48 KiB)
+constexpr int64_t kQWindow = 32 * (int64_t)kBitWords;  // coarse ids per bitmap window
 constexpr int kWaves = kBlock / 64;
 constexpr int kWCap = 1024;                  // candidates of a row handled by one wavefront
 constexpr int kWEdges = 8;                   // entries per lane loaded together
-constexpr int kShortRow = 64;                // member rows read by one thread (bitmap path)
-constexpr uint32_t kLongCap = 1024;          // long member rows listed in LDS (bitmap path)
+constexpr int kWShort = 32;                  // member rows read by one lane (wavefront path)
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -82,7 +84,22 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows_wave(
             continue;
         }
         // gather into the set: each lane takes one member at a time and
-        // loads kWEdges of its entries together
+        // loads kWEdges of its entries together; rows longer than kWShort
+        // are walked by the whole wavefront instead, one after the other
+        auto put = [&](int32_t cv) {
+            if (cv < 0 || (int64_t)cv == a) return;
+            const uint32_t key = (uint32_t)cv;
+            uint32_t h = qhash(key);
+            for (;;) {  // the set has room for every candidate, so this ends
+                const uint32_t prev = atomicCAS(&tab[h], kEmpty, key);
+                if (prev == kEmpty) {
+                    list[atomicAdd(&nums[wv], 1u)] = key;
+                    break;
+                }
+                if (prev == key) break;
+                h = (h + 1) & (kWCap - 1);
+            }
+        };
         for (int64_t i0 = m0; i0 < m1; i0 += 64) {
             const int64_t i = i0 + lane;
             int64_t s = 0, e = 0;
@@ -91,7 +108,9 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows_wave(
                 s = row_ptr[v];
                 e = row_ptr[v + 1];
             }
-            int64_t len = e - s, lmax = len;
+            const bool lng = e - s > kWShort;
+            const int64_t len = lng ? 0 : e - s;
+            int64_t lmax = len;
             for (int off = 32; off > 0; off >>= 1) lmax = max(lmax, __shfl_xor(lmax, off, 64));
             for (int64_t c0 = 0; c0 < lmax; c0 += kWEdges) {
                 int32_t x[kWEdges];
@@ -101,20 +120,27 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows_wave(
 #pragma unroll
                 for (int k = 0; k < kWEdges; k++) c[k] = agg[x[k]];
 #pragma unroll
-                for (int k = 0; k < kWEdges; k++) {
-                    if (c0 + k < len && c[k] >= 0 && (int64_t)c[k] != a) {
-                        const uint32_t key = (uint32_t)c[k];
-                        uint32_t h = qhash(key);
-                        for (;;) {  // the set has room for every candidate, so this ends
-                            const uint32_t prev = atomicCAS(&tab[h], kEmpty, key);
-                            if (prev == kEmpty) {
-                                list[atomicAdd(&nums[wv], 1u)] = key;
-                                break;
-                            }
-                            if (prev == key) break;
-                            h = (h + 1) & (kWCap - 1);
-                        }
+                for (int k = 0; k < kWEdges; k++)
+                    if (c0 + k < len) put(c[k]);
+            }
+            unsigned long long longs = __ballot(lng);
+            while (longs) {
+                const int src = __ffsll(longs) - 1;
+                longs &= longs - 1;
+                const int64_t rs = __shfl(s, src, 64), re = __shfl(e, src, 64);
+                for (int64_t j0 = rs + lane; j0 < re; j0 += 64 * kWEdges) {
+                    int32_t x[kWEdges];
+#pragma unroll
+                    for (int k = 0; k < kWEdges; k++) {
+                        const int64_t j = j0 + 64 * k;
+                        x[k] = col[j < re ? j : rs];
                     }
+                    int32_t c[kWEdges];
+#pragma unroll
+                    for (int k = 0; k < kWEdges; k++) c[k] = agg[x[k]];
+#pragma unroll
+                    for (int k = 0; k < kWEdges; k++)
+                        if (j0 + 64 * k < re) put(c[k]);
                 }
             }
         }
@@ -205,6 +231,28 @@ __device__ __forceinline__ unsigned long long block_sum(unsigned long long x,
     return t;
 }
 
+// Minimum of *mn and maximum of *mx over the workgroup, in every thread (all
+// threads must call it).
+__device__ __forceinline__ void block_minmax(int32_t *mn, int32_t *mx, int32_t *scratch) {
+    int32_t a = *mn, b = *mx;
+    for (int off = 32; off > 0; off >>= 1) {
+        a = min(a, __shfl_xor(a, off, 64));
+        b = max(b, __shfl_xor(b, off, 64));
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63u) == 0) {
+        scratch[threadIdx.x >> 6] = a;
+        scratch[kWaves + (threadIdx.x >> 6)] = b;
+    }
+    __syncthreads();
+    for (int w = 0; w < kWaves; w++) {
+        a = min(a, scratch[w]);
+        b = max(b, scratch[kWaves + w]);
+    }
+    *mn = a;
+    *mx = b;
+}
+
 // Exclusive prefix of x over the workgroup in thread order; *total gets the
 // sum.  All threads must call it.
 __device__ __forceinline__ uint32_t block_excl(uint32_t x, uint32_t *scratch, uint32_t *total) {
@@ -226,6 +274,91 @@ __device__ __forceinline__ uint32_t block_excl(uint32_t x, uint32_t *scratch, ui
     return before + incl - x;
 }
 
+// Exclusive prefix of x over the workgroup in thread order (64-bit); *total
+// gets the sum.  All threads must call it.
+__device__ __forceinline__ unsigned long long block_excl64(unsigned long long x,
+                                                           unsigned long long *scratch,
+                                                           unsigned long long *total) {
+    const int lane = (int)(threadIdx.x & 63u), wave = (int)(threadIdx.x >> 6);
+    unsigned long long incl = x;
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    __syncthreads();
+    if (lane == 63) scratch[wave] = incl;
+    __syncthreads();
+    unsigned long long before = 0, t = 0;
+    for (int w = 0; w < kWaves; w++) {
+        if (w < wave) before += scratch[w];
+        t += scratch[w];
+    }
+    *total = t;
+    return before + incl - x;
+}
+
+// LDS of walk_members: the entry offsets and row starts of one chunk of
+// kBlock members.
+struct WalkLds {
+    unsigned long long off[kBlock + 1];
+    int64_t start[kBlock];
+    unsigned long long scan[kWaves];
+};
+
+// f(c) for the coarse id c = agg[col[j]] of every entry j of every member of
+// an aggregate (members[m0 .. m1)).  The members go in chunks of kBlock; the
+// chunk's entries are numbered through a prefix sum of the row lengths and
+// dealt out evenly, kWEdges per thread loaded together, each finding its
+// row by binary search over the offsets.  Rows of any length mix keep every
+// thread equally busy.  All threads must call it.
+template <typename F>
+__device__ __forceinline__ void walk_members(const int64_t *__restrict__ row_ptr,
+                                             const int32_t *__restrict__ col,
+                                             const int32_t *__restrict__ agg,
+                                             const int32_t *__restrict__ members, int64_t m0,
+                                             int64_t m1, WalkLds &w, F f) {
+    const int tid = (int)threadIdx.x;
+    for (int64_t c0 = m0; c0 < m1; c0 += kBlock) {
+        const int64_t i = c0 + tid;
+        int64_t rs = 0;
+        unsigned long long len = 0;
+        if (i < m1) {
+            const int32_t v = members[i];
+            rs = row_ptr[v];
+            len = (unsigned long long)(row_ptr[v + 1] - rs);
+        }
+        unsigned long long tot;
+        const unsigned long long ex = block_excl64(len, w.scan, &tot);
+        w.off[tid] = ex;
+        w.start[tid] = rs;
+        if (tid == 0) w.off[kBlock] = tot;
+        __syncthreads();
+        for (unsigned long long q0 = tid; q0 < tot; q0 += (unsigned long long)kBlock * kWEdges) {
+            int32_t x[kWEdges];
+#pragma unroll
+            for (int k = 0; k < kWEdges; k++) {
+                unsigned long long q = q0 + (unsigned long long)k * kBlock;
+                if (q >= tot) q = tot - 1;  // a valid entry; its result is not used
+                // the last row r with off[r] <= q (it is not empty: off[r + 1] > q)
+                int lo = 0, hi = kBlock;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (w.off[mid] <= q) lo = mid;
+                    else hi = mid;
+                }
+                x[k] = col[w.start[lo] + (int64_t)(q - w.off[lo])];
+            }
+            int32_t c[kWEdges];
+#pragma unroll
+            for (int k = 0; k < kWEdges; k++) c[k] = agg[x[k]];
+#pragma unroll
+            for (int k = 0; k < kWEdges; k++)
+                if (q0 + (unsigned long long)k * kBlock < tot) f(c[k]);
+        }
+        __syncthreads();  // the offsets are rewritten by the next chunk
+    }
+}
+
 // FILL = false: ccnt[a] = number of distinct coarse neighbours of row a.
 // FILL = true:  ccol[crow[a] ...] = those neighbours in increasing order.
 // The listed (large) coarse rows big[0 .. *big_count), one workgroup each.
@@ -241,12 +374,13 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows(const int64_t *__restric
                                                         int32_t *__restrict__ ccol,
                                                         const int32_t *__restrict__ big,
                                                         const uint32_t *__restrict__ big_count) {
-    __shared__ uint32_t buf[kQCap];
+    static_assert(kBitWords >= kQCap, "the sort buffer is the bitmap");
+    __shared__ uint32_t buf[kBitWords];
     __shared__ unsigned long long red[kWaves];
     __shared__ uint32_t scan_s[kWaves];
     __shared__ uint32_t fill_s;
-    __shared__ uint32_t longm[kLongCap];
-    __shared__ uint32_t nlong_s;
+    __shared__ WalkLds walk;
+    __shared__ int32_t range_s[2 * kWaves];
     const int tid = (int)threadIdx.x;
     const int64_t nbig = *big_count;
     for (int64_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
@@ -263,13 +397,9 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows(const int64_t *__restric
             // gather the candidate ids (self excluded) into LDS
             if (tid == 0) fill_s = 0;
             __syncthreads();
-            for (int64_t i = m0 + tid; i < m1; i += kBlock) {
-                const int32_t v = members[i];
-                for (int64_t j = row_ptr[v], e = row_ptr[v + 1]; j < e; j++) {
-                    const int32_t c = agg[col[j]];
-                    if (c >= 0 && (int64_t)c != a) buf[atomicAdd(&fill_s, 1u)] = (uint32_t)c;
-                }
-            }
+            walk_members(row_ptr, col, agg, members, m0, m1, walk, [&](int32_t c) {
+                if (c >= 0 && (int64_t)c != a) buf[atomicAdd(&fill_s, 1u)] = (uint32_t)c;
+            });
             __syncthreads();
             const uint32_t m = fill_s;
             uint32_t P = 1;
@@ -305,87 +435,63 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows(const int64_t *__restric
             }
             distinct = run;
         } else {
-            // bitmap windows over the coarse id space.  Members with short
-            // rows are read one per thread; members with long rows (listed
-            // once, in LDS) by the whole workgroup each.
-            if (tid == 0) nlong_s = 0u;
-            __syncthreads();
-            for (int64_t i = m0 + tid; i < m1; i += kBlock) {
-                const int32_t v = members[i];
-                if (row_ptr[v + 1] - row_ptr[v] > kShortRow) {
-                    const uint32_t k = atomicAdd(&nlong_s, 1u);
-                    if (k < kLongCap) longm[k] = (uint32_t)(i - m0);
-                }
-            }
-            __syncthreads();
-            const uint32_t nlong = nlong_s;
+            // bitmap windows over the coarse id space
             uint32_t run = 0;
-            for (int64_t lo = 0; lo < n_agg; lo += kQWindow) {
-                for (int i = tid; i < kQCap; i += kBlock) buf[i] = 0u;
+            // The first window also finds the smallest and largest candidate;
+            // later windows cover only that range, and each window emits
+            // only the words inside it.  In a disjoint union the candidates
+            // lie in the row's own graph, so a big row never sweeps the
+            // coarse ids of the other graphs.
+            int64_t hi = n_agg;
+            int32_t tmin = INT32_MAX, tmax = -1;
+            bool first = true;
+            for (int64_t lo = 0; lo < hi;) {
+                for (int i = tid; i < kBitWords; i += kBlock) buf[i] = 0u;
                 __syncthreads();
-                for (int64_t i = m0 + tid; i < m1; i += kBlock) {
-                    const int32_t v = members[i];
-                    const int64_t rs = row_ptr[v], len = row_ptr[v + 1] - rs;
-                    if (len > kShortRow) continue;
-                    for (int64_t c0 = 0; c0 < len; c0 += kWEdges) {
-                        int32_t x[kWEdges];
-#pragma unroll
-                        for (int k = 0; k < kWEdges; k++) x[k] = col[c0 + k < len ? rs + c0 + k : rs];
-                        int32_t c[kWEdges];
-#pragma unroll
-                        for (int k = 0; k < kWEdges; k++) c[k] = agg[x[k]];
-#pragma unroll
-                        for (int k = 0; k < kWEdges; k++) {
-                            const int64_t ck = c[k];
-                            if (c0 + k < len && ck != a && ck >= lo && ck < lo + kQWindow) {
-                                const int64_t o = ck - lo;
-                                atomicOr(&buf[o >> 5], 1u << (o & 31));
+                walk_members(row_ptr, col, agg, members, m0, m1, walk, [&](int32_t c) {
+                    if (c < 0 || (int64_t)c == a) return;
+                    if (first) {
+                        tmin = min(tmin, c);
+                        tmax = max(tmax, c);
+                    }
+                    const int64_t o = (int64_t)c - lo;
+                    if (o >= 0 && o < kQWindow) atomicOr(&buf[o >> 5], 1u << (o & 31));
+                });
+                __syncthreads();
+                if (first) {
+                    block_minmax(&tmin, &tmax, range_s);
+                    hi = (int64_t)tmax + 1;  // no candidate at all: tmax = -1 ends the sweep
+                }
+                // emit the set ids of this window in increasing order
+                const int64_t e_lo = max(lo, (int64_t)tmin);
+                const int64_t e_hi = min(lo + kQWindow, hi);
+                if (e_lo < e_hi) {
+                    const int w0 = (int)((e_lo - lo) >> 5), w1 = (int)((e_hi - lo + 31) >> 5);
+                    for (int c0 = w0; c0 < w1; c0 += kBlock) {
+                        const int wi = c0 + tid;
+                        const uint32_t word = wi < w1 ? buf[wi] : 0u;
+                        uint32_t tot;
+                        const uint32_t pos = block_excl((uint32_t)__popc(word), scan_s, &tot);
+                        if (FILL) {
+                            uint32_t wv = word, k = 0;
+                            while (wv) {
+                                const int bit = __ffs(wv) - 1;
+                                wv &= wv - 1;
+                                ccol[crow[a] + run + pos + k] =
+                                    (int32_t)(lo + (int64_t)wi * 32 + bit);
+                                k++;
                             }
                         }
-                    }
-                }
-                for (uint32_t t = 0; t < (nlong <= kLongCap ? nlong : 0u); t++) {
-                    const int32_t v = members[m0 + longm[t]];
-                    for (int64_t j = row_ptr[v] + tid, e = row_ptr[v + 1]; j < e; j += kBlock) {
-                        const int64_t c = agg[col[j]];
-                        if (c != a && c >= lo && c < lo + kQWindow) {
-                            const int64_t o = c - lo;
-                            atomicOr(&buf[o >> 5], 1u << (o & 31));
-                        }
-                    }
-                }
-                if (nlong > kLongCap) {  // too many long members to list: scan them all
-                    for (int64_t i = m0; i < m1; i++) {
-                        const int32_t v = members[i];
-                        if (row_ptr[v + 1] - row_ptr[v] <= kShortRow) continue;
-                        for (int64_t j = row_ptr[v] + tid, e = row_ptr[v + 1]; j < e;
-                             j += kBlock) {
-                            const int64_t c = agg[col[j]];
-                            if (c != a && c >= lo && c < lo + kQWindow) {
-                                const int64_t o = c - lo;
-                                atomicOr(&buf[o >> 5], 1u << (o & 31));
-                            }
-                        }
+                        run += tot;
                     }
                 }
                 __syncthreads();
-                for (int c0 = 0; c0 < kQCap; c0 += kBlock) {
-                    const int wi = c0 + tid;
-                    const uint32_t word = buf[wi];
-                    uint32_t tot;
-                    const uint32_t pos = block_excl((uint32_t)__popc(word), scan_s, &tot);
-                    if (FILL) {
-                        uint32_t wv = word, k = 0;
-                        while (wv) {
-                            const int bit = __ffs(wv) - 1;
-                            wv &= wv - 1;
-                            ccol[crow[a] + run + pos + k] = (int32_t)(lo + (int64_t)wi * 32 + bit);
-                            k++;
-                        }
-                    }
-                    run += tot;
+                int64_t next = lo + kQWindow;
+                if (first) {
+                    if ((int64_t)tmin > next) next = tmin;
+                    first = false;
                 }
-                __syncthreads();
+                lo = next;
             }
             distinct = run;
         }

@@ -108,6 +108,12 @@ int mis2_server_create(mis2_server **out, int device, void *arena, size_t arena_
         delete s;
         return rc;
     }
+    // unions change from step to step: tuned plans are looked up, never timed
+    if ((rc = mis2_set_option(s->ctx, MIS2_OPT_AUTOTUNE, 2))) {
+        mis2_destroy(s->ctx);
+        delete s;
+        return rc;
+    }
     if ((rc = mis2_set_workspace(s->ctx, arena, arena_bytes))) {
         mis2_destroy(s->ctx);
         delete s;

@@ -244,6 +244,27 @@ def test_quotient_big_rows_use_bitmap_windows(ctx):
     assert np.array_equal(ccol.cpu().numpy(), ocol)
 
 
+@pytest.mark.parametrize("hub_label,leaf_lo,leaf_step", [
+    (5, 200_000, 7),         # candidates all above the first window, spanning two more
+    (399_999, 130_000, 9),   # candidates cross the first window's end; own id above them
+    (250_000, 0, 1),         # candidates inside the first window only
+])
+def test_quotient_big_row_candidate_range(ctx, hub_label, leaf_lo, leaf_step):
+    # a coarse id space of several bitmap windows (131072 ids each) in which
+    # the one big row's candidates cover only part, as in a disjoint union
+    # (the isolated vertices that pad the graph to n_agg are their own labels)
+    n, n_agg = 20001, 400_000
+    rp, c = graphs.disjoint_union([graphs.star(n, 0), graphs.edgeless(n_agg - n)])
+    agg = np.arange(n_agg, dtype=np.int32)
+    agg[0] = hub_label
+    agg[1:n] = leaf_lo + leaf_step * np.arange(n - 1)
+    assert agg.max() < n_agg
+    crow, ccol = ctx.quotient(rp, c, agg, n_agg)
+    orow, ocol = oracle.quotient(rp, c, agg, n_agg)
+    assert np.array_equal(crow.cpu().numpy(), orow)
+    assert np.array_equal(ccol.cpu().numpy(), ocol)
+
+
 def test_quotient_many_long_members(ctx):
     # one aggregate of 1100 vertices whose rows are all long (70 entries):
     # more long members than the workgroup path lists in LDS

@@ -98,3 +98,21 @@ def test_tuned_batched_levels_match_oracle(api):
         for a, b in zip(got[i], want):
             assert (a["n"], a["nnz"], a["n_agg"]) == (b["n"], b["nnz"], b["n_agg"]), i
             assert np.array_equal(a["agg"].cpu().numpy(), b["agg"]), i
+
+
+def test_lookup_only_never_tunes(api):
+    # autotune = 2 takes a class's tuned plan when one exists, else the
+    # degree rule, and never times candidates itself
+    rp, cc = graphs.cycle(150_001)  # a class (every degree 2) no other test tunes
+    look = api.Context(0, autotune=2)
+    _mis2_ok(look, rp, cc, 1, "lookup, new class")
+    assert look.last_plan()["source"] == 0 and look.last_tuning() == []
+    tuner = api.Context(0)
+    _mis2_ok(tuner, rp, cc, 1, "tuning")
+    p = tuner.last_plan()
+    assert p["source"] in (1, 2)
+    _agg_ok(look, rp, cc, 3, "lookup, tuned class")
+    q = look.last_plan()
+    assert q["source"] == 1 and (q["lanes"], q["blocks"]) == (p["lanes"], p["blocks"])
+    with pytest.raises(Exception):
+        api.Context(0, autotune=3)
