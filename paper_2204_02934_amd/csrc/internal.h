@@ -146,6 +146,8 @@ struct Workspace {
         unsigned long long *part = nullptr;
         int32_t *big = nullptr;
         uint32_t *big_count = nullptr;
+        uint32_t *gbits = nullptr;   // [kGiantSlots * giant_words(n)]
+        uint32_t *gmeta = nullptr;   // [kGiantMeta]
     } q;
 };
 
@@ -428,6 +430,12 @@ hipError_t exclusive_scan_u32_i64(const uint32_t *in, int64_t n, int64_t *out,
 hipError_t launch_scan_tiles(uint32_t *blocksum, int64_t nb, uint32_t *d_total, hipStream_t s);
 
 // quotient.hip: coarse graph of an aggregation.
+// Coarse rows with more than kGiantCand candidates take one of kGiantSlots
+// bitmap slots (a bit per coarse id) filled by the whole grid.
+constexpr int kGiantSlots = 8;
+constexpr int64_t kGiantCand = 65536;
+constexpr int kGiantMeta = 3 * kGiantSlots + 1;  // rows, smallest and largest ids, count
+inline size_t giant_words(int64_t n) { return (size_t)((n + 31) / 32); }
 struct QuotientWs {
     uint32_t *cnt;              // [n_agg] member / row counts
     int64_t *moff;              // [n_agg + 1] member offsets
@@ -435,10 +443,13 @@ struct QuotientWs {
     unsigned long long *part;   // [scan_parts(n)]
     int32_t *big;               // [n_agg] coarse rows left to whole workgroups
     uint32_t *big_count;        // [1]
+    uint32_t *gbits;            // [kGiantSlots * giant_words(n_agg)] bitmaps of giant rows
+    uint32_t *gmeta;            // [kGiantMeta]
 };
-hipError_t quotient_graph(const int64_t *row_ptr, const int32_t *col, int64_t n, const int32_t *agg,
-                          int64_t n_agg, int64_t *crow, int32_t *ccol, const QuotientWs &q,
-                          hipStream_t s);
+// nnz: stored entries of the fine graph (no coarse row has more candidates).
+hipError_t quotient_graph(const int64_t *row_ptr, const int32_t *col, int64_t n, int64_t nnz,
+                          const int32_t *agg, int64_t n_agg, int64_t *crow, int32_t *ccol,
+                          const QuotientWs &q, hipStream_t s);
 
 // batch.hip: graph-local numbering of a union's aggregates.
 hipError_t launch_graph_bounds(const int32_t *list, const uint32_t *d_count, const int64_t *voff,

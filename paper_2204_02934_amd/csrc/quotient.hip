@@ -373,7 +373,8 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows(const int64_t *__restric
                                                         const int64_t *__restrict__ crow,
                                                         int32_t *__restrict__ ccol,
                                                         const int32_t *__restrict__ big,
-                                                        const uint32_t *__restrict__ big_count) {
+                                                        const uint32_t *__restrict__ big_count,
+                                                        uint32_t *__restrict__ gmeta) {
     static_assert(kBitWords >= kQCap, "the sort buffer is the bitmap");
     __shared__ uint32_t buf[kBitWords];
     __shared__ unsigned long long red[kWaves];
@@ -381,6 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows(const int64_t *__restric
     __shared__ uint32_t fill_s;
     __shared__ WalkLds walk;
     __shared__ int32_t range_s[2 * kWaves];
+    __shared__ uint32_t giant_s;
     const int tid = (int)threadIdx.x;
     const int64_t nbig = *big_count;
     for (int64_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
@@ -392,6 +394,27 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows(const int64_t *__restric
             cand += (unsigned long long)(row_ptr[v + 1] - row_ptr[v]);
         }
         cand = block_sum(cand, red);
+        if (gmeta && cand > (unsigned long long)kGiantCand) {
+            // a giant row: the count pass claims a bitmap slot for it (the
+            // slot kernels then count and write it); without a free slot it
+            // stays here
+            if (tid == 0) {
+                uint32_t taken = 0;
+                if (!FILL) {
+                    const uint32_t k = atomicAdd(&gmeta[3 * kGiantSlots], 1u);
+                    if (k < (uint32_t)kGiantSlots) {
+                        gmeta[k] = (uint32_t)a;
+                        taken = 1;
+                    }
+                } else {
+                    const uint32_t cnt = min(gmeta[3 * kGiantSlots], (uint32_t)kGiantSlots);
+                    for (uint32_t k = 0; k < cnt; k++) taken |= gmeta[k] == (uint32_t)a ? 1u : 0u;
+                }
+                giant_s = taken;
+            }
+            __syncthreads();
+            if (giant_s) continue;  // uniform; the next block_sum synchronises first
+        }
         uint32_t distinct = 0;
         if (cand <= (unsigned long long)kQCap) {
             // gather the candidate ids (self excluded) into LDS
@@ -500,6 +523,91 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows(const int64_t *__restric
     }
 }
 
+// Giant rows, one bitmap slot each (gmeta: rows [0, S), smallest ids
+// [S, 2S), largest ids [2S, 3S), rows claimed [3S]).  Slot blockIdx.y; the
+// workgroups of a slot share its members in chunks of kBlock and set the bit
+// of every candidate (a plain read first skips bits already set: most
+// candidates of a giant row repeat).
+__global__ __launch_bounds__(kBlock) void k_giant_set(const int64_t *__restrict__ row_ptr,
+                                                      const int32_t *__restrict__ col,
+                                                      const int32_t *__restrict__ agg,
+                                                      const int64_t *__restrict__ moff,
+                                                      const int32_t *__restrict__ members,
+                                                      uint32_t *__restrict__ gbits, int64_t words,
+                                                      uint32_t *__restrict__ gmeta) {
+    __shared__ WalkLds walk;
+    __shared__ int32_t range_s[2 * kWaves];
+    const int slot = (int)blockIdx.y;
+    if ((uint32_t)slot >= min(gmeta[3 * kGiantSlots], (uint32_t)kGiantSlots)) return;
+    const int64_t a = gmeta[slot];
+    const int64_t m0 = moff[a], m1 = moff[a + 1];
+    uint32_t *bits = gbits + (int64_t)slot * words;
+    int32_t tmin = INT32_MAX, tmax = -1;
+    for (int64_t c0 = m0 + (int64_t)blockIdx.x * kBlock; c0 < m1;
+         c0 += (int64_t)gridDim.x * kBlock) {
+        walk_members(row_ptr, col, agg, members, c0, min(c0 + kBlock, m1), walk, [&](int32_t c) {
+            if (c < 0 || (int64_t)c == a) return;
+            tmin = min(tmin, c);
+            tmax = max(tmax, c);
+            const uint32_t bit = 1u << (c & 31);
+            if (!(bits[c >> 5] & bit)) atomicOr(&bits[c >> 5], bit);
+        });
+    }
+    block_minmax(&tmin, &tmax, range_s);
+    if (threadIdx.x == 0 && tmax >= 0) {
+        atomicMin((int32_t *)&gmeta[kGiantSlots + slot], tmin);
+        atomicMax((int32_t *)&gmeta[2 * kGiantSlots + slot], tmax);
+    }
+}
+
+// One workgroup per giant slot: FILL = false: ccnt[a] = the bits set;
+// FILL = true: their ids in increasing order to ccol[crow[a] ...].
+template <bool FILL>
+__global__ __launch_bounds__(kBlock) void k_giant_emit(const uint32_t *__restrict__ gbits,
+                                                       int64_t words,
+                                                       const uint32_t *__restrict__ gmeta,
+                                                       uint32_t *__restrict__ ccnt,
+                                                       const int64_t *__restrict__ crow,
+                                                       int32_t *__restrict__ ccol) {
+    __shared__ uint32_t scan_s[kWaves];
+    const int slot = (int)blockIdx.x;
+    if ((uint32_t)slot >= min(gmeta[3 * kGiantSlots], (uint32_t)kGiantSlots)) return;
+    const int64_t a = gmeta[slot];
+    const int32_t lo = (int32_t)gmeta[kGiantSlots + slot];
+    const int32_t hi = (int32_t)gmeta[2 * kGiantSlots + slot];
+    const uint32_t *bits = gbits + (int64_t)slot * words;
+    uint32_t run = 0;
+    if (hi >= 0) {
+        const int64_t w0 = lo >> 5, w1 = ((int64_t)hi >> 5) + 1;
+        for (int64_t c0 = w0; c0 < w1; c0 += kBlock) {
+            const int64_t wi = c0 + (int64_t)threadIdx.x;
+            const uint32_t word = wi < w1 ? bits[wi] : 0u;
+            uint32_t tot;
+            const uint32_t pos = block_excl((uint32_t)__popc(word), scan_s, &tot);
+            if (FILL) {
+                uint32_t wv = word, k = 0;
+                while (wv) {
+                    const int bit = __ffs(wv) - 1;
+                    wv &= wv - 1;
+                    ccol[crow[a] + run + pos + k] = (int32_t)(wi * 32 + bit);
+                    k++;
+                }
+            }
+            run += tot;
+        }
+    }
+    if (!FILL && threadIdx.x == 0) ccnt[a] = run;
+}
+
+// gmeta before a count pass: no rows, empty ranges.
+__global__ void k_giant_init(uint32_t *__restrict__ gmeta) {
+    const int i = (int)threadIdx.x;
+    if (i < kGiantMeta)
+        gmeta[i] = (i >= kGiantSlots && i < 2 * kGiantSlots) ? (uint32_t)INT32_MAX
+                   : (i >= 2 * kGiantSlots && i < 3 * kGiantSlots) ? 0xFFFFFFFFu
+                   : 0u;
+}
+
 int grid_for(int64_t work, int per_block, int cap) {
     int64_t b = (work + per_block - 1) / per_block;
     if (b < 1) b = 1;
@@ -509,9 +617,9 @@ int grid_for(int64_t work, int per_block, int cap) {
 
 }  // namespace
 
-hipError_t quotient_graph(const int64_t *row_ptr, const int32_t *col, int64_t n, const int32_t *agg,
-                          int64_t n_agg, int64_t *crow, int32_t *ccol, const QuotientWs &q,
-                          hipStream_t s) {
+hipError_t quotient_graph(const int64_t *row_ptr, const int32_t *col, int64_t n, int64_t nnz,
+                          const int32_t *agg, int64_t n_agg, int64_t *crow, int32_t *ccol,
+                          const QuotientWs &q, hipStream_t s) {
     hipError_t e;
     if ((e = launch_fill_u32(q.cnt, 0u, n_agg, s)) != hipSuccess) return e;
     if (n > 0)
@@ -524,7 +632,15 @@ hipError_t quotient_graph(const int64_t *row_ptr, const int32_t *col, int64_t n,
                            n, agg, q.moff, q.cnt, q.members);
     const int wblocks = grid_for(n_agg, kWaves, 8192);
     const int bblocks = 1024;
+    // no coarse row has more candidates than the fine graph has entries
+    const bool giant = nnz > kGiantCand && n_agg > 0;
+    const int64_t words = (int64_t)giant_words(n_agg);
+    uint32_t *gmeta = giant ? q.gmeta : nullptr;
     if ((e = launch_fill_u32(q.big_count, 0u, 1, s)) != hipSuccess) return e;
+    if (giant) {
+        hipLaunchKernelGGL(k_giant_init, dim3(1), dim3(64), 0, s, q.gmeta);
+        if ((e = launch_fill_u32(q.gbits, 0u, kGiantSlots * words, s)) != hipSuccess) return e;
+    }
     if (n_agg > 0) {
         hipLaunchKernelGGL(k_coarse_rows_wave<false>, dim3(wblocks), dim3(kBlock), 0, s, row_ptr,
                            col, agg, n_agg, q.moff, q.members, q.cnt, (const int64_t *)nullptr,
@@ -532,7 +648,14 @@ hipError_t quotient_graph(const int64_t *row_ptr, const int32_t *col, int64_t n,
         hipLaunchKernelGGL(k_coarse_rows<false>, dim3(bblocks), dim3(kBlock), 0, s, row_ptr, col,
                            agg, n_agg, q.moff, q.members, q.cnt, (const int64_t *)nullptr,
                            (int32_t *)nullptr, (const int32_t *)q.big,
-                           (const uint32_t *)q.big_count);
+                           (const uint32_t *)q.big_count, gmeta);
+    }
+    if (giant) {
+        hipLaunchKernelGGL(k_giant_set, dim3(256, kGiantSlots), dim3(kBlock), 0, s, row_ptr, col,
+                           agg, q.moff, q.members, q.gbits, words, q.gmeta);
+        hipLaunchKernelGGL(k_giant_emit<false>, dim3(kGiantSlots), dim3(kBlock), 0, s,
+                           (const uint32_t *)q.gbits, words, (const uint32_t *)q.gmeta, q.cnt,
+                           (const int64_t *)nullptr, (int32_t *)nullptr);
     }
     if ((e = exclusive_scan_u32_i64(q.cnt, n_agg, crow, q.part, s)) != hipSuccess) return e;
     if (n_agg > 0) {
@@ -541,8 +664,12 @@ hipError_t quotient_graph(const int64_t *row_ptr, const int32_t *col, int64_t n,
                            q.big_count);
         hipLaunchKernelGGL(k_coarse_rows<true>, dim3(bblocks), dim3(kBlock), 0, s, row_ptr, col,
                            agg, n_agg, q.moff, q.members, q.cnt, crow, ccol,
-                           (const int32_t *)q.big, (const uint32_t *)q.big_count);
+                           (const int32_t *)q.big, (const uint32_t *)q.big_count, gmeta);
     }
+    if (giant)
+        hipLaunchKernelGGL(k_giant_emit<true>, dim3(kGiantSlots), dim3(kBlock), 0, s,
+                           (const uint32_t *)q.gbits, words, (const uint32_t *)q.gmeta, q.cnt, crow,
+                           ccol);
     return hipGetLastError();
 }
 

@@ -265,6 +265,40 @@ def test_quotient_big_row_candidate_range(ctx, hub_label, leaf_lo, leaf_step):
     assert np.array_equal(ccol.cpu().numpy(), ocol)
 
 
+def _giant_case(kind):
+    # complete graphs of 300 vertices: an aggregate of most of one holds
+    # about 89k candidates, past the 65536 that send a row to a bitmap slot
+    k = 300
+    if kind == "one_giant_few_neighbours":
+        rp, c = graphs.complete(k)
+        agg = np.zeros(k, np.int32)
+        agg[-3:] = [1, 2, 3]
+        return rp, c, agg, 4
+    if kind == "giant_with_no_neighbour":
+        rp, c = graphs.complete(k)
+        return rp, c, np.zeros(k, np.int32), 1
+    # ten giant rows: more than the eight slots, the rest stay on one
+    # workgroup each; labels interleaved so the rows' ids spread out
+    rp, c = graphs.disjoint_union([graphs.complete(k)] * 10)
+    agg = np.empty(10 * k, np.int32)
+    for i in range(10):
+        agg[i * k:(i + 1) * k - 5] = 19 - i
+        agg[(i + 1) * k - 5:(i + 1) * k] = 20 + i * 5 + np.arange(5)
+    return rp, c, agg, 70
+
+
+@pytest.mark.parametrize("kind", ["one_giant_few_neighbours", "giant_with_no_neighbour",
+                                  "more_giants_than_slots"])
+def test_quotient_giant_rows(ctx, kind):
+    rp, c, agg, n_agg = _giant_case(kind)
+    deg = np.diff(rp)
+    assert np.bincount(agg, weights=deg, minlength=n_agg).max() > 65536
+    crow, ccol = ctx.quotient(rp, c, agg, n_agg)
+    orow, ocol = oracle.quotient(rp, c, agg, n_agg)
+    assert np.array_equal(crow.cpu().numpy(), orow)
+    assert np.array_equal(ccol.cpu().numpy(), ocol)
+
+
 def test_quotient_many_long_members(ctx):
     # one aggregate of 1100 vertices whose rows are all long (70 entries):
     # more long members than the workgroup path lists in LDS
