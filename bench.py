@@ -633,6 +633,57 @@ def run_c5(args):
     }
 
 
+def run_launch_cost(args):
+    """Dispatch cost of a small kernel on this GPU: back-to-back direct launches
+    against the same launches replayed from a captured HIP graph (torch's
+    graph capture), GPU time per launch from events, host time per direct
+    launch from the host clock.  Sets the price of the host-driven round loop's
+    launches against what graph replay would save."""
+    import torch
+    dev = torch.device("cuda", 0)
+    x = torch.zeros(256, device=dev)
+    n = 400
+    for _ in range(50):
+        x.add_(1.0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    direct, host = [], []
+    for _ in range(5):
+        e0.record()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            x.add_(1.0)
+        host.append((time.perf_counter() - t0) / n)
+        e1.record()
+        torch.cuda.synchronize()
+        direct.append(e0.elapsed_time(e1) / n)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            x.add_(1.0)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(n):
+            x.add_(1.0)
+    before = float(x[0].item())
+    graph = []
+    for _ in range(5):
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        graph.append(e0.elapsed_time(e1) / n)
+    after = float(x[0].item())
+    assert after == before + 5 * n, (before, after)  # every replayed launch ran
+    return {"metric": "small-kernel dispatch cost", "unit": "us per launch",
+            "kernel": "add_ on 256 floats", "launches": n,
+            "direct_gpu_us": 1e3 * min(direct), "graph_gpu_us": 1e3 * min(graph),
+            "direct_host_us": 1e6 * min(host), "reps": 5}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -656,6 +707,9 @@ def main():
     ap.add_argument("--cgs", action="store_true",
                     help="c1, c2, l100: cluster vs point multicolor Gauss-Seidel (Algorithm 4) "
                          "instead of the step")
+    ap.add_argument("--launch-cost", action="store_true",
+                    help="dispatch cost of a small kernel, direct against HIP graph replay, "
+                         "instead of the step")
     ap.add_argument("--lanes", type=int, default=None,
                     help="c1-c3: lanes per row of the sweeps (-2 = staged, -1 = flat) instead "
                          "of the tuned plan")
@@ -669,6 +723,11 @@ def main():
     if args.gpus != 1:
         raise SystemExit("bench.py measures one GPU: the library has no multi-GPU path "
                          "(--gpus %d requested)" % args.gpus)
+    if args.launch_cost:
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        print(json.dumps(run_launch_cost(args)), flush=True)
+        return
     if args.galerkin:
         import torch
         assert torch.cuda.is_available(), "bench.py needs a GPU"
