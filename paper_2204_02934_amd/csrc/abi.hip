@@ -330,9 +330,23 @@ struct AblRun {
     AblTuples T, M;
 };
 
+// The words a run of rounds starts from: size counters zero (a masked run
+// keeps slot 0, which holds its active count), round table row 0 = n and
+// the long-row flags clear (unmasked runs).  Callers launch them with the
+// round-0 tuples (filled = true) or run_rounds does (filled = false).
+FillSpans round_fills(const mis2_graph *g, const Workspace &ws, bool masked) {
+    FillSpans f;
+    f.add(ws.ctr + (masked ? kCtrSlot : 0), 0u,
+          (int64_t)(masked ? kCtrRing - 1 : kCtrRing) * kCtrSlot);
+    if (!masked) f.add(ws.rt, (uint32_t)g->n, 2);
+    if (!masked) f.add(ws.lflag, 0u, (int64_t)kSplit * kCtrLine);
+    return f;
+}
+
 int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspace &ws,
                const Geometry &gm, bool masked, int phase, hipStream_t s, int32_t *iters_out,
-               std::vector<Launch> *launches, int *long_rows, const AblRun *abl = nullptr) {
+               std::vector<Launch> *launches, int *long_rows, const AblRun *abl = nullptr,
+               bool filled = false) {
     const int lanes = abl ? 1 : lanes_for(ctx, g);
     unsigned long long *degs = ws.degs + (size_t)phase * kTraceCap * kDegStride;
     if (ctx->account) {
@@ -342,14 +356,7 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
     // size counters: every ring slot zero except slot 0 of a masked start,
     // which holds its active count; each Refresh Column clears the slot two
     // rounds ahead.
-    {
-        FillSpans f;
-        f.add(ws.ctr + (masked ? kCtrSlot : 0), 0u,
-              (int64_t)(masked ? kCtrRing - 1 : kCtrRing) * kCtrSlot);
-        if (!masked) f.add(ws.rt, (uint32_t)g->n, 2);
-        if (!masked) f.add(ws.lflag, 0u, (int64_t)kSplit * kCtrLine);
-        HIP_TRY(ctx, launch_fill_spans(f, s));
-    }
+    if (!filled) HIP_TRY(ctx, launch_fill_spans(round_fills(g, ws, masked), s));
     if (ctx->plan.persistent && !abl) {
         if (!masked) *long_rows = 0;
         int rc = run_rounds_persistent(ctx, g, seed, ws, gm, masked, phase, s, iters_out, launches,
@@ -701,8 +708,10 @@ int time_mis2(mis2_ctx *ctx, const mis2_graph *g, const Workspace &ws, hipStream
     int long_rows = 0;
     HIP_TRY(ctx, hipStreamSynchronize(s));
     const auto t0 = std::chrono::steady_clock::now();
-    HIP_TRY(ctx, launch_init_tuples(tparams(ctx, g->n, 0, 0), g->n, ws.T, s));
-    int rc = run_rounds(ctx, g, 0, ws, gm, false, 0, s, &iters, &launches, &long_rows);
+    HIP_TRY(ctx, launch_init_tuples(tparams(ctx, g->n, 0, 0), g->n, ws.T,
+                                    round_fills(g, ws, false), s));
+    int rc = run_rounds(ctx, g, 0, ws, gm, false, 0, s, &iters, &launches, &long_rows, nullptr,
+                        true);
     if (rc) return rc;
     HIP_TRY(ctx, hipStreamSynchronize(s));
     *sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1112,10 +1121,12 @@ int mis2_run(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, uint8_t *status,
     ctx->events_used = 0;
     std::vector<Launch> launches;
     const Geometry gm = geometry(ctx, g->n, lanes_for(ctx, g));
-    HIP_TRY(ctx, launch_init_tuples(tparams(ctx, g->n, seed, 0), g->n, ws.T, s));
+    HIP_TRY(ctx, launch_init_tuples(tparams(ctx, g->n, seed, 0), g->n, ws.T,
+                                    round_fills(g, ws, false), s));
     int32_t iters = 0;
     int long_rows = 0;
-    if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, &iters, &launches, &long_rows)))
+    if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, &iters, &launches, &long_rows,
+                         nullptr, true)))
         return rc;
     // the root count goes straight to the coherent host buffer (no copy)
     HIP_TRY(ctx, launch_status(g->n, ws.T, status, ws.blocksum, ctx->pinned, s));
@@ -1312,8 +1323,10 @@ int phase1_labels(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Works
     int rc;
     const int64_t n = g->n;
     uint32_t *sc = ws.scalars;
-    HIP_TRY(ctx, launch_init_tuples(tparams(ctx, n, seed, 0), n, ws.T, s));
-    if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, iters, launches, long_rows)))
+    HIP_TRY(ctx, launch_init_tuples(tparams(ctx, n, seed, 0), n, ws.T, round_fills(g, ws, false),
+                                    s));
+    if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, iters, launches, long_rows, nullptr,
+                         true)))
         return rc;
     {
         FillSpans f;
@@ -1345,14 +1358,13 @@ int aggregate_basic_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int3
     int32_t it = 0;
     int long_rows = 0;
     if ((rc = phase1_labels(ctx, g, seed, ws, gm, s, roots, &it, &launches, &long_rows))) return rc;
-    HIP_TRY(ctx, launch_copy_i32(ws.label, agg_id, n, s));
     SegIO left_io{};
     left_io.wl_out = ws.wl2[0];
     left_io.cnt_out = ws.cnt2[0];
     left_io.n = n;
     left_io.seg = gm.seg;
     left_io.S = gm.S;
-    HIP_TRY(ctx, launch_list_unlabelled(gm.blocks, n, ws.label, left_io, s));
+    HIP_TRY(ctx, launch_list_unlabelled(gm.blocks, n, ws.label, agg_id, left_io, s));
     SegIO join_io{};
     join_io.wl_in = ws.wl2[0];
     join_io.cnt_in = ws.cnt2[0];
@@ -1406,8 +1418,9 @@ int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
     act_io.seg = gm.seg;
     act_io.S = gm.S;
     HIP_TRY(ctx, launch_init_masked(gm.blocks, tparams(ctx, n, seed, 0), n, ws.label, ws.T, ws.M,
-                                    act_io, s));
-    if ((rc = run_rounds(ctx, g, seed, ws, gm, true, 1, s, &it2, &launches, &long_rows)))
+                                    act_io, round_fills(g, ws, true), s));
+    if ((rc = run_rounds(ctx, g, seed, ws, gm, true, 1, s, &it2, &launches, &long_rows, nullptr,
+                         true)))
         return rc;
     HIP_TRY(ctx, launch_accept_phase2(n, g->row_ptr, g->col, ws.T, ws.label, ws.flag, s));
     HIP_TRY(ctx, compact_u8_nz(ws.flag, n, ws.list, sc + kS_Count2, ws.blocksum, s));
@@ -1419,14 +1432,13 @@ int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
 
     // Phase 3: each unlabelled vertex joins its best-coupled aggregate, all
     // counted on the labels frozen after phase 2.
-    HIP_TRY(ctx, launch_copy_i32(ws.label, agg_id, n, s));
     SegIO left_io{};
     left_io.wl_out = ws.wl2[0];
     left_io.cnt_out = ws.cnt2[0];
     left_io.n = n;
     left_io.seg = gm.seg;
     left_io.S = gm.S;
-    HIP_TRY(ctx, launch_list_unlabelled(gm.blocks, n, ws.label, left_io, s));
+    HIP_TRY(ctx, launch_list_unlabelled(gm.blocks, n, ws.label, agg_id, left_io, s));
     SegIO p3_io{};
     p3_io.wl_in = ws.wl2[0];
     p3_io.cnt_in = ws.cnt2[0];

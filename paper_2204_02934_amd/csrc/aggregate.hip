@@ -163,17 +163,12 @@ __global__ __launch_bounds__(kBlock) void k_accept_phase2(int64_t n,
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_copy_i32(const int32_t *__restrict__ src,
-                                                     int32_t *__restrict__ dst, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock)
-        dst[i] = src[i];
-}
-
 // Each wavefront lists, in order, the vertices of its own range still
-// unlabelled after phase 2, as its segment of io.wl_out.
+// unlabelled after phase 2, as its segment of io.wl_out, and copies the
+// labels of its range to copy_to (the segments cover every vertex).
 __global__ __launch_bounds__(kBlock) void k_list_unlabelled(int64_t n,
                                                             const int32_t *__restrict__ label,
+                                                            int32_t *__restrict__ copy_to,
                                                             SegIO io) {
     const int64_t w = wave_id();
     const int lane = (int)(threadIdx.x & 63u);
@@ -181,7 +176,9 @@ __global__ __launch_bounds__(kBlock) void k_list_unlabelled(int64_t n,
     uint32_t kept = 0;
     for (int64_t v0 = lo; v0 < hi; v0 += 64) {
         const int64_t v = v0 + lane;
-        const bool keep = v < hi && label[v] == -1;
+        const int32_t lv = v < hi ? label[v] : 0;
+        if (v < hi) copy_to[v] = lv;
+        const bool keep = v < hi && lv == -1;
         const uint64_t mask = __ballot(keep);
         if (keep) io.wl_out[lo + kept + (uint32_t)__popcll(mask & lanes_below(lane))] = (int32_t)v;
         kept += (uint32_t)__popcll(mask);
@@ -556,16 +553,9 @@ hipError_t launch_accept_phase2(int64_t n, const int64_t *row_ptr, const int32_t
     return hipGetLastError();
 }
 
-hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, src, dst,
-                       n);
-    return hipGetLastError();
-}
-
-hipError_t launch_list_unlabelled(int blocks, int64_t n, const int32_t *label, const SegIO &io,
-                                  hipStream_t s) {
-    hipLaunchKernelGGL(k_list_unlabelled, dim3(blocks), dim3(kBlock), 0, s, n, label, io);
+hipError_t launch_list_unlabelled(int blocks, int64_t n, const int32_t *label, int32_t *copy_to,
+                                  const SegIO &io, hipStream_t s) {
+    hipLaunchKernelGGL(k_list_unlabelled, dim3(blocks), dim3(kBlock), 0, s, n, label, copy_to, io);
     return hipGetLastError();
 }
 

@@ -384,9 +384,6 @@ hipError_t launch_col_round(int lanes, int blocks, const int64_t *row_ptr, const
 hipError_t launch_dec_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                             uint32_t *T, const uint32_t *M, const RoundsArgs &a, int r,
                             hipStream_t s, hipEvent_t e0, hipEvent_t e1);
-hipError_t launch_init_tuples(const TupleParams &tp, int64_t n, uint32_t *T, hipStream_t s);
-hipError_t launch_init_masked(int blocks, const TupleParams &tp, int64_t n, const int32_t *label,
-                              uint32_t *T, uint32_t *M, const SegIO &io, hipStream_t s);
 int64_t status_blocks(int64_t n);
 hipError_t launch_status(int64_t n, const uint32_t *T, uint8_t *status, uint32_t *blocksum,
                          uint32_t *d_total, hipStream_t s);
@@ -407,6 +404,14 @@ struct FillSpans {
     }
 };
 hipError_t launch_fill_spans(const FillSpans &f, hipStream_t s);
+// Round-0 tuples (T), then the fills f, in one launch.
+hipError_t launch_init_tuples(const TupleParams &tp, int64_t n, uint32_t *T, const FillSpans &f,
+                              hipStream_t s);
+// Induced-subgraph start (T, M, both round-0 worklists into io) and the fills
+// f, in one launch.
+hipError_t launch_init_masked(int blocks, const TupleParams &tp, int64_t n, const int32_t *label,
+                              uint32_t *T, uint32_t *M, const SegIO &io, const FillSpans &f,
+                              hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t count, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, uint8_t value, int64_t count, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long value, int64_t count,
@@ -470,8 +475,9 @@ hipError_t launch_label_roots(int64_t n, const int64_t *row_ptr, const int32_t *
 hipError_t launch_accept_phase2(int64_t n, const int64_t *row_ptr, const int32_t *col,
                                 const uint32_t *T, const int32_t *label, uint8_t *flag,
                                 hipStream_t s);
-hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStream_t s);
-hipError_t launch_list_unlabelled(int blocks, int64_t n, const int32_t *label, const SegIO &io,
+// Lists the vertices still unlabelled (label -1), and copies label to copy_to.
+hipError_t launch_list_unlabelled(int blocks, int64_t n, const int32_t *label, int32_t *copy_to,
+                                  const SegIO &io,
                                   hipStream_t s);
 // io: the unaggregated rows (wl_in / cnt_in) and the list of long rows it
 // leaves (wl_out / cnt_out); io_long: that list as input.

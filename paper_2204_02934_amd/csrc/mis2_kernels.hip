@@ -1820,22 +1820,44 @@ __global__ __launch_bounds__(64) void k_fold_deg(unsigned long long *split,
     fold_deg(split, target, target_w);
 }
 
-// Round-0 tuples for every vertex.
+// The fills of f (p[k][0 .. n[k]) = v[k]), spread over the grid.
+__device__ __forceinline__ void fill_span_words(const FillSpans &f) {
+    int64_t total = 0;
+    for (int k = 0; k < f.k; k++) total += f.n[k];
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * kBlock) {
+        int64_t o = t;
+        int k = 0;  // the span of word t (a fixed trip count: no early exit)
+        for (int q = 0; q + 1 < kFillSpans; q++)
+            if (k == q && q + 1 < f.k && o >= f.n[q]) {
+                o -= f.n[q];
+                k = q + 1;
+            }
+        f.p[k][o] = f.v[k];
+    }
+}
+
+// Round-0 tuples for every vertex, and the round loop's start-up fills
+// (words no other part of this launch touches).
 __global__ __launch_bounds__(kBlock) void k_init_tuples(TupleParams tp, int64_t n,
-                                                        uint32_t *__restrict__ T) {
+                                                        uint32_t *__restrict__ T, FillSpans f) {
     for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * kBlock)
         T[v] = make_tuple(tp, (uint32_t)v);
+    fill_span_words(f);
 }
 
 // Induced-subgraph start: vertices with label -1 take part; the others read
 // as OUT in T (neutral for the minimum) and as absent in M.  Each wavefront
 // also lists the active vertices of its own range, in order, as its segment
-// of both round-0 worklists.
+// of both round-0 worklists.  The launch also does the round loop's
+// start-up fills f (words this launch does not otherwise touch).
 __global__ __launch_bounds__(kBlock) void k_init_masked(TupleParams tp, int64_t n,
                                                         const int32_t *__restrict__ label,
                                                         uint32_t *__restrict__ T,
-                                                        uint32_t *__restrict__ M, SegIO io) {
+                                                        uint32_t *__restrict__ M, SegIO io,
+                                                        FillSpans f) {
+    fill_span_words(f);
     const int64_t w = wave_id();
     const int lane = (int)(threadIdx.x & 63u);
     const int64_t lo = w * io.seg, hi = min(n, lo + io.seg);
@@ -1892,21 +1914,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(V *__restrict__ p, V value, int
 
 // Up to kFillSpans fills of 32-bit words in one launch (one dispatch instead
 // of one per array at the start of a run).
-__global__ __launch_bounds__(kBlock) void k_fill_spans(FillSpans f) {
-    int64_t total = 0;
-    for (int k = 0; k < f.k; k++) total += f.n[k];
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * kBlock) {
-        int64_t o = t;
-        int k = 0;  // the span of word t (a fixed trip count: no early exit)
-        for (int q = 0; q + 1 < kFillSpans; q++)
-            if (k == q && q + 1 < f.k && o >= f.n[q]) {
-                o -= f.n[q];
-                k = q + 1;
-            }
-        f.p[k][o] = f.v[k];
-    }
-}
+__global__ __launch_bounds__(kBlock) void k_fill_spans(FillSpans f) { fill_span_words(f); }
 
 // CSR checks: bit 0 row_ptr[0] != 0, bit 1 decreasing or out-of-range
 // row_ptr, bit 2 row_ptr[n] != nnz, bit 3 column out of range, bit 4
@@ -2234,15 +2242,18 @@ int64_t coop_threshold(int lanes) {
     return lanes >= 64 ? 1024 : (int64_t)32 * std::max(lanes, 1);
 }
 
-hipError_t launch_init_tuples(const TupleParams &tp, int64_t n, uint32_t *T, hipStream_t s) {
+hipError_t launch_init_tuples(const TupleParams &tp, int64_t n, uint32_t *T, const FillSpans &f,
+                              hipStream_t s) {
     hipLaunchKernelGGL(k_init_tuples, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, tp, n,
-                       T);
+                       T, f);
     return hipGetLastError();
 }
 
 hipError_t launch_init_masked(int blocks, const TupleParams &tp, int64_t n, const int32_t *label,
-                              uint32_t *T, uint32_t *M, const SegIO &io, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_masked, dim3(blocks), dim3(kBlock), 0, s, tp, n, label, T, M, io);
+                              uint32_t *T, uint32_t *M, const SegIO &io, const FillSpans &f,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_init_masked, dim3(blocks), dim3(kBlock), 0, s, tp, n, label, T, M, io,
+                       f);
     return hipGetLastError();
 }
 

@@ -103,7 +103,9 @@ def test_tuned_batched_levels_match_oracle(api):
 def test_lookup_only_never_tunes(api):
     # autotune = 2 takes a class's tuned plan when one exists, else the
     # degree rule, and never times candidates itself
-    rp, cc = graphs.cycle(150_001)  # a class (every degree 2) no other test tunes
+    # every degree 2, n in [393216, 524288): a class no other test tunes (the
+    # paths of the tuple-width tests sit at 2^12, 2^17 and 2^20)
+    rp, cc = graphs.cycle(400_001)
     look = api.Context(0, autotune=2)
     _mis2_ok(look, rp, cc, 1, "lookup, new class")
     assert look.last_plan()["source"] == 0 and look.last_tuning() == []
