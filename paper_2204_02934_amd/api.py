@@ -272,7 +272,10 @@ class Context:
         p_cap = max(n + g.nnz, 1)  # P row i holds at most deg(i) + 1 entries
         pcol = torch.empty(p_cap, dtype=torch.int32, device=self.device)
         pval = torch.empty(p_cap, dtype=torch.float64, device=self.device)
-        c_cap = max(min(n_agg * n_agg, 32 * n_agg), 1)
+        # A_c's size is known only after its count pass: start from the size
+        # the last call on a graph of this shape needed, if any
+        caps = self.__dict__.setdefault("_smoothed_caps", {})
+        c_cap = max(min(n_agg * n_agg, 32 * n_agg), caps.get((n, g.nnz, int(n_agg)), 0), 1)
         ccol = torch.empty(c_cap, dtype=torch.int32, device=self.device)
         cval = torch.empty(c_cap, dtype=torch.float64, device=self.device)
         pn, cn, need = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_size_t(0)
@@ -296,6 +299,7 @@ class Context:
             else:
                 break
         _check(self.lib, self.ptr, rc)
+        caps[(n, g.nnz, int(n_agg))] = cn.value
         del keep
         return ((prow, pcol[:pn.value], pval[:pn.value]),
                 (crow, ccol[:cn.value], cval[:cn.value]))

@@ -49,9 +49,10 @@ int grid_of_s(int64_t work, int per_block, int cap) {
 
 struct SetLds {
     int32_t slot[kSetCap];
-    int32_t list[kSetMax];
-    int64_t src_lo[64];   // a batch of 64 source rows: first entry
-    int64_t src_end[65];  // inclusive prefix of their lengths (src_end[0] = 0)
+    int32_t list[kSetMax];  // the columns in the set, in insertion order
+    int64_t src_lo[64];     // a batch of 64 source rows: first entry
+    int64_t src_end[65];    // inclusive prefix of their lengths (src_end[0] = 0)
+    uint32_t n;             // columns inserted (may pass kSetMax: the row is then bad)
 };
 
 __device__ __forceinline__ void wave_sync_s() {
@@ -64,13 +65,18 @@ __device__ __forceinline__ uint32_t set_hash(int32_t c) {
     return ((uint32_t)c * 2654435761u) >> 20;  // 12 bits: kSetCap slots
 }
 
-// Inserts c (c >= 0) into the set; returns 1 if it was new, 0 if present,
-// and 2 if the set is full (the caller flags an error).
+// Inserts c (c >= 0) into the set, appending it to the list when it is new
+// (while the list has room); returns 1 if it was new, 0 if present, and 2 if
+// the set is full (the caller flags an error).
 __device__ __forceinline__ int set_insert(SetLds &sh, int32_t c) {
     uint32_t h = set_hash(c) & (kSetCap - 1);
     for (int probe = 0; probe < kSetCap; probe++) {
         const int32_t old = atomicCAS(&sh.slot[h], kEmpty, c);
-        if (old == kEmpty) return 1;
+        if (old == kEmpty) {
+            const uint32_t k = atomicAdd(&sh.n, 1u);
+            if (k < (uint32_t)kSetMax) sh.list[k] = c;
+            return 1;
+        }
         if (old == c) return 0;
         h = (h + 1) & (kSetCap - 1);
     }
@@ -191,40 +197,45 @@ __global__ __launch_bounds__(kSThreads) void k_sym(SymArgs a) {
     const int lane = (int)(threadIdx.x & 63u);
     const int64_t w0 = (int64_t)blockIdx.x * kSWaves + (threadIdx.x >> 6);
     const int64_t stride = (int64_t)gridDim.x * kSWaves;
+    // the set starts empty and is emptied after each row by clearing the
+    // slots of the listed columns only (the whole table after a bad row)
+    for (int q = lane; q < kSetCap; q += 64) sh.slot[q] = kEmpty;
+    if (lane == 0) sh.n = 0u;
+    wave_sync_s();
     for (int64_t r = w0; r < a.rows; r += stride) {
-        for (int q = lane; q < kSetCap; q += 64) sh.slot[q] = kEmpty;
-        wave_sync_s();
         bool full = false;
-        const uint32_t added = insert_row<K>(sh, a, r, &full);
+        insert_row<K>(sh, a, r, &full);
         wave_sync_s();
-        const uint32_t distinct = group_sum<64>(added);
+        const uint32_t distinct = sh.n;
         const bool bad = __ballot(full) != 0 || distinct > (uint32_t)kSetMax;
-        if (!FILL) {
-            if (lane == 0) {
-                a.count[r] = bad ? 0u : distinct;
-                if (bad) atomicOr(a.err, 1u);
-            }
-            continue;
+        if (!FILL && lane == 0) {
+            a.count[r] = bad ? 0u : distinct;
+            if (bad) atomicOr(a.err, 1u);
         }
-        if (bad) continue;  // the count pass flagged it; the call fails
-        // list the set's columns, then place each at its rank
-        uint32_t n_list = 0;
-        for (int q0 = 0; q0 < kSetCap; q0 += 64) {
-            const int32_t c = sh.slot[q0 + lane];
-            const bool has = c != kEmpty;
-            const uint64_t m = __ballot(has);
-            if (has) sh.list[n_list + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = c;
-            n_list += (uint32_t)__popcll(m);
+        if (FILL && !bad) {
+            // place each column at its rank among the row's columns
+            int32_t *out = a.out_col + a.out_ptr[r];
+            for (uint32_t x0 = 0; x0 < distinct; x0 += 64) {
+                const uint32_t x = x0 + lane;
+                const int32_t c = x < distinct ? sh.list[x] : 0;
+                uint32_t rank = 0;
+                for (uint32_t y = 0; y < distinct; y++) rank += sh.list[y] < c;
+                if (x < distinct) out[rank] = c;
+            }
         }
         wave_sync_s();
-        int32_t *out = a.out_col + a.out_ptr[r];
-        for (uint32_t x0 = 0; x0 < n_list; x0 += 64) {
-            const uint32_t x = x0 + lane;
-            const int32_t c = x < n_list ? sh.list[x] : 0;
-            uint32_t rank = 0;
-            for (uint32_t y = 0; y < n_list; y++) rank += sh.list[y] < c;
-            if (x < n_list) out[rank] = c;
+        if (bad) {
+            for (int q = lane; q < kSetCap; q += 64) sh.slot[q] = kEmpty;
+        } else {
+            for (uint32_t x = lane; x < distinct; x += 64) {
+                const int32_t c = sh.list[x];
+                uint32_t h = set_hash(c) & (kSetCap - 1);
+                while (sh.slot[h] != c) h = (h + 1) & (kSetCap - 1);
+                sh.slot[h] = kEmpty;
+            }
         }
+        wave_sync_s();
+        if (lane == 0) sh.n = 0u;
         wave_sync_s();
     }
 }
