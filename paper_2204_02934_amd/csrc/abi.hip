@@ -1328,14 +1328,15 @@ int phase1_labels(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Works
     if ((rc = run_rounds(ctx, g, seed, ws, gm, false, 0, s, iters, launches, long_rows, nullptr,
                          true)))
         return rc;
+    // the roots, numbered by increasing id: the fills and per-tile root
+    // counts in one launch, then the ordered scatter
     {
         FillSpans f;
         f.add(sc, 0u, kScalars);
         f.add((uint32_t *)ws.label, 0xFFFFFFFFu, n);  // -1
-        HIP_TRY(ctx, launch_fill_spans(f, s));
+        HIP_TRY(ctx, count_in_with_fills(ws.T, n, f, roots, ws.blocksum, s));
     }
-    if (roots) HIP_TRY(ctx, launch_fill_u8(roots, 0, n, s));
-    HIP_TRY(ctx, compact_u32_eq(ws.T, kIn, n, ws.list, sc + kS_Count1, ws.blocksum, s));
+    HIP_TRY(ctx, scatter_counted_u32_eq(ws.T, kIn, n, ws.list, sc + kS_Count1, ws.blocksum, s));
     HIP_TRY(ctx, launch_label_roots(n, g->row_ptr, g->col, ws.list, sc + kS_Count1, nullptr, false,
                                     ws.label, ws.aggsize, roots, 1, s));
     return MIS2_OK;
@@ -1417,13 +1418,19 @@ int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
     act_io.n = n;
     act_io.seg = gm.seg;
     act_io.S = gm.S;
-    HIP_TRY(ctx, launch_init_masked(gm.blocks, tparams(ctx, n, seed, 0), n, ws.label, ws.T, ws.M,
-                                    act_io, round_fills(g, ws, true), s));
+    {
+        // with the round loop's fills, the tile counts that phase-2 acceptance adds to
+        FillSpans f = round_fills(g, ws, true);
+        f.add(ws.blocksum, 0u, compact_blocks(n));
+        HIP_TRY(ctx, launch_init_masked(gm.blocks, tparams(ctx, n, seed, 0), n, ws.label, ws.T,
+                                        ws.M, act_io, f, s));
+    }
     if ((rc = run_rounds(ctx, g, seed, ws, gm, true, 1, s, &it2, &launches, &long_rows, nullptr,
                          true)))
         return rc;
-    HIP_TRY(ctx, launch_accept_phase2(n, g->row_ptr, g->col, ws.T, ws.label, ws.flag, s));
-    HIP_TRY(ctx, compact_u8_nz(ws.flag, n, ws.list, sc + kS_Count2, ws.blocksum, s));
+    HIP_TRY(ctx, launch_accept_phase2(n, g->row_ptr, g->col, ws.T, ws.label, ws.flag,
+                                      ws.blocksum, s));
+    HIP_TRY(ctx, scatter_counted_u8_nz(ws.flag, n, ws.list, sc + kS_Count2, ws.blocksum, s));
     HIP_TRY(ctx, launch_label_roots(n, g->row_ptr, g->col, ws.list, sc + kS_Count2,
                                     sc + kS_Count1, true, ws.label, ws.aggsize, roots, 2, s));
     if (P2)

@@ -14,6 +14,8 @@ namespace {
 constexpr int kItems = 8;                  // elements per thread per tile
 constexpr int kTile = kBlock * kItems;     // 2048 elements per tile
 constexpr int kWaves = kBlock / 64;
+static_assert(kTile == kCompactTile, "one tile size for every compaction");
+constexpr int64_t kOnePassTiles = 4096;    // one-launch scatter up to this many tiles
 
 struct PredU32Eq {
     const uint32_t *a;
@@ -115,6 +117,88 @@ __global__ __launch_bounds__(kBlock) void k_tile_scatter(P pred, int64_t n,
     }
 }
 
+// k_tile_count with fills beside it: zero_u8 over the tile (when not null)
+// and the spans of f over the grid.
+template <class P>
+__global__ __launch_bounds__(kBlock) void k_tile_count_fill(P pred, int64_t n,
+                                                            uint32_t *__restrict__ blocksum,
+                                                            FillSpans f, uint8_t *zero_u8) {
+    __shared__ uint32_t part[kWaves];
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; j++) {
+        const int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
+        if (i < n && pred(i)) c++;
+        if (zero_u8 && i < n) zero_u8[i] = 0;
+    }
+    for (int off = 32; off > 0; off >>= 1) c += (uint32_t)__shfl_xor((int)c, off, 64);
+    if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kWaves; w++) t += part[w];
+        blocksum[blockIdx.x] = t;
+    }
+    fill_span_words(f);
+}
+
+// k_tile_scatter with its own scan: workgroup b sums the counts of tiles
+// 0 .. b-1 itself (blocksum holds every tile's count, as k_tile_count wrote
+// it), and the last workgroup writes the total to *d_count.
+template <class P>
+__global__ __launch_bounds__(kBlock) void k_scan_scatter(P pred, int64_t n,
+                                                         const uint32_t *__restrict__ blocksum,
+                                                         int32_t *__restrict__ out,
+                                                         uint32_t *__restrict__ d_count) {
+    __shared__ uint32_t wcount[kItems][kWaves];
+    __shared__ uint32_t red[kWaves];
+    const int lane = (int)(threadIdx.x & 63u), wave = (int)(threadIdx.x >> 6);
+    uint32_t pre = 0;
+    for (int64_t t = threadIdx.x; t < (int64_t)blockIdx.x; t += kBlock) pre += blocksum[t];
+    for (int off = 32; off > 0; off >>= 1) pre += (uint32_t)__shfl_xor((int)pre, off, 64);
+    if (lane == 0) red[wave] = pre;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    uint64_t masks[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; j++) {
+        const int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
+        const bool p = i < n && pred(i);
+        masks[j] = __ballot(p);
+        if (lane == 0) wcount[j][wave] = (uint32_t)__popcll(masks[j]);
+    }
+    __syncthreads();
+    uint32_t run = 0;
+    for (int w = 0; w < kWaves; w++) run += red[w];
+#pragma unroll
+    for (int j = 0; j < kItems; j++) {
+        uint32_t before = run;
+        for (int w = 0; w < wave; w++) before += wcount[j][w];
+        const int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
+        if ((masks[j] >> lane) & 1ull)
+            out[before + (uint32_t)__popcll(masks[j] & lanes_below(lane))] = (int32_t)i;
+        for (int w = 0; w < kWaves; w++) run += wcount[j][w];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *d_count = run;
+}
+
+template <class P>
+hipError_t scatter_counted(P pred, int64_t n, int32_t *out, uint32_t *d_count,
+                           uint32_t *blocksum, hipStream_t s) {
+    const int64_t nb = compact_blocks(n);
+    if (nb > 0 && nb <= kOnePassTiles) {
+        hipLaunchKernelGGL(k_scan_scatter<P>, dim3((unsigned)nb), dim3(kBlock), 0, s, pred, n,
+                           (const uint32_t *)blocksum, out, d_count);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kBlock), 0, s, blocksum, nb, d_count);
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_tile_scatter<P>, dim3((unsigned)nb), dim3(kBlock), 0, s, pred, n,
+                           (const uint32_t *)blocksum, out);
+    }
+    return hipGetLastError();
+}
+
 template <class P>
 hipError_t compact(P pred, int64_t n, int32_t *out, uint32_t *d_count, uint32_t *blocksum,
                    hipStream_t s) {
@@ -138,6 +222,25 @@ int64_t compact_blocks(int64_t n) { return n <= 0 ? 0 : (n + kTile - 1) / kTile;
 hipError_t compact_u32_eq(const uint32_t *a, uint32_t value, int64_t n, int32_t *out,
                           uint32_t *d_count, uint32_t *blocksum, hipStream_t s) {
     return compact(PredU32Eq{a, value}, n, out, d_count, blocksum, s);
+}
+
+hipError_t count_in_with_fills(const uint32_t *T, int64_t n, const FillSpans &f, uint8_t *zero_u8,
+                               uint32_t *blocksum, hipStream_t s) {
+    const int64_t nb = compact_blocks(n);
+    if (nb <= 0) return launch_fill_spans(f, s);
+    hipLaunchKernelGGL(k_tile_count_fill<PredU32Eq>, dim3((unsigned)nb), dim3(kBlock), 0, s,
+                       PredU32Eq{T, kIn}, n, blocksum, f, zero_u8);
+    return hipGetLastError();
+}
+
+hipError_t scatter_counted_u32_eq(const uint32_t *a, uint32_t value, int64_t n, int32_t *out,
+                                  uint32_t *d_count, uint32_t *blocksum, hipStream_t s) {
+    return scatter_counted(PredU32Eq{a, value}, n, out, d_count, blocksum, s);
+}
+
+hipError_t scatter_counted_u8_nz(const uint8_t *a8, int64_t n, int32_t *out, uint32_t *d_count,
+                                 uint32_t *blocksum, hipStream_t s) {
+    return scatter_counted(PredU8Nz{a8}, n, out, d_count, blocksum, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -404,6 +404,23 @@ struct FillSpans {
     }
 };
 hipError_t launch_fill_spans(const FillSpans &f, hipStream_t s);
+// The fills of f (p[k][0 .. n[k]) = v[k]), spread over the launch's grid of
+// kBlock-thread workgroups; for kernels that carry fills beside their work.
+__device__ __forceinline__ void fill_span_words(const FillSpans &f) {
+    int64_t total = 0;
+    for (int k = 0; k < f.k; k++) total += f.n[k];
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * kBlock) {
+        int64_t o = t;
+        int k = 0;  // the span of word t (a fixed trip count: no early exit)
+        for (int q = 0; q + 1 < kFillSpans; q++)
+            if (k == q && q + 1 < f.k && o >= f.n[q]) {
+                o -= f.n[q];
+                k = q + 1;
+            }
+        f.p[k][o] = f.v[k];
+    }
+}
 // Round-0 tuples (T), then the fills f, in one launch.
 hipError_t launch_init_tuples(const TupleParams &tp, int64_t n, uint32_t *T, const FillSpans &f,
                               hipStream_t s);
@@ -421,7 +438,20 @@ hipError_t launch_validate(int64_t n, int64_t nnz, const int64_t *row_ptr, const
 
 // compact.hip: out = [v : pred(v)] in increasing v, size -> *d_count.
 // blocksum needs compact_blocks(n) + 1 entries.
+constexpr int kCompactTile = 2048;  // vertices per compaction tile
 int64_t compact_blocks(int64_t n);
+// Phase 1's start: the fills f, zero_u8[0 .. n) = 0 (when not null), and the
+// per-tile counts of T == IN into blocksum, in one launch.
+hipError_t count_in_with_fills(const uint32_t *T, int64_t n, const FillSpans &f, uint8_t *zero_u8,
+                               uint32_t *blocksum, hipStream_t s);
+// The rest of an ordered compaction whose per-tile counts are in blocksum:
+// out = the indices i with a[i] == value (or a8[i] != 0), in increasing
+// order, *d_count = how many.  One launch up to kOnePassTiles tiles (each
+// workgroup sums the counts of the tiles before it), else scan and scatter.
+hipError_t scatter_counted_u32_eq(const uint32_t *a, uint32_t value, int64_t n, int32_t *out,
+                                  uint32_t *d_count, uint32_t *blocksum, hipStream_t s);
+hipError_t scatter_counted_u8_nz(const uint8_t *a8, int64_t n, int32_t *out, uint32_t *d_count,
+                                 uint32_t *blocksum, hipStream_t s);
 hipError_t compact_u32_eq(const uint32_t *a, uint32_t value, int64_t n, int32_t *out,
                           uint32_t *d_count, uint32_t *blocksum, hipStream_t s);
 hipError_t compact_u8_nz(const uint8_t *a, int64_t n, int32_t *out, uint32_t *d_count,
@@ -472,9 +502,11 @@ hipError_t launch_label_roots(int64_t n, const int64_t *row_ptr, const int32_t *
                               const int32_t *roots, const uint32_t *d_count,
                               const uint32_t *d_base, bool only_unlabelled, int32_t *label,
                               int32_t *aggsize, uint8_t *root_mark, uint8_t mark, hipStream_t s);
+// flag[v] for the phase-2 roots that become aggregates; each set flag is
+// added to tile_count[v / kCompactTile] (zero beforehand).
 hipError_t launch_accept_phase2(int64_t n, const int64_t *row_ptr, const int32_t *col,
                                 const uint32_t *T, const int32_t *label, uint8_t *flag,
-                                hipStream_t s);
+                                uint32_t *tile_count, hipStream_t s);
 // Lists the vertices still unlabelled (label -1), and copies label to copy_to.
 hipError_t launch_list_unlabelled(int blocks, int64_t n, const int32_t *label, int32_t *copy_to,
                                   const SegIO &io,

@@ -1820,23 +1820,6 @@ __global__ __launch_bounds__(64) void k_fold_deg(unsigned long long *split,
     fold_deg(split, target, target_w);
 }
 
-// The fills of f (p[k][0 .. n[k]) = v[k]), spread over the grid.
-__device__ __forceinline__ void fill_span_words(const FillSpans &f) {
-    int64_t total = 0;
-    for (int k = 0; k < f.k; k++) total += f.n[k];
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * kBlock) {
-        int64_t o = t;
-        int k = 0;  // the span of word t (a fixed trip count: no early exit)
-        for (int q = 0; q + 1 < kFillSpans; q++)
-            if (k == q && q + 1 < f.k && o >= f.n[q]) {
-                o -= f.n[q];
-                k = q + 1;
-            }
-        f.p[k][o] = f.v[k];
-    }
-}
-
 // Round-0 tuples for every vertex, and the round loop's start-up fills
 // (words no other part of this launch touches).
 __global__ __launch_bounds__(kBlock) void k_init_tuples(TupleParams tp, int64_t n,
