@@ -12,8 +12,7 @@
 // every coarse row is a sorted set).  A coarse row whose members have at most
 // kWCap stored entries in all is handled by one wavefront: it puts the
 // aggregate ids of the members' neighbours into an LDS hash set and sorts the
-// distinct ones (member rows longer than kWShort are read by the whole
-// wavefront).  Larger rows are listed and handled by a whole workgroup each,
+// distinct ones (the members' entries are dealt out evenly over its lanes).  Larger rows are listed and handled by a whole workgroup each,
 // whose threads share the members' entries evenly: the same gather and sort
 // for up to kQCap candidates, else a sweep over the coarse id space in
 // windows of 32*kBitWords ids with an LDS bitmap, which emits ids in
@@ -21,6 +20,7 @@
 // row's candidates span.  Both kernels run twice: once to count each row,
 // once (after a prefix sum) to write it.
 #include "internal.h"
+#include "lanes.h"
 
 namespace mis2 {
 
@@ -32,7 +32,6 @@ constexpr int64_t kQWindow = 32 * (int64_t)kBitWords;  // coarse ids per bitmap 
 constexpr int kWaves = kBlock / 64;
 constexpr int kWCap = 1024;                  // candidates of a row handled by one wavefront
 constexpr int kWEdges = 8;                   // entries per lane loaded together
-constexpr int kWShort = 32;                  // member rows read by one lane (wavefront path)
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -62,6 +61,8 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows_wave(
     __shared__ uint32_t tabs[kWaves][kWCap];
     __shared__ uint32_t lists[kWaves][kWCap];
     __shared__ uint32_t nums[kWaves];
+    __shared__ uint32_t woffs[kWaves][65];
+    __shared__ int64_t wsts[kWaves][64];
     const int wv = (int)(threadIdx.x >> 6);
     uint32_t *tab = tabs[wv];
     uint32_t *list = lists[wv];
@@ -83,9 +84,10 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows_wave(
             if (!FILL && lane == 0) big[atomicAdd(big_count, 1u)] = (int32_t)a;
             continue;
         }
-        // gather into the set: each lane takes one member at a time and
-        // loads kWEdges of its entries together; rows longer than kWShort
-        // are walked by the whole wavefront instead, one after the other
+        // gather into the set: the members go 64 at a time; their entries
+        // are numbered by a wave scan of the row lengths and dealt out
+        // evenly, kWEdges per lane loaded together, each lane finding its
+        // row by binary search over the offsets
         auto put = [&](int32_t cv) {
             if (cv < 0 || (int64_t)cv == a) return;
             const uint32_t key = (uint32_t)cv;
@@ -100,49 +102,43 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows_wave(
                 h = (h + 1) & (kWCap - 1);
             }
         };
-        for (int64_t i0 = m0; i0 < m1; i0 += 64) {
-            const int64_t i = i0 + lane;
-            int64_t s = 0, e = 0;
+        uint32_t *woff = woffs[wv];
+        int64_t *wst = wsts[wv];
+        for (int64_t c0 = m0; c0 < m1; c0 += 64) {
+            const int64_t i = c0 + lane;
+            int64_t rs = 0;
+            uint32_t len = 0;  // a row of this path has at most kWCap entries
             if (i < m1) {
                 const int32_t v = members[i];
-                s = row_ptr[v];
-                e = row_ptr[v + 1];
+                rs = row_ptr[v];
+                len = (uint32_t)(row_ptr[v + 1] - rs);
             }
-            const bool lng = e - s > kWShort;
-            const int64_t len = lng ? 0 : e - s;
-            int64_t lmax = len;
-            for (int off = 32; off > 0; off >>= 1) lmax = max(lmax, __shfl_xor(lmax, off, 64));
-            for (int64_t c0 = 0; c0 < lmax; c0 += kWEdges) {
+            const uint32_t incl = wave_incl_scan(len);
+            const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+            woff[lane + 1] = incl;
+            wst[lane] = rs;
+            if (lane == 0) woff[0] = 0u;
+            wave_sync();
+            for (uint32_t q0 = (uint32_t)lane; q0 < tot; q0 += 64u * kWEdges) {
                 int32_t x[kWEdges];
 #pragma unroll
-                for (int k = 0; k < kWEdges; k++) x[k] = col[c0 + k < len ? s + c0 + k : 0];
+                for (int k = 0; k < kWEdges; k++) {
+                    uint32_t q = q0 + 64u * (uint32_t)k;
+                    if (q >= tot) q = tot - 1;  // a valid entry; its result is not used
+                    int r = 0;  // the last row with woff[r] <= q (it is not empty)
+#pragma unroll
+                    for (int st = 32; st > 0; st >>= 1)
+                        if (woff[r + st] <= q) r += st;
+                    x[k] = col[wst[r] + (int64_t)(q - woff[r])];
+                }
                 int32_t c[kWEdges];
 #pragma unroll
                 for (int k = 0; k < kWEdges; k++) c[k] = agg[x[k]];
 #pragma unroll
                 for (int k = 0; k < kWEdges; k++)
-                    if (c0 + k < len) put(c[k]);
+                    if (q0 + 64u * (uint32_t)k < tot) put(c[k]);
             }
-            unsigned long long longs = __ballot(lng);
-            while (longs) {
-                const int src = __ffsll(longs) - 1;
-                longs &= longs - 1;
-                const int64_t rs = __shfl(s, src, 64), re = __shfl(e, src, 64);
-                for (int64_t j0 = rs + lane; j0 < re; j0 += 64 * kWEdges) {
-                    int32_t x[kWEdges];
-#pragma unroll
-                    for (int k = 0; k < kWEdges; k++) {
-                        const int64_t j = j0 + 64 * k;
-                        x[k] = col[j < re ? j : rs];
-                    }
-                    int32_t c[kWEdges];
-#pragma unroll
-                    for (int k = 0; k < kWEdges; k++) c[k] = agg[x[k]];
-#pragma unroll
-                    for (int k = 0; k < kWEdges; k++)
-                        if (j0 + 64 * k < re) put(c[k]);
-                }
-            }
+            wave_sync();  // the offsets are rewritten by the next chunk
         }
         wave_sync();
         const uint32_t m = nums[wv];
