@@ -323,10 +323,11 @@ def kernel_sources_digest():
 
 def measured_traffic(workload, kernel, launches_per_step, plan):
     """HBM bytes per launch of `kernel` from profiles/traffic_<workload>.json
-    (rocprofv3 FETCH_SIZE and WRITE_SIZE runs of this bench with an explicit
-    launch plan, scaled by the same counters on a plain device copy of known
-    size; bytes per step over the launches per step counted here), or None
-    when there is no such measurement for the current sources and plan."""
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE runs of this bench, one pair per
+    explicit launch plan, scaled by the same counters on a plain device copy
+    of known size; bytes per step over the launches per step counted here),
+    or None when there is no such measurement for the current sources and
+    the plan this run used."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
     if not os.path.exists(path):
         return None
@@ -334,13 +335,15 @@ def measured_traffic(workload, kernel, launches_per_step, plan):
         t = json.load(fh)
     if t.get("sources_sha256") != kernel_sources_digest():
         return None
-    tp = t.get("plan", {})
-    if (tp.get("lanes"), tp.get("tail")) != (plan.get("lanes"), plan.get("tail")):
-        return None
-    k = t.get("kernels", {}).get(kernel)
-    if k is None or "hbm_bytes_per_step" not in k:
-        return None
-    return k["hbm_bytes_per_step"] / launches_per_step
+    for m in t.get("measurements", []):
+        tp = m.get("plan", {})
+        if (tp.get("lanes"), tp.get("tail")) != (plan.get("lanes"), plan.get("tail")):
+            continue
+        k = m.get("kernels", {}).get(kernel)
+        if k is None or "hbm_bytes_per_step" not in k:
+            return None
+        return k["hbm_bytes_per_step"] / launches_per_step
+    return None
 
 
 def sweep_bytes(rec, identity, written=0):

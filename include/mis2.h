@@ -87,7 +87,8 @@ extern "C" {
                                      vertices runs with the fastest of a few launch plans for
                                      its class (half octave of n and degree histogram), timed
                                      once per class and device on its first sight in the
-                                     process; 2: the plan of a class tuned before in the
+                                     process (candidates in a fixed order; a later one wins
+                                     only when at least 1% faster); 2: the plan of a class tuned before in the
                                      process, never a tuning run (a class not seen yet takes
                                      the degree rule); 0: the fixed degree rule.  Plans never
                                      change results. */

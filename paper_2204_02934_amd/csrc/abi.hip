@@ -634,6 +634,7 @@ int collect_sweeps(mis2_ctx *ctx, const std::vector<Launch> &launches, const Wor
 // kept for the class, process-wide, so every context on the device uses it.
 // ---------------------------------------------------------------------------
 constexpr int64_t kTuneMinN = 16384;   // smaller graphs keep the degree rule
+constexpr double kTuneMargin = 0.01;    // a candidate replaces the best when 1% faster
 constexpr size_t kSeenCap = 32;        // graphs remembered per context
 
 struct TuneEntry {
@@ -759,7 +760,9 @@ int tune(mis2_ctx *ctx, const mis2_graph *g, const Workspace &ws, hipStream_t s,
         const Geometry gm = geometry(ctx, g->n, lanes_for(ctx, g));
         ctx->tuning.push_back({p.lanes == kStagedLanes ? MIS2_LANES_STAGED : p.lanes, gm.blocks,
                                p.tail > 0 ? 1 : 0, (float)(t * 1e3)});
-        if (ctx->tuning.size() == 1 || t < best_t) {
+        // a later candidate must be clearly faster: timing noise alone does
+        // not flip the choice between plans that run alike
+        if (ctx->tuning.size() == 1 || t < best_t * (1.0 - kTuneMargin)) {
             best_t = t;
             *best = p;
         }
