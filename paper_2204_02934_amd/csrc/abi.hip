@@ -869,6 +869,7 @@ size_t workspace_bytes(int64_t n, int op) {
         b += align_up(4 * un) + align_up(4);            // large coarse rows and their count
         b += align_up(4 * (size_t)kGiantSlots * giant_words(n));  // giant rows' bitmaps
         b += align_up(4 * (size_t)kGiantMeta);
+        b += align_up(un);                              // row classes
     }
     return b;
 }
@@ -915,6 +916,7 @@ bool carve(void *base, size_t bytes, int64_t n, int op, Workspace *ws) {
         ws->q.big_count = (uint32_t *)take(4);
         ws->q.gbits = (uint32_t *)take(4 * (size_t)kGiantSlots * giant_words(n));
         ws->q.gmeta = (uint32_t *)take(4 * (size_t)kGiantMeta);
+        ws->q.cls = (uint8_t *)take(un);
     }
     return true;
 }
@@ -1487,8 +1489,8 @@ int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
 int quotient_impl(mis2_ctx *ctx, const mis2_graph *g, const int32_t *agg, int64_t n_agg,
                   int64_t *crow, int32_t *ccol, int64_t *nnz_out, const Workspace &ws,
                   hipStream_t s) {
-    QuotientWs q{ws.q.cnt, ws.q.moff, ws.q.members, ws.q.part, ws.q.big, ws.q.big_count,
-                 ws.q.gbits, ws.q.gmeta};
+    QuotientWs q{ws.q.cnt,   ws.q.moff,  ws.q.members, ws.q.part, ws.q.big,
+                 ws.q.big_count, ws.q.gbits, ws.q.gmeta, ws.q.cls};
     HIP_TRY(ctx, quotient_graph(g->row_ptr, g->col, g->n, g->nnz, agg, n_agg, crow, ccol, q, s));
     int64_t nnz = 0;
     HIP_TRY(ctx, hipMemcpyAsync(&ctx->pinned[0], crow + n_agg, sizeof(int64_t),
@@ -1617,8 +1619,8 @@ int batch_level(mis2_ctx *ctx, const mis2_graph &cur, uint64_t seed, int64_t sto
     bl->n_next = n_next;
     bl->nnz_next = 0;
     if (n_next > 0) {
-        QuotientWs q{ws.q.cnt,  ws.q.moff,     ws.q.members, ws.q.part,
-                     ws.q.big,  ws.q.big_count, ws.q.gbits,   ws.q.gmeta};
+        QuotientWs q{ws.q.cnt,       ws.q.moff,  ws.q.members, ws.q.part, ws.q.big,
+                     ws.q.big_count, ws.q.gbits, ws.q.gmeta,   ws.q.cls};
         HIP_TRY(ctx, quotient_graph(cur.row_ptr, cur.col, cur.n, cur.nnz, ar.map, n_next, crow_next,
                                     ccol_next, q, s));
         HIP_TRY(ctx, hipMemcpyAsync(&ctx->pinned[0], crow_next + n_next, sizeof(int64_t),

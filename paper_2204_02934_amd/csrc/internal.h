@@ -148,6 +148,7 @@ struct Workspace {
         uint32_t *big_count = nullptr;
         uint32_t *gbits = nullptr;   // [kGiantSlots * giant_words(n)]
         uint32_t *gmeta = nullptr;   // [kGiantMeta]
+        uint8_t *cls = nullptr;      // [n] which pass handles each coarse row
     } q;
 };
 
@@ -480,6 +481,7 @@ struct QuotientWs {
     uint32_t *big_count;        // [1]
     uint32_t *gbits;            // [kGiantSlots * giant_words(n_agg)] bitmaps of giant rows
     uint32_t *gmeta;            // [kGiantMeta]
+    uint8_t *cls;               // [n_agg] the pass of each coarse row (small, middle, large)
 };
 // nnz: stored entries of the fine graph (no coarse row has more candidates).
 hipError_t quotient_graph(const int64_t *row_ptr, const int32_t *col, int64_t n, int64_t nnz,

@@ -9,16 +9,18 @@
 // for graphs that stop coarsening) and edges to it are dropped.
 //
 // Member lists are built by a counting sort (their order does not matter:
-// every coarse row is a sorted set).  A coarse row whose members have at most
-// kWCap stored entries in all is handled by one wavefront: it puts the
-// aggregate ids of the members' neighbours into an LDS hash set and sorts the
-// distinct ones (the members' entries are dealt out evenly over its lanes).  Larger rows are listed and handled by a whole workgroup each,
-// whose threads share the members' entries evenly: the same gather and sort
-// for up to kQCap candidates, else a sweep over the coarse id space in
-// windows of 32*kBitWords ids with an LDS bitmap, which emits ids in
-// increasing order and, after the first window, visits only the range the
-// row's candidates span.  Both kernels run twice: once to count each row,
-// once (after a prefix sum) to write it.
+// every coarse row is a sorted set).  Rows go to one of four paths by their
+// candidate count (the members' stored entries): up to kWSmall and up to
+// kWCap, one wavefront each (two passes; the first, with a small LDS hash
+// set, keeps many rows in flight and marks the rows it leaves to the
+// second); up to kGiantCand, one workgroup each; beyond, a bitmap slot that
+// the whole grid fills.  A wavefront puts the aggregate ids of the members'
+// neighbours into its LDS hash set and ranks the distinct ones; a workgroup
+// sorts them in LDS or sweeps windows of 32*kBitWords coarse ids with an LDS
+// bitmap, which emits ids in increasing order and, after the first window,
+// visits only the range the row's candidates span.  Every path deals the
+// members' entries out evenly over its lanes.  Each kernel runs twice: once
+// to count each row, once (after a prefix sum) to write it.
 #include "internal.h"
 #include "lanes.h"
 
@@ -31,6 +33,7 @@ constexpr int kBitWords = 12288;             // LDS bitmap words (48 KiB)
 constexpr int64_t kQWindow = 32 * (int64_t)kBitWords;  // coarse ids per bitmap window
 constexpr int kWaves = kBlock / 64;
 constexpr int kWCap = 1024;                  // candidates of a row handled by one wavefront
+constexpr int kWSmall = 128;                 // rows a wavefront takes in the first pass
 constexpr int kWEdges = 8;                   // entries per lane loaded together
 
 __device__ __forceinline__ void wave_sync() {
@@ -39,27 +42,40 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Coarse rows with at most kWCap candidates, one wavefront each (the others
-// are appended to big[] by the counting pass).  The candidates go into a
-// per-wavefront LDS hash set (open addressing, kWCap slots, so it never
-// fills); each id that enters it is also appended to a list.  The distinct
-// ids are then sorted -- in registers with a 64-lane bitonic network when
-// there are at most 64, in LDS otherwise -- and the set is emptied by
-// clearing just their slots.  FILL = false: ccnt[a]; FILL = true:
-// ccol[crow[a] ...].
-__device__ __forceinline__ uint32_t qhash(uint32_t c) { return (c * 2654435761u) >> 22; }
+// Coarse rows with at most CAP candidates, one wavefront each.  kRowsMark:
+// every coarse row; the count pass marks in cls[a] whether row a has more
+// than CAP candidates (1) or not (0), and the fill pass skips the marked
+// rows.  kRowsMarked: the rows marked 1; the count pass marks 2 on those with
+// more than CAP candidates and lists them in next[] for the workgroup kernel.
+// kRowsList: every coarse row, listing those with more than CAP in next[].  The candidates go into a per-wavefront LDS hash set
+// (open addressing, CAP slots, so it never fills); each id that enters it is
+// also appended to a list.  The distinct ids are then ranked -- by counting,
+// each against all the others, when there are at most 64, else by a bitonic
+// sort in LDS -- and the set is emptied by clearing just their slots.  A
+// small CAP keeps the LDS per wavefront small, so that many rows are in
+// flight at once: the rows of a fine mesh's aggregates are a few dozen
+// candidates each.  FILL = false: ccnt[a]; FILL = true: ccol[crow[a] ...].
+template <int CAP>
+__device__ __forceinline__ uint32_t qhash(uint32_t c) {
+    static_assert((CAP & (CAP - 1)) == 0 && CAP >= 64 && CAP <= 65536, "CAP: a power of two");
+    constexpr int bits = __builtin_ctz(CAP);
+    return (c * 2654435761u) >> (32 - bits);
+}
 
-template <bool FILL>
+// MODE: which rows a pass takes and what it does with the rows of more
+// than CAP candidates.
+enum { kRowsMark = 0, kRowsMarked = 1, kRowsList = 2 };
+
+template <bool FILL, int CAP, int MODE>
 __global__ __launch_bounds__(kBlock) void k_coarse_rows_wave(
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ agg, int64_t n_agg, const int64_t *__restrict__ moff,
     const int32_t *__restrict__ members, uint32_t *__restrict__ ccnt,
-    const int64_t *__restrict__ crow, int32_t *__restrict__ ccol, int32_t *__restrict__ big,
-    uint32_t *__restrict__ big_count) {
-    static_assert(kWCap == 1024, "qhash yields 10 bits");
+    const int64_t *__restrict__ crow, int32_t *__restrict__ ccol, uint8_t *__restrict__ cls,
+    int32_t *__restrict__ next, uint32_t *__restrict__ next_count) {
     constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-    __shared__ uint32_t tabs[kWaves][kWCap];
-    __shared__ uint32_t lists[kWaves][kWCap];
+    __shared__ uint32_t tabs[kWaves][CAP];
+    __shared__ uint32_t lists[kWaves][CAP];
     __shared__ uint32_t nums[kWaves];
     __shared__ uint32_t woffs[kWaves][65];
     __shared__ int64_t wsts[kWaves][64];
@@ -68,22 +84,29 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows_wave(
     uint32_t *list = lists[wv];
     const int lane = (int)(threadIdx.x & 63u);
     const int64_t nw = (int64_t)gridDim.x * kWaves;
-    for (int i = lane; i < kWCap; i += 64) tab[i] = kEmpty;
+    for (int i = lane; i < CAP; i += 64) tab[i] = kEmpty;
     if (lane == 0) nums[wv] = 0u;
     wave_sync();
-    for (int64_t a = (int64_t)blockIdx.x * kWaves + wv; a < n_agg; a += nw) {
+    auto row = [&](const int64_t a) {
         const int64_t m0 = moff[a], m1 = moff[a + 1];
-        // candidates: stored entries of all members
-        unsigned long long cand = 0;
+        // candidates: stored entries of all members (each lane's part
+        // clamped: only "more than CAP" matters)
+        uint32_t cand = 0;
         for (int64_t i = m0 + lane; i < m1; i += 64) {
             const int32_t v = members[i];
-            cand += (unsigned long long)(row_ptr[v + 1] - row_ptr[v]);
+            const int64_t d = row_ptr[v + 1] - row_ptr[v];
+            cand = (uint32_t)min((int64_t)cand + d, (int64_t)1 << 24);
         }
-        for (int off = 32; off > 0; off >>= 1) cand += __shfl_xor(cand, off, 64);
-        if (cand > (unsigned long long)kWCap) {
-            if (!FILL && lane == 0) big[atomicAdd(big_count, 1u)] = (int32_t)a;
-            continue;
+        cand = group_sum<64>(cand);
+        if (!FILL && lane == 0) {
+            if (MODE == kRowsMark) {
+                cls[a] = cand > (uint32_t)CAP ? 1 : 0;
+            } else if (cand > (uint32_t)CAP) {
+                if (MODE == kRowsMarked) cls[a] = 2;
+                next[atomicAdd(next_count, 1u)] = (int32_t)a;
+            }
         }
+        if (cand > (uint32_t)CAP) return;
         // gather into the set: the members go 64 at a time; their entries
         // are numbered by a wave scan of the row lengths and dealt out
         // evenly, kWEdges per lane loaded together, each lane finding its
@@ -91,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows_wave(
         auto put = [&](int32_t cv) {
             if (cv < 0 || (int64_t)cv == a) return;
             const uint32_t key = (uint32_t)cv;
-            uint32_t h = qhash(key);
+            uint32_t h = qhash<CAP>(key);
             for (;;) {  // the set has room for every candidate, so this ends
                 const uint32_t prev = atomicCAS(&tab[h], kEmpty, key);
                 if (prev == kEmpty) {
@@ -99,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows_wave(
                     break;
                 }
                 if (prev == key) break;
-                h = (h + 1) & (kWCap - 1);
+                h = (h + 1) & (CAP - 1);
             }
         };
         uint32_t *woff = woffs[wv];
@@ -107,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows_wave(
         for (int64_t c0 = m0; c0 < m1; c0 += 64) {
             const int64_t i = c0 + lane;
             int64_t rs = 0;
-            uint32_t len = 0;  // a row of this path has at most kWCap entries
+            uint32_t len = 0;  // a row of this path has at most CAP entries
             if (i < m1) {
                 const int32_t v = members[i];
                 rs = row_ptr[v];
@@ -142,54 +165,75 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rows_wave(
         }
         wave_sync();
         const uint32_t m = nums[wv];
-        // empty the set again: clear the slot of each distinct id (its probe
-        // run holds it exactly once; other lanes' clears only leave holes)
-        for (uint32_t i = lane; i < m; i += 64) {
-            const uint32_t key = list[i];
-            uint32_t h = qhash(key);
-            while (tab[h] != key) h = (h + 1) & (kWCap - 1);
-            tab[h] = kEmpty;
-        }
         if (m <= 64) {
-            // one id per lane; bitonic network over lane order with shuffles
-            uint32_t x = (uint32_t)lane < m ? list[lane] : kEmpty;
-            for (int k = 2; k <= 64; k <<= 1) {
-                for (int j = k >> 1; j > 0; j >>= 1) {
-                    const uint32_t y = (uint32_t)__shfl_xor((int)x, j, 64);
-                    const bool lower = (lane & j) == 0;
-                    const bool up = (lane & k) == 0;
-                    x = (lower == up) ? min(x, y) : max(x, y);
-                }
+            // rank each id by counting the smaller ones (ids are distinct)
+            if (FILL && (uint32_t)lane < m) {
+                const uint32_t x = list[lane];
+                uint32_t rank = 0;
+                for (uint32_t y = 0; y < m; y++) rank += list[y] < x ? 1u : 0u;
+                ccol[crow[a] + rank] = (int32_t)x;
             }
-            if (FILL && (uint32_t)lane < m) ccol[crow[a] + lane] = (int32_t)x;
-        } else {
+        } else if (FILL) {
+            // bitonic sort of a copy in the set's table, then the table
+            // is cleared whole
             uint32_t P = 1;
             while (P < m) P <<= 1;
-            for (uint32_t i = m + lane; i < P; i += 64) list[i] = kEmpty;
+            for (uint32_t i = lane; i < P; i += 64) tab[i] = i < m ? list[i] : kEmpty;
             wave_sync();
             for (uint32_t k = 2; k <= P; k <<= 1) {
-                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
                     for (uint32_t i = lane; i < P; i += 64) {
-                        const uint32_t ixj = i ^ j;
+                        const uint32_t ixj = i ^ jj;
                         if (ixj > i) {
-                            const uint32_t x = list[i], y = list[ixj];
+                            const uint32_t x = tab[i], y = tab[ixj];
                             const bool up = (i & k) == 0;
                             if ((x > y) == up) {
-                                list[i] = y;
-                                list[ixj] = x;
+                                tab[i] = y;
+                                tab[ixj] = x;
                             }
                         }
                     }
                     wave_sync();
                 }
             }
-            if (FILL)
-                for (uint32_t i = lane; i < m; i += 64) ccol[crow[a] + i] = (int32_t)list[i];
+            for (uint32_t i = lane; i < m; i += 64) ccol[crow[a] + i] = (int32_t)tab[i];
+        }
+        wave_sync();
+        // empty the set again
+        if (FILL && m > 64) {
+            for (int i = lane; i < CAP; i += 64) tab[i] = kEmpty;
+        } else {
+            // clear the slot of each distinct id (its probe run holds it
+            // exactly once; other lanes' clears only leave holes)
+            for (uint32_t i = lane; i < m; i += 64) {
+                const uint32_t key = list[i];
+                uint32_t h = qhash<CAP>(key);
+                while (tab[h] != key) h = (h + 1) & (CAP - 1);
+                tab[h] = kEmpty;
+            }
         }
         if (!FILL && lane == 0) ccnt[a] = m;
         wave_sync();
         if (lane == 0) nums[wv] = 0u;
         wave_sync();
+    };
+    const int64_t w0 = (int64_t)blockIdx.x * kWaves + wv;
+    if (MODE != kRowsMarked) {
+        for (int64_t a = w0; a < n_agg; a += nw) row(a);
+    } else {
+        // the wavefront's rows w0, w0 + nw, ...: 64 marks read at once (2:
+        // marked by this kernel's count pass), so the marked rows stay
+        // spread over all wavefronts
+        for (int64_t j0 = 0; w0 + j0 * nw < n_agg; j0 += 64) {
+            const int64_t v = w0 + (j0 + lane) * nw;
+            const bool mine = v < n_agg && cls[v] >= 1;
+            uint64_t mask = __ballot(mine);
+            while (mask) {
+                const int r = __ffsll((unsigned long long)mask) - 1;
+                mask &= mask - 1;
+                row(w0 + (j0 + r) * nw);
+            }
+        }
     }
 }
 
@@ -637,10 +681,25 @@ hipError_t quotient_graph(const int64_t *row_ptr, const int32_t *col, int64_t n,
         hipLaunchKernelGGL(k_giant_init, dim3(1), dim3(64), 0, s, q.gmeta);
         if ((e = launch_fill_u32(q.gbits, 0u, kGiantSlots * words, s)) != hipSuccess) return e;
     }
+    // two wavefront passes (rows of up to kWSmall candidates first) when
+    // rows are small on average and many; else one
+    const bool two = n_agg >= 16384 && nnz <= (int64_t)kWSmall * 2 * n_agg;
     if (n_agg > 0) {
-        hipLaunchKernelGGL(k_coarse_rows_wave<false>, dim3(wblocks), dim3(kBlock), 0, s, row_ptr,
-                           col, agg, n_agg, q.moff, q.members, q.cnt, (const int64_t *)nullptr,
-                           (int32_t *)nullptr, q.big, q.big_count);
+        if (two) {
+            hipLaunchKernelGGL((k_coarse_rows_wave<false, kWSmall, kRowsMark>), dim3(wblocks),
+                               dim3(kBlock), 0, s, row_ptr, col, agg, n_agg, q.moff, q.members,
+                               q.cnt, (const int64_t *)nullptr, (int32_t *)nullptr, q.cls, q.big,
+                               q.big_count);
+            hipLaunchKernelGGL((k_coarse_rows_wave<false, kWCap, kRowsMarked>), dim3(wblocks),
+                               dim3(kBlock), 0, s, row_ptr, col, agg, n_agg, q.moff, q.members,
+                               q.cnt, (const int64_t *)nullptr, (int32_t *)nullptr, q.cls, q.big,
+                               q.big_count);
+        } else {
+            hipLaunchKernelGGL((k_coarse_rows_wave<false, kWCap, kRowsList>), dim3(wblocks),
+                               dim3(kBlock), 0, s, row_ptr, col, agg, n_agg, q.moff, q.members,
+                               q.cnt, (const int64_t *)nullptr, (int32_t *)nullptr, q.cls, q.big,
+                               q.big_count);
+        }
         hipLaunchKernelGGL(k_coarse_rows<false>, dim3(bblocks), dim3(kBlock), 0, s, row_ptr, col,
                            agg, n_agg, q.moff, q.members, q.cnt, (const int64_t *)nullptr,
                            (int32_t *)nullptr, (const int32_t *)q.big,
@@ -655,9 +714,18 @@ hipError_t quotient_graph(const int64_t *row_ptr, const int32_t *col, int64_t n,
     }
     if ((e = exclusive_scan_u32_i64(q.cnt, n_agg, crow, q.part, s)) != hipSuccess) return e;
     if (n_agg > 0) {
-        hipLaunchKernelGGL(k_coarse_rows_wave<true>, dim3(wblocks), dim3(kBlock), 0, s, row_ptr,
-                           col, agg, n_agg, q.moff, q.members, q.cnt, crow, ccol, q.big,
-                           q.big_count);
+        if (two) {
+            hipLaunchKernelGGL((k_coarse_rows_wave<true, kWSmall, kRowsMark>), dim3(wblocks),
+                               dim3(kBlock), 0, s, row_ptr, col, agg, n_agg, q.moff, q.members,
+                               q.cnt, crow, ccol, q.cls, q.big, q.big_count);
+            hipLaunchKernelGGL((k_coarse_rows_wave<true, kWCap, kRowsMarked>), dim3(wblocks),
+                               dim3(kBlock), 0, s, row_ptr, col, agg, n_agg, q.moff, q.members,
+                               q.cnt, crow, ccol, q.cls, q.big, q.big_count);
+        } else {
+            hipLaunchKernelGGL((k_coarse_rows_wave<true, kWCap, kRowsList>), dim3(wblocks),
+                               dim3(kBlock), 0, s, row_ptr, col, agg, n_agg, q.moff, q.members,
+                               q.cnt, crow, ccol, q.cls, q.big, q.big_count);
+        }
         hipLaunchKernelGGL(k_coarse_rows<true>, dim3(bblocks), dim3(kBlock), 0, s, row_ptr, col,
                            agg, n_agg, q.moff, q.members, q.cnt, crow, ccol,
                            (const int32_t *)q.big, (const uint32_t *)q.big_count, gmeta);
