@@ -296,6 +296,7 @@ RoundsArgs round_args(const mis2_ctx *ctx, const mis2_graph *g, uint64_t seed,
     a.rt_host = nullptr;  // set by run_rounds for launched rounds
     a.ctr = ws.ctr;
     a.alive_host = ctx->alive_host;
+    a.epoch = 0;  // run_rounds gives each run its own
     a.degs = ctx->account ? degs : nullptr;
     a.dsplit = ctx->account ? ws.dsplit : nullptr;
     a.bar = ws.bar;
@@ -378,6 +379,10 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
     int longs = masked ? (*long_rows > 0 ? 1 : 0) : -1;
     const int cfrom = masked ? 0 : kCompactFrom;
     int cstart = -1;  // first compacting round
+    // a new epoch: words still arriving from the late rounds of the run
+    // before this one carry the old one and are ignored
+    ctx->epoch = ctx->epoch % kEpochMax + 1;
+    a.epoch = ctx->epoch;
     __atomic_store_n(ctx->alive_host + 1, ~0ull, __ATOMIC_RELEASE);
     __atomic_store_n(ctx->alive_host, ~0ull, __ATOMIC_RELEASE);
     ctx->tail_used[phase] = 0;
@@ -388,10 +393,10 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
     int last_seen = -2;
     for (;;) {
         const unsigned long long v = __atomic_load_n(ctx->alive_host, __ATOMIC_ACQUIRE);
-        int seen = -1;  // round of the latest Refresh Column that has started
+        int seen = -1;  // round of the latest Refresh Column of this run that has started
         uint32_t live = 1;
-        if (v != ~0ull) {
-            seen = (int)(v >> 32);
+        if (v != ~0ull && (uint32_t)(v >> 48) == a.epoch) {
+            seen = (int)((v >> 32) & 0xFFFFu);
             live = (uint32_t)v & ~kLongRowsBit;
             if (longs < 0 && seen >= 1) longs = ((uint32_t)v & kLongRowsBit) ? 1 : 0;
         }
@@ -418,7 +423,8 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
                 !(a.colc && longs < 0)) {
                 // worklist2 at round `seen` (word 1, written before word 0)
                 const unsigned long long w2 = __atomic_load_n(ctx->alive_host + 1, __ATOMIC_ACQUIRE);
-                if (w2 != ~0ull && (int)(w2 >> 32) == seen && (uint32_t)w2 < (uint32_t)kTailCap) {
+                if (w2 != ~0ull && (uint32_t)(w2 >> 48) == a.epoch &&
+                    (int)((w2 >> 32) & 0xFFFFu) == seen && (uint32_t)w2 < (uint32_t)kTailCap) {
                     int cs = -1;  // first compacting round
                     if (a.colc && longs > 0) cs = cstart >= 0 ? cstart : std::max(round, cfrom);
                     Launch lt{3, phase, round, lanes, nullptr, nullptr};
@@ -1423,18 +1429,15 @@ int aggregate_impl(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, int32_t *a
     act_io.n = n;
     act_io.seg = gm.seg;
     act_io.S = gm.S;
-    {
-        // with the round loop's fills, the tile counts that phase-2 acceptance adds to
-        FillSpans f = round_fills(g, ws, true);
-        f.add(ws.blocksum, 0u, compact_blocks(n));
-        HIP_TRY(ctx, launch_init_masked(gm.blocks, tparams(ctx, n, seed, 0), n, ws.label, ws.T,
-                                        ws.M, act_io, f, s));
-    }
+    HIP_TRY(ctx, launch_init_masked(gm.blocks, tparams(ctx, n, seed, 0), n, ws.label, ws.T, ws.M,
+                                    act_io, round_fills(g, ws, true), s));
     if ((rc = run_rounds(ctx, g, seed, ws, gm, true, 1, s, &it2, &launches, &long_rows, nullptr,
                          true)))
         return rc;
-    HIP_TRY(ctx, launch_accept_phase2(n, g->row_ptr, g->col, ws.T, ws.label, ws.flag,
-                                      ws.blocksum, s));
+    // the accepted roots, numbered by increasing id: per-tile counts (plain
+    // stores), then the ordered scatter
+    HIP_TRY(ctx, launch_accept_phase2(n, g->row_ptr, g->col, ws.T, ws.label, ws.flag, s));
+    HIP_TRY(ctx, count_u8_nz(ws.flag, n, ws.blocksum, s));
     HIP_TRY(ctx, scatter_counted_u8_nz(ws.flag, n, ws.list, sc + kS_Count2, ws.blocksum, s));
     HIP_TRY(ctx, launch_label_roots(n, g->row_ptr, g->col, ws.list, sc + kS_Count2,
                                     sc + kS_Count1, true, ws.label, ws.aggsize, roots, 2, s));

@@ -121,25 +121,46 @@ __global__ __launch_bounds__(kBlock) void k_label_roots(const int64_t *__restric
 // flag[v] = 1 iff v is a root of the phase-2 MIS-2 (T_v = IN in the masked
 // run) with at least two neighbours that are unlabelled after phase 1.  Each
 // wavefront scans 64 vertices at a time and counts the candidates' rows
-// cooperatively, one row at a time.  The flags set are added to the count
-// of their compaction tile (tile_count, zero beforehand; 64 vertices never
-// straddle a tile).
+// cooperatively, one row at a time.
+constexpr int64_t kAcceptLane = 32;  // rows a lane counts alone in k_accept_phase2
+
 __global__ __launch_bounds__(kBlock) void k_accept_phase2(int64_t n,
                                                           const int64_t *__restrict__ row_ptr,
                                                           const int32_t *__restrict__ col,
                                                           const uint32_t *__restrict__ T,
                                                           const int32_t *__restrict__ label,
-                                                          uint8_t *__restrict__ flag,
-                                                          uint32_t *__restrict__ tile_count) {
-    static_assert(kCompactTile % 64 == 0, "a 64-vertex chunk lies in one tile");
+                                                          uint8_t *__restrict__ flag) {
     const int lane = (int)(threadIdx.x & 63u);
     const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
     for (int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * 64; base < n;
          base += waves * 64) {
         const int64_t v = base + lane;
         const bool cand = v < n && label[v] == -1 && T[v] == kIn;
-        uint64_t mask = __ballot(cand);
+        // a candidate with a row of up to kAcceptLane entries counts its own
+        // row, kCoopLoads entries loaded together; longer rows go to the
+        // whole wavefront one at a time
+        int64_t rs = 0, re = 0;
+        if (cand) {
+            rs = row_ptr[v];
+            re = row_ptr[v + 1];
+        }
+        const bool own = cand && re - rs <= kAcceptLane;
         uint8_t f = 0;
+        if (own) {
+            int cnt = 0;
+            for (int64_t b = rs; b < re; b += kCoopLoads) {
+                int32_t x[kCoopLoads];
+#pragma unroll
+                for (int k = 0; k < kCoopLoads; k++) x[k] = col[b + k < re ? b + k : rs];
+                int32_t lb[kCoopLoads];
+#pragma unroll
+                for (int k = 0; k < kCoopLoads; k++) lb[k] = label[x[k]];
+#pragma unroll
+                for (int k = 0; k < kCoopLoads; k++) cnt += (b + k < re) & (lb[k] == -1);
+            }
+            f = cnt >= 2;
+        }
+        uint64_t mask = __ballot(cand && !own);
         while (mask) {
             const int t = __ffsll((unsigned long long)mask) - 1;
             mask &= mask - 1;
@@ -164,8 +185,6 @@ __global__ __launch_bounds__(kBlock) void k_accept_phase2(int64_t n,
             if (lane == t) f = cnt >= 2;
         }
         if (v < n) flag[v] = f;
-        const uint32_t set = (uint32_t)__popcll(__ballot(v < n && f != 0));
-        if (lane == 0 && set) atomicAdd(&tile_count[base / kCompactTile], set);
     }
 }
 
@@ -553,9 +572,9 @@ hipError_t launch_label_roots(int64_t n, const int64_t *row_ptr, const int32_t *
 
 hipError_t launch_accept_phase2(int64_t n, const int64_t *row_ptr, const int32_t *col,
                                 const uint32_t *T, const int32_t *label, uint8_t *flag,
-                                uint32_t *tile_count, hipStream_t s) {
+                                hipStream_t s) {
     hipLaunchKernelGGL(k_accept_phase2, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, n,
-                       row_ptr, col, T, label, flag, tile_count);
+                       row_ptr, col, T, label, flag);
     return hipGetLastError();
 }
 

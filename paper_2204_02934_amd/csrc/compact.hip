@@ -243,6 +243,14 @@ hipError_t scatter_counted_u8_nz(const uint8_t *a8, int64_t n, int32_t *out, uin
     return scatter_counted(PredU8Nz{a8}, n, out, d_count, blocksum, s);
 }
 
+hipError_t count_u8_nz(const uint8_t *a8, int64_t n, uint32_t *blocksum, hipStream_t s) {
+    const int64_t nb = compact_blocks(n);
+    if (nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_count<PredU8Nz>, dim3((unsigned)nb), dim3(kBlock), 0, s,
+                       PredU8Nz{a8}, n, blocksum);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Exclusive prefix sum of u32 counts into int64 offsets: out[i] = sum of
 // in[0..i), out[n] = total.  Tile sums, a one-workgroup scan of the tile sums

@@ -234,7 +234,10 @@ constexpr int kBarWords = kMaxBlocks + 64;
 // Also the arguments of the launched round kernels (k_col_round /
 // k_dec_round, which take the round number as a second argument).
 // alive_host (may be null): host-pinned word where workgroup 0 of every
-// Refresh Column stores (round << 32) | |worklist1| at the start of its round.
+// Refresh Column stores (epoch << 48) | (round << 32) | |worklist1| at the
+// start of its round (and word 1 the same with |worklist2|).  The epoch tells
+// the host's poll of one run from the late rounds of the run before it,
+// which may still be starting when the next run resets the words.
 struct RoundsArgs {
     BatchInfo batch;
     int32_t *wl1[2];
@@ -245,6 +248,7 @@ struct RoundsArgs {
     uint32_t *rt_host;   // host-pinned copy of the round table rows (may be null)
     uint32_t *ctr;
     unsigned long long *alive_host;
+    uint32_t epoch;            // 1 .. kEpochMax, a new one per run of rounds
     unsigned long long *degs;  // [kTraceCap][kDegStride] or null
     unsigned long long *dsplit;  // [2][kSplit][16] partial row-length sums, or null
     uint32_t *bar;
@@ -281,6 +285,12 @@ struct AblTuples {
 // Bit of the host-reported |worklist1| word that says round 0 met rows long
 // enough for the cooperative pass (|worklist1| < 2^31 always).
 constexpr uint32_t kLongRowsBit = 0x80000000u;
+constexpr uint32_t kEpochMax = 0x7FFFu;  // epochs in the top 16 bits of a host word
+// A host word: epoch, round and a 32-bit value.
+__host__ __device__ inline unsigned long long host_word(uint32_t epoch, int round, uint32_t value) {
+    return ((unsigned long long)epoch << 48) | ((unsigned long long)((uint32_t)round & 0xFFFFu) << 32) |
+           value;
+}
 
 // mis2_kernels.hip
 // Degree histogram of the plan tuner: kHistBlocks partial rows of kHistWords
@@ -453,6 +463,8 @@ hipError_t scatter_counted_u32_eq(const uint32_t *a, uint32_t value, int64_t n, 
                                   uint32_t *d_count, uint32_t *blocksum, hipStream_t s);
 hipError_t scatter_counted_u8_nz(const uint8_t *a8, int64_t n, int32_t *out, uint32_t *d_count,
                                  uint32_t *blocksum, hipStream_t s);
+// Per-tile counts of a8[i] != 0 into blocksum (plain stores, every tile).
+hipError_t count_u8_nz(const uint8_t *a8, int64_t n, uint32_t *blocksum, hipStream_t s);
 hipError_t compact_u32_eq(const uint32_t *a, uint32_t value, int64_t n, int32_t *out,
                           uint32_t *d_count, uint32_t *blocksum, hipStream_t s);
 hipError_t compact_u8_nz(const uint8_t *a, int64_t n, int32_t *out, uint32_t *d_count,
@@ -504,11 +516,10 @@ hipError_t launch_label_roots(int64_t n, const int64_t *row_ptr, const int32_t *
                               const int32_t *roots, const uint32_t *d_count,
                               const uint32_t *d_base, bool only_unlabelled, int32_t *label,
                               int32_t *aggsize, uint8_t *root_mark, uint8_t mark, hipStream_t s);
-// flag[v] for the phase-2 roots that become aggregates; each set flag is
-// added to tile_count[v / kCompactTile] (zero beforehand).
+// flag[v] = 1 for the phase-2 roots that become aggregates, else 0.
 hipError_t launch_accept_phase2(int64_t n, const int64_t *row_ptr, const int32_t *col,
                                 const uint32_t *T, const int32_t *label, uint8_t *flag,
-                                uint32_t *tile_count, hipStream_t s);
+                                hipStream_t s);
 // Lists the vertices still unlabelled (label -1), and copies label to copy_to.
 hipError_t launch_list_unlabelled(int blocks, int64_t n, const int32_t *label, int32_t *copy_to,
                                   const SegIO &io,
@@ -573,6 +584,7 @@ struct mis2_ctx {
     size_t ws_bytes = 0;
     uint32_t *pinned = nullptr;  // host-pinned scalars for read-back
     uint32_t *pinned_ctr = nullptr;  // host-pinned [2][kCtrList]: worklist1 counters per chunk
+    uint32_t epoch = 0;                        // of the last run of rounds (host words)
     unsigned long long *alive_host = nullptr;  // host-pinned [8]: (round << 32) | |worklist1|,
                                                // (round << 32) | |worklist2|, tail row counts
     uint32_t *pinned_rt = nullptr;  // host-pinned [2][kTraceCap + 2][kRoundStride] round tables

@@ -1271,11 +1271,10 @@ __device__ __forceinline__ void round_start(const RoundsArgs &a, int r) {
             if (a.alive_host) {
                 // word 1: (round, |worklist2|), stored before word 0 so that a
                 // host that reads word 0 of round r finds word 1 of round r
-                __hip_atomic_store(a.alive_host + 1, ((unsigned long long)(uint32_t)r << 32) | c2,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(a.alive_host + 1, host_word(a.epoch, r, c2), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
                 __hip_atomic_store(a.alive_host,
-                                   ((unsigned long long)(uint32_t)r << 32) | c1 |
-                                       (longs ? kLongRowsBit : 0u),
+                                   host_word(a.epoch, r, c1 | (longs ? kLongRowsBit : 0u)),
                                    __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
             }
         }

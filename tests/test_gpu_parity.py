@@ -155,6 +155,22 @@ def test_aggregate_lane_plans(api, lanes):
             _check_agg(c, rp, cc, 3, name)
 
 
+def test_runs_ignore_late_rounds_of_the_run_before(api):
+    # rounds queued past the end of one run can still be starting when the
+    # next run of the same call (phase 2 after phase 1) begins; the next run
+    # must not take their "worklist empty" word for its own.  Slow rounds
+    # (64 lanes per row on 7 workgroups) and a short host path between the
+    # phases made that happen on some runs; every repetition must match.
+    rp, cc = dict(SMALL)["grid27_ragged"]
+    d = oracle.aggregate(rp, cc, 3, detail=True)
+    for rep in range(12):
+        c = api.Context(0, lanes=64, blocks=7)
+        agg, na, roots = c.aggregate(rp, cc, 3, want_roots=True)
+        assert na == d["n_agg"], (rep, na, d["n_agg"])
+        assert np.array_equal(roots.cpu().numpy() == 2, d["roots"] == 2), rep
+        assert np.array_equal(agg.cpu().numpy(), d["agg"]), rep
+
+
 def test_persistent_and_launched_rounds_agree(api):
     rp, cc = dict(SMALL)["grid27_30"]
     a = api.Context(0, persistent=True)
