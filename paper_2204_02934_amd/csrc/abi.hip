@@ -1774,6 +1774,7 @@ int mis2_galerkin(mis2_ctx *ctx, const mis2_graph *g, const double *val, const d
 // arrays sized by the entries of P and AP, known only as the call proceeds.
 namespace {
 struct SmoothedWs {
+    uint8_t *cls;  // [max(n, n_agg)] rows left to the large-set structure pass
     uint32_t *size, *cnt, *cursor, *flag;
     unsigned long long *part;
     int64_t *apptr, *moff;
@@ -1783,7 +1784,8 @@ struct SmoothedWs {
 
 size_t smoothed_bytes(int64_t n, int64_t n_agg, int64_t p_nnz, int64_t ap_nnz) {
     const size_t un = (size_t)std::max<int64_t>(n, 1), ua = (size_t)std::max<int64_t>(n_agg, 1);
-    size_t b = align_up(4 * ua) + align_up(4 * std::max(un, ua)) + align_up(4 * ua) + align_up(64);
+    size_t b = align_up(std::max(un, ua));
+    b += align_up(4 * ua) + align_up(4 * std::max(un, ua)) + align_up(4 * ua) + align_up(64);
     b += align_up(8 * (size_t)scan_parts(std::max<int64_t>(n, n_agg)));
     b += align_up(8 * (un + 1)) + align_up(8 * (ua + 1));
     b += 2 * align_up(4 * (size_t)std::max<int64_t>(p_nnz, 1));
@@ -1801,6 +1803,7 @@ SmoothedWs carve_smoothed(void *base, int64_t n, int64_t n_agg, int64_t p_nnz, i
         return (void *)r;
     };
     SmoothedWs w;
+    w.cls = (uint8_t *)take(std::max(un, ua));
     w.size = (uint32_t *)take(4 * ua);
     w.cnt = (uint32_t *)take(4 * std::max(un, ua));
     w.cursor = (uint32_t *)take(4 * ua);
@@ -1869,7 +1872,7 @@ int mis2_smoothed(mis2_ctx *ctx, const mis2_graph *g, const double *val, const d
     // P: structure (count, offsets, columns), then values
     HIP_TRY(ctx, launch_smoothed_sym(0, false, n, g->row_ptr, g->col, agg, nullptr, nullptr,
                                      nullptr, nullptr, nullptr, w.cnt, nullptr, nullptr,
-                                     w.flag + 1, s));
+                                     w.flag + 1, w.cls, s));
     HIP_TRY(ctx, exclusive_scan_u32_i64(w.cnt, n, prow, w.part, s));
     int64_t pn = 0;
     if ((rc = read_total(ctx, prow + n, w.flag + 1, &pn, &flags, s))) return rc;
@@ -1886,13 +1889,13 @@ int mis2_smoothed(mis2_ctx *ctx, const mis2_graph *g, const double *val, const d
     }
     w = carve_smoothed(ctx->ws, n, n_agg, pn, 0);
     HIP_TRY(ctx, launch_smoothed_sym(0, true, n, g->row_ptr, g->col, agg, nullptr, nullptr,
-                                     nullptr, nullptr, nullptr, nullptr, prow, pcol, w.flag + 1,
+                                     nullptr, nullptr, nullptr, nullptr, prow, pcol, w.flag + 1, w.cls,
                                      s));
     HIP_TRY(ctx, launch_p_values(n, pn, g->row_ptr, g->col, val, diag, agg, w.size, omega, prow,
                                  pcol, pval, w.prow_of, s));
     // AP = A P
     HIP_TRY(ctx, launch_smoothed_sym(1, false, n, g->row_ptr, g->col, agg, prow, pcol, nullptr,
-                                     nullptr, nullptr, w.cnt, nullptr, nullptr, w.flag + 1, s));
+                                     nullptr, nullptr, w.cnt, nullptr, nullptr, w.flag + 1, w.cls, s));
     HIP_TRY(ctx, exclusive_scan_u32_i64(w.cnt, n, w.apptr, w.part, s));
     int64_t apn = 0;
     if ((rc = read_total(ctx, w.apptr + n, w.flag + 1, &apn, &flags, s))) return rc;
@@ -1905,7 +1908,7 @@ int mis2_smoothed(mis2_ctx *ctx, const mis2_graph *g, const double *val, const d
     }
     w = carve_smoothed(ctx->ws, n, n_agg, pn, apn);
     HIP_TRY(ctx, launch_smoothed_sym(1, true, n, g->row_ptr, g->col, agg, prow, pcol, nullptr,
-                                     nullptr, nullptr, nullptr, w.apptr, w.apcol, w.flag + 1, s));
+                                     nullptr, nullptr, nullptr, w.apptr, w.apcol, w.flag + 1, w.cls, s));
     HIP_TRY(ctx, launch_ap_values(n, apn, g->row_ptr, g->col, val, diag, prow, pcol, pval,
                                   w.apptr, w.apcol, w.apval, s));
     // R_a: the P entries of column a in increasing order (hence increasing row)
@@ -1917,7 +1920,7 @@ int mis2_smoothed(mis2_ctx *ctx, const mis2_graph *g, const double *val, const d
     // Ac = P^T (A P)
     HIP_TRY(ctx, launch_smoothed_sym(2, false, n_agg, g->row_ptr, g->col, agg, w.apptr, w.apcol,
                                      w.moff, w.members, w.prow_of, w.cnt, nullptr, nullptr,
-                                     w.flag + 1, s));
+                                     w.flag + 1, w.cls, s));
     HIP_TRY(ctx, exclusive_scan_u32_i64(w.cnt, n_agg, crow, w.part, s));
     int64_t cn = 0;
     if ((rc = read_total(ctx, crow + n_agg, w.flag + 1, &cn, &flags, s))) return rc;
@@ -1930,7 +1933,7 @@ int mis2_smoothed(mis2_ctx *ctx, const mis2_graph *g, const double *val, const d
                     "room for %lld", (long long)cn, (long long)c_cap);
     HIP_TRY(ctx, launch_smoothed_sym(2, true, n_agg, g->row_ptr, g->col, agg, w.apptr, w.apcol,
                                      w.moff, w.members, w.prow_of, nullptr, crow, ccol,
-                                     w.flag + 1, s));
+                                     w.flag + 1, w.cls, s));
     HIP_TRY(ctx, launch_c_values(n_agg, cn, w.moff, w.members, w.prow_of, pval, w.apptr, w.apcol,
                                  w.apval, crow, ccol, cval, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));

@@ -328,7 +328,7 @@ hipError_t launch_smoothed_sym(int kind, bool fill, int64_t rows, const int64_t 
                                const int32_t *col, const int32_t *agg, const int64_t *sptr,
                                const int32_t *scol, const int64_t *moff, const int32_t *members,
                                const int32_t *prow_of, uint32_t *count, const int64_t *out_ptr,
-                               int32_t *out_col, uint32_t *err, hipStream_t s);
+                               int32_t *out_col, uint32_t *err, uint8_t *cls, hipStream_t s);
 hipError_t launch_p_values(int64_t n, int64_t p_nnz, const int64_t *row_ptr, const int32_t *col,
                            const double *val, const double *diag, const int32_t *agg,
                            const uint32_t *size, double omega, const int64_t *prow,

@@ -36,10 +36,13 @@ namespace mis2 {
 
 namespace {
 
-constexpr int kSetCap = 4096;       // LDS hash-set slots per wavefront
+constexpr int kSetCap = 4096;       // LDS hash-set slots per wavefront (large set)
 constexpr int kSetMax = 2048;       // distinct columns a row may have (load factor 1/2)
-constexpr int kSThreads = 128;            // structure kernels: 2 wavefronts per workgroup
-constexpr int kSWaves = kSThreads / 64;     // (50 KB of LDS per workgroup)
+constexpr int kSmallCap = 512;      // slots of the small set of the first pass
+constexpr int kSmallMax = 256;      // distinct columns a row may have there
+constexpr int kSThreads = 128;      // large-set pass: 2 wavefronts per workgroup (50 KB of LDS)
+constexpr int kSWaves = kSThreads / 64;
+constexpr int kSmallThreads = 256;  // small-set pass: 4 wavefronts per workgroup (17 KB)
 constexpr int32_t kEmpty = -1;
 
 int grid_of_s(int64_t work, int per_block, int cap) {
@@ -47,12 +50,15 @@ int grid_of_s(int64_t work, int per_block, int cap) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
 }
 
+// A wavefront's hash set of CAP slots and the list of its columns (at most
+// MAX are kept; a row with more is bad for this set).
+template <int CAP, int MAX>
 struct SetLds {
-    int32_t slot[kSetCap];
-    int32_t list[kSetMax];  // the columns in the set, in insertion order
+    int32_t slot[CAP];
+    int32_t list[MAX];      // the columns in the set, in insertion order
     int64_t src_lo[64];     // a batch of 64 source rows: first entry
     int64_t src_end[65];    // inclusive prefix of their lengths (src_end[0] = 0)
-    uint32_t n;             // columns inserted (may pass kSetMax: the row is then bad)
+    uint32_t n;             // columns inserted (may pass MAX: the row is then bad)
 };
 
 __device__ __forceinline__ void wave_sync_s() {
@@ -61,24 +67,27 @@ __device__ __forceinline__ void wave_sync_s() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+template <int CAP>
 __device__ __forceinline__ uint32_t set_hash(int32_t c) {
-    return ((uint32_t)c * 2654435761u) >> 20;  // 12 bits: kSetCap slots
+    static_assert((CAP & (CAP - 1)) == 0 && CAP >= 64, "CAP: a power of two");
+    return ((uint32_t)c * 2654435761u) >> (32 - __builtin_ctz(CAP));
 }
 
 // Inserts c (c >= 0) into the set, appending it to the list when it is new
 // (while the list has room); returns 1 if it was new, 0 if present, and 2 if
-// the set is full (the caller flags an error).
-__device__ __forceinline__ int set_insert(SetLds &sh, int32_t c) {
-    uint32_t h = set_hash(c) & (kSetCap - 1);
-    for (int probe = 0; probe < kSetCap; probe++) {
+// the set is full (the row is bad for this set).
+template <int CAP, int MAX>
+__device__ __forceinline__ int set_insert(SetLds<CAP, MAX> &sh, int32_t c) {
+    uint32_t h = set_hash<CAP>(c) & (CAP - 1);
+    for (int probe = 0; probe < CAP; probe++) {
         const int32_t old = atomicCAS(&sh.slot[h], kEmpty, c);
         if (old == kEmpty) {
             const uint32_t k = atomicAdd(&sh.n, 1u);
-            if (k < (uint32_t)kSetMax) sh.list[k] = c;
+            if (k < (uint32_t)MAX) sh.list[k] = c;
             return 1;
         }
         if (old == c) return 0;
-        h = (h + 1) & (kSetCap - 1);
+        h = (h + 1) & (CAP - 1);
     }
     return 2;
 }
@@ -110,6 +119,7 @@ struct SymArgs {
     const int64_t *out_ptr;   // fill pass
     int32_t *out_col;
     uint32_t *err;            // |= 1: a row with more than kSetMax columns
+    uint8_t *cls;             // [rows] 1: the row is left to the large-set pass
 };
 
 // Source rows of output row r: [first, last) of an index range, and the row
@@ -134,8 +144,8 @@ __device__ __forceinline__ int64_t source_row(const SymArgs &a, int64_t r, int64
 
 // Inserts every candidate column of output row r; returns the number of new
 // columns this lane inserted, and sets *full when the set overflowed.
-template <int K>
-__device__ uint32_t insert_row(SetLds &sh, const SymArgs &a, int64_t r, bool *full) {
+template <int K, class Set>
+__device__ uint32_t insert_row(Set &sh, const SymArgs &a, int64_t r, bool *full) {
     const int lane = (int)(threadIdx.x & 63u);
     uint32_t added = 0;
     bool ovf = false;
@@ -190,27 +200,41 @@ __device__ uint32_t insert_row(SetLds &sh, const SymArgs &a, int64_t r, bool *fu
     return added;
 }
 
-template <int K, bool FILL>
-__global__ __launch_bounds__(kSThreads) void k_sym(SymArgs a) {
-    __shared__ SetLds sh_all[kSWaves];
-    SetLds &sh = sh_all[threadIdx.x >> 6];
+// One output row per wavefront.  SMALL: the first pass, with the small set
+// (kSmallCap slots, kSmallMax columns), over every row; a row with more
+// columns is marked in a.cls[r] = 1 (count pass) and left to the second
+// pass.  Else: the large set over the rows marked 1 (64 marks read at a
+// time over rows spread across all wavefronts); a row with more than
+// kSetMax columns sets the error flag.
+template <int K, bool FILL, bool SMALL>
+__global__ __launch_bounds__(SMALL ? kSmallThreads : kSThreads) void k_sym(SymArgs a) {
+    constexpr int CAP = SMALL ? kSmallCap : kSetCap;
+    constexpr int MAX = SMALL ? kSmallMax : kSetMax;
+    constexpr int WAVES = (SMALL ? kSmallThreads : kSThreads) / 64;
+    __shared__ SetLds<CAP, MAX> sh_all[WAVES];
+    SetLds<CAP, MAX> &sh = sh_all[threadIdx.x >> 6];
     const int lane = (int)(threadIdx.x & 63u);
-    const int64_t w0 = (int64_t)blockIdx.x * kSWaves + (threadIdx.x >> 6);
-    const int64_t stride = (int64_t)gridDim.x * kSWaves;
+    const int64_t w0 = (int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
+    const int64_t stride = (int64_t)gridDim.x * WAVES;
     // the set starts empty and is emptied after each row by clearing the
     // slots of the listed columns only (the whole table after a bad row)
-    for (int q = lane; q < kSetCap; q += 64) sh.slot[q] = kEmpty;
+    for (int q = lane; q < CAP; q += 64) sh.slot[q] = kEmpty;
     if (lane == 0) sh.n = 0u;
     wave_sync_s();
-    for (int64_t r = w0; r < a.rows; r += stride) {
+    auto row = [&](const int64_t r) {
         bool full = false;
         insert_row<K>(sh, a, r, &full);
         wave_sync_s();
         const uint32_t distinct = sh.n;
-        const bool bad = __ballot(full) != 0 || distinct > (uint32_t)kSetMax;
+        const bool bad = __ballot(full) != 0 || distinct > (uint32_t)MAX;
         if (!FILL && lane == 0) {
-            a.count[r] = bad ? 0u : distinct;
-            if (bad) atomicOr(a.err, 1u);
+            if (SMALL) {
+                a.cls[r] = bad ? 1 : 0;
+                if (!bad) a.count[r] = distinct;
+            } else {
+                a.count[r] = bad ? 0u : distinct;
+                if (bad) atomicOr(a.err, 1u);
+            }
         }
         if (FILL && !bad) {
             // place each column at its rank among the row's columns
@@ -225,18 +249,35 @@ __global__ __launch_bounds__(kSThreads) void k_sym(SymArgs a) {
         }
         wave_sync_s();
         if (bad) {
-            for (int q = lane; q < kSetCap; q += 64) sh.slot[q] = kEmpty;
+            for (int q = lane; q < CAP; q += 64) sh.slot[q] = kEmpty;
         } else {
             for (uint32_t x = lane; x < distinct; x += 64) {
                 const int32_t c = sh.list[x];
-                uint32_t h = set_hash(c) & (kSetCap - 1);
-                while (sh.slot[h] != c) h = (h + 1) & (kSetCap - 1);
+                uint32_t h = set_hash<CAP>(c) & (CAP - 1);
+                while (sh.slot[h] != c) h = (h + 1) & (CAP - 1);
                 sh.slot[h] = kEmpty;
             }
         }
         wave_sync_s();
         if (lane == 0) sh.n = 0u;
         wave_sync_s();
+    };
+    if (SMALL) {
+        for (int64_t r = w0; r < a.rows; r += stride) {
+            // the fill pass skips the rows the count pass left to the large set
+            if (FILL && a.cls[r] != 0) continue;  // uniform: one row per wavefront
+            row(r);
+        }
+    } else {
+        for (int64_t j0 = 0; w0 + j0 * stride < a.rows; j0 += 64) {
+            const int64_t v = w0 + (j0 + lane) * stride;
+            uint64_t mask = __ballot(v < a.rows && a.cls[v] != 0);
+            while (mask) {
+                const int q = __ffsll((unsigned long long)mask) - 1;
+                mask &= mask - 1;
+                row(w0 + (j0 + q) * stride);
+            }
+        }
     }
 }
 
@@ -352,20 +393,27 @@ hipError_t launch_smoothed_sym(int kind, bool fill, int64_t rows, const int64_t 
                                const int32_t *col, const int32_t *agg, const int64_t *sptr,
                                const int32_t *scol, const int64_t *moff, const int32_t *members,
                                const int32_t *prow_of, uint32_t *count, const int64_t *out_ptr,
-                               int32_t *out_col, uint32_t *err, hipStream_t s) {
+                               int32_t *out_col, uint32_t *err, uint8_t *cls, hipStream_t s) {
     if (rows <= 0) return hipSuccess;
     SymArgs a{rows, row_ptr, col, agg, sptr, scol, moff, members, prow_of, count, out_ptr,
-              out_col, err};
-    const dim3 grid(grid_of_s(rows, kSWaves, 8192)), block(kSThreads);
+              out_col, err, cls};
+    // the small-set pass over every row, then the large-set pass over the
+    // rows it left
+    const dim3 g1(grid_of_s(rows, kSmallThreads / 64, 16384)), b1(kSmallThreads);
+    const dim3 g2(grid_of_s(rows, kSWaves, 8192)), b2(kSThreads);
+#define MIS2_SYM2(K, F)                                                        \
+    hipLaunchKernelGGL((k_sym<K, F, true>), g1, b1, 0, s, a);                  \
+    hipLaunchKernelGGL((k_sym<K, F, false>), g2, b2, 0, s, a);
     switch (kind * 2 + (fill ? 1 : 0)) {
-        case 0: hipLaunchKernelGGL((k_sym<kP, false>), grid, block, 0, s, a); break;
-        case 1: hipLaunchKernelGGL((k_sym<kP, true>), grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_sym<kAP, false>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_sym<kAP, true>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_sym<kC, false>), grid, block, 0, s, a); break;
-        case 5: hipLaunchKernelGGL((k_sym<kC, true>), grid, block, 0, s, a); break;
+        case 0: MIS2_SYM2(kP, false) break;
+        case 1: MIS2_SYM2(kP, true) break;
+        case 2: MIS2_SYM2(kAP, false) break;
+        case 3: MIS2_SYM2(kAP, true) break;
+        case 4: MIS2_SYM2(kC, false) break;
+        case 5: MIS2_SYM2(kC, true) break;
         default: return hipErrorInvalidValue;
     }
+#undef MIS2_SYM2
     return hipGetLastError();
 }
 

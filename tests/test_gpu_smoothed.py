@@ -68,6 +68,32 @@ def test_smoothed_27pt_40cube(ctx):
          % (w[1].size, w[3].size - 1, w[4].size))
 
 
+def test_smoothed_rows_past_the_small_set(ctx):
+    # a hub with 600 spokes of three vertices, each spoke its own aggregate:
+    # the hub's row of P, the rows of A P next to it and the hub aggregate's
+    # row of P^T A P hold more than 256 columns (the first, small-set pass
+    # leaves them to the second); the other rows are small
+    import torch
+    k = 600
+    u = np.concatenate([np.zeros(k, np.int64), 1 + 3 * np.arange(k), 2 + 3 * np.arange(k)])
+    w = np.concatenate([1 + 3 * np.arange(k), 2 + 3 * np.arange(k), 3 + 3 * np.arange(k)])
+    rp, c = graphs.from_edges(1 + 3 * k, u, w)
+    agg = np.zeros(1 + 3 * k, np.int32)
+    agg[1:] = 1 + np.repeat(np.arange(k), 3)
+    na = k + 1
+    val, diag = graphs.matrix_values(rp, c, 9, shift=0.25)
+    want = oracle.smoothed(rp, c, val, diag, agg, na, 2.0 / 3.0)
+    prow, pcol = want[0], want[1]
+    assert prow[1] - prow[0] > 256  # the hub's row of P
+    dev = torch.device("cuda", 0)
+    (gp, gc, gv), (hp, hc, hv) = ctx.smoothed(rp, c, torch.as_tensor(val, device=dev),
+                                              torch.as_tensor(diag, device=dev), agg, na,
+                                              2.0 / 3.0)
+    got = [x.cpu().numpy() for x in (gp, gc, gv, hp, hc, hv)]
+    for i, (g, x) in enumerate(zip(got, want)):
+        assert g.shape == x.shape and np.array_equal(g, x), i
+
+
 def test_smoothed_rejects_labels_out_of_range(ctx):
     import torch
     from paper_2204_02934_amd._lib import Mis2Error
