@@ -281,6 +281,23 @@ def test_quotient_big_row_candidate_range(ctx, hub_label, leaf_lo, leaf_step):
     assert np.array_equal(ccol.cpu().numpy(), ocol)
 
 
+def test_quotient_two_wavefront_passes(ctx):
+    # many small coarse rows (5-point aggregates, about 25 candidates) and a
+    # few past 128 (27-point aggregates, several hundred): at least 16384
+    # rows and a small average, so the rows of up to 128 candidates take the
+    # first wavefront pass and the others are marked for the second
+    gs = [graphs.grid2d_5pt(400, 400), graphs.grid3d_27pt(20, 20, 20)]
+    rp, c = graphs.disjoint_union(gs)
+    agg, na = oracle.aggregate(rp, c, 0)
+    cand = np.bincount(agg, weights=np.diff(rp), minlength=na)
+    assert na >= 16384 and rp[-1] <= 256 * na
+    assert (cand > 128).sum() > 100 and (cand <= 128).sum() > 10000
+    crow, ccol = ctx.quotient(rp, c, agg, na)
+    orow, ocol = oracle.quotient(rp, c, agg, na)
+    assert np.array_equal(crow.cpu().numpy(), orow)
+    assert np.array_equal(ccol.cpu().numpy(), ocol)
+
+
 def _giant_case(kind):
     # complete graphs of 300 vertices: an aggregate of most of one holds
     # about 89k candidates, past the 65536 that send a row to a bitmap slot
