@@ -3,8 +3,10 @@
 // out = [v in 0..n-1 : pred(v)] in increasing v.  Used wherever a numbering
 // must be deterministic: aggregate ids are ranks of roots in increasing
 // vertex id, so the positions here are exact prefix sums (no atomics).
-// Three launches: per-tile counts, one-workgroup scan of the tile counts,
-// per-tile scatter with a workgroup scan built from wave64 ballots.
+// Up to 4096 tiles: per-tile counts, then one scatter launch in which each
+// workgroup sums the counts of the tiles before its own and scans its tile
+// with wave64 ballots.  Past that: counts, a one-workgroup scan of the
+// counts, then the per-tile scatter.
 #include "internal.h"
 
 namespace mis2 {
