@@ -58,7 +58,9 @@ extern "C" {
                                      per CSR row */
 #define MIS2_LANES_STAGED     (-2) /* one row per lane, each row's column indices staged in LDS
                                      by 16-byte loads (rows of more than 32 entries go to the
-                                     whole wavefront) */
+                                     whole wavefront); on graphs without such rows, once
+                                     fewer than n/4 rows are left in worklist2, the rounds
+                                     run 4 lanes per row */
 #define MIS2_OPT_GRID_BLOCKS   2  /* 0 = automatic; else 1..8192 256-thread workgroups per sweep */
 #define MIS2_OPT_PROFILE       3  /* 1: time every sweep launch with HIP events on the call's stream */
 #define MIS2_OPT_ACCOUNT       4  /* 1: sweeps also sum the CSR row lengths they visit (extra atomics) */

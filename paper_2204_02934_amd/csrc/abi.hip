@@ -344,6 +344,16 @@ FillSpans round_fills(const mis2_graph *g, const Workspace &ws, bool masked) {
     return f;
 }
 
+// Staged plans on graphs without long rows switch to kLateLanes-lane kernels
+// once the host sees |worklist2| * kLateShare < n.  Measured on gfx950 (27-point 100^3,
+// mis2_run + mis2_aggregate, staged sweeps at 1024 workgroups with the tail):
+// 1.055-1.061 ms staged throughout; switching at n/2 1.041, n/4 1.035, n/8
+// 1.052 ms; 2 lanes at n/4 1.048 ms.  The staged kernels stage each row in
+// LDS, which pays while rows are dense and costs 1-2 us per launch once they
+// are sparse.
+constexpr int kLateLanes = 4;
+constexpr uint64_t kLateShare = 4;
+
 int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspace &ws,
                const Geometry &gm, bool masked, int phase, hipStream_t s, int32_t *iters_out,
                std::vector<Launch> *launches, int *long_rows, const AblRun *abl = nullptr,
@@ -389,6 +399,7 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
     // the last rounds go to the one-workgroup tail once both worklists fit it
     const bool tail_ok = ctx->plan.tail > 0 && !abl && lanes != 0 && g->nnz > 0;
     int round = 0;  // rounds issued
+    int late_lanes = 0;  // staged plans: lanes of the sparse rounds once switched
     auto last_progress = std::chrono::steady_clock::now();
     int last_seen = -2;
     for (;;) {
@@ -456,8 +467,19 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
                 if (cstart < 0) cstart = round;
                 mode = round == cstart ? 1 : 2;
             }
-            Launch lc{0, phase, round, lanes, nullptr, nullptr, false, mode};
-            Launch ld{1, phase, round, lanes, nullptr, nullptr};
+            // the staged sweeps hand the sparse rounds to 4-lane kernels
+            // (same segments, same results), whose per-launch cost is lower
+            // once few rows are left; only where no row is long, so that no
+            // round compacts (the two kernels' compaction thresholds differ)
+            if (lanes == kStagedLanes && !abl && !late_lanes && longs == 0) {
+                const unsigned long long w2 = __atomic_load_n(ctx->alive_host + 1, __ATOMIC_ACQUIRE);
+                if (w2 != ~0ull && (uint32_t)(w2 >> 48) == a.epoch &&
+                    (uint64_t)(uint32_t)w2 * kLateShare < (uint64_t)g->n)
+                    late_lanes = kLateLanes;
+            }
+            const int rl = late_lanes ? late_lanes : lanes;
+            Launch lc{0, phase, round, rl, nullptr, nullptr, false, mode};
+            Launch ld{1, phase, round, rl, nullptr, nullptr};
             if (ctx->profile) {
                 lc.e0 = take_event(ctx), lc.e1 = take_event(ctx);
                 ld.e0 = take_event(ctx), ld.e1 = take_event(ctx);
@@ -470,9 +492,9 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
                 HIP_TRY(ctx, launch_abl_round(1, abl->unpacked, abl->all, gm.blocks, g->row_ptr,
                                               g->col, abl->T, abl->M, a, round, s, ld.e0, ld.e1));
             } else {
-                HIP_TRY(ctx, launch_col_round(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
+                HIP_TRY(ctx, launch_col_round(rl, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
                                               a, round, mode, s, lc.e0, lc.e1));
-                HIP_TRY(ctx, launch_dec_round(lanes, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
+                HIP_TRY(ctx, launch_dec_round(rl, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
                                               a, round, s, ld.e0, ld.e1));
             }
             launches->push_back(lc);

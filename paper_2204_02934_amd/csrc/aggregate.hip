@@ -120,8 +120,9 @@ __global__ __launch_bounds__(kBlock) void k_label_roots(const int64_t *__restric
 
 // flag[v] = 1 iff v is a root of the phase-2 MIS-2 (T_v = IN in the masked
 // run) with at least two neighbours that are unlabelled after phase 1.  Each
-// wavefront scans 64 vertices at a time and counts the candidates' rows
-// cooperatively, one row at a time.
+// wavefront scans 64 vertices at a time; a candidate's row of up to
+// kAcceptLane entries is counted by its own lane, longer ones by the whole
+// wavefront, one row at a time.
 constexpr int64_t kAcceptLane = 32;  // rows a lane counts alone in k_accept_phase2
 
 __global__ __launch_bounds__(kBlock) void k_accept_phase2(int64_t n,
@@ -146,18 +147,17 @@ __global__ __launch_bounds__(kBlock) void k_accept_phase2(int64_t n,
         }
         const bool own = cand && re - rs <= kAcceptLane;
         uint8_t f = 0;
-        if (own) {
+        if (own && re > rs) {
+            // every entry loads at once (from clamped valid addresses), then
+            // every label: two dependent steps for the whole row
+            int32_t x[kAcceptLane];
+#pragma unroll
+            for (int k = 0; k < (int)kAcceptLane; k++) x[k] = col[rs + k < re ? rs + k : rs];
+#pragma unroll
+            for (int k = 0; k < (int)kAcceptLane; k++) x[k] = label[x[k]];
             int cnt = 0;
-            for (int64_t b = rs; b < re; b += kCoopLoads) {
-                int32_t x[kCoopLoads];
 #pragma unroll
-                for (int k = 0; k < kCoopLoads; k++) x[k] = col[b + k < re ? b + k : rs];
-                int32_t lb[kCoopLoads];
-#pragma unroll
-                for (int k = 0; k < kCoopLoads; k++) lb[k] = label[x[k]];
-#pragma unroll
-                for (int k = 0; k < kCoopLoads; k++) cnt += (b + k < re) & (lb[k] == -1);
-            }
+            for (int k = 0; k < (int)kAcceptLane; k++) cnt += (rs + k < re) & (x[k] == -1);
             f = cnt >= 2;
         }
         uint64_t mask = __ballot(cand && !own);
@@ -255,26 +255,13 @@ __device__ __forceinline__ void p3_group_best(int &bc, int &bs, int &ba) {
 constexpr int32_t kPad = -2;  // label of a padding lane; never equals an aggregate id
 
 // Short rows: lane j of the group holds the tent labels of neighbours
-// k*L + j for k < K, all loaded before any is used.  Every lane broadcasts
-// its K labels to the group once; each lane counts, for each of its own
-// labels, the equal ones among all L*K (its coupling), and keeps its best
-// candidate in the order above.
+// k*L + j for k < K, and the sizes of their aggregates, all loaded before any
+// is used.  Every lane broadcasts its K labels to the group once; each lane
+// counts, for each of its own labels, the equal ones among all L*K (its
+// coupling), and keeps its best candidate in the order above.
 template <int L, int K>
-__device__ __forceinline__ void p3_short(const int32_t *__restrict__ col,
-                                         const int32_t *__restrict__ label,
-                                         const int32_t *__restrict__ aggsize, int64_t s, int64_t e,
-                                         int sub, int &bc, int &bs, int &ba) {
-    int32_t x[K], a[K];
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        const int64_t j = s + k * L + sub;
-        x[k] = col[j < e ? j : 0];
-    }
-#pragma unroll
-    for (int k = 0; k < K; k++) a[k] = label[x[k]];
-#pragma unroll
-    for (int k = 0; k < K; k++)
-        if (s + k * L + sub >= e) a[k] = kPad;
+__device__ __forceinline__ void p3_count(const int32_t (&a)[K], const int32_t (&sz)[K], int &bc,
+                                         int &bs, int &ba) {
     int cnt[K];
 #pragma unroll
     for (int k = 0; k < K; k++) cnt[k] = 0;
@@ -287,9 +274,6 @@ __device__ __forceinline__ void p3_short(const int32_t *__restrict__ col,
             for (int k = 0; k < K; k++) cnt[k] += (b == a[k]);
         }
     }
-    int sz[K];
-#pragma unroll
-    for (int k = 0; k < K; k++) sz[k] = aggsize[a[k] >= 0 ? a[k] : 0];
 #pragma unroll
     for (int k = 0; k < K; k++) {
         if (a[k] >= 0 && better(cnt[k], sz[k], a[k], bc, bs, ba)) {
@@ -301,9 +285,10 @@ __device__ __forceinline__ void p3_short(const int32_t *__restrict__ col,
 }
 
 // One group of L lanes per unaggregated row of the wavefront's segment.  Rows
-// of at most K chunks of L entries take p3_short; longer rows are listed, in
-// order, in the wavefront's segment of io.wl_out for k_phase3_long.  The
-// group's best candidate is reduced with the candidate order above.
+// of at most K chunks of L entries are counted in registers; longer rows are
+// listed, in order, in the wavefront's segment of io.wl_out for
+// k_phase3_long.  The group's best candidate is reduced with the candidate
+// order above.
 template <int L>
 __global__ __launch_bounds__(kBlock) void k_phase3(const int64_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col,
@@ -334,7 +319,22 @@ __global__ __launch_bounds__(kBlock) void k_phase3(const int64_t *__restrict__ r
         const int64_t es = is_long ? s : e;  // long rows are left to k_phase3_long
         const int64_t wmax = group_max64<64>((es - s + L - 1) / L);
         int bc = 0, bs = 0x7FFFFFFF, ba = 0x7FFFFFFF;
-        if (wmax > 0) p3_short<L, K>(col, label, aggsize, s, es, sub, bc, bs, ba);
+        if (wmax > 0) {
+            int32_t a[K], sz[K];
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const int64_t j = s + k * L + sub;
+                a[k] = col[j < es ? j : 0];
+            }
+#pragma unroll
+            for (int k = 0; k < K; k++) a[k] = label[a[k]];
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                if (s + k * L + sub >= es) a[k] = kPad;
+                sz[k] = aggsize[a[k] >= 0 ? a[k] : 0];
+            }
+            p3_count<L, K>(a, sz, bc, bs, ba);
+        }
         p3_group_best<L>(bc, bs, ba);
         if (valid && sub == 0 && !is_long) {
             if (bc > 0)

@@ -1422,9 +1422,11 @@ __device__ __forceinline__ void tail_sum3(TailLds &sh, unsigned long long a, uns
 // workgroup scan gives each workgroup its first position (kept in LDS as 16
 // bits), and then every thread copies up to kTailCap / kTailThreads entries:
 // a binary search in those positions finds an entry's workgroup, its four
-// counts its wavefront.
+// counts its wavefront.  Only positions below the size are searched and
+// copied, and with copy false only the size is taken (a run that has ended
+// needs no list).
 __device__ uint32_t tail_gather(TailLds &sh, const int32_t *wl, const uint32_t *cnt, int64_t S,
-                                int64_t seg, int32_t *dst) {
+                                int64_t seg, int32_t *dst, bool copy = true) {
     constexpr int kJ = kMaxBlocks / kTailThreads;  // workgroups per thread, at most
     const int B = (int)(S / 4);
     const int J = (B + kTailThreads - 1) / kTailThreads;
@@ -1442,6 +1444,7 @@ __device__ uint32_t tail_gather(TailLds &sh, const int32_t *wl, const uint32_t *
     uint32_t total = 0;
     uint32_t at = tail_scan(sh, mine, &total);
     if (total > (uint32_t)kTailCap) return 0xFFFFFFFFu;  // the same in every thread
+    if (!copy || total == 0u) return total;
 #pragma unroll
     for (int j = 0; j < kJ; j++) {
         const int b = tid * J + j;
@@ -1454,22 +1457,24 @@ __device__ uint32_t tail_gather(TailLds &sh, const int32_t *wl, const uint32_t *
 #pragma unroll
     for (int i = 0; i < kPer; i++) {
         const uint32_t p = (uint32_t)(tid + i * kTailThreads);
-        // the last workgroup whose first position is <= p (a workgroup after
-        // an empty one starts where it starts, so this one holds entry p)
-        int lo = 0, hi = B - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if ((uint32_t)sh.off[mid] <= p) lo = mid; else hi = mid - 1;
+        val[i] = 0;
+        if (p < total) {
+            // the last workgroup whose first position is <= p (a workgroup
+            // after an empty one starts where it starts, so this one holds
+            // entry p)
+            int lo = 0, hi = B - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if ((uint32_t)sh.off[mid] <= p) lo = mid; else hi = mid - 1;
+            }
+            const uint4 c = *(const uint4 *)(cnt + 4 * (size_t)lo);
+            uint32_t q = p - (uint32_t)sh.off[lo];
+            int w = 0;
+            if (q >= c.x) { q -= c.x; w = 1;
+                if (q >= c.y) { q -= c.y; w = 2;
+                    if (q >= c.z) { q -= c.z; w = 3; } } }
+            val[i] = wl[(4 * (int64_t)lo + w) * seg + q];
         }
-        const bool ok = p < total;
-        const uint4 c = *(const uint4 *)(cnt + 4 * (size_t)lo);
-        uint32_t q = ok ? p - (uint32_t)sh.off[lo] : 0u;
-        int w = 0;
-        if (q >= c.x) { q -= c.x; w = 1;
-            if (q >= c.y) { q -= c.y; w = 2;
-                if (q >= c.z) { q -= c.z; w = 3; } } }
-        // positions past the end read slot 0 (always within the list)
-        val[i] = wl[ok ? (4 * (int64_t)lo + w) * seg + q : 0];
     }
 #pragma unroll
     for (int i = 0; i < kPer; i++) {
@@ -1525,7 +1530,9 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const int64_t *__restrict
     {
         const int cur = r & 1;
         const uint32_t c1 = tail_gather(sh, a.wl1[cur], a.cnt1[cur], a.S, a.seg, sh.l1);
-        const uint32_t c2 = tail_gather(sh, a.wl2[cur], a.cnt2[cur], a.S, a.seg, sh.l2);
+        // an empty worklist1 ends the run at once: worklist2's size is still
+        // recorded, its entries are not needed
+        const uint32_t c2 = tail_gather(sh, a.wl2[cur], a.cnt2[cur], a.S, a.seg, sh.l2, c1 != 0u);
         if (tid == 0) {
             sh.n1 = c1;
             sh.n2 = c2;
