@@ -125,6 +125,17 @@ __global__ __launch_bounds__(kBlock) void k_label_roots(const int64_t *__restric
 // wavefront, one row at a time.
 constexpr int64_t kAcceptLane = 32;  // rows a lane counts alone in k_accept_phase2
 
+// Buffer resource over n labels: a load whose byte offset is at or past
+// 4n returns 0 without a memory access (the range check of raw buffer
+// loads), which predicates a load per lane without a branch.  Word 3 is the
+// gfx9 data-format word (32-bit elements).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t label_rsrc(const int32_t *label, int64_t n) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)label, (short)0, (int)(uint32_t)(4 * n),
+                                             0x00020000);
+}
+
+// BUF: 4n < 2^32, so every label is reachable by a 32-bit buffer offset.
+template <bool BUF>
 __global__ __launch_bounds__(kBlock) void k_accept_phase2(int64_t n,
                                                           const int64_t *__restrict__ row_ptr,
                                                           const int32_t *__restrict__ col,
@@ -138,8 +149,7 @@ __global__ __launch_bounds__(kBlock) void k_accept_phase2(int64_t n,
         const int64_t v = base + lane;
         const bool cand = v < n && label[v] == -1 && T[v] == kIn;
         // a candidate with a row of up to kAcceptLane entries counts its own
-        // row, kCoopLoads entries loaded together; longer rows go to the
-        // whole wavefront one at a time
+        // row; longer rows go to the whole wavefront one at a time
         int64_t rs = 0, re = 0;
         if (cand) {
             rs = row_ptr[v];
@@ -147,17 +157,31 @@ __global__ __launch_bounds__(kBlock) void k_accept_phase2(int64_t n,
         }
         const bool own = cand && re - rs <= kAcceptLane;
         uint8_t f = 0;
-        if (own && re > rs) {
-            // every entry loads at once (from clamped valid addresses), then
-            // every label: two dependent steps for the whole row
+        if (own) {
+            // every entry of the row loads at once, then every label: two
+            // dependent steps for the whole row; each load is issued only for
+            // the entries the lane's row has
+            const int len = (int)(re - rs);
             int32_t x[kAcceptLane];
 #pragma unroll
-            for (int k = 0; k < (int)kAcceptLane; k++) x[k] = col[rs + k < re ? rs + k : rs];
+            for (int k = 0; k < (int)kAcceptLane; k++) {
+                x[k] = 0;
+                if (k < len) x[k] = col[rs + k];
+            }
+            if constexpr (BUF) {
+                const __amdgpu_buffer_rsrc_t rl = label_rsrc(label, n);
 #pragma unroll
-            for (int k = 0; k < (int)kAcceptLane; k++) x[k] = label[x[k]];
+                for (int k = 0; k < (int)kAcceptLane; k++)
+                    x[k] = __builtin_amdgcn_raw_buffer_load_b32(
+                        rl, k < len ? (int)(4u * (uint32_t)x[k]) : (int)0xFFFFFFFCu, 0, 0);
+            } else {
+                // entries past the row all read label 0: one line for the wavefront
+#pragma unroll
+                for (int k = 0; k < (int)kAcceptLane; k++) x[k] = label[k < len ? x[k] : 0];
+            }
             int cnt = 0;
 #pragma unroll
-            for (int k = 0; k < (int)kAcceptLane; k++) cnt += (rs + k < re) & (x[k] == -1);
+            for (int k = 0; k < (int)kAcceptLane; k++) cnt += (k < len) & (x[k] == -1);
             f = cnt >= 2;
         }
         uint64_t mask = __ballot(cand && !own);
@@ -256,31 +280,50 @@ constexpr int32_t kPad = -2;  // label of a padding lane; never equals an aggreg
 
 // Short rows: lane j of the group holds the tent labels of neighbours
 // k*L + j for k < K, and the sizes of their aggregates, all loaded before any
-// is used.  Every lane broadcasts its K labels to the group once; each lane
-// counts, for each of its own labels, the equal ones among all L*K (its
-// coupling), and keeps its best candidate in the order above.
-template <int L, int K>
-__device__ __forceinline__ void p3_count(const int32_t (&a)[K], const int32_t (&sz)[K], int &bc,
-                                         int &bs, int &ba) {
-    int cnt[K];
+// is used.  Every lane broadcasts its labels to the group; each lane counts,
+// for each of its own labels, the equal ones among the group's (its
+// coupling), and keeps its best candidate in the order above.  Only the
+// first C chunks take part, C the chunk count of the longest row in the
+// wavefront: later chunks hold pads in every lane.
+template <int L, int K, int C>
+__device__ __forceinline__ void p3_count_c(const int32_t (&a)[K], const int32_t (&sz)[K], int &bc,
+                                           int &bs, int &ba) {
+    int cnt[C];
 #pragma unroll
-    for (int k = 0; k < K; k++) cnt[k] = 0;
+    for (int k = 0; k < C; k++) cnt[k] = 0;
 #pragma unroll
-    for (int t = 0; t < L; t++) {
+    for (int k2 = 0; k2 < C; k2++) {
 #pragma unroll
-        for (int k2 = 0; k2 < K; k2++) {
+        for (int t = 0; t < L; t++) {
             const int32_t b = __shfl(a[k2], t, L);
 #pragma unroll
-            for (int k = 0; k < K; k++) cnt[k] += (b == a[k]);
+            for (int k = 0; k < C; k++) cnt[k] += (b == a[k]);
         }
     }
 #pragma unroll
-    for (int k = 0; k < K; k++) {
+    for (int k = 0; k < C; k++) {
         if (a[k] >= 0 && better(cnt[k], sz[k], a[k], bc, bs, ba)) {
             bc = cnt[k];
             bs = sz[k];
             ba = a[k];
         }
+    }
+}
+
+// chunks: 1..K, the same in every lane of the wavefront.
+template <int L, int K>
+__device__ __forceinline__ void p3_count(const int32_t (&a)[K], const int32_t (&sz)[K], int chunks,
+                                         int &bc, int &bs, int &ba) {
+    static_assert(K >= 1 && K <= 8, "chunks per lane");
+    switch (__builtin_amdgcn_readfirstlane(chunks)) {
+        case 1: p3_count_c<L, K, 1>(a, sz, bc, bs, ba); break;
+        case 2: if constexpr (K >= 2) p3_count_c<L, K, 2>(a, sz, bc, bs, ba); break;
+        case 3: if constexpr (K >= 3) p3_count_c<L, K, 3>(a, sz, bc, bs, ba); break;
+        case 4: if constexpr (K >= 4) p3_count_c<L, K, 4>(a, sz, bc, bs, ba); break;
+        case 5: if constexpr (K >= 5) p3_count_c<L, K, 5>(a, sz, bc, bs, ba); break;
+        case 6: if constexpr (K >= 6) p3_count_c<L, K, 6>(a, sz, bc, bs, ba); break;
+        case 7: if constexpr (K >= 7) p3_count_c<L, K, 7>(a, sz, bc, bs, ba); break;
+        default: p3_count_c<L, K, K>(a, sz, bc, bs, ba); break;
     }
 }
 
@@ -333,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_phase3(const int64_t *__restrict__ r
                 if (s + k * L + sub >= es) a[k] = kPad;
                 sz[k] = aggsize[a[k] >= 0 ? a[k] : 0];
             }
-            p3_count<L, K>(a, sz, bc, bs, ba);
+            p3_count<L, K>(a, sz, (int)wmax, bc, bs, ba);
         }
         p3_group_best<L>(bc, bs, ba);
         if (valid && sub == 0 && !is_long) {
@@ -351,12 +394,19 @@ __global__ __launch_bounds__(kBlock) void k_phase3(const int64_t *__restrict__ r
 }
 
 // Long unaggregated rows, one at a time per wavefront: the couplings are
-// counted in an LDS hash map (aggregate id -> count; kP3Slots slots, so any
-// row of up to kP3Slots entries fits), then the wavefront reduces its entries
-// with the candidate order.  Rows longer than that count each label against
-// the whole row, 64 labels at a time.
+// counted in an LDS hash map (aggregate id -> count) of cap slots, cap the
+// power of two >= 2 * len between 64 and kP3Slots, so that clearing and
+// reading the map cost in proportion to the row (every row of up to
+// kP3Slots entries fits: it has at most len distinct ids); then the
+// wavefront reduces its entries with the candidate order.  Rows longer than
+// kP3Slots count each label against the whole row, 64 labels at a time.
+// The grid is small enough to be resident at once (the map takes 64 KiB per
+// workgroup): wavefront w takes the list segments w, w + W, w + 2W, ... (W
+// wavefronts in the grid), reading 64 segment sizes in one load.  Measured on
+// gfx950 (Chung-Lu 4M, 22 791 rows of 33-291 entries): one wavefront per
+// segment with the whole 2048-slot map for every row took 288 us.
 constexpr int kP3Slots = 2048;
-__device__ __forceinline__ uint32_t p3hash(uint32_t a) { return (a * 2654435761u) >> 21; }
+constexpr int kP3LongBlocks = 512;  // 2 resident workgroups on each of 256 compute units
 
 __device__ __forceinline__ void p3_reduce(int &bc, int &bs, int &ba) {
     p3_group_best<64>(bc, bs, ba);
@@ -368,90 +418,102 @@ __global__ __launch_bounds__(kBlock) void k_phase3_long(const int64_t *__restric
                                                         const int32_t *__restrict__ aggsize,
                                                         SegIO io, int32_t *__restrict__ agg_out,
                                                         uint32_t *__restrict__ err) {
-    static_assert(kP3Slots == 2048, "p3hash yields 11 bits");
     constexpr uint32_t kEmpty = 0xFFFFFFFFu;
     __shared__ uint32_t keys_s[kBlock / 64][kP3Slots];
     __shared__ uint32_t cnts_s[kBlock / 64][kP3Slots];
-    const int64_t w = wave_id();
-    if (w >= io.S) return;
     uint32_t *keys = keys_s[threadIdx.x >> 6];
     uint32_t *cnts = cnts_s[threadIdx.x >> 6];
     const int lane = (int)(threadIdx.x & 63u);
-    const int64_t count = io.cnt_in[w];
-    const int64_t sbase = w * io.seg;
-    for (int64_t i = 0; i < count; i++) {
-        const int32_t v = io.wl_in[sbase + i];
-        const int64_t s = row_ptr[v], e = row_ptr[v + 1];
-        int bc = 0, bs = 0x7FFFFFFF, ba = 0x7FFFFFFF;
-        if (e - s <= kP3Slots) {
-            for (int k = lane; k < kP3Slots; k += 64) {
-                keys[k] = kEmpty;
-                cnts[k] = 0u;
-            }
-            wave_lds_sync();
-            for (int64_t j0 = s; j0 < e; j0 += 64 * kCoopLoads) {
-                int32_t x[kCoopLoads];
+    const int64_t W = (int64_t)gridDim.x * (kBlock / 64);
+    const int64_t w = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    for (int64_t w0 = w; w0 < io.S; w0 += 64 * W) {
+        const int64_t mine = w0 + (int64_t)lane * W;  // the segment this lane reads the size of
+        const uint32_t my_count = mine < io.S ? io.cnt_in[mine] : 0u;
+        uint64_t todo = __ballot(my_count != 0u);
+        while (todo) {
+            const int j = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            const int64_t count = __shfl((int)my_count, j, 64);
+            const int64_t sbase = (w0 + (int64_t)j * W) * io.seg;
+            for (int64_t i = 0; i < count; i++) {
+                const int32_t v = io.wl_in[sbase + i];
+                const int64_t s = row_ptr[v], e = row_ptr[v + 1];
+                int bc = 0, bs = 0x7FFFFFFF, ba = 0x7FFFFFFF;
+                if (e - s <= kP3Slots) {
+                    int lg = 6;
+                    while ((int64_t)1 << lg < 2 * (e - s) && lg < 11) lg++;
+                    const uint32_t cap = 1u << lg;
+                    for (uint32_t k = (uint32_t)lane; k < cap; k += 64) {
+                        keys[k] = kEmpty;
+                        cnts[k] = 0u;
+                    }
+                    wave_lds_sync();
+                    for (int64_t j0 = s; j0 < e; j0 += 64 * kCoopLoads) {
+                        int32_t x[kCoopLoads];
 #pragma unroll
-                for (int k = 0; k < kCoopLoads; k++) {
-                    const int64_t j = j0 + (int64_t)k * 64 + lane;
-                    x[k] = col[j < e ? j : s];
-                }
-                int32_t a[kCoopLoads];
-#pragma unroll
-                for (int k = 0; k < kCoopLoads; k++) a[k] = label[x[k]];
-#pragma unroll
-                for (int k = 0; k < kCoopLoads; k++) {
-                    if (j0 + (int64_t)k * 64 + lane < e && a[k] >= 0) {
-                        const uint32_t key = (uint32_t)a[k];
-                        uint32_t h = p3hash(key);
-                        for (;;) {  // the map has a slot for every entry of the row
-                            const uint32_t prev = atomicCAS(&keys[h], kEmpty, key);
-                            if (prev == kEmpty || prev == key) break;
-                            h = (h + 1) & (kP3Slots - 1);
+                        for (int k = 0; k < kCoopLoads; k++) {
+                            const int64_t jj = j0 + (int64_t)k * 64 + lane;
+                            x[k] = col[jj < e ? jj : s];
                         }
-                        atomicAdd(&cnts[h], 1u);
+                        int32_t a[kCoopLoads];
+#pragma unroll
+                        for (int k = 0; k < kCoopLoads; k++) a[k] = label[x[k]];
+#pragma unroll
+                        for (int k = 0; k < kCoopLoads; k++) {
+                            if (j0 + (int64_t)k * 64 + lane < e && a[k] >= 0) {
+                                const uint32_t key = (uint32_t)a[k];
+                                uint32_t h = (key * 2654435761u) >> (32 - lg);
+                                for (;;) {  // the map has a slot for every entry of the row
+                                    const uint32_t prev = atomicCAS(&keys[h], kEmpty, key);
+                                    if (prev == kEmpty || prev == key) break;
+                                    h = (h + 1) & (cap - 1);
+                                }
+                                atomicAdd(&cnts[h], 1u);
+                            }
+                        }
+                    }
+                    wave_lds_sync();
+                    for (uint32_t k = (uint32_t)lane; k < cap; k += 64) {
+                        const uint32_t key = keys[k];
+                        if (key != kEmpty) {
+                            const int c = (int)cnts[k], sz = aggsize[key];
+                            if (better(c, sz, (int)key, bc, bs, ba)) {
+                                bc = c;
+                                bs = sz;
+                                ba = (int)key;
+                            }
+                        }
+                    }
+                    wave_lds_sync();
+                } else {
+                    for (int64_t c1 = s; c1 < e; c1 += 64) {
+                        const int64_t jj = c1 + lane;
+                        const int32_t a = jj < e ? label[col[jj]] : kPad;
+                        int cnt = 0;
+                        for (int64_t c2 = s; c2 < e; c2 += 64) {
+                            const int64_t j2 = c2 + lane;
+                            const int32_t a2 = j2 < e ? label[col[j2]] : kPad;
+                            for (int t = 0; t < 64; t++)
+                                cnt += (__builtin_amdgcn_readlane(a2, t) == a);
+                        }
+                        if (a >= 0) {
+                            const int sz = aggsize[a];
+                            if (better(cnt, sz, a, bc, bs, ba)) {
+                                bc = cnt;
+                                bs = sz;
+                                ba = a;
+                            }
+                        }
                     }
                 }
-            }
-            wave_lds_sync();
-            for (int k = lane; k < kP3Slots; k += 64) {
-                const uint32_t key = keys[k];
-                if (key != kEmpty) {
-                    const int c = (int)cnts[k], sz = aggsize[key];
-                    if (better(c, sz, (int)key, bc, bs, ba)) {
-                        bc = c;
-                        bs = sz;
-                        ba = (int)key;
-                    }
+                p3_reduce(bc, bs, ba);
+                if (lane == 0) {
+                    if (bc > 0)
+                        agg_out[v] = ba;
+                    else
+                        atomicOr(err, 1u);
                 }
             }
-            wave_lds_sync();
-        } else {
-            for (int64_t c1 = s; c1 < e; c1 += 64) {
-                const int64_t j = c1 + lane;
-                const int32_t a = j < e ? label[col[j]] : kPad;
-                int cnt = 0;
-                for (int64_t c2 = s; c2 < e; c2 += 64) {
-                    const int64_t j2 = c2 + lane;
-                    const int32_t a2 = j2 < e ? label[col[j2]] : kPad;
-                    for (int t = 0; t < 64; t++) cnt += (__builtin_amdgcn_readlane(a2, t) == a);
-                }
-                if (a >= 0) {
-                    const int sz = aggsize[a];
-                    if (better(cnt, sz, a, bc, bs, ba)) {
-                        bc = cnt;
-                        bs = sz;
-                        ba = a;
-                    }
-                }
-            }
-        }
-        p3_reduce(bc, bs, ba);
-        if (lane == 0) {
-            if (bc > 0)
-                agg_out[v] = ba;
-            else
-                atomicOr(err, 1u);
         }
     }
 }
@@ -573,8 +635,12 @@ hipError_t launch_label_roots(int64_t n, const int64_t *row_ptr, const int32_t *
 hipError_t launch_accept_phase2(int64_t n, const int64_t *row_ptr, const int32_t *col,
                                 const uint32_t *T, const int32_t *label, uint8_t *flag,
                                 hipStream_t s) {
-    hipLaunchKernelGGL(k_accept_phase2, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, n,
-                       row_ptr, col, T, label, flag);
+    if (4 * n < ((int64_t)1 << 32))
+        hipLaunchKernelGGL(k_accept_phase2<true>, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0,
+                           s, n, row_ptr, col, T, label, flag);
+    else
+        hipLaunchKernelGGL(k_accept_phase2<false>, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock),
+                           0, s, n, row_ptr, col, T, label, flag);
     return hipGetLastError();
 }
 
@@ -621,8 +687,8 @@ hipError_t launch_phase3(int lanes, int blocks, const int64_t *row_ptr, const in
                          const SegIO &io_long, int32_t *agg_out, uint32_t *err, hipStream_t s) {
     MIS2_P3_DISPATCH(lanes, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col, label, aggsize, io,
                      agg_out, err);
-    hipLaunchKernelGGL(k_phase3_long, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col, label,
-                       aggsize, io_long, agg_out, err);
+    hipLaunchKernelGGL(k_phase3_long, dim3(std::min(blocks, kP3LongBlocks)), dim3(kBlock), 0, s,
+                       row_ptr, col, label, aggsize, io_long, agg_out, err);
     return hipGetLastError();
 }
 
