@@ -183,6 +183,81 @@ def test_persistent_and_launched_rounds_agree(api):
     assert not any(r["kind"] == 2 for r in b.last_sweeps())
 
 
+def _hubs_graph(parts, seed=0):
+    """Disjoint complete bipartite components K_{m,L}.  In each, the id with
+    the smallest round-0 tuple (G6: priority hash of (seed, 0, v) above the id
+    bits) goes to a hub, so that hub is a phase-1 root, every leaf joins its
+    aggregate, and the other m - 1 hubs (rows of L entries, no unlabelled
+    neighbour) are left to phase 3."""
+    n = sum(m + L for m, L in parts)
+    b = oracle.id_bits(n)
+    t = np.array([oracle.pack(oracle.hash_priority(seed, 0, v), v, b) for v in range(n)],
+                 np.uint64)
+    src, dst = [], []
+    base = 0
+    for m, L in parts:
+        ids = np.arange(base, base + m + L)
+        first = ids[np.argmin(t[ids])]
+        rest = ids[ids != first]
+        hubs = np.concatenate([[first], rest[:m - 1]])
+        leaves = rest[m - 1:]
+        for h in hubs:
+            src += [h] * L + list(leaves)
+            dst += list(leaves) + [h] * L
+        base += m + L
+    a, c = np.array(src, np.int64), np.array(dst, np.int64)
+    o = np.lexsort((c, a))
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, a[o] + 1, 1)
+    return np.cumsum(rp), c[o].astype(np.int32)
+
+
+def _phase3_rows(rp, c, seed=0):
+    """Row lengths of the vertices still unlabelled after phase 2 (oracle)."""
+    n = rp.size - 1
+    r = oracle.aggregate(rp, c, seed, detail=True)["roots"]
+    src = np.repeat(np.arange(n), np.diff(rp))
+    lab = r == 1
+    lab[c[(r == 1)[src]]] = True
+    lab2 = lab | (r == 2)
+    lab2[c[(r == 2)[src] & ~lab[c]]] = True
+    return np.sort(np.diff(rp)[~lab2])
+
+
+def test_phase3_rows_of_every_map_size(api):
+    # phase-3 rows of 40, 300 and 2100 entries (coupling maps of 128 and 1024
+    # slots, and the whole-row count past 2048 entries), on the automatic grid
+    # and on grids wider than the resident long-row grid (several segments
+    # per wavefront)
+    rp, c = _hubs_graph([(4, 2100), (4, 300), (3, 40)])
+    assert list(_phase3_rows(rp, c)) == [40, 40, 300, 300, 300, 2100, 2100, 2100]
+    for blocks in (0, 2049, 8192):
+        _say("phase-3 map sizes, blocks", blocks)
+        _check_agg(api.Context(0, blocks=blocks), rp, c, 0, "hubs/%d" % blocks)
+    rp, c = dict(SMALL)["chunglu_50k"]
+    assert (_phase3_rows(rp, c) > 32).sum() > 100
+    for blocks in (2049, 8192):
+        _say("chunglu_50k phase 3, blocks", blocks)
+        _check_agg(api.Context(0, blocks=blocks), rp, c, 0, "chunglu_50k/%d" % blocks)
+
+
+def test_staged_plan_hands_sparse_rounds_to_four_lanes(api):
+    # on a graph with no row past 32 entries the staged plan runs its later
+    # rounds with the 4-lane kernels, once and for good; results unchanged
+    ctx = api.Context(0, lanes=-2)
+    rp, c = _c2()
+    _say("staged switch: 27-point 100^3")
+    _check_mis2(ctx, rp, c, 0, "c2")
+    lanes = [r["lanes"] for r in ctx.last_sweeps() if r["kind"] in (0, 1)]
+    k = lanes.index(4)
+    assert k >= 2 and set(lanes[:k]) == {-2} and set(lanes[k:]) == {4}, lanes
+    _check_agg(ctx, rp, c, 0, "c2")
+    # with long rows the plan stays staged
+    rp, c = dict(SMALL)["chunglu_50k"]
+    _check_mis2(ctx, rp, c, 0, "chunglu_50k")
+    assert {r["lanes"] for r in ctx.last_sweeps() if r["kind"] in (0, 1)} == {-2}
+
+
 def test_aggregate_empty(ctx):
     agg, na = ctx.aggregate(np.zeros(1, np.int64), np.zeros(0, np.int32))
     assert agg.numel() == 0 and na == 0
