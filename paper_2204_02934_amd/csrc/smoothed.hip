@@ -23,10 +23,11 @@
 // and after a prefix sum a fill pass lists the set's columns and places each
 // at its rank among them (so rows come out ascending).  A row with more than
 // kSetMax distinct columns sets an error flag.
-// Value (numeric) kernels: one thread per output entry, which finds its row
-// by binary search in the row offsets and folds its terms one after the
-// other in the stated order, each term one rounded product (the file is
-// compiled without contraction into fused multiply-adds).
+// Value (numeric) kernels: P one thread per entry, which finds its row by
+// binary search in the row offsets; AP and Ac one wavefront per output row
+// (see k_row_values).  Each entry folds its terms one after the other in the
+// stated order, each term one rounded product (the file is compiled without
+// contraction into fused multiply-adds).
 #include "internal.h"
 #include "lanes.h"
 
@@ -291,17 +292,6 @@ __device__ __forceinline__ int64_t row_of(const int64_t *ptr, int64_t rows, int6
     return lo;
 }
 
-// Position of column c in the ascending cols[lo, hi), or -1.
-__device__ __forceinline__ int64_t find_col(const int32_t *cols, int64_t lo, int64_t hi,
-                                            int32_t c) {
-    int64_t l = lo, h = hi;
-    while (l < h) {
-        const int64_t mid = l + (h - l) / 2;
-        if (cols[mid] < c) l = mid + 1; else h = mid;
-    }
-    return (l < hi && cols[l] == c) ? l : -1;
-}
-
 // P values, one thread per entry (see the file comment).
 __global__ __launch_bounds__(kBlock) void k_p_values(int64_t n, const int64_t *__restrict__ row_ptr,
                                                      const int32_t *__restrict__ col,
@@ -331,59 +321,173 @@ __global__ __launch_bounds__(kBlock) void k_p_values(int64_t n, const int64_t *_
     }
 }
 
-// AP values, one thread per entry.
-__global__ __launch_bounds__(kBlock) void k_ap_values(int64_t n, const int64_t *__restrict__ row_ptr,
-                                                      const int32_t *__restrict__ col,
-                                                      const double *__restrict__ val,
-                                                      const double *__restrict__ diag,
-                                                      const int64_t *__restrict__ prow,
-                                                      const int32_t *__restrict__ pcol,
-                                                      const double *__restrict__ pval,
-                                                      const int64_t *__restrict__ aptr,
-                                                      const int32_t *__restrict__ acol,
-                                                      double *__restrict__ aval) {
-    const int64_t nnz = aptr[n];
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nnz; q += stride) {
-        const int64_t i = row_of(aptr, n, q);
-        const int32_t b = acol[q];
-        double acc = 0.0;
-        int64_t p = find_col(pcol, prow[i], prow[i + 1], b);
-        if (p >= 0) acc = acc + diag[i] * pval[p];
-        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++) {
-            const int32_t j = col[e];
-            p = find_col(pcol, prow[j], prow[j + 1], b);
-            if (p >= 0) acc = acc + val[e] * pval[p];
-        }
-        aval[q] = acc;
+// AP and Ac values: one wavefront per output row.  An output entry (r, b)
+// is the sum, over the row's terms t in their stated order, of coef_t *
+// S[src_t][b] (skipped where S has no such entry).  The row's columns go to
+// LDS, 64 at a time (a slot pass); the terms go kVT at a time: each entry of
+// the chunk's source rows finds its column's slot by binary search and
+// writes its rounded product into a kVT x 64 table cleared to +0.0, and then
+// every lane folds its slot's column of the table in term order.  An absent
+// term reads +0.0, and adding +0.0 changes no sum that starts from +0.0 (such
+// a sum is never -0.0), so the result is that of skipping it.  Entries of a
+// term have distinct columns, so no two writes meet.
+constexpr int kVT = 16;           // terms per chunk
+constexpr int kVU = 4;            // staged entries per lane per step
+constexpr int kValThreads = 128;  // 2 wavefronts per workgroup (17.5 KB of LDS)
+
+struct ValLds {
+    double table[kVT][64];
+    double coef[kVT];
+    int64_t lo[kVT];        // first entry of each term's source row
+    uint32_t pre[kVT + 1];  // prefix of the chunk's source row lengths
+    int32_t outc[64];       // the slot pass's output columns
+};
+
+// Terms of AP row i: (i, d_i), then (j, A_ij) for row i's entries in CSR order.
+struct ApTerms {
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const double *val;
+    const double *diag;
+    struct Row {
+        int64_t r, base, count;
+    };
+    __device__ Row row(int64_t r) const {
+        const int64_t b = row_ptr[r];
+        return {r, b, 1 + row_ptr[r + 1] - b};
     }
+    __device__ void term(const Row &w, int64_t t, int64_t &src, double &coef) const {
+        if (t == 0) {
+            src = w.r;
+            coef = diag[w.r];
+        } else {
+            src = col[w.base + t - 1];
+            coef = val[w.base + t - 1];
+        }
+    }
+};
+
+// Terms of Ac row a: (i, P[i][a]) for the rows i holding P[i][a], increasing i.
+struct CTerms {
+    const int64_t *moff;
+    const int32_t *members;
+    const int32_t *prow_of;
+    const double *pval;
+    struct Row {
+        int64_t base, count;
+    };
+    __device__ Row row(int64_t a) const {
+        const int64_t b = moff[a];
+        return {b, moff[a + 1] - b};
+    }
+    __device__ void term(const Row &w, int64_t t, int64_t &src, double &coef) const {
+        const int32_t p = members[w.base + t];
+        src = prow_of[p];
+        coef = pval[p];
+    }
+};
+
+// Stages one chunk of tc <= kVT terms (lane t < tc holds term t's source row
+// start lo, length len and coefficient cf) into the table and folds it into
+// acc (lanes < ns).  Ends with the wavefront synchronised.
+__device__ __forceinline__ void fold_chunk(ValLds &sh, int lane, int tc, int64_t lo, uint32_t len,
+                                           double cf, int ns, int32_t cmin, int32_t cmax,
+                                           const int32_t *__restrict__ scol,
+                                           const double *__restrict__ sval, double &acc) {
+    const uint32_t incl = wave_incl_scan(len);
+    const uint32_t E = (uint32_t)__shfl((int)incl, 63, 64);
+    if (lane < tc) {
+        sh.lo[lane] = lo;
+        sh.coef[lane] = cf;
+        sh.pre[lane + 1] = incl;
+    }
+    if (lane == 0) sh.pre[0] = 0u;
+    for (int t = 0; t < tc; t++) sh.table[t][lane] = 0.0;
+    wave_sync_s();
+    for (uint32_t k0 = 0; k0 < E; k0 += 64 * kVU) {
+        // kVU entries per lane, every load issued before any is used (entries
+        // past E reread entry E - 1 and are dropped)
+        int tt[kVU];
+        int32_t c[kVU];
+        double v[kVU];
+#pragma unroll
+        for (int u = 0; u < kVU; u++) {
+            const uint32_t k = k0 + (uint32_t)(u * 64 + lane);
+            const uint32_t kk = k < E ? k : E - 1;
+            int lo_t = 0, hi_t = tc - 1;  // the term of entry kk: last t with pre[t] <= kk
+            while (lo_t < hi_t) {
+                const int mid = (lo_t + hi_t + 1) >> 1;
+                if (sh.pre[mid] <= kk) lo_t = mid; else hi_t = mid - 1;
+            }
+            const int64_t e = sh.lo[lo_t] + (int64_t)(kk - sh.pre[lo_t]);
+            tt[u] = k < E ? lo_t : -1;
+            c[u] = scol[e];
+            v[u] = sval[e];
+        }
+#pragma unroll
+        for (int u = 0; u < kVU; u++) {
+            if (tt[u] >= 0 && c[u] >= cmin && c[u] <= cmax) {
+                int l = 0, h = ns;  // its slot: the first output column >= c
+                while (l < h) {
+                    const int mid = (l + h) >> 1;
+                    if (sh.outc[mid] < c[u]) l = mid + 1; else h = mid;
+                }
+                if (l < ns && sh.outc[l] == c[u]) sh.table[tt[u]][l] = sh.coef[tt[u]] * v[u];
+            }
+        }
+    }
+    wave_sync_s();
+    if (lane < ns)
+        for (int t = 0; t < tc; t++) acc = acc + sh.table[t][lane];
+    wave_sync_s();
 }
 
-// Ac values, one thread per entry: rows of R_a in increasing id (members
-// hold P entry indices in increasing order, hence increasing row).
-__global__ __launch_bounds__(kBlock) void k_c_values(int64_t n_agg, const int64_t *__restrict__ moff,
-                                                     const int32_t *__restrict__ members,
-                                                     const int32_t *__restrict__ prow_of,
-                                                     const double *__restrict__ pval,
-                                                     const int64_t *__restrict__ aptr,
-                                                     const int32_t *__restrict__ acol,
-                                                     const double *__restrict__ aval,
-                                                     const int64_t *__restrict__ crow,
-                                                     const int32_t *__restrict__ ccol,
-                                                     double *__restrict__ cval) {
-    const int64_t nnz = crow[n_agg];
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nnz; q += stride) {
-        const int64_t a = row_of(crow, n_agg, q);
-        const int32_t b = ccol[q];
-        double acc = 0.0;
-        for (int64_t t = moff[a]; t < moff[a + 1]; t++) {
-            const int32_t p = members[t];
-            const int64_t i = prow_of[p];
-            const int64_t u = find_col(acol, aptr[i], aptr[i + 1], b);
-            if (u >= 0) acc = acc + pval[p] * aval[u];
+template <class Terms>
+__global__ __launch_bounds__(kValThreads) void k_row_values(
+    int64_t rows, Terms tm, const int64_t *__restrict__ sptr, const int32_t *__restrict__ scol,
+    const double *__restrict__ sval, const int64_t *__restrict__ optr,
+    const int32_t *__restrict__ ocol, double *__restrict__ oval) {
+    __shared__ ValLds sh_all[kValThreads / 64];
+    ValLds &sh = sh_all[threadIdx.x >> 6];
+    const int lane = (int)(threadIdx.x & 63u);
+    const int64_t W = (int64_t)gridDim.x * (kValThreads / 64);
+    for (int64_t r = (int64_t)blockIdx.x * (kValThreads / 64) + (threadIdx.x >> 6); r < rows;
+         r += W) {
+        const int64_t o0 = optr[r], m = optr[r + 1] - o0;
+        const typename Terms::Row w = tm.row(r);
+        for (int64_t s0 = 0; s0 < m; s0 += 64) {
+            const int ns = (int)min<int64_t>(64, m - s0);
+            const int32_t myc = lane < ns ? ocol[o0 + s0 + lane] : INT32_MAX;
+            const int32_t cmin = __shfl(myc, 0, 64), cmax = __shfl(myc, ns - 1, 64);
+            sh.outc[lane] = myc;
+            double acc = 0.0;
+            for (int64_t tb = 0; tb < w.count; tb += 64) {
+                // the source rows and coefficients of 64 terms, one per lane,
+                // in one round of loads; each chunk takes its own by shuffles
+                const int tn = (int)min<int64_t>(64, w.count - tb);
+                int64_t my_lo = 0;
+                uint32_t my_len = 0;
+                double my_cf = 0.0;
+                if (lane < tn) {
+                    int64_t src;
+                    tm.term(w, tb + lane, src, my_cf);
+                    my_lo = sptr[src];
+                    my_len = (uint32_t)(sptr[src + 1] - my_lo);
+                }
+                for (int c0 = 0; c0 < tn; c0 += kVT) {
+                    const int tc = min(kVT, tn - c0);
+                    // every lane shuffles (a lane that is switched off in a
+                    // shuffle cannot be read from), then lanes past tc drop it
+                    const int from = c0 + (lane < tc ? lane : 0);
+                    const int64_t lo = __shfl(my_lo, from, 64);
+                    const uint32_t len_from = (uint32_t)__shfl((int)my_len, from, 64);
+                    const double cf = __shfl(my_cf, from, 64);
+                    const uint32_t len = lane < tc ? len_from : 0u;
+                    fold_chunk(sh, lane, tc, lo, len, cf, ns, cmin, cmax, scol, sval, acc);
+                }
+            }
+            if (lane < ns) oval[o0 + s0 + lane] = acc;
         }
-        cval[q] = acc;
     }
 }
 
@@ -432,8 +536,9 @@ hipError_t launch_ap_values(int64_t n, int64_t ap_nnz, const int64_t *row_ptr, c
                             const int32_t *pcol, const double *pval, const int64_t *aptr,
                             const int32_t *acol, double *aval, hipStream_t s) {
     if (n <= 0 || ap_nnz <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ap_values, dim3(grid_of_s(ap_nnz, kBlock, 16384)), dim3(kBlock), 0, s, n,
-                       row_ptr, col, val, diag, prow, pcol, pval, aptr, acol, aval);
+    const ApTerms tm{row_ptr, col, val, diag};
+    hipLaunchKernelGGL(k_row_values<ApTerms>, dim3(grid_of_s(n, kValThreads / 64, 16384)),
+                       dim3(kValThreads), 0, s, n, tm, prow, pcol, pval, aptr, acol, aval);
     return hipGetLastError();
 }
 
@@ -442,8 +547,9 @@ hipError_t launch_c_values(int64_t n_agg, int64_t c_nnz, const int64_t *moff,
                            const int64_t *aptr, const int32_t *acol, const double *aval,
                            const int64_t *crow, const int32_t *ccol, double *cval, hipStream_t s) {
     if (n_agg <= 0 || c_nnz <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_c_values, dim3(grid_of_s(c_nnz, kBlock, 16384)), dim3(kBlock), 0, s,
-                       n_agg, moff, members, prow_of, pval, aptr, acol, aval, crow, ccol, cval);
+    const CTerms tm{moff, members, prow_of, pval};
+    hipLaunchKernelGGL(k_row_values<CTerms>, dim3(grid_of_s(n_agg, kValThreads / 64, 16384)),
+                       dim3(kValThreads), 0, s, n_agg, tm, aptr, acol, aval, crow, ccol, cval);
     return hipGetLastError();
 }
 
