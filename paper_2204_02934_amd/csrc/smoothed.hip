@@ -321,27 +321,42 @@ __global__ __launch_bounds__(kBlock) void k_p_values(int64_t n, const int64_t *_
     }
 }
 
-// AP and Ac values: one wavefront per output row.  An output entry (r, b)
-// is the sum, over the row's terms t in their stated order, of coef_t *
-// S[src_t][b] (skipped where S has no such entry).  The row's columns go to
-// LDS, 64 at a time (a slot pass); the terms go kVT at a time: each entry of
-// the chunk's source rows finds its column's slot by binary search and
-// writes its rounded product into a kVT x 64 table cleared to +0.0, and then
-// every lane folds its slot's column of the table in term order.  An absent
-// term reads +0.0, and adding +0.0 changes no sum that starts from +0.0 (such
-// a sum is never -0.0), so the result is that of skipping it.  Entries of a
-// term have distinct columns, so no two writes meet.
+// AP and Ac values: one group of G lanes per output row (G = 32 for AP,
+// whose rows are short, so a wavefront has two rows in flight; 64 for Ac).
+// An output entry (r, b) is the sum, over the row's terms t in their stated
+// order, of coef_t * S[src_t][b] (skipped where S has no such entry).  The
+// row's columns go to LDS, G at a time (a slot pass); the terms go kVT at a
+// time: each entry of the chunk's source rows finds its column's slot by
+// binary search and writes its rounded product into a kVT x G table cleared
+// to +0.0, and then every lane folds its slot's column of the table in term
+// order.  An absent term reads +0.0, and adding +0.0 changes no sum that
+// starts from +0.0 (such a sum is never -0.0), so the result is that of
+// skipping it.  Entries of a term have distinct columns, so no two writes
+// meet.
 constexpr int kVT = 16;           // terms per chunk
 constexpr int kVU = 4;            // staged entries per lane per step
-constexpr int kValThreads = 128;  // 2 wavefronts per workgroup (17.5 KB of LDS)
+constexpr int kValThreads = 128;  // 2 wavefronts per workgroup
 
+template <int G>
 struct ValLds {
-    double table[kVT][64];
+    double table[kVT][G];
     double coef[kVT];
     int64_t lo[kVT];        // first entry of each term's source row
     uint32_t pre[kVT + 1];  // prefix of the chunk's source row lengths
-    int32_t outc[64];       // the slot pass's output columns
+    int32_t outc[G];        // the slot pass's output columns
 };
+
+// Inclusive prefix sum over each aligned group of G lanes.
+template <int G>
+__device__ __forceinline__ uint32_t group_incl_scan(uint32_t x) {
+    const int gl = (int)(threadIdx.x & (G - 1));
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+        const uint32_t y = __shfl_up(x, (unsigned)d, G);
+        if (gl >= d) x += y;
+    }
+    return x;
+}
 
 // Terms of AP row i: (i, d_i), then (j, A_ij) for row i's entries in CSR order.
 struct ApTerms {
@@ -387,24 +402,26 @@ struct CTerms {
     }
 };
 
-// Stages one chunk of tc <= kVT terms (lane t < tc holds term t's source row
-// start lo, length len and coefficient cf) into the table and folds it into
-// acc (lanes < ns).  Ends with the wavefront synchronised.
-__device__ __forceinline__ void fold_chunk(ValLds &sh, int lane, int tc, int64_t lo, uint32_t len,
+// Stages one chunk of tc <= kVT terms (group lane t < tc holds term t's
+// source row start lo, length len and coefficient cf) into the table and
+// folds it into acc (group lanes < ns).  The group's lanes run it together;
+// LDS accesses are ordered for the whole wavefront.
+template <int G>
+__device__ __forceinline__ void fold_chunk(ValLds<G> &sh, int gl, int tc, int64_t lo, uint32_t len,
                                            double cf, int ns, int32_t cmin, int32_t cmax,
                                            const int32_t *__restrict__ scol,
                                            const double *__restrict__ sval, double &acc) {
-    const uint32_t incl = wave_incl_scan(len);
-    const uint32_t E = (uint32_t)__shfl((int)incl, 63, 64);
-    if (lane < tc) {
-        sh.lo[lane] = lo;
-        sh.coef[lane] = cf;
-        sh.pre[lane + 1] = incl;
+    const uint32_t incl = group_incl_scan<G>(len);
+    const uint32_t E = (uint32_t)__shfl((int)incl, G - 1, G);
+    if (gl < tc) {
+        sh.lo[gl] = lo;
+        sh.coef[gl] = cf;
+        sh.pre[gl + 1] = incl;
     }
-    if (lane == 0) sh.pre[0] = 0u;
-    for (int t = 0; t < tc; t++) sh.table[t][lane] = 0.0;
+    if (gl == 0) sh.pre[0] = 0u;
+    for (int t = 0; t < tc; t++) sh.table[t][gl] = 0.0;
     wave_sync_s();
-    for (uint32_t k0 = 0; k0 < E; k0 += 64 * kVU) {
+    for (uint32_t k0 = 0; k0 < E; k0 += G * kVU) {
         // kVU entries per lane, every load issued before any is used (entries
         // past E reread entry E - 1 and are dropped)
         int tt[kVU];
@@ -412,7 +429,7 @@ __device__ __forceinline__ void fold_chunk(ValLds &sh, int lane, int tc, int64_t
         double v[kVU];
 #pragma unroll
         for (int u = 0; u < kVU; u++) {
-            const uint32_t k = k0 + (uint32_t)(u * 64 + lane);
+            const uint32_t k = k0 + (uint32_t)(u * G + gl);
             const uint32_t kk = k < E ? k : E - 1;
             int lo_t = 0, hi_t = tc - 1;  // the term of entry kk: last t with pre[t] <= kk
             while (lo_t < hi_t) {
@@ -437,56 +454,58 @@ __device__ __forceinline__ void fold_chunk(ValLds &sh, int lane, int tc, int64_t
         }
     }
     wave_sync_s();
-    if (lane < ns)
-        for (int t = 0; t < tc; t++) acc = acc + sh.table[t][lane];
+    if (gl < ns)
+        for (int t = 0; t < tc; t++) acc = acc + sh.table[t][gl];
     wave_sync_s();
 }
 
-template <class Terms>
+template <int G, class Terms>
 __global__ __launch_bounds__(kValThreads) void k_row_values(
     int64_t rows, Terms tm, const int64_t *__restrict__ sptr, const int32_t *__restrict__ scol,
     const double *__restrict__ sval, const int64_t *__restrict__ optr,
     const int32_t *__restrict__ ocol, double *__restrict__ oval) {
-    __shared__ ValLds sh_all[kValThreads / 64];
-    ValLds &sh = sh_all[threadIdx.x >> 6];
-    const int lane = (int)(threadIdx.x & 63u);
-    const int64_t W = (int64_t)gridDim.x * (kValThreads / 64);
-    for (int64_t r = (int64_t)blockIdx.x * (kValThreads / 64) + (threadIdx.x >> 6); r < rows;
-         r += W) {
+    static_assert(G == 32 || G == 64, "a group is half or all of a wavefront");
+    __shared__ ValLds<G> sh_all[kValThreads / G];
+    ValLds<G> &sh = sh_all[threadIdx.x / G];
+    const int gl = (int)(threadIdx.x & (G - 1));
+    const int64_t NG = (int64_t)gridDim.x * (kValThreads / G);
+    for (int64_t r = (int64_t)blockIdx.x * (kValThreads / G) + threadIdx.x / G; r < rows;
+         r += NG) {
         const int64_t o0 = optr[r], m = optr[r + 1] - o0;
         const typename Terms::Row w = tm.row(r);
-        for (int64_t s0 = 0; s0 < m; s0 += 64) {
-            const int ns = (int)min<int64_t>(64, m - s0);
-            const int32_t myc = lane < ns ? ocol[o0 + s0 + lane] : INT32_MAX;
-            const int32_t cmin = __shfl(myc, 0, 64), cmax = __shfl(myc, ns - 1, 64);
-            sh.outc[lane] = myc;
+        for (int64_t s0 = 0; s0 < m; s0 += G) {
+            const int ns = (int)min<int64_t>(G, m - s0);
+            const int32_t myc = gl < ns ? ocol[o0 + s0 + gl] : INT32_MAX;
+            const int32_t cmin = __shfl(myc, 0, G), cmax = __shfl(myc, ns - 1, G);
+            sh.outc[gl] = myc;
             double acc = 0.0;
-            for (int64_t tb = 0; tb < w.count; tb += 64) {
-                // the source rows and coefficients of 64 terms, one per lane,
+            for (int64_t tb = 0; tb < w.count; tb += G) {
+                // the source rows and coefficients of G terms, one per lane,
                 // in one round of loads; each chunk takes its own by shuffles
-                const int tn = (int)min<int64_t>(64, w.count - tb);
+                const int tn = (int)min<int64_t>(G, w.count - tb);
                 int64_t my_lo = 0;
                 uint32_t my_len = 0;
                 double my_cf = 0.0;
-                if (lane < tn) {
+                if (gl < tn) {
                     int64_t src;
-                    tm.term(w, tb + lane, src, my_cf);
+                    tm.term(w, tb + gl, src, my_cf);
                     my_lo = sptr[src];
                     my_len = (uint32_t)(sptr[src + 1] - my_lo);
                 }
                 for (int c0 = 0; c0 < tn; c0 += kVT) {
                     const int tc = min(kVT, tn - c0);
-                    // every lane shuffles (a lane that is switched off in a
-                    // shuffle cannot be read from), then lanes past tc drop it
-                    const int from = c0 + (lane < tc ? lane : 0);
-                    const int64_t lo = __shfl(my_lo, from, 64);
-                    const uint32_t len_from = (uint32_t)__shfl((int)my_len, from, 64);
-                    const double cf = __shfl(my_cf, from, 64);
-                    const uint32_t len = lane < tc ? len_from : 0u;
-                    fold_chunk(sh, lane, tc, lo, len, cf, ns, cmin, cmax, scol, sval, acc);
+                    // every lane of the group shuffles (a lane that is switched
+                    // off in a shuffle cannot be read from), then lanes past tc
+                    // drop it
+                    const int from = c0 + (gl < tc ? gl : 0);
+                    const int64_t lo = __shfl(my_lo, from, G);
+                    const uint32_t len_from = (uint32_t)__shfl((int)my_len, from, G);
+                    const double cf = __shfl(my_cf, from, G);
+                    const uint32_t len = gl < tc ? len_from : 0u;
+                    fold_chunk<G>(sh, gl, tc, lo, len, cf, ns, cmin, cmax, scol, sval, acc);
                 }
             }
-            if (lane < ns) oval[o0 + s0 + lane] = acc;
+            if (gl < ns) oval[o0 + s0 + gl] = acc;
         }
     }
 }
@@ -537,7 +556,7 @@ hipError_t launch_ap_values(int64_t n, int64_t ap_nnz, const int64_t *row_ptr, c
                             const int32_t *acol, double *aval, hipStream_t s) {
     if (n <= 0 || ap_nnz <= 0) return hipSuccess;
     const ApTerms tm{row_ptr, col, val, diag};
-    hipLaunchKernelGGL(k_row_values<ApTerms>, dim3(grid_of_s(n, kValThreads / 64, 16384)),
+    hipLaunchKernelGGL((k_row_values<32, ApTerms>), dim3(grid_of_s(n, kValThreads / 32, 16384)),
                        dim3(kValThreads), 0, s, n, tm, prow, pcol, pval, aptr, acol, aval);
     return hipGetLastError();
 }
@@ -548,7 +567,7 @@ hipError_t launch_c_values(int64_t n_agg, int64_t c_nnz, const int64_t *moff,
                            const int64_t *crow, const int32_t *ccol, double *cval, hipStream_t s) {
     if (n_agg <= 0 || c_nnz <= 0) return hipSuccess;
     const CTerms tm{moff, members, prow_of, pval};
-    hipLaunchKernelGGL(k_row_values<CTerms>, dim3(grid_of_s(n_agg, kValThreads / 64, 16384)),
+    hipLaunchKernelGGL((k_row_values<64, CTerms>), dim3(grid_of_s(n_agg, kValThreads / 64, 16384)),
                        dim3(kValThreads), 0, s, n_agg, tm, aptr, acol, aval, crow, ccol, cval);
     return hipGetLastError();
 }
