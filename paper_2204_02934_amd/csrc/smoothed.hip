@@ -23,9 +23,8 @@
 // and after a prefix sum a fill pass lists the set's columns and places each
 // at its rank among them (so rows come out ascending).  A row with more than
 // kSetMax distinct columns sets an error flag.
-// Value (numeric) kernels: P one thread per entry, which finds its row by
-// binary search in the row offsets; AP and Ac one wavefront per output row
-// (see k_row_values).  Each entry folds its terms one after the other in the
+// Value (numeric) kernels: P one group of lanes per row (k_p_values); AP
+// and Ac one group per output row (k_row_values).  Each entry folds its terms one after the other in the
 // stated order, each term one rounded product (the file is compiled without
 // contraction into fused multiply-adds).
 #include "internal.h"
@@ -282,17 +281,12 @@ __global__ __launch_bounds__(SMALL ? kSmallThreads : kSThreads) void k_sym(SymAr
     }
 }
 
-// Row of entry e in a CSR of `rows` rows: the last r with ptr[r] <= e.
-__device__ __forceinline__ int64_t row_of(const int64_t *ptr, int64_t rows, int64_t e) {
-    int64_t lo = 0, hi = rows - 1;
-    while (lo < hi) {
-        const int64_t mid = lo + (hi - lo + 1) / 2;
-        if (ptr[mid] <= e) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
+// P values: one group of kPG lanes per row i, one lane per entry (i, a) of
+// P's row (kPG at a time).  The row of A goes kPG entries at a time, each
+// lane loading one entry's aggregate and value; the group then folds them in
+// CSR order by shuffles, every lane adding the entries of its own aggregate.
+constexpr int kPG = 8;
 
-// P values, one thread per entry (see the file comment).
 __global__ __launch_bounds__(kBlock) void k_p_values(int64_t n, const int64_t *__restrict__ row_ptr,
                                                      const int32_t *__restrict__ col,
                                                      const double *__restrict__ val,
@@ -303,21 +297,42 @@ __global__ __launch_bounds__(kBlock) void k_p_values(int64_t n, const int64_t *_
                                                      const int32_t *__restrict__ pcol,
                                                      double *__restrict__ pval,
                                                      int32_t *__restrict__ prow_of) {
-    const int64_t nnz = prow[n];
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < nnz; p += stride) {
-        const int64_t i = row_of(prow, n, p);
-        const int32_t a = pcol[p];
-        double s = 0.0;
-        if (agg[i] == a) s = s + diag[i];
-        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++)
-            if (agg[col[e]] == a) s = s + val[e];
-        const double w = omega / diag[i];
-        const double ind = agg[i] == a ? 1.0 : 0.0;
-        const double t = w * s;
-        const double r = ind - t;
-        pval[p] = r / sqrt((double)size[a]);
-        prow_of[p] = (int32_t)i;
+    const int gl = (int)(threadIdx.x & (kPG - 1));
+    const int64_t NG = (int64_t)gridDim.x * (kBlock / kPG);
+    for (int64_t i = (int64_t)blockIdx.x * (kBlock / kPG) + threadIdx.x / kPG; i < n; i += NG) {
+        const int64_t p0 = prow[i], pm = prow[i + 1] - p0;
+        const int64_t rs = row_ptr[i], re = row_ptr[i + 1];
+        const int32_t ai = agg[i];
+        const double di = diag[i];
+        for (int64_t s0 = 0; s0 < pm; s0 += kPG) {
+            const bool mine = s0 + gl < pm;
+            const int32_t a = mine ? pcol[p0 + s0 + gl] : -1;
+            double sum = 0.0;
+            if (ai == a) sum = sum + di;
+            for (int64_t e0 = rs; e0 < re; e0 += kPG) {
+                const int cnt = (int)min<int64_t>(kPG, re - e0);
+                int32_t ag = -1;
+                double v = 0.0;
+                if (gl < cnt) {
+                    ag = agg[col[e0 + gl]];
+                    v = val[e0 + gl];
+                }
+                // every lane of the group runs the shuffles
+                for (int t = 0; t < cnt; t++) {
+                    const int32_t at = __shfl(ag, t, kPG);
+                    const double vt = __shfl(v, t, kPG);
+                    if (at == a) sum = sum + vt;
+                }
+            }
+            if (mine) {
+                const double w = omega / di;
+                const double ind = ai == a ? 1.0 : 0.0;
+                const double t = w * sum;
+                const double r = ind - t;
+                pval[p0 + s0 + gl] = r / sqrt((double)size[a]);
+                prow_of[p0 + s0 + gl] = (int32_t)i;
+            }
+        }
     }
 }
 
@@ -545,7 +560,7 @@ hipError_t launch_p_values(int64_t n, int64_t p_nnz, const int64_t *row_ptr, con
                            const uint32_t *size, double omega, const int64_t *prow,
                            const int32_t *pcol, double *pval, int32_t *prow_of, hipStream_t s) {
     if (n <= 0 || p_nnz <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_p_values, dim3(grid_of_s(p_nnz, kBlock, 16384)), dim3(kBlock), 0, s, n,
+    hipLaunchKernelGGL(k_p_values, dim3(grid_of_s(n, kBlock / kPG, 16384)), dim3(kBlock), 0, s, n,
                        row_ptr, col, val, diag, agg, size, omega, prow, pcol, pval, prow_of);
     return hipGetLastError();
 }
