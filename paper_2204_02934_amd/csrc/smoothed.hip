@@ -44,6 +44,7 @@ constexpr int kSThreads = 128;      // large-set pass: 2 wavefronts per workgrou
 constexpr int kSWaves = kSThreads / 64;
 constexpr int kSmallThreads = 256;  // small-set pass: 4 wavefronts per workgroup (17 KB)
 constexpr int32_t kEmpty = -1;
+constexpr int kSU = 4;              // candidates per lane whose loads go out together
 
 int grid_of_s(int64_t work, int per_block, int cap) {
     const int64_t b = (work + per_block - 1) / per_block;
@@ -181,16 +182,29 @@ __device__ uint32_t insert_row(Set &sh, const SymArgs &a, int64_t r, bool *full)
             if (lane == 0) sh.src_end[0] = 0;
             wave_sync_s();
             const int64_t total = sh.src_end[64];
-            for (int64_t k0 = 0; k0 < total; k0 += 64) {
-                const int64_t k = k0 + lane;
-                if (k < total) {
-                    // the source holding candidate k: last q with src_end[q] <= k
+            for (int64_t k0 = 0; k0 < total; k0 += 64 * kSU) {
+                // kSU candidates per lane, every load issued before any insert
+                // (candidates past the total reread the last one and are dropped)
+                int32_t cand[kSU];
+                bool ok[kSU];
+#pragma unroll
+                for (int u = 0; u < kSU; u++) {
+                    const int64_t k = k0 + u * 64 + lane;
+                    ok[u] = k < total;
+                    const int64_t kk = ok[u] ? k : total - 1;
+                    // the source holding candidate kk: last q with src_end[q] <= kk
                     int q = 0;
                     for (int step = 32; step > 0; step >>= 1)
-                        if (q + step <= 63 && sh.src_end[q + step] <= k) q += step;
-                    const int rc = set_insert(sh, a.scol[sh.src_lo[q] + (k - sh.src_end[q])]);
-                    added += rc == 1;
-                    ovf |= rc == 2;
+                        if (q + step <= 63 && sh.src_end[q + step] <= kk) q += step;
+                    cand[u] = a.scol[sh.src_lo[q] + (kk - sh.src_end[q])];
+                }
+#pragma unroll
+                for (int u = 0; u < kSU; u++) {
+                    if (ok[u]) {
+                        const int rc = set_insert(sh, cand[u]);
+                        added += rc == 1;
+                        ovf |= rc == 2;
+                    }
                 }
             }
             wave_sync_s();
