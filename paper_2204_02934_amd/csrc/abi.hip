@@ -214,6 +214,14 @@ int32_t parse_trace(mis2_ctx *ctx, int phase) {
 
 constexpr int kFallBack = 1;
 
+// Round 0 of an unmasked run on one graph of at least kGenMinN vertices
+// computes its neighbours' tuples rather than gathering them (the tuples are
+// a pure function of the id).  Measured on gfx950 (mis2_run +
+// mis2_aggregate): Chung-Lu 4M 12.42 -> 11.63 ms; 7-point 100^3 0.617 ->
+// 0.611 ms; 27-point 100^3, staged sweeps, 1.053 -> 1.073 ms (its T, 4 MB,
+// stays in the L2s, so a gather costs less than the hash).
+constexpr int64_t kGenMinN = (int64_t)1 << 21;
+
 RoundsArgs round_args(const mis2_ctx *ctx, const mis2_graph *g, uint64_t seed,
                       const Workspace &ws, const Geometry &gm, bool masked,
                       unsigned long long *degs, int lanes);
@@ -310,6 +318,9 @@ RoundsArgs round_args(const mis2_ctx *ctx, const mis2_graph *g, uint64_t seed,
     a.b = tp.b;
     a.masked = masked ? 1 : 0;
     a.max_rounds = kTraceCap;
+    // round 0's tuples computed in place of gathered where T outgrows the L2
+    // of an XCD (4 MB); on smaller graphs the gathers hit and the hash costs more
+    a.gen0 = g->n >= kGenMinN ? 1 : 0;
     // compacted Refresh Column rows (L-lane sweeps only; the flat sweeps
     // read the CSR as given)
     if (ws.colc && ws.lenc && lanes > 0 && ctx->plan.compact && g->nnz > 0) {

@@ -224,6 +224,11 @@ struct SegIO {
     // (stride kCtrLine), or null.
     uint32_t *long_flag;
     int64_t nnz;  // entries of the CSR (the staged sweeps' 16-byte loads stay below it)
+    // Refresh Column of round 0 of an unmasked run on one graph: every tuple
+    // is still make_tuple(t0, u), so the sweep computes the neighbours'
+    // tuples instead of gathering them from T (gen0 true).
+    bool gen0;
+    TupleParams t0;
 };
 
 // Arguments of the persistent round kernel.  bar: [kMaxBlocks] per-workgroup
@@ -256,6 +261,7 @@ struct RoundsArgs {
     int32_t *lenc;   // [n] their lengths
     uint32_t *lflag; // [kSplit][kCtrLine] set by round 0 when a row is long (zero at the start)
     int abl;         // ablation kernels only: kAblFixed | kAblXorshift
+    int gen0;        // 1: round 0's Refresh Column may compute the tuples it would gather
     int64_t n, seg, S;
     int64_t nnz;
     uint64_t seed, pmask;

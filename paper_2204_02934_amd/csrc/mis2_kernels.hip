@@ -223,7 +223,8 @@ constexpr int kCoopLoads = 8;  // loads per lane per cooperative step
 // count.
 __device__ __forceinline__ uint32_t coop_min_T(const int32_t *col, const uint32_t *__restrict__ T,
                                                int64_t s, int64_t e, int32_t *out = nullptr,
-                                               uint32_t *written = nullptr) {
+                                               uint32_t *written = nullptr,
+                                               const SegIO *gio = nullptr) {
     const int lane = (int)(threadIdx.x & 63u);
     uint32_t m = kOut;
     uint32_t wc = 0;
@@ -235,8 +236,13 @@ __device__ __forceinline__ uint32_t coop_min_T(const int32_t *col, const uint32_
             x[k] = col[j < e ? j : s];  // entry s exists: the row is not empty
         }
         uint32_t t[kCoopLoads];
+        if (gio && gio->gen0) {
 #pragma unroll
-        for (int k = 0; k < kCoopLoads; k++) t[k] = T[x[k]];
+            for (int k = 0; k < kCoopLoads; k++) t[k] = make_tuple(gio->t0, (uint32_t)x[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < kCoopLoads; k++) t[k] = T[x[k]];
+        }
 #pragma unroll
         for (int k = 0; k < kCoopLoads; k++)
             if (b + (int64_t)k * 64 + lane < e) m = min(m, t[k]);
@@ -364,9 +370,9 @@ __device__ __forceinline__ uint32_t sweep_column(const int64_t *__restrict__ row
                 const int64_t hs = __shfl(s[u], src, 64), he = __shfl(e[u], src, 64);
                 uint32_t hm, hw = 0;
                 if (RD && __shfl((int)cf[u], src, 64) != 0)
-                    hm = coop_min_T(colc, T, hs, he, wout, &hw);
+                    hm = coop_min_T(colc, T, hs, he, wout, &hw, &io);
                 else
-                    hm = coop_min_T(col, T, hs, he, wout, &hw);
+                    hm = coop_min_T(col, T, hs, he, wout, &hw, &io);
                 if (WR && lane == 0) wsum += hw;
                 if ((lane & ~(L - 1)) == (src & ~(L - 1))) {
                     m[u] = (sub == 0) ? min(m[u], hm) : kOut;
@@ -402,10 +408,17 @@ __device__ __forceinline__ uint32_t sweep_column(const int64_t *__restrict__ row
                 fetched = true;
             }
             uint32_t t[U][K];
+            if (io.gen0) {
 #pragma unroll
-            for (int u = 0; u < U; u++)
+                for (int u = 0; u < U; u++)
 #pragma unroll
-                for (int k = 0; k < K; k++) t[u][k] = T[x[u][k]];
+                    for (int k = 0; k < K; k++) t[u][k] = make_tuple(io.t0, (uint32_t)x[u][k]);
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; u++)
+#pragma unroll
+                    for (int k = 0; k < K; k++) t[u][k] = T[x[u][k]];
+            }
 #pragma unroll
             for (int u = 0; u < U; u++)
 #pragma unroll
@@ -735,9 +748,9 @@ __device__ __forceinline__ uint32_t sweep_column_staged(const int64_t *__restric
             const int64_t hs = __shfl(s, src, 64), he = __shfl(e, src, 64);
             uint32_t hm, hw = 0;
             if (RD && __shfl(cf, src, 64) != 0)
-                hm = coop_min_T(colc, T, hs, he, wout, &hw);
+                hm = coop_min_T(colc, T, hs, he, wout, &hw, &io);
             else
-                hm = coop_min_T(col, T, hs, he, wout, &hw);
+                hm = coop_min_T(col, T, hs, he, wout, &hw, &io);
             if (WR && lane == 0) wsum += hw;
             if ((lane & ~(H - 1)) == src) {
                 m = min(m, hm);
@@ -771,8 +784,13 @@ __device__ __forceinline__ uint32_t sweep_column_staged(const int64_t *__restric
                 x[u] = k < len ? y : v[0];
             }
             uint32_t t[kStagedUnroll];
+            if (io.gen0) {
 #pragma unroll
-            for (int u = 0; u < kStagedUnroll; u++) t[u] = T[x[u]];
+                for (int u = 0; u < kStagedUnroll; u++) t[u] = make_tuple(io.t0, (uint32_t)x[u]);
+            } else {
+#pragma unroll
+                for (int u = 0; u < kStagedUnroll; u++) t[u] = T[x[u]];
+            }
 #pragma unroll
             for (int u = 0; u < kStagedUnroll; u++) m = min(m, t[u]);
         }
@@ -1002,7 +1020,8 @@ __device__ __forceinline__ uint32_t flat_column(const int64_t *__restrict__ row_
         while (heavy) {
             const int src = __ffsll((unsigned long long)heavy) - 1;
             heavy &= heavy - 1;
-            const uint32_t hm = coop_min_T(col, T, __shfl(s, src, 64), __shfl(e, src, 64));
+            const uint32_t hm =
+                coop_min_T(col, T, __shfl(s, src, 64), __shfl(e, src, 64), nullptr, nullptr, &io);
             if (lane == src) m = min(m, hm);
         }
         uint32_t total;
@@ -1023,8 +1042,13 @@ __device__ __forceinline__ uint32_t flat_column(const int64_t *__restrict__ row_
                 x[j] = col[f < total ? sh.start[r] + (int64_t)(f - sh.off[r]) : 0];
             }
             uint32_t t[kFlatEP];
+            if (io.gen0) {
 #pragma unroll
-            for (int j = 0; j < kFlatEP; j++) t[j] = T[x[j]];
+                for (int j = 0; j < kFlatEP; j++) t[j] = make_tuple(io.t0, (uint32_t)x[j]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < kFlatEP; j++) t[j] = T[x[j]];
+            }
             uint32_t part = kOut;
             int pr = rr[0];
 #pragma unroll
@@ -1218,6 +1242,10 @@ __device__ __forceinline__ SegIO round_col_io(const RoundsArgs &a, int r) {
     io.S = a.S;
     io.nnz = a.nnz;
     if (r == 0 && !a.masked) io.long_flag = a.lflag;
+    if (r == 0 && a.gen0 && !a.masked && !a.batch.voff && !a.abl) {
+        io.gen0 = true;
+        io.t0 = TupleParams{xs64star(a.seed << 32), a.pmask, a.b, a.batch};
+    }
     return io;
 }
 
@@ -1282,13 +1310,16 @@ __device__ __forceinline__ void round_start(const RoundsArgs &a, int r) {
     clear_slot(a.ctr, r);
 }
 
-template <int L, bool RD, bool WR>
+// GEN: the kernel that may compute round 0's tuples (k_col_round0); the
+// others never do, so the code that would is compiled out of them.
+template <int L, bool RD, bool WR, bool GEN = false>
 __device__ __forceinline__ void col_round(const int64_t *__restrict__ row_ptr,
                                           const int32_t *__restrict__ col,
                                           const uint32_t *__restrict__ T, uint32_t *__restrict__ M,
                                           const RoundsArgs &a, int r) {
     round_start(a, r);
     SegIO io = round_col_io(a, r);
+    if (!GEN) io.gen0 = false;
     if (RD) {
         io.ccol_in = a.colc;
         io.lenc_in = a.lenc;
@@ -1310,6 +1341,17 @@ __global__ __launch_bounds__(kBlock) void k_col_round(const int64_t *__restrict_
                                                       uint32_t *__restrict__ M, RoundsArgs a,
                                                       int r) {
     col_round<L, false, false>(row_ptr, col, T, M, a, r);
+}
+
+// Round 0: computes the neighbours' tuples where that is exact (unmasked,
+// one graph), else gathers them as k_col_round does.
+template <int L>
+__global__ __launch_bounds__(kBlock) void k_col_round0(const int64_t *__restrict__ row_ptr,
+                                                       const int32_t *__restrict__ col,
+                                                       const uint32_t *__restrict__ T,
+                                                       uint32_t *__restrict__ M, RoundsArgs a,
+                                                       int r) {
+    col_round<L, false, false, true>(row_ptr, col, T, M, a, r);
 }
 
 // The first compacting round: reads the CSR's rows, writes compacted ones.
@@ -1778,7 +1820,8 @@ __global__ __launch_bounds__(kBlock) void k_rounds(const int64_t *__restrict__ r
     }
     for (;;) {
         uint32_t *slot_next = a.ctr + (size_t)((r + 1) % kCtrRing) * kCtrSlot;
-        const SegIO cio = round_col_io(a, r);
+        SegIO cio = round_col_io(a, r);
+        cio.gen0 = false;  // the persistent kernel gathers in every round
         clear_slot(a.ctr, r);
         uint32_t *row_cur = a.rt + (size_t)r * kRoundStride;
         if (blockIdx.x == 0 && threadIdx.x == 0) stamp(row_cur + kRtStamp0);
@@ -2190,6 +2233,9 @@ hipError_t launch_col_round(int lanes, int blocks, const int64_t *row_ptr, const
                                  row_ptr, col, T, M, a, r);
     } else if (mode == 2) {
         MIS2_LANE_DISPATCH_TIMED(lanes, k_col_round_rw, dim3(blocks), dim3(kBlock), s, e0, e1,
+                                 row_ptr, col, T, M, a, r);
+    } else if (r == 0) {
+        MIS2_LANE_DISPATCH_TIMED(lanes, k_col_round0, dim3(blocks), dim3(kBlock), s, e0, e1,
                                  row_ptr, col, T, M, a, r);
     } else {
         MIS2_LANE_DISPATCH_TIMED(lanes, k_col_round, dim3(blocks), dim3(kBlock), s, e0, e1,

@@ -258,6 +258,24 @@ def test_staged_plan_hands_sparse_rounds_to_four_lanes(api):
     assert {r["lanes"] for r in ctx.last_sweeps() if r["kind"] in (0, 1)} == {-2}
 
 
+def test_round0_computed_tuples_every_sweep_form(api):
+    # a graph of at least 2^21 vertices: round 0's Refresh Column computes the
+    # neighbours' tuples instead of gathering them, in each sweep form (lanes
+    # per row, staged, flat) and in the whole-wavefront path of the hub's row
+    rp, c = graphs.disjoint_union([graphs.grid2d_5pt(1500, 1500), graphs.star(5000, 0)])
+    assert rp.size - 1 >= 1 << 21
+    o = oracle.mis2_ex(rp, c, 3)
+    d = oracle.aggregate(rp, c, 3, detail=True)
+    for lanes in (1, 4, -2, -1):
+        _say("computed round-0 tuples, lanes", lanes)
+        ctx = api.Context(0, lanes=lanes)
+        status, nr, it = ctx.mis2(rp, c, 3)
+        assert np.array_equal(status.cpu().numpy(), o["status"]), lanes
+        assert it == o["n_iters"] and np.array_equal(ctx.last_trace(0), o["trace"][:, :2])
+        agg, na = ctx.aggregate(rp, c, 3)
+        assert na == d["n_agg"] and np.array_equal(agg.cpu().numpy(), d["agg"]), lanes
+
+
 def test_aggregate_empty(ctx):
     agg, na = ctx.aggregate(np.zeros(1, np.int64), np.zeros(0, np.int32))
     assert agg.numel() == 0 and na == 0
