@@ -90,7 +90,9 @@ extern "C" {
                                      its class (half octave of n and degree histogram), timed
                                      once per class and device on its first sight in the
                                      process (candidates in a fixed order; a later one wins
-                                     only when at least 1% faster); 2: the plan of a class tuned before in the
+                                     only when at least 1% faster, the last one, the fastest
+                                     with the one-workgroup tail, when no slower); 2: the
+                                     plan of a class tuned before in the
                                      process, never a tuning run (a class not seen yet takes
                                      the degree rule); 0: the fixed degree rule.  Plans never
                                      change results. */
