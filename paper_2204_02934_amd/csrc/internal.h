@@ -229,6 +229,10 @@ struct SegIO {
     // tuples instead of gathering them from T (gen0 true).
     bool gen0;
     TupleParams t0;
+    // Decide Set of round 0: no vertex is IN yet, so no M is OUT and a row
+    // whose own M differs from its tuple stays undecided without reading its
+    // neighbours (dec0 true).
+    bool dec0;
 };
 
 // Arguments of the persistent round kernel.  bar: [kMaxBlocks] per-workgroup

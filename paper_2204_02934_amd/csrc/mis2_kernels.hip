@@ -507,8 +507,9 @@ __device__ __forceinline__ uint32_t sweep_decide(const int64_t *__restrict__ row
             any_out[u] = (sub == 0) & (mv[u] == kOut);
             all_eq[u] = (sub != 0) | (mv[u] == t0[u]);
             if (sub == 0) dsum += (unsigned long long)(e[u] - s[u]);
-            // M_v = OUT already decides the row (OUT), whatever the neighbours hold
-            if (mv[u] == kOut) e[u] = s[u];
+            // M_v = OUT already decides the row (OUT), whatever the neighbours
+            // hold; in round 0, M_v != T_v keeps it undecided
+            if (mv[u] == kOut || (io.dec0 && mv[u] != t0[u])) e[u] = s[u];
         }
         // high-degree rows: the whole wavefront streams each one in turn
 #pragma unroll
@@ -851,8 +852,9 @@ __device__ __forceinline__ uint32_t sweep_decide_staged(const int64_t *__restric
         int any_out = (sub == 0) & (mv == kOut);
         int all_eq = (sub != 0) | (mv == t0);
         if (sub == 0) dsum += (unsigned long long)(e - s);
-        // M_v = OUT already decides the row (OUT), whatever the neighbours hold
-        if (mv == kOut) e = s;
+        // M_v = OUT already decides the row (OUT), whatever the neighbours
+        // hold; in round 0, M_v != T_v keeps it undecided
+        if (mv == kOut || (io.dec0 && mv != t0)) e = s;
         uint64_t heavy = __ballot(sub == 0 && e - s > kStagedCap);
         while (heavy) {
             const int src = __ffsll((unsigned long long)heavy) - 1;
@@ -1100,8 +1102,9 @@ __device__ __forceinline__ uint32_t flat_decide(const int64_t *__restrict__ row_
         int any_out = mv == kOut;
         int all_eq = mv == t0;
         dsum += (unsigned long long)(ok ? e - s : 0);
-        // M_v = OUT already decides the row (OUT), whatever the neighbours hold
-        const int64_t len = ok && mv != kOut ? e - s : 0;
+        // M_v = OUT already decides the row (OUT), whatever the neighbours
+        // hold; in round 0, M_v != T_v keeps it undecided
+        const int64_t len = ok && mv != kOut && !(io.dec0 && mv != t0) ? e - s : 0;
         uint64_t heavy = __ballot(len > kFlatHeavy);
         while (heavy) {
             const int src = __ffsll((unsigned long long)heavy) - 1;
@@ -1263,6 +1266,7 @@ __device__ __forceinline__ SegIO round_dec_io(const RoundsArgs &a, int r) {
     io.seg = a.seg;
     io.S = a.S;
     io.nnz = a.nnz;
+    io.dec0 = r == 0;
     return io;
 }
 
