@@ -318,8 +318,9 @@ RoundsArgs round_args(const mis2_ctx *ctx, const mis2_graph *g, uint64_t seed,
     a.b = tp.b;
     a.masked = masked ? 1 : 0;
     a.max_rounds = kTraceCap;
-    // round 0's tuples computed in place of gathered where T outgrows the L2
-    // of an XCD (4 MB); on smaller graphs the gathers hit and the hash costs more
+    // rounds 0 and 1 compute their tuples in place of gathering them where T
+    // outgrows the L2 of an XCD (4 MB); on smaller graphs the gathers hit and
+    // the hash costs more
     a.gen0 = g->n >= kGenMinN ? 1 : 0;
     // compacted Refresh Column rows (L-lane sweeps only; the flat sweeps
     // read the CSR as given)
@@ -507,6 +508,10 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
                                               a, round, mode, s, lc.e0, lc.e1));
                 HIP_TRY(ctx, launch_dec_round(rl, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
                                               a, round, s, ld.e0, ld.e1));
+                // round 1's Refresh Column computes its tuples once the IN
+                // vertices have marked their neighbourhoods
+                if (round == 0 && a.gen0 && !masked && !a.batch.voff)
+                    HIP_TRY(ctx, launch_push_in(g->n, g->row_ptr, g->col, ws.T, ws.M, s));
             }
             launches->push_back(lc);
             launches->push_back(ld);

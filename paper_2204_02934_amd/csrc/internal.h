@@ -224,10 +224,14 @@ struct SegIO {
     // (stride kCtrLine), or null.
     uint32_t *long_flag;
     int64_t nnz;  // entries of the CSR (the staged sweeps' 16-byte loads stay below it)
-    // Refresh Column of round 0 of an unmasked run on one graph: every tuple
-    // is still make_tuple(t0, u), so the sweep computes the neighbours'
-    // tuples instead of gathering them from T (gen0 true).
-    bool gen0;
+    // Refresh Column of rounds 0 and 1 of an unmasked run on one graph: a
+    // neighbour's tuple is computed, make_tuple(t0, u), instead of gathered
+    // from T.  gen0 1 (round 0): every tuple is still that.  2 (round 1):
+    // round 0's Decide Set made no vertex OUT, and every IN vertex has set M
+    // to OUT on itself and its neighbours since (k_push_in); a row with M
+    // OUT keeps M OUT, any other has no IN neighbour, so all its
+    // neighbours' tuples are round 1's function of the id.
+    int gen0;
     TupleParams t0;
     // Decide Set of round 0: no vertex is IN yet, so no M is OUT and a row
     // whose own M differs from its tuple stays undecided without reading its
@@ -265,7 +269,7 @@ struct RoundsArgs {
     int32_t *lenc;   // [n] their lengths
     uint32_t *lflag; // [kSplit][kCtrLine] set by round 0 when a row is long (zero at the start)
     int abl;         // ablation kernels only: kAblFixed | kAblXorshift
-    int gen0;        // 1: round 0's Refresh Column may compute the tuples it would gather
+    int gen0;        // 1: rounds 0 and 1 of Refresh Column may compute the tuples they gather
     int64_t n, seg, S;
     int64_t nnz;
     uint64_t seed, pmask;
@@ -402,6 +406,10 @@ hipError_t launch_abl_round(int kind, bool unpacked, bool all, int blocks,
 hipError_t launch_col_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                             const uint32_t *T, uint32_t *M, const RoundsArgs &a, int r, int mode,
                             hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+// M = OUT on every IN vertex of T and on its neighbours (after round 0's
+// Decide Set, for round 1's computed tuples).
+hipError_t launch_push_in(int64_t n, const int64_t *row_ptr, const int32_t *col, const uint32_t *T,
+                          uint32_t *M, hipStream_t s);
 hipError_t launch_dec_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                             uint32_t *T, const uint32_t *M, const RoundsArgs &a, int r,
                             hipStream_t s, hipEvent_t e0, hipEvent_t e1);

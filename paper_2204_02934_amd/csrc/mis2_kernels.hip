@@ -439,6 +439,7 @@ __device__ __forceinline__ uint32_t sweep_column(const int64_t *__restrict__ row
             m[u] = group_min<L>(m[u]);
             bool keep = false;
             if (ok[u] && sub == 0) {
+                if (io.gen0 == 2 && M[v[u]] == kOut) m[u] = kOut;  // pushed by an IN vertex
                 if (m[u] == kIn) m[u] = kOut;
                 M[v[u]] = m[u];
                 keep = (m[u] != kOut);
@@ -798,6 +799,7 @@ __device__ __forceinline__ uint32_t sweep_column_staged(const int64_t *__restric
         m = group_min<H>(m);
         bool keep = false;
         if (ok[0] && sub == 0) {
+            if (io.gen0 == 2 && M[v[0]] == kOut) m = kOut;  // pushed by an IN vertex
             if (m == kIn) m = kOut;
             M[v[0]] = m;
             keep = (m != kOut);
@@ -1070,6 +1072,7 @@ __device__ __forceinline__ uint32_t flat_column(const int64_t *__restrict__ row_
         if (me >= 0) m = min(m, sh.acc[me]);
         bool keep = false;
         if (ok) {
+            if (io.gen0 == 2 && M[v] == kOut) m = kOut;  // pushed by an IN vertex
             if (m == kIn) m = kOut;
             M[v] = m;
             keep = (m != kOut);
@@ -1245,9 +1248,9 @@ __device__ __forceinline__ SegIO round_col_io(const RoundsArgs &a, int r) {
     io.S = a.S;
     io.nnz = a.nnz;
     if (r == 0 && !a.masked) io.long_flag = a.lflag;
-    if (r == 0 && a.gen0 && !a.masked && !a.batch.voff && !a.abl) {
-        io.gen0 = true;
-        io.t0 = TupleParams{xs64star(a.seed << 32), a.pmask, a.b, a.batch};
+    if (r <= 1 && a.gen0 && !a.masked && !a.batch.voff && !a.abl) {
+        io.gen0 = r + 1;
+        io.t0 = TupleParams{xs64star((a.seed << 32) ^ (uint64_t)r), a.pmask, a.b, a.batch};
     }
     return io;
 }
@@ -1314,8 +1317,9 @@ __device__ __forceinline__ void round_start(const RoundsArgs &a, int r) {
     clear_slot(a.ctr, r);
 }
 
-// GEN: the kernel that may compute round 0's tuples (k_col_round0); the
-// others never do, so the code that would is compiled out of them.
+// GEN: the kernel that may compute the tuples of rounds 0 and 1
+// (k_col_round0); the others never do, so the code that would is compiled
+// out of them.
 template <int L, bool RD, bool WR, bool GEN = false>
 __device__ __forceinline__ void col_round(const int64_t *__restrict__ row_ptr,
                                           const int32_t *__restrict__ col,
@@ -1323,7 +1327,7 @@ __device__ __forceinline__ void col_round(const int64_t *__restrict__ row_ptr,
                                           const RoundsArgs &a, int r) {
     round_start(a, r);
     SegIO io = round_col_io(a, r);
-    if (!GEN) io.gen0 = false;
+    if (!GEN) io.gen0 = 0;
     if (RD) {
         io.ccol_in = a.colc;
         io.lenc_in = a.lenc;
@@ -1347,8 +1351,9 @@ __global__ __launch_bounds__(kBlock) void k_col_round(const int64_t *__restrict_
     col_round<L, false, false>(row_ptr, col, T, M, a, r);
 }
 
-// Round 0: computes the neighbours' tuples where that is exact (unmasked,
-// one graph), else gathers them as k_col_round does.
+// Rounds 0 and 1: computes the neighbours' tuples where that is exact
+// (unmasked, one graph; round 1 after k_push_in), else gathers them as
+// k_col_round does.
 template <int L>
 __global__ __launch_bounds__(kBlock) void k_col_round0(const int64_t *__restrict__ row_ptr,
                                                        const int32_t *__restrict__ col,
@@ -1825,7 +1830,7 @@ __global__ __launch_bounds__(kBlock) void k_rounds(const int64_t *__restrict__ r
     for (;;) {
         uint32_t *slot_next = a.ctr + (size_t)((r + 1) % kCtrRing) * kCtrSlot;
         SegIO cio = round_col_io(a, r);
-        cio.gen0 = false;  // the persistent kernel gathers in every round
+        cio.gen0 = 0;  // the persistent kernel gathers in every round
         clear_slot(a.ctr, r);
         uint32_t *row_cur = a.rt + (size_t)r * kRoundStride;
         if (blockIdx.x == 0 && threadIdx.x == 0) stamp(row_cur + kRtStamp0);
@@ -1910,6 +1915,21 @@ __global__ __launch_bounds__(kBlock) void k_init_masked(TupleParams tp, int64_t 
         seg_append(io, sg, act, (int32_t)v, kept);
     }
     seg_finish(io, w, kept);
+}
+
+// M[v] = OUT for every v with T_v = IN and for its neighbours: one lane per
+// vertex, which walks the row of an IN vertex (IN vertices are few).  Writes
+// that meet store the same value.
+__global__ __launch_bounds__(kBlock) void k_push_in(int64_t n, const int64_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ col,
+                                                    const uint32_t *__restrict__ T,
+                                                    uint32_t *__restrict__ M) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += stride) {
+        if (T[v] != kIn) continue;
+        M[v] = kOut;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) M[col[e]] = kOut;
+    }
 }
 
 // status[v] = (T_v == IN); the tile's IN count goes to blocksum[tile] (tiles
@@ -2228,6 +2248,14 @@ TupleParams tuple_params(int64_t n, uint64_t seed, uint64_t iter) {
         MIS2_LANE_DISPATCH(L, KERNEL, GRID, BLOCK, 0, S, __VA_ARGS__);                  \
     }
 
+hipError_t launch_push_in(int64_t n, const int64_t *row_ptr, const int32_t *col, const uint32_t *T,
+                          uint32_t *M, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_push_in, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, n, row_ptr,
+                       col, T, M);
+    return hipGetLastError();
+}
+
 hipError_t launch_col_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                             const uint32_t *T, uint32_t *M, const RoundsArgs &a, int r, int mode,
                             hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
@@ -2238,7 +2266,7 @@ hipError_t launch_col_round(int lanes, int blocks, const int64_t *row_ptr, const
     } else if (mode == 2) {
         MIS2_LANE_DISPATCH_TIMED(lanes, k_col_round_rw, dim3(blocks), dim3(kBlock), s, e0, e1,
                                  row_ptr, col, T, M, a, r);
-    } else if (r == 0) {
+    } else if (r <= 1) {
         MIS2_LANE_DISPATCH_TIMED(lanes, k_col_round0, dim3(blocks), dim3(kBlock), s, e0, e1,
                                  row_ptr, col, T, M, a, r);
     } else {
