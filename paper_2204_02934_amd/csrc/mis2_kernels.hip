@@ -660,13 +660,15 @@ __device__ __forceinline__ v4i32 load4_clamped(const int32_t *p, int64_t j, int6
 
 // Copies the column indices of the step's rows into their LDS slots: groups
 // of 4 lanes take one row each (16 rows per pass), `chunks` (1 or 2)
-// 16-byte loads per lane, 16 entries per chunk.  Row r's start s is held by
-// lane r * H; cf (same lanes) selects the compacted copy.  Entries past a
-// row's end are written too and never read.
+// 16-byte loads per lane, 16 entries per chunk.  Row r's start s and length
+// len are held by lane r * H; cf (same lanes) selects the compacted copy.  A
+// chunk is loaded only when the row reaches into it (a row of length 0, one
+// that needs no scan, loads nothing); entries past a row's end are written
+// too and never read.
 template <int H>
 __device__ __forceinline__ void stage_rows(StagedLds<H> &sh, const int32_t *col,
-                                           const int32_t *colc, const int64_t s, const int cf,
-                                           int chunks, int64_t nnz) {
+                                           const int32_t *colc, const int64_t s, const int len,
+                                           const int cf, int chunks, int64_t nnz) {
     constexpr int R = 64 / H;
     const int lane = (int)(threadIdx.x & 63u);
     const int sub = lane & 3;
@@ -674,15 +676,16 @@ __device__ __forceinline__ void stage_rows(StagedLds<H> &sh, const int32_t *col,
     for (int g = 0; g < R / 16; g++) {
         const int rr = g * 16 + (lane >> 2);
         const int64_t sr = __shfl(s, rr * H, 64);
+        const int rlen = __shfl(len, rr * H, 64);
         const int rcf = __shfl(cf, rr * H, 64);
         const int32_t *src = rcf ? colc : col;
         v4i32 x[2];
 #pragma unroll
         for (int c = 0; c < 2; c++)
-            if (c < chunks) x[c] = load4_clamped(src, sr + c * 16 + sub * 4, nnz);
+            if (c < chunks && rlen > c * 16) x[c] = load4_clamped(src, sr + c * 16 + sub * 4, nnz);
 #pragma unroll
         for (int c = 0; c < 2; c++) {
-            if (c < chunks) {
+            if (c < chunks && rlen > c * 16) {
                 int32_t *d = &sh.idx[rr * kStagedStride + c * 16 + sub * 4];
                 d[0] = x[c].x;
                 d[1] = x[c].y;
@@ -763,7 +766,7 @@ __device__ __forceinline__ uint32_t sweep_column_staged(const int64_t *__restric
         }
         const int len = (int)(e - s);
         const int maxlen = (int)group_max<64>((uint32_t)len);
-        if (maxlen > 0) stage_rows<H>(sh, col, colc, s, cf, maxlen > 16 ? 2 : 1, io.nnz);
+        if (maxlen > 0) stage_rows<H>(sh, col, colc, s, len, cf, maxlen > 16 ? 2 : 1, io.nnz);
         // the next rows' extents and own values load while this step's
         // gathers are in flight
         int64_t sn = 0, en = 0;
@@ -875,7 +878,7 @@ __device__ __forceinline__ uint32_t sweep_decide_staged(const int64_t *__restric
         }
         const int len = (int)(e - s);
         const int maxlen = (int)group_max<64>((uint32_t)len);
-        if (maxlen > 0) stage_rows<H>(sh, col, col, s, 0, maxlen > 16 ? 2 : 1, io.nnz);
+        if (maxlen > 0) stage_rows<H>(sh, col, col, s, len, 0, maxlen > 16 ? 2 : 1, io.nnz);
         int64_t sn = 0, en = 0;
         uint32_t tn = 0, mvn = 0;
         if (more) {
