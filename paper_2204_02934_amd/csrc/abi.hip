@@ -322,6 +322,7 @@ RoundsArgs round_args(const mis2_ctx *ctx, const mis2_graph *g, uint64_t seed,
     // outgrows the L2 of an XCD (4 MB); on smaller graphs the gathers hit and
     // the hash costs more
     a.gen0 = g->n >= kGenMinN ? 1 : 0;
+    a.near = ws.near;
     // compacted Refresh Column rows (L-lane sweeps only; the flat sweeps
     // read the CSR as given)
     if (ws.colc && ws.lenc && lanes > 0 && ctx->plan.compact && g->nnz > 0) {
@@ -353,6 +354,8 @@ FillSpans round_fills(const mis2_graph *g, const Workspace &ws, bool masked) {
           (int64_t)(masked ? kCtrRing - 1 : kCtrRing) * kCtrSlot);
     if (!masked) f.add(ws.rt, (uint32_t)g->n, 2);
     if (!masked) f.add(ws.lflag, 0u, (int64_t)kSplit * kCtrLine);
+    // round 1's marks start clear (set after round 0)
+    if (!masked && g->n >= kGenMinN && ws.near) f.add((uint32_t *)ws.near, 0u, (g->n + 3) / 4);
     return f;
 }
 
@@ -509,9 +512,14 @@ int run_rounds(mis2_ctx *ctx, const mis2_graph *g, uint64_t seed, const Workspac
                 HIP_TRY(ctx, launch_dec_round(rl, gm.blocks, g->row_ptr, g->col, ws.T, ws.M,
                                               a, round, s, ld.e0, ld.e1));
                 // round 1's Refresh Column computes its tuples once the IN
-                // vertices have marked their neighbourhoods
-                if (round == 0 && a.gen0 && !masked && !a.batch.voff)
+                // vertices have marked their neighbourhoods, and its Decide
+                // Set reads the marks of their neighbours
+                if (round == 0 && a.gen0 && !masked && !a.batch.voff) {
                     HIP_TRY(ctx, launch_push_in(g->n, g->row_ptr, g->col, ws.T, ws.M, s));
+                    if (ws.near)
+                        HIP_TRY(ctx,
+                                launch_push_near(g->n, g->row_ptr, g->col, ws.M, ws.near, s));
+                }
             }
             launches->push_back(lc);
             launches->push_back(ld);
@@ -896,6 +904,7 @@ size_t workspace_bytes(int64_t n, int op) {
     const size_t un = (size_t)n;
     size_t b = 0;
     b += align_up(4 * un) * 2;                          // T, M
+    b += align_up(un);                                  // near (round 1 of large graphs)
     b += align_up(4 * un) * 4;                          // wl1[2], wl2[2]
     b += align_up(4 * (size_t)kMaxWaves) * 4;           // cnt1[2], cnt2[2]
     b += align_up(4 * (size_t)(kTraceCap + 2) * kRoundStride);  // round table
@@ -933,6 +942,7 @@ bool carve(void *base, size_t bytes, int64_t n, int op, Workspace *ws) {
     };
     ws->T = (uint32_t *)take(4 * un);
     ws->M = (uint32_t *)take(4 * un);
+    ws->near = (uint8_t *)take(un);
     ws->wl1[0] = (int32_t *)take(4 * un);
     ws->wl1[1] = (int32_t *)take(4 * un);
     ws->wl2[0] = (int32_t *)take(4 * un);

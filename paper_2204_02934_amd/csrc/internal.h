@@ -117,6 +117,7 @@ constexpr int kMaxWaves = kMaxBlocks * (kBlock / 64);
 struct Workspace {
     uint32_t *T = nullptr;        // [n] packed row status tuples
     uint32_t *M = nullptr;        // [n] radius-1 minima
+    uint8_t *near = nullptr;      // [n] 1: within distance 2 of an IN vertex of round 0 (k_push_near)
     int32_t *wl1[2] = {};         // [n] undecided vertices (per-wave segments), double buffered
     int32_t *wl2[2] = {};         // [n] vertices without an IN neighbour, double buffered
     uint32_t *cnt1[2] = {};       // [kMaxWaves] per-wave sizes of wl1[i]
@@ -237,6 +238,12 @@ struct SegIO {
     // whose own M differs from its tuple stays undecided without reading its
     // neighbours (dec0 true).
     bool dec0;
+    // Decide Set of round 1 after k_push_near (dec1 true): a neighbour's M is
+    // OUT exactly when an IN vertex of round 0 lies within distance 2, which
+    // near[v] records, so a row whose own M differs from its tuple (it
+    // cannot join) reads near[v] instead of its neighbours.
+    bool dec1;
+    const uint8_t *near;
 };
 
 // Arguments of the persistent round kernel.  bar: [kMaxBlocks] per-workgroup
@@ -270,6 +277,7 @@ struct RoundsArgs {
     uint32_t *lflag; // [kSplit][kCtrLine] set by round 0 when a row is long (zero at the start)
     int abl;         // ablation kernels only: kAblFixed | kAblXorshift
     int gen0;        // 1: rounds 0 and 1 of Refresh Column may compute the tuples they gather
+    uint8_t *near;   // Workspace::near
     int64_t n, seg, S;
     int64_t nnz;
     uint64_t seed, pmask;
@@ -410,6 +418,10 @@ hipError_t launch_col_round(int lanes, int blocks, const int64_t *row_ptr, const
 // Decide Set, for round 1's computed tuples).
 hipError_t launch_push_in(int64_t n, const int64_t *row_ptr, const int32_t *col, const uint32_t *T,
                           uint32_t *M, hipStream_t s);
+// near = 1 on every vertex whose M is OUT (after launch_push_in: the IN
+// vertices of round 0 and their neighbours) and on its neighbours.
+hipError_t launch_push_near(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                            const uint32_t *M, uint8_t *near, hipStream_t s);
 hipError_t launch_dec_round(int lanes, int blocks, const int64_t *row_ptr, const int32_t *col,
                             uint32_t *T, const uint32_t *M, const RoundsArgs &a, int r,
                             hipStream_t s, hipEvent_t e0, hipEvent_t e1);

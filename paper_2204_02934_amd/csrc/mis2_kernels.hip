@@ -511,6 +511,11 @@ __device__ __forceinline__ uint32_t sweep_decide(const int64_t *__restrict__ row
             // M_v = OUT already decides the row (OUT), whatever the neighbours
             // hold; in round 0, M_v != T_v keeps it undecided
             if (mv[u] == kOut || (io.dec0 && mv[u] != t0[u])) e[u] = s[u];
+            // in round 1, near[v] stands for the neighbours' OUT test
+            if (io.dec1 && ok[u] && mv[u] != kOut && mv[u] != t0[u]) {
+                any_out[u] = (sub == 0) & (io.near[v[u]] != 0);
+                e[u] = s[u];
+            }
         }
         // high-degree rows: the whole wavefront streams each one in turn
 #pragma unroll
@@ -860,6 +865,11 @@ __device__ __forceinline__ uint32_t sweep_decide_staged(const int64_t *__restric
         // M_v = OUT already decides the row (OUT), whatever the neighbours
         // hold; in round 0, M_v != T_v keeps it undecided
         if (mv == kOut || (io.dec0 && mv != t0)) e = s;
+        // in round 1, near[v] stands for the neighbours' OUT test
+        if (io.dec1 && ok[0] && mv != kOut && mv != t0) {
+            any_out = (sub == 0) & (io.near[v[0]] != 0);
+            e = s;
+        }
         uint64_t heavy = __ballot(sub == 0 && e - s > kStagedCap);
         while (heavy) {
             const int src = __ffsll((unsigned long long)heavy) - 1;
@@ -1107,10 +1117,13 @@ __device__ __forceinline__ uint32_t flat_decide(const int64_t *__restrict__ row_
         const uint32_t mv = M[v];
         int any_out = mv == kOut;
         int all_eq = mv == t0;
+        // in round 1, near[v] stands for the neighbours' OUT test
+        const bool by_near = io.dec1 && ok && mv != kOut && mv != t0;
+        if (by_near) any_out = io.near[v] != 0;
         dsum += (unsigned long long)(ok ? e - s : 0);
         // M_v = OUT already decides the row (OUT), whatever the neighbours
         // hold; in round 0, M_v != T_v keeps it undecided
-        const int64_t len = ok && mv != kOut && !(io.dec0 && mv != t0) ? e - s : 0;
+        const int64_t len = ok && mv != kOut && !(io.dec0 && mv != t0) && !by_near ? e - s : 0;
         uint64_t heavy = __ballot(len > kFlatHeavy);
         while (heavy) {
             const int src = __ffsll((unsigned long long)heavy) - 1;
@@ -1273,6 +1286,10 @@ __device__ __forceinline__ SegIO round_dec_io(const RoundsArgs &a, int r) {
     io.S = a.S;
     io.nnz = a.nnz;
     io.dec0 = r == 0;
+    if (r == 1 && a.gen0 && !a.masked && !a.batch.voff && !a.abl && a.near) {
+        io.dec1 = true;
+        io.near = a.near;
+    }
     return io;
 }
 
@@ -1845,7 +1862,8 @@ __global__ __launch_bounds__(kBlock) void k_rounds(const int64_t *__restrict__ r
         if (a.dsplit && blockIdx.x == 0 && threadIdx.x < 64)
             fold_deg(a.dsplit + (size_t)kSplit * kDegLine, a.degs + kDegStride * r + 1,
                      a.degs + kDegStride * r + 2);
-        const SegIO dio = round_dec_io(a, r);
+        SegIO dio = round_dec_io(a, r);
+        dio.dec1 = false;  // the persistent kernel runs no k_push_near
         const TupleParams next{xs64star((a.seed << 32) ^ (uint64_t)(r + 1)), a.pmask, a.b, a.batch};
         sg = seg_of(dio, w);
         kept = any_decide<L>(row_ptr, col, T, M, next, dio, sg);
@@ -1932,6 +1950,32 @@ __global__ __launch_bounds__(kBlock) void k_push_in(int64_t n, const int64_t *__
         if (T[v] != kIn) continue;
         M[v] = kOut;
         for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) M[col[e]] = kOut;
+    }
+}
+
+// near = 1 on every vertex whose M is OUT and on its neighbours.  A
+// wavefront takes 64 vertices at a time and writes the rows of the marked
+// ones, one after another, 64 entries per step, so a long row (a hub next to
+// an IN vertex) costs its length / 64 steps and is walked once.
+__global__ __launch_bounds__(kBlock) void k_push_near(int64_t n, const int64_t *__restrict__ row_ptr,
+                                                      const int32_t *__restrict__ col,
+                                                      const uint32_t *__restrict__ M,
+                                                      uint8_t *__restrict__ near) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const int64_t W = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * 64; base < n;
+         base += W * 64) {
+        const int64_t v = base + lane;
+        const bool mark = v < n && M[v] == kOut;
+        if (mark) near[v] = 1;
+        uint64_t todo = __ballot(mark);
+        while (todo) {
+            const int j = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            const int64_t u = base + j;
+            const int64_t s = row_ptr[u], e = row_ptr[u + 1];
+            for (int64_t k = s + lane; k < e; k += 64) near[col[k]] = 1;
+        }
     }
 }
 
@@ -2256,6 +2300,14 @@ hipError_t launch_push_in(int64_t n, const int64_t *row_ptr, const int32_t *col,
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_push_in, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, n, row_ptr,
                        col, T, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_push_near(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                            const uint32_t *M, uint8_t *near, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_push_near, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, n,
+                       row_ptr, col, M, near);
     return hipGetLastError();
 }
 
