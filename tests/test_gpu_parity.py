@@ -261,9 +261,10 @@ def test_staged_plan_hands_sparse_rounds_to_four_lanes(api):
 def test_round0_computed_tuples_every_sweep_form(api):
     # a graph of at least 2^21 vertices: rounds 0 and 1 of Refresh Column
     # compute the neighbours' tuples instead of gathering them (round 1 after
-    # the IN vertices have marked their neighbourhoods), in each sweep form
-    # (lanes per row, staged, flat) and in the whole-wavefront path of the
-    # hub's row
+    # the IN vertices have marked their neighbourhoods), and round 1's Decide
+    # Set reads the two-hop marks for rows that cannot join, in each sweep
+    # form (lanes per row, staged, flat) and in the whole-wavefront path of
+    # the hub's row
     rp, c = graphs.disjoint_union([graphs.grid2d_5pt(1500, 1500), graphs.star(5000, 0)])
     assert rp.size - 1 >= 1 << 21
     o = oracle.mis2_ex(rp, c, 3)
