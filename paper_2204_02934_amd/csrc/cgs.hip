@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_pos(int64_t n, const int32_t
 // ---- apply ----------------------------------------------------------------
 //
 // One wavefront per cluster.  The cluster's rows are taken in batches of at
-// most 64 rows of at most 64 entries each and kCgsCap entries in all; lane k
+// most 64 rows of at most 64 entries each and Cap entries in all; lane k
 // holds the batch's k-th row.  The batch is staged in LDS in parallel: for
 // each entry (row order, then CSR order) either the product a_ij * x_j with
 // index kOne (x_j is final for this pass when j is not a row of the batch:
@@ -241,13 +241,17 @@ __global__ __launch_bounds__(kBlock) void k_scatter_pos(int64_t n, const int32_t
 // 64 entries is a batch of its own, read from global memory in pieces of 64
 // (no row of its batch but itself, and it has no self-loop).
 constexpr int kCgsWaves = kBlock / 64;
-constexpr int kCgsCap = 512;
-constexpr int kCgsU = kCgsCap / 64;
 constexpr int kOne = 64;
+// 256 entries per batch and 8 waves per SIMD (the most a SIMD holds): on the
+// 27-point and 7-point 100^3 plans, 384, 512, 768 and 1024 entries at the
+// occupancy their LDS allows (7, 6, 4, 3 waves) all sweep slower
+constexpr int kCgsLaunchCap = 256;
+constexpr int kCgsLaunchWaves = 8;
 
+template <int Cap>
 struct CgsStage {
-    double v[kCgsCap + 64];  // 64 spare entries: reads past a batch's end stay inside
-    uint8_t tag[kCgsCap + 64];
+    double v[Cap + 64];  // 64 spare entries: reads past a batch's end stay inside
+    uint8_t tag[Cap + 64];
     double xb[65];
     int64_t rs[64];
     int32_t off[65];
@@ -289,8 +293,10 @@ __device__ __forceinline__ double chain_w(double acc, double term) {
     return acc;
 }
 
-// (6 waves per SIMD keep every cluster of a colour of up to 6144 resident)
-__global__ __launch_bounds__(kBlock, 6) void k_cgs_cluster(const int64_t *__restrict__ row_ptr,
+// Cap: LDS entries per batch; MinW: waves per SIMD that the LDS of a wave
+// (about 9 bytes per entry) still allows
+template <int Cap, int MinW>
+__global__ __launch_bounds__(kBlock, MinW) void k_cgs_cluster(const int64_t *__restrict__ row_ptr,
                                                         const int32_t *__restrict__ col,
                                                         const double *__restrict__ val,
                                                         const double *__restrict__ diag,
@@ -300,9 +306,10 @@ __global__ __launch_bounds__(kBlock, 6) void k_cgs_cluster(const int64_t *__rest
                                                         const int64_t *__restrict__ cluster_off,
                                                         int64_t k0, int64_t k1, int backward) {
 #pragma clang fp contract(off)
-    __shared__ CgsStage stage[kCgsWaves];
+    constexpr int kCgsCap = Cap, kCgsU = Cap / 64;
+    __shared__ CgsStage<Cap> stage[kCgsWaves];
     const int lane = threadIdx.x & 63;
-    CgsStage &S = stage[threadIdx.x >> 6];
+    CgsStage<Cap> &S = stage[threadIdx.x >> 6];
     const int64_t k = k0 + (int64_t)blockIdx.x * kCgsWaves + (threadIdx.x >> 6);
     if (k >= k1) return;
     const int64_t r0 = cluster_off[k], r1 = cluster_off[k + 1], m = r1 - r0;
@@ -324,7 +331,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_cgs_cluster(const int64_t *__rest
         // to kCgsCap are used, and those are exact
         const int64_t incl =
             (int64_t)wave_incl_scan((uint32_t)(len < kCgsCap + 1 ? len : kCgsCap + 1));
-        // rows before the first one longer than 64, within kCgsCap entries
+        // rows before the first one longer than 64, within Cap entries
         const uint64_t longm = __ballot(valid && len > 64);
         const int first_long = longm ? __ffsll((unsigned long long)longm) - 1 : 64;
         int nb = __popcll(__ballot(valid && incl <= kCgsCap));
@@ -607,8 +614,9 @@ hipError_t launch_cgs_sweep(const int64_t *row_ptr, const int32_t *col, const do
     if (k1 <= k0) return hipSuccess;
     const int64_t blocks = (k1 - k0 + kCgsWaves - 1) / kCgsWaves;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_cgs_cluster, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col,
-                       val, diag, b, x, rows, pos, cluster_off, k0, k1, backward ? 1 : 0);
+    hipLaunchKernelGGL((k_cgs_cluster<kCgsLaunchCap, kCgsLaunchWaves>), dim3((unsigned)blocks),
+                       dim3(kBlock), 0, s, row_ptr, col, val, diag, b, x, rows, pos, cluster_off,
+                       k0, k1, backward ? 1 : 0);
     return hipGetLastError();
 }
 
