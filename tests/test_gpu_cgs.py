@@ -38,6 +38,11 @@ GRAPHS = {
     "edgeless50": lambda: graphs.edgeless(50),
     "union": lambda: graphs.disjoint_union([graphs.grid2d_5pt(10, 10), graphs.complete(9),
                                             graphs.edgeless(5), graphs.path(17)]),
+    # the cluster sweep's batch limits: rows of exactly 64 entries (K65), rows
+    # of 65 (K66, each a batch of its own) and 17 rows of 16 (K17: the first
+    # batch holds exactly 256 entries, the last row starts a second)
+    "cliques": lambda: graphs.disjoint_union([graphs.complete(65), graphs.complete(66),
+                                              graphs.complete(17)]),
 }
 
 
