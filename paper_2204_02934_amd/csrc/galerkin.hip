@@ -31,7 +31,11 @@ namespace mis2 {
 
 namespace {
 
-constexpr int kGCap = 511;  // coarse columns of a row held in LDS
+// coarse columns of a row held in LDS: 17 KB per 4-wave block, so registers
+// (69 VGPRs, 7 waves per SIMD) rather than LDS set the occupancy; 511 columns
+// (30 KB, 5 waves) took 9% longer on the 27-point 100^3 aggregation, whose
+// coarse rows have at most 29 columns
+constexpr int kGCap = 255;
 constexpr int kGWaves = kBlock / 64;
 
 struct GStage {
