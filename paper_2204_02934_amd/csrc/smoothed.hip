@@ -362,7 +362,10 @@ __global__ __launch_bounds__(kBlock) void k_p_values(int64_t n, const int64_t *_
 // starts from +0.0 (such a sum is never -0.0), so the result is that of
 // skipping it.  Entries of a term have distinct columns, so no two writes
 // meet.
-constexpr int kVT = 16;           // terms per chunk
+// terms per chunk: 12 leaves a 32-lane group's table small enough (14 KB per
+// workgroup) for registers, not LDS, to set the occupancy (5 waves per SIMD
+// against 4 at 16 terms); the sums are the same term by term for any chunk
+constexpr int kVT = 12;
 constexpr int kVU = 4;            // staged entries per lane per step
 constexpr int kValThreads = 128;  // 2 wavefronts per workgroup
 
