@@ -220,8 +220,10 @@ __device__ uint32_t insert_row(Set &sh, const SymArgs &a, int64_t r, bool *full)
 // pass.  Else: the large set over the rows marked 1 (64 marks read at a
 // time over rows spread across all wavefronts); a row with more than
 // kSetMax columns sets the error flag.
+// (the small-set pass asks for 8 workgroups per CU, 8 waves per SIMD: its LDS
+// allows them, and the register cap, 64, spills nothing)
 template <int K, bool FILL, bool SMALL>
-__global__ __launch_bounds__(SMALL ? kSmallThreads : kSThreads) void k_sym(SymArgs a) {
+__global__ __launch_bounds__(SMALL ? kSmallThreads : kSThreads, SMALL ? 8 : 1) void k_sym(SymArgs a) {
     constexpr int CAP = SMALL ? kSmallCap : kSetCap;
     constexpr int MAX = SMALL ? kSmallMax : kSetMax;
     constexpr int WAVES = (SMALL ? kSmallThreads : kSThreads) / 64;
