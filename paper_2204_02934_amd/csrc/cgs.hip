@@ -367,8 +367,10 @@ __global__ __launch_bounds__(kBlock, MinW) void k_cgs_cluster(const int64_t *__r
         if (lane == 0) S.off[0] = 0;
         wave_sync();
         // stage the batch's entries, all of a lane's loads in flight at once
-        // (slots past tot re-read entry 0 and store nothing)
-        {
+        // (slots past tot re-read entry 0 and store nothing).  A batch with no
+        // entries (rows without off-diagonal entries) loads nothing: its rows'
+        // CSR starts may equal nnz, one past the last entry
+        if (tot > 0) {
             int64_t pp[kCgsU];
 #pragma unroll
             for (int c = 0; c < kCgsU; c++) {

@@ -43,6 +43,8 @@ GRAPHS = {
     # batch holds exactly 256 entries, the last row starts a second)
     "cliques": lambda: graphs.disjoint_union([graphs.complete(65), graphs.complete(66),
                                               graphs.complete(17)]),
+    # isolated vertices last: their CSR start is nnz, which no load may use
+    "isolated_last": lambda: graphs.disjoint_union([graphs.grid2d_5pt(9, 7), graphs.edgeless(4)]),
 }
 
 
